@@ -1,0 +1,215 @@
+"""Python access to the plain FP64 CPU oracle (``q1_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it.  The product library never imports, links or calls
+anything here, and nothing here calls the product library.
+
+The oracle computes the operator by its plain definition: element matrices by
+2x2x2 Gauss quadrature (paper Section 2), a CSR matrix summed element by
+element (Section 3, assembly by column search and addition), and products
+with that matrix.  ``pcg``/``fpcg`` are Hestenes-Stiefel PCG and flexible PCG
+built from the CG operations of Table 4.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "q1_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+PRECOND_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP over SpMV rows)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        L.orc_ke_laplace.argtypes = [_f64p, ctypes.c_double, _f64p]
+        L.orc_ke_elasticity.argtypes = [_f64p, ctypes.c_double, ctypes.c_double, _f64p]
+        L.orc_csr_pattern.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _i32p,
+                                      _i64p, ctypes.c_void_p]
+        L.orc_csr_pattern.restype = ctypes.c_int64
+        L.orc_csr_assemble.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _f64p,
+                                       _i32p, _f64p, ctypes.c_void_p, _i64p, _i32p, _f64p]
+        L.orc_spmv.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p]
+        L.orc_diag.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_pcg.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p,
+                              ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                              ctypes.c_void_p]
+        L.orc_fpcg.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p,
+                               ctypes.c_double, ctypes.c_int, PRECOND_FN, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                               ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def ke_laplace(X: np.ndarray, k: float = 1.0) -> np.ndarray:
+    """8x8 scalar-Laplace element matrix of the hexahedron with nodes X[8,3]."""
+    Ke = np.zeros(64)
+    if lib().orc_ke_laplace(np.ascontiguousarray(X, dtype=np.float64).ravel(), float(k), Ke):
+        raise ValueError("non-positive Jacobian determinant")
+    return Ke.reshape(8, 8)
+
+
+def ke_elasticity(X: np.ndarray, lam: float, mu: float) -> np.ndarray:
+    """24x24 isotropic-elasticity element matrix, DOF 3*node + component."""
+    Ke = np.zeros(576)
+    if lib().orc_ke_elasticity(np.ascontiguousarray(X, dtype=np.float64).ravel(),
+                               float(lam), float(mu), Ke):
+        raise ValueError("non-positive Jacobian determinant")
+    return Ke.reshape(24, 24)
+
+
+@dataclass
+class CSR:
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def matvec(self, x: np.ndarray) -> np.ndarray:
+        y = np.empty(self.n)
+        lib().orc_spmv(self.n, self.rowptr, self.col, self.val,
+                       np.ascontiguousarray(x, dtype=np.float64), y)
+        return y
+
+    def diag(self) -> np.ndarray:
+        d = np.empty(self.n)
+        lib().orc_diag(self.n, self.rowptr, self.col, self.val, d)
+        return d
+
+    def to_dense(self) -> np.ndarray:
+        A = np.zeros((self.n, self.n))
+        rows = np.repeat(np.arange(self.n), np.diff(self.rowptr))
+        A[rows, self.col] = self.val
+        return A
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
+
+
+def csr_pattern(dpn: int, n_nodes: int, conn: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    ne = conn.shape[1]
+    rowptr = np.zeros(n_nodes * dpn + 1, dtype=np.int64)
+    nnz = lib().orc_csr_pattern(dpn, n_nodes, ne, conn.ravel(), rowptr, None)
+    if nnz < 0:
+        raise MemoryError("oracle pattern allocation failed")
+    col = np.empty(nnz, dtype=np.int32)
+    lib().orc_csr_pattern(dpn, n_nodes, ne, conn.ravel(), rowptr,
+                          col.ctypes.data_as(ctypes.c_void_p))
+    return rowptr, col
+
+
+def assemble(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
+             mask: np.ndarray | None = None) -> CSR:
+    """Assembled operator with Dirichlet elimination on the masked nodes.
+
+    physics = 1 (scalar Laplace, coef [1, ne] = k) or 3 (elasticity,
+    coef [2, ne] = lambda, mu).  xyz [3, nn], conn [8, ne], mask uint8 [nn]."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    nn, ne = xyz.shape[1], conn.shape[1]
+    rowptr, col = csr_pattern(physics, nn, conn)
+    val = np.empty(col.shape[0])
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        mptr = mask.ctypes.data_as(ctypes.c_void_p)
+    else:
+        mptr = None
+    rc = lib().orc_csr_assemble(physics, nn, ne, xyz.ravel(), conn.ravel(), coef.ravel(),
+                                mptr, rowptr, col, val)
+    if rc == -1:
+        raise ValueError("element with non-positive Jacobian determinant")
+    if rc != 0:
+        raise RuntimeError(f"oracle assembly failed ({rc})")
+    return CSR(nn * physics, rowptr, col, val)
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    status: int
+    iters: int
+    rel_res: float
+    history: np.ndarray
+
+
+def pcg(A: CSR, b: np.ndarray, rtol: float = 1e-8, maxit: int = 20000,
+        jacobi: bool = True) -> SolveResult:
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n)
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1)
+    st = lib().orc_pcg(A.n, A.rowptr, A.col, A.val, b, x, float(rtol), int(maxit),
+                       int(bool(jacobi)), ctypes.byref(it), ctypes.byref(rr),
+                       hist.ctypes.data_as(ctypes.c_void_p))
+    return SolveResult(x, int(st), it.value, rr.value, hist[: it.value + 1].copy())
+
+
+def fpcg(A: CSR, b: np.ndarray, precond, rtol: float = 1e-8, maxit: int = 20000) -> SolveResult:
+    """Flexible PCG; ``precond(r) -> z`` is any Python callable on numpy arrays."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n)
+
+    def _cb(_ctx, n, rp, zp):
+        try:
+            r = np.ctypeslib.as_array(rp, shape=(n,))
+            z = np.ctypeslib.as_array(zp, shape=(n,))
+            z[:] = precond(r.copy())
+            return 0 if np.all(np.isfinite(z)) else 1
+        except Exception:  # a failing preconditioner is a breakdown
+            return 1
+
+    cb = PRECOND_FN(_cb)
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1)
+    st = lib().orc_fpcg(A.n, A.rowptr, A.col, A.val, b, x, float(rtol), int(maxit), cb, None,
+                        ctypes.byref(it), ctypes.byref(rr),
+                        hist.ctypes.data_as(ctypes.c_void_p))
+    return SolveResult(x, int(st), it.value, rr.value, hist[: it.value + 1].copy())
+
+
+def true_rel_res(A: CSR, x: np.ndarray, b: np.ndarray) -> float:
+    r = b - A.matvec(x)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))

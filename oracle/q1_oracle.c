@@ -1,0 +1,370 @@
+/*
+ * q1_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see
+ * q1_oracle.h).  Every routine is the textbook definition written out with
+ * plain loops: element matrices by quadrature (paper Section 2, element
+ * matrix equations for scalar Laplace and linear elasticity), global assembly
+ * by column search and addition (Section 3), CSR products and
+ * Hestenes-Stiefel PCG (the CG operations of Table 4).
+ */
+#include "q1_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- reference element (Section 2: isoparametric map, Gaussian quadrature) */
+
+void orc_quadrature(double pts[8][3], double w[8]) {
+  const double g = 1.0 / sqrt(3.0);
+  for (int q = 0; q < 8; ++q) {
+    pts[q][0] = (q & 1) ? g : -g;
+    pts[q][1] = (q & 2) ? g : -g;
+    pts[q][2] = (q & 4) ? g : -g;
+    w[q] = 1.0;
+  }
+}
+
+/* phi_a(xi) = N_i(xi0) N_j(xi1) N_k(xi2), a = i + 2j + 4k,
+ * N_0(t) = (1 - t)/2, N_1(t) = (1 + t)/2. */
+static double n1d(int s, double t) { return s ? 0.5 * (1.0 + t) : 0.5 * (1.0 - t); }
+static double dn1d(int s) { return s ? 0.5 : -0.5; }
+
+void orc_ref_grad(const double xi[3], double dphi[8][3]) {
+  for (int a = 0; a < 8; ++a) {
+    int i = a & 1, j = (a >> 1) & 1, k = (a >> 2) & 1;
+    dphi[a][0] = dn1d(i) * n1d(j, xi[1]) * n1d(k, xi[2]);
+    dphi[a][1] = n1d(i, xi[0]) * dn1d(j) * n1d(k, xi[2]);
+    dphi[a][2] = n1d(i, xi[0]) * n1d(j, xi[1]) * dn1d(k);
+  }
+}
+
+/* J_rc = sum_a X[a][r] dphi[a][c]; inverse by cofactors; G[a][r] = sum_c
+ * dphi[a][c] Jinv[c][r] is the physical gradient J^{-T} grad_hat phi_a.
+ * Returns det J. */
+static double physical_gradients(const double X[24], const double dphi[8][3],
+                                 double G[8][3]) {
+  double J[3][3] = {{0}};
+  for (int a = 0; a < 8; ++a)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] += X[3 * a + r] * dphi[a][c];
+  double C[3][3]; /* cofactor matrix */
+  C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  C[0][1] = -(J[1][0] * J[2][2] - J[1][2] * J[2][0]);
+  C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  C[1][0] = -(J[0][1] * J[2][2] - J[0][2] * J[2][1]);
+  C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  C[1][2] = -(J[0][0] * J[2][1] - J[0][1] * J[2][0]);
+  C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  C[2][1] = -(J[0][0] * J[1][2] - J[0][2] * J[1][0]);
+  C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+  double Jinv[3][3]; /* Jinv = adj(J)/det, adj = C^T */
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Jinv[r][c] = C[c][r] / det;
+  for (int a = 0; a < 8; ++a)
+    for (int r = 0; r < 3; ++r) {
+      double s = 0.0;
+      for (int c = 0; c < 3; ++c) s += dphi[a][c] * Jinv[c][r];
+      G[a][r] = s;
+    }
+  return det;
+}
+
+/* [A^e]_ab = sum_q k w_q detJ (J^{-T} grad_hat phi_a) . (J^{-T} grad_hat phi_b)
+ * (scalar Laplace element matrix, with the cell coefficient k). */
+int orc_ke_laplace(const double X[24], double k, double Ke[64]) {
+  double pts[8][3], w[8];
+  orc_quadrature(pts, w);
+  memset(Ke, 0, 64 * sizeof(double));
+  for (int q = 0; q < 8; ++q) {
+    double dphi[8][3], G[8][3];
+    orc_ref_grad(pts[q], dphi);
+    double det = physical_gradients(X, dphi, G);
+    if (!(det > 0.0)) return -1;
+    double s = k * w[q] * det;
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b)
+        Ke[8 * a + b] += s * (G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2]);
+  }
+  return 0;
+}
+
+/* [A^e]_{3a+i,3b+j} = sum_q w_q detJ (e_i (x) grad phi_a) : sigma(e_j (x) grad phi_b)
+ * with sigma(eps) = lambda tr(eps) I + 2 mu eps, which expands to
+ * lambda G_ai G_bj + mu (delta_ij G_a.G_b + G_aj G_bi). */
+int orc_ke_elasticity(const double X[24], double lam, double mu, double Ke[576]) {
+  double pts[8][3], w[8];
+  orc_quadrature(pts, w);
+  memset(Ke, 0, 576 * sizeof(double));
+  for (int q = 0; q < 8; ++q) {
+    double dphi[8][3], G[8][3];
+    orc_ref_grad(pts[q], dphi);
+    double det = physical_gradients(X, dphi, G);
+    if (!(det > 0.0)) return -1;
+    double s = w[q] * det;
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) {
+        double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            double v = lam * G[a][i] * G[b][j] + mu * ((i == j ? gg : 0.0) + G[a][j] * G[b][i]);
+            Ke[24 * (3 * a + i) + 3 * b + j] += s * v;
+          }
+      }
+  }
+  return 0;
+}
+
+/* ---- CSR pattern ------------------------------------------------------- */
+
+static int cmp_i32(const void *p, const void *q) {
+  int32_t a = *(const int32_t *)p, b = *(const int32_t *)q;
+  return (a > b) - (a < b);
+}
+
+/* node -> element incidence lists */
+static int node_elems(int64_t nn, int64_t ne, const int32_t *conn, int64_t **ptr_out,
+                      int64_t **lst_out) {
+  int64_t *ptr = (int64_t *)calloc((size_t)nn + 1, sizeof(int64_t));
+  int64_t *lst = (int64_t *)malloc((size_t)(8 * ne + 1) * sizeof(int64_t));
+  if (!ptr || !lst) { free(ptr); free(lst); return -1; }
+  for (int a = 0; a < 8; ++a)
+    for (int64_t e = 0; e < ne; ++e) ptr[conn[a * ne + e] + 1]++;
+  for (int64_t n = 0; n < nn; ++n) ptr[n + 1] += ptr[n];
+  int64_t *fill = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+  if (!fill) { free(ptr); free(lst); return -1; }
+  memcpy(fill, ptr, (size_t)nn * sizeof(int64_t));
+  for (int64_t e = 0; e < ne; ++e)
+    for (int a = 0; a < 8; ++a) {
+      int32_t n = conn[a * ne + e];
+      /* an element lists a node once even if (degenerately) repeated */
+      int dup = 0;
+      for (int b = 0; b < a; ++b) dup |= (conn[b * ne + e] == n);
+      if (!dup) lst[fill[n]++] = e;
+    }
+  /* recompute ptr with the de-duplicated counts */
+  int64_t *ptr2 = (int64_t *)calloc((size_t)nn + 1, sizeof(int64_t));
+  if (!ptr2) { free(ptr); free(lst); free(fill); return -1; }
+  int64_t w = 0;
+  for (int64_t n = 0; n < nn; ++n) {
+    ptr2[n] = w;
+    for (int64_t t = ptr[n]; t < fill[n]; ++t) lst[w++] = lst[t];
+  }
+  ptr2[nn] = w;
+  free(ptr); free(fill);
+  *ptr_out = ptr2; *lst_out = lst;
+  return 0;
+}
+
+int64_t orc_csr_pattern(int dpn, int64_t nn, int64_t ne, const int32_t *conn,
+                        int64_t *rowptr, int32_t *col) {
+  int64_t *nptr, *nlst;
+  if (node_elems(nn, ne, conn, &nptr, &nlst)) return -1;
+  int64_t cap = 64;
+  int32_t *buf = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+  if (!buf) { free(nptr); free(nlst); return -1; }
+  int64_t nnz = 0;
+  rowptr[0] = 0;
+  for (int64_t n = 0; n < nn; ++n) {
+    int64_t m = 0, need = 8 * (nptr[n + 1] - nptr[n]);
+    if (need > cap) {
+      cap = need;
+      int32_t *nb = (int32_t *)realloc(buf, (size_t)cap * sizeof(int32_t));
+      if (!nb) { free(buf); free(nptr); free(nlst); return -1; }
+      buf = nb;
+    }
+    for (int64_t t = nptr[n]; t < nptr[n + 1]; ++t)
+      for (int a = 0; a < 8; ++a) buf[m++] = conn[a * ne + nlst[t]];
+    qsort(buf, (size_t)m, sizeof(int32_t), cmp_i32);
+    int64_t u = 0;
+    for (int64_t t = 0; t < m; ++t)
+      if (t == 0 || buf[t] != buf[t - 1]) buf[u++] = buf[t];
+    for (int c = 0; c < dpn; ++c) {
+      int64_t row = n * dpn + c;
+      if (col)
+        for (int64_t t = 0; t < u; ++t)
+          for (int d = 0; d < dpn; ++d) col[nnz + t * dpn + d] = buf[t] * dpn + d;
+      nnz += u * dpn;
+      rowptr[row + 1] = nnz;
+    }
+  }
+  free(buf); free(nptr); free(nlst);
+  return nnz;
+}
+
+static int64_t find_col(const int64_t *rowptr, const int32_t *col, int64_t row, int32_t c) {
+  int64_t lo = rowptr[row], hi = rowptr[row + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (col[mid] == c) return mid;
+    if (col[mid] < c) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
+                     const int32_t *conn, const double *coef, const uint8_t *mask,
+                     const int64_t *rowptr, const int32_t *col, double *val) {
+  const int dpn = physics;
+  const int nd = 8 * dpn;
+  const int64_t nrows = nn * dpn;
+  memset(val, 0, (size_t)rowptr[nrows] * sizeof(double));
+  double X[24], Ke[576];
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int a = 0; a < 8; ++a) {
+      int32_t n = conn[a * ne + e];
+      X[3 * a + 0] = xyz[0 * nn + n];
+      X[3 * a + 1] = xyz[1 * nn + n];
+      X[3 * a + 2] = xyz[2 * nn + n];
+    }
+    int rc = (physics == 1) ? orc_ke_laplace(X, coef[e], Ke)
+                            : orc_ke_elasticity(X, coef[e], coef[ne + e], Ke);
+    if (rc) return -1;
+    for (int p = 0; p < nd; ++p) {
+      int64_t row = (int64_t)conn[(p / dpn) * ne + e] * dpn + p % dpn;
+      for (int s = 0; s < nd; ++s) {
+        int32_t c = conn[(s / dpn) * ne + e] * dpn + s % dpn;
+        int64_t t = find_col(rowptr, col, row, c);
+        if (t < 0) return -2;
+        val[t] += Ke[nd * p + s];
+      }
+    }
+  }
+  if (mask) {
+    for (int64_t row = 0; row < nrows; ++row) {
+      int rfix = mask[row / dpn] != 0;
+      for (int64_t t = rowptr[row]; t < rowptr[row + 1]; ++t) {
+        int cfix = mask[col[t] / dpn] != 0;
+        if (rfix || cfix) val[t] = (col[t] == row) ? 1.0 : 0.0;
+      }
+    }
+  }
+  return 0;
+}
+
+/* ---- products -------------------------------------------------------- */
+
+void orc_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t t = rowptr[i]; t < rowptr[i + 1]; ++t) s += val[t] * x[col[t]];
+    y[i] = s;
+  }
+}
+
+void orc_diag(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              double *d) {
+  for (int64_t i = 0; i < n; ++i) {
+    d[i] = 0.0;
+    for (int64_t t = rowptr[i]; t < rowptr[i + 1]; ++t)
+      if (col[t] == i) d[i] = val[t];
+  }
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+static double dot(int64_t n, const double *a, const double *b) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+/* ---- Krylov solvers (CG operations of Table 4) ------------------------- */
+
+int orc_pcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+            const double *b, double *x, double rtol, int maxit, int jacobi,
+            int *iters, double *rel_res, double *res_hist) {
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  double *z = (double *)malloc((size_t)n * sizeof(double));
+  double *p = (double *)malloc((size_t)n * sizeof(double));
+  double *q = (double *)malloc((size_t)n * sizeof(double));
+  double *d = (double *)malloc((size_t)n * sizeof(double));
+  if (!r || !z || !p || !q || !d) { free(r); free(z); free(p); free(q); free(d); return -2; }
+  orc_diag(n, rowptr, col, val, d);
+  for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+  const double bnorm = sqrt(dot(n, b, b));
+  int status = -4, k = 0;
+  double rnorm = bnorm;
+  if (res_hist) res_hist[0] = rnorm;
+  if (bnorm == 0.0) { status = 0; goto done; }
+  for (int64_t i = 0; i < n; ++i) z[i] = jacobi ? r[i] / d[i] : r[i];
+  double rho = dot(n, r, z);
+  memcpy(p, z, (size_t)n * sizeof(double));
+  for (k = 0; k < maxit;) {
+    orc_spmv(n, rowptr, col, val, p, q);
+    double pq = dot(n, p, q);
+    if (!(pq > 0.0) || !isfinite(pq)) { status = -5; break; }
+    double alpha = rho / pq;
+    for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+    ++k;
+    rnorm = sqrt(dot(n, r, r));
+    if (res_hist) res_hist[k] = rnorm;
+    if (rnorm <= rtol * bnorm) { status = 0; break; }
+    for (int64_t i = 0; i < n; ++i) z[i] = jacobi ? r[i] / d[i] : r[i];
+    double rho_new = dot(n, r, z);
+    double beta = rho_new / rho;
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    rho = rho_new;
+  }
+done:
+  if (iters) *iters = k;
+  if (rel_res) *rel_res = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  free(r); free(z); free(p); free(q); free(d);
+  return status;
+}
+
+int orc_fpcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+             const double *b, double *x, double rtol, int maxit, orc_precond_fn M, void *ctx,
+             int *iters, double *rel_res, double *res_hist) {
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  double *rold = (double *)malloc((size_t)n * sizeof(double));
+  double *z = (double *)malloc((size_t)n * sizeof(double));
+  double *p = (double *)malloc((size_t)n * sizeof(double));
+  double *q = (double *)malloc((size_t)n * sizeof(double));
+  if (!r || !rold || !z || !p || !q) {
+    free(r); free(rold); free(z); free(p); free(q); return -2;
+  }
+  for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+  const double bnorm = sqrt(dot(n, b, b));
+  int status = -4, k = 0;
+  double rnorm = bnorm;
+  if (res_hist) res_hist[0] = rnorm;
+  if (bnorm == 0.0) { status = 0; goto done; }
+  if (M(ctx, n, r, z)) { status = -5; goto done; }
+  double rho = dot(n, r, z);
+  memcpy(p, z, (size_t)n * sizeof(double));
+  for (k = 0; k < maxit;) {
+    orc_spmv(n, rowptr, col, val, p, q);
+    double pq = dot(n, p, q);
+    if (!(pq > 0.0) || !isfinite(pq)) { status = -5; break; }
+    double alpha = rho / pq;
+    memcpy(rold, r, (size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+    ++k;
+    rnorm = sqrt(dot(n, r, r));
+    if (res_hist) res_hist[k] = rnorm;
+    if (rnorm <= rtol * bnorm) { status = 0; break; }
+    if (M(ctx, n, r, z)) { status = -5; break; }
+    double num = 0.0;
+    for (int64_t i = 0; i < n; ++i) num += z[i] * (r[i] - rold[i]);
+    double beta = num / rho;
+    rho = dot(n, r, z);
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+done:
+  if (iters) *iters = k;
+  if (rel_res) *rel_res = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  free(r); free(rold); free(z); free(p); free(q);
+  return status;
+}

@@ -1,0 +1,81 @@
+/*
+ * q1_oracle.h -- plain FP64 CPU oracle for the trilinear (Q1) hexahedral
+ * scalar-Laplace and isotropic-elasticity operators.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may call it.  It shares no code with the GPU
+ * library: it assembles element matrices by quadrature, sums them into a CSR
+ * matrix and multiplies, which is the plain definition of the operator
+ * (paper Section 2, the element matrices; Section 3, the remark on matrix
+ * assembly by column search and addition).  It never performs a matrix-free
+ * apply.
+ *
+ * Conventions (the paper leaves them open; the readings are listed with the
+ * design notes of the repository):
+ *   reference cube [-1,1]^3, local node a = i + 2j + 4k sits at
+ *   (2i-1, 2j-1, 2k-1); 2x2x2 Gauss-Legendre quadrature, points +-1/sqrt(3),
+ *   weights 1; J_rc = dx_r/dxi_c; DOF numbering node*dpn + component.
+ *   Coordinates are [3][n_nodes] (structure of arrays), connectivity is
+ *   [8][n_elems], cell coefficients are [ncoef][n_elems]: k for Laplace,
+ *   (lambda, mu) for elasticity.  Dirichlet: a constrained DOF c gets row and
+ *   column zeroed and A_cc = 1 (symmetric elimination).
+ */
+#ifndef Q1_ORACLE_H
+#define Q1_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* 2x2x2 Gauss-Legendre rule, q = qx + 2 qy + 4 qz. */
+void orc_quadrature(double pts[8][3], double w[8]);
+/* Reference gradients of the 8 trilinear basis functions at xi. */
+void orc_ref_grad(const double xi[3], double dphi[8][3]);
+
+/* Element matrices.  X is [8][3] (node-major).  Return 0, or -1 when
+ * det J <= 0 at some quadrature point. */
+int orc_ke_laplace(const double X[24], double k, double Ke[64]);
+int orc_ke_elasticity(const double X[24], double lam, double mu, double Ke[576]);
+
+/* CSR pattern of the assembled operator, columns sorted.  rowptr has
+ * n_nodes*dpn + 1 entries.  With col == NULL only rowptr is filled.
+ * Returns nnz, or -1 on allocation failure. */
+int64_t orc_csr_pattern(int dpn, int64_t n_nodes, int64_t n_elems, const int32_t *conn,
+                        int64_t *rowptr, int32_t *col);
+
+/* Fill values: element loop in element order, column found by binary search,
+ * then Dirichlet elimination.  physics = 1 (Laplace) or 3 (elasticity).
+ * Returns 0, -1 (bad element) or -2 (missing column). */
+int orc_csr_assemble(int physics, int64_t n_nodes, int64_t n_elems, const double *xyz,
+                     const int32_t *conn, const double *coef, const uint8_t *mask_nodes,
+                     const int64_t *rowptr, const int32_t *col, double *val);
+
+/* y = A x, rows in parallel (OpenMP), each row summed in column order. */
+void orc_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              const double *x, double *y);
+void orc_diag(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              double *d);
+/* Number of threads the OpenMP regions use. */
+int orc_num_threads(void);
+
+/* Preconditioned CG (Hestenes-Stiefel), x0 = 0, stop when ||r||_2 <= rtol ||b||_2
+ * on the recurrence residual.  jacobi != 0 uses z = D^{-1} r.  res_hist, if
+ * not NULL, receives ||r_k||_2 for k = 0..iters.  Returns 0 (converged),
+ * -4 (maxit reached, x holds the last iterate) or -5 (breakdown). */
+int orc_pcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+            const double *b, double *x, double rtol, int maxit, int jacobi,
+            int *iters, double *rel_res, double *res_hist);
+
+/* Flexible PCG with a variable preconditioner z = M(r):
+ * beta = z_{k+1}^T (r_{k+1} - r_k) / (r_k^T z_k).  Same stopping rule and
+ * return codes as orc_pcg. */
+typedef int (*orc_precond_fn)(void *ctx, int64_t n, const double *r, double *z);
+int orc_fpcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+             const double *b, double *x, double rtol, int maxit, orc_precond_fn M, void *ctx,
+             int *iters, double *rel_res, double *res_hist);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
