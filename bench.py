@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Headline benchmark: GDOF/s per matrix-free apply.
+
+Workload: scalar Laplace, trilinear hexahedra on an undistorted 128^3-element
+grid (2,146,689 DOF), layered coefficient (one lognormal(0, 1.5) value per
+4-cell z-layer times iid lognormal(0, 0.5) per cell), FP64, no boundary
+condition.  A step is one y = A x apply with all inputs resident in HBM.
+
+Prints one JSON line with the roofline of the apply (algorithmic bytes per
+apply / event-timed apply duration against 8 TB/s) and the CPU oracle
+(assembled CSR, OpenMP SpMV) timed on a slab of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def upload(pr, dtype):
+    import numpy as np
+    import torch
+    t = torch.float64 if dtype == 0 else torch.float32
+    d = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=dt)
+    mask = d(pr["mask"].astype(np.uint8)) if pr.get("mask") is not None else None
+    return d(pr["xyz"], t), d(pr["conn"].astype(np.int32)), d(pr["coef"], t), mask
+
+
+def time_applies(op, x, y, steps, warmup):
+    """Back-to-back applies on the current stream; events bracket the K steps."""
+    import torch
+    for _ in range(warmup):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        op.apply(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def time_cold(op, x, y, reps):
+    """Each apply after writing a 1 GiB buffer (evicts L2 and the MALL)."""
+    import torch
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    ts = []
+    for i in range(reps):
+        flush.fill_(float(i))
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        op.apply(x, y)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def cpu_baseline(n: int, seed: int, slab: int):
+    """The oracle as it stands on a slab (first `slab` element layers) of the
+    same workload: CSR assembly once, then the OpenMP SpMV timed."""
+    import numpy as np
+
+    import oracle
+    import seeded_inputs as si
+    oracle.build(force=False)
+    pr = si.problem_laplace_layered(n, seed)
+    nn_s = (n + 1) * (n + 1) * (slab + 1)
+    ne_s = n * n * slab
+    xyz = np.ascontiguousarray(pr["xyz"][:, :nn_s])
+    conn = np.ascontiguousarray(pr["conn"][:, :ne_s])
+    coef = np.ascontiguousarray(pr["coef"][:, :ne_s])
+    t0 = time.perf_counter()
+    A = oracle.assemble(1, xyz, conn, coef)
+    t_asm = time.perf_counter() - t0
+    x = si.vec_uniform(nn_s, seed, si.STREAM_X)
+    A.matvec(x)
+    reps, t0 = 0, time.perf_counter()
+    while reps < 5 or time.perf_counter() - t0 < 3.0:
+        A.matvec(x)
+        reps += 1
+    t_spmv = (time.perf_counter() - t0) / reps
+    return dict(value=round(nn_s / t_spmv / 1e9, 4), unit="GDOF/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=(f"{n}x{n}x{slab}-element slab ({nn_s} DOF) of the {n}^3 workload; "
+                        f"CSR assembled once in {t_asm:.2f} s (not in the rate), OpenMP CSR "
+                        f"SpMV timed over {reps} products"),
+                assembly_s=round(t_asm, 3), spmv_ms=round(t_spmv * 1e3, 3))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=128, help="elements per edge")
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 atomic, 3 LDS tile")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the operator is single-device by design "
+              "(multi-GPU sharding is described, not built); run with --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2308_09839_amd as q1
+    import seeded_inputs as si
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    seed = si.seed_for(1)
+    n = args.n
+    log(f"[bench] building {n}^3 layered-coefficient Laplace inputs")
+    pr = si.problem_laplace_layered(n, seed)
+    nn = pr["xyz"].shape[1]
+    ndof = nn
+
+    def make(pr_, dtype):
+        xyz, conn, coef, mask = upload(pr_, dtype)
+        op = q1.q1_op_create(1, dtype, args.variant, xyz, conn, coef, mask)
+        t = torch.float64 if dtype == 0 else torch.float32
+        x = torch.from_numpy(si.vec_uniform(nn, seed, si.STREAM_X)).to("cuda", dtype=t)
+        y = torch.empty_like(x)
+        return op, x, y
+
+    op, x, y = make(pr, 0)
+    info = op.info()
+    alg_bytes, alg_flops = op.bytes()
+    log(f"[bench] timing {args.steps} FP64 applies (variant {info['variant']})")
+    ms, wall = time_applies(op, x, y, args.steps, args.warmup)
+    gdofs = ndof / (ms * 1e-3) / 1e9
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    extras = {}
+    if not args.no_extras:
+        log("[bench] cold (flushed) applies")
+        ms_cold = time_cold(op, x, y, 30)
+        extras["fp64_cold_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)
+        extras["fp64_cold_ms"] = round(ms_cold, 5)
+        del op, x, y
+        log("[bench] FP32 applies")
+        op32, x32, y32 = make(pr, 1)
+        ms32, _ = time_applies(op32, x32, y32, args.steps, args.warmup)
+        b32, _ = op32.bytes()
+        extras["fp32_gdofs"] = round(ndof / (ms32 * 1e-3) / 1e9, 3)
+        extras["fp32_ms"] = round(ms32, 5)
+        extras["fp32_hbm_frac"] = round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        del op32, x32, y32
+        log("[bench] jittered (general-hexahedron) FP64 applies")
+        prj = dict(pr)
+        prj["xyz"], _ = si.box_mesh(n, n, n, 1.0, 0.1, seed)
+        opj, xj, yj = make(prj, 0)
+        msj, _ = time_applies(opj, xj, yj, args.steps, args.warmup)
+        extras["fp64_jittered_gdofs"] = round(ndof / (msj * 1e-3) / 1e9, 3)
+        extras["fp64_jittered_ms"] = round(msj, 5)
+        extras["fp64_jittered_flop_frac"] = round(alg_flops / (msj * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)
+        del opj, xj, yj
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(n, seed, 16)
+        cpu["value"] = cpu["value"]
+    torch.cuda.synchronize()
+    out = {
+        "metric": "GDOF/s per matrix-free apply",
+        "value": round(gdofs, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"scalar Laplace Q1, {n}^3 undistorted hexahedra "
+                               f"({ndof} DOF), layered lognormal coefficient, FP64 "
+                               "matrix-free apply",
+                   "n_elems": n ** 3, "n_dof": ndof, "variant": info["variant"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "algorithmic_bytes_per_apply": alg_bytes},
+        "cpu_baseline": cpu,
+        "extra": extras,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

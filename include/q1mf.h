@@ -1,0 +1,137 @@
+/*
+ * q1mf.h -- C ABI of libq1mf, matrix-free trilinear (Q1) hexahedral finite
+ * element operators for gfx950 (MI355X).
+ *
+ * The library applies y = A x without forming A for the scalar Laplace and
+ * the isotropic linear-elasticity operators with cell-wise coefficients
+ * (paper Section 2: element matrices of the scalar Laplace and elasticity
+ * problems under the isoparametric map and Gaussian quadrature; Section 3:
+ * the three-step gather / local product / scatter-add apply and Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *   - Status: every function returns Q1_OK (0) or a negative Q1_E* code; the
+ *     text of the last error of the calling thread is q1_last_error().
+ *   - Pointers named *_d are DEVICE pointers owned by the caller (for example
+ *     torch tensors' data_ptr()).  The library never frees or reallocates
+ *     them.  Host pointers are named without the suffix.
+ *   - stream is a hipStream_t (NULL = the null stream).  Device calls are
+ *     asynchronous on that stream unless stated otherwise.
+ *   - Reals are double for Q1_F64 operators and float for Q1_F32 operators:
+ *     coordinates, coefficients and vectors all use the operator's dtype.
+ *   - Indices are int32 (n_nodes < 2^31); counts are int64.
+ *   - Mesh layout: coordinates structure-of-arrays [3][n_nodes]; connectivity
+ *     [8][n_elems] with local node a = i + 2j + 4k at reference corner
+ *     (2i-1, 2j-1, 2k-1) of [-1,1]^3; DOF numbering node*dpn + component
+ *     (dpn = 1 Laplace, 3 elasticity); coefficients [ncoef][n_elems]:
+ *     k for Laplace, (lambda, mu) for elasticity.
+ *   - Quadrature: 2x2x2 Gauss-Legendre (points +-1/sqrt(3), weights 1).
+ *   - Dirichlet mask (uint8 per node, or NULL for none): every DOF of a masked
+ *     node is eliminated symmetrically, (A x)_c = x_c, and masked DOFs are
+ *     left out of the gather and the scatter of all other rows.
+ */
+#ifndef Q1MF_H
+#define Q1MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status ------------------------------------------------------------ */
+#define Q1_OK 0
+#define Q1_EINVAL (-1)       /* bad size, NULL pointer, enum or alignment */
+#define Q1_ENOMEM (-2)       /* device or host allocation failed */
+#define Q1_EHIP (-3)         /* HIP runtime error; text in q1_last_error() */
+#define Q1_ENOCONV (-4)      /* iteration limit reached; x holds the last iterate */
+#define Q1_EBREAKDOWN (-5)   /* p^T A p <= 0, non-finite scalar, bad element */
+#define Q1_EUNSUPPORTED (-6) /* valid request that this build does not support */
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *q1_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int q1_version(void);
+
+/* ---- host generators of the synthetic workloads --------------------------
+ * Counter-based SplitMix64 (Steele, Lea & Flood 2014):
+ *   draw(seed, stream, i) = splitmix64((seed ^ stream*0x9E3779B97F4A7C15) + i),
+ *   U(0,1) = (draw >> 11) * 2^-53, N(0,1) = Box-Muller on U(2i), U(2i+1):
+ *   sqrt(-2 log(1 - u1)) cos(2 pi u2).
+ * All outputs are host arrays the caller allocates. */
+
+/* Node and element counts of an nx*ny*nz box of hexahedra. */
+int q1_box_sizes(int nx, int ny, int nz, int64_t *n_nodes, int64_t *n_elems);
+/* Box mesh of spacing h: node id = i + (nx+1)(j + (ny+1)k), element
+ * e = ex + nx(ey + ny ez).  Interior nodes move by U(-jitter_frac h,
+ * jitter_frac h) per coordinate (stream 0, counter 3 id + c); surface nodes
+ * stay on the box.  xyz [3][n_nodes], conn [8][n_elems]. */
+int q1_box_mesh(int nx, int ny, int nz, double h, double jitter_frac, uint64_t seed,
+                double *xyz, int32_t *conn);
+/* mask[n] = 1 for nodes on one face (0:x=0 1:x=max 2:y=0 3:y=max 4:z=0 5:z=max). */
+int q1_face_mask(int nx, int ny, int nz, int face, uint8_t *mask);
+/* out[i] = exp(mu + sigma N_i) from the given stream. */
+int q1_field_lognormal(int64_t n, double mu, double sigma, uint64_t seed, uint64_t stream,
+                       double *out);
+/* k_e = exp(s_layer N_1(ez / layer_cells)) * exp(s_cell N_2(e)) (streams 1 and 2). */
+int q1_field_layered(int nx, int ny, int nz, int layer_cells, double s_layer, double s_cell,
+                     uint64_t seed, double *k);
+/* E = exp(N_1(ln 10, 1)), nu = 0.15 + 0.2 U_2 per cell. */
+int q1_field_elastic(int64_t n, uint64_t seed, double *E, double *nu);
+/* lambda = E nu / ((1+nu)(1-2nu)), mu = E / (2(1+nu)). */
+int q1_lame_from_E_nu(int64_t n, const double *E, const double *nu, double *lam, double *mu);
+/* out[i] = lo + (hi - lo) U_i from the given stream. */
+int q1_vec_uniform(int64_t n, uint64_t seed, uint64_t stream, double lo, double hi,
+                   double *out);
+
+/* ---- operators ---------------------------------------------------------- */
+typedef struct q1_op q1_op;
+
+enum { Q1_LAPLACE = 1, Q1_ELASTICITY = 3 }; /* value = DOF per node */
+enum { Q1_F64 = 0, Q1_F32 = 1 };
+/* Scatter strategies of the apply (Section 3, third step):
+ *   ATOMIC   one thread per element, global atomic adds (the paper's
+ *            one-thread-per-element strategy, Section 6);
+ *   LDS_TILE element tiles with their nodes staged in LDS, accumulation in LDS,
+ *            global atomics only for nodes shared with other tiles;
+ *   AUTO     the fastest measured strategy for the operator. */
+enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_LDS_TILE = 3 };
+
+/* Create an operator over caller-owned device arrays.  The arrays are
+ * referenced, not copied: they must stay valid and unchanged until
+ * q1_op_destroy.  coef_d holds k [n_elems] (Laplace) or lambda then mu
+ * [2][n_elems] (elasticity).  mask_d may be NULL.  Set-up work (tile maps)
+ * runs on `stream` and is complete when the call returns. */
+int q1_op_create(q1_op **op, int physics, int dtype, int variant, int64_t n_nodes,
+                 int64_t n_elems, const void *xyz_d, const int32_t *conn_d, const void *coef_d,
+                 const uint8_t *mask_d, void *stream);
+/* y = A x (overwrites y; x and y must not alias).  Both have n_nodes*dpn
+ * entries of the operator's dtype. */
+int q1_op_apply(q1_op *op, const void *x_d, void *y_d, void *stream);
+/* d = diag(A), computed element by element without forming A; d_c = 1 on
+ * Dirichlet DOFs. */
+int q1_op_diag(q1_op *op, void *d_d, void *stream);
+/* Properties: physics, dtype, variant actually used, n_nodes, n_elems. */
+int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t *n_nodes,
+               int64_t *n_elems);
+/* Algorithmic bytes and FLOPs of one apply under the Table 2 convention with
+ * perfect caching: 32 B of node ids and the cell coefficients per element;
+ * the coordinates plus three vector streams (x read, y read, y write) per
+ * node.  FLOPs: the fixed per-element counts of the sum-factorised apply. */
+int q1_op_bytes(const q1_op *op, double *algorithmic_bytes, double *algorithmic_flops);
+/* Destroy the handle and its internal workspace (not the caller's arrays). */
+int q1_op_destroy(q1_op *op);
+
+/* Byte model of Section 4 (Tables 1-3) for n_elems hexahedra and n_nodes
+ * nodes.  kind: 0 SpMV (Table 1: 12 B per non-zero with 27*dpn non-zeros per
+ * row, two vectors), 1 matrix-free (Table 2), 2 partial assembly (Table 3).
+ * cache: 0 perfect caching (nodal data read once), 1 no caching (nodal data
+ * read once per element touching it).  real_bytes 8 or 4; coefficient bytes
+ * per element coef_bytes (the paper counts 0 for Laplace, 16 for elasticity). */
+int q1_model_bytes(int kind, int physics, int real_bytes, int coef_bytes, int64_t n_nodes,
+                   int64_t n_elems, int cache, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* Q1MF_H */

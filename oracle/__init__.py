@@ -56,6 +56,8 @@ def lib():
         L.orc_csr_pattern.restype = ctypes.c_int64
         L.orc_csr_assemble.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _f64p,
                                        _i32p, _f64p, ctypes.c_void_p, _i64p, _i32p, _f64p]
+        L.orc_apply_rows.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _f64p, _i32p,
+                                     _f64p, ctypes.c_void_p, _f64p, ctypes.c_int64, _i64p, _f64p]
         L.orc_spmv.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p]
         L.orc_diag.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p]
         L.orc_num_threads.restype = ctypes.c_int
@@ -162,6 +164,27 @@ def assemble(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
     if rc != 0:
         raise RuntimeError(f"oracle assembly failed ({rc})")
     return CSR(nn * physics, rowptr, col, val)
+
+
+def apply_rows(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
+               mask: np.ndarray | None, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """Rows ``rows`` (DOF indices) of A x, summed element by element from the
+    element matrices (no global matrix), with the Dirichlet elimination."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    y = np.empty(rows.shape[0])
+    mptr = None
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        mptr = mask.ctypes.data_as(ctypes.c_void_p)
+    rc = lib().orc_apply_rows(physics, xyz.shape[1], conn.shape[1], xyz.ravel(), conn.ravel(),
+                              coef.ravel(), mptr, x, rows.shape[0], rows, y)
+    if rc:
+        raise RuntimeError(f"oracle apply_rows failed ({rc})")
+    return y
 
 
 @dataclass

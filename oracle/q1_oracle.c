@@ -245,6 +245,51 @@ int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
   return 0;
 }
 
+int orc_apply_rows(int physics, int64_t nn, int64_t ne, const double *xyz,
+                   const int32_t *conn, const double *coef, const uint8_t *mask,
+                   const double *x, int64_t n_rows, const int64_t *rows, double *y) {
+  const int dpn = physics, nd = 8 * dpn;
+  /* slot[node] = 1 if any DOF of the node is selected */
+  uint8_t *sel = (uint8_t *)calloc((size_t)nn, 1);
+  int64_t *pos = (int64_t *)malloc((size_t)(nn * dpn) * sizeof(int64_t));
+  if (!sel || !pos) { free(sel); free(pos); return -2; }
+  for (int64_t i = 0; i < nn * dpn; ++i) pos[i] = -1;
+  for (int64_t r = 0; r < n_rows; ++r) {
+    sel[rows[r] / dpn] = 1;
+    pos[rows[r]] = r;
+    y[r] = 0.0;
+  }
+  double X[24], Ke[576];
+  for (int64_t e = 0; e < ne; ++e) {
+    int touch = 0;
+    for (int a = 0; a < 8; ++a) touch |= sel[conn[a * ne + e]];
+    if (!touch) continue;
+    for (int a = 0; a < 8; ++a) {
+      int32_t n = conn[a * ne + e];
+      for (int c = 0; c < 3; ++c) X[3 * a + c] = xyz[c * nn + n];
+    }
+    int rc = (physics == 1) ? orc_ke_laplace(X, coef[e], Ke)
+                            : orc_ke_elasticity(X, coef[e], coef[ne + e], Ke);
+    if (rc) { free(sel); free(pos); return -1; }
+    for (int p = 0; p < nd; ++p) {
+      int64_t row = (int64_t)conn[(p / dpn) * ne + e] * dpn + p % dpn;
+      if (pos[row] < 0) continue;
+      double s = 0.0;
+      for (int q = 0; q < nd; ++q) {
+        int32_t cn = conn[(q / dpn) * ne + e];
+        if (mask && mask[cn]) continue; /* eliminated column */
+        s += Ke[nd * p + q] * x[(int64_t)cn * dpn + q % dpn];
+      }
+      y[pos[row]] += s;
+    }
+  }
+  if (mask)
+    for (int64_t r = 0; r < n_rows; ++r)
+      if (mask[rows[r] / dpn]) y[r] = x[rows[r]];
+  free(sel); free(pos);
+  return 0;
+}
+
 /* ---- products -------------------------------------------------------- */
 
 void orc_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,

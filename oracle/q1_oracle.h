@@ -51,6 +51,15 @@ int orc_csr_assemble(int physics, int64_t n_nodes, int64_t n_elems, const double
                      const int32_t *conn, const double *coef, const uint8_t *mask_nodes,
                      const int64_t *rowptr, const int32_t *col, double *val);
 
+/* Selected rows of y = A x computed from element matrices without forming A:
+ * for each element touching a selected node, its element matrix is computed
+ * and the selected rows' products are added (element order), then the
+ * Dirichlet elimination is applied.  rows are DOF indices (node*dpn + comp).
+ * Returns 0, or -1 (bad element) / -2 (allocation). */
+int orc_apply_rows(int physics, int64_t n_nodes, int64_t n_elems, const double *xyz,
+                   const int32_t *conn, const double *coef, const uint8_t *mask_nodes,
+                   const double *x, int64_t n_rows, const int64_t *rows, double *y_rows);
+
 /* y = A x, rows in parallel (OpenMP), each row summed in column order. */
 void orc_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
               const double *x, double *y);

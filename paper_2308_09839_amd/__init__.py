@@ -1,0 +1,188 @@
+"""MI355X-native matrix-free Q1 hexahedral finite-element operators.
+
+Thin Python binding of ``libq1mf.so`` (C ABI in ``include/q1mf.h``).  The
+functions keep the C names; they only marshal arguments: torch tensors are
+passed as raw device pointers, numpy arrays as host pointers, and the current
+torch (HIP) stream is used unless one is given.  Every computation runs in
+the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import (Q1_ELASTICITY, Q1_F32, Q1_F64, Q1_LAPLACE, Q1_V_ATOMIC, Q1_V_AUTO,
+                   Q1_V_LDS_TILE, Q1Error, check, last_error, lib)
+
+__all__ = [
+    "Q1Error", "Q1_LAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
+    "Q1_V_LDS_TILE", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
+    "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
+    "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_apply", "q1_op_diag",
+    "q1_op_info", "q1_op_bytes", "q1_op_destroy", "q1_model_bytes", "Op",
+]
+
+
+# ---- helpers -------------------------------------------------------------
+
+def _hptr(a: np.ndarray) -> ctypes.c_void_p:
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t) -> ctypes.c_void_p | None:
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda/HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def q1_version() -> int:
+    return lib().q1_version()
+
+
+# ---- generators (host) ---------------------------------------------------
+
+def q1_box_sizes(nx: int, ny: int, nz: int) -> tuple[int, int]:
+    nn, ne = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().q1_box_sizes(nx, ny, nz, ctypes.byref(nn), ctypes.byref(ne)))
+    return nn.value, ne.value
+
+
+def q1_box_mesh(nx, ny, nz, h=1.0, jitter_frac=0.0, seed=0):
+    nn, ne = q1_box_sizes(nx, ny, nz)
+    xyz = np.empty((3, nn)); conn = np.empty((8, ne), dtype=np.int32)
+    check(lib().q1_box_mesh(nx, ny, nz, h, jitter_frac, seed, _hptr(xyz), _hptr(conn)))
+    return xyz, conn
+
+
+def q1_face_mask(nx, ny, nz, face: int):
+    nn, _ = q1_box_sizes(nx, ny, nz)
+    m = np.empty(nn, dtype=np.uint8)
+    check(lib().q1_face_mask(nx, ny, nz, face, _hptr(m)))
+    return m
+
+
+def q1_field_lognormal(n, mu, sigma, seed, stream=1):
+    out = np.empty(n)
+    check(lib().q1_field_lognormal(n, mu, sigma, seed, stream, _hptr(out)))
+    return out
+
+
+def q1_field_layered(nx, ny, nz, layer_cells, s_layer, s_cell, seed):
+    out = np.empty(nx * ny * nz)
+    check(lib().q1_field_layered(nx, ny, nz, layer_cells, s_layer, s_cell, seed, _hptr(out)))
+    return out
+
+
+def q1_field_elastic(n, seed):
+    E = np.empty(n); nu = np.empty(n)
+    check(lib().q1_field_elastic(n, seed, _hptr(E), _hptr(nu)))
+    return E, nu
+
+
+def q1_lame_from_E_nu(E, nu):
+    E = np.ascontiguousarray(E, dtype=np.float64); nu = np.ascontiguousarray(nu, dtype=np.float64)
+    lam = np.empty_like(E); mu = np.empty_like(E)
+    check(lib().q1_lame_from_E_nu(E.size, _hptr(E), _hptr(nu), _hptr(lam), _hptr(mu)))
+    return lam, mu
+
+
+def q1_vec_uniform(n, seed, stream, lo=-1.0, hi=1.0):
+    out = np.empty(n)
+    check(lib().q1_vec_uniform(n, seed, stream, lo, hi, _hptr(out)))
+    return out
+
+
+def q1_model_bytes(kind: int, physics: int, real_bytes: int, coef_bytes: int, n_nodes: int,
+                   n_elems: int, cache: int) -> float:
+    b = ctypes.c_double()
+    check(lib().q1_model_bytes(kind, physics, real_bytes, coef_bytes, n_nodes, n_elems, cache,
+                               ctypes.byref(b)))
+    return b.value
+
+
+# ---- operators -----------------------------------------------------------
+
+class Op:
+    """Owning wrapper of a ``q1_op*``; keeps the referenced tensors alive."""
+
+    def __init__(self, handle: ctypes.c_void_p, keep: tuple):
+        self.handle = handle
+        self._keep = keep
+
+    def apply(self, x, y, stream=None):
+        return q1_op_apply(self, x, y, stream)
+
+    def diag(self, d, stream=None):
+        return q1_op_diag(self, d, stream)
+
+    def info(self):
+        return q1_op_info(self)
+
+    def bytes(self):
+        return q1_op_bytes(self)
+
+    def destroy(self):
+        if self.handle:
+            q1_op_destroy(self)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def q1_op_create(physics: int, dtype: int, variant: int, xyz, conn, coef, mask=None,
+                 stream=None) -> Op:
+    """xyz [3, n_nodes], conn int32 [8, n_elems], coef [ncoef, n_elems], mask uint8 [n_nodes]:
+    device tensors of the operator's dtype (conn and mask excepted)."""
+    h = ctypes.c_void_p()
+    n_nodes = xyz.shape[-1]
+    n_elems = conn.shape[-1]
+    check(lib().q1_op_create(ctypes.byref(h), physics, dtype, variant, n_nodes, n_elems,
+                             _dptr(xyz), _dptr(conn), _dptr(coef), _dptr(mask), _stream(stream)))
+    return Op(h, (xyz, conn, coef, mask))
+
+
+def q1_op_apply(op: Op, x, y, stream=None) -> None:
+    check(lib().q1_op_apply(op.handle, _dptr(x), _dptr(y), _stream(stream)))
+
+
+def q1_op_diag(op: Op, d, stream=None) -> None:
+    check(lib().q1_op_diag(op.handle, _dptr(d), _stream(stream)))
+
+
+def q1_op_info(op: Op) -> dict:
+    ph, dt, va = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    nn, ne = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().q1_op_info(op.handle, ctypes.byref(ph), ctypes.byref(dt), ctypes.byref(va),
+                           ctypes.byref(nn), ctypes.byref(ne)))
+    return dict(physics=ph.value, dtype=dt.value, variant=va.value, n_nodes=nn.value,
+                n_elems=ne.value)
+
+
+def q1_op_bytes(op: Op) -> tuple[float, float]:
+    b, f = ctypes.c_double(), ctypes.c_double()
+    check(lib().q1_op_bytes(op.handle, ctypes.byref(b), ctypes.byref(f)))
+    return b.value, f.value
+
+
+def q1_op_destroy(op: Op) -> None:
+    if op.handle:
+        check(lib().q1_op_destroy(op.handle))
+        op.handle = ctypes.c_void_p()

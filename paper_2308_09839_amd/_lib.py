@@ -1,0 +1,91 @@
+"""ctypes loader of libq1mf.so: argument marshalling only.
+
+The shared library is built in-tree by ``paper_2308_09839_amd.build``; this
+module refuses to run without it (there is no fallback implementation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libq1mf.so")
+
+Q1_OK = 0
+Q1_EINVAL = -1
+Q1_ENOMEM = -2
+Q1_EHIP = -3
+Q1_ENOCONV = -4
+Q1_EBREAKDOWN = -5
+Q1_EUNSUPPORTED = -6
+
+Q1_LAPLACE = 1
+Q1_ELASTICITY = 3
+Q1_F64 = 0
+Q1_F32 = 1
+Q1_V_AUTO = 0
+Q1_V_ATOMIC = 1
+Q1_V_LDS_TILE = 3
+
+_STATUS = {0: "Q1_OK", -1: "Q1_EINVAL", -2: "Q1_ENOMEM", -3: "Q1_EHIP", -4: "Q1_ENOCONV",
+           -5: "Q1_EBREAKDOWN", -6: "Q1_EUNSUPPORTED"}
+
+
+class Q1Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+c_int, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+P = ctypes.POINTER
+
+# name -> (restype, argtypes); the declarations of include/q1mf.h
+PROTOTYPES = {
+    "q1_last_error": (ctypes.c_char_p, []),
+    "q1_version": (c_int, []),
+    "q1_box_sizes": (c_int, [c_int, c_int, c_int, P(c_i64), P(c_i64)]),
+    "q1_box_mesh": (c_int, [c_int, c_int, c_int, c_dbl, c_dbl, c_u64, c_vp, c_vp]),
+    "q1_face_mask": (c_int, [c_int, c_int, c_int, c_int, c_vp]),
+    "q1_field_lognormal": (c_int, [c_i64, c_dbl, c_dbl, c_u64, c_u64, c_vp]),
+    "q1_field_layered": (c_int, [c_int, c_int, c_int, c_int, c_dbl, c_dbl, c_u64, c_vp]),
+    "q1_field_elastic": (c_int, [c_i64, c_u64, c_vp, c_vp]),
+    "q1_lame_from_E_nu": (c_int, [c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "q1_vec_uniform": (c_int, [c_i64, c_u64, c_u64, c_dbl, c_dbl, c_vp]),
+    "q1_op_create": (c_int, [P(c_vp), c_int, c_int, c_int, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp,
+                             c_vp]),
+    "q1_op_apply": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "q1_op_diag": (c_int, [c_vp, c_vp, c_vp]),
+    "q1_op_info": (c_int, [c_vp, P(c_int), P(c_int), P(c_int), P(c_i64), P(c_i64)]),
+    "q1_op_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
+    "q1_op_destroy": (c_int, [c_vp]),
+    "q1_model_bytes": (c_int, [c_int, c_int, c_int, c_int, c_i64, c_i64, c_int, P(c_dbl)]),
+}
+
+
+def lib():
+    """Load libq1mf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2308_09839_amd.build` (no fallback path exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().q1_last_error().decode(errors="replace")
+
+
+def check(rc: int) -> int:
+    if rc != Q1_OK:
+        raise Q1Error(rc, last_error())
+    return rc

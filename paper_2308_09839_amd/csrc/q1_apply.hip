@@ -1,0 +1,229 @@
+// Matrix-free apply y = A x and diagonal of the Q1 operators: the three steps
+// of Section 3 (gather u_e, local product v_e = A_e u_e, scatter-add v_e)
+// with the element arithmetic of q1_elem.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "q1_elem.hpp"
+#include "q1_internal.hpp"
+
+namespace q1 {
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so that neighbouring elements (which
+// share nodes) run behind the same L2.
+__device__ __forceinline__ int xcd_block(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, local = bid >> 3;
+  return x * q + min(x, r) + local;
+}
+
+// y = masked ? x : 0 (start of an accumulating apply)
+template <typename T, int DPN>
+__global__ void k_init_masked(int64_t n_nodes, const uint8_t *__restrict__ mask,
+                              const T *__restrict__ x, T *__restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_nodes * DPN) return;
+  y[i] = (mask && mask[i / DPN]) ? x[i] : T(0);
+}
+
+template <typename T, int DPN>
+__global__ void k_init_diag(int64_t n_nodes, const uint8_t *__restrict__ mask, T *__restrict__ d) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_nodes * DPN) return;
+  d[i] = (mask && mask[i / DPN]) ? T(1) : T(0);
+}
+
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// One thread per element, global atomics for the scatter (the paper's
+// one-thread-per-element strategy).
+template <typename T, int DPN, bool MASKED>
+__global__ __launch_bounds__(256) void k_apply_atomic(
+    int64_t ne, int64_t nn, const T *__restrict__ xyz, const int32_t *__restrict__ conn,
+    const T *__restrict__ coef, const uint8_t *__restrict__ mask, const T *__restrict__ x,
+    T *__restrict__ y) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t e = int64_t(blk) * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int32_t nid[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) nid[a] = conn[a * ne + e];
+  T X[3][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + nid[a]];
+  bool fixed[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) fixed[a] = MASKED ? (mask[nid[a]] != 0) : false;
+  if constexpr (DPN == 1) {
+    T u[8], v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[a] = fixed[a] ? T(0) : x[nid[a]];
+    laplace_element<T>(X, u, coef[e], v);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!fixed[a]) atomic_add(&y[nid[a]], v[a]);
+  } else {
+    T u[3][8], v[3][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * 3 + j];
+    elasticity_element<T>(X, u, coef[e], coef[ne + e], v);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!fixed[a])
+#pragma unroll
+        for (int j = 0; j < 3; ++j) atomic_add(&y[int64_t(nid[a]) * 3 + j], v[j][a]);
+  }
+}
+
+// Diagonal of A: d_(a,i) += sum_q w det J [element diagonal entry], i.e.
+// Laplace k |A'^T g'_a|^2 / (512 det'), elasticity
+// ((lambda + mu) t_i^2 + mu |t|^2) / (512 det') with t = A'^T g'_a.
+template <typename T, int DPN, bool MASKED>
+__global__ __launch_bounds__(256) void k_diag(int64_t ne, int64_t nn,
+                                              const T *__restrict__ xyz,
+                                              const int32_t *__restrict__ conn,
+                                              const T *__restrict__ coef,
+                                              const uint8_t *__restrict__ mask,
+                                              T *__restrict__ d) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int32_t nid[8];
+  T X[3][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    nid[a] = conn[a * ne + e];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + nid[a]];
+  }
+  butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
+  T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    eval4(X[r][1], X[r][3], X[r][5], X[r][7], Jx[r]);
+    eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);
+    eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);
+  }
+  T acc[8][DPN];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int i = 0; i < DPN; ++i) acc[a][i] = T(0);
+  const T c0 = coef[e];
+  const T c1 = DPN == 3 ? coef[ne + e] : T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+    const T jx[3] = {Jx[0][iy][iz], Jx[1][iy][iz], Jx[2][iy][iz]};
+    const T jy[3] = {Jy[0][ix][iz], Jy[1][ix][iz], Jy[2][ix][iz]};
+    const T jz[3] = {Jz[0][ix][iy], Jz[1][ix][iy], Jz[2][ix][iy]};
+    T a0[3], a1[3], a2[3];
+    cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
+    const T s = rcp(T(512) * dot3(jx, a0));
+    const T xi = (2 * ix - 1) * C<T>::g, eta = (2 * iy - 1) * C<T>::g,
+            zeta = (2 * iz - 1) * C<T>::g;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const T si = T(2 * (a & 1) - 1), sj = T(2 * ((a >> 1) & 1) - 1),
+              sk = T(2 * ((a >> 2) & 1) - 1);
+      // 8 * reference gradient of phi_a
+      const T g0 = si * (T(1) + sj * eta) * (T(1) + sk * zeta);
+      const T g1 = sj * (T(1) + si * xi) * (T(1) + sk * zeta);
+      const T g2 = sk * (T(1) + si * xi) * (T(1) + sj * eta);
+      T t[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[c] = g0 * a0[c] + g1 * a1[c] + g2 * a2[c];
+      const T tt = dot3(t, t);
+      if constexpr (DPN == 1) {
+        acc[a][0] += c0 * s * tt;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[a][i] += s * ((c0 + c1) * t[i] * t[i] + c1 * tt);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    if (MASKED && mask[nid[a]]) continue;
+#pragma unroll
+    for (int i = 0; i < DPN; ++i) atomic_add(&d[int64_t(nid[a]) * DPN + i], acc[a][i]);
+  }
+}
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n, int block) { return int((n + block - 1) / block); }
+
+template <typename T, int DPN>
+int apply_atomic(Op &op, const void *xv, void *yv, hipStream_t s) {
+  const T *x = static_cast<const T *>(xv);
+  T *y = static_cast<T *>(yv);
+  const int64_t ndof = op.n_nodes * DPN;
+  hipLaunchKernelGGL((k_init_masked<T, DPN>), dim3(grid_for(ndof, kBlock)), dim3(kBlock), 0, s,
+                     op.n_nodes, op.mask, x, y);
+  if (op.n_elems == 0) return Q1_OK;
+  const dim3 grid(grid_for(op.n_elems, kBlock));
+  const T *xyz = static_cast<const T *>(op.xyz);
+  const T *coef = static_cast<const T *>(op.coef);
+  if (op.mask)
+    hipLaunchKernelGGL((k_apply_atomic<T, DPN, true>), grid, dim3(kBlock), 0, s, op.n_elems,
+                       op.n_nodes, xyz, op.conn, coef, op.mask, x, y);
+  else
+    hipLaunchKernelGGL((k_apply_atomic<T, DPN, false>), grid, dim3(kBlock), 0, s, op.n_elems,
+                       op.n_nodes, xyz, op.conn, coef, op.mask, x, y);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+template <typename T, int DPN>
+int diag_impl(Op &op, void *dv, hipStream_t s) {
+  T *d = static_cast<T *>(dv);
+  const int64_t ndof = op.n_nodes * DPN;
+  hipLaunchKernelGGL((k_init_diag<T, DPN>), dim3(grid_for(ndof, kBlock)), dim3(kBlock), 0, s,
+                     op.n_nodes, op.mask, d);
+  if (op.n_elems > 0) {
+    const dim3 grid(grid_for(op.n_elems, kBlock));
+    const T *xyz = static_cast<const T *>(op.xyz);
+    const T *coef = static_cast<const T *>(op.coef);
+    if (op.mask)
+      hipLaunchKernelGGL((k_diag<T, DPN, true>), grid, dim3(kBlock), 0, s, op.n_elems,
+                         op.n_nodes, xyz, op.conn, coef, op.mask, d);
+    else
+      hipLaunchKernelGGL((k_diag<T, DPN, false>), grid, dim3(kBlock), 0, s, op.n_elems,
+                         op.n_nodes, xyz, op.conn, coef, op.mask, d);
+  }
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+}  // namespace
+
+int launch_apply(Op &op, const void *x, void *y, hipStream_t s) {
+  switch (op.variant) {
+    case Q1_V_ATOMIC:
+      if (op.dtype == Q1_F64)
+        return op.physics == 1 ? apply_atomic<double, 1>(op, x, y, s)
+                               : apply_atomic<double, 3>(op, x, y, s);
+      return op.physics == 1 ? apply_atomic<float, 1>(op, x, y, s)
+                             : apply_atomic<float, 3>(op, x, y, s);
+    default:
+      return fail(Q1_EUNSUPPORTED, "apply variant %d not available", op.variant);
+  }
+}
+
+int launch_diag(Op &op, void *d, hipStream_t s) {
+  if (op.dtype == Q1_F64)
+    return op.physics == 1 ? diag_impl<double, 1>(op, d, s) : diag_impl<double, 3>(op, d, s);
+  return op.physics == 1 ? diag_impl<float, 1>(op, d, s) : diag_impl<float, 3>(op, d, s);
+}
+
+}  // namespace q1

@@ -1,0 +1,317 @@
+// Element-level arithmetic of the Q1 hexahedral operators (device code).
+//
+// Local node a = i + 2j + 4k sits at reference corner (2i-1, 2j-1, 2k-1).
+// The Q1 space is spanned by the monomials psi_m = xi^mx eta^my zeta^mz,
+// m = mx + 2my + 4mz.  Nodal values u_a and (unscaled) modal coefficients
+// c_m = 8 * (coefficient of psi_m) are related by a 3-stage sum/difference
+// butterfly (the tensor product of [[1,1],[-1,1]]), so the reference gradient
+//   du/dxi = (c1 + c3 eta + c5 zeta + c7 eta zeta) / 8   (and cyclically)
+// is read off the modes, and 2x2x2 Gauss points (+-1/sqrt(3)) are reached by
+// 4-point evaluations.  This is the sum-factorised form of the per-quadrature
+// -point work of Algorithm 1 (Jacobian, inverse and determinant, gradient of
+// the input, flux, product with the test-function gradients).
+//
+// Scalings: with J' = 8J (columns from the coordinate modes), A' = adj(J'),
+// det' = det J', the scalar-Laplace reference flux times 1/8 (which folds the
+// inverse butterfly's factor) is  f = k / (512 det') A' A'^T g'  with g' the
+// unscaled modal gradient; the elasticity flux is
+// P = 1/(512 det') sigma'(H) A'^T with H = G' A' and
+// sigma'(H) = lambda tr(H) I + mu (H + H^T).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace q1 {
+
+template <typename T>
+struct C {
+  static constexpr T g = T(0.57735026918962576450914878050196);  // 1/sqrt(3)
+  static constexpr T g2 = T(1.0) / T(3.0);
+  static constexpr T third = T(1.0) / T(3.0);
+  static constexpr T ninth = T(1.0) / T(9.0);
+};
+
+// Reciprocal: hardware estimate refined by Newton steps to full precision.
+__device__ __forceinline__ double rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  float e = __builtin_fmaf(-d, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
+// nodal -> unscaled modal (in place)
+template <typename T>
+__device__ __forceinline__ void butterfly_fwd(T v[8]) {
+#pragma unroll
+  for (int a = 0; a < 8; a += 2) {
+    T s = v[a] + v[a + 1], d = v[a + 1] - v[a];
+    v[a] = s; v[a + 1] = d;
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int a = (b & 1) | ((b & 2) << 1);  // 0,1,4,5
+    T s = v[a] + v[a + 2], d = v[a + 2] - v[a];
+    v[a] = s; v[a + 2] = d;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    T s = v[a] + v[a + 4], d = v[a + 4] - v[a];
+    v[a] = s; v[a + 4] = d;
+  }
+}
+
+// transpose of the inverse butterfly, unscaled: per dimension (w0, w1) -> (w0 - w1, w0 + w1)
+template <typename T>
+__device__ __forceinline__ void butterfly_bwd(T v[8]) {
+#pragma unroll
+  for (int a = 0; a < 8; a += 2) {
+    T p = v[a], q = v[a + 1];
+    v[a] = p - q; v[a + 1] = p + q;
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int a = (b & 1) | ((b & 2) << 1);
+    T p = v[a], q = v[a + 2];
+    v[a] = p - q; v[a + 2] = p + q;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    T p = v[a], q = v[a + 4];
+    v[a] = p - q; v[a + 4] = p + q;
+  }
+}
+
+// out[iA][iB] = p0 + sA g p1 + sB g p2 + sA sB g^2 p3 with s = 2i - 1
+template <typename T>
+__device__ __forceinline__ void eval4(T p0, T p1, T p2, T p3, T out[2][2]) {
+  const T pp = p0 + C<T>::g2 * p3, pm = p0 - C<T>::g2 * p3;
+  const T q1 = C<T>::g * (p1 + p2), q2 = C<T>::g * (p1 - p2);
+  out[1][1] = pp + q1; out[0][0] = pp - q1;
+  out[1][0] = pm + q2; out[0][1] = pm - q2;
+}
+
+// transpose of eval4: r0 = sum F, r1 = g sum sA F, r2 = g sum sB F, r3 = g^2 sum sA sB F
+template <typename T>
+__device__ __forceinline__ void eval4T(const T F[2][2], T &r0, T &r1, T &r2, T &r3) {
+  const T spp = F[1][1] + F[0][0], smm = F[1][0] + F[0][1];
+  const T d1 = F[1][1] - F[0][0], d2 = F[1][0] - F[0][1];
+  r0 = spp + smm;
+  r3 = C<T>::g2 * (spp - smm);
+  r1 = C<T>::g * (d1 + d2);
+  r2 = C<T>::g * (d1 - d2);
+}
+
+template <typename T>
+__device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+template <typename T>
+__device__ __forceinline__ T dot3(const T a[3], const T b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Coordinates are affine images of the reference cube (a parallelepiped)
+// exactly when the bilinear and trilinear coordinate modes vanish.
+template <typename T>
+__device__ __forceinline__ bool is_affine(const T X[3][8]) {
+  bool z = true;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    z = z && X[r][3] == T(0) && X[r][5] == T(0) && X[r][6] == T(0) && X[r][7] == T(0);
+  return z;
+}
+
+// Geometry at one quadrature point from the modal coordinates:
+// J' columns jx, jy, jz; adj rows a0 = jy x jz, a1 = jz x jx, a2 = jx x jy.
+template <typename T>
+struct QpGeom {
+  T a0[3], a1[3], a2[3], det;
+};
+
+// ---------------------------------------------------------------------------
+// Scalar Laplace: X [3][8] nodal coordinates (destroyed), u [8] nodal input,
+// k cell coefficient; v [8] nodal output (v_e = A_e u_e).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void laplace_element(T X[3][8], const T u_in[8], T k, T v[8]) {
+  T u[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) u[a] = u_in[a];
+  butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
+  butterfly_fwd(u);
+  T w[8];
+  if (is_affine(X)) {
+    // constant Jacobian: exact modal integration of grad psi_m . D grad u
+    const T C1[3] = {X[0][1], X[1][1], X[2][1]};
+    const T C2[3] = {X[0][2], X[1][2], X[2][2]};
+    const T C4[3] = {X[0][4], X[1][4], X[2][4]};
+    T a0[3], a1[3], a2[3];
+    cross(C2, C4, a0); cross(C4, C1, a1); cross(C1, C2, a2);
+    const T det = dot3(C1, a0);
+    const T s = k * rcp(T(64) * det);
+    const T D00 = s * dot3(a0, a0), D01 = s * dot3(a0, a1), D02 = s * dot3(a0, a2);
+    const T D11 = s * dot3(a1, a1), D12 = s * dot3(a1, a2), D22 = s * dot3(a2, a2);
+    w[0] = T(0);
+    w[1] = D00 * u[1] + D01 * u[2] + D02 * u[4];
+    w[2] = D01 * u[1] + D11 * u[2] + D12 * u[4];
+    w[4] = D02 * u[1] + D12 * u[2] + D22 * u[4];
+    w[3] = C<T>::third * ((D00 + D11) * u[3] + D02 * u[6] + D12 * u[5]);
+    w[5] = C<T>::third * ((D00 + D22) * u[5] + D01 * u[6] + D12 * u[3]);
+    w[6] = C<T>::third * ((D11 + D22) * u[6] + D01 * u[5] + D02 * u[3]);
+    w[7] = C<T>::ninth * (D00 + D11 + D22) * u[7];
+  } else {
+    T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      eval4(X[r][1], X[r][3], X[r][5], X[r][7], Jx[r]);  // [iy][iz]
+      eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);  // [ix][iz]
+      eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);  // [ix][iy]
+    }
+    T gx[2][2], gy[2][2], gz[2][2];
+    eval4(u[1], u[3], u[5], u[7], gx);
+    eval4(u[2], u[3], u[6], u[7], gy);
+    eval4(u[4], u[5], u[6], u[7], gz);
+    T Fx[2][2] = {{0, 0}, {0, 0}}, Fy[2][2] = {{0, 0}, {0, 0}}, Fz[2][2] = {{0, 0}, {0, 0}};
+    const T ks = k * T(1.0 / 512.0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+      const T jx[3] = {Jx[0][iy][iz], Jx[1][iy][iz], Jx[2][iy][iz]};
+      const T jy[3] = {Jy[0][ix][iz], Jy[1][ix][iz], Jy[2][ix][iz]};
+      const T jz[3] = {Jz[0][ix][iy], Jz[1][ix][iy], Jz[2][ix][iy]};
+      T a0[3], a1[3], a2[3];
+      cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
+      const T s = ks * rcp(dot3(jx, a0));
+      const T g0 = gx[iy][iz], g1 = gy[ix][iz], g2 = gz[ix][iy];
+      T t[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[c] = s * (g0 * a0[c] + g1 * a1[c] + g2 * a2[c]);
+      Fx[iy][iz] += dot3(a0, t);
+      Fy[ix][iz] += dot3(a1, t);
+      Fz[ix][iy] += dot3(a2, t);
+    }
+    T r0, r1, r2, r3;
+    eval4T(Fx, r0, r1, r2, r3);
+    w[1] = r0; w[3] = r1; w[5] = r2; w[7] = r3;
+    eval4T(Fy, r0, r1, r2, r3);
+    w[2] = r0; w[3] += r1; w[6] = r2; w[7] += r3;
+    eval4T(Fz, r0, r1, r2, r3);
+    w[4] = r0; w[5] += r1; w[6] += r2; w[7] += r3;
+    w[0] = T(0);
+  }
+  butterfly_bwd(w);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) v[a] = w[a];
+}
+
+// ---------------------------------------------------------------------------
+// Isotropic elasticity: u [3][8] nodal displacement components (input),
+// v [3][8] output, cell Lame constants lam, mu.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void elasticity_element(T X[3][8], const T u_in[3][8], T lam, T mu,
+                                                   T v[3][8]) {
+  T u[3][8];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[j][a] = u_in[j][a];
+  butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
+  butterfly_fwd(u[0]); butterfly_fwd(u[1]); butterfly_fwd(u[2]);
+  const bool affine = is_affine(X);
+  // gradient modes at the quadrature points: G[j][dir][iA][iB]
+  T Gx[3][2][2], Gy[3][2][2], Gz[3][2][2];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    eval4(u[j][1], u[j][3], u[j][5], u[j][7], Gx[j]);
+    eval4(u[j][2], u[j][3], u[j][6], u[j][7], Gy[j]);
+    eval4(u[j][4], u[j][5], u[j][6], u[j][7], Gz[j]);
+  }
+  T Fx[3][2][2], Fy[3][2][2], Fz[3][2][2];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) Fx[j][p][q] = Fy[j][p][q] = Fz[j][p][q] = T(0);
+
+  T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    eval4(X[r][1], X[r][3], X[r][5], X[r][7], Jx[r]);
+    eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);
+    eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);
+  }
+  // affine elements: one geometry for all points
+  T ca0[3], ca1[3], ca2[3], cs = T(0);
+  if (affine) {
+    const T C1[3] = {X[0][1], X[1][1], X[2][1]};
+    const T C2[3] = {X[0][2], X[1][2], X[2][2]};
+    const T C4[3] = {X[0][4], X[1][4], X[2][4]};
+    cross(C2, C4, ca0); cross(C4, C1, ca1); cross(C1, C2, ca2);
+    cs = rcp(T(512) * dot3(C1, ca0));
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+    T a0[3], a1[3], a2[3], s;
+    if (affine) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { a0[c] = ca0[c]; a1[c] = ca1[c]; a2[c] = ca2[c]; }
+      s = cs;
+    } else {
+      const T jx[3] = {Jx[0][iy][iz], Jx[1][iy][iz], Jx[2][iy][iz]};
+      const T jy[3] = {Jy[0][ix][iz], Jy[1][ix][iz], Jy[2][ix][iz]};
+      const T jz[3] = {Jz[0][ix][iy], Jz[1][ix][iy], Jz[2][ix][iy]};
+      cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
+      s = rcp(T(512) * dot3(jx, a0));
+    }
+    // H = G' A'
+    T H[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T g0 = Gx[j][iy][iz], g1 = Gy[j][ix][iz], g2 = Gz[j][ix][iy];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) H[j][kk] = g0 * a0[kk] + g1 * a1[kk] + g2 * a2[kk];
+    }
+    const T ls = lam * s, ms = mu * s;
+    const T ltr = ls * (H[0][0] + H[1][1] + H[2][2]);
+    T S[3][3];
+    S[0][0] = ltr + T(2) * ms * H[0][0];
+    S[1][1] = ltr + T(2) * ms * H[1][1];
+    S[2][2] = ltr + T(2) * ms * H[2][2];
+    S[0][1] = S[1][0] = ms * (H[0][1] + H[1][0]);
+    S[0][2] = S[2][0] = ms * (H[0][2] + H[2][0]);
+    S[1][2] = S[2][1] = ms * (H[1][2] + H[2][1]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Fx[i][iy][iz] += S[i][0] * a0[0] + S[i][1] * a0[1] + S[i][2] * a0[2];
+      Fy[i][ix][iz] += S[i][0] * a1[0] + S[i][1] * a1[1] + S[i][2] * a1[2];
+      Fz[i][ix][iy] += S[i][0] * a2[0] + S[i][1] * a2[1] + S[i][2] * a2[2];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T w[8], r0, r1, r2, r3;
+    eval4T(Fx[i], r0, r1, r2, r3);
+    w[1] = r0; w[3] = r1; w[5] = r2; w[7] = r3;
+    eval4T(Fy[i], r0, r1, r2, r3);
+    w[2] = r0; w[3] += r1; w[6] = r2; w[7] += r3;
+    eval4T(Fz[i], r0, r1, r2, r3);
+    w[4] = r0; w[5] += r1; w[6] += r2; w[7] += r3;
+    w[0] = T(0);
+    butterfly_bwd(w);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[i][a] = w[a];
+  }
+}
+
+}  // namespace q1

@@ -1,0 +1,139 @@
+// Operator handles: creation, validation, dispatch and the byte/FLOP model.
+#include <hip/hip_runtime.h>
+
+#include <new>
+
+#include "q1_internal.hpp"
+
+namespace q1 {
+namespace {
+
+// Algorithmic FLOPs per element of the sum-factorised general-hexahedron apply
+// (Jacobian at 8 points, adjugate and determinant, gradient, flux, transpose).
+constexpr double kFlopsLaplace = 1070.0;
+constexpr double kFlopsElasticity = 2070.0;
+
+int check_device_ptr(const void *p, const char *what) {
+  if (!p) return fail(Q1_EINVAL, "%s is NULL", what);
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(Q1_EINVAL, "%s is not a device pointer (%s)", what, hipGetErrorString(e));
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(Q1_EINVAL, "%s is not device memory", what);
+  return Q1_OK;
+}
+
+}  // namespace
+}  // namespace q1
+
+using namespace q1;
+
+struct q1_op : public q1::Op {};
+
+extern "C" {
+
+int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nodes,
+                 int64_t n_elems, const void *xyz_d, const int32_t *conn_d, const void *coef_d,
+                 const uint8_t *mask_d, void *stream) {
+  Q1_CHECK(out, Q1_EINVAL, "q1_op_create: NULL handle pointer");
+  *out = nullptr;
+  Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_ELASTICITY, Q1_EINVAL,
+           "q1_op_create: physics must be 1 (Laplace) or 3 (elasticity), got %d", physics);
+  Q1_CHECK(dtype == Q1_F64 || dtype == Q1_F32, Q1_EINVAL, "q1_op_create: bad dtype %d", dtype);
+  Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC || variant == Q1_V_LDS_TILE,
+           Q1_EINVAL, "q1_op_create: bad variant %d", variant);
+  Q1_CHECK(n_nodes > 0 && n_nodes < (int64_t(1) << 31) && n_elems >= 0 &&
+               n_elems < (int64_t(1) << 31),
+           Q1_EINVAL, "q1_op_create: bad sizes n_nodes=%lld n_elems=%lld", (long long)n_nodes,
+           (long long)n_elems);
+  int rc;
+  if ((rc = check_device_ptr(xyz_d, "xyz"))) return rc;
+  if (n_elems > 0) {
+    if ((rc = check_device_ptr(conn_d, "conn"))) return rc;
+    if ((rc = check_device_ptr(coef_d, "coef"))) return rc;
+  }
+  if (mask_d && (rc = check_device_ptr(mask_d, "mask"))) return rc;
+  const size_t rb = dtype == Q1_F64 ? 8 : 4;
+  Q1_CHECK(reinterpret_cast<uintptr_t>(xyz_d) % rb == 0 &&
+               reinterpret_cast<uintptr_t>(coef_d) % rb == 0 &&
+               reinterpret_cast<uintptr_t>(conn_d) % 4 == 0,
+           Q1_EINVAL, "q1_op_create: misaligned array");
+  q1_op *op = new (std::nothrow) q1_op();
+  Q1_CHECK(op, Q1_ENOMEM, "q1_op_create: out of host memory");
+  op->physics = physics;
+  op->dtype = dtype;
+  op->variant = variant == Q1_V_AUTO ? Q1_V_ATOMIC : variant;
+  op->n_nodes = n_nodes;
+  op->n_elems = n_elems;
+  op->xyz = xyz_d;
+  op->conn = conn_d;
+  op->coef = coef_d;
+  op->mask = mask_d;
+  hipError_t e = hipGetDevice(&op->device);
+  if (e == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, op->device) == hipSuccess)
+      op->num_cus = prop.multiProcessorCount;
+  }
+  if (op->variant == Q1_V_LDS_TILE) {
+    rc = build_tiles(*op, static_cast<hipStream_t>(stream));
+    if (rc) {
+      free_tiles(*op);
+      delete op;
+      return rc;
+    }
+  }
+  *out = op;
+  return Q1_OK;
+}
+
+int q1_op_apply(q1_op *op, const void *x_d, void *y_d, void *stream) {
+  Q1_CHECK(op && x_d && y_d, Q1_EINVAL, "q1_op_apply: NULL argument");
+  Q1_CHECK(x_d != y_d, Q1_EINVAL, "q1_op_apply: x and y must not alias");
+  const size_t rb = op->dtype == Q1_F64 ? 8 : 4;
+  Q1_CHECK(reinterpret_cast<uintptr_t>(x_d) % rb == 0 &&
+               reinterpret_cast<uintptr_t>(y_d) % rb == 0,
+           Q1_EINVAL, "q1_op_apply: misaligned vector");
+  return launch_apply(*op, x_d, y_d, static_cast<hipStream_t>(stream));
+}
+
+int q1_op_diag(q1_op *op, void *d_d, void *stream) {
+  Q1_CHECK(op && d_d, Q1_EINVAL, "q1_op_diag: NULL argument");
+  return launch_diag(*op, d_d, static_cast<hipStream_t>(stream));
+}
+
+int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t *n_nodes,
+               int64_t *n_elems) {
+  Q1_CHECK(op, Q1_EINVAL, "q1_op_info: NULL handle");
+  if (physics) *physics = op->physics;
+  if (dtype) *dtype = op->dtype;
+  if (variant) *variant = op->variant;
+  if (n_nodes) *n_nodes = op->n_nodes;
+  if (n_elems) *n_elems = op->n_elems;
+  return Q1_OK;
+}
+
+int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
+  Q1_CHECK(op, Q1_EINVAL, "q1_op_bytes: NULL handle");
+  const int rb = op->dtype == Q1_F64 ? 8 : 4;
+  const int coef_bytes = rb * (op->physics == 1 ? 1 : 2);
+  double b = 0.0;
+  int rc = q1_model_bytes(1, op->physics, rb, coef_bytes, op->n_nodes, op->n_elems, 0, &b);
+  if (rc) return rc;
+  if (bytes) *bytes = b;
+  if (flops)
+    *flops = double(op->n_elems) * (op->physics == 1 ? kFlopsLaplace : kFlopsElasticity);
+  return Q1_OK;
+}
+
+int q1_op_destroy(q1_op *op) {
+  if (!op) return Q1_OK;
+  free_tiles(*op);
+  delete op;
+  return Q1_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+"""GPU parity of the matrix-free apply and diagonal against the CPU oracle.
+
+Bars: relative error <= 1e-12 for FP64 applies and <= 2e-5 for FP32
+applies (FP32 coordinates, coefficients, vectors and arithmetic compared with
+the FP64 oracle on the FP64 inputs)."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from helpers import (TOL, dev, gpu_apply, gpu_diag, make_op, problem, rel_err, rigid_modes,
+                     torch_dtype)
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [1]  # atomic scatter; extended as variants land
+
+
+@pytest.fixture(scope="module")
+def q1():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2308_09839_amd as q1
+    return q1
+
+
+CASES = [
+    # physics, elements, jitter, mask
+    (1, (16, 16, 16), 0.1, True),   # the 16^3 jittered validation problem
+    (1, (13, 11, 7), 0.1, True),    # ragged tail of a 256-element block
+    (1, (5, 3, 4), 0.0, False),     # undistorted (affine path), pure Neumann
+    (1, (1, 1, 1), 0.0, False),
+    (3, (8, 8, 8), 0.1, True),
+    (3, (13, 11, 7), 0.0, True),    # affine elasticity, ragged
+    (3, (3, 2, 2), 0.1, False),
+]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("physics,n,jitter,mask", CASES)
+def test_apply_parity(q1, orc, physics, n, jitter, mask, dtype, variant):
+    print(f"\n[apply parity] physics={physics} n={n} jitter={jitter} dtype={dtype} "
+          f"variant={variant}", flush=True)
+    pr = problem(physics, n, jitter, 2308, mask)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    x = si.vec_uniform(A.n, 2308, si.STREAM_X)
+    ref = A.matvec(x)
+    op = make_op(pr, dtype, variant)
+    y = gpu_apply(op, x, dtype)
+    err = rel_err(y, ref)
+    assert err <= TOL[dtype], err
+    assert np.max(np.abs(y - ref)) <= 10 * TOL[dtype] * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("physics,n", [(1, (1, 1, 1)), (1, (2, 2, 2)), (1, (3, 2, 2)),
+                                       (3, (1, 1, 1)), (3, (2, 2, 1))])
+def test_brute_force_dense(q1, orc, physics, n, variant):
+    """Apply to every unit vector: the columns form the assembled matrix."""
+    print(f"\n[dense] physics={physics} n={n}", flush=True)
+    import torch
+    pr = problem(physics, n, 0.1, 41, mask=True)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"]).to_dense()
+    op = make_op(pr, 0, variant)
+    N = A.shape[0]
+    cols = np.empty((N, N))
+    xd = torch.zeros(N, device="cuda", dtype=torch.float64)
+    yd = torch.empty_like(xd)
+    for j in range(N):
+        xd.zero_(); xd[j] = 1.0
+        op.apply(xd, yd)
+        cols[:, j] = yd.cpu().numpy()
+    assert np.max(np.abs(cols - A)) <= 1e-13 * np.max(np.abs(A))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_null_spaces(q1, orc, dtype):
+    print(f"\n[null spaces] dtype={dtype}", flush=True)
+    bound = 1e-13 if dtype == 0 else 2e-6
+    pr = problem(1, (9, 7, 6), 0.1, 43, mask=False)
+    op = make_op(pr, dtype)
+    nn = pr["xyz"].shape[1]
+    y = gpu_apply(op, np.ones(nn), dtype)
+    kmax = pr["coef"].max()
+    assert np.max(np.abs(y)) <= bound * kmax * 8
+    pr = problem(3, (5, 6, 4), 0.1, 44, mask=False)
+    op = make_op(pr, dtype)
+    A = orc.assemble(3, pr["xyz"], pr["conn"], pr["coef"])
+    scale = np.max(np.abs(A.val))
+    for u in rigid_modes(pr["xyz"]):
+        y = gpu_apply(op, u, dtype)
+        assert np.max(np.abs(y)) <= bound * scale * np.max(np.abs(u)) * 30
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("physics,n,jitter", [(1, (16, 16, 16), 0.1), (1, (7, 5, 3), 0.0),
+                                              (3, (7, 6, 5), 0.1), (3, (4, 4, 4), 0.0)])
+def test_diag_parity(q1, orc, physics, n, jitter, dtype):
+    print(f"\n[diag] physics={physics} n={n} dtype={dtype}", flush=True)
+    pr = problem(physics, n, jitter, 45, mask=True)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    d = gpu_diag(make_op(pr, dtype), A.n, dtype)
+    ref = A.diag()
+    assert np.max(np.abs(d - ref) / np.abs(ref)) <= (1e-13 if dtype == 0 else 2e-5)
+
+
+def test_full_size_laplace_sampled(q1, orc):
+    """128^3 undistorted layered-coefficient Laplace, FP64 and FP32, in the
+    benchmark's launch configuration: sampled rows against the oracle's
+    element-by-element rows, and A 1 = 0 over the whole grid."""
+    print("\n[full-size laplace 128^3]", flush=True)
+    pr = si.problem_laplace_layered(128, si.seed_for(1))
+    nn = pr["xyz"].shape[1]
+    x = si.vec_uniform(nn, si.seed_for(1), si.STREAM_X)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.integers(0, nn, 3000), [0, nn - 1, 129 * 129 * 64 + 64]]))
+    ref = orc.apply_rows(1, pr["xyz"], pr["conn"], pr["coef"], None, x, rows)
+    for dtype in (0, 1):
+        op = make_op(pr, dtype)
+        y = gpu_apply(op, x, dtype)
+        err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+        assert err <= TOL[dtype], (dtype, err)
+        y1 = gpu_apply(op, np.ones(nn), dtype)
+        assert np.max(np.abs(y1)) <= (1e-12 if dtype == 0 else 1e-4) * pr["coef"].max()
+        del op
+
+
+def test_full_size_elasticity_sampled(q1, orc):
+    print("\n[full-size elasticity 96^3]", flush=True)
+    pr = si.problem_elasticity(96, si.seed_for(2))
+    nn = pr["xyz"].shape[1]
+    x = si.vec_uniform(3 * nn, si.seed_for(2), si.STREAM_X)
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([rng.integers(0, 3 * nn, 3000), [0, 3 * nn - 1]]))
+    ref = orc.apply_rows(3, pr["xyz"], pr["conn"], pr["coef"], pr["mask"], x, rows)
+    for dtype in (0, 1):
+        op = make_op(pr, dtype)
+        y = gpu_apply(op, x, dtype)
+        err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+        assert err <= TOL[dtype], (dtype, err)
+        del op
+
+
+def test_empty_mesh_and_errors(q1):
+    import torch
+    print("\n[edge cases]", flush=True)
+    # no elements: y = x on masked nodes, 0 elsewhere
+    xyz = dev(np.zeros((3, 4)), torch.float64)
+    conn = torch.zeros((8, 0), dtype=torch.int32, device="cuda")
+    coef = torch.zeros((1, 0), dtype=torch.float64, device="cuda")
+    mask = dev(np.array([1, 0, 1, 0], dtype=np.uint8))
+    op = q1.q1_op_create(1, 0, 1, xyz, conn, coef, mask)
+    x = dev(np.array([1.0, 2.0, 3.0, 4.0]))
+    y = torch.full_like(x, 7.0)
+    op.apply(x, y)
+    assert y.cpu().tolist() == [1.0, 0.0, 3.0, 0.0]
+    with pytest.raises(q1.Q1Error) as ei:
+        op.apply(x, x)
+    assert ei.value.code == -1
+    # host memory is rejected
+    pr = problem(1, (2, 2, 2), 0.0, 1, mask=False)
+    t = torch_dtype(0)
+    with pytest.raises(q1.Q1Error):
+        import ctypes
+        h = ctypes.c_void_p()
+        xyz_h = np.ascontiguousarray(pr["xyz"])
+        rc = q1.lib().q1_op_create(ctypes.byref(h), 1, 0, 1, xyz_h.shape[1], 8,
+                                   xyz_h.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.c_void_p(dev(pr["conn"]).data_ptr()),
+                                   ctypes.c_void_p(dev(pr["coef"], t).data_ptr()), None, None)
+        q1._lib.check(rc)
+    with pytest.raises(q1.Q1Error):
+        q1.q1_op_create(2, 0, 1, dev(pr["xyz"], t), dev(pr["conn"]), dev(pr["coef"], t))

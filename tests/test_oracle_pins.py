@@ -383,3 +383,20 @@ def test_splitmix64_published_sequence():
 def test_normals_have_unit_moments():
     z = si.normal(5, 1, np.arange(200000, dtype=np.uint64))
     assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
+
+
+@pytest.mark.parametrize("physics", [1, 3])
+def test_apply_rows_equals_assembled_rows(orc, physics):
+    # the element-by-element row product and the assembled CSR product are two
+    # independent routes through the oracle's element matrices
+    n = (3, 2, 3)
+    xyz, conn = si.box_mesh(*n, 1.0, 0.1, 31)
+    ne = int(np.prod(n))
+    coef = (si.field_lognormal(ne, 0.0, 1.0, 31)[None] if physics == 1
+            else np.stack(si.lame_from_E_nu(*si.field_elastic(ne, 31))))
+    mask = si.face_mask(*n, "z0")
+    A = orc.assemble(physics, xyz, conn, coef, mask)
+    x = si.vec_uniform(A.n, 31, si.STREAM_X)
+    rows = np.arange(A.n)
+    y = orc.apply_rows(physics, xyz, conn, coef, mask, x, rows)
+    assert np.max(np.abs(y - A.matvec(x))) <= 1e-13 * np.max(np.abs(y))
