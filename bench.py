@@ -116,6 +116,8 @@ def main() -> int:
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 atomic, 3 LDS tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -148,6 +150,12 @@ def main() -> int:
         y = torch.empty_like(x)
         return op, x, y
 
+    if args.copy_ref_mb > 0:
+        a = torch.ones(args.copy_ref_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     op, x, y = make(pr, 0)
     info = op.info()
     alg_bytes, alg_flops = op.bytes()
@@ -157,6 +165,13 @@ def main() -> int:
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     extras = {}
     if not args.no_extras:
+        for v in (1, 3):
+            if v == info["variant"]:
+                continue
+            opv = q1.q1_op_create(1, 0, v, *upload(pr, 0))
+            msv, _ = time_applies(opv, x, y, args.steps, args.warmup)
+            extras[f"fp64_variant{v}_gdofs"] = round(ndof / (msv * 1e-3) / 1e9, 3)
+            del opv
         log("[bench] cold (flushed) applies")
         ms_cold = time_cold(op, x, y, 30)
         extras["fp64_cold_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)

@@ -215,6 +215,8 @@ int launch_apply(Op &op, const void *x, void *y, hipStream_t s) {
                                : apply_atomic<double, 3>(op, x, y, s);
       return op.physics == 1 ? apply_atomic<float, 1>(op, x, y, s)
                              : apply_atomic<float, 3>(op, x, y, s);
+    case Q1_V_LDS_TILE:
+      return launch_apply_tile(op, x, y, s);
     default:
       return fail(Q1_EUNSUPPORTED, "apply variant %d not available", op.variant);
   }

@@ -28,17 +28,19 @@ int fail(int code, const char *fmt, ...);
     if (!(cond)) return ::q1::fail((code), __VA_ARGS__);   \
   } while (0)
 
-// Per-tile data of the LDS-tiled apply (built once at operator creation).
+// Tiles of the LDS-tiled apply (built once at operator creation).
 struct TileMap {
   int n_tiles = 0;
-  int max_nodes = 0;     // largest node count of a tile (LDS sizing)
-  int tile_elems = 0;    // elements per tile (threads per workgroup)
-  int32_t *node_ptr = nullptr;   // [n_tiles+1] offsets into nodes
-  int32_t *nodes = nullptr;      // tile node lists (global node ids); sign bit set = shared node
-  int32_t *elem = nullptr;       // [n_tiles*tile_elems] global element id or -1
-  uint16_t *lconn = nullptr;     // [8][n_tiles*tile_elems] tile-local node index
-  int64_t n_shared = 0;          // number of distinct shared nodes
-  int32_t *shared = nullptr;     // [n_shared] shared global node ids (zeroed before apply)
+  int64_t n_steps = 0;            // steps of at most 64 elements (one wavefront)
+  int max_nodes = 0;              // LDS accumulator entries per tile
+  int32_t *node_ptr = nullptr;    // [n_tiles+1] node list of each tile
+  uint32_t *nodes = nullptr;      // global node ids | shared bit 31 | Dirichlet bit 30
+  int32_t *tile_step = nullptr;   // [n_tiles+1] step range of each tile
+  uint16_t *lconn = nullptr;      // [n_steps*64][8] corner indices into the tile list (0xffff: empty)
+  void *coef_t = nullptr;         // cell coefficients in lane order [ncoef][n_steps*64]
+  int64_t n_reset = 0;            // shared or Dirichlet nodes, reset before each apply
+  int32_t *reset = nullptr;
+  bool lds_atomic = false;        // corners collide within a step: accumulate with LDS atomics
   size_t bytes = 0;
 };
 
@@ -62,6 +64,7 @@ inline int xcd_count() { return 8; }
 int launch_apply(Op &op, const void *x, void *y, hipStream_t s);
 int launch_diag(Op &op, void *d, hipStream_t s);
 int build_tiles(Op &op, hipStream_t s);
+int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s);
 void free_tiles(Op &op);
 
 }  // namespace q1

@@ -1,21 +1,388 @@
-// LDS-tiled apply: set-up of the tile maps (placeholder until the tiled
-// kernels land; creation with this variant reports it as unsupported).
+// LDS-tiled apply: tile-resident accumulators.
+//
+// Set-up (once per operator, host).  Elements are grouped into tiles by their
+// centroids: an (x, y) patch of PATCH x PATCH elements and a z-range of
+// LAYERS element layers (an 8x8xLAYERS brick on a Cartesian grid).  A tile is
+// processed by ONE wavefront in steps of at most 64 elements (one per lane),
+// ordered by layer and then lexicographically.  Per tile the set-up stores the
+// sorted list of its distinct nodes (global id, plus a flag for nodes that
+// other tiles also touch and a flag for Dirichlet nodes), and per element the
+// 8 indices of its corners in that list.  Nothing depends on the mesh being
+// Cartesian; the grouping only decides how much reuse there is.
+//
+// Apply.  The wave clears an LDS accumulator for the tile's nodes; per step
+// each lane gathers its element's coordinates and input values from global
+// memory (neighbouring lanes share nodes, so the gathers coalesce and hit in
+// L2), computes the element product (Section 3, step 2; q1_elem.hpp) and adds
+// it into the accumulator.  After the last step the wave writes the tile's
+// nodes once (Section 3, step 3): plain stores for nodes owned by this tile
+// alone, global atomic adds for shared nodes.  The step loop issues no global
+// stores, so its load waits never queue behind writes.  A small kernel first
+// resets the shared and Dirichlet nodes (y = x on Dirichlet nodes, 0 on shared
+// ones).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "q1_elem.hpp"
 #include "q1_internal.hpp"
 
 namespace q1 {
 
-int build_tiles(Op &op, hipStream_t) {
-  (void)op;
-  return fail(Q1_EUNSUPPORTED, "LDS-tile variant not built yet");
+constexpr int kLanes = 64;
+constexpr uint32_t kSharedBit = 0x80000000u;
+constexpr uint32_t kFixedBit = 0x40000000u;
+constexpr uint32_t kIdMask = 0x3fffffffu;
+
+__device__ __forceinline__ int xcd_block_t(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, local = bid >> 3;
+  return x * q + min(x, r) + local;
+}
+
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(float *p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void gbl_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gbl_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// y on the reset list: x on Dirichlet nodes, 0 elsewhere
+template <typename T, int DPN>
+__global__ void k_reset_nodes(int64_t n, const int32_t *__restrict__ ids,
+                              const uint8_t *__restrict__ mask, const T *__restrict__ x,
+                              T *__restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t g = ids[i];
+  const bool fx = mask && mask[g];
+#pragma unroll
+  for (int j = 0; j < DPN; ++j) y[g * DPN + j] = fx ? x[g * DPN + j] : T(0);
+}
+
+// Accumulation: with LDS_ATOMIC the corner contributions are added with LDS
+// atomics; otherwise corner by corner with plain read-add-write, which the
+// set-up allows only when no two lanes of a step share a node at the same
+// local corner (true on any consistently numbered structured grid).
+template <typename T, bool LDS_ATOMIC>
+__device__ __forceinline__ void acc_add(T *p, T v) {
+  if constexpr (LDS_ATOMIC)
+    lds_add(p, v);
+  else
+    *p += v;
+}
+
+template <typename T, int DPN, bool LDS_ATOMIC>
+__global__ __launch_bounds__(64) void k_apply_tile(
+    int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,  // [n_tiles+1]
+    const uint32_t *__restrict__ nodes,                                 // ids | flags
+    const int32_t *__restrict__ tile_step,                              // [n_tiles+1]
+    const uint4 *__restrict__ lconn,                                    // [n_steps*64]
+    const T *__restrict__ coef_t, int64_t coef_stride, const T *__restrict__ xyz,
+    const T *__restrict__ x, T *__restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sV = reinterpret_cast<T *>(smem_raw);                             // [DPN][max_nodes]
+  uint32_t *sId = reinterpret_cast<uint32_t *>(sV + DPN * max_nodes);  // [max_nodes]
+  const int lane = threadIdx.x;
+  const int tile = xcd_block_t(blockIdx.x, gridDim.x);
+  const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
+  const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
+  // first step's corner indices and coefficients
+  uint4 pk_n = lconn[int64_t(s0) * kLanes + lane];
+  T c0_n = coef_t[int64_t(s0) * kLanes + lane];
+  T c1_n = DPN == 3 ? coef_t[coef_stride + int64_t(s0) * kLanes + lane] : T(0);
+  for (int i = lane; i < nm; i += kLanes) {
+    sId[i] = nodes[n0 + i];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) sV[j * max_nodes + i] = T(0);
+  }
+  __syncthreads();
+  for (int s = s0; s < s1; ++s) {
+    const uint4 pk = pk_n;
+    const T c0 = c0_n, c1 = c1_n;
+    {  // prefetch the next step's (clamped to this tile's last step)
+      const int64_t nslot = int64_t(min(s + 1, s1 - 1)) * kLanes + lane;
+      pk_n = lconn[nslot];
+      c0_n = coef_t[nslot];
+      if constexpr (DPN == 3) c1_n = coef_t[coef_stride + nslot];
+    }
+    if (pk.x == 0xffffffffu) continue;  // empty lane
+    const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16),
+                       int(pk.z & 0xffff), int(pk.z >> 16), int(pk.w & 0xffff), int(pk.w >> 16)};
+    int64_t g[8];
+    bool fixed[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const uint32_t raw = sId[lc[a]];
+      g[a] = raw & kIdMask;
+      fixed[a] = (raw & kFixedBit) != 0;
+    }
+    T X[3][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      X[0][a] = xyz[g[a]];
+      X[1][a] = xyz[nn + g[a]];
+      X[2][a] = xyz[2 * nn + g[a]];
+    }
+    if constexpr (DPN == 1) {
+      T u[8], v[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) u[a] = fixed[a] ? T(0) : x[g[a]];
+      laplace_element<T>(X, u, c0, v);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) acc_add<T, LDS_ATOMIC>(&sV[lc[a]], v[a]);
+    } else {
+      T u[3][8], v[3][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) u[j][a] = fixed[a] ? T(0) : x[g[a] * 3 + j];
+      elasticity_element<T>(X, u, c0, c1, v);
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc_add<T, LDS_ATOMIC>(&sV[j * max_nodes + lc[a]], v[j][a]);
+    }
+  }
+  __syncthreads();
+  for (int i = lane; i < nm; i += kLanes) {
+    const uint32_t raw = sId[i];
+    if (raw & kFixedBit) continue;  // y = x written by the reset kernel
+    const int64_t gg = raw & kIdMask;
+    if (raw & kSharedBit) {
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) gbl_add(&y[gg * DPN + j], sV[j * max_nodes + i]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) y[gg * DPN + j] = sV[j * max_nodes + i];
+    }
+  }
+}
+
+namespace {
+
+struct HostTiles {
+  std::vector<int32_t> node_ptr{0}, tile_step{0}, reset;
+  std::vector<uint32_t> nodes;
+  std::vector<uint16_t> lconn;
+  std::vector<int32_t> step_elem;  // element of each lane slot (-1 = empty)
+  int max_nodes = 0;
+  bool corner_collision = false;   // two lanes of a step share a node at one corner
+};
+
+// Group elements into tiles and steps; record node lists and corner indices.
+template <typename T>
+int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
+               const std::vector<uint8_t> &mask, int64_t nn, int64_t ne, int patch, int layers,
+               HostTiles &H) {
+  std::vector<double> cen(size_t(3) * ne);
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int64_t e = 0; e < ne; ++e)
+    for (int r = 0; r < 3; ++r) {
+      double c = 0;
+      for (int a = 0; a < 8; ++a) c += double(xyz[r * nn + conn[a * ne + e]]);
+      c *= 0.125;
+      cen[3 * e + r] = c;
+      lo[r] = std::min(lo[r], c);
+    }
+  // element size from the node bounding box
+  double vol = 1.0;
+  int live = 0;
+  for (int r = 0; r < 3; ++r) {
+    double nlo = 1e300, nhi = -1e300;
+    for (int64_t n = 0; n < nn; ++n) {
+      nlo = std::min(nlo, double(xyz[r * nn + n]));
+      nhi = std::max(nhi, double(xyz[r * nn + n]));
+    }
+    if (nhi > nlo) { vol *= nhi - nlo; ++live; }
+  }
+  double h = live ? std::pow(vol / double(ne), 1.0 / live) : 1.0;
+  if (!(h > 0)) h = 1.0;
+  std::vector<int32_t> lz(ne), iy(ne), ix(ne);
+  int64_t npx = 1, npy = 1;
+  for (int64_t e = 0; e < ne; ++e) {
+    ix[e] = int32_t(std::floor((cen[3 * e + 0] - lo[0]) / h + 0.5));
+    iy[e] = int32_t(std::floor((cen[3 * e + 1] - lo[1]) / h + 0.5));
+    lz[e] = int32_t(std::floor((cen[3 * e + 2] - lo[2]) / h + 0.5));
+    npx = std::max<int64_t>(npx, ix[e] / patch + 1);
+    npy = std::max<int64_t>(npy, iy[e] / patch + 1);
+  }
+  std::vector<uint64_t> tkey(ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    const uint64_t px = ix[e] / patch, py = iy[e] / patch, cz = lz[e] / layers;
+    tkey[e] = (cz * uint64_t(npy) + py) * uint64_t(npx) + px;
+  }
+  std::vector<int32_t> order(ne);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (tkey[a] != tkey[b]) return tkey[a] < tkey[b];
+    if (lz[a] != lz[b]) return lz[a] < lz[b];
+    if (iy[a] != iy[b]) return iy[a] < iy[b];
+    return ix[a] < ix[b];
+  });
+  // tiles = runs of equal tile key; steps = runs of one layer, <= 64 elements
+  std::vector<int64_t> tb;
+  for (int64_t k = 0; k < ne; ++k)
+    if (k == 0 || tkey[order[k]] != tkey[order[k - 1]]) tb.push_back(k);
+  tb.push_back(ne);
+  const int n_tiles = int(tb.size()) - 1;
+  std::vector<int32_t> stamp(nn, -1), ntile(nn, 0);
+  for (int t = 0; t < n_tiles; ++t)
+    for (int64_t k = tb[t]; k < tb[t + 1]; ++k)
+      for (int a = 0; a < 8; ++a) {
+        const int32_t g = conn[a * ne + order[k]];
+        if (stamp[g] != t) { stamp[g] = t; ++ntile[g]; }
+      }
+  for (int64_t n = 0; n < nn; ++n)
+    if (ntile[n] > 1 || (!mask.empty() && mask[n])) H.reset.push_back(int32_t(n));
+  std::vector<int32_t> local(nn, -1), list;
+  for (int t = 0; t < n_tiles; ++t) {
+    list.clear();
+    for (int64_t k = tb[t]; k < tb[t + 1]; ++k)
+      for (int a = 0; a < 8; ++a) list.push_back(conn[a * ne + order[k]]);
+    std::sort(list.begin(), list.end());
+    list.erase(std::unique(list.begin(), list.end()), list.end());
+    if (list.size() >= 65535) return fail(Q1_EUNSUPPORTED, "tile with %zu nodes", list.size());
+    H.max_nodes = std::max<int>(H.max_nodes, int(list.size()));
+    for (size_t i = 0; i < list.size(); ++i) {
+      const int32_t g = list[i];
+      local[g] = int32_t(i);
+      uint32_t v = uint32_t(g);
+      if (ntile[g] > 1) v |= kSharedBit;
+      if (!mask.empty() && mask[g]) v |= kFixedBit;
+      H.nodes.push_back(v);
+    }
+    H.node_ptr.push_back(int32_t(H.nodes.size()));
+    for (int64_t j = tb[t]; j < tb[t + 1];) {
+      int64_t je = j;
+      while (je < tb[t + 1] && lz[order[je]] == lz[order[j]] && je - j < kLanes) ++je;
+      for (int a = 0; a < 8 && !H.corner_collision; ++a) {
+        std::vector<int32_t> cs;
+        for (int64_t k = j; k < je; ++k) cs.push_back(conn[a * ne + order[k]]);
+        std::sort(cs.begin(), cs.end());
+        H.corner_collision = std::adjacent_find(cs.begin(), cs.end()) != cs.end();
+      }
+      for (int64_t k = j; k < j + kLanes; ++k) {
+        if (k < je) {
+          H.step_elem.push_back(order[k]);
+          for (int a = 0; a < 8; ++a) H.lconn.push_back(uint16_t(local[conn[a * ne + order[k]]]));
+        } else {
+          H.step_elem.push_back(-1);
+          for (int a = 0; a < 8; ++a) H.lconn.push_back(0xffff);
+        }
+      }
+      j = je;
+    }
+    H.tile_step.push_back(int32_t(H.step_elem.size() / kLanes));
+    for (int32_t g : list) local[g] = -1;
+  }
+  return Q1_OK;
+}
+
+template <typename T>
+int build_tiles_t(Op &op, hipStream_t s, int patch, int layers) {
+  const int64_t ne = op.n_elems, nn = op.n_nodes;
+  const int ncoef = op.physics == 1 ? 1 : 2;
+  TileMap &tm = op.tiles;
+  Q1_CHECK(nn <= int64_t(kIdMask), Q1_EUNSUPPORTED, "LDS-tile variant supports < 2^30 nodes");
+  Q1_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> conn(size_t(8) * ne);
+  std::vector<T> xyz(size_t(3) * nn), coef(size_t(ncoef) * ne);
+  std::vector<uint8_t> mask;
+  Q1_HIP(hipMemcpy(conn.data(), op.conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  Q1_HIP(hipMemcpy(xyz.data(), op.xyz, xyz.size() * sizeof(T), hipMemcpyDeviceToHost));
+  Q1_HIP(hipMemcpy(coef.data(), op.coef, coef.size() * sizeof(T), hipMemcpyDeviceToHost));
+  if (op.mask) {
+    mask.resize(nn);
+    Q1_HIP(hipMemcpy(mask.data(), op.mask, size_t(nn), hipMemcpyDeviceToHost));
+  }
+  for (size_t i = 0; i < conn.size(); ++i)
+    Q1_CHECK(conn[i] >= 0 && conn[i] < nn, Q1_EINVAL, "connectivity entry %zu out of range", i);
+  HostTiles H;
+  int rc = plan_tiles<T>(conn, xyz, mask, nn, ne, patch, layers, H);
+  if (rc) return rc;
+  const int64_t n_slots = int64_t(H.step_elem.size());
+  std::vector<T> coef_t(size_t(ncoef) * n_slots, T(0));
+  for (int64_t k = 0; k < n_slots; ++k)
+    if (H.step_elem[k] >= 0)
+      for (int c = 0; c < ncoef; ++c) coef_t[c * n_slots + k] = coef[c * ne + H.step_elem[k]];
+  tm.n_tiles = int(H.node_ptr.size()) - 1;
+  tm.n_steps = n_slots / kLanes;
+  tm.max_nodes = H.max_nodes;
+  tm.n_reset = int64_t(H.reset.size());
+  tm.lds_atomic = H.corner_collision;
+  auto up = [&](auto **dst, const auto &v) -> int {
+    using E = typename std::remove_reference<decltype(v)>::type::value_type;
+    const size_t b = std::max<size_t>(1, v.size()) * sizeof(E);
+    Q1_HIP(hipMalloc(reinterpret_cast<void **>(dst), b));
+    if (!v.empty()) Q1_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice));
+    tm.bytes += b;
+    return Q1_OK;
+  };
+  T *coef_dev = nullptr;
+  if ((rc = up(&tm.node_ptr, H.node_ptr)) || (rc = up(&tm.nodes, H.nodes)) ||
+      (rc = up(&tm.tile_step, H.tile_step)) || (rc = up(&tm.lconn, H.lconn)) ||
+      (rc = up(&tm.reset, H.reset)) || (rc = up(&coef_dev, coef_t)))
+    return rc;
+  tm.coef_t = coef_dev;
+  return Q1_OK;
+}
+
+template <typename T, int DPN>
+int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s) {
+  const TileMap &tm = op.tiles;
+  const T *x = static_cast<const T *>(xv);
+  T *y = static_cast<T *>(yv);
+  if (tm.n_reset > 0)
+    hipLaunchKernelGGL((k_reset_nodes<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
+                       s, tm.n_reset, tm.reset, op.mask, x, y);
+  const size_t lds = size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
+  auto kern = tm.lds_atomic ? k_apply_tile<T, DPN, true> : k_apply_tile<T, DPN, false>;
+  hipLaunchKernelGGL(kern, dim3(tm.n_tiles), dim3(kLanes), lds, s, tm.max_nodes, op.n_nodes,
+                     tm.node_ptr, tm.nodes, tm.tile_step,
+                     reinterpret_cast<const uint4 *>(tm.lconn),
+                     static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
+                     static_cast<const T *>(op.xyz), x, y);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+}  // namespace
+
+// Tile depth in element layers (an 8x8xLAYERS brick on a Cartesian grid).
+static int tile_layers(const Op &op) { return op.physics == 1 ? 8 : 4; }
+
+int build_tiles(Op &op, hipStream_t s) {
+  Q1_CHECK(op.n_elems > 0, Q1_EUNSUPPORTED, "LDS-tile variant needs at least one element");
+  const int layers = tile_layers(op);
+  int rc = op.dtype == Q1_F64 ? build_tiles_t<double>(op, s, 8, layers)
+                              : build_tiles_t<float>(op, s, 8, layers);
+  if (rc) return rc;
+  const size_t lds = size_t(op.tiles.max_nodes) *
+                     (op.physics * (op.dtype == Q1_F64 ? 8 : 4) + 4);
+  Q1_CHECK(lds <= 64 * 1024, Q1_EUNSUPPORTED, "tile needs %zu B of LDS", lds);
+  return Q1_OK;
+}
+
+int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s) {
+  if (op.dtype == Q1_F64)
+    return op.physics == 1 ? apply_tile_t<double, 1>(op, x, y, s)
+                           : apply_tile_t<double, 3>(op, x, y, s);
+  return op.physics == 1 ? apply_tile_t<float, 1>(op, x, y, s)
+                         : apply_tile_t<float, 3>(op, x, y, s);
 }
 
 void free_tiles(Op &op) {
   TileMap &t = op.tiles;
-  if (t.node_ptr) (void)hipFree(t.node_ptr);
-  if (t.nodes) (void)hipFree(t.nodes);
-  if (t.elem) (void)hipFree(t.elem);
-  if (t.lconn) (void)hipFree(t.lconn);
-  if (t.shared) (void)hipFree(t.shared);
+  void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset, t.coef_t};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
   t = TileMap{};
 }
 

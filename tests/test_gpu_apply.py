@@ -12,7 +12,7 @@ from helpers import (TOL, dev, gpu_apply, gpu_diag, make_op, problem, rel_err, r
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [1]  # atomic scatter; extended as variants land
+VARIANTS = [1, 3]  # atomic scatter, LDS tiles
 
 
 @pytest.fixture(scope="module")
@@ -73,18 +73,19 @@ def test_brute_force_dense(q1, orc, physics, n, variant):
     assert np.max(np.abs(cols - A)) <= 1e-13 * np.max(np.abs(A))
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("dtype", [0, 1])
-def test_null_spaces(q1, orc, dtype):
+def test_null_spaces(q1, orc, dtype, variant):
     print(f"\n[null spaces] dtype={dtype}", flush=True)
     bound = 1e-13 if dtype == 0 else 2e-6
     pr = problem(1, (9, 7, 6), 0.1, 43, mask=False)
-    op = make_op(pr, dtype)
+    op = make_op(pr, dtype, variant)
     nn = pr["xyz"].shape[1]
     y = gpu_apply(op, np.ones(nn), dtype)
     kmax = pr["coef"].max()
     assert np.max(np.abs(y)) <= bound * kmax * 8
     pr = problem(3, (5, 6, 4), 0.1, 44, mask=False)
-    op = make_op(pr, dtype)
+    op = make_op(pr, dtype, variant)
     A = orc.assemble(3, pr["xyz"], pr["conn"], pr["coef"])
     scale = np.max(np.abs(A.val))
     for u in rigid_modes(pr["xyz"]):
@@ -104,7 +105,8 @@ def test_diag_parity(q1, orc, physics, n, jitter, dtype):
     assert np.max(np.abs(d - ref) / np.abs(ref)) <= (1e-13 if dtype == 0 else 2e-5)
 
 
-def test_full_size_laplace_sampled(q1, orc):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_size_laplace_sampled(q1, orc, variant):
     """128^3 undistorted layered-coefficient Laplace, FP64 and FP32, in the
     benchmark's launch configuration: sampled rows against the oracle's
     element-by-element rows, and A 1 = 0 over the whole grid."""
@@ -116,7 +118,7 @@ def test_full_size_laplace_sampled(q1, orc):
     rows = np.unique(np.concatenate([rng.integers(0, nn, 3000), [0, nn - 1, 129 * 129 * 64 + 64]]))
     ref = orc.apply_rows(1, pr["xyz"], pr["conn"], pr["coef"], None, x, rows)
     for dtype in (0, 1):
-        op = make_op(pr, dtype)
+        op = make_op(pr, dtype, variant)
         y = gpu_apply(op, x, dtype)
         err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
         assert err <= TOL[dtype], (dtype, err)
@@ -125,7 +127,8 @@ def test_full_size_laplace_sampled(q1, orc):
         del op
 
 
-def test_full_size_elasticity_sampled(q1, orc):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_size_elasticity_sampled(q1, orc, variant):
     print("\n[full-size elasticity 96^3]", flush=True)
     pr = si.problem_elasticity(96, si.seed_for(2))
     nn = pr["xyz"].shape[1]
@@ -134,7 +137,7 @@ def test_full_size_elasticity_sampled(q1, orc):
     rows = np.unique(np.concatenate([rng.integers(0, 3 * nn, 3000), [0, 3 * nn - 1]]))
     ref = orc.apply_rows(3, pr["xyz"], pr["conn"], pr["coef"], pr["mask"], x, rows)
     for dtype in (0, 1):
-        op = make_op(pr, dtype)
+        op = make_op(pr, dtype, variant)
         y = gpu_apply(op, x, dtype)
         err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
         assert err <= TOL[dtype], (dtype, err)
