@@ -94,8 +94,9 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
  *            one-thread-per-element strategy, Section 6);
  *   LDS_TILE element tiles with their nodes staged in LDS, accumulation in LDS,
  *            global atomics only for nodes shared with other tiles;
- *   AUTO     the fastest measured strategy for the operator. */
-enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_LDS_TILE = 3 };
+ *   AUTO     the fastest measured strategy for the operator;
+ *   CSR      the assembled matrix (made by q1_csr_create only). */
+enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_LDS_TILE = 3, Q1_V_CSR = 4 };
 
 /* Create an operator over caller-owned device arrays.  The arrays are
  * referenced, not copied: they must stay valid and unchanged until
@@ -117,10 +118,76 @@ int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t 
 /* Algorithmic bytes and FLOPs of one apply under the Table 2 convention with
  * perfect caching: 32 B of node ids and the cell coefficients per element;
  * the coordinates plus three vector streams (x read, y read, y write) per
- * node.  FLOPs: the fixed per-element counts of the sum-factorised apply. */
+ * node.  FLOPs: the fixed per-element counts of the sum-factorised apply.
+ * For a CSR operator: values and column indices per non-zero, row pointer,
+ * x read and y write per row (Table 1 convention), 2 FLOPs per non-zero. */
 int q1_op_bytes(const q1_op *op, double *algorithmic_bytes, double *algorithmic_flops);
 /* Destroy the handle and its internal workspace (not the caller's arrays). */
 int q1_op_destroy(q1_op *op);
+
+/* ---- matrix-based comparison (Section 1 and Table 1: SpMV; Section 3: the
+ *      fill by column search and atomic addition) ---------------------------
+ * q1_csr_create assembles the operator `like` describes into CSR on the device
+ * (pattern on the host from the connectivity, values by an element loop that
+ * binary-searches each column and adds atomically, then the symmetric
+ * Dirichlet elimination) and returns a new operator whose apply is the SpMV.
+ * It references the same caller arrays as `like`.  Returns Q1_EUNSUPPORTED
+ * for 2^31 or more non-zeros.  Synchronises `stream`. */
+int q1_csr_create(q1_op **op_csr, const q1_op *like, void *stream);
+/* Rows and non-zeros of a CSR operator. */
+int q1_csr_info(const q1_op *op_csr, int64_t *nrows, int64_t *nnz);
+/* Copy the matrix to caller HOST arrays rowptr [nrows+1], col [nnz], val [nnz]
+ * (operator dtype); any of them may be NULL.  Synchronous. */
+int q1_csr_export(const q1_op *op_csr, int32_t *rowptr, int32_t *col, void *val);
+
+/* ---- Krylov solvers (the CG operations of Table 4) ------------------------
+ * Vectors b_d and x_d have the operator's dtype; every dot product
+ * accumulates in FP64 and is deterministic (fixed reduction order, no
+ * atomics).  x0 = 0; convergence when ||r_k||_2 <= rtol ||b||_2 on the
+ * recurrence residual.  The calls synchronise `stream` and return Q1_OK,
+ * Q1_ENOCONV (x holds the last iterate) or Q1_EBREAKDOWN (p^T A p <= 0 or a
+ * non-finite scalar); st (may be NULL) is filled in every case. */
+typedef struct {
+  int iters;           /* Krylov iterations (inner iterations summed for IR) */
+  int status;          /* return code of the solve */
+  double rel_res;      /* recurrence (or outer) residual ||r||/||b|| */
+  double true_rel_res; /* ||b - A x||/||b|| recomputed at the end */
+  double seconds;      /* host wall time of the solve, set-up included */
+  int fallback_at;     /* flexible PCG: iteration of the switch to Jacobi, -1 if none */
+  int outer_iters;     /* iterative refinement: outer steps */
+} q1_stats;
+enum { Q1_PC_NONE = 0, Q1_PC_JACOBI = 1 };
+
+/* Preconditioned CG (Hestenes-Stiefel) with z = D^{-1} r (Jacobi, D the
+ * matrix-free diagonal) or z = r. */
+int q1_pcg(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit,
+           q1_stats *st, void *stream);
+
+/* A preconditioner callback: enqueue z = M(r) on `stream` (device vectors of
+ * the operator's dtype) and return Q1_OK, or any other value to report
+ * failure. */
+typedef int (*q1_precond_fn)(void *ctx, const void *r_d, void *z_d, void *stream);
+/* Flexible PCG (beta = z_{k+1}^T (r_{k+1} - r_k) / (r_k^T z_k)) with a
+ * variable preconditioner M.  Safeguard: on a failing call, z^T r <= 0, a
+ * non-finite value, or no decrease of ||r|| over safeguard_m iterations
+ * (0 = off), the solve continues with Jacobi; st->fallback_at records when. */
+int q1_fpcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,
+            int maxit, int safeguard_m, q1_stats *st, void *stream);
+
+/* Jacobi preconditioner object, usable as the ctx of q1_precond_jacobi. */
+typedef struct q1_jacobi q1_jacobi;
+int q1_jacobi_create(q1_jacobi **J, q1_op *op, void *stream);
+int q1_precond_jacobi(void *ctx, const void *r_d, void *z_d, void *stream);
+int q1_jacobi_destroy(q1_jacobi *J);
+
+/* Mixed-precision iterative refinement: r = b - A64 x in FP64; s = r/||r||
+ * rounded to FP32; Jacobi-PCG with the FP32 operator, FP32 vectors and FP64
+ * dots solves A32 d = s to inner_rtol (at most max_inner iterations); then
+ * x += ||r|| d in FP64; until ||r|| <= rtol ||b||.  op64 and op32 describe the
+ * same operator (Q1_F64 and Q1_F32).  Returns Q1_EBREAKDOWN if an outer step
+ * does not reduce ||r||, Q1_ENOCONV after max_outer steps.  b_d, x_d: FP64. */
+int q1_ir_solve(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
+                double inner_rtol, int max_outer, int max_inner, q1_stats *st, void *stream);
 
 /* Byte model of Section 4 (Tables 1-3) for n_elems hexahedra and n_nodes
  * nodes.  kind: 0 SpMV (Table 1: 12 B per non-zero with 27*dpn non-zeros per

@@ -12,12 +12,14 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (Q1_ELASTICITY, Q1_F32, Q1_F64, Q1_LAPLACE, Q1_V_ATOMIC, Q1_V_AUTO,
-                   Q1_V_LDS_TILE, Q1Error, check, last_error, lib)
+from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32, Q1_F64,
+                   Q1_LAPLACE, Q1_OK, Q1_PC_JACOBI, Q1_PC_NONE, Q1_V_ATOMIC, Q1_V_AUTO, Q1_V_CSR,
+                   Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
-    "Q1Error", "Q1_LAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
-    "Q1_V_LDS_TILE", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
+    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_fpcg", "q1_ir_solve", "Jacobi",
+    "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
+    "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
     "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_apply", "q1_op_diag",
     "q1_op_info", "q1_op_bytes", "q1_op_destroy", "q1_model_bytes", "Op",
@@ -186,3 +188,101 @@ def q1_op_destroy(op: Op) -> None:
     if op.handle:
         check(lib().q1_op_destroy(op.handle))
         op.handle = ctypes.c_void_p()
+
+
+# ---- CSR comparison --------------------------------------------------------
+
+def q1_csr_create(like: Op, stream=None) -> Op:
+    h = ctypes.c_void_p()
+    check(lib().q1_csr_create(ctypes.byref(h), like.handle, _stream(stream)))
+    return Op(h, like._keep)
+
+
+def q1_csr_info(op: Op) -> tuple[int, int]:
+    nr, nz = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().q1_csr_info(op.handle, ctypes.byref(nr), ctypes.byref(nz)))
+    return nr.value, nz.value
+
+
+def q1_csr_export(op: Op):
+    """(rowptr int32, col int32, val) as host numpy arrays."""
+    nr, nz = q1_csr_info(op)
+    info = q1_op_info(op)
+    rowptr = np.empty(nr + 1, dtype=np.int32)
+    col = np.empty(nz, dtype=np.int32)
+    val = np.empty(nz, dtype=np.float64 if info["dtype"] == Q1_F64 else np.float32)
+    check(lib().q1_csr_export(op.handle, _hptr(rowptr), _hptr(col), _hptr(val)))
+    return rowptr, col, val
+
+
+# ---- solvers ---------------------------------------------------------------
+
+def _solve_rc(rc: int) -> int:
+    """Non-convergence and breakdown are outcomes reported in the stats."""
+    if rc not in (Q1_OK, Q1_ENOCONV, Q1_EBREAKDOWN):
+        check(rc)
+    return rc
+
+
+def q1_pcg(op: Op, pc: int, b, x, rtol: float, maxit: int, stream=None) -> dict:
+    st = Q1Stats()
+    _solve_rc(lib().q1_pcg(op.handle, pc, _dptr(b), _dptr(x), rtol, maxit, ctypes.byref(st),
+                           _stream(stream)))
+    return st.as_dict()
+
+
+class Jacobi:
+    """Device Jacobi preconditioner (z = D^{-1} r) usable with q1_fpcg."""
+
+    def __init__(self, op: Op, stream=None):
+        self.handle = ctypes.c_void_p()
+        check(lib().q1_jacobi_create(ctypes.byref(self.handle), op.handle, _stream(stream)))
+        self._op = op
+        self.fn = ctypes.cast(lib().q1_precond_jacobi, ctypes.c_void_p)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().q1_jacobi_destroy(self.handle)
+                self.handle = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+def q1_jacobi_create(op: Op, stream=None) -> Jacobi:
+    return Jacobi(op, stream)
+
+
+def q1_fpcg(op: Op, precond, b, x, rtol: float, maxit: int, safeguard_m: int = 0,
+            stream=None) -> dict:
+    """precond: a Jacobi/learned preconditioner object with .fn and .handle, a
+    (function pointer, ctx) pair, or a Python callable f(r_ptr, z_ptr, stream_ptr) -> int
+    that enqueues z = M(r) on the stream."""
+    keep = None
+    if hasattr(precond, "fn") and hasattr(precond, "handle"):
+        fn, ctx = precond.fn, precond.handle
+    elif isinstance(precond, tuple):
+        fn, ctx = precond
+    elif precond is None:
+        fn, ctx = None, None
+    else:
+        def _cb(_ctx, r, z, s, _f=precond):
+            try:
+                return int(_f(r, z, s))
+            except Exception:
+                return -1
+        keep = PRECOND_FN(_cb)
+        fn, ctx = ctypes.cast(keep, ctypes.c_void_p), None
+    st = Q1Stats()
+    _solve_rc(lib().q1_fpcg(op.handle, fn, ctx, _dptr(b), _dptr(x), rtol, maxit, safeguard_m,
+                            ctypes.byref(st), _stream(stream)))
+    del keep
+    return st.as_dict()
+
+
+def q1_ir_solve(op64: Op, op32: Op, b, x, rtol: float, inner_rtol: float = 1e-4,
+                max_outer: int = 50, max_inner: int = 20000, stream=None) -> dict:
+    st = Q1Stats()
+    _solve_rc(lib().q1_ir_solve(op64.handle, op32.handle, _dptr(b), _dptr(x), rtol, inner_rtol,
+                                max_outer, max_inner, ctypes.byref(st), _stream(stream)))
+    return st.as_dict()

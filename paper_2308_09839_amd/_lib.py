@@ -26,6 +26,23 @@ Q1_F32 = 1
 Q1_V_AUTO = 0
 Q1_V_ATOMIC = 1
 Q1_V_LDS_TILE = 3
+Q1_V_CSR = 4
+
+Q1_PC_NONE = 0
+Q1_PC_JACOBI = 1
+
+
+class Q1Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("fallback_at", ctypes.c_int), ("outer_iters", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PRECOND_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_void_p)
 
 _STATUS = {0: "Q1_OK", -1: "Q1_EINVAL", -2: "Q1_ENOMEM", -3: "Q1_EHIP", -4: "Q1_ENOCONV",
            -5: "Q1_EBREAKDOWN", -6: "Q1_EUNSUPPORTED"}
@@ -62,6 +79,15 @@ PROTOTYPES = {
     "q1_op_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
     "q1_op_destroy": (c_int, [c_vp]),
     "q1_model_bytes": (c_int, [c_int, c_int, c_int, c_int, c_i64, c_i64, c_int, P(c_dbl)]),
+    "q1_csr_create": (c_int, [P(c_vp), c_vp, c_vp]),
+    "q1_csr_info": (c_int, [c_vp, P(c_i64), P(c_i64)]),
+    "q1_csr_export": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "q1_pcg": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, P(Q1Stats), c_vp]),
+    "q1_fpcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),
+    "q1_jacobi_create": (c_int, [P(c_vp), c_vp, c_vp]),
+    "q1_precond_jacobi": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "q1_jacobi_destroy": (c_int, [c_vp]),
+    "q1_ir_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),
 }
 
 

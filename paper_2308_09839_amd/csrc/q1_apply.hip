@@ -23,7 +23,9 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk) {
 // y = masked ? x : 0 (start of an accumulating apply)
 template <typename T, int DPN>
 __global__ void k_init_masked(int64_t n_nodes, const uint8_t *__restrict__ mask,
-                              const T *__restrict__ x, T *__restrict__ y) {
+                              const T *__restrict__ x, T *__restrict__ y,
+                              const int *__restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n_nodes * DPN) return;
   y[i] = (mask && mask[i / DPN]) ? x[i] : T(0);
@@ -45,7 +47,8 @@ template <typename T, int DPN, bool MASKED>
 __global__ __launch_bounds__(256) void k_apply_atomic(
     int64_t ne, int64_t nn, const T *__restrict__ xyz, const int32_t *__restrict__ conn,
     const T *__restrict__ coef, const uint8_t *__restrict__ mask, const T *__restrict__ x,
-    T *__restrict__ y) {
+    T *__restrict__ y, const int *__restrict__ stop) {
+  if (stop && *stop) return;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t e = int64_t(blk) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
@@ -164,22 +167,22 @@ constexpr int kBlock = 256;
 inline int grid_for(int64_t n, int block) { return int((n + block - 1) / block); }
 
 template <typename T, int DPN>
-int apply_atomic(Op &op, const void *xv, void *yv, hipStream_t s) {
+int apply_atomic(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
   const int64_t ndof = op.n_nodes * DPN;
   hipLaunchKernelGGL((k_init_masked<T, DPN>), dim3(grid_for(ndof, kBlock)), dim3(kBlock), 0, s,
-                     op.n_nodes, op.mask, x, y);
+                     op.n_nodes, op.mask, x, y, stop);
   if (op.n_elems == 0) return Q1_OK;
   const dim3 grid(grid_for(op.n_elems, kBlock));
   const T *xyz = static_cast<const T *>(op.xyz);
   const T *coef = static_cast<const T *>(op.coef);
   if (op.mask)
     hipLaunchKernelGGL((k_apply_atomic<T, DPN, true>), grid, dim3(kBlock), 0, s, op.n_elems,
-                       op.n_nodes, xyz, op.conn, coef, op.mask, x, y);
+                       op.n_nodes, xyz, op.conn, coef, op.mask, x, y, stop);
   else
     hipLaunchKernelGGL((k_apply_atomic<T, DPN, false>), grid, dim3(kBlock), 0, s, op.n_elems,
-                       op.n_nodes, xyz, op.conn, coef, op.mask, x, y);
+                       op.n_nodes, xyz, op.conn, coef, op.mask, x, y, stop);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
@@ -207,16 +210,18 @@ int diag_impl(Op &op, void *dv, hipStream_t s) {
 
 }  // namespace
 
-int launch_apply(Op &op, const void *x, void *y, hipStream_t s) {
+int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
   switch (op.variant) {
     case Q1_V_ATOMIC:
       if (op.dtype == Q1_F64)
-        return op.physics == 1 ? apply_atomic<double, 1>(op, x, y, s)
-                               : apply_atomic<double, 3>(op, x, y, s);
-      return op.physics == 1 ? apply_atomic<float, 1>(op, x, y, s)
-                             : apply_atomic<float, 3>(op, x, y, s);
+        return op.physics == 1 ? apply_atomic<double, 1>(op, x, y, s, stop)
+                               : apply_atomic<double, 3>(op, x, y, s, stop);
+      return op.physics == 1 ? apply_atomic<float, 1>(op, x, y, s, stop)
+                             : apply_atomic<float, 3>(op, x, y, s, stop);
     case Q1_V_LDS_TILE:
-      return launch_apply_tile(op, x, y, s);
+      return launch_apply_tile(op, x, y, s, stop);
+    case Q1_V_CSR:
+      return launch_spmv(op, x, y, s, stop);
     default:
       return fail(Q1_EUNSUPPORTED, "apply variant %d not available", op.variant);
   }

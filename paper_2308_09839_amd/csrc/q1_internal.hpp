@@ -44,6 +44,14 @@ struct TileMap {
   size_t bytes = 0;
 };
 
+// Assembled CSR matrix of the matrix-based comparison.
+struct CsrData {
+  int64_t nrows = 0, nnz = 0;
+  int32_t *rowptr = nullptr;  // [nrows+1]
+  int32_t *col = nullptr;     // [nnz], sorted within each row
+  void *val = nullptr;        // [nnz] of the operator's dtype
+};
+
 struct Op {
   int physics = 1;  // DOF per node
   int dtype = Q1_F64;
@@ -56,15 +64,20 @@ struct Op {
   int device = 0;
   int num_cus = 256;
   TileMap tiles;
+  CsrData csr;
 };
 
 inline int xcd_count() { return 8; }
 
 // launchers (defined in the .hip files)
-int launch_apply(Op &op, const void *x, void *y, hipStream_t s);
+// stop: optional device flag; when it is non-zero at kernel start the launch does nothing
+int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop = nullptr);
 int launch_diag(Op &op, void *d, hipStream_t s);
 int build_tiles(Op &op, hipStream_t s);
-int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s);
+int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop);
 void free_tiles(Op &op);
+int csr_create(Op &op, hipStream_t s);
+int launch_spmv(const Op &op, const void *x, void *y, hipStream_t s, const int *stop);
+void free_csr(Op &op);
 
 }  // namespace q1

@@ -124,6 +124,12 @@ int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t 
 int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
   Q1_CHECK(op, Q1_EINVAL, "q1_op_bytes: NULL handle");
   const int rb = op->dtype == Q1_F64 ? 8 : 4;
+  if (op->variant == Q1_V_CSR) {  // values + column indices + row pointers + x read + y write
+    if (bytes)
+      *bytes = double(op->csr.nnz) * (rb + 4) + double(op->csr.nrows) * (4 + 2 * rb);
+    if (flops) *flops = 2.0 * double(op->csr.nnz);
+    return Q1_OK;
+  }
   const int coef_bytes = rb * (op->physics == 1 ? 1 : 2);
   double b = 0.0;
   int rc = q1_model_bytes(1, op->physics, rb, coef_bytes, op->n_nodes, op->n_elems, 0, &b);
@@ -137,7 +143,46 @@ int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
 int q1_op_destroy(q1_op *op) {
   if (!op) return Q1_OK;
   free_tiles(*op);
+  free_csr(*op);
   delete op;
+  return Q1_OK;
+}
+
+int q1_csr_create(q1_op **out, const q1_op *like, void *stream) {
+  Q1_CHECK(out && like, Q1_EINVAL, "q1_csr_create: NULL argument");
+  *out = nullptr;
+  q1_op *op = new (std::nothrow) q1_op();
+  Q1_CHECK(op, Q1_ENOMEM, "q1_csr_create: out of host memory");
+  static_cast<Op &>(*op) = static_cast<const Op &>(*like);
+  op->tiles = TileMap{};
+  op->csr = CsrData{};
+  op->variant = Q1_V_CSR;
+  const int rc = csr_create(*op, static_cast<hipStream_t>(stream));
+  if (rc) {
+    free_csr(*op);
+    delete op;
+    return rc;
+  }
+  *out = op;
+  return Q1_OK;
+}
+
+int q1_csr_info(const q1_op *op, int64_t *nrows, int64_t *nnz) {
+  Q1_CHECK(op && op->variant == Q1_V_CSR, Q1_EINVAL, "q1_csr_info: not a CSR operator");
+  if (nrows) *nrows = op->csr.nrows;
+  if (nnz) *nnz = op->csr.nnz;
+  return Q1_OK;
+}
+
+int q1_csr_export(const q1_op *op, int32_t *rowptr, int32_t *col, void *val) {
+  Q1_CHECK(op && op->variant == Q1_V_CSR, Q1_EINVAL, "q1_csr_export: not a CSR operator");
+  const CsrData &m = op->csr;
+  const size_t rb = op->dtype == Q1_F64 ? 8 : 4;
+  if (rowptr)
+    Q1_HIP(hipMemcpy(rowptr, m.rowptr, size_t(m.nrows + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (col && m.nnz)
+    Q1_HIP(hipMemcpy(col, m.col, size_t(m.nnz) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (val && m.nnz) Q1_HIP(hipMemcpy(val, m.val, size_t(m.nnz) * rb, hipMemcpyDeviceToHost));
   return Q1_OK;
 }
 

@@ -1,0 +1,717 @@
+// Krylov solvers on the device: Jacobi-preconditioned CG, flexible PCG and
+// FP32/FP64 iterative refinement, built from the CG operations of Table 4
+// (operator apply, the dot p^T A p, the axpys of x and r with the dot r^T r,
+// the axpy of p).
+//
+// Reductions are deterministic and need no grid-wide fence: a kernel writes
+// one partial sum per block (a fixed-order wave64 shuffle tree and a fixed
+// combination of the block's waves), and every block of the NEXT kernel in
+// stream order re-reduces the partials in the same fixed order, so all blocks
+// see bit-identical scalars.  (A device-scope fence per block would write back
+// and invalidate the whole L2 on this GPU.)  Iteration scalars never leave the
+// device; the host reads a small status record every few iterations, and a
+// device flag marks the solve finished, after which every queued kernel --
+// the operator apply included -- returns at once.
+//
+// PCG iteration k (vectors x, r, p, q and the inverse diagonal w; z = w r is
+// never stored):
+//   apply      q = A p
+//   dot        partials of p.q
+//   update     alpha = rho_k / p.q; x += alpha p; r -= alpha q;
+//              partials of rho_{k+1} = r.(w r) and of r.r
+//   direction  convergence test on r.r; beta = rho_{k+1} / rho_k;
+//              p = w r + beta p
+// Vectors are of the operator's type T (double or float); every dot product
+// accumulates in double.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "q1_internal.hpp"
+
+namespace q1 {
+
+constexpr int kRT = 256;     // threads per reduction block
+constexpr int kMaxRB = 256;  // partial sums per reduction (at most one per thread)
+
+// Device status record, read by the host every few iterations.
+struct Status {
+  int done, status, iter, pad;
+  double rr, bb, rho, aux;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum of N values over the block, returned to every thread (fixed order).
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N]) {
+  __shared__ double sh[N][kRT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh[i][w] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = sh[i][0];
+#pragma unroll
+    for (int k = 1; k < kRT / 64; ++k) s += sh[i][k];
+    v[i] = s;
+  }
+}
+
+// Re-reduce nb partials written by an earlier kernel (same value in every block).
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb) {
+  double v[1] = {int(threadIdx.x) < nb ? part[threadIdx.x] : 0.0};
+  block_sum<1>(v);
+  return v[0];
+}
+
+struct Range {
+  int64_t i0, i1;
+};
+__device__ __forceinline__ Range block_range(int64_t n) {
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = int64_t(blockIdx.x) * chunk;
+  return {i0, i0 + chunk < n ? i0 + chunk : n};
+}
+
+// ---- kernels ---------------------------------------------------------------
+
+// w = 1/d (Jacobi) or 1
+template <typename T>
+__global__ void k_inv_diag(int64_t n, const T *__restrict__ d, T *__restrict__ w, int jacobi) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = jacobi ? T(1) / d[i] : T(1);
+}
+
+// x = 0, r = b, p = w b; partials rho_0 = b.(w b) and b.b
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_pcg_init(int64_t n, const T *__restrict__ b,
+                                                  const T *__restrict__ w, T *__restrict__ x,
+                                                  T *__restrict__ r, T *__restrict__ p,
+                                                  double *__restrict__ part_rho,
+                                                  double *__restrict__ part_bb, int set_p) {
+  const Range rg = block_range(n);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    const T bi = b[i];
+    const T zi = w[i] * bi;
+    x[i] = T(0);
+    r[i] = bi;
+    if (set_p) p[i] = zi;
+    v[0] += double(bi) * double(zi);
+    v[1] += double(bi) * double(bi);
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    part_rho[blockIdx.x] = v[0];
+    part_bb[blockIdx.x] = v[1];
+  }
+}
+
+// partials of a.c (skipped once the solve is done)
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_dot(int64_t n, const T *__restrict__ a,
+                                             const T *__restrict__ c, double *__restrict__ part,
+                                             const Status *__restrict__ st) {
+  if (st && st->done) return;
+  const Range rg = block_range(n);
+  double v[1] = {0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) v[0] += double(a[i]) * double(c[i]);
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// alpha = rho_k / p.q; x += alpha p; r -= alpha q; partials rho_{k+1}, r.r.
+// FLEX (flexible PCG): keeps r_k in r_old and leaves rho_{k+1} to the
+// preconditioner step.
+template <typename T, bool FLEX>
+__global__ __launch_bounds__(kRT) void k_pcg_update(
+    int64_t n, const T *__restrict__ p, const T *__restrict__ q, const T *__restrict__ w,
+    T *__restrict__ x, T *__restrict__ r, T *__restrict__ r_old,
+    const double *__restrict__ part_pq, const double *__restrict__ part_rho_k,
+    double *__restrict__ part_rho_k1, double *__restrict__ part_rr, Status *__restrict__ st) {
+  if (st->done) return;
+  const int nb = gridDim.x;
+  const double pq = sum_partials(part_pq, nb);
+  const double rho = sum_partials(part_rho_k, nb);
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->done = 1;
+      st->status = Q1_EBREAKDOWN;
+    }
+    return;
+  }
+  const double alpha = rho / pq;
+  const Range rg = block_range(n);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    const T ri = r[i];
+    if constexpr (FLEX) r_old[i] = ri;
+    const T rn = T(double(ri) - alpha * double(q[i]));
+    x[i] = T(double(x[i]) + alpha * double(p[i]));
+    r[i] = rn;
+    if constexpr (!FLEX) v[0] += double(rn) * double(w[i] * rn);
+    v[1] += double(rn) * double(rn);
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    if constexpr (!FLEX) part_rho_k1[blockIdx.x] = v[0];
+    part_rr[blockIdx.x] = v[1];
+  }
+}
+
+// Convergence test after iteration `it`; beta = rho_{k+1} / rho_k;
+// p = z + beta p with z = w r (PCG) or the stored z (flexible PCG).
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_pcg_direction(
+    int64_t n, const T *__restrict__ r, const T *__restrict__ w, const T *__restrict__ z,
+    T *__restrict__ p, const double *__restrict__ part_num, const double *__restrict__ part_den,
+    const double *__restrict__ part_rr, const double *__restrict__ part_bb, double tol2, int it,
+    int maxit, Status *__restrict__ st) {
+  if (st->done) return;
+  const int nb = gridDim.x;
+  const double num = sum_partials(part_num, nb);
+  const double den = sum_partials(part_den, nb);
+  const double rr = sum_partials(part_rr, nb);
+  const double bb = sum_partials(part_bb, nb);
+  const bool conv = rr <= tol2 * bb;
+  const bool bad = !isfinite(rr);
+  const bool stop = conv || bad || it >= maxit;
+  if (!stop) {
+    const double beta = num / den;
+    const Range rg = block_range(n);
+    for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+      const T zi = z ? z[i] : T(w[i] * r[i]);
+      p[i] = T(double(zi) + beta * double(p[i]));
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->iter = it;
+    st->rr = rr;
+    st->bb = bb;
+    st->rho = num;
+    if (stop) {
+      st->done = 1;
+      st->status = conv ? Q1_OK : (bad ? Q1_EBREAKDOWN : Q1_ENOCONV);
+    }
+  }
+}
+
+// Flexible PCG: partials of z.r (rho_{k+1}) and z.(r - r_old)
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_fpcg_dots(int64_t n, const T *__restrict__ z,
+                                                   const T *__restrict__ r,
+                                                   const T *__restrict__ r_old,
+                                                   double *__restrict__ part_rho,
+                                                   double *__restrict__ part_num,
+                                                   const Status *__restrict__ st) {
+  if (st->done) return;
+  const Range rg = block_range(n);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    const double zi = double(z[i]), ri = double(r[i]);
+    v[0] += zi * ri;
+    v[1] += zi * (ri - double(r_old[i]));
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    part_rho[blockIdx.x] = v[0];
+    part_num[blockIdx.x] = v[1];
+  }
+}
+
+// z = w r
+template <typename T>
+__global__ void k_jacobi(int64_t n, const T *__restrict__ w, const T *__restrict__ r,
+                         T *__restrict__ z) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = w[i] * r[i];
+}
+
+// y = b - y (residual from y = A x)
+template <typename T>
+__global__ void k_residual(int64_t n, const T *__restrict__ b, T *__restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = b[i] - y[i];
+}
+
+// single-block sum of partials into *out
+__global__ __launch_bounds__(kRT) void k_finalize(const double *__restrict__ part, int nb,
+                                                  double *__restrict__ out) {
+  const double s = sum_partials(part, nb);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// Iterative refinement helpers
+// s = (float) (r / scale) with scale = sqrt(*nrm2)
+__global__ void k_scale_to_f32(int64_t n, const double *__restrict__ r,
+                               const double *__restrict__ nrm2, float *__restrict__ s) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) s[i] = float(r[i] / sqrt(*nrm2));
+}
+// x += sqrt(*nrm2) * d (FP64 update with the FP32 correction)
+__global__ void k_ir_update(int64_t n, const float *__restrict__ d,
+                            const double *__restrict__ nrm2, double *__restrict__ x) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += sqrt(*nrm2) * double(d[i]);
+}
+
+// ---- host drivers ------------------------------------------------------------
+
+namespace {
+
+struct Work {
+  void *r = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *r_old = nullptr,
+       *z = nullptr;
+  double *part = nullptr;  // [8][kMaxRB]
+  Status *st = nullptr;    // device
+  Status *hst = nullptr;   // pinned host mirror
+  Work() = default;
+  Work(const Work &) = delete;
+  ~Work() {
+    void *d[] = {r, p, q, w, r_old, z, part, st};
+    for (void *v : d)
+      if (v) (void)hipFree(v);
+    if (hst) (void)hipHostFree(hst);
+  }
+};
+
+int nblocks_for(int64_t n) {
+  const int64_t b = (n + int64_t(kRT) * 8 - 1) / (int64_t(kRT) * 8);
+  return int(std::max<int64_t>(1, std::min<int64_t>(kMaxRB, b)));
+}
+
+inline dim3 grid1(int64_t n) { return dim3(unsigned((n + 255) / 256)); }
+
+template <typename T>
+int alloc_work(Work &W, int64_t n, bool flex) {
+  const size_t b = size_t(std::max<int64_t>(n, 1)) * sizeof(T);
+  Q1_HIP(hipMalloc(&W.r, b));
+  Q1_HIP(hipMalloc(&W.p, b));
+  Q1_HIP(hipMalloc(&W.q, b));
+  Q1_HIP(hipMalloc(&W.w, b));
+  if (flex) {
+    Q1_HIP(hipMalloc(&W.r_old, b));
+    Q1_HIP(hipMalloc(&W.z, b));
+  }
+  Q1_HIP(hipMalloc(&W.part, 8 * kMaxRB * sizeof(double)));
+  Q1_HIP(hipMalloc(&W.st, sizeof(Status)));
+  Q1_HIP(hipHostMalloc(&W.hst, sizeof(Status), hipHostMallocDefault));
+  return Q1_OK;
+}
+
+template <typename T>
+int setup_diag(Op &op, Work &W, int pc, hipStream_t s) {
+  const int64_t n = op.n_nodes * op.physics;
+  if (pc == Q1_PC_JACOBI) {
+    const int rc = launch_diag(op, W.q, s);  // q as scratch
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL((k_inv_diag<T>), grid1(n), dim3(256), 0, s, n, static_cast<const T *>(W.q),
+                     static_cast<T *>(W.w), pc == Q1_PC_JACOBI ? 1 : 0);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+int read_status(Work &W, hipStream_t s) {
+  Q1_HIP(hipMemcpyAsync(W.hst, W.st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  Q1_HIP(hipStreamSynchronize(s));
+  return Q1_OK;
+}
+
+// ||b - A x||_2 / ||b||_2 with q and two partial rows as scratch (synchronises)
+template <typename T>
+int true_residual(Op &op, Work &W, const T *b, const T *x, double *out, hipStream_t s) {
+  const int64_t n = op.n_nodes * op.physics;
+  const int nb = nblocks_for(n);
+  T *q = static_cast<T *>(W.q);
+  int rc = launch_apply(op, x, q, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_residual<T>), grid1(n), dim3(256), 0, s, n, b, q);
+  hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, q, q, W.part + 6 * kMaxRB,
+                     nullptr);
+  hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, b, b, W.part + 7 * kMaxRB,
+                     nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, W.part + 6 * kMaxRB, nb, &W.st->aux);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, W.part + 7 * kMaxRB, nb, &W.st->bb);
+  Q1_HIP(hipGetLastError());
+  if ((rc = read_status(W, s))) return rc;
+  *out = W.hst->bb > 0 ? std::sqrt(W.hst->aux / W.hst->bb) : 0.0;
+  return Q1_OK;
+}
+
+// Preconditioned CG on the operator's vector type T with x0 = 0.  Returns
+// Q1_OK, Q1_ENOCONV (x = last iterate) or Q1_EBREAKDOWN.
+template <typename T>
+int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *stats,
+          hipStream_t s, bool true_res) {
+  const int64_t n = op.n_nodes * op.physics;
+  Work W;
+  int rc = alloc_work<T>(W, n, false);
+  if (rc) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  if ((rc = setup_diag<T>(op, W, pc, s))) return rc;
+  const int nb = nblocks_for(n);
+  double *P = W.part;
+  double *part_rho[2] = {P, P + kMaxRB};
+  double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB;
+  T *r = static_cast<T *>(W.r), *p = static_cast<T *>(W.p), *q = static_cast<T *>(W.q),
+    *w = static_cast<T *>(W.w);
+  Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
+  hipLaunchKernelGGL((k_pcg_init<T>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r, p, part_rho[0],
+                     part_bb, 1);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
+  Q1_HIP(hipGetLastError());
+  if ((rc = read_status(W, s))) return rc;
+  const double bb = W.hst->bb;
+  int status = Q1_OK, iters = 0;
+  double rr = bb;
+  if (bb > 0.0) {
+    const double tol2 = rtol * rtol;
+    status = Q1_ENOCONV;
+    int launched = 0, batch = 1;
+    while (launched < maxit) {
+      const int m = std::min(batch, maxit - launched);
+      for (int j = 0; j < m; ++j) {
+        const int k = launched + j;
+        if ((rc = launch_apply(op, p, q, s, &W.st->done))) return rc;
+        hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
+        hipLaunchKernelGGL((k_pcg_update<T, false>), dim3(nb), dim3(kRT), 0, s, n, p, q, w, x, r,
+                           nullptr, part_pq, part_rho[k & 1], part_rho[(k + 1) & 1], part_rr,
+                           W.st);
+        hipLaunchKernelGGL((k_pcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, r, w, nullptr, p,
+                           part_rho[(k + 1) & 1], part_rho[k & 1], part_rr, part_bb, tol2, k + 1,
+                           maxit, W.st);
+      }
+      Q1_HIP(hipGetLastError());
+      launched += m;
+      if ((rc = read_status(W, s))) return rc;
+      if (W.hst->done) break;
+      batch = std::min(batch * 2, 32);
+    }
+    iters = W.hst->iter;
+    rr = W.hst->rr;
+    if (W.hst->done) status = W.hst->status;
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->iters = iters;
+    stats->status = status;
+    stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    stats->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    stats->true_rel_res = stats->rel_res;
+    stats->fallback_at = -1;
+    stats->outer_iters = 0;
+    if (true_res && bb > 0.0) {
+      double t;
+      if ((rc = true_residual<T>(op, W, b, x, &t, s))) return rc;
+      stats->true_rel_res = t;
+    }
+  }
+  return status;
+}
+
+// Flexible PCG with a caller preconditioner z = M(r); falls back to Jacobi
+// for the rest of the solve when M fails, gives z.r <= 0 or a non-finite
+// value, or when the residual has not dropped below its value safeguard_m
+// iterations earlier.
+template <typename T>
+int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, int maxit,
+           int safeguard_m, q1_stats *stats, hipStream_t s) {
+  const int64_t n = op.n_nodes * op.physics;
+  Work W;
+  int rc = alloc_work<T>(W, n, true);
+  if (rc) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  if ((rc = setup_diag<T>(op, W, Q1_PC_JACOBI, s))) return rc;
+  const int nb = nblocks_for(n);
+  double *P = W.part;
+  double *part_rho[2] = {P, P + kMaxRB};
+  double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB,
+         *part_num = P + 5 * kMaxRB;
+  T *r = static_cast<T *>(W.r), *p = static_cast<T *>(W.p), *q = static_cast<T *>(W.q),
+    *w = static_cast<T *>(W.w), *ro = static_cast<T *>(W.r_old), *z = static_cast<T *>(W.z);
+  Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
+  hipLaunchKernelGGL((k_pcg_init<T>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r, p, part_rho[0],
+                     part_bb, 0);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
+  Q1_HIP(hipGetLastError());
+  if ((rc = read_status(W, s))) return rc;
+  const double bb = W.hst->bb;
+  int status = Q1_OK, iters = 0, fallback_at = -1;
+  double rr = bb;
+  std::vector<double> hist;
+  hist.push_back(bb);
+  // z_0 = M(r_0); p_0 = z_0
+  auto precondition = [&](int k) -> int {
+    bool ok = fallback_at < 0 && M != nullptr;
+    if (ok) ok = M(ctx, r, z, s) == Q1_OK;
+    if (ok) {
+      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, part_rho[k & 1], W.st);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rho[k & 1], nb, &W.st->aux);
+      Q1_HIP(hipGetLastError());
+      int rc2 = read_status(W, s);
+      if (rc2) return rc2;
+      ok = std::isfinite(W.hst->aux) && W.hst->aux > 0.0;
+    }
+    if (!ok) {
+      if (fallback_at < 0) fallback_at = k;
+      (void)hipGetLastError();
+      hipLaunchKernelGGL((k_jacobi<T>), grid1(n), dim3(256), 0, s, n, w, r, z);
+      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, part_rho[k & 1], W.st);
+      Q1_HIP(hipGetLastError());
+    }
+    return Q1_OK;
+  };
+  if (bb > 0.0) {
+    const double tol2 = rtol * rtol;
+    status = Q1_ENOCONV;
+    if ((rc = precondition(0))) return rc;
+    Q1_HIP(hipMemcpyAsync(p, z, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < maxit; ++k) {
+      if ((rc = launch_apply(op, p, q, s, &W.st->done))) return rc;
+      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
+      hipLaunchKernelGGL((k_pcg_update<T, true>), dim3(nb), dim3(kRT), 0, s, n, p, q, w, x, r,
+                         ro, part_pq, part_rho[k & 1], nullptr, part_rr, W.st);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rr, nb, &W.st->rr);
+      Q1_HIP(hipGetLastError());
+      if ((rc = read_status(W, s))) return rc;
+      if (W.hst->done) break;  // breakdown
+      iters = k + 1;
+      rr = W.hst->rr;
+      hist.push_back(rr);
+      if (rr <= tol2 * bb) {
+        status = Q1_OK;
+        break;
+      }
+      if (iters >= maxit) break;
+      // stagnation safeguard
+      if (safeguard_m > 0 && fallback_at < 0 && int(hist.size()) > safeguard_m &&
+          !(rr < hist[hist.size() - 1 - safeguard_m]))
+        fallback_at = iters;
+      if ((rc = precondition(k + 1))) return rc;
+      hipLaunchKernelGGL((k_fpcg_dots<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, ro,
+                         part_rho[(k + 1) & 1], part_num, W.st);
+      // beta = z_{k+1}.(r_{k+1} - r_k) / rho_k ; p = z + beta p
+      hipLaunchKernelGGL((k_pcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, r, w, z, p,
+                         part_num, part_rho[k & 1], part_rr, part_bb, 0.0, k + 1, maxit + 1,
+                         W.st);
+      Q1_HIP(hipGetLastError());
+    }
+    if (W.hst->done && W.hst->status == Q1_EBREAKDOWN) status = Q1_EBREAKDOWN;
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->iters = iters;
+    stats->status = status;
+    stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    stats->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    stats->fallback_at = fallback_at;
+    stats->outer_iters = 0;
+    stats->true_rel_res = stats->rel_res;
+    if (bb > 0.0) {
+      double t;
+      if ((rc = true_residual<T>(op, W, b, x, &t, s))) return rc;
+      stats->true_rel_res = t;
+    }
+  }
+  return status;
+}
+
+}  // namespace
+
+// Jacobi preconditioner object usable as a q1_precond_fn context.
+struct Jacobi {
+  Op *op = nullptr;
+  void *w = nullptr;
+};
+
+}  // namespace q1
+
+using namespace q1;
+
+struct q1_jacobi : public q1::Jacobi {};
+
+extern "C" {
+
+int q1_pcg(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit,
+           q1_stats *st, void *stream) {
+  Q1_CHECK(op && b_d && x_d, Q1_EINVAL, "q1_pcg: NULL argument");
+  Q1_CHECK(pc == Q1_PC_NONE || pc == Q1_PC_JACOBI, Q1_EINVAL, "q1_pcg: bad preconditioner %d", pc);
+  Q1_CHECK(rtol >= 0 && maxit >= 0, Q1_EINVAL, "q1_pcg: need rtol >= 0 and maxit >= 0");
+  Op &o = *reinterpret_cast<Op *>(op);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (o.dtype == Q1_F64)
+    return pcg_t<double>(o, pc, static_cast<const double *>(b_d), static_cast<double *>(x_d),
+                         rtol, maxit, st, s, true);
+  return pcg_t<float>(o, pc, static_cast<const float *>(b_d), static_cast<float *>(x_d), rtol,
+                      maxit, st, s, true);
+}
+
+int q1_fpcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,
+            int maxit, int safeguard_m, q1_stats *st, void *stream) {
+  Q1_CHECK(op && b_d && x_d, Q1_EINVAL, "q1_fpcg: NULL argument");
+  Q1_CHECK(rtol >= 0 && maxit >= 0, Q1_EINVAL, "q1_fpcg: need rtol >= 0 and maxit >= 0");
+  Op &o = *reinterpret_cast<Op *>(op);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (o.dtype == Q1_F64)
+    return fpcg_t<double>(o, M, ctx, static_cast<const double *>(b_d),
+                          static_cast<double *>(x_d), rtol, maxit, safeguard_m, st, s);
+  return fpcg_t<float>(o, M, ctx, static_cast<const float *>(b_d), static_cast<float *>(x_d),
+                       rtol, maxit, safeguard_m, st, s);
+}
+
+int q1_jacobi_create(q1_jacobi **out, q1_op *op, void *stream) {
+  Q1_CHECK(out && op, Q1_EINVAL, "q1_jacobi_create: NULL argument");
+  *out = nullptr;
+  Op &o = *reinterpret_cast<Op *>(op);
+  q1_jacobi *J = new (std::nothrow) q1_jacobi();
+  Q1_CHECK(J, Q1_ENOMEM, "q1_jacobi_create: out of host memory");
+  J->op = &o;
+  const int64_t n = o.n_nodes * o.physics;
+  const size_t rb = o.dtype == Q1_F64 ? 8 : 4;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipMalloc(&J->w, size_t(n) * rb) != hipSuccess) {
+    delete J;
+    return fail(Q1_ENOMEM, "q1_jacobi_create: device allocation failed");
+  }
+  int rc = launch_diag(o, J->w, s);
+  if (!rc) {
+    if (o.dtype == Q1_F64)
+      hipLaunchKernelGGL((k_inv_diag<double>), grid1(n), dim3(256), 0, s, n,
+                         static_cast<const double *>(J->w), static_cast<double *>(J->w), 1);
+    else
+      hipLaunchKernelGGL((k_inv_diag<float>), grid1(n), dim3(256), 0, s, n,
+                         static_cast<const float *>(J->w), static_cast<float *>(J->w), 1);
+    if (hipGetLastError() != hipSuccess) rc = fail(Q1_EHIP, "q1_jacobi_create: launch failed");
+  }
+  if (rc) {
+    (void)hipFree(J->w);
+    delete J;
+    return rc;
+  }
+  *out = J;
+  return Q1_OK;
+}
+
+int q1_precond_jacobi(void *ctx, const void *r_d, void *z_d, void *stream) {
+  Q1_CHECK(ctx && r_d && z_d, Q1_EINVAL, "q1_precond_jacobi: NULL argument");
+  q1_jacobi *J = static_cast<q1_jacobi *>(ctx);
+  const int64_t n = J->op->n_nodes * J->op->physics;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (J->op->dtype == Q1_F64)
+    hipLaunchKernelGGL((k_jacobi<double>), grid1(n), dim3(256), 0, s, n,
+                       static_cast<const double *>(J->w), static_cast<const double *>(r_d),
+                       static_cast<double *>(z_d));
+  else
+    hipLaunchKernelGGL((k_jacobi<float>), grid1(n), dim3(256), 0, s, n,
+                       static_cast<const float *>(J->w), static_cast<const float *>(r_d),
+                       static_cast<float *>(z_d));
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+int q1_jacobi_destroy(q1_jacobi *J) {
+  if (!J) return Q1_OK;
+  if (J->w) (void)hipFree(J->w);
+  delete J;
+  return Q1_OK;
+}
+
+int q1_ir_solve(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
+                double inner_rtol, int max_outer, int max_inner, q1_stats *st, void *stream) {
+  Q1_CHECK(op64 && op32 && b_d && x_d, Q1_EINVAL, "q1_ir_solve: NULL argument");
+  Op &A64 = *reinterpret_cast<Op *>(op64);
+  Op &A32 = *reinterpret_cast<Op *>(op32);
+  Q1_CHECK(A64.dtype == Q1_F64 && A32.dtype == Q1_F32, Q1_EINVAL,
+           "q1_ir_solve: needs an FP64 and an FP32 operator");
+  Q1_CHECK(A64.n_nodes == A32.n_nodes && A64.physics == A32.physics, Q1_EINVAL,
+           "q1_ir_solve: operators of different sizes");
+  Q1_CHECK(rtol > 0 && inner_rtol > 0 && inner_rtol < 1 && max_outer > 0 && max_inner > 0,
+           Q1_EINVAL, "q1_ir_solve: bad tolerances or limits");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = A64.n_nodes * A64.physics;
+  const auto t0 = std::chrono::steady_clock::now();
+  Work W;  // FP64 residual, norms
+  int rc = alloc_work<double>(W, n, false);
+  if (rc) return rc;
+  float *s32 = nullptr, *d32 = nullptr;
+  struct Free {
+    float **a, **b;
+    ~Free() {
+      if (*a) (void)hipFree(*a);
+      if (*b) (void)hipFree(*b);
+    }
+  } fr{&s32, &d32};
+  Q1_HIP(hipMalloc(&s32, size_t(n) * sizeof(float)));
+  Q1_HIP(hipMalloc(&d32, size_t(n) * sizeof(float)));
+  const int nb = nblocks_for(n);
+  double *r = static_cast<double *>(W.r);
+  double *part_bb = W.part + 4 * kMaxRB, *part_rr = W.part + 3 * kMaxRB;
+  Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
+  Q1_HIP(hipMemsetAsync(x_d, 0, size_t(n) * sizeof(double), s));
+  Q1_HIP(hipMemcpyAsync(r, b_d, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL((k_dot<double>), dim3(nb), dim3(kRT), 0, s, n, b_d, b_d, part_bb, nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->rr);  // r_0 = b
+  Q1_HIP(hipGetLastError());
+  if ((rc = read_status(W, s))) return rc;
+  const double bb = W.hst->bb;
+  double rr = bb;
+  int outer = 0, inner_total = 0, status = Q1_OK;
+  double prev_rr = INFINITY;
+  while (bb > 0.0 && rr > rtol * rtol * bb) {
+    if (outer >= max_outer) {
+      status = Q1_ENOCONV;
+      break;
+    }
+    if (!(rr < prev_rr)) {  // no progress: refinement diverges or stagnates
+      status = Q1_EBREAKDOWN;
+      break;
+    }
+    prev_rr = rr;
+    // s = r / ||r|| in FP32; solve A32 d = s to inner_rtol; x += ||r|| d
+    hipLaunchKernelGGL(k_scale_to_f32, grid1(n), dim3(256), 0, s, n, r, &W.st->rr, s32);
+    Q1_HIP(hipGetLastError());
+    q1_stats ist{};
+    rc = pcg_t<float>(A32, Q1_PC_JACOBI, s32, d32, inner_rtol, max_inner, &ist, s, false);
+    if (rc != Q1_OK && rc != Q1_ENOCONV) return rc;
+    inner_total += ist.iters;
+    hipLaunchKernelGGL(k_ir_update, grid1(n), dim3(256), 0, s, n, d32, &W.st->rr, x_d);
+    // r = b - A64 x in FP64
+    if ((rc = launch_apply(A64, x_d, r, s))) return rc;
+    hipLaunchKernelGGL((k_residual<double>), grid1(n), dim3(256), 0, s, n, b_d, r);
+    hipLaunchKernelGGL((k_dot<double>), dim3(nb), dim3(kRT), 0, s, n, r, r, part_rr, nullptr);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rr, nb, &W.st->rr);
+    Q1_HIP(hipGetLastError());
+    if ((rc = read_status(W, s))) return rc;
+    rr = W.hst->rr;
+    ++outer;
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (st) {
+    st->iters = inner_total;
+    st->outer_iters = outer;
+    st->status = status;
+    st->seconds = std::chrono::duration<double>(t1 - t0).count();
+    st->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    st->true_rel_res = st->rel_res;
+    st->fallback_at = -1;
+  }
+  return status;
+}
+
+}  // extern "C"

@@ -57,7 +57,8 @@ __device__ __forceinline__ void gbl_add(float *p, float v) { unsafeAtomicAdd(p, 
 template <typename T, int DPN>
 __global__ void k_reset_nodes(int64_t n, const int32_t *__restrict__ ids,
                               const uint8_t *__restrict__ mask, const T *__restrict__ x,
-                              T *__restrict__ y) {
+                              T *__restrict__ y, const int *__restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t g = ids[i];
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(64) void k_apply_tile(
     const int32_t *__restrict__ tile_step,                              // [n_tiles+1]
     const uint4 *__restrict__ lconn,                                    // [n_steps*64]
     const T *__restrict__ coef_t, int64_t coef_stride, const T *__restrict__ xyz,
-    const T *__restrict__ x, T *__restrict__ y) {
+    const T *__restrict__ x, T *__restrict__ y, const int *__restrict__ stop) {
+  if (stop && *stop) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sV = reinterpret_cast<T *>(smem_raw);                             // [DPN][max_nodes]
   uint32_t *sId = reinterpret_cast<uint32_t *>(sV + DPN * max_nodes);  // [max_nodes]
@@ -335,20 +337,20 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
 }
 
 template <typename T, int DPN>
-int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s) {
+int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
   const TileMap &tm = op.tiles;
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
   if (tm.n_reset > 0)
     hipLaunchKernelGGL((k_reset_nodes<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
-                       s, tm.n_reset, tm.reset, op.mask, x, y);
+                       s, tm.n_reset, tm.reset, op.mask, x, y, stop);
   const size_t lds = size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   auto kern = tm.lds_atomic ? k_apply_tile<T, DPN, true> : k_apply_tile<T, DPN, false>;
   hipLaunchKernelGGL(kern, dim3(tm.n_tiles), dim3(kLanes), lds, s, tm.max_nodes, op.n_nodes,
                      tm.node_ptr, tm.nodes, tm.tile_step,
                      reinterpret_cast<const uint4 *>(tm.lconn),
                      static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
-                     static_cast<const T *>(op.xyz), x, y);
+                     static_cast<const T *>(op.xyz), x, y, stop);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
@@ -374,12 +376,12 @@ int build_tiles(Op &op, hipStream_t s) {
   return Q1_OK;
 }
 
-int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s) {
+int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
   if (op.dtype == Q1_F64)
-    return op.physics == 1 ? apply_tile_t<double, 1>(op, x, y, s)
-                           : apply_tile_t<double, 3>(op, x, y, s);
-  return op.physics == 1 ? apply_tile_t<float, 1>(op, x, y, s)
-                         : apply_tile_t<float, 3>(op, x, y, s);
+    return op.physics == 1 ? apply_tile_t<double, 1>(op, x, y, s, stop)
+                           : apply_tile_t<double, 3>(op, x, y, s, stop);
+  return op.physics == 1 ? apply_tile_t<float, 1>(op, x, y, s, stop)
+                         : apply_tile_t<float, 3>(op, x, y, s, stop);
 }
 
 void free_tiles(Op &op) {

@@ -1,0 +1,193 @@
+"""GPU parity of the CSR comparison path and the Krylov solvers against the
+CPU oracle: pattern bit-equal, values and SpMV to 1e-13/1e-12, the first PCG
+iterates to 1e-10, converged solves judged by the oracle's operator,
+flexible PCG reducing to PCG for a fixed SPD preconditioner, iterative
+refinement to 1e-10, and the failure paths (zero right-hand side, breakdown,
+iteration limit, failing preconditioner)."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from helpers import TOL, dev, gpu_apply, make_op, problem, rel_err, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q1():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2308_09839_amd as q1
+    return q1
+
+
+def rhs(A, pr, seed):
+    b = si.vec_uniform(A.n, seed, si.STREAM_RHS)
+    if pr.get("mask") is not None:
+        b[si.dof_mask(pr["mask"], pr["physics"]) == 1] = 0.0
+    return b
+
+
+# -- CSR ------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("physics,n,jitter,mask", [(1, (16, 16, 16), 0.1, True),
+                                                   (1, (7, 5, 3), 0.0, False),
+                                                   (3, (6, 5, 4), 0.1, True)])
+def test_csr_parity(q1, orc, physics, n, jitter, mask, dtype):
+    print(f"\n[csr] physics={physics} n={n} dtype={dtype}", flush=True)
+    pr = problem(physics, n, jitter, 51, mask)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    op = make_op(pr, dtype, 0)
+    csr = q1.q1_csr_create(op)
+    rowptr, col, val = q1.q1_csr_export(csr)
+    assert np.array_equal(rowptr.astype(np.int64), A.rowptr)
+    assert np.array_equal(col, A.col)
+    tol = 1e-13 if dtype == 0 else 2e-6
+    assert np.max(np.abs(val - A.val)) <= tol * np.max(np.abs(A.val))
+    x = si.vec_uniform(A.n, 52, si.STREAM_X)
+    ref = A.matvec(x)
+    y_csr = gpu_apply(csr, x, dtype)
+    y_mf = gpu_apply(op, x, dtype)
+    assert rel_err(y_csr, ref) <= TOL[dtype]
+    assert rel_err(y_mf, y_csr) <= 2 * TOL[dtype]
+    nb, fl = csr.bytes()
+    assert fl == 2.0 * A.nnz
+
+
+# -- PCG ------------------------------------------------------------------------
+
+def solve_gpu(q1, op, b, dtype, pc=1, rtol=1e-8, maxit=20000):
+    import torch
+    t = torch_dtype(dtype)
+    bd = dev(b, t)
+    xd = torch.empty_like(bd)
+    st = q1.q1_pcg(op, pc, bd, xd, rtol, maxit)
+    return xd.double().cpu().numpy(), st
+
+
+@pytest.mark.parametrize("csr", [False, True])
+def test_pcg_first_iterates(q1, orc, csr):
+    print(f"\n[pcg iterates] csr={csr}", flush=True)
+    pr = problem(1, (16, 16, 16), 0.1, 2308, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 2308)
+    op = make_op(pr, 0, 0)
+    if csr:
+        op = q1.q1_csr_create(op)
+    for k in range(1, 11):
+        ref = orc.pcg(A, b, rtol=0.0, maxit=k)
+        x, st = solve_gpu(q1, op, b, 0, rtol=0.0, maxit=k)
+        assert st["status"] == -4 and st["iters"] == k
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), k
+
+
+@pytest.mark.parametrize("physics,n,jitter", [(1, (16, 16, 16), 0.1), (1, (13, 11, 7), 0.0),
+                                              (3, (8, 8, 8), 0.1)])
+def test_pcg_converged(q1, orc, physics, n, jitter):
+    print(f"\n[pcg converged] physics={physics} n={n}", flush=True)
+    pr = problem(physics, n, jitter, 2308, True)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 61)
+    ref = orc.pcg(A, b, rtol=1e-8)
+    x, st = solve_gpu(q1, make_op(pr, 0, 0), b, 0, rtol=1e-8)
+    assert st["status"] == 0
+    assert orc.true_rel_res(A, x, b) <= 1e-8 * (1 + 1e-3)
+    assert abs(st["iters"] - ref.iters) <= 0.02 * ref.iters + 2
+    assert abs(st["true_rel_res"] - orc.true_rel_res(A, x, b)) <= 1e-12
+
+
+def test_pcg_fp32_operator(q1, orc):
+    print("\n[pcg fp32]", flush=True)
+    pr = problem(1, (12, 12, 12), 0.1, 63, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 63)
+    x, st = solve_gpu(q1, make_op(pr, 1, 0), b, 1, rtol=1e-5)
+    assert st["status"] == 0
+    assert orc.true_rel_res(A, x, b) <= 1e-4
+
+
+def test_pcg_edge_cases(q1, orc):
+    print("\n[pcg edge cases]", flush=True)
+    pr = problem(1, (5, 4, 3), 0.1, 64, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    op = make_op(pr, 0, 0)
+    # zero right-hand side
+    x, st = solve_gpu(q1, op, np.zeros(A.n), 0)
+    assert st["status"] == 0 and st["iters"] == 0 and np.all(x == 0)
+    # iteration limit: status ENOCONV, x = the oracle's iterate
+    b = rhs(A, pr, 64)
+    x, st = solve_gpu(q1, op, b, 0, rtol=1e-14, maxit=3)
+    ref = orc.pcg(A, b, rtol=0.0, maxit=3)
+    assert st["status"] == -4 and st["iters"] == 3
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    # negative definite operator: breakdown at the first p^T A p
+    prn = dict(pr)
+    prn["coef"] = -pr["coef"]
+    x, st = solve_gpu(q1, make_op(prn, 0, 0), b, 0, pc=0)
+    assert st["status"] == -5
+
+
+# -- flexible PCG -----------------------------------------------------------------
+
+def test_fpcg_with_jacobi_equals_pcg(q1, orc):
+    import torch
+    print("\n[fpcg = pcg]", flush=True)
+    pr = problem(1, (12, 10, 8), 0.1, 71, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 71)
+    op = make_op(pr, 0, 0)
+    J = q1.q1_jacobi_create(op)
+    for k in (1, 5, 20):
+        bd = dev(b, torch.float64)
+        xd = torch.empty_like(bd)
+        st = q1.q1_fpcg(op, J, bd, xd, 0.0, k)
+        ref = orc.pcg(A, b, rtol=0.0, maxit=k)
+        x = xd.cpu().numpy()
+        assert st["iters"] == k and st["fallback_at"] == -1
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), k
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    st = q1.q1_fpcg(op, J, bd, xd, 1e-8, 5000)
+    assert st["status"] == 0
+    assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
+
+
+def test_fpcg_safeguard_fallback(q1, orc):
+    import torch
+    print("\n[fpcg safeguard]", flush=True)
+    pr = problem(1, (10, 10, 10), 0.1, 72, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 72)
+    op = make_op(pr, 0, 0)
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    calls = []
+
+    def failing(r, z, s):  # reports failure without touching z
+        calls.append(1)
+        return 1
+
+    st = q1.q1_fpcg(op, failing, bd, xd, 1e-8, 5000)
+    assert st["status"] == 0 and st["fallback_at"] == 0 and len(calls) == 1
+    assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
+    ref = orc.pcg(A, b, rtol=1e-8)
+    assert abs(st["iters"] - ref.iters) <= 0.02 * ref.iters + 2
+
+
+# -- mixed-precision iterative refinement ---------------------------------------------
+
+@pytest.mark.parametrize("physics,n", [(1, (16, 16, 16)), (3, (10, 10, 10))])
+def test_ir_reaches_fp64_tolerance(q1, orc, physics, n):
+    import torch
+    print(f"\n[ir] physics={physics} n={n}", flush=True)
+    pr = problem(physics, n, 0.1 if physics == 1 else 0.0, 81, True)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 81)
+    op64 = make_op(pr, 0, 0)
+    op32 = make_op(pr, 1, 0)
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    st = q1.q1_ir_solve(op64, op32, bd, xd, 1e-10, 1e-4)
+    assert st["status"] == 0 and st["outer_iters"] >= 2
+    assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-10 * (1 + 1e-3)
