@@ -107,6 +107,93 @@ def cpu_baseline(n: int, seed: int, slab: int):
                 assembly_s=round(t_asm, 3), spmv_ms=round(t_spmv * 1e3, 3))
 
 
+def bench_csr(q1, si, n, seed, args):
+    """Same-GPU CSR SpMV of the assembled 128^3 operator (the matrix-based comparison)."""
+    import torch
+    pr = si.problem_laplace_layered(n, seed)
+    nn = pr["xyz"].shape[1]
+    op = q1.q1_op_create(1, 0, 0, *upload(pr, 0))
+    t0 = time.perf_counter()
+    csr = q1.q1_csr_create(op)
+    t_asm = time.perf_counter() - t0
+    x = torch.from_numpy(si.vec_uniform(nn, seed, si.STREAM_X)).to("cuda")
+    y = torch.empty_like(x)
+    ms, _ = time_applies(csr, x, y, args.steps, args.warmup)
+    b, _ = csr.bytes()
+    nnz = q1.q1_csr_info(csr)[1]
+    return {"csr_spmv_gdofs": round(nn / (ms * 1e-3) / 1e9, 3), "csr_spmv_ms": round(ms, 5),
+            "csr_hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "csr_nnz": nnz,
+            "csr_assembly_s": round(t_asm, 3)}
+
+
+def bench_cg16(q1, si, n, seed, args):
+    """16^3 jittered Laplace, k = exp(N(0,1)), Dirichlet on z=0: FP64 Jacobi-PCG
+    to a 1e-8 relative residual, wall time of the whole solve."""
+    import numpy as np
+    import torch
+
+    import oracle
+    s0 = si.seed_for(0)
+    pr = si.problem_laplace_jittered(16, s0)
+    nn = pr["xyz"].shape[1]
+    b = si.vec_uniform(nn, s0, si.STREAM_RHS)
+    b[pr["mask"] == 1] = 0.0
+    op = q1.q1_op_create(1, 0, 0, *upload(pr, 0))
+    bd = torch.from_numpy(b).to("cuda")
+    xd = torch.empty_like(bd)
+    q1.q1_pcg(op, 1, bd, xd, 1e-8, 20000)  # warm-up
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        st = q1.q1_pcg(op, 1, bd, xd, 1e-8, 20000)
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    oracle.build(force=False)
+    A = oracle.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    t0 = time.perf_counter()
+    ref = oracle.pcg(A, b, rtol=1e-8)
+    t_cpu = time.perf_counter() - t0
+    return {"cg16_gpu_s": round(ts[len(ts) // 2], 6), "cg16_iters": st["iters"],
+            "cg16_true_rel_res": st["true_rel_res"],
+            "cg16_oracle_true_rel_res": oracle.true_rel_res(A, xd.cpu().numpy(), b),
+            "cg16_cpu_oracle_s": round(t_cpu, 5), "cg16_cpu_oracle_iters": ref.iters}
+
+
+def bench_ir96(q1, si, n, seed, args):
+    """96^3 elasticity, Dirichlet on z=0, random body force: FP64 Jacobi-PCG vs
+    FP32-apply iterative refinement with FP64 residuals, both to 1e-10."""
+    import torch
+    s2 = si.seed_for(2)
+    pr = si.problem_elasticity(96, s2)
+    nn = pr["xyz"].shape[1]
+    b = si.vec_uniform(3 * nn, s2, si.STREAM_RHS)
+    b[si.dof_mask(pr["mask"], 3) == 1] = 0.0
+    op64 = q1.q1_op_create(3, 0, 0, *upload(pr, 0))
+    op32 = q1.q1_op_create(3, 1, 0, *upload(pr, 1))
+    bd = torch.from_numpy(b).to("cuda")
+    xd = torch.empty_like(bd)
+    t0 = time.perf_counter()
+    st64 = q1.q1_pcg(op64, 1, bd, xd, 1e-10, 50000)
+    t64 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sti = q1.q1_ir_solve(op64, op32, bd, xd, 1e-10, 1e-4)
+    tir = time.perf_counter() - t0
+    x32 = torch.empty(3 * nn, dtype=torch.float32, device="cuda")
+    y32 = torch.empty_like(x32)
+    ms32, _ = time_applies(op32, x32, y32, 50, 5)
+    xx = torch.empty(3 * nn, dtype=torch.float64, device="cuda")
+    yy = torch.empty_like(xx)
+    ms64, _ = time_applies(op64, xx, yy, 50, 5)
+    return {"el96_pcg64_s": round(t64, 4), "el96_pcg64_iters": st64["iters"],
+            "el96_pcg64_status": st64["status"], "el96_pcg64_true_rel_res": st64["true_rel_res"],
+            "el96_ir_s": round(tir, 4), "el96_ir_inner_iters": sti["iters"],
+            "el96_ir_outer": sti["outer_iters"], "el96_ir_status": sti["status"],
+            "el96_ir_rel_res": sti["rel_res"],
+            "el96_apply_fp64_gdofs": round(3 * nn / (ms64 * 1e-3) / 1e9, 3),
+            "el96_apply_fp32_gdofs": round(3 * nn / (ms32 * 1e-3) / 1e9, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +281,13 @@ def main() -> int:
         extras["fp64_jittered_ms"] = round(msj, 5)
         extras["fp64_jittered_flop_frac"] = round(alg_flops / (msj * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)
         del opj, xj, yj
+        for name, fn in (("csr", bench_csr), ("cg16", bench_cg16), ("cg_elasticity96", bench_ir96)):
+            try:
+                log(f"[bench] {name}")
+                extras.update(fn(q1, si, n, seed, args))
+            except Exception as exc:  # an extra must not take down the headline line
+                log(f"[bench] {name} failed: {exc!r}")
+                extras[f"{name}_error"] = repr(exc)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
