@@ -189,6 +189,18 @@ int q1_jacobi_destroy(q1_jacobi *J);
 int q1_ir_solve(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
                 double inner_rtol, int max_outer, int max_inner, q1_stats *st, void *stream);
 
+/* Batched persistent Jacobi-PCG: nprob independent scalar-Laplace problems
+ * (FP64 operators created with Q1_V_LDS_TILE or AUTO), each with nrhs
+ * right-hand sides (1..4), solved by ONE cooperative kernel launch.  b_d and
+ * x_d hold nprob*nrhs device vectors (problem-major, FP64); st, if not NULL,
+ * nprob*nrhs records.  Each problem gets a share of the co-resident
+ * wavefronts in proportion to its elements and synchronises them with its own
+ * barrier; p^T A p comes from element energies inside the apply.  Returns the
+ * worst status over all solves; Q1_EUNSUPPORTED for other operators or when
+ * more problems than co-resident wavefronts are given.  Synchronises `stream`. */
+int q1_batched_pcg(int nprob, q1_op *const *ops, int nrhs, const double *const *b_d,
+                   double *const *x_d, double rtol, int maxit, q1_stats *st, void *stream);
+
 /* Byte model of Section 4 (Tables 1-3) for n_elems hexahedra and n_nodes
  * nodes.  kind: 0 SpMV (Table 1: 12 B per non-zero with 27*dpn non-zeros per
  * row, two vectors), 1 matrix-free (Table 2), 2 partial assembly (Table 3).

@@ -1,0 +1,100 @@
+"""Persistent batched PCG (one cooperative launch for many problems and
+right-hand sides) against the CPU oracle: truncated solves equal the
+oracle's iterates, converged solves meet the tolerance under the oracle's
+operator with the oracle's iteration counts, and the full 32-problem,
+4-right-hand-side workload converges everywhere."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from helpers import dev, make_op
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q1():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2308_09839_amd as q1
+    return q1
+
+
+def laplace_box(n, seed):
+    xyz, conn = si.box_mesh(n, n, n, 1.0, 0.0, seed)
+    k = si.field_lognormal(n ** 3, 0.0, 1.0, seed)[None]
+    return dict(physics=1, n=(n, n, n), xyz=xyz, conn=conn, coef=k, mask=si.face_mask(n, n, n, "z0"))
+
+
+def rhs_set(pr, seed, nrhs):
+    nn = pr["xyz"].shape[1]
+    out = []
+    for c in range(nrhs):
+        b = si.vec_uniform(nrhs * nn, seed, si.STREAM_RHS)[c * nn:(c + 1) * nn].copy()
+        b[pr["mask"] == 1] = 0.0
+        out.append(b)
+    return out
+
+
+def run(q1, probs, bs, rtol, maxit):
+    import torch
+    ops = [make_op(pr, 0, 0) for pr in probs]
+    bd = [[dev(b, torch.float64) for b in row] for row in bs]
+    xd = [[torch.empty_like(b) for b in row] for row in bd]
+    st = q1.q1_batched_pcg(ops, bd, xd, rtol, maxit)
+    return [[x.cpu().numpy() for x in row] for row in xd], st
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 4])
+def test_batched_matches_oracle(q1, orc, nrhs):
+    print(f"\n[batched] nrhs={nrhs}", flush=True)
+    sizes = [4, 9, 6, 12, 3]
+    probs = [laplace_box(n, 300 + i) for i, n in enumerate(sizes)]
+    bs = [rhs_set(pr, 400 + i, nrhs) for i, pr in enumerate(probs)]
+    xs, st = run(q1, probs, bs, 1e-8, 5000)
+    for i, pr in enumerate(probs):
+        A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+        for c in range(nrhs):
+            s = st[i * nrhs + c]
+            ref = orc.pcg(A, bs[i][c], rtol=1e-8)
+            assert s["status"] == 0, (i, c, s)
+            assert orc.true_rel_res(A, xs[i][c], bs[i][c]) <= 1e-8 * (1 + 1e-3)
+            assert abs(s["iters"] - ref.iters) <= 0.02 * ref.iters + 2, (s["iters"], ref.iters)
+
+
+def test_batched_truncated_iterates(q1, orc):
+    print("\n[batched iterates]", flush=True)
+    probs = [laplace_box(n, 500 + n) for n in (5, 8)]
+    bs = [rhs_set(pr, 600 + i, 2) for i, pr in enumerate(probs)]
+    for k in (1, 3, 7):
+        xs, st = run(q1, probs, bs, 0.0, k)
+        for i, pr in enumerate(probs):
+            A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+            for c in range(2):
+                ref = orc.pcg(A, bs[i][c], rtol=0.0, maxit=k)
+                assert st[i * 2 + c]["status"] == -4 and st[i * 2 + c]["iters"] == k
+                assert np.linalg.norm(xs[i][c] - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_batched_zero_rhs(q1, orc):
+    print("\n[batched zero rhs]", flush=True)
+    probs = [laplace_box(4, 7), laplace_box(5, 8)]
+    bs = [[np.zeros(pr["xyz"].shape[1])] for pr in probs]
+    xs, st = run(q1, probs, bs, 1e-8, 100)
+    assert all(s["status"] == 0 and s["iters"] == 0 for s in st)
+    assert all(np.all(x[0] == 0) for x in xs)
+
+
+def test_batched_full_workload(q1, orc):
+    """32 problems with edges U{16..64}, 4 right-hand sides each, to 1e-8."""
+    print("\n[batched full workload]", flush=True)
+    seed = si.seed_for(3)
+    sizes = si.batch_sizes(32, seed)
+    probs = [laplace_box(int(n), seed + 1000 * i) for i, n in enumerate(sizes)]
+    bs = [rhs_set(pr, seed + 2000 * i, 4) for i, pr in enumerate(probs)]
+    xs, st = run(q1, probs, bs, 1e-8, 20000)
+    assert all(s["status"] == 0 for s in st)
+    for i, pr in enumerate(probs):
+        A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+        for c in range(4):
+            assert orc.true_rel_res(A, xs[i][c], bs[i][c]) <= 1e-8 * (1 + 1e-3)
