@@ -162,7 +162,8 @@ def bench_cg16(q1, si, n, seed, args):
 
 def bench_ir96(q1, si, n, seed, args):
     """96^3 elasticity, Dirichlet on z=0, random body force: FP64 Jacobi-PCG vs
-    FP32-apply iterative refinement with FP64 residuals, both to 1e-10."""
+    FP32-apply iterative refinement with FP64 residuals and vs mixed-precision
+    PCG with reliable updates, all to 1e-10."""
     import torch
     s2 = si.seed_for(2)
     pr = si.problem_elasticity(96, s2)
@@ -179,6 +180,9 @@ def bench_ir96(q1, si, n, seed, args):
     t0 = time.perf_counter()
     sti = q1.q1_ir_solve(op64, op32, bd, xd, 1e-10, 1e-4)
     tir = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    stm = q1.q1_mpcg(op64, op32, bd, xd, 1e-10, 0.1, 50000)
+    tmp = time.perf_counter() - t0
     x32 = torch.empty(3 * nn, dtype=torch.float32, device="cuda")
     y32 = torch.empty_like(x32)
     ms32, _ = time_applies(op32, x32, y32, 50, 5)
@@ -190,6 +194,9 @@ def bench_ir96(q1, si, n, seed, args):
             "el96_ir_s": round(tir, 4), "el96_ir_inner_iters": sti["iters"],
             "el96_ir_outer": sti["outer_iters"], "el96_ir_status": sti["status"],
             "el96_ir_rel_res": sti["rel_res"],
+            "el96_mpcg_s": round(tmp, 4), "el96_mpcg_iters": stm["iters"],
+            "el96_mpcg_refreshes": stm["outer_iters"], "el96_mpcg_status": stm["status"],
+            "el96_mpcg_true_rel_res": stm["true_rel_res"],
             "el96_apply_fp64_gdofs": round(3 * nn / (ms64 * 1e-3) / 1e9, 3),
             "el96_apply_fp32_gdofs": round(3 * nn / (ms32 * 1e-3) / 1e9, 3)}
 

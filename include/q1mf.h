@@ -189,6 +189,17 @@ int q1_jacobi_destroy(q1_jacobi *J);
 int q1_ir_solve(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
                 double inner_rtol, int max_outer, int max_inner, q1_stats *st, void *stream);
 
+/* Mixed-precision Jacobi-PCG with reliable updates: the recurrences use the
+ * FP32 operator, FP32 vectors and FP64 dots; x (FP64) accumulates the FP32
+ * corrections.  Each time the recurrence residual has fallen by the factor
+ * delta (e.g. 0.1) since the last refresh, the correction is added to x in
+ * FP64, the true residual b - A64 x is recomputed with the FP64 operator and
+ * rounded into the recurrence, and the search direction is kept.  Stops when
+ * the FP64 true residual satisfies ||r|| <= rtol ||b||.  st->iters counts
+ * Krylov iterations, st->outer_iters the refreshes.  b_d, x_d: FP64. */
+int q1_mpcg(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
+            double delta, int maxit, q1_stats *st, void *stream);
+
 /* Batched persistent Jacobi-PCG: nprob independent scalar-Laplace problems
  * (FP64 operators created with Q1_V_LDS_TILE or AUTO), each with nrhs
  * right-hand sides (1..4), solved by ONE cooperative kernel launch.  b_d and

@@ -269,6 +269,36 @@ __global__ void k_ir_update(int64_t n, const float *__restrict__ d,
   if (i < n) x[i] += sqrt(*nrm2) * double(d[i]);
 }
 
+// Reliable update of the mixed-precision CG: x64 += x32, x32 = 0
+__global__ void k_fold_correction(int64_t n, float *__restrict__ x32, double *__restrict__ x64) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x64[i] += double(x32[i]);
+    x32[i] = 0.0f;
+  }
+}
+// r32 = (float) r64 with partials of rho = r32.(w r32) and r32.r32
+__global__ __launch_bounds__(kRT) void k_refresh_residual(int64_t n, const double *__restrict__ r64,
+                                                          const float *__restrict__ w,
+                                                          float *__restrict__ r32,
+                                                          double *__restrict__ part_rho,
+                                                          double *__restrict__ part_rr) {
+  const Range rg = block_range(n);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    const float ri = float(r64[i]);
+    r32[i] = ri;
+    v[0] += double(ri) * double(w[i] * ri);
+    v[1] += double(ri) * double(ri);
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    part_rho[blockIdx.x] = v[0];
+    part_rr[blockIdx.x] = v[1];
+  }
+}
+__global__ void k_clear_done(Status *st) { st->done = 0; st->status = 0; }
+
 // ---- host drivers ------------------------------------------------------------
 
 namespace {
@@ -531,6 +561,123 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
   return status;
 }
 
+// Mixed-precision PCG with reliable updates.  The Krylov recurrences run on
+// the FP32 operator with FP32 vectors and FP64 dots; x is the FP64 sum of FP32
+// corrections.  Whenever the recurrence residual has fallen by delta since the
+// last refresh, the correction is folded into the FP64 x, the true residual
+// b - A64 x is recomputed in FP64 and rounded into the recurrence; the search
+// direction is kept, so the Krylov history survives the refresh.
+int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double delta, int maxit,
+           q1_stats *stats, hipStream_t s) {
+  const int64_t n = A64.n_nodes * A64.physics;
+  Work W;  // FP32 recurrences
+  int rc = alloc_work<float>(W, n, false);
+  if (rc) return rc;
+  float *x32 = nullptr;
+  double *r64 = nullptr;
+  struct Free {
+    float **a;
+    double **b;
+    ~Free() {
+      if (*a) (void)hipFree(*a);
+      if (*b) (void)hipFree(*b);
+    }
+  } fr{&x32, &r64};
+  Q1_HIP(hipMalloc(&x32, size_t(n) * sizeof(float)));
+  Q1_HIP(hipMalloc(&r64, size_t(n) * sizeof(double)));
+  const auto t0 = std::chrono::steady_clock::now();
+  if ((rc = setup_diag<float>(A32, W, Q1_PC_JACOBI, s))) return rc;
+  const int nb = nblocks_for(n);
+  double *P = W.part;
+  double *part_rho[2] = {P, P + kMaxRB};
+  double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB;
+  float *r = static_cast<float *>(W.r), *p = static_cast<float *>(W.p),
+        *q = static_cast<float *>(W.q), *w = static_cast<float *>(W.w);
+  Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
+  Q1_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
+  Q1_HIP(hipMemsetAsync(x32, 0, size_t(n) * sizeof(float), s));
+  hipLaunchKernelGGL((k_dot<double>), dim3(nb), dim3(kRT), 0, s, n, b, b, part_bb, nullptr);
+  hipLaunchKernelGGL(k_refresh_residual, dim3(nb), dim3(kRT), 0, s, n, b, w, r, part_rho[0],
+                     part_rr);
+  hipLaunchKernelGGL((k_jacobi<float>), grid1(n), dim3(256), 0, s, n, w, r, p);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
+  Q1_HIP(hipGetLastError());
+  if ((rc = read_status(W, s))) return rc;
+  const double bb = W.hst->bb;
+  double rr_true = bb, rr_ref = bb;
+  int status = Q1_OK, k = 0, refreshes = 0;
+  if (bb > 0.0) {
+    const double tol2 = rtol * rtol;
+    status = Q1_ENOCONV;
+    while (k < maxit) {
+      // inner recurrences until the residual fell by delta (or to the tolerance)
+      const double thr = std::max(delta * delta * rr_ref, 0.5 * tol2 * bb);
+      int batch = 1;
+      bool stop = false;
+      while (!stop && k < maxit) {
+        const int m = std::min(batch, maxit - k);
+        for (int j = 0; j < m; ++j, ++k) {
+          if ((rc = launch_apply(A32, p, q, s, &W.st->done))) return rc;
+          hipLaunchKernelGGL((k_dot<float>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
+          hipLaunchKernelGGL((k_pcg_update<float, false>), dim3(nb), dim3(kRT), 0, s, n, p, q, w,
+                             x32, r, nullptr, part_pq, part_rho[k & 1], part_rho[(k + 1) & 1],
+                             part_rr, W.st);
+          hipLaunchKernelGGL((k_pcg_direction<float>), dim3(nb), dim3(kRT), 0, s, n, r, w,
+                             nullptr, p, part_rho[(k + 1) & 1], part_rho[k & 1], part_rr, part_bb,
+                             thr / bb, k + 1, maxit, W.st);
+        }
+        Q1_HIP(hipGetLastError());
+        if ((rc = read_status(W, s))) return rc;
+        stop = W.hst->done != 0;
+        batch = std::min(batch * 2, 32);
+      }
+      if (W.hst->done && W.hst->status == Q1_EBREAKDOWN) {
+        status = Q1_EBREAKDOWN;
+        break;
+      }
+      // the loop ran k iterations; the last direction step was skipped if it stopped early
+      k = W.hst->iter;
+      // reliable update: fold the correction, recompute the residual in FP64
+      hipLaunchKernelGGL(k_fold_correction, grid1(n), dim3(256), 0, s, n, x32, x);
+      if ((rc = launch_apply(A64, x, r64, s))) return rc;
+      hipLaunchKernelGGL((k_residual<double>), grid1(n), dim3(256), 0, s, n, b, r64);
+      hipLaunchKernelGGL((k_dot<double>), dim3(nb), dim3(kRT), 0, s, n, r64, r64,
+                         P + 6 * kMaxRB, nullptr);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, P + 6 * kMaxRB, nb, &W.st->aux);
+      Q1_HIP(hipGetLastError());
+      if ((rc = read_status(W, s))) return rc;
+      rr_true = W.hst->aux;
+      ++refreshes;
+      if (rr_true <= tol2 * bb) {
+        status = Q1_OK;
+        break;
+      }
+      if (k >= maxit) break;
+      rr_ref = rr_true;
+      // continue the recurrences from the true residual, keeping p
+      hipLaunchKernelGGL(k_refresh_residual, dim3(nb), dim3(kRT), 0, s, n, r64, w, r,
+                         part_rho[k & 1], part_rr);
+      hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(1), 0, s, W.st);
+      // beta = rho(new r) / rho_{k-1}; p = w r + beta p
+      hipLaunchKernelGGL((k_pcg_direction<float>), dim3(nb), dim3(kRT), 0, s, n, r, w, nullptr, p,
+                         part_rho[k & 1], part_rho[(k + 1) & 1], part_rr, part_bb, 0.0, k,
+                         maxit + 1, W.st);
+      Q1_HIP(hipGetLastError());
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->iters = k;
+    stats->outer_iters = refreshes;
+    stats->status = status;
+    stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+    stats->rel_res = bb > 0 ? std::sqrt(rr_true / bb) : 0.0;
+    stats->true_rel_res = stats->rel_res;
+    stats->fallback_at = -1;
+  }
+  return status;
+}
+
 }  // namespace
 
 // Jacobi preconditioner object usable as a q1_precond_fn context.
@@ -629,6 +776,20 @@ int q1_jacobi_destroy(q1_jacobi *J) {
   if (J->w) (void)hipFree(J->w);
   delete J;
   return Q1_OK;
+}
+
+int q1_mpcg(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
+            double delta, int maxit, q1_stats *st, void *stream) {
+  Q1_CHECK(op64 && op32 && b_d && x_d, Q1_EINVAL, "q1_mpcg: NULL argument");
+  Op &A64 = *reinterpret_cast<Op *>(op64);
+  Op &A32 = *reinterpret_cast<Op *>(op32);
+  Q1_CHECK(A64.dtype == Q1_F64 && A32.dtype == Q1_F32, Q1_EINVAL,
+           "q1_mpcg: needs an FP64 and an FP32 operator");
+  Q1_CHECK(A64.n_nodes == A32.n_nodes && A64.physics == A32.physics, Q1_EINVAL,
+           "q1_mpcg: operators of different sizes");
+  Q1_CHECK(rtol > 0 && delta > 0 && delta < 1 && maxit >= 0, Q1_EINVAL,
+           "q1_mpcg: need rtol > 0, 0 < delta < 1, maxit >= 0");
+  return mpcg_t(A64, A32, b_d, x_d, rtol, delta, maxit, st, static_cast<hipStream_t>(stream));
 }
 
 int q1_ir_solve(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,

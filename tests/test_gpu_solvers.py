@@ -191,3 +191,52 @@ def test_ir_reaches_fp64_tolerance(q1, orc, physics, n):
     st = q1.q1_ir_solve(op64, op32, bd, xd, 1e-10, 1e-4)
     assert st["status"] == 0 and st["outer_iters"] >= 2
     assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-10 * (1 + 1e-3)
+
+
+# -- mixed-precision PCG with reliable updates ---------------------------------------
+
+@pytest.mark.parametrize("physics,n", [(1, (16, 16, 16)), (3, (10, 10, 10))])
+def test_mpcg_reaches_fp64_tolerance(q1, orc, physics, n):
+    """FP32 recurrences with FP64 refreshes reach an FP64 tolerance that FP32
+    PCG alone cannot, in about the iterations of FP64 PCG."""
+    import torch
+    print(f"\n[mpcg] physics={physics} n={n}", flush=True)
+    pr = problem(physics, n, 0.1 if physics == 1 else 0.0, 82, True)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 82)
+    op64, op32 = make_op(pr, 0, 0), make_op(pr, 1, 0)
+    bd = dev(b, torch.float64)
+    xd = torch.full_like(bd, 7.0)  # x is overwritten, not used as a guess
+    st = q1.q1_mpcg(op64, op32, bd, xd, 1e-10, 0.1, 20000)
+    x = xd.cpu().numpy()
+    assert st["status"] == 0 and st["outer_iters"] >= 2
+    t = orc.true_rel_res(A, x, b)
+    assert t <= 1e-10 * (1 + 1e-3)
+    assert abs(st["true_rel_res"] - t) <= 1e-13
+    ref = orc.pcg(A, b, rtol=1e-10)
+    assert st["iters"] <= 1.25 * ref.iters + 5, (st["iters"], ref.iters)
+
+
+def test_mpcg_edge_cases(q1, orc):
+    import torch
+    print("\n[mpcg edge cases]", flush=True)
+    pr = problem(1, (6, 5, 4), 0.1, 83, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    op64, op32 = make_op(pr, 0, 0), make_op(pr, 1, 0)
+    bd = dev(np.zeros(A.n), torch.float64)
+    xd = torch.full_like(bd, 3.0)
+    st = q1.q1_mpcg(op64, op32, bd, xd, 1e-10, 0.1, 100)
+    assert st["status"] == 0 and st["iters"] == 0 and bool((xd == 0).all())
+    # iteration limit: ENOCONV with x the FP64 sum of the corrections so far
+    b = rhs(A, pr, 83)
+    bd = dev(b, torch.float64)
+    st = q1.q1_mpcg(op64, op32, bd, xd, 1e-14, 0.1, 4)
+    assert st["status"] == -4 and st["iters"] == 4
+    ref = orc.pcg(A, b, rtol=0.0, maxit=4)
+    x = xd.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
+    assert abs(st["true_rel_res"] - orc.true_rel_res(A, x, b)) <= 1e-12
+    with pytest.raises(q1.Q1Error):
+        q1.q1_mpcg(op64, op32, bd, xd, 1e-10, 1.5, 100)
+    with pytest.raises(q1.Q1Error):
+        q1.q1_mpcg(op32, op64, bd, xd, 1e-10, 0.1, 100)
