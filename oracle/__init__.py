@@ -8,7 +8,8 @@ The oracle computes the operator by its plain definition: element matrices by
 2x2x2 Gauss quadrature (paper Section 2), a CSR matrix summed element by
 element (Section 3, assembly by column search and addition), and products
 with that matrix.  ``pcg``/``fpcg`` are Hestenes-Stiefel PCG and flexible PCG
-built from the CG operations of Table 4.
+built from the CG operations of Table 4.  ``unet_oracle`` (numpy, FP64) is
+the learned preconditioner's network written as its definitions.
 """
 from __future__ import annotations
 
