@@ -212,6 +212,102 @@ int q1_mpcg(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rto
 int q1_batched_pcg(int nprob, q1_op *const *ops, int nrhs, const double *const *b_d,
                    double *const *x_d, double rtol, int maxit, q1_stats *st, void *stream);
 
+/* ---- learned preconditioner --------------------------------------------------
+ * The paper lists learned preconditioning only as an outlook beside its future
+ * matrix-free preconditioners (Section 6) and fixes no network.  This library
+ * defines one: a 3-level 3-D convolutional U-Net on the node grid (16/32/64
+ * channels; per level two 3x3x3 zero-padded convolutions with bias and ReLU;
+ * 2x2x2 average pooling down; nearest 2x upsampling concatenated with the
+ * skip tensor up; a 1x1 head), trained with Adam on residual -> error pairs,
+ * and used as z = N(r) inside q1_fpcg, which falls back to Jacobi when z fails
+ * (z.r <= 0, non-finite, stagnation).
+ *
+ * Tensors are channel-last [B][D][H][W][C] (z, y, x, channel), BF16 as
+ * uint16_t bit patterns, C a multiple of 8.  Convolution weights are FP32
+ * W[27][Cin][Cout] with tap t = 9 (dz+1) + 3 (dy+1) + (dx+1) and
+ * y[v][co] = b[co] + sum_t sum_ci x[v + d_t][ci] W[t][ci][co] (zero outside
+ * the grid).  Matrix-core operands are BF16, accumulation FP32. */
+
+/* Single-layer primitives (synchronise `stream`; they allocate temporaries).
+ * Forward: the input is the channel concatenation of a (ca channels; when
+ * up_a, a lives on the half grid D/2 x H/2 x W/2 and is read at the parent
+ * voxel, i.e. nearest 2x upsampling) and b (cb channels, may be 0 and NULL).
+ * w_d is [27][ca+cb][cout]; bias_d may be NULL; relu != 0 applies max(0, .);
+ * y_d is FP32 [B][D][H][W][cout].  cout is 16, 32, 48, 64 or 96, otherwise
+ * Q1_EUNSUPPORTED. */
+int q1_conv3d_forward(int B, int D, int H, int W, const uint16_t *a_d, int ca, int up_a,
+                      const uint16_t *b_d, int cb, const float *w_d, const float *bias_d,
+                      int cout, int relu, float *y_d, void *stream);
+/* Backward-data: gx = adjoint of x -> conv(x, w) applied to gy (BF16
+ * [V][cout]); w_d [27][cin][cout]; gx_d FP32 [V][cin]; cin as cout above. */
+int q1_conv3d_backward_data(int B, int D, int H, int W, const uint16_t *gy_d, int cout,
+                            const float *w_d, int cin, float *gx_d, void *stream);
+/* Backward-weight: gw[t][ci][co] = sum_v x[v + d_t][ci] gy[v][co] and
+ * gb[co] = sum_v gy[v][co], x read as in the forward; gw_d FP32
+ * [27][ca+cb][cout], gb_d FP32 [cout]; cout a multiple of 16.  Deterministic. */
+int q1_conv3d_backward_weight(int B, int D, int H, int W, const uint16_t *a_d, int ca, int up_a,
+                              const uint16_t *b_d, int cb, const uint16_t *gy_d, int cout,
+                              float *gw_d, float *gb_d, void *stream);
+
+typedef struct q1_unet q1_unet;
+/* Network for a D x H x W grid (multiples of 4) and up to `batch` samples
+ * per pass.  Weights are He-normal from `seed` (SplitMix64), biases zero.
+ * The handle owns its parameters, gradients, Adam moments and activations.
+ * Synchronises `stream`. */
+int q1_unet_create(q1_unet **net, int D, int H, int W, int batch, uint64_t seed, void *stream);
+int q1_unet_destroy(q1_unet *net);
+int q1_unet_info(const q1_unet *net, int64_t *nparams, int *D, int *H, int *W, int *batch);
+/* Device pointers to the FP32 parameter and gradient vectors (nparams each).
+ * Layout, in the layer order enc1a enc1b enc2a enc2b enc3a enc3b dec2a dec2b
+ * dec1a dec1b: W[27][Cin][Cout] then b[Cout] (Cin 2, 16, 16, 32, 32, 64,
+ * 64+32, 32, 32+16, 16; Cout 16, 16, 32, 32, 64, 64, 32, 32, 16, 16), then
+ * the head w[16] and b.  After writing parameters call q1_unet_commit. */
+int q1_unet_params(q1_unet *net, float **theta_d, float **grad_d);
+/* Refresh the packed BF16 weights from the FP32 parameters. */
+int q1_unet_commit(q1_unet *net, void *stream);
+/* Copy the parameters (which = 0) or gradients (which = 1) to buf_d
+ * (to_net = 0) or from buf_d into the network (to_net = 1, parameters only;
+ * call q1_unet_commit afterwards); buf_d is a device FP32 [nparams]. */
+int q1_unet_copy(q1_unet *net, int which, int to_net, float *buf_d, void *stream);
+/* out = N(in) for the first nbatch samples: in_d BF16 [nbatch][D][H][W][8]
+ * (channels 2..7 must be zero), out_d FP32 [nbatch][D][H][W].  Activations
+ * stay in the handle for q1_unet_backward; in_d must stay unchanged until then. */
+int q1_unet_forward(q1_unet *net, const uint16_t *in_d, float *out_d, int nbatch, void *stream);
+/* Loss of the last forward: L = sum w (out - target)^2 / sum w and
+ * dout = dL/dout (all FP32 [nbatch][D][H][W]); *loss_d (device, may be NULL). */
+int q1_unet_mse(q1_unet *net, const float *out_d, const float *target_d, const float *weight_d,
+                float *dout_d, float *loss_d, void *stream);
+/* Gradient of the parameters for dL/dout = dout_d at the last forward's
+ * activations, written to the gradient vector (overwritten, deterministic). */
+int q1_unet_backward(q1_unet *net, const float *dout_d, void *stream);
+/* One Adam step (Kingma and Ba) on the parameters with the current gradient;
+ * step counts from 1; repacks the BF16 weights. */
+int q1_unet_adam_step(q1_unet *net, float lr, float b1, float b2, float eps, int step,
+                      void *stream);
+
+typedef struct q1_unet_pc q1_unet_pc;
+/* Preconditioner context for an nx x ny x nz-element box mesh (nodes
+ * x-fastest, (nx+1)(ny+1)(nz+1) <= the grid) with cell coefficients k_d
+ * (FP64 [nx*ny*nz], x-fastest) and optional Dirichlet node mask mask_d; the
+ * node grid sits at the origin of the network grid.  The network handle, k_d
+ * and mask_d must outlive the context.  Synchronises `stream`. */
+int q1_unet_pc_create(q1_unet_pc **pc, q1_unet *net, int nx, int ny, int nz, const double *k_d,
+                      const uint8_t *mask_d, void *stream);
+int q1_unet_pc_destroy(q1_unet_pc *pc);
+/* Network input of a nodal FP64 vector r: channel 0 = r on free nodes scaled
+ * to unit RMS over them (0 on Dirichlet nodes), channel 1 = half the mean of
+ * ln k over each node's cells, everything else 0; in_d BF16 [D][H][W][8]. */
+int q1_unet_encode(q1_unet_pc *pc, const double *r_d, uint16_t *in_d, void *stream);
+/* Training target of a nodal FP64 error e: e on free nodes scaled to unit
+ * RMS, 0 elsewhere (FP32 [D][H][W]); weight_d (may be NULL) = 1 on free
+ * nodes, 0 elsewhere. */
+int q1_unet_encode_target(q1_unet_pc *pc, const double *e_d, float *target_d, float *weight_d,
+                          void *stream);
+/* q1_precond_fn for q1_fpcg with ctx = q1_unet_pc: z = N(encode(r)) on free
+ * nodes, 0 on Dirichlet nodes (FP64 vectors).  Flexible PCG is invariant to a
+ * positive scaling of z, so the output is not rescaled by ||r||. */
+int q1_unet_precond(void *ctx, const void *r_d, void *z_d, void *stream);
+
 /* Byte model of Section 4 (Tables 1-3) for n_elems hexahedra and n_nodes
  * nodes.  kind: 0 SpMV (Table 1: 12 B per non-zero with 27*dpn non-zeros per
  * row, two vectors), 1 matrix-free (Table 2), 2 partial assembly (Table 3).

@@ -23,6 +23,8 @@ __all__ = [
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
     "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_apply", "q1_op_diag",
     "q1_op_info", "q1_op_bytes", "q1_op_destroy", "q1_model_bytes", "Op",
+    "q1_conv3d_forward", "q1_conv3d_backward_data", "q1_conv3d_backward_weight", "UNet",
+    "q1_unet_create", "UNetPrecond", "q1_unet_pc_create",
 ]
 
 
@@ -310,3 +312,127 @@ def q1_batched_pcg(ops, b, x, rtol: float, maxit: int, stream=None) -> list[dict
                                    ctypes.cast(xa, VP), rtol, maxit, ctypes.cast(st, VP),
                                    _stream(stream)))
     return [s_.as_dict() for s_ in st]
+
+
+# ---- learned preconditioner ------------------------------------------------------
+
+def q1_conv3d_forward(a, ca: int, w, cout: int, bias=None, b=None, cb: int = 0, up_a: int = 0,
+                      relu: int = 0, y=None, stream=None):
+    """y (FP32 [B, D, H, W, cout]) = conv3d(concat(up?(a), b)); a, b BF16 channel-last;
+    the output grid is b's, or a's (doubled when up_a)."""
+    import torch
+    ref = b if b is not None else a
+    B, D, H, W = ref.shape[:4]
+    if b is None and up_a:
+        D, H, W = 2 * D, 2 * H, 2 * W
+    if y is None:
+        y = torch.empty((B, D, H, W, cout), dtype=torch.float32, device=a.device)
+    check(lib().q1_conv3d_forward(B, D, H, W, _dptr(a), ca, up_a, _dptr(b), cb, _dptr(w),
+                                  _dptr(bias), cout, relu, _dptr(y), _stream(stream)))
+    return y
+
+
+def q1_conv3d_backward_data(gy, cout: int, w, cin: int, stream=None):
+    import torch
+    B, D, H, W = gy.shape[:4]
+    gx = torch.empty((B, D, H, W, cin), dtype=torch.float32, device=gy.device)
+    check(lib().q1_conv3d_backward_data(B, D, H, W, _dptr(gy), cout, _dptr(w), cin, _dptr(gx),
+                                        _stream(stream)))
+    return gx
+
+
+def q1_conv3d_backward_weight(a, ca: int, gy, cout: int, b=None, cb: int = 0, up_a: int = 0,
+                              stream=None):
+    import torch
+    B, D, H, W = gy.shape[:4]
+    gw = torch.empty((27, ca + cb, cout), dtype=torch.float32, device=gy.device)
+    gb = torch.empty((cout,), dtype=torch.float32, device=gy.device)
+    check(lib().q1_conv3d_backward_weight(B, D, H, W, _dptr(a), ca, up_a, _dptr(b), cb, _dptr(gy),
+                                          cout, _dptr(gw), _dptr(gb), _stream(stream)))
+    return gw, gb
+
+
+class UNet:
+    """Handle of the network (q1_unet_*).  theta/grad are views of the
+    library's FP32 parameter and gradient vectors."""
+
+    def __init__(self, D: int, H: int, W: int, batch: int, seed: int = 0, stream=None):
+        import torch
+        self.handle = ctypes.c_void_p()
+        check(lib().q1_unet_create(ctypes.byref(self.handle), D, H, W, batch, seed,
+                                   _stream(stream)))
+        n = ctypes.c_int64()
+        check(lib().q1_unet_info(self.handle, ctypes.byref(n), None, None, None, None))
+        self.nparams, self.D, self.H, self.W, self.batch = n.value, D, H, W, batch
+
+    def get(self, which: int = 0, stream=None):
+        """Copy of the parameters (which=0) or gradients (which=1), FP32 on the device."""
+        import torch
+        buf = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        check(lib().q1_unet_copy(self.handle, which, 0, _dptr(buf), _stream(stream)))
+        return buf
+
+    def set_params(self, theta, stream=None):
+        """Overwrite the parameters from a device FP32 vector and repack."""
+        check(lib().q1_unet_copy(self.handle, 0, 1, _dptr(theta), _stream(stream)))
+        self.commit(stream)
+
+    def commit(self, stream=None):
+        check(lib().q1_unet_commit(self.handle, _stream(stream)))
+
+    def forward(self, inp, out, nbatch: int, stream=None):
+        check(lib().q1_unet_forward(self.handle, _dptr(inp), _dptr(out), nbatch, _stream(stream)))
+
+    def mse(self, out, target, weight, dout, loss=None, stream=None):
+        check(lib().q1_unet_mse(self.handle, _dptr(out), _dptr(target), _dptr(weight), _dptr(dout),
+                                _dptr(loss), _stream(stream)))
+
+    def backward(self, dout, stream=None):
+        check(lib().q1_unet_backward(self.handle, _dptr(dout), _stream(stream)))
+
+    def adam_step(self, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        check(lib().q1_unet_adam_step(self.handle, lr, b1, b2, eps, step, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib_loaded():
+            lib().q1_unet_destroy(h)
+            self.handle = None
+
+
+def q1_unet_create(D, H, W, batch, seed=0, stream=None) -> UNet:
+    return UNet(D, H, W, batch, seed, stream)
+
+
+class UNetPrecond:
+    """q1_unet_pc: the network as a q1_fpcg preconditioner on a box mesh."""
+
+    def __init__(self, net: UNet, nx: int, ny: int, nz: int, k, mask=None, stream=None):
+        self.net, self.k, self.mask = net, k, mask  # kept alive with the context
+        self.handle = ctypes.c_void_p()
+        check(lib().q1_unet_pc_create(ctypes.byref(self.handle), net.handle, nx, ny, nz, _dptr(k),
+                                      _dptr(mask), _stream(stream)))
+        self.fn = ctypes.cast(lib().q1_unet_precond, ctypes.c_void_p)
+
+    def encode(self, r, inp, stream=None):
+        check(lib().q1_unet_encode(self.handle, _dptr(r), _dptr(inp), _stream(stream)))
+
+    def encode_target(self, e, target, weight=None, stream=None):
+        check(lib().q1_unet_encode_target(self.handle, _dptr(e), _dptr(target), _dptr(weight),
+                                          _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib_loaded():
+            lib().q1_unet_pc_destroy(h)
+            self.handle = None
+
+
+def q1_unet_pc_create(net, nx, ny, nz, k, mask=None, stream=None) -> UNetPrecond:
+    return UNetPrecond(net, nx, ny, nz, k, mask, stream)
+
+
+def _lib_loaded() -> bool:
+    from . import _lib as L
+    return L._lib is not None
+

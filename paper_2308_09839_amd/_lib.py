@@ -58,6 +58,7 @@ _lib = None
 
 c_int, c_i64, c_u64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
 P = ctypes.POINTER
+c_flt = ctypes.c_float
 
 # name -> (restype, argtypes); the declarations of include/q1mf.h
 PROTOTYPES = {
@@ -90,6 +91,27 @@ PROTOTYPES = {
     "q1_batched_pcg": (c_int, [c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_vp, c_vp]),
     "q1_mpcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_int, P(Q1Stats), c_vp]),
     "q1_ir_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),
+    "q1_conv3d_forward": (c_int, [c_int, c_int, c_int, c_int, c_vp, c_int, c_int, c_vp, c_int,
+                                  c_vp, c_vp, c_int, c_int, c_vp, c_vp]),
+    "q1_conv3d_backward_data": (c_int, [c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int,
+                                        c_vp, c_vp]),
+    "q1_conv3d_backward_weight": (c_int, [c_int, c_int, c_int, c_int, c_vp, c_int, c_int, c_vp,
+                                          c_int, c_vp, c_int, c_vp, c_vp, c_vp]),
+    "q1_unet_create": (c_int, [P(c_vp), c_int, c_int, c_int, c_int, c_u64, c_vp]),
+    "q1_unet_destroy": (c_int, [c_vp]),
+    "q1_unet_info": (c_int, [c_vp, P(c_i64), P(c_int), P(c_int), P(c_int), P(c_int)]),
+    "q1_unet_params": (c_int, [c_vp, P(c_vp), P(c_vp)]),
+    "q1_unet_commit": (c_int, [c_vp, c_vp]),
+    "q1_unet_copy": (c_int, [c_vp, c_int, c_int, c_vp, c_vp]),
+    "q1_unet_forward": (c_int, [c_vp, c_vp, c_vp, c_int, c_vp]),
+    "q1_unet_mse": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "q1_unet_backward": (c_int, [c_vp, c_vp, c_vp]),
+    "q1_unet_adam_step": (c_int, [c_vp, c_flt, c_flt, c_flt, c_flt, c_int, c_vp]),
+    "q1_unet_pc_create": (c_int, [P(c_vp), c_vp, c_int, c_int, c_int, c_vp, c_vp, c_vp]),
+    "q1_unet_pc_destroy": (c_int, [c_vp]),
+    "q1_unet_encode": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "q1_unet_encode_target": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "q1_unet_precond": (c_int, [c_vp, c_vp, c_vp, c_vp]),
 }
 
 

@@ -1,0 +1,778 @@
+// The learned preconditioner: a 3-level 3-D convolutional U-Net on the node
+// grid (channels 16/32/64, two 3x3x3 convolutions with ReLU per level, 2x2x2
+// average pooling down, nearest upsampling and concatenation with the skip
+// tensor up, 1x1 head), trained with Adam on residual -> error pairs and used
+// as z = N(r) inside flexible PCG.  The paper names learned preconditioning
+// only as an outlook next to its future matrix-free preconditioners
+// (Section 6); the network, its encoding and its training are this library's.
+//
+// Storage: BF16 activations and packed BF16 weights for the matrix cores,
+// FP32 master weights, gradients and Adam moments in one flat vector whose
+// layout is, per convolution, W[27][Cin][Cout] then b[Cout], and for the head
+// w[16] then b.  Activations are kept from the last forward for the backward.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "q1_conv.hpp"
+#include "q1_internal.hpp"
+
+namespace q1 {
+
+namespace {
+
+struct LayerSpec {
+  int cin_real, cin, cout, level, ca, up;  // ca: channels read from the upsampled tensor
+};
+// enc1a enc1b enc2a enc2b enc3a enc3b dec2a dec2b dec1a dec1b
+constexpr LayerSpec kSpec[10] = {
+    {2, 8, 16, 1, 8, 0},    {16, 16, 16, 1, 16, 0}, {16, 16, 32, 2, 16, 0},
+    {32, 32, 32, 2, 32, 0}, {32, 32, 64, 3, 32, 0}, {64, 64, 64, 3, 64, 0},
+    {96, 96, 32, 2, 64, 1}, {32, 32, 32, 2, 32, 0}, {48, 48, 16, 1, 32, 1},
+    {16, 16, 16, 1, 16, 0}};
+constexpr int kInC = 8;  // stored input channels (2 used)
+
+struct Layer {
+  LayerSpec s;
+  int64_t wo = 0, bo = 0;
+  int ngroups = 0, nchunks = 0, ngroups_b = 0, nchunks_b = 0;
+  bf16 *wp = nullptr, *wq = nullptr;
+};
+
+}  // namespace
+
+struct UNet {
+  int D = 0, H = 0, W = 0, B = 0;
+  int64_t nparams = 0, head_o = 0;
+  float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  Layer L[10];
+  bf16 *act[10] = {};
+  bf16 *p1 = nullptr, *p2 = nullptr;
+  bf16 *g1a = nullptr, *g1b = nullptr, *g2a = nullptr, *g2b = nullptr, *g3a = nullptr,
+       *g3b = nullptr;
+  float *gup1 = nullptr, *gskip1 = nullptr, *gup2 = nullptr, *gskip2 = nullptr, *gp2 = nullptr,
+        *gp1 = nullptr;
+  float *part = nullptr, *bpart = nullptr, *hpart = nullptr;
+  double *mpart = nullptr;
+  size_t part_cap = 0, bpart_cap = 0;
+  const bf16 *last_in = nullptr;
+  int last_nb = 0;
+  std::vector<void *> allocs;
+
+  int64_t vox(int level) const {
+    const int f = 1 << (level - 1);
+    return int64_t(B) * (D / f) * (H / f) * (W / f);
+  }
+  ~UNet() {
+    for (void *p : allocs) (void)hipFree(p);
+  }
+};
+
+struct UNetPC {
+  UNet *net = nullptr;
+  int nx = 0, ny = 0, nz = 0;
+  int64_t nn = 0, n_free = 0;
+  const uint8_t *mask = nullptr;
+  bf16 *in = nullptr;   // one input sample [D][H][W][8] with the coefficient channel set
+  float *out = nullptr;  // [D][H][W]
+  float *kap = nullptr;  // nodal channel-1 values [nn]
+  double *part = nullptr;
+  ~UNetPC() {
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    if (kap) (void)hipFree(kap);
+    if (part) (void)hipFree(part);
+  }
+};
+
+namespace {
+
+template <typename T>
+int dalloc(UNet &n, T **p, size_t count) {
+  void *q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+    return fail(Q1_ENOMEM, "q1_unet: device allocation of %zu bytes failed", count * sizeof(T));
+  n.allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return Q1_OK;
+}
+
+// SplitMix64 + Box-Muller for the initial weights
+inline uint64_t mix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline double u01(uint64_t seed, uint64_t i) {
+  return (double(mix(seed ^ mix(i)) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+int pack_all(UNet &n, hipStream_t s) {
+  for (int l = 0; l < 10; ++l) {
+    Layer &L = n.L[l];
+    int rc = pack_forward(n.theta + L.wo, L.s.cin_real, L.s.cin, L.s.cout, L.nchunks * 4, L.wp, s);
+    if (rc) return rc;
+    if (L.wq && (rc = pack_backward(n.theta + L.wo, L.s.cin_real, L.s.cout, L.nchunks_b * 4, L.wq, s)))
+      return rc;
+  }
+  return Q1_OK;
+}
+
+ConvArgs conv_args(const UNet &n, int l, int nb, const bf16 *a, const bf16 *b) {
+  const Layer &L = n.L[l];
+  const int f = 1 << (L.s.level - 1);
+  ConvArgs c;
+  c.a = a;
+  c.ca = L.s.ca;
+  c.up_a = L.s.up;
+  c.b = b;
+  c.cb = L.s.cin - L.s.ca;
+  c.B = nb;
+  c.D = n.D / f;
+  c.H = n.H / f;
+  c.W = n.W / f;
+  return c;
+}
+
+int layer_forward(UNet &n, int l, int nb, const bf16 *a, const bf16 *b, hipStream_t s) {
+  const Layer &L = n.L[l];
+  ConvArgs c = conv_args(n, l, nb, a, b);
+  c.wp = L.wp;
+  c.ngroups = L.ngroups;
+  c.nchunks = L.nchunks;
+  c.cout = L.s.cout;
+  c.bias = n.theta + L.bo;
+  c.relu = 1;
+  c.out_bf = n.act[l];
+  return conv_forward(c, s);
+}
+
+// input gradient of layer l from its pre-activation gradient g
+int layer_backward_data(UNet &n, int l, int nb, const bf16 *g, const bf16 *mask, bf16 *out_bf,
+                        float *out_f32, int split, float *out2, hipStream_t s) {
+  const Layer &L = n.L[l];
+  const int f = 1 << (L.s.level - 1);
+  ConvArgs c;
+  c.a = g;
+  c.ca = L.s.cout;
+  c.B = nb;
+  c.D = n.D / f;
+  c.H = n.H / f;
+  c.W = n.W / f;
+  c.wp = L.wq;
+  c.ngroups = L.ngroups_b;
+  c.nchunks = L.nchunks_b;
+  c.cout = L.s.cin;
+  c.mask = mask;
+  c.out_bf = out_bf;
+  c.out_f32 = out_f32;
+  c.split = split;
+  c.out2_f32 = out2;
+  return conv_forward(c, s);
+}
+
+int layer_wgrad(UNet &n, int l, int nb, const bf16 *a, const bf16 *b, const bf16 *g,
+                hipStream_t s) {
+  const Layer &L = n.L[l];
+  const ConvArgs c = conv_args(n, l, nb, a, b);
+  ConvWArgs w;
+  w.a = c.a;
+  w.b = c.b;
+  w.ca = c.ca;
+  w.cb = c.cb;
+  w.up_a = c.up_a;
+  w.B = nb;
+  w.D = c.D;
+  w.H = c.H;
+  w.W = c.W;
+  w.g = g;
+  w.cout = L.s.cout;
+  w.cin_real = L.s.cin_real;
+  w.nchunks = wgrad_chunks(w);
+  w.part = n.part;
+  w.bpart = n.bpart;
+  return conv_wgrad(w, n.grad + L.wo, n.grad + L.bo, s);
+}
+
+int unet_forward(UNet &n, const bf16 *in, float *out, int nb, hipStream_t s) {
+  int rc;
+  const int D = n.D, H = n.H, W = n.W;
+  bf16 **A = n.act;
+  if ((rc = layer_forward(n, 0, nb, in, nullptr, s))) return rc;
+  if ((rc = layer_forward(n, 1, nb, A[0], nullptr, s))) return rc;
+  if ((rc = pool2(A[1], nb, D, H, W, 16, n.p1, s))) return rc;
+  if ((rc = layer_forward(n, 2, nb, n.p1, nullptr, s))) return rc;
+  if ((rc = layer_forward(n, 3, nb, A[2], nullptr, s))) return rc;
+  if ((rc = pool2(A[3], nb, D / 2, H / 2, W / 2, 32, n.p2, s))) return rc;
+  if ((rc = layer_forward(n, 4, nb, n.p2, nullptr, s))) return rc;
+  if ((rc = layer_forward(n, 5, nb, A[4], nullptr, s))) return rc;
+  if ((rc = layer_forward(n, 6, nb, A[5], A[3], s))) return rc;
+  if ((rc = layer_forward(n, 7, nb, A[6], nullptr, s))) return rc;
+  if ((rc = layer_forward(n, 8, nb, A[7], A[1], s))) return rc;
+  if ((rc = layer_forward(n, 9, nb, A[8], nullptr, s))) return rc;
+  if ((rc = head_forward(A[9], int64_t(nb) * D * H * W, n.theta + n.head_o, out, s))) return rc;
+  n.last_in = in;
+  n.last_nb = nb;
+  return Q1_OK;
+}
+
+int unet_backward(UNet &n, const float *dout, hipStream_t s) {
+  int rc;
+  const int nb = n.last_nb;
+  const int D = n.D, H = n.H, W = n.W;
+  bf16 **A = n.act;
+  const int64_t v1 = int64_t(nb) * D * H * W;
+  const int hblk = int(std::min<int64_t>(1024, (v1 + 255) / 256));
+  if ((rc = head_backward(dout, A[9], v1, n.theta + n.head_o, n.g1a, n.hpart, hblk,
+                          n.grad + n.head_o, s)))
+    return rc;
+  // level 1 decoder
+  if ((rc = layer_wgrad(n, 9, nb, A[8], nullptr, n.g1a, s))) return rc;
+  if ((rc = layer_backward_data(n, 9, nb, n.g1a, A[8], n.g1b, nullptr, 0, nullptr, s))) return rc;
+  if ((rc = layer_wgrad(n, 8, nb, A[7], A[1], n.g1b, s))) return rc;
+  if ((rc = layer_backward_data(n, 8, nb, n.g1b, nullptr, nullptr, n.gup1, 32, n.gskip1, s)))
+    return rc;
+  if ((rc = up_adjoint_mask(n.gup1, A[7], nb, D / 2, H / 2, W / 2, 32, n.g2a, s))) return rc;
+  // level 2 decoder
+  if ((rc = layer_wgrad(n, 7, nb, A[6], nullptr, n.g2a, s))) return rc;
+  if ((rc = layer_backward_data(n, 7, nb, n.g2a, A[6], n.g2b, nullptr, 0, nullptr, s))) return rc;
+  if ((rc = layer_wgrad(n, 6, nb, A[5], A[3], n.g2b, s))) return rc;
+  if ((rc = layer_backward_data(n, 6, nb, n.g2b, nullptr, nullptr, n.gup2, 64, n.gskip2, s)))
+    return rc;
+  if ((rc = up_adjoint_mask(n.gup2, A[5], nb, D / 4, H / 4, W / 4, 64, n.g3a, s))) return rc;
+  // level 3
+  if ((rc = layer_wgrad(n, 5, nb, A[4], nullptr, n.g3a, s))) return rc;
+  if ((rc = layer_backward_data(n, 5, nb, n.g3a, A[4], n.g3b, nullptr, 0, nullptr, s))) return rc;
+  if ((rc = layer_wgrad(n, 4, nb, n.p2, nullptr, n.g3b, s))) return rc;
+  if ((rc = layer_backward_data(n, 4, nb, n.g3b, nullptr, nullptr, n.gp2, 0, nullptr, s)))
+    return rc;
+  if ((rc = pool_adjoint_add_mask(n.gskip2, n.gp2, A[3], nb, D / 2, H / 2, W / 2, 32, n.g2a, s)))
+    return rc;
+  // level 2 encoder
+  if ((rc = layer_wgrad(n, 3, nb, A[2], nullptr, n.g2a, s))) return rc;
+  if ((rc = layer_backward_data(n, 3, nb, n.g2a, A[2], n.g2b, nullptr, 0, nullptr, s))) return rc;
+  if ((rc = layer_wgrad(n, 2, nb, n.p1, nullptr, n.g2b, s))) return rc;
+  if ((rc = layer_backward_data(n, 2, nb, n.g2b, nullptr, nullptr, n.gp1, 0, nullptr, s)))
+    return rc;
+  if ((rc = pool_adjoint_add_mask(n.gskip1, n.gp1, A[1], nb, D, H, W, 16, n.g1a, s))) return rc;
+  // level 1 encoder
+  if ((rc = layer_wgrad(n, 1, nb, A[0], nullptr, n.g1a, s))) return rc;
+  if ((rc = layer_backward_data(n, 1, nb, n.g1a, A[0], n.g1b, nullptr, 0, nullptr, s))) return rc;
+  return layer_wgrad(n, 0, nb, n.last_in, nullptr, n.g1b, s);
+}
+
+// ---- preconditioner encoding ---------------------------------------------------------
+
+constexpr int kEB = 256;
+
+// mean of ln k over the cells adjacent to each node, halved (input channel 1)
+__global__ void k_kappa(const double *__restrict__ k, int nx, int ny, int nz,
+                        float *__restrict__ kap) {
+  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nn = int64_t(nx + 1) * (ny + 1) * (nz + 1);
+  if (id >= nn) return;
+  const int i = int(id % (nx + 1)), j = int((id / (nx + 1)) % (ny + 1)),
+            kk = int(id / (int64_t(nx + 1) * (ny + 1)));
+  double s = 0.0;
+  int c = 0;
+  for (int dz = -1; dz <= 0; ++dz)
+    for (int dy = -1; dy <= 0; ++dy)
+      for (int dx = -1; dx <= 0; ++dx) {
+        const int ex = i + dx, ey = j + dy, ez = kk + dz;
+        if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+        s += log(k[(int64_t(ez) * ny + ey) * nx + ex]);
+        ++c;
+      }
+  kap[id] = float(0.5 * s / c);
+}
+
+// per-block partials of sum over free nodes of v^2
+__global__ __launch_bounds__(kEB) void k_free_norm(const double *__restrict__ v,
+                                                  const uint8_t *__restrict__ mask, int64_t nn,
+                                                  double *__restrict__ part) {
+  __shared__ double sh[kEB / 64];
+  double s = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kEB + threadIdx.x; i < nn; i += int64_t(gridDim.x) * kEB)
+    if (!mask || !mask[i]) s += v[i] * v[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kEB / 64; ++k) t += sh[k];
+    part[blockIdx.x] = t;
+  }
+}
+
+__device__ __forceinline__ double scale_from(const double *part, int nparts, int64_t n_free) {
+  double s = 0.0;
+  for (int k = 0; k < nparts; ++k) s += part[k];
+  return s > 0.0 ? sqrt(double(n_free) / s) : 0.0;
+}
+
+// full input sample [D][H][W][8]: channel 0 = r scaled to unit RMS on free nodes,
+// channel 1 = kappa on mesh nodes, zero elsewhere
+__global__ void k_encode(const double *__restrict__ r, const uint8_t *__restrict__ mask,
+                         const float *__restrict__ kap, const double *__restrict__ part, int nparts,
+                         int64_t n_free, int nx, int ny, int nz, int D, int H, int W,
+                         bf16 *__restrict__ in) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= int64_t(D) * H * W) return;
+  const int x = int(v % W), y = int((v / W) % H), z = int(v / (int64_t(W) * H));
+  unsigned short c0 = 0, c1 = 0;
+  if (x <= nx && y <= ny && z <= nz) {
+    const int64_t id = (int64_t(z) * (ny + 1) + y) * (nx + 1) + x;
+    const double sc = scale_from(part, nparts, n_free);
+    if (!mask || !mask[id]) c0 = __builtin_bit_cast(unsigned short, static_cast<__bf16>(float(r[id] * sc)));
+    c1 = __builtin_bit_cast(unsigned short, static_cast<__bf16>(kap[id]));
+  }
+  uint4 o;
+  o.x = unsigned(c0) | (unsigned(c1) << 16);
+  o.y = o.z = o.w = 0u;
+  *reinterpret_cast<uint4 *>(in + v * kInC) = o;
+}
+
+// target on the grid: e scaled to unit RMS on free nodes; weight 1 there, else 0
+__global__ void k_encode_target(const double *__restrict__ e, const uint8_t *__restrict__ mask,
+                                const double *__restrict__ part, int nparts, int64_t n_free,
+                                int nx, int ny, int nz, int D, int H, int W,
+                                float *__restrict__ tgt, float *__restrict__ wgt) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= int64_t(D) * H * W) return;
+  const int x = int(v % W), y = int((v / W) % H), z = int(v / (int64_t(W) * H));
+  float t = 0.f, w = 0.f;
+  if (x <= nx && y <= ny && z <= nz) {
+    const int64_t id = (int64_t(z) * (ny + 1) + y) * (nx + 1) + x;
+    if (!mask || !mask[id]) {
+      t = float(e[id] * scale_from(part, nparts, n_free));
+      w = 1.f;
+    }
+  }
+  tgt[v] = t;
+  if (wgt) wgt[v] = w;
+}
+
+// z on the nodes: the network output on free nodes, 0 on Dirichlet nodes
+__global__ void k_decode(const float *__restrict__ out, const uint8_t *__restrict__ mask, int nx,
+                         int ny, int nz, int H, int W, double *__restrict__ z) {
+  const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nn = int64_t(nx + 1) * (ny + 1) * (nz + 1);
+  if (id >= nn) return;
+  const int x = int(id % (nx + 1)), y = int((id / (nx + 1)) % (ny + 1)),
+            zz = int(id / (int64_t(nx + 1) * (ny + 1)));
+  z[id] = (mask && mask[id]) ? 0.0 : double(out[(int64_t(zz) * H + y) * W + x]);
+}
+
+inline dim3 grid_for(int64_t n, int bs = 256) { return dim3(unsigned((n + bs - 1) / bs)); }
+
+int pc_norm(UNetPC &pc, const double *v, hipStream_t s, int *nparts) {
+  const int nb = int(std::min<int64_t>(256, (pc.nn + kEB - 1) / kEB));
+  hipLaunchKernelGGL(k_free_norm, dim3(nb), dim3(kEB), 0, s, v, pc.mask, pc.nn, pc.part);
+  Q1_HIP(hipGetLastError());
+  *nparts = nb;
+  return Q1_OK;
+}
+
+int pc_encode(UNetPC &pc, const double *r, bf16 *in, hipStream_t s) {
+  int np = 0, rc = pc_norm(pc, r, s, &np);
+  if (rc) return rc;
+  const UNet &n = *pc.net;
+  hipLaunchKernelGGL(k_encode, grid_for(int64_t(n.D) * n.H * n.W), dim3(256), 0, s, r, pc.mask,
+                     pc.kap, pc.part, np, pc.n_free, pc.nx, pc.ny, pc.nz, n.D, n.H, n.W, in);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+}  // namespace
+}  // namespace q1
+
+using namespace q1;
+
+struct q1_unet : public q1::UNet {};
+struct q1_unet_pc : public q1::UNetPC {};
+
+extern "C" {
+
+int q1_unet_create(q1_unet **out, int D, int H, int W, int batch, uint64_t seed, void *stream) {
+  Q1_CHECK(out, Q1_EINVAL, "q1_unet_create: NULL argument");
+  *out = nullptr;
+  Q1_CHECK(D >= 4 && H >= 4 && W >= 4 && D % 4 == 0 && H % 4 == 0 && W % 4 == 0 && batch >= 1,
+           Q1_EINVAL, "q1_unet_create: grid %dx%dx%d must be multiples of 4, batch >= 1", D, H, W);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  q1_unet *np = new (std::nothrow) q1_unet();
+  Q1_CHECK(np, Q1_ENOMEM, "q1_unet_create: out of host memory");
+  UNet &n = *np;
+  n.D = D;
+  n.H = H;
+  n.W = W;
+  n.B = batch;
+  int64_t off = 0;
+  size_t part_cap = 0, bpart_cap = 0;
+  for (int l = 0; l < 10; ++l) {
+    Layer &L = n.L[l];
+    L.s = kSpec[l];
+    L.wo = off;
+    L.bo = off + int64_t(27) * L.s.cin_real * L.s.cout;
+    off = L.bo + L.s.cout;
+    L.ngroups = 27 * L.s.cin / 8;
+    L.nchunks = (L.ngroups + 3) / 4;
+    L.ngroups_b = 27 * L.s.cout / 8;
+    L.nchunks_b = (L.ngroups_b + 3) / 4;
+    const int f = 1 << (L.s.level - 1);
+    ConvWArgs w;
+    w.B = batch;
+    w.D = D / f;
+    w.H = H / f;
+    w.W = W / f;
+    w.ca = L.s.cin;
+    w.cout = L.s.cout;
+    const int nch = wgrad_chunks(w);
+    part_cap = std::max(part_cap, size_t(nch) * 27 * L.s.cin_real * L.s.cout);
+    bpart_cap = std::max(bpart_cap, size_t(nch) * L.s.cout);
+  }
+  n.head_o = off;
+  n.nparams = off + 17;
+  int rc = Q1_OK;
+  auto A = [&](auto **p, size_t cnt) {
+    if (!rc) rc = dalloc(n, p, cnt);
+  };
+  A(&n.theta, n.nparams);
+  A(&n.grad, n.nparams);
+  A(&n.m, n.nparams);
+  A(&n.v, n.nparams);
+  for (int l = 0; l < 10; ++l) {
+    Layer &L = n.L[l];
+    A(&L.wp, size_t(L.nchunks) * 4 * L.s.cout * 8);
+    if (l > 0) A(&L.wq, size_t(L.nchunks_b) * 4 * L.s.cin * 8);
+    A(&n.act[l], size_t(n.vox(L.s.level)) * L.s.cout);
+  }
+  A(&n.p1, size_t(n.vox(2)) * 16);
+  A(&n.p2, size_t(n.vox(3)) * 32);
+  A(&n.g1a, size_t(n.vox(1)) * 16);
+  A(&n.g1b, size_t(n.vox(1)) * 16);
+  A(&n.g2a, size_t(n.vox(2)) * 32);
+  A(&n.g2b, size_t(n.vox(2)) * 32);
+  A(&n.g3a, size_t(n.vox(3)) * 64);
+  A(&n.g3b, size_t(n.vox(3)) * 64);
+  A(&n.gup1, size_t(n.vox(1)) * 32);
+  A(&n.gskip1, size_t(n.vox(1)) * 16);
+  A(&n.gup2, size_t(n.vox(2)) * 64);
+  A(&n.gskip2, size_t(n.vox(2)) * 32);
+  A(&n.gp2, size_t(n.vox(3)) * 32);
+  A(&n.gp1, size_t(n.vox(2)) * 16);
+  A(&n.part, part_cap);
+  A(&n.bpart, bpart_cap);
+  A(&n.hpart, size_t(1024) * 17);
+  A(&n.mpart, size_t(1024) * 2);
+  n.part_cap = part_cap;
+  n.bpart_cap = bpart_cap;
+  if (!rc) {
+    // He-normal weights (std sqrt(2 / fan_in)), zero biases, zero moments
+    std::vector<float> th(size_t(n.nparams), 0.f);
+    uint64_t key = mix(seed ^ 0x5eed5eedull);
+    for (int l = 0; l < 10; ++l) {
+      const Layer &L = n.L[l];
+      const double sd = std::sqrt(2.0 / (27.0 * L.s.cin_real));
+      for (int64_t i = L.wo; i < L.bo; ++i) {
+        const double u1 = u01(key, 2 * uint64_t(i)), u2 = u01(key, 2 * uint64_t(i) + 1);
+        th[size_t(i)] = float(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
+      }
+    }
+    for (int64_t i = n.head_o; i < n.head_o + 16; ++i) {
+      const double u1 = u01(key, 2 * uint64_t(i)), u2 = u01(key, 2 * uint64_t(i) + 1);
+      th[size_t(i)] = float(std::sqrt(2.0 / 16.0) * std::sqrt(-2.0 * std::log(u1)) *
+                            std::cos(6.283185307179586 * u2));
+    }
+    if (hipMemcpyAsync(n.theta, th.data(), th.size() * sizeof(float), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemsetAsync(n.m, 0, size_t(n.nparams) * sizeof(float), s) != hipSuccess ||
+        hipMemsetAsync(n.v, 0, size_t(n.nparams) * sizeof(float), s) != hipSuccess ||
+        hipMemsetAsync(n.grad, 0, size_t(n.nparams) * sizeof(float), s) != hipSuccess)
+      rc = fail(Q1_EHIP, "q1_unet_create: initialisation failed");
+    if (!rc) rc = pack_all(n, s);
+    if (!rc && hipStreamSynchronize(s) != hipSuccess)
+      rc = fail(Q1_EHIP, "q1_unet_create: initialisation failed");
+  }
+  if (rc) {
+    delete np;
+    return rc;
+  }
+  *out = np;
+  return Q1_OK;
+}
+
+int q1_unet_destroy(q1_unet *net) {
+  delete net;
+  return Q1_OK;
+}
+
+int q1_unet_info(const q1_unet *net, int64_t *nparams, int *D, int *H, int *W, int *batch) {
+  Q1_CHECK(net, Q1_EINVAL, "q1_unet_info: NULL network");
+  if (nparams) *nparams = net->nparams;
+  if (D) *D = net->D;
+  if (H) *H = net->H;
+  if (W) *W = net->W;
+  if (batch) *batch = net->B;
+  return Q1_OK;
+}
+
+int q1_unet_params(q1_unet *net, float **theta_d, float **grad_d) {
+  Q1_CHECK(net, Q1_EINVAL, "q1_unet_params: NULL network");
+  if (theta_d) *theta_d = net->theta;
+  if (grad_d) *grad_d = net->grad;
+  return Q1_OK;
+}
+
+int q1_unet_commit(q1_unet *net, void *stream) {
+  Q1_CHECK(net, Q1_EINVAL, "q1_unet_commit: NULL network");
+  return pack_all(*net, static_cast<hipStream_t>(stream));
+}
+
+int q1_unet_copy(q1_unet *net, int which, int to_net, float *buf_d, void *stream) {
+  Q1_CHECK(net && buf_d, Q1_EINVAL, "q1_unet_copy: NULL argument");
+  Q1_CHECK((which == 0 || which == 1) && (to_net == 0 || to_net == 1) && !(which == 1 && to_net),
+           Q1_EINVAL, "q1_unet_copy: which %d to_net %d", which, to_net);
+  float *lib_buf = which == 0 ? net->theta : net->grad;
+  const size_t bytes = size_t(net->nparams) * sizeof(float);
+  Q1_HIP(hipMemcpyAsync(to_net ? lib_buf : buf_d, to_net ? buf_d : lib_buf, bytes,
+                        hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  return Q1_OK;
+}
+
+int q1_unet_forward(q1_unet *net, const uint16_t *in_d, float *out_d, int nbatch, void *stream) {
+  Q1_CHECK(net && in_d && out_d, Q1_EINVAL, "q1_unet_forward: NULL argument");
+  Q1_CHECK(nbatch >= 1 && nbatch <= net->B, Q1_EINVAL, "q1_unet_forward: nbatch %d not in [1, %d]",
+           nbatch, net->B);
+  return unet_forward(*net, in_d, out_d, nbatch, static_cast<hipStream_t>(stream));
+}
+
+int q1_unet_mse(q1_unet *net, const float *out_d, const float *target_d, const float *weight_d,
+                float *dout_d, float *loss_d, void *stream) {
+  Q1_CHECK(net && out_d && target_d && weight_d && dout_d, Q1_EINVAL, "q1_unet_mse: NULL argument");
+  Q1_CHECK(net->last_nb >= 1, Q1_EINVAL, "q1_unet_mse: no forward pass yet");
+  const int64_t n = int64_t(net->last_nb) * net->D * net->H * net->W;
+  const int nblk = int(std::min<int64_t>(1024, (n + 255) / 256));
+  return mse(out_d, target_d, weight_d, n, net->mpart, nblk, dout_d, loss_d,
+             static_cast<hipStream_t>(stream));
+}
+
+int q1_unet_backward(q1_unet *net, const float *dout_d, void *stream) {
+  Q1_CHECK(net && dout_d, Q1_EINVAL, "q1_unet_backward: NULL argument");
+  Q1_CHECK(net->last_nb >= 1, Q1_EINVAL, "q1_unet_backward: no forward pass yet");
+  return unet_backward(*net, dout_d, static_cast<hipStream_t>(stream));
+}
+
+int q1_unet_adam_step(q1_unet *net, float lr, float b1, float b2, float eps, int step,
+                      void *stream) {
+  Q1_CHECK(net, Q1_EINVAL, "q1_unet_adam_step: NULL network");
+  Q1_CHECK(step >= 1 && lr > 0 && b1 >= 0 && b1 < 1 && b2 >= 0 && b2 < 1 && eps > 0, Q1_EINVAL,
+           "q1_unet_adam_step: bad hyper-parameters");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = adam(net->theta, net->grad, net->m, net->v, net->nparams, lr, b1, b2, eps, step, s);
+  return rc ? rc : pack_all(*net, s);
+}
+
+// ---- single-layer primitives (synchronous: they pack the weights into temporaries) ----
+
+namespace {
+struct TmpBuf {
+  void *p = nullptr;
+  ~TmpBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+bool conv_cout_ok(int c) { return c == 16 || c == 32 || c == 48 || c == 64 || c == 96; }
+}  // namespace
+
+int q1_conv3d_forward(int B, int D, int H, int W, const uint16_t *a_d, int ca, int up_a,
+                      const uint16_t *b_d, int cb, const float *w_d, const float *bias_d, int cout,
+                      int relu, float *y_d, void *stream) {
+  Q1_CHECK(a_d && w_d && y_d && (cb == 0 || b_d), Q1_EINVAL, "q1_conv3d_forward: NULL argument");
+  Q1_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1 && ca >= 8 && ca % 8 == 0 && cb >= 0 && cb % 8 == 0,
+           Q1_EINVAL, "q1_conv3d_forward: bad sizes (channels must be multiples of 8)");
+  Q1_CHECK(!up_a || (D % 2 == 0 && H % 2 == 0 && W % 2 == 0), Q1_EINVAL,
+           "q1_conv3d_forward: upsampled input needs an even grid");
+  Q1_CHECK(conv_cout_ok(cout), Q1_EUNSUPPORTED, "q1_conv3d_forward: cout %d", cout);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int cin = ca + cb, ngroups = 27 * cin / 8, nchunks = (ngroups + 3) / 4;
+  TmpBuf wp;
+  Q1_HIP(hipMalloc(&wp.p, size_t(nchunks) * 4 * cout * 8 * sizeof(bf16)));
+  int rc = pack_forward(w_d, cin, cin, cout, nchunks * 4, static_cast<bf16 *>(wp.p), s);
+  if (rc) return rc;
+  ConvArgs c;
+  c.a = a_d;
+  c.ca = ca;
+  c.up_a = up_a;
+  c.b = b_d;
+  c.cb = cb;
+  c.B = B;
+  c.D = D;
+  c.H = H;
+  c.W = W;
+  c.wp = static_cast<bf16 *>(wp.p);
+  c.ngroups = ngroups;
+  c.nchunks = nchunks;
+  c.cout = cout;
+  c.bias = bias_d;
+  c.relu = relu;
+  c.out_f32 = y_d;
+  if ((rc = conv_forward(c, s))) return rc;
+  Q1_HIP(hipStreamSynchronize(s));
+  return Q1_OK;
+}
+
+int q1_conv3d_backward_data(int B, int D, int H, int W, const uint16_t *gy_d, int cout,
+                            const float *w_d, int cin, float *gx_d, void *stream) {
+  Q1_CHECK(gy_d && w_d && gx_d, Q1_EINVAL, "q1_conv3d_backward_data: NULL argument");
+  Q1_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1 && cout % 8 == 0 && cout >= 8, Q1_EINVAL,
+           "q1_conv3d_backward_data: bad sizes");
+  Q1_CHECK(conv_cout_ok(cin), Q1_EUNSUPPORTED, "q1_conv3d_backward_data: cin %d", cin);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ngroups = 27 * cout / 8, nchunks = (ngroups + 3) / 4;
+  TmpBuf wq;
+  Q1_HIP(hipMalloc(&wq.p, size_t(nchunks) * 4 * cin * 8 * sizeof(bf16)));
+  int rc = pack_backward(w_d, cin, cout, nchunks * 4, static_cast<bf16 *>(wq.p), s);
+  if (rc) return rc;
+  ConvArgs c;
+  c.a = gy_d;
+  c.ca = cout;
+  c.B = B;
+  c.D = D;
+  c.H = H;
+  c.W = W;
+  c.wp = static_cast<bf16 *>(wq.p);
+  c.ngroups = ngroups;
+  c.nchunks = nchunks;
+  c.cout = cin;
+  c.out_f32 = gx_d;
+  if ((rc = conv_forward(c, s))) return rc;
+  Q1_HIP(hipStreamSynchronize(s));
+  return Q1_OK;
+}
+
+int q1_conv3d_backward_weight(int B, int D, int H, int W, const uint16_t *a_d, int ca, int up_a,
+                              const uint16_t *b_d, int cb, const uint16_t *gy_d, int cout,
+                              float *gw_d, float *gb_d, void *stream) {
+  Q1_CHECK(a_d && gy_d && gw_d && gb_d && (cb == 0 || b_d), Q1_EINVAL,
+           "q1_conv3d_backward_weight: NULL argument");
+  Q1_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1 && ca >= 8 && ca % 8 == 0 && cb >= 0 &&
+               cb % 8 == 0 && cout % 16 == 0 && cout >= 16,
+           Q1_EINVAL, "q1_conv3d_backward_weight: bad sizes");
+  Q1_CHECK(!up_a || (D % 2 == 0 && H % 2 == 0 && W % 2 == 0), Q1_EINVAL,
+           "q1_conv3d_backward_weight: upsampled input needs an even grid");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ConvWArgs w;
+  w.a = a_d;
+  w.ca = ca;
+  w.up_a = up_a;
+  w.b = b_d;
+  w.cb = cb;
+  w.B = B;
+  w.D = D;
+  w.H = H;
+  w.W = W;
+  w.g = gy_d;
+  w.cout = cout;
+  w.cin_real = ca + cb;
+  w.nchunks = wgrad_chunks(w);
+  TmpBuf part, bpart;
+  Q1_HIP(hipMalloc(&part.p, size_t(w.nchunks) * 27 * w.cin_real * cout * sizeof(float)));
+  Q1_HIP(hipMalloc(&bpart.p, size_t(w.nchunks) * cout * sizeof(float)));
+  w.part = static_cast<float *>(part.p);
+  w.bpart = static_cast<float *>(bpart.p);
+  int rc = conv_wgrad(w, gw_d, gb_d, s);
+  if (rc) return rc;
+  Q1_HIP(hipStreamSynchronize(s));
+  return Q1_OK;
+}
+
+int q1_unet_pc_create(q1_unet_pc **out, q1_unet *net, int nx, int ny, int nz, const double *k_d,
+                      const uint8_t *mask_d, void *stream) {
+  Q1_CHECK(out && net && k_d, Q1_EINVAL, "q1_unet_pc_create: NULL argument");
+  *out = nullptr;
+  Q1_CHECK(nx >= 1 && ny >= 1 && nz >= 1 && nx + 1 <= net->W && ny + 1 <= net->H &&
+               nz + 1 <= net->D,
+           Q1_EINVAL, "q1_unet_pc_create: %dx%dx%d-element mesh does not fit the %dx%dx%d grid",
+           nx, ny, nz, net->W, net->H, net->D);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  q1_unet_pc *pc = new (std::nothrow) q1_unet_pc();
+  Q1_CHECK(pc, Q1_ENOMEM, "q1_unet_pc_create: out of host memory");
+  pc->net = net;
+  pc->nx = nx;
+  pc->ny = ny;
+  pc->nz = nz;
+  pc->nn = int64_t(nx + 1) * (ny + 1) * (nz + 1);
+  pc->mask = mask_d;
+  const int64_t nv = int64_t(net->D) * net->H * net->W;
+  int rc = Q1_OK;
+  if (hipMalloc(&pc->in, size_t(nv) * kInC * sizeof(bf16)) != hipSuccess ||
+      hipMalloc(&pc->out, size_t(nv) * sizeof(float)) != hipSuccess ||
+      hipMalloc(&pc->kap, size_t(pc->nn) * sizeof(float)) != hipSuccess ||
+      hipMalloc(&pc->part, 256 * sizeof(double)) != hipSuccess)
+    rc = fail(Q1_ENOMEM, "q1_unet_pc_create: device allocation failed");
+  if (!rc) {
+    hipLaunchKernelGGL(k_kappa, grid_for(pc->nn), dim3(256), 0, s, k_d, nx, ny, nz, pc->kap);
+    if (hipGetLastError() != hipSuccess) rc = fail(Q1_EHIP, "q1_unet_pc_create: launch failed");
+  }
+  if (!rc) {
+    pc->n_free = pc->nn;
+    if (mask_d) {
+      std::vector<uint8_t> m(size_t(pc->nn));
+      if (hipMemcpyAsync(m.data(), mask_d, m.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        rc = fail(Q1_EHIP, "q1_unet_pc_create: mask copy failed");
+      else
+        pc->n_free = pc->nn - std::count_if(m.begin(), m.end(), [](uint8_t c) { return c != 0; });
+    }
+  }
+  if (rc) {
+    delete pc;
+    return rc;
+  }
+  *out = pc;
+  return Q1_OK;
+}
+
+int q1_unet_pc_destroy(q1_unet_pc *pc) {
+  delete pc;
+  return Q1_OK;
+}
+
+int q1_unet_encode(q1_unet_pc *pc, const double *r_d, uint16_t *in_d, void *stream) {
+  Q1_CHECK(pc && r_d && in_d, Q1_EINVAL, "q1_unet_encode: NULL argument");
+  return pc_encode(*pc, r_d, in_d, static_cast<hipStream_t>(stream));
+}
+
+int q1_unet_encode_target(q1_unet_pc *pc, const double *e_d, float *target_d, float *weight_d,
+                          void *stream) {
+  Q1_CHECK(pc && e_d && target_d, Q1_EINVAL, "q1_unet_encode_target: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int np = 0, rc = pc_norm(*pc, e_d, s, &np);
+  if (rc) return rc;
+  const UNet &n = *pc->net;
+  hipLaunchKernelGGL(k_encode_target, grid_for(int64_t(n.D) * n.H * n.W), dim3(256), 0, s, e_d,
+                     pc->mask, pc->part, np, pc->n_free, pc->nx, pc->ny, pc->nz, n.D, n.H, n.W,
+                     target_d, weight_d);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+int q1_unet_precond(void *ctx, const void *r_d, void *z_d, void *stream) {
+  Q1_CHECK(ctx && r_d && z_d, Q1_EINVAL, "q1_unet_precond: NULL argument");
+  q1_unet_pc &pc = *static_cast<q1_unet_pc *>(ctx);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = pc_encode(pc, static_cast<const double *>(r_d), pc.in, s);
+  if (rc) return rc;
+  if ((rc = unet_forward(*pc.net, pc.in, pc.out, 1, s))) return rc;
+  hipLaunchKernelGGL(k_decode, grid_for(pc.nn), dim3(256), 0, s, pc.out, pc.mask, pc.nx, pc.ny,
+                     pc.nz, pc.net->H, pc.net->W, static_cast<double *>(z_d));
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,294 @@
+"""GPU parity of the learned preconditioner's kernels against the FP64 network
+oracle on identical BF16-rounded operands: convolution forward,
+backward-data and backward-weight to 1e-4 of the largest entry (FP32
+accumulation of up to 27 x 96 products), the whole network forward and
+gradient with the oracle rounding every stored tensor as the library does,
+the loss, Adam, and the preconditioner's encoding."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import unet_oracle as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q1():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2308_09839_amd as q1
+    return q1
+
+
+def rnd(shape, seed, lo=-1.0, hi=1.0):
+    n = int(np.prod(shape))
+    return (lo + (hi - lo) * si.uniform(seed, si.STREAM_X, np.arange(n, dtype=np.uint64))).reshape(shape)
+
+
+def bf(a):
+    """BF16 device tensor of a (torch's round-to-nearest-even conversion)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).cuda()
+
+
+def f32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def maxrel(x, ref):
+    return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+def normrel(x, ref):
+    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-30))
+
+
+# -- single layers ---------------------------------------------------------------
+
+FWD_CASES = [  # B, fine grid, ca, up_a, cb, cout, relu
+    (2, (5, 6, 7), 16, 0, 0, 16, 0),
+    (1, (8, 8, 8), 8, 0, 0, 16, 1),
+    (1, (6, 8, 10), 64, 1, 32, 32, 1),
+    (2, (4, 6, 4), 32, 1, 16, 16, 0),
+    (1, (5, 5, 5), 64, 0, 0, 64, 0),
+    (1, (3, 5, 9), 16, 0, 0, 48, 0),
+    (1, (4, 4, 5), 16, 0, 0, 96, 1),
+]
+
+
+@pytest.mark.parametrize("B,grid,ca,up,cb,cout,relu", FWD_CASES)
+def test_conv_forward(q1, B, grid, ca, up, cb, cout, relu):
+    print(f"\n[conv fwd] B={B} grid={grid} ca={ca} up={up} cb={cb} cout={cout}", flush=True)
+    D, H, W = grid
+    ga = (B, D // 2, H // 2, W // 2, ca) if up else (B, D, H, W, ca)
+    a = U.bf16_round(rnd(ga, 1))
+    b = U.bf16_round(rnd((B, D, H, W, cb), 2)) if cb else None
+    w = rnd((27, ca + cb, cout), 3) * 0.2
+    bias = rnd((cout,), 4)
+    y = q1.q1_conv3d_forward(bf(a), ca, f32(w), cout, bias=f32(bias), b=bf(b) if cb else None,
+                             cb=cb, up_a=up, relu=relu)
+    x = U.up2(a) if up else a
+    if cb:
+        x = np.concatenate([x, b], axis=4)
+    ref = U.conv3d(x, U.bf16_round(w), bias.astype(np.float32))
+    if relu:
+        ref = U.relu(ref)
+    assert maxrel(host(y), ref) <= 1e-4
+
+
+BWD_CASES = [  # B, grid, cout (gradient channels in), cin (out)
+    (2, (5, 6, 7), 16, 16), (1, (6, 4, 6), 32, 96), (1, (5, 7, 4), 16, 48),
+    (1, (5, 5, 5), 64, 64), (2, (4, 4, 6), 32, 16), (1, (3, 3, 3), 64, 32)]
+
+
+@pytest.mark.parametrize("B,grid,cout,cin", BWD_CASES)
+def test_conv_backward_data(q1, B, grid, cout, cin):
+    print(f"\n[conv bwd data] B={B} grid={grid} cout={cout} cin={cin}", flush=True)
+    gy = U.bf16_round(rnd((B,) + grid + (cout,), 5))
+    w = rnd((27, cin, cout), 6) * 0.2
+    gx = q1.q1_conv3d_backward_data(bf(gy), cout, f32(w), cin)
+    ref = U.conv3d_backward_data(gy, U.bf16_round(w))
+    assert maxrel(host(gx), ref) <= 1e-4
+
+
+WG_CASES = [  # B, fine grid, ca, up_a, cb, cout
+    (2, (5, 6, 7), 16, 0, 0, 16), (1, (8, 8, 8), 8, 0, 0, 16), (1, (6, 8, 10), 64, 1, 32, 32),
+    (2, (4, 6, 4), 32, 1, 16, 16), (1, (5, 5, 5), 64, 0, 0, 64), (3, (3, 4, 5), 32, 0, 0, 32)]
+
+
+@pytest.mark.parametrize("B,grid,ca,up,cb,cout", WG_CASES)
+def test_conv_backward_weight(q1, B, grid, ca, up, cb, cout):
+    print(f"\n[conv bwd weight] B={B} grid={grid} ca={ca} up={up} cb={cb} cout={cout}", flush=True)
+    D, H, W = grid
+    ga = (B, D // 2, H // 2, W // 2, ca) if up else (B, D, H, W, ca)
+    a = U.bf16_round(rnd(ga, 7))
+    b = U.bf16_round(rnd((B, D, H, W, cb), 8)) if cb else None
+    gy = U.bf16_round(rnd((B, D, H, W, cout), 9))
+    gw, gb = q1.q1_conv3d_backward_weight(bf(a), ca, bf(gy), cout, b=bf(b) if cb else None, cb=cb,
+                                          up_a=up)
+    x = U.up2(a) if up else a
+    if cb:
+        x = np.concatenate([x, b], axis=4)
+    rw, rb = U.conv3d_backward_weight(x, gy)
+    assert maxrel(host(gw), rw) <= 1e-4
+    assert maxrel(host(gb), rb) <= 1e-5
+
+
+def test_conv_argument_errors(q1):
+    import torch
+    a = torch.zeros((1, 4, 4, 4, 16), dtype=torch.bfloat16, device="cuda")
+    w = torch.zeros((27, 16, 24), dtype=torch.float32, device="cuda")
+    with pytest.raises(q1.Q1Error):
+        q1.q1_conv3d_forward(a, 16, w, 24)  # unsupported output width
+    with pytest.raises(q1.Q1Error):
+        q1.q1_conv3d_forward(a, 12, w, 16)  # channels not a multiple of 8
+
+
+# -- the whole network ------------------------------------------------------------
+
+def net_inputs(B, D, H, W, seed):
+    x = np.zeros((B, D, H, W, 8))
+    x[..., :2] = rnd((B, D, H, W, 2), seed) * np.array([1.0, 0.5])
+    return U.bf16_round(x)
+
+
+def oracle_theta(seed):
+    th = U.init_params(seed) * 0.8
+    lay, _ = U.param_layout()
+    for name, wo, ws, bo, co in lay:
+        th[bo:bo + co] = rnd((co,), seed + wo % 101, -0.05, 0.1)
+    return th.astype(np.float32).astype(np.float64)
+
+
+def test_unet_forward_backward(q1):
+    import torch
+    B, D, H, W = 2, 8, 8, 12
+    print(f"\n[unet] B={B} grid={D}x{H}x{W}", flush=True)
+    th = oracle_theta(31)
+    net = q1.UNet(D, H, W, B, seed=1)
+    assert net.nparams == th.size
+    net.set_params(f32(th))
+    assert np.array_equal(host(net.get(0)), th)
+    x = net_inputs(B, D, H, W, 32)
+    xd = bf(x)
+    out = torch.empty((B, D, H, W), dtype=torch.float32, device="cuda")
+    net.forward(xd, out, B)
+    ref, cache = U.unet_forward(th, x[..., :2], bf16=True)
+    assert normrel(host(out), ref) <= 2e-3, normrel(host(out), ref)
+    # loss and gradient of the loss
+    tgt = rnd((B, D, H, W), 33)
+    wgt = (rnd((B, D, H, W), 34, 0, 1) > 0.25).astype(np.float64)
+    dout = torch.empty_like(out)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    net.mse(out, f32(tgt), f32(wgt), dout, loss)
+    L_ref, g_ref = U.mse_loss(host(out), tgt.astype(np.float32), wgt)
+    assert abs(float(loss.item()) - L_ref) <= 1e-5 * L_ref
+    assert maxrel(host(dout), g_ref) <= 1e-5
+    # parameter gradient for the same dout, oracle on the same stored roundings
+    net.backward(dout)
+    g = host(net.get(1))
+    gr = U.unet_backward(th, cache, host(dout), bf16=True)
+    lay, _ = U.param_layout()
+    for name, wo, ws, bo, co in lay:
+        sz = int(np.prod(ws))
+        e_w = normrel(g[wo:wo + sz], gr[wo:wo + sz])
+        e_b = normrel(g[bo:bo + co], gr[bo:bo + co])
+        print(f"  {name}: w {e_w:.2e} b {e_b:.2e}")
+        assert e_w <= 1e-2 and e_b <= 1e-2, name
+
+
+def test_unet_adam_step(q1):
+    import torch
+    B, D, H, W = 1, 4, 4, 4
+    th = oracle_theta(41)
+    net = q1.UNet(D, H, W, B, seed=2)
+    net.set_params(f32(th))
+    x = bf(net_inputs(B, D, H, W, 42))
+    out = torch.empty((B, D, H, W), dtype=torch.float32, device="cuda")
+    dout = torch.empty_like(out)
+    net.forward(x, out, B)
+    net.mse(out, f32(rnd((B, D, H, W), 43)), torch.ones_like(out), dout)
+    net.backward(dout)
+    g = host(net.get(1))
+    net.adam_step(1e-3, 1)
+    t1 = host(net.get(0))
+    ref, m, v = U.adam_step(th, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3, 0.9, 0.999, 1e-8)
+    assert np.max(np.abs(t1 - ref)) <= 1e-3 * 1e-4 + 1e-7 * np.max(np.abs(th))
+
+
+def test_unet_training_lowers_the_loss(q1):
+    import torch
+    B, D, H, W = 2, 8, 8, 8
+    print("\n[unet training]", flush=True)
+    net = q1.UNet(D, H, W, B, seed=3)
+    x = bf(net_inputs(B, D, H, W, 51))
+    tgt = f32(rnd((B, D, H, W), 52) * 0.5)
+    wgt = torch.ones_like(tgt)
+    out = torch.empty_like(tgt)
+    dout = torch.empty_like(tgt)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    for step in range(1, 61):
+        net.forward(x, out, B)
+        net.mse(out, tgt, wgt, dout, loss)
+        hist.append(float(loss.item()))
+        net.backward(dout)
+        net.adam_step(3e-3, step)
+    print("  loss", hist[0], "->", hist[-1])
+    assert all(np.isfinite(hist)) and hist[-1] < 0.5 * hist[0]
+
+
+# -- the preconditioner ------------------------------------------------------------
+
+def test_unet_encoding_and_precond(q1, orc):
+    import torch
+    nx, ny, nz = 6, 5, 4
+    D, H, W = 8, 8, 8
+    print("\n[unet precond encoding]", flush=True)
+    k = si.field_lognormal(nx * ny * nz, 0.0, 2.0, 61)
+    mask = si.face_mask(nx, ny, nz, "z0")
+    nn = (nx + 1) * (ny + 1) * (nz + 1)
+    r = si.vec_uniform(nn, 62, si.STREAM_RHS)
+    free = mask == 0
+    net = q1.UNet(D, H, W, 1, seed=4)
+    th = oracle_theta(63)
+    net.set_params(f32(th))
+    kd = torch.from_numpy(k).cuda()
+    md = torch.from_numpy(mask.astype(np.uint8)).cuda()
+    pc = q1.UNetPrecond(net, nx, ny, nz, kd, md)
+    rd = torch.from_numpy(r).cuda()
+    inp = torch.zeros((D, H, W, 8), dtype=torch.bfloat16, device="cuda")
+    pc.encode(rd, inp)
+    kap = U.nodal_mean_log(nx, ny, nz, k)
+    ref_in = U.encode_input(r, free, kap, nx, ny, nz, D, H, W)[0]
+    got = host(inp)
+    assert np.all(got[..., 2:] == 0)
+    assert np.array_equal(got[..., :2], U.bf16_round(ref_in.astype(np.float32)))
+    tg = torch.empty((D, H, W), dtype=torch.float32, device="cuda")
+    wg = torch.empty_like(tg)
+    pc.encode_target(rd, tg, wg)
+    ref_t = U.encode_input(r, free, kap, nx, ny, nz, D, H, W)[0, ..., 0]
+    assert maxrel(host(tg), ref_t) <= 1e-6
+    ref_w = np.zeros((D, H, W))
+    ref_w[:nz + 1, :ny + 1, :nx + 1] = free.reshape(nz + 1, ny + 1, nx + 1)
+    assert np.array_equal(host(wg), ref_w)
+    # z = decode(N(encode(r)))
+    z = torch.empty_like(rd)
+    assert q1.lib().q1_unet_precond(pc.handle, q1._dptr(rd), q1._dptr(z),
+                                     q1._stream(None)) == 0
+    out, _ = U.unet_forward(th, U.bf16_round(ref_in[None].astype(np.float32)), bf16=True)
+    zr = U.decode_output(out, free, nx, ny, nz)
+    assert normrel(host(z), zr) <= 2e-3
+    assert np.all(host(z)[~free] == 0)
+
+
+def test_fpcg_with_untrained_network_still_converges(q1, orc):
+    """An untrained network is a poor preconditioner; flexible PCG with its
+    safeguards must still reach the tolerance under the oracle's operator."""
+    import torch
+    from helpers import make_op
+    nx = ny = nz = 6
+    print("\n[fpcg untrained net]", flush=True)
+    xyz, conn = si.box_mesh(nx, ny, nz)
+    k = si.field_lognormal(nx * ny * nz, 0.0, 2.0, 71)
+    mask = si.face_mask(nx, ny, nz, "z0")
+    pr = dict(physics=1, xyz=xyz, conn=conn, coef=k[None], mask=mask)
+    A = orc.assemble(1, xyz, conn, k[None], mask)
+    b = si.vec_uniform(A.n, 72, si.STREAM_RHS)
+    b[mask == 1] = 0.0
+    op = make_op(pr, 0, 0)
+    net = q1.UNet(8, 8, 8, 1, seed=5)
+    kd = torch.from_numpy(k).cuda()
+    md = torch.from_numpy(mask.astype(np.uint8)).cuda()
+    pc = q1.UNetPrecond(net, nx, ny, nz, kd, md)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.empty_like(bd)
+    st = q1.q1_fpcg(op, pc, bd, xd, 1e-8, 2000, safeguard_m=20)
+    assert st["status"] == 0
+    assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
