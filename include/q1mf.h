@@ -166,6 +166,14 @@ int q1_pcg(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit
 /* A preconditioner callback: enqueue z = M(r) on `stream` (device vectors of
  * the operator's dtype) and return Q1_OK, or any other value to report
  * failure. */
+/* q1_pcg that also records iterates: after iteration snap_iters[i] (counted
+ * from 1, ascending; 0 = the initial x = 0) x is copied to the device vector
+ * snap_d[i] (host array of nsnap device pointers, operator dtype); snapshots
+ * past the last iteration receive the final x.  Used to harvest the
+ * residual -> error pairs the learned preconditioner is trained on. */
+int q1_pcg_trace(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit, int nsnap,
+                 const int *snap_iters, void *const *snap_d, q1_stats *st, void *stream);
+
 typedef int (*q1_precond_fn)(void *ctx, const void *r_d, void *z_d, void *stream);
 /* Flexible PCG (beta = z_{k+1}^T (r_{k+1} - r_k) / (r_k^T z_k)) with a
  * variable preconditioner M.  Safeguard: on a failing call, z^T r <= 0, a

@@ -17,7 +17,7 @@ from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32,
                    Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
-    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_batched_pcg", "q1_mpcg", "q1_fpcg", "q1_ir_solve", "Jacobi",
+    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_trace", "q1_batched_pcg", "q1_mpcg", "q1_fpcg", "q1_ir_solve", "Jacobi",
     "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
@@ -230,6 +230,18 @@ def q1_pcg(op: Op, pc: int, b, x, rtol: float, maxit: int, stream=None) -> dict:
     st = Q1Stats()
     _solve_rc(lib().q1_pcg(op.handle, pc, _dptr(b), _dptr(x), rtol, maxit, ctypes.byref(st),
                            _stream(stream)))
+    return st.as_dict()
+
+
+def q1_pcg_trace(op: Op, pc: int, b, x, rtol: float, maxit: int, snap_iters, snaps,
+                 stream=None) -> dict:
+    """q1_pcg recording x after the given iterations into the device vectors `snaps`."""
+    n = len(snap_iters)
+    it = (ctypes.c_int * max(n, 1))(*[int(k) for k in snap_iters])
+    ptr = (ctypes.c_void_p * max(n, 1))(*[_dptr(v) for v in snaps])
+    st = Q1Stats()
+    _solve_rc(lib().q1_pcg_trace(op.handle, pc, _dptr(b), _dptr(x), rtol, maxit, n, it, ptr,
+                                 ctypes.byref(st), _stream(stream)))
     return st.as_dict()
 
 

@@ -84,6 +84,8 @@ PROTOTYPES = {
     "q1_csr_info": (c_int, [c_vp, P(c_i64), P(c_i64)]),
     "q1_csr_export": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "q1_pcg": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, P(Q1Stats), c_vp]),
+    "q1_pcg_trace": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_int, c_vp, c_vp, P(Q1Stats),
+                             c_vp]),
     "q1_fpcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),
     "q1_jacobi_create": (c_int, [P(c_vp), c_vp, c_vp]),
     "q1_precond_jacobi": (c_int, [c_vp, c_vp, c_vp, c_vp]),

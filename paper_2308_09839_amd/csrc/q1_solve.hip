@@ -385,9 +385,18 @@ int true_residual(Op &op, Work &W, const T *b, const T *x, double *out, hipStrea
 
 // Preconditioned CG on the operator's vector type T with x0 = 0.  Returns
 // Q1_OK, Q1_ENOCONV (x = last iterate) or Q1_EBREAKDOWN.
+// Snapshots of the iterate: after iteration iters[i] (counted from 1), x is
+// copied to dst[i]; iters ascending.  A snapshot past the end of the solve
+// receives the final iterate.
+struct Snapshots {
+  int n = 0;
+  const int *iters = nullptr;
+  void *const *dst = nullptr;
+};
+
 template <typename T>
 int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *stats,
-          hipStream_t s, bool true_res) {
+          hipStream_t s, bool true_res, const Snapshots &snap = Snapshots()) {
   const int64_t n = op.n_nodes * op.physics;
   Work W;
   int rc = alloc_work<T>(W, n, false);
@@ -412,7 +421,10 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
   if (bb > 0.0) {
     const double tol2 = rtol * rtol;
     status = Q1_ENOCONV;
-    int launched = 0, batch = 1;
+    int launched = 0, batch = 1, next_snap = 0;
+    while (next_snap < snap.n && snap.iters[next_snap] <= 0)
+      Q1_HIP(hipMemcpyAsync(snap.dst[next_snap++], x, size_t(n) * sizeof(T),
+                            hipMemcpyDeviceToDevice, s));
     while (launched < maxit) {
       const int m = std::min(batch, maxit - launched);
       for (int j = 0; j < m; ++j) {
@@ -425,6 +437,9 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
         hipLaunchKernelGGL((k_pcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, r, w, nullptr, p,
                            part_rho[(k + 1) & 1], part_rho[k & 1], part_rr, part_bb, tol2, k + 1,
                            maxit, W.st);
+        while (next_snap < snap.n && snap.iters[next_snap] == k + 1)
+          Q1_HIP(hipMemcpyAsync(snap.dst[next_snap++], x, size_t(n) * sizeof(T),
+                                hipMemcpyDeviceToDevice, s));
       }
       Q1_HIP(hipGetLastError());
       launched += m;
@@ -435,6 +450,9 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
     iters = W.hst->iter;
     rr = W.hst->rr;
     if (W.hst->done) status = W.hst->status;
+    while (next_snap < snap.n)
+      Q1_HIP(hipMemcpyAsync(snap.dst[next_snap++], x, size_t(n) * sizeof(T),
+                            hipMemcpyDeviceToDevice, s));
   }
   const auto t1 = std::chrono::steady_clock::now();
   if (stats) {
@@ -706,6 +724,30 @@ int q1_pcg(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit
                          rtol, maxit, st, s, true);
   return pcg_t<float>(o, pc, static_cast<const float *>(b_d), static_cast<float *>(x_d), rtol,
                       maxit, st, s, true);
+}
+
+int q1_pcg_trace(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit, int nsnap,
+                 const int *snap_iters, void *const *snap_d, q1_stats *st, void *stream) {
+  Q1_CHECK(op && b_d && x_d && nsnap >= 0 && (nsnap == 0 || (snap_iters && snap_d)), Q1_EINVAL,
+           "q1_pcg_trace: NULL argument");
+  Q1_CHECK(pc == Q1_PC_NONE || pc == Q1_PC_JACOBI, Q1_EINVAL, "q1_pcg_trace: bad preconditioner");
+  Q1_CHECK(rtol >= 0 && maxit >= 0, Q1_EINVAL, "q1_pcg_trace: need rtol >= 0 and maxit >= 0");
+  for (int i = 0; i < nsnap; ++i) {
+    Q1_CHECK(snap_d[i], Q1_EINVAL, "q1_pcg_trace: NULL snapshot %d", i);
+    Q1_CHECK(i == 0 || snap_iters[i] >= snap_iters[i - 1], Q1_EINVAL,
+             "q1_pcg_trace: snapshot iterations must ascend");
+  }
+  Op &o = *reinterpret_cast<Op *>(op);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Snapshots sn;
+  sn.n = nsnap;
+  sn.iters = snap_iters;
+  sn.dst = snap_d;
+  if (o.dtype == Q1_F64)
+    return pcg_t<double>(o, pc, static_cast<const double *>(b_d), static_cast<double *>(x_d), rtol,
+                         maxit, st, s, true, sn);
+  return pcg_t<float>(o, pc, static_cast<const float *>(b_d), static_cast<float *>(x_d), rtol,
+                      maxit, st, s, true, sn);
 }
 
 int q1_fpcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,

@@ -240,3 +240,28 @@ def test_mpcg_edge_cases(q1, orc):
         q1.q1_mpcg(op64, op32, bd, xd, 1e-10, 1.5, 100)
     with pytest.raises(q1.Q1Error):
         q1.q1_mpcg(op32, op64, bd, xd, 1e-10, 0.1, 100)
+
+
+def test_pcg_trace_snapshots(q1, orc):
+    """Recorded iterates equal the oracle's PCG iterates after the same number
+    of iterations; snapshots past convergence hold the final x."""
+    import torch
+    print("\n[pcg trace]", flush=True)
+    pr = problem(1, (10, 9, 8), 0.1, 91, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 91)
+    op = make_op(pr, 0, 0)
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    its = [0, 1, 2, 5, 9, 9, 30, 100000]
+    snaps = [torch.full_like(bd, 5.0) for _ in its]
+    st = q1.q1_pcg_trace(op, 1, bd, xd, 1e-8, 5000, its, snaps)
+    assert st["status"] == 0
+    for k, s in zip(its, snaps):
+        if k == 0:
+            assert bool((s == 0).all())
+            continue
+        ref = orc.pcg(A, b, rtol=0.0, maxit=min(k, st["iters"]))
+        x = s.cpu().numpy()
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), k
+    assert torch.equal(snaps[-1], xd)
