@@ -301,6 +301,14 @@ typedef struct q1_unet_pc q1_unet_pc;
  * and mask_d must outlive the context.  Synchronises `stream`. */
 int q1_unet_pc_create(q1_unet_pc **pc, q1_unet *net, int nx, int ny, int nz, const double *k_d,
                       const uint8_t *mask_d, void *stream);
+/* Switch the context to the two-level form: with the FP64 scalar operator op
+ * of the same mesh and w = 1 / diag(A),
+ *   z1 = omega w r,  r1 = r - A z1,  d = N(encode(r1)),
+ *   c = d.r1 / d.A d (0 if not positive), z = z1 + c d + omega w (r1 - c A d),
+ * i.e. damped-Jacobi smoothing around the network acting as a coarse
+ * correction, its scale chosen to minimise the energy norm of the error.
+ * Costs two operator applies per use.  op must outlive the context. */
+int q1_unet_pc_two_level(q1_unet_pc *pc, q1_op *op, double omega, void *stream);
 int q1_unet_pc_destroy(q1_unet_pc *pc);
 /* Network input of a nodal FP64 vector r: channel 0 = r on free nodes scaled
  * to unit RMS over them (0 on Dirichlet nodes), channel 1 = half the mean of

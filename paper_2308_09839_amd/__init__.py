@@ -426,6 +426,11 @@ class UNetPrecond:
                                       _dptr(mask), _stream(stream)))
         self.fn = ctypes.cast(lib().q1_unet_precond, ctypes.c_void_p)
 
+    def two_level(self, op: Op, omega: float = 0.6, stream=None):
+        """Jacobi smoothing around the network's energy-scaled correction."""
+        self.op = op
+        check(lib().q1_unet_pc_two_level(self.handle, op.handle, omega, _stream(stream)))
+
     def encode(self, r, inp, stream=None):
         check(lib().q1_unet_encode(self.handle, _dptr(r), _dptr(inp), _stream(stream)))
 

@@ -111,6 +111,7 @@ PROTOTYPES = {
     "q1_unet_adam_step": (c_int, [c_vp, c_flt, c_flt, c_flt, c_flt, c_int, c_vp]),
     "q1_unet_pc_create": (c_int, [P(c_vp), c_vp, c_int, c_int, c_int, c_vp, c_vp, c_vp]),
     "q1_unet_pc_destroy": (c_int, [c_vp]),
+    "q1_unet_pc_two_level": (c_int, [c_vp, c_vp, c_dbl, c_vp]),
     "q1_unet_encode": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "q1_unet_encode_target": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "q1_unet_precond": (c_int, [c_vp, c_vp, c_vp, c_vp]),

@@ -80,11 +80,14 @@ struct UNetPC {
   float *out = nullptr;  // [D][H][W]
   float *kap = nullptr;  // nodal channel-1 values [nn]
   double *part = nullptr;
+  // two-level form: Jacobi smoothing around the network's coarse correction
+  Op *op = nullptr;
+  double omega = 0.0;
+  double *w = nullptr, *z1 = nullptr, *r1 = nullptr, *d = nullptr, *q = nullptr;
   ~UNetPC() {
-    if (in) (void)hipFree(in);
-    if (out) (void)hipFree(out);
-    if (kap) (void)hipFree(kap);
-    if (part) (void)hipFree(part);
+    for (void *p : {(void *)in, (void *)out, (void *)kap, (void *)part, (void *)w, (void *)z1,
+                    (void *)r1, (void *)d, (void *)q})
+      if (p) (void)hipFree(p);
   }
 };
 
@@ -366,6 +369,65 @@ __global__ void k_decode(const float *__restrict__ out, const uint8_t *__restric
   const int x = int(id % (nx + 1)), y = int((id / (nx + 1)) % (ny + 1)),
             zz = int(id / (int64_t(nx + 1) * (ny + 1)));
   z[id] = (mask && mask[id]) ? 0.0 : double(out[(int64_t(zz) * H + y) * W + x]);
+}
+
+__global__ void k_inv(int64_t n, const double *__restrict__ d, double *__restrict__ w) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = 1.0 / d[i];
+}
+// z1 = omega w r ; (w = 1 / diag A)
+__global__ void k_smooth(int64_t n, const double *__restrict__ w, const double *__restrict__ r,
+                         double omega, double *__restrict__ z) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = omega * w[i] * r[i];
+}
+// r1 = r - q
+__global__ void k_sub(int64_t n, const double *__restrict__ r, const double *__restrict__ q,
+                      double *__restrict__ r1) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) r1[i] = r[i] - q[i];
+}
+// per-block partials of d.r1 and d.q
+__global__ __launch_bounds__(kEB) void k_dot2(int64_t n, const double *__restrict__ d,
+                                             const double *__restrict__ r1,
+                                             const double *__restrict__ q,
+                                             double *__restrict__ part) {
+  __shared__ double sh[2][kEB / 64];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kEB + threadIdx.x; i < n; i += int64_t(gridDim.x) * kEB) {
+    a += d[i] * r1[i];
+    b += d[i] * q[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = a;
+    sh[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int k = 0; k < kEB / 64; ++k) t += sh[threadIdx.x][k];
+    part[2 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+// c = (d.r1) / (d.A d) (0 when not positive and finite); z = z1 + c d + omega w (r1 - c A d)
+__global__ void k_two_level_combine(int64_t n, const double *__restrict__ part, int nparts,
+                                    const double *__restrict__ z1, const double *__restrict__ d,
+                                    const double *__restrict__ r1, const double *__restrict__ q,
+                                    const double *__restrict__ w, double omega,
+                                    double *__restrict__ z) {
+  double dr = 0.0, dq = 0.0;
+  for (int k = 0; k < nparts; ++k) {
+    dr += part[2 * k];
+    dq += part[2 * k + 1];
+  }
+  const double c = (dq > 0.0 && isfinite(dr / dq)) ? dr / dq : 0.0;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = z1[i] + c * d[i] + omega * w[i] * (r1[i] - c * q[i]);
 }
 
 inline dim3 grid_for(int64_t n, int bs = 256) { return dim3(unsigned((n + bs - 1) / bs)); }
@@ -738,6 +800,29 @@ int q1_unet_pc_create(q1_unet_pc **out, q1_unet *net, int nx, int ny, int nz, co
   return Q1_OK;
 }
 
+int q1_unet_pc_two_level(q1_unet_pc *pc, q1_op *op, double omega, void *stream) {
+  Q1_CHECK(pc && op, Q1_EINVAL, "q1_unet_pc_two_level: NULL argument");
+  Op &o = *reinterpret_cast<Op *>(op);
+  Q1_CHECK(o.physics == 1 && o.dtype == Q1_F64 && o.n_nodes == pc->nn, Q1_EINVAL,
+           "q1_unet_pc_two_level: needs the FP64 scalar operator of the context's mesh");
+  Q1_CHECK(omega > 0.0 && omega < 2.0, Q1_EINVAL, "q1_unet_pc_two_level: omega %g", omega);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t b = size_t(pc->nn) * sizeof(double);
+  if (!pc->w) {
+    if (hipMalloc(&pc->w, b) != hipSuccess || hipMalloc(&pc->z1, b) != hipSuccess ||
+        hipMalloc(&pc->r1, b) != hipSuccess || hipMalloc(&pc->d, b) != hipSuccess ||
+        hipMalloc(&pc->q, b) != hipSuccess)
+      return fail(Q1_ENOMEM, "q1_unet_pc_two_level: device allocation failed");
+  }
+  int rc = launch_diag(o, pc->q, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_inv, grid_for(pc->nn), dim3(256), 0, s, pc->nn, pc->q, pc->w);
+  Q1_HIP(hipGetLastError());
+  pc->op = &o;
+  pc->omega = omega;
+  return Q1_OK;
+}
+
 int q1_unet_pc_destroy(q1_unet_pc *pc) {
   delete pc;
   return Q1_OK;
@@ -766,11 +851,32 @@ int q1_unet_precond(void *ctx, const void *r_d, void *z_d, void *stream) {
   Q1_CHECK(ctx && r_d && z_d, Q1_EINVAL, "q1_unet_precond: NULL argument");
   q1_unet_pc &pc = *static_cast<q1_unet_pc *>(ctx);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int rc = pc_encode(pc, static_cast<const double *>(r_d), pc.in, s);
-  if (rc) return rc;
+  const double *r = static_cast<const double *>(r_d);
+  double *z = static_cast<double *>(z_d);
+  const dim3 g = grid_for(pc.nn);
+  int rc;
+  if (!pc.op) {  // z = N(r)
+    if ((rc = pc_encode(pc, r, pc.in, s))) return rc;
+    if ((rc = unet_forward(*pc.net, pc.in, pc.out, 1, s))) return rc;
+    hipLaunchKernelGGL(k_decode, g, dim3(256), 0, s, pc.out, pc.mask, pc.nx, pc.ny, pc.nz,
+                       pc.net->H, pc.net->W, z);
+    Q1_HIP(hipGetLastError());
+    return Q1_OK;
+  }
+  // two-level: pre-smooth, network correction scaled to minimise the energy
+  // norm of the error, post-smooth
+  hipLaunchKernelGGL(k_smooth, g, dim3(256), 0, s, pc.nn, pc.w, r, pc.omega, pc.z1);
+  if ((rc = launch_apply(*pc.op, pc.z1, pc.q, s))) return rc;
+  hipLaunchKernelGGL(k_sub, g, dim3(256), 0, s, pc.nn, r, pc.q, pc.r1);
+  if ((rc = pc_encode(pc, pc.r1, pc.in, s))) return rc;
   if ((rc = unet_forward(*pc.net, pc.in, pc.out, 1, s))) return rc;
-  hipLaunchKernelGGL(k_decode, grid_for(pc.nn), dim3(256), 0, s, pc.out, pc.mask, pc.nx, pc.ny,
-                     pc.nz, pc.net->H, pc.net->W, static_cast<double *>(z_d));
+  hipLaunchKernelGGL(k_decode, g, dim3(256), 0, s, pc.out, pc.mask, pc.nx, pc.ny, pc.nz,
+                     pc.net->H, pc.net->W, pc.d);
+  if ((rc = launch_apply(*pc.op, pc.d, pc.q, s))) return rc;
+  const int nb = int(std::min<int64_t>(256, (pc.nn + kEB - 1) / kEB));
+  hipLaunchKernelGGL(k_dot2, dim3(nb), dim3(kEB), 0, s, pc.nn, pc.d, pc.r1, pc.q, pc.part);
+  hipLaunchKernelGGL(k_two_level_combine, g, dim3(256), 0, s, pc.nn, pc.part, nb, pc.z1, pc.d,
+                     pc.r1, pc.q, pc.w, pc.omega, z);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }

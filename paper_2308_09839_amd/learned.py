@@ -146,14 +146,17 @@ class Trainer:
 
 
 def evaluate(net: UNet, n: int, seeds, rtol: float = 1e-8, sigma: float = 2.0,
-             safeguard_m: int = 50, log=print):
+             safeguard_m: int = 50, omega: float | None = 0.6, log=print):
     """Flexible PCG with the network against Jacobi-PCG on held-out fields:
-    iterations and wall time (every network inference included)."""
+    iterations and wall time (every network inference included).  omega:
+    damping of the two-level form's Jacobi smoothing, None for z = N(r)."""
     import torch
     rows = []
     for seed in seeds:
         P = Problem(n, seed, sigma)
         pc = UNetPrecond(net, n, n, n, P.k, P.mask)
+        if omega is not None:
+            pc.two_level(P.op, omega)
         x = torch.empty_like(P.b)
         q1_pcg(P.op, Q1_PC_JACOBI, P.b, x, rtol, 100000)  # warm-up
         torch.cuda.synchronize()

@@ -292,3 +292,45 @@ def test_fpcg_with_untrained_network_still_converges(q1, orc):
     st = q1.q1_fpcg(op, pc, bd, xd, 1e-8, 2000, safeguard_m=20)
     assert st["status"] == 0
     assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
+
+
+def test_two_level_precond(q1, orc):
+    """Two-level form against its composition from the oracle: damped Jacobi
+    with the assembled diagonal, the network oracle as the correction, the
+    energy-optimal scale, and the assembled operator."""
+    import torch
+    from helpers import make_op
+    nx, ny, nz = 6, 5, 4
+    D = H = W = 8
+    omega = 0.6
+    print("\n[unet two-level]", flush=True)
+    xyz, conn = si.box_mesh(nx, ny, nz)
+    k = si.field_lognormal(nx * ny * nz, 0.0, 2.0, 81)
+    mask = si.face_mask(nx, ny, nz, "z0")
+    free = mask == 0
+    A = orc.assemble(1, xyz, conn, k[None], mask)
+    r = si.vec_uniform(A.n, 82, si.STREAM_RHS)
+    r[~free] = 0.0
+    th = oracle_theta(83)
+    net = q1.UNet(D, H, W, 1, seed=6)
+    net.set_params(f32(th))
+    op = make_op(dict(physics=1, xyz=xyz, conn=conn, coef=k[None], mask=mask), 0, 0)
+    pc = q1.UNetPrecond(net, nx, ny, nz, torch.from_numpy(k).cuda(),
+                        torch.from_numpy(mask.astype(np.uint8)).cuda())
+    pc.two_level(op, omega)
+    rd = torch.from_numpy(r).cuda()
+    z = torch.empty_like(rd)
+    assert q1.lib().q1_unet_precond(pc.handle, q1._dptr(rd), q1._dptr(z), q1._stream(None)) == 0
+    # oracle composition
+    w = 1.0 / A.diag()
+    z1 = omega * w * r
+    r1 = r - A.matvec(z1)
+    kap = U.nodal_mean_log(nx, ny, nz, k)
+    x_in = U.encode_input(r1, free, kap, nx, ny, nz, D, H, W)
+    out, _ = U.unet_forward(th, U.bf16_round(x_in.astype(np.float32)), bf16=True)
+    d = U.decode_output(out, free, nx, ny, nz)
+    Ad = A.matvec(d)
+    c = (d @ r1) / (d @ Ad)
+    zr = z1 + c * d + omega * w * (r1 - c * Ad)
+    assert normrel(host(z), zr) <= 2e-3
+    assert np.all(host(z)[~free] == 0)
