@@ -274,8 +274,10 @@ int q1_unet_params(q1_unet *net, float **theta_d, float **grad_d);
 /* Refresh the packed BF16 weights from the FP32 parameters. */
 int q1_unet_commit(q1_unet *net, void *stream);
 /* Copy the parameters (which = 0) or gradients (which = 1) to buf_d
- * (to_net = 0) or from buf_d into the network (to_net = 1, parameters only;
- * call q1_unet_commit afterwards); buf_d is a device FP32 [nparams]. */
+ * (to_net = 0) or from buf_d into the network (to_net = 1; after writing
+ * parameters call q1_unet_commit; writing gradients lets a caller apply Adam
+ * to gradients it combined itself, e.g. summed over data-parallel ranks);
+ * buf_d is a device FP32 [nparams]. */
 int q1_unet_copy(q1_unet *net, int which, int to_net, float *buf_d, void *stream);
 /* out = N(in) for the first nbatch samples: in_d BF16 [nbatch][D][H][W][8]
  * (channels 2..7 must be zero), out_d FP32 [nbatch][D][H][W].  Activations

@@ -389,6 +389,10 @@ class UNet:
         check(lib().q1_unet_copy(self.handle, 0, 1, _dptr(theta), _stream(stream)))
         self.commit(stream)
 
+    def set_grad(self, grad, stream=None):
+        """Overwrite the gradient vector (e.g. with gradients summed elsewhere)."""
+        check(lib().q1_unet_copy(self.handle, 1, 1, _dptr(grad), _stream(stream)))
+
     def commit(self, stream=None):
         check(lib().q1_unet_commit(self.handle, _stream(stream)))
 

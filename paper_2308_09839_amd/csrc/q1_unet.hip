@@ -597,8 +597,8 @@ int q1_unet_commit(q1_unet *net, void *stream) {
 
 int q1_unet_copy(q1_unet *net, int which, int to_net, float *buf_d, void *stream) {
   Q1_CHECK(net && buf_d, Q1_EINVAL, "q1_unet_copy: NULL argument");
-  Q1_CHECK((which == 0 || which == 1) && (to_net == 0 || to_net == 1) && !(which == 1 && to_net),
-           Q1_EINVAL, "q1_unet_copy: which %d to_net %d", which, to_net);
+  Q1_CHECK((which == 0 || which == 1) && (to_net == 0 || to_net == 1), Q1_EINVAL,
+           "q1_unet_copy: which %d to_net %d", which, to_net);
   float *lib_buf = which == 0 ? net->theta : net->grad;
   const size_t bytes = size_t(net->nparams) * sizeof(float);
   Q1_HIP(hipMemcpyAsync(to_net ? lib_buf : buf_d, to_net ? buf_d : lib_buf, bytes,

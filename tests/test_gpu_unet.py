@@ -184,22 +184,21 @@ def test_unet_forward_backward(q1):
 
 
 def test_unet_adam_step(q1):
-    import torch
     B, D, H, W = 1, 4, 4, 4
     th = oracle_theta(41)
     net = q1.UNet(D, H, W, B, seed=2)
     net.set_params(f32(th))
-    x = bf(net_inputs(B, D, H, W, 42))
-    out = torch.empty((B, D, H, W), dtype=torch.float32, device="cuda")
-    dout = torch.empty_like(out)
-    net.forward(x, out, B)
-    net.mse(out, f32(rnd((B, D, H, W), 43)), torch.ones_like(out), dout)
-    net.backward(dout)
-    g = host(net.get(1))
-    net.adam_step(1e-3, 1)
-    t1 = host(net.get(0))
-    ref, m, v = U.adam_step(th, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3, 0.9, 0.999, 1e-8)
-    assert np.max(np.abs(t1 - ref)) <= 1e-3 * 1e-4 + 1e-7 * np.max(np.abs(th))
+    g = rnd(th.shape, 44, -1e-2, 1e-2).astype(np.float32).astype(np.float64)
+    m = np.zeros_like(g)
+    v = np.zeros_like(g)
+    ref = th
+    for step in (1, 2, 3):
+        net.set_grad(f32(g))
+        net.adam_step(1e-3, step)
+        ref, m, v = U.adam_step(ref, g, m, v, step, 1e-3, 0.9, 0.999, 1e-8)
+        t = host(net.get(0))
+        assert np.max(np.abs(t - ref)) <= 1e-6 * 1e-3 + 1e-6 * np.max(np.abs(th)), step
+        g = g[::-1].copy()
 
 
 def test_unet_training_lowers_the_loss(q1):
