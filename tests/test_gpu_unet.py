@@ -161,19 +161,21 @@ def test_unet_forward_backward(q1):
     net.forward(xd, out, B)
     ref, cache = U.unet_forward(th, x[..., :2], bf16=True)
     assert normrel(host(out), ref) <= 2e-3, normrel(host(out), ref)
-    # loss and gradient of the loss
-    tgt = rnd((B, D, H, W), 33)
+    # loss kernel on seeded values (not on the network output)
+    o_s = rnd((B, D, H, W), 35).astype(np.float32).astype(np.float64)
+    tgt = rnd((B, D, H, W), 33).astype(np.float32).astype(np.float64)
     wgt = (rnd((B, D, H, W), 34, 0, 1) > 0.25).astype(np.float64)
     dout = torch.empty_like(out)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    net.mse(out, f32(tgt), f32(wgt), dout, loss)
-    L_ref, g_ref = U.mse_loss(host(out), tgt.astype(np.float32), wgt)
+    net.mse(f32(o_s), f32(tgt), f32(wgt), dout, loss)
+    L_ref, g_ref = U.mse_loss(o_s, tgt, wgt)
     assert abs(float(loss.item()) - L_ref) <= 1e-5 * L_ref
     assert maxrel(host(dout), g_ref) <= 1e-5
-    # parameter gradient for the same dout, oracle on the same stored roundings
-    net.backward(dout)
+    # parameter gradient for a seeded dL/dout, oracle on the same stored roundings
+    g_out = (rnd((B, D, H, W), 36) * 1e-2).astype(np.float32).astype(np.float64)
+    net.backward(f32(g_out))
     g = host(net.get(1))
-    gr = U.unet_backward(th, cache, host(dout), bf16=True)
+    gr = U.unet_backward(th, cache, g_out, bf16=True)
     lay, _ = U.param_layout()
     for name, wo, ws, bo, co in lay:
         sz = int(np.prod(ws))
