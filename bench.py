@@ -244,6 +244,79 @@ def bench_batched(q1, si, n, seed, args):
             "batched_gdofs": round(4 * ndof * iters / 128 / st[0]["seconds"] / 1e9, 3)}
 
 
+def unet_forward_flops(D: int, H: int, W: int) -> float:
+    """Algorithmic FLOPs of one network forward on a D x H x W grid: 2 * 27 * Cin * Cout per
+    voxel and convolution (real input channels), plus the 1x1 head."""
+    from oracle import unet_oracle as U  # layer table only
+    f = 0.0
+    for _, ci, co, lvl in U.LAYERS:
+        s = 2 ** (lvl - 1)
+        f += 2.0 * 27 * ci * co * (D // s) * (H // s) * (W // s)
+    return f + 2.0 * 16 * D * H * W
+
+
+def bench_learned(q1, si, n, seed, args):
+    """Learned preconditioner on 64^3 scalar Laplace, k = exp(N(0, 2^2)) iid,
+    Dirichlet on z=0: harvest Jacobi-PCG trajectories, train the U-Net on the
+    GPU (time reported separately), then flexible PCG with the two-level
+    learned preconditioner against FP64 Jacobi-PCG to 1e-8 on held-out fields,
+    every inference inside the timed solve."""
+    import torch
+    from paper_2308_09839_amd import learned as Lm
+    n4 = 64
+    G = Lm.grid_for(n4)
+    B = 4
+    net = q1.UNet(G, G, G, B, seed=si.seed_for(4))
+    # forward / backward timing (HIP events on the current stream)
+    inp = torch.zeros((B, G, G, G, 8), dtype=torch.bfloat16, device="cuda")
+    out = torch.empty((B, G, G, G), dtype=torch.float32, device="cuda")
+    res = {}
+    for nb in (1, B):
+        for _ in range(3):
+            net.forward(inp, out, nb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            net.forward(inp, out, nb)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        res[f"nn_forward_b{nb}_ms"] = round(ms, 4)
+        res[f"nn_forward_b{nb}_tflops"] = round(nb * unet_forward_flops(G, G, G) / (ms * 1e-3) / 1e12, 2)
+    dout = torch.zeros_like(out)
+    net.forward(inp, out, B)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        net.forward(inp, out, B)
+        net.backward(dout)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    res["nn_train_step_b4_ms"] = round(ms, 3)
+    res["nn_train_step_b4_tflops"] = round(3 * B * unet_forward_flops(G, G, G) / (ms * 1e-3) / 1e12, 2)
+    quiet = lambda m: log(m)
+    data = Lm.harvest(n4, [Lm.TRAIN_SEED0 + j for j in range(args.nn_fields)], 16, log=quiet)
+    tr = Lm.Trainer(net, data, B, seed=1)
+    hist, t_train = tr.train(args.nn_steps, lr=1e-3, log=quiet, log_every=100)
+    rows = Lm.evaluate(net, n4, [Lm.EVAL_SEED0 + j for j in range(args.nn_eval)], omega=0.6,
+                       log=quiet)
+    jt = sum(r["jacobi_s"] for r in rows) / len(rows)
+    nt = sum(r["nn_s"] for r in rows) / len(rows)
+    res.update({"nn_pairs": int(data["r"].shape[0]), "nn_train_steps": args.nn_steps,
+                "nn_train_s": round(t_train, 2), "nn_loss_first": hist[0][1],
+                "nn_loss_last": hist[-1][1],
+                "nn_eval_jacobi_iters": [r["jacobi_iters"] for r in rows],
+                "nn_eval_fpcg_iters": [r["nn_iters"] for r in rows],
+                "nn_eval_jacobi_ms": round(jt * 1e3, 2), "nn_eval_fpcg_ms": round(nt * 1e3, 2),
+                "nn_eval_fpcg_true_rel_res": max(r["nn_true_rel_res"] for r in rows),
+                "nn_eval_fallback_at": [r["nn_fallback_at"] for r in rows],
+                "nn_wall_speedup_vs_jacobi": round(jt / nt, 3)})
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +326,9 @@ def main() -> int:
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 atomic, 3 LDS tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
+    ap.add_argument("--nn-fields", type=int, default=24, help="training fields of the learned leg")
+    ap.add_argument("--nn-steps", type=int, default=400, help="Adam steps of the learned leg")
+    ap.add_argument("--nn-eval", type=int, default=2, help="held-out fields of the learned leg")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -332,6 +408,7 @@ def main() -> int:
         extras["fp64_jittered_flop_frac"] = round(alg_flops / (msj * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)
         del opj, xj, yj
         for name, fn in (("csr", bench_csr), ("cg16", bench_cg16), ("cg_elasticity96", bench_ir96),
+                         ("learned64", bench_learned),
                          ("batched32", bench_batched)):
             try:
                 log(f"[bench] {name}")

@@ -411,9 +411,12 @@ class UNet:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and _lib_loaded():
-            lib().q1_unet_destroy(h)
-            self.handle = None
+        try:
+            if h is not None and h.value and _lib_loaded():
+                lib().q1_unet_destroy(h)
+        except Exception:  # interpreter shutdown
+            pass
+        self.handle = None
 
 
 def q1_unet_create(D, H, W, batch, seed=0, stream=None) -> UNet:
@@ -444,9 +447,12 @@ class UNetPrecond:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and _lib_loaded():
-            lib().q1_unet_pc_destroy(h)
-            self.handle = None
+        try:
+            if h is not None and h.value and _lib_loaded():
+                lib().q1_unet_pc_destroy(h)
+        except Exception:  # interpreter shutdown
+            pass
+        self.handle = None
 
 
 def q1_unet_pc_create(net, nx, ny, nz, k, mask=None, stream=None) -> UNetPrecond:

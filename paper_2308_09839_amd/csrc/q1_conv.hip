@@ -5,22 +5,27 @@
 // (pooling, upsampling adjoints, ReLU masks, the 1x1 head, the loss, Adam,
 // weight packing).
 //
-// Tensors are channel-last [B][D][H][W][C] (z, y, x, channel) with C a
-// multiple of 8, so 8 channels of one voxel are one 16-byte load.  A
-// convolution is the implicit GEMM  Y^T (Cout x V) = Wp (Cout x K) * X^T (K x V)
-// with K = 27 taps x Cin in groups of 8 channels: group g = tap * Cin/8 + cg.
-// The 16x16x32 instruction takes, per lane l, 8 consecutive K of row l%16 of
-// the first operand and 8 consecutive K of column l%16 of the second, K-block
-// l/16; so each lane loads one group (16 bytes) of the packed weights for its
-// output channel and one group of the shifted input voxel for its voxel.  The
-// result holds 4 consecutive output channels of one voxel per lane.
+// Tensors are channel-last with a zero halo (PGrid): 8 channels of one voxel
+// are one 16-byte load and every tap of an output tile is in memory, so the
+// inner loops have no bounds tests.  A convolution is the implicit GEMM
+// Y^T (Cout x V) = Wp (Cout x K) * X^T (K x V) with K = 27 taps x Cin in
+// groups of 8 channels: group g = tap * Cin/8 + cg.  The 16x16x32 instruction
+// takes, per lane l, 8 consecutive K of row l%16 of the first operand and 8
+// consecutive K of column l%16 of the second, K-block l/16; so each lane
+// loads one group (16 bytes) of the packed weights for its output channel and
+// one group of the shifted input voxel for its voxel, the shift of group g
+// coming from a per-block table in LDS.  The result holds 4 consecutive
+// output channels of one voxel per lane.  A wavefront owns a 4 x 4 x 4 voxel
+// tile: 16 voxels per instruction column block, 4 z-slices.
 //
 // Backward-data is the same kernel: the adjoint of a 3x3x3 correlation is
 // the correlation with the tap-reversed kernel and transposed channel blocks,
 // so only the weight packing differs.  Backward-weight contracts over voxels
-// (K = 32 voxels per instruction), with the gradient block as the first
-// operand (rows = output channels) and the shifted input as the second
-// (columns = input channels); one wavefront keeps all 27 taps' accumulators.
+// (K = 32 voxels per instruction, bricks of 4 x 4 x 2), with the gradient
+// block as the first operand (rows = output channels) and the shifted input
+// as the second (columns = input channels); one wavefront keeps all 27 taps'
+// accumulators and writes one partial sum per brick chunk, which a second
+// kernel adds in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,14 +50,28 @@ __device__ __forceinline__ bf16x8 ld8(const bf16 *p) {
 
 // ---- convolution forward / backward-data ---------------------------------------
 
-constexpr int kZB = 4;  // z-slices per wavefront tile (tile: 4 x 4 x kZB voxels)
+constexpr int kZB = 4;                   // z-slices per wavefront tile (tile: 4 x 4 x kZB)
+constexpr int kMaxGroups = 27 * 96 / 8;  // largest K / 8 (96 input channels)
 
 template <int NB>  // NB = Cout / 16
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
+  __shared__ int goff[kMaxGroups + 4];
+  const PGrid g = a.g;
+  const int CG = a.cin >> 3;
+  for (int i = threadIdx.x; i < a.nchunks * 4; i += blockDim.x) {
+    int off = 0;  // padding groups have zero weights; any finite input will do
+    if (i < a.ngroups) {
+      const int tap = i / CG, cg = i - tap * CG;
+      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+      off = ((dz * g.Hp + dy) * g.Wp + dx) * a.cin + cg * 8;
+    }
+    goff[i] = off;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int TX = (a.W + 3) >> 2, TY = (a.H + 3) >> 2, TZ = (a.D + kZB - 1) / kZB;
-  const int64_t ntiles = int64_t(a.B) * TZ * TY * TX;
+  const int TX = (g.W + 3) >> 2, TY = (g.H + 3) >> 2, TZ = (g.D + kZB - 1) / kZB;
+  const int64_t ntiles = int64_t(g.B) * TZ * TY * TX;
   if (wave >= ntiles) return;
   int64_t t = wave;
   const int tx = int(t % TX);
@@ -63,63 +82,37 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
   const int b = int(t / TZ);
   const int kg = lane >> 4, j = lane & 15;
   const int vx = tx * 4 + (j & 3), vy = ty * 4 + (j >> 2), z0 = tz * kZB;
-  const int CG = (a.ca + a.cb) >> 3, CGA = a.ca >> 3;
-  const int Dc = a.D >> 1, Hc = a.H >> 1, Wc = a.W >> 1;
+  const bf16 *xb = a.x + g.at(b, z0, vy, vx) * a.cin;
+  const int zstep = g.Hp * g.Wp * a.cin;
+  const bf16 *wrow = a.wp + (size_t(kg) * a.cout + j) * 8;
+  const int wstep = 4 * a.cout * 8;
   f32x4 acc[NB][kZB];
 #pragma unroll
   for (int r = 0; r < NB; ++r)
 #pragma unroll
     for (int z = 0; z < kZB; ++z) acc[r][z] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int tap = 0, cg = kg;
-  while (cg >= CG) {
-    cg -= CG;
-    ++tap;
-  }
-  const bf16 *wrow = a.wp + size_t(j) * 8;
+#pragma unroll 2
   for (int c = 0; c < a.nchunks; ++c) {
-    const int g = 4 * c + kg;
-    bf16x8 wv[NB];
+    const int off = goff[4 * c + kg];
+    bf16x8 wv[NB], xv[kZB];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) wv[r] = ld8(wrow + (size_t(g) * a.cout + r * 16) * 8);
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const int x = vx + dx, y = vy + dy;
-    const bool inxy = g < a.ngroups && x >= 0 && x < a.W && y >= 0 && y < a.H;
-    bf16x8 xv[kZB];
+    for (int r = 0; r < NB; ++r) wv[r] = ld8(wrow + c * wstep + r * 128);
 #pragma unroll
-    for (int zb = 0; zb < kZB; ++zb) {
-      const int z = z0 + zb + dz;
-      if (inxy && z >= 0 && z < a.D) {
-        const bf16 *src;
-        if (cg < CGA) {
-          src = a.up_a ? a.a + ((((size_t)b * Dc + (z >> 1)) * Hc + (y >> 1)) * Wc + (x >> 1)) * a.ca
-                       : a.a + ((((size_t)b * a.D + z) * a.H + y) * a.W + x) * a.ca;
-          src += cg * 8;
-        } else {
-          src = a.b + ((((size_t)b * a.D + z) * a.H + y) * a.W + x) * a.cb + (cg - CGA) * 8;
-        }
-        xv[zb] = ld8(src);
-      } else {
-        xv[zb] = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-      }
-    }
+    for (int zb = 0; zb < kZB; ++zb) xv[zb] = ld8(xb + zb * zstep + off);
 #pragma unroll
     for (int r = 0; r < NB; ++r)
 #pragma unroll
       for (int zb = 0; zb < kZB; ++zb)
         acc[r][zb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[r], xv[zb], acc[r][zb], 0, 0, 0);
-    cg += 4;
-    while (cg >= CG) {
-      cg -= CG;
-      ++tap;
-    }
   }
   // epilogue: lane holds output channels r*16 + 4*kg + i of voxel (vx, vy, z0 + zb)
-  if (vx >= a.W || vy >= a.H) return;
+  if (vx >= g.W || vy >= g.H) return;
+  const PGrid f = g.twice();
 #pragma unroll
   for (int zb = 0; zb < kZB; ++zb) {
     const int z = z0 + zb;
-    if (z >= a.D) break;
-    const size_t vox = (((size_t)b * a.D + z) * a.H + vy) * a.W + vx;
+    if (z >= g.D) break;
+    const int64_t vox = g.at(b, z, vy, vx);
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
       const int c0 = r * 16 + kg * 4;
@@ -129,60 +122,60 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         v[i] = acc[r][zb][i] + (a.bias ? a.bias[c0 + i] : 0.f);
         if (a.relu) v[i] = fmaxf(v[i], 0.f);
       }
-      if (a.mask) {
-        const bf16 *m = a.mask + vox * a.cout + c0;
+      if (a.mask.p) {
+        const bf16 *m = a.mask.p + vox * a.mask.cs + a.mask.co + c0;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (!(bf2f(m[i]) > 0.f)) v[i] = 0.f;
       }
-      if (a.out_bf) {
-        ushort4 o{f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
-        *reinterpret_cast<ushort4 *>(a.out_bf + vox * a.cout + c0) = o;
+      if (a.out.p) {
+        const ushort4 o{f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+        if (!a.out_up) {
+          *reinterpret_cast<ushort4 *>(a.out.p + vox * a.out.cs + a.out.co + c0) = o;
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int64_t fv = f.at(b, 2 * z + (k >> 2), 2 * vy + ((k >> 1) & 1), 2 * vx + (k & 1));
+            *reinterpret_cast<ushort4 *>(a.out.p + fv * a.out.cs + a.out.co + c0) = o;
+          }
+        }
       }
-      if (a.out_f32) {
-        float4 o{v[0], v[1], v[2], v[3]};
+      if (a.o32) {
+        const float4 o{v[0], v[1], v[2], v[3]};
         if (a.split == 0)
-          *reinterpret_cast<float4 *>(a.out_f32 + vox * a.cout + c0) = o;
+          *reinterpret_cast<float4 *>(a.o32 + vox * a.cout + c0) = o;
         else if (c0 < a.split)
-          *reinterpret_cast<float4 *>(a.out_f32 + vox * a.split + c0) = o;
+          *reinterpret_cast<float4 *>(a.o32 + vox * a.split + c0) = o;
         else
-          *reinterpret_cast<float4 *>(a.out2_f32 + vox * (a.cout - a.split) + (c0 - a.split)) = o;
+          *reinterpret_cast<float4 *>(a.o32b + vox * (a.cout - a.split) + (c0 - a.split)) = o;
       }
     }
   }
 }
 
 // ---- convolution backward-weight ---------------------------------------------------
-// Bricks of 4 (x) x 4 (y) x 2 (z) voxels: K-block kg of a lane covers the 8
-// voxels x = 0..3, y = 2 (kg & 1) + {0, 1}, z = kg >> 1 of the brick.
-
-__device__ __forceinline__ unsigned short wg_load_x(const ConvWArgs &a, int b, int x, int y, int z,
-                                                    int ci) {
-  if (ci >= a.ca + a.cb || x < 0 || x >= a.W || y < 0 || y >= a.H || z < 0 || z >= a.D) return 0;
-  if (ci < a.ca) {
-    if (a.up_a)
-      return a.a[((((size_t)b * (a.D >> 1) + (z >> 1)) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) +
-                   (x >> 1)) *
-                      a.ca +
-                  ci];
-    return a.a[((((size_t)b * a.D + z) * a.H + y) * a.W + x) * a.ca + ci];
-  }
-  return a.b[((((size_t)b * a.D + z) * a.H + y) * a.W + x) * a.cb + (ci - a.ca)];
-}
+// Bricks of 4 (x) x 4 (y) x 2 (z) voxels over the grid rounded up (the
+// round-up region reads zeros): K-block kg of a lane covers the 8 voxels
+// x = 0..3, y = 2 (kg & 1) + {0, 1}, z = kg >> 1 of the brick.
 
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int nrb = a.cout >> 4, ncb = (a.ca + a.cb + 15) >> 4;
+  const int nrb = a.cout >> 4, ncb = (a.cin + 15) >> 4;
   if (wave >= int64_t(a.nchunks) * nrb * ncb) return;
+  const PGrid g = a.g;
   const int rbo = int(wave % nrb);
   const int cbi = int((wave / nrb) % ncb);
   const int ch = int(wave / (int64_t(nrb) * ncb));
   const int kg = lane >> 4, j = lane & 15;
-  const int BX = (a.W + 3) >> 2, BY = (a.H + 3) >> 2, BZ = (a.D + 1) >> 1;
-  const int64_t nbr = int64_t(a.B) * BZ * BY * BX;
+  const int BX = (g.W + 3) >> 2, BY = (g.H + 3) >> 2, BZ = (g.D + 1) >> 1;
+  const int64_t nbr = int64_t(g.B) * BZ * BY * BX;
   const int64_t br0 = nbr * ch / a.nchunks, br1 = nbr * (ch + 1) / a.nchunks;
   const int co = rbo * 16 + j, ci = cbi * 16 + j;
+  const int ci_ld = ci < a.cin ? ci : 0;  // columns past cin are computed but not stored
+  int vo[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) vo[i] = ((i >> 2) * g.Wp + (i & 3));
   f32x4 acc[27];
 #pragma unroll
   for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -195,22 +188,23 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWArgs a) {
     q /= BY;
     const int bz = int(q % BZ) * 2 + (kg >> 1);
     const int b = int(q / BZ);
+    const int64_t vb = g.at(b, bz, by, bx);
+    const bf16 *gp = a.gy + vb * a.cout + co;
     u16x8 gu;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int x = bx + (i & 3), y = by + (i >> 2);
-      gu[i] = (x < a.W && y < a.H && bz < a.D)
-                  ? a.g[((((size_t)b * a.D + bz) * a.H + y) * a.W + x) * a.cout + co]
-                  : (unsigned short)0;
+      gu[i] = gp[vo[i] * a.cout];
       bsum += bf2f(gu[i]);
     }
     const bf16x8 gv = __builtin_bit_cast(bf16x8, gu);
+    const bf16 *xp = a.x + vb * a.cin + ci_ld;
 #pragma unroll
     for (int t = 0; t < 27; ++t) {
       const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      const int toff = ((dz * g.Hp + dy) * g.Wp + dx) * a.cin;
       u16x8 xu;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) xu[i] = wg_load_x(a, b, bx + (i & 3) + dx, by + (i >> 2) + dy, bz + dz, ci);
+      for (int i = 0; i < 8; ++i) xu[i] = xp[toff + vo[i] * a.cin];
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gv, __builtin_bit_cast(bf16x8, xu), acc[t],
                                                        0, 0, 0);
     }
@@ -231,14 +225,19 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWArgs a) {
   }
 }
 
-// out[k] = sum over c < nparts of part[c * n + k] (fixed order)
-__global__ void k_sum_parts(const float *__restrict__ part, int nparts, int64_t n,
-                            float *__restrict__ out) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+// out[k] = sum over c < nparts of part[c * n + k]: a block covers 64 consecutive k, its
+// four wavefronts add every fourth part, and the four sums are combined in a fixed order
+__global__ __launch_bounds__(256) void k_sum_parts(const float *__restrict__ part, int nparts,
+                                                   int64_t n, float *__restrict__ out) {
+  __shared__ float sh[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t k = int64_t(blockIdx.x) * 64 + lane;
   float s = 0.f;
-  for (int c = 0; c < nparts; ++c) s += part[c * n + k];
-  out[k] = s;
+  if (k < n)
+    for (int c = w; c < nparts; c += 4) s += part[c * n + k];
+  sh[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && k < n) out[k] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
 // ---- weight packing ----------------------------------------------------------------------
@@ -275,83 +274,114 @@ __global__ void k_pack_bwd(const float *__restrict__ W, int cin, int cout, int n
   wq[i] = f2bf(v);
 }
 
-// ---- pooling, upsampling adjoints, masks -----------------------------------------------
+// ---- layout changes, pooling, upsampling adjoints, masks ------------------------------
 
-// 2x2x2 average pooling, [B][D][H][W][C] -> [B][D/2][H/2][W/2][C]
-__global__ void k_pool2(const bf16 *__restrict__ in, int B, int D, int H, int W, int C,
-                        bf16 *__restrict__ out) {
-  const int Dc = D >> 1, Hc = H >> 1, Wc = W >> 1;
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t n = int64_t(B) * Dc * Hc * Wc * C;
-  if (i >= n) return;
-  const int c = int(i % C);
+// decompose a logical element index over [B][D][H][W][C]
+struct Elem {
+  int b, z, y, x, c;
+};
+__device__ __forceinline__ Elem decompose(int64_t i, const PGrid &g, int C) {
+  Elem e;
+  e.c = int(i % C);
   int64_t v = i / C;
-  const int x = int(v % Wc) * 2;
-  v /= Wc;
-  const int y = int(v % Hc) * 2;
-  v /= Hc;
-  const int z = int(v % Dc) * 2;
-  const int b = int(v / Dc);
+  e.x = int(v % g.W);
+  v /= g.W;
+  e.y = int(v % g.H);
+  v /= g.H;
+  e.z = int(v % g.D);
+  e.b = int(v / g.D);
+  return e;
+}
+
+// padded concatenation of unpadded a (half grid when up_a) and b, 8 channels per thread
+__global__ void k_gather_padded(const bf16 *__restrict__ a, int ca, int up_a,
+                                const bf16 *__restrict__ b, int cb, PGrid g,
+                                bf16 *__restrict__ out) {
+  const int C8 = (ca + cb) >> 3;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(g.B) * g.D * g.H * g.W * C8) return;
+  const Elem e = decompose(i, g, C8);
+  const int c = e.c * 8;
+  const bf16 *src;
+  if (c < ca) {
+    if (up_a) {
+      const int Dc = g.D / 2, Hc = g.H / 2, Wc = g.W / 2;
+      src = a + ((((int64_t)e.b * Dc + (e.z >> 1)) * Hc + (e.y >> 1)) * Wc + (e.x >> 1)) * ca + c;
+    } else {
+      src = a + ((((int64_t)e.b * g.D + e.z) * g.H + e.y) * g.W + e.x) * ca + c;
+    }
+  } else {
+    src = b + ((((int64_t)e.b * g.D + e.z) * g.H + e.y) * g.W + e.x) * cb + (c - ca);
+  }
+  *reinterpret_cast<uint4 *>(out + g.at(e.b, e.z, e.y, e.x) * (ca + cb) + c) =
+      *reinterpret_cast<const uint4 *>(src);
+}
+
+__global__ void k_unpad_f32(const float *__restrict__ in, PGrid g, int C, float *__restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(g.B) * g.D * g.H * g.W * C) return;
+  const Elem e = decompose(i, g, C);
+  out[i] = in[g.at(e.b, e.z, e.y, e.x) * C + e.c];
+}
+
+// 2x2x2 average pooling of a channel window into a padded coarse tensor [C]
+__global__ void k_pool2(Slice in, PGrid f, int C, bf16 *__restrict__ out) {
+  const PGrid g = f.half();
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(g.B) * g.D * g.H * g.W * C) return;
+  const Elem e = decompose(i, g, C);
   float s = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    s += bf2f(in[((((size_t)b * D + z + (k >> 2)) * H + y + ((k >> 1) & 1)) * W + x + (k & 1)) * C + c]);
-  out[i] = f2bf(s * 0.125f);
+    s += bf2f(in.p[f.at(e.b, 2 * e.z + (k >> 2), 2 * e.y + ((k >> 1) & 1), 2 * e.x + (k & 1)) * in.cs +
+                   in.co + e.c]);
+  out[g.at(e.b, e.z, e.y, e.x) * C + e.c] = f2bf(s * 0.125f);
 }
 
-// coarse gpre = (sum of the 8 children of gup) * (mask > 0), gup FP32 fine, mask/out coarse
-__global__ void k_up_adjoint_mask(const float *__restrict__ gup, const bf16 *__restrict__ mask,
-                                  int B, int Dc, int Hc, int Wc, int C, bf16 *__restrict__ out) {
+// coarse gpre = (sum of the 8 children of gup) * (mask > 0); gup FP32 padded fine [C];
+// the mask is the coarse activation, stored upsampled (read at the first child)
+__global__ void k_up_adjoint_mask(const float *__restrict__ gup, Slice mask, PGrid g, int C,
+                                  bf16 *__restrict__ out) {
+  const PGrid f = g.twice();
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t n = int64_t(B) * Dc * Hc * Wc * C;
-  if (i >= n) return;
-  const int c = int(i % C);
-  int64_t v = i / C;
-  const int x = int(v % Wc) * 2;
-  v /= Wc;
-  const int y = int(v % Hc) * 2;
-  v /= Hc;
-  const int z = int(v % Dc) * 2;
-  const int b = int(v / Dc);
-  const int D = 2 * Dc, H = 2 * Hc, W = 2 * Wc;
+  if (i >= int64_t(g.B) * g.D * g.H * g.W * C) return;
+  const Elem e = decompose(i, g, C);
   float s = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    s += gup[((((size_t)b * D + z + (k >> 2)) * H + y + ((k >> 1) & 1)) * W + x + (k & 1)) * C + c];
-  out[i] = f2bf(bf2f(mask[i]) > 0.f ? s : 0.f);
+    s += gup[f.at(e.b, 2 * e.z + (k >> 2), 2 * e.y + ((k >> 1) & 1), 2 * e.x + (k & 1)) * C + e.c];
+  const float m = bf2f(mask.p[f.at(e.b, 2 * e.z, 2 * e.y, 2 * e.x) * mask.cs + mask.co + e.c]);
+  out[g.at(e.b, e.z, e.y, e.x) * C + e.c] = f2bf(m > 0.f ? s : 0.f);
 }
 
-// fine gpre = (gskip + gp[parent] / 8) * (mask > 0)
+// fine gpre = (gskip + gp[parent] / 8) * (mask > 0), all padded
 __global__ void k_pool_adjoint_add_mask(const float *__restrict__ gskip,
-                                        const float *__restrict__ gp,
-                                        const bf16 *__restrict__ mask, int B, int D, int H, int W,
-                                        int C, bf16 *__restrict__ out) {
+                                        const float *__restrict__ gp, Slice mask, PGrid f, int C,
+                                        bf16 *__restrict__ out) {
+  const PGrid g = f.half();
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t n = int64_t(B) * D * H * W * C;
-  if (i >= n) return;
-  const int c = int(i % C);
-  int64_t v = i / C;
-  const int x = int(v % W);
-  v /= W;
-  const int y = int(v % H);
-  v /= H;
-  const int z = int(v % D);
-  const int b = int(v / D);
-  const float p = gp[((((size_t)b * (D >> 1) + (z >> 1)) * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1)) * C + c];
-  const float s = gskip[i] + 0.125f * p;
-  out[i] = f2bf(bf2f(mask[i]) > 0.f ? s : 0.f);
+  if (i >= int64_t(f.B) * f.D * f.H * f.W * C) return;
+  const Elem e = decompose(i, f, C);
+  const int64_t v = f.at(e.b, e.z, e.y, e.x);
+  const float s = gskip[v * C + e.c] + 0.125f * gp[g.at(e.b, e.z >> 1, e.y >> 1, e.x >> 1) * C + e.c];
+  const float m = bf2f(mask.p[v * mask.cs + mask.co + e.c]);
+  out[v * C + e.c] = f2bf(m > 0.f ? s : 0.f);
 }
 
 // ---- head, loss -------------------------------------------------------------------------
 
-// out[v] = sum_c t[v][c] wh[c] + bh
-__global__ void k_head_fwd(const bf16 *__restrict__ t, int C, int64_t nv,
-                           const float *__restrict__ wh, float *__restrict__ out) {
-  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
+// out[b][z][y][x] (unpadded) = sum_c t[v][c] wh[c] + bh, t padded [16]
+__global__ void k_head_fwd(const bf16 *__restrict__ t, PGrid g, const float *__restrict__ wh,
+                           float *__restrict__ out) {
+  constexpr int C = 16;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(g.B) * g.D * g.H * g.W) return;
+  const Elem e = decompose(i, g, 1);
+  const bf16 *tv = t + g.at(e.b, e.z, e.y, e.x) * C;
   float s = wh[C];
-  for (int c = 0; c < C; ++c) s += bf2f(t[v * C + c]) * wh[c];
-  out[v] = s;
+#pragma unroll
+  for (int c = 0; c < C; ++c) s += bf2f(tv[c]) * wh[c];
+  out[i] = s;
 }
 
 constexpr int kHB = 256;  // threads per block of the head / loss reductions
@@ -359,7 +389,7 @@ constexpr int kHB = 256;  // threads per block of the head / loss reductions
 // gpre[v][c] = dout[v] wh[c] (t[v][c] > 0); per-block partials of
 // dL/dwh[c] = sum_v dout[v] t[v][c] and dL/dbh = sum_v dout[v]
 __global__ __launch_bounds__(kHB) void k_head_bwd(const float *__restrict__ dout,
-                                                 const bf16 *__restrict__ t, int64_t nv,
+                                                 const bf16 *__restrict__ t, PGrid g,
                                                  const float *__restrict__ wh,
                                                  bf16 *__restrict__ gpre,
                                                  float *__restrict__ part /*[nblk][17]*/) {
@@ -368,8 +398,11 @@ __global__ __launch_bounds__(kHB) void k_head_bwd(const float *__restrict__ dout
   float acc[C + 1];
 #pragma unroll
   for (int c = 0; c <= C; ++c) acc[c] = 0.f;
-  for (int64_t v = int64_t(blockIdx.x) * kHB + threadIdx.x; v < nv; v += int64_t(gridDim.x) * kHB) {
-    const float d = dout[v];
+  const int64_t nv = int64_t(g.B) * g.D * g.H * g.W;
+  for (int64_t i = int64_t(blockIdx.x) * kHB + threadIdx.x; i < nv; i += int64_t(gridDim.x) * kHB) {
+    const Elem e = decompose(i, g, 1);
+    const int64_t v = g.at(e.b, e.z, e.y, e.x);
+    const float d = dout[i];
     acc[C] += d;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -460,9 +493,13 @@ __global__ void k_adam(float *__restrict__ th, const float *__restrict__ g, floa
 // ---- host launchers ---------------------------------------------------------------------
 
 static inline dim3 g1(int64_t n, int bs = 256) { return dim3(unsigned((n + bs - 1) / bs)); }
+static inline int64_t logical(const PGrid &g) { return int64_t(g.B) * g.D * g.H * g.W; }
 
 int conv_forward(const ConvArgs &a, hipStream_t s) {
-  const int64_t ntiles = int64_t(a.B) * ((a.D + kZB - 1) / kZB) * ((a.H + 3) / 4) * ((a.W + 3) / 4);
+  Q1_CHECK(a.cin % 8 == 0 && a.nchunks * 4 <= kMaxGroups + 4, Q1_EUNSUPPORTED,
+           "conv: %d input channels", a.cin);
+  const int64_t ntiles = int64_t(a.g.B) * ((a.g.D + kZB - 1) / kZB) * ((a.g.H + 3) / 4) *
+                         ((a.g.W + 3) / 4);
   const dim3 grid(unsigned((ntiles + 3) / 4)), block(256);
   switch (a.cout) {
     case 16: hipLaunchKernelGGL(k_conv_fwd<1>, grid, block, 0, s, a); break;
@@ -477,17 +514,17 @@ int conv_forward(const ConvArgs &a, hipStream_t s) {
 }
 
 int wgrad_chunks(const ConvWArgs &a) {
-  const int64_t nbr = int64_t(a.B) * ((a.D + 1) / 2) * ((a.H + 3) / 4) * ((a.W + 3) / 4);
-  const int units = (a.cout / 16) * ((a.ca + a.cb + 15) / 16);
+  const int64_t nbr = int64_t(a.g.B) * ((a.g.D + 1) / 2) * ((a.g.H + 3) / 4) * ((a.g.W + 3) / 4);
+  const int units = (a.cout / 16) * ((a.cin + 15) / 16);
   return int(std::max<int64_t>(1, std::min<int64_t>(nbr, std::max(1, 4096 / units))));
 }
 
 int conv_wgrad(ConvWArgs a, float *gw, float *gb, hipStream_t s) {
-  const int64_t waves = int64_t(a.nchunks) * (a.cout / 16) * ((a.ca + a.cb + 15) / 16);
+  const int64_t waves = int64_t(a.nchunks) * (a.cout / 16) * ((a.cin + 15) / 16);
   hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, s, a);
   const int64_t nk = int64_t(27) * a.cin_real * a.cout;
-  hipLaunchKernelGGL(k_sum_parts, g1(nk), dim3(256), 0, s, a.part, a.nchunks, nk, gw);
-  hipLaunchKernelGGL(k_sum_parts, g1(a.cout), dim3(256), 0, s, a.bpart, a.nchunks,
+  hipLaunchKernelGGL(k_sum_parts, g1(nk, 64), dim3(256), 0, s, a.part, a.nchunks, nk, gw);
+  hipLaunchKernelGGL(k_sum_parts, g1(a.cout, 64), dim3(256), 0, s, a.bpart, a.nchunks,
                      int64_t(a.cout), gb);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
@@ -508,39 +545,52 @@ int pack_backward(const float *W, int cin, int cout, int ngroups_pad, bf16 *wq, 
   return Q1_OK;
 }
 
-int pool2(const bf16 *in, int B, int D, int H, int W, int C, bf16 *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_pool2, g1(int64_t(B) * (D / 2) * (H / 2) * (W / 2) * C), dim3(256), 0, s,
-                     in, B, D, H, W, C, out);
+int gather_padded(const bf16 *a, int ca, int up_a, const bf16 *b, int cb, const PGrid &g, bf16 *out,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_padded, g1(logical(g) * ((ca + cb) / 8)), dim3(256), 0, s, a, ca, up_a,
+                     b, cb, g, out);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
 
-int up_adjoint_mask(const float *gup, const bf16 *mask, int B, int Dc, int Hc, int Wc, int C,
-                    bf16 *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_up_adjoint_mask, g1(int64_t(B) * Dc * Hc * Wc * C), dim3(256), 0, s, gup,
-                     mask, B, Dc, Hc, Wc, C, out);
+int unpad_f32(const float *in, const PGrid &g, int C, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpad_f32, g1(logical(g) * C), dim3(256), 0, s, in, g, C, out);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
 
-int pool_adjoint_add_mask(const float *gskip, const float *gp, const bf16 *mask, int B, int D,
-                          int H, int W, int C, bf16 *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_pool_adjoint_add_mask, g1(int64_t(B) * D * H * W * C), dim3(256), 0, s,
-                     gskip, gp, mask, B, D, H, W, C, out);
+int pool2(Slice in, const PGrid &fine, int C, bf16 *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool2, g1(logical(fine.half()) * C), dim3(256), 0, s, in, fine, C, out);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
 
-int head_forward(const bf16 *t, int64_t nv, const float *wh, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_head_fwd, g1(nv), dim3(256), 0, s, t, 16, nv, wh, out);
+int up_adjoint_mask(const float *gup, Slice mask_fine, const PGrid &coarse, int C, bf16 *out,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_up_adjoint_mask, g1(logical(coarse) * C), dim3(256), 0, s, gup, mask_fine,
+                     coarse, C, out);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
 
-int head_backward(const float *dout, const bf16 *t, int64_t nv, const float *wh, bf16 *gpre,
+int pool_adjoint_add_mask(const float *gskip, const float *gp, Slice mask, const PGrid &fine, int C,
+                          bf16 *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_adjoint_add_mask, g1(logical(fine) * C), dim3(256), 0, s, gskip, gp,
+                     mask, fine, C, out);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+int head_forward(const bf16 *t, const PGrid &g, const float *wh, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_head_fwd, g1(logical(g)), dim3(256), 0, s, t, g, wh, out);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+int head_backward(const float *dout, const bf16 *t, const PGrid &g, const float *wh, bf16 *gpre,
                   float *part, int nblk, float *gwh, hipStream_t s) {
-  hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(kHB), 0, s, dout, t, nv, wh, gpre, part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, nblk, int64_t(17), gwh);
+  hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(kHB), 0, s, dout, t, g, wh, gpre, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, nblk, int64_t(17), gwh);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }

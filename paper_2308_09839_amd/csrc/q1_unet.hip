@@ -10,6 +10,11 @@
 // FP32 master weights, gradients and Adam moments in one flat vector whose
 // layout is, per convolution, W[27][Cin][Cout] then b[Cout], and for the head
 // w[16] then b.  Activations are kept from the last forward for the backward.
+// Every tensor a convolution reads has a zero halo (PGrid).  The skip and
+// upsampled tensors are written by their producers straight into the
+// concatenation buffers the decoder reads (cat1 = [up(t2), s1] on the finest
+// grid, cat2 = [up(b3), s2] on the middle one), so no convolution reads two
+// tensors or upsamples on the fly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,14 +30,13 @@ namespace q1 {
 namespace {
 
 struct LayerSpec {
-  int cin_real, cin, cout, level, ca, up;  // ca: channels read from the upsampled tensor
+  int cin_real, cin, cout, level;
 };
 // enc1a enc1b enc2a enc2b enc3a enc3b dec2a dec2b dec1a dec1b
-constexpr LayerSpec kSpec[10] = {
-    {2, 8, 16, 1, 8, 0},    {16, 16, 16, 1, 16, 0}, {16, 16, 32, 2, 16, 0},
-    {32, 32, 32, 2, 32, 0}, {32, 32, 64, 3, 32, 0}, {64, 64, 64, 3, 64, 0},
-    {96, 96, 32, 2, 64, 1}, {32, 32, 32, 2, 32, 0}, {48, 48, 16, 1, 32, 1},
-    {16, 16, 16, 1, 16, 0}};
+constexpr LayerSpec kSpec[10] = {{2, 8, 16, 1},   {16, 16, 16, 1}, {16, 16, 32, 2},
+                                 {32, 32, 32, 2}, {32, 32, 64, 3}, {64, 64, 64, 3},
+                                 {96, 96, 32, 2}, {32, 32, 32, 2}, {48, 48, 16, 1},
+                                 {16, 16, 16, 1}};
 constexpr int kInC = 8;  // stored input channels (2 used)
 
 struct Layer {
@@ -49,22 +53,22 @@ struct UNet {
   int64_t nparams = 0, head_o = 0;
   float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
   Layer L[10];
-  bf16 *act[10] = {};
-  bf16 *p1 = nullptr, *p2 = nullptr;
+  // padded activations: input, own outputs, concatenations, pooled tensors
+  bf16 *xin = nullptr, *act0 = nullptr, *act2 = nullptr, *act4 = nullptr, *act6 = nullptr,
+       *act8 = nullptr, *act9 = nullptr, *cat1 = nullptr, *cat2 = nullptr, *p1 = nullptr,
+       *p2 = nullptr;
   bf16 *g1a = nullptr, *g1b = nullptr, *g2a = nullptr, *g2b = nullptr, *g3a = nullptr,
        *g3b = nullptr;
   float *gup1 = nullptr, *gskip1 = nullptr, *gup2 = nullptr, *gskip2 = nullptr, *gp2 = nullptr,
         *gp1 = nullptr;
   float *part = nullptr, *bpart = nullptr, *hpart = nullptr;
   double *mpart = nullptr;
-  size_t part_cap = 0, bpart_cap = 0;
-  const bf16 *last_in = nullptr;
   int last_nb = 0;
   std::vector<void *> allocs;
 
-  int64_t vox(int level) const {
+  PGrid grid(int level, int nb) const {
     const int f = 1 << (level - 1);
-    return int64_t(B) * (D / f) * (H / f) * (W / f);
+    return PGrid(nb, D / f, H / f, W / f);
   }
   ~UNet() {
     for (void *p : allocs) (void)hipFree(p);
@@ -99,6 +103,8 @@ int dalloc(UNet &n, T **p, size_t count) {
   if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
     return fail(Q1_ENOMEM, "q1_unet: device allocation of %zu bytes failed", count * sizeof(T));
   n.allocs.push_back(q);
+  if (hipMemset(q, 0, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+    return fail(Q1_EHIP, "q1_unet: clearing a buffer failed");
   *p = static_cast<T *>(q);
   return Q1_OK;
 }
@@ -125,74 +131,73 @@ int pack_all(UNet &n, hipStream_t s) {
   return Q1_OK;
 }
 
-ConvArgs conv_args(const UNet &n, int l, int nb, const bf16 *a, const bf16 *b) {
-  const Layer &L = n.L[l];
-  const int f = 1 << (L.s.level - 1);
-  ConvArgs c;
-  c.a = a;
-  c.ca = L.s.ca;
-  c.up_a = L.s.up;
-  c.b = b;
-  c.cb = L.s.cin - L.s.ca;
-  c.B = nb;
-  c.D = n.D / f;
-  c.H = n.H / f;
-  c.W = n.W / f;
-  return c;
+struct LayerIO {
+  const bf16 *in;
+  Slice out;
+  int up;
+};
+
+// where each layer reads and writes (see the header comment)
+LayerIO layer_io(const UNet &n, int l) {
+  switch (l) {
+    case 0: return {n.xin, {n.act0, 16, 0}, 0};
+    case 1: return {n.act0, {n.cat1, 48, 32}, 0};
+    case 2: return {n.p1, {n.act2, 32, 0}, 0};
+    case 3: return {n.act2, {n.cat2, 96, 64}, 0};
+    case 4: return {n.p2, {n.act4, 64, 0}, 0};
+    case 5: return {n.act4, {n.cat2, 96, 0}, 1};
+    case 6: return {n.cat2, {n.act6, 32, 0}, 0};
+    case 7: return {n.act6, {n.cat1, 48, 0}, 1};
+    case 8: return {n.cat1, {n.act8, 16, 0}, 0};
+    default: return {n.act8, {n.act9, 16, 0}, 0};
+  }
 }
 
-int layer_forward(UNet &n, int l, int nb, const bf16 *a, const bf16 *b, hipStream_t s) {
+int layer_forward(UNet &n, int l, int nb, hipStream_t s) {
   const Layer &L = n.L[l];
-  ConvArgs c = conv_args(n, l, nb, a, b);
+  const LayerIO io = layer_io(n, l);
+  ConvArgs c;
+  c.x = io.in;
+  c.cin = L.s.cin;
+  c.g = n.grid(L.s.level, nb);
   c.wp = L.wp;
   c.ngroups = L.ngroups;
   c.nchunks = L.nchunks;
   c.cout = L.s.cout;
   c.bias = n.theta + L.bo;
   c.relu = 1;
-  c.out_bf = n.act[l];
+  c.out = io.out;
+  c.out_up = io.up;
   return conv_forward(c, s);
 }
 
-// input gradient of layer l from its pre-activation gradient g
-int layer_backward_data(UNet &n, int l, int nb, const bf16 *g, const bf16 *mask, bf16 *out_bf,
-                        float *out_f32, int split, float *out2, hipStream_t s) {
+// input gradient of layer l from its pre-activation gradient g (padded [cout])
+int layer_backward_data(UNet &n, int l, int nb, const bf16 *g, Slice mask, bf16 *out_bf,
+                        float *o32, int split, float *o32b, hipStream_t s) {
   const Layer &L = n.L[l];
-  const int f = 1 << (L.s.level - 1);
   ConvArgs c;
-  c.a = g;
-  c.ca = L.s.cout;
-  c.B = nb;
-  c.D = n.D / f;
-  c.H = n.H / f;
-  c.W = n.W / f;
+  c.x = g;
+  c.cin = L.s.cout;
+  c.g = n.grid(L.s.level, nb);
   c.wp = L.wq;
   c.ngroups = L.ngroups_b;
   c.nchunks = L.nchunks_b;
   c.cout = L.s.cin;
   c.mask = mask;
-  c.out_bf = out_bf;
-  c.out_f32 = out_f32;
+  c.out = Slice{out_bf, L.s.cin, 0};
+  c.o32 = o32;
   c.split = split;
-  c.out2_f32 = out2;
+  c.o32b = o32b;
   return conv_forward(c, s);
 }
 
-int layer_wgrad(UNet &n, int l, int nb, const bf16 *a, const bf16 *b, const bf16 *g,
-                hipStream_t s) {
+int layer_wgrad(UNet &n, int l, int nb, const bf16 *g, hipStream_t s) {
   const Layer &L = n.L[l];
-  const ConvArgs c = conv_args(n, l, nb, a, b);
   ConvWArgs w;
-  w.a = c.a;
-  w.b = c.b;
-  w.ca = c.ca;
-  w.cb = c.cb;
-  w.up_a = c.up_a;
-  w.B = nb;
-  w.D = c.D;
-  w.H = c.H;
-  w.W = c.W;
-  w.g = g;
+  w.x = layer_io(n, l).in;
+  w.cin = L.s.cin;
+  w.g = n.grid(L.s.level, nb);
+  w.gy = g;
   w.cout = L.s.cout;
   w.cin_real = L.s.cin_real;
   w.nchunks = wgrad_chunks(w);
@@ -203,22 +208,14 @@ int layer_wgrad(UNet &n, int l, int nb, const bf16 *a, const bf16 *b, const bf16
 
 int unet_forward(UNet &n, const bf16 *in, float *out, int nb, hipStream_t s) {
   int rc;
-  const int D = n.D, H = n.H, W = n.W;
-  bf16 **A = n.act;
-  if ((rc = layer_forward(n, 0, nb, in, nullptr, s))) return rc;
-  if ((rc = layer_forward(n, 1, nb, A[0], nullptr, s))) return rc;
-  if ((rc = pool2(A[1], nb, D, H, W, 16, n.p1, s))) return rc;
-  if ((rc = layer_forward(n, 2, nb, n.p1, nullptr, s))) return rc;
-  if ((rc = layer_forward(n, 3, nb, A[2], nullptr, s))) return rc;
-  if ((rc = pool2(A[3], nb, D / 2, H / 2, W / 2, 32, n.p2, s))) return rc;
-  if ((rc = layer_forward(n, 4, nb, n.p2, nullptr, s))) return rc;
-  if ((rc = layer_forward(n, 5, nb, A[4], nullptr, s))) return rc;
-  if ((rc = layer_forward(n, 6, nb, A[5], A[3], s))) return rc;
-  if ((rc = layer_forward(n, 7, nb, A[6], nullptr, s))) return rc;
-  if ((rc = layer_forward(n, 8, nb, A[7], A[1], s))) return rc;
-  if ((rc = layer_forward(n, 9, nb, A[8], nullptr, s))) return rc;
-  if ((rc = head_forward(A[9], int64_t(nb) * D * H * W, n.theta + n.head_o, out, s))) return rc;
-  n.last_in = in;
+  const PGrid g1 = n.grid(1, nb), g2 = n.grid(2, nb);
+  if ((rc = gather_padded(in, kInC, 0, nullptr, 0, g1, n.xin, s))) return rc;
+  for (int l = 0; l < 10; ++l) {
+    if ((rc = layer_forward(n, l, nb, s))) return rc;
+    if (l == 1 && (rc = pool2(Slice{n.cat1, 48, 32}, g1, 16, n.p1, s))) return rc;
+    if (l == 3 && (rc = pool2(Slice{n.cat2, 96, 64}, g2, 32, n.p2, s))) return rc;
+  }
+  if ((rc = head_forward(n.act9, g1, n.theta + n.head_o, out, s))) return rc;
   n.last_nb = nb;
   return Q1_OK;
 }
@@ -226,46 +223,55 @@ int unet_forward(UNet &n, const bf16 *in, float *out, int nb, hipStream_t s) {
 int unet_backward(UNet &n, const float *dout, hipStream_t s) {
   int rc;
   const int nb = n.last_nb;
-  const int D = n.D, H = n.H, W = n.W;
-  bf16 **A = n.act;
-  const int64_t v1 = int64_t(nb) * D * H * W;
+  const PGrid g1 = n.grid(1, nb), g2 = n.grid(2, nb), g3 = n.grid(3, nb);
+  const int64_t v1 = int64_t(nb) * n.D * n.H * n.W;
   const int hblk = int(std::min<int64_t>(1024, (v1 + 255) / 256));
-  if ((rc = head_backward(dout, A[9], v1, n.theta + n.head_o, n.g1a, n.hpart, hblk,
+  const Slice none{};
+  if ((rc = head_backward(dout, n.act9, g1, n.theta + n.head_o, n.g1a, n.hpart, hblk,
                           n.grad + n.head_o, s)))
     return rc;
   // level 1 decoder
-  if ((rc = layer_wgrad(n, 9, nb, A[8], nullptr, n.g1a, s))) return rc;
-  if ((rc = layer_backward_data(n, 9, nb, n.g1a, A[8], n.g1b, nullptr, 0, nullptr, s))) return rc;
-  if ((rc = layer_wgrad(n, 8, nb, A[7], A[1], n.g1b, s))) return rc;
-  if ((rc = layer_backward_data(n, 8, nb, n.g1b, nullptr, nullptr, n.gup1, 32, n.gskip1, s)))
+  if ((rc = layer_wgrad(n, 9, nb, n.g1a, s))) return rc;
+  if ((rc = layer_backward_data(n, 9, nb, n.g1a, Slice{n.act8, 16, 0}, n.g1b, nullptr, 0,
+                                nullptr, s)))
     return rc;
-  if ((rc = up_adjoint_mask(n.gup1, A[7], nb, D / 2, H / 2, W / 2, 32, n.g2a, s))) return rc;
+  if ((rc = layer_wgrad(n, 8, nb, n.g1b, s))) return rc;
+  if ((rc = layer_backward_data(n, 8, nb, n.g1b, none, nullptr, n.gup1, 32, n.gskip1, s)))
+    return rc;
+  if ((rc = up_adjoint_mask(n.gup1, Slice{n.cat1, 48, 0}, g2, 32, n.g2a, s))) return rc;
   // level 2 decoder
-  if ((rc = layer_wgrad(n, 7, nb, A[6], nullptr, n.g2a, s))) return rc;
-  if ((rc = layer_backward_data(n, 7, nb, n.g2a, A[6], n.g2b, nullptr, 0, nullptr, s))) return rc;
-  if ((rc = layer_wgrad(n, 6, nb, A[5], A[3], n.g2b, s))) return rc;
-  if ((rc = layer_backward_data(n, 6, nb, n.g2b, nullptr, nullptr, n.gup2, 64, n.gskip2, s)))
+  if ((rc = layer_wgrad(n, 7, nb, n.g2a, s))) return rc;
+  if ((rc = layer_backward_data(n, 7, nb, n.g2a, Slice{n.act6, 32, 0}, n.g2b, nullptr, 0,
+                                nullptr, s)))
     return rc;
-  if ((rc = up_adjoint_mask(n.gup2, A[5], nb, D / 4, H / 4, W / 4, 64, n.g3a, s))) return rc;
+  if ((rc = layer_wgrad(n, 6, nb, n.g2b, s))) return rc;
+  if ((rc = layer_backward_data(n, 6, nb, n.g2b, none, nullptr, n.gup2, 64, n.gskip2, s)))
+    return rc;
+  if ((rc = up_adjoint_mask(n.gup2, Slice{n.cat2, 96, 0}, g3, 64, n.g3a, s))) return rc;
   // level 3
-  if ((rc = layer_wgrad(n, 5, nb, A[4], nullptr, n.g3a, s))) return rc;
-  if ((rc = layer_backward_data(n, 5, nb, n.g3a, A[4], n.g3b, nullptr, 0, nullptr, s))) return rc;
-  if ((rc = layer_wgrad(n, 4, nb, n.p2, nullptr, n.g3b, s))) return rc;
-  if ((rc = layer_backward_data(n, 4, nb, n.g3b, nullptr, nullptr, n.gp2, 0, nullptr, s)))
+  if ((rc = layer_wgrad(n, 5, nb, n.g3a, s))) return rc;
+  if ((rc = layer_backward_data(n, 5, nb, n.g3a, Slice{n.act4, 64, 0}, n.g3b, nullptr, 0,
+                                nullptr, s)))
     return rc;
-  if ((rc = pool_adjoint_add_mask(n.gskip2, n.gp2, A[3], nb, D / 2, H / 2, W / 2, 32, n.g2a, s)))
+  if ((rc = layer_wgrad(n, 4, nb, n.g3b, s))) return rc;
+  if ((rc = layer_backward_data(n, 4, nb, n.g3b, none, nullptr, n.gp2, 0, nullptr, s))) return rc;
+  if ((rc = pool_adjoint_add_mask(n.gskip2, n.gp2, Slice{n.cat2, 96, 64}, g2, 32, n.g2a, s)))
     return rc;
   // level 2 encoder
-  if ((rc = layer_wgrad(n, 3, nb, A[2], nullptr, n.g2a, s))) return rc;
-  if ((rc = layer_backward_data(n, 3, nb, n.g2a, A[2], n.g2b, nullptr, 0, nullptr, s))) return rc;
-  if ((rc = layer_wgrad(n, 2, nb, n.p1, nullptr, n.g2b, s))) return rc;
-  if ((rc = layer_backward_data(n, 2, nb, n.g2b, nullptr, nullptr, n.gp1, 0, nullptr, s)))
+  if ((rc = layer_wgrad(n, 3, nb, n.g2a, s))) return rc;
+  if ((rc = layer_backward_data(n, 3, nb, n.g2a, Slice{n.act2, 32, 0}, n.g2b, nullptr, 0,
+                                nullptr, s)))
     return rc;
-  if ((rc = pool_adjoint_add_mask(n.gskip1, n.gp1, A[1], nb, D, H, W, 16, n.g1a, s))) return rc;
+  if ((rc = layer_wgrad(n, 2, nb, n.g2b, s))) return rc;
+  if ((rc = layer_backward_data(n, 2, nb, n.g2b, none, nullptr, n.gp1, 0, nullptr, s))) return rc;
+  if ((rc = pool_adjoint_add_mask(n.gskip1, n.gp1, Slice{n.cat1, 48, 32}, g1, 16, n.g1a, s)))
+    return rc;
   // level 1 encoder
-  if ((rc = layer_wgrad(n, 1, nb, A[0], nullptr, n.g1a, s))) return rc;
-  if ((rc = layer_backward_data(n, 1, nb, n.g1a, A[0], n.g1b, nullptr, 0, nullptr, s))) return rc;
-  return layer_wgrad(n, 0, nb, n.last_in, nullptr, n.g1b, s);
+  if ((rc = layer_wgrad(n, 1, nb, n.g1a, s))) return rc;
+  if ((rc = layer_backward_data(n, 1, nb, n.g1a, Slice{n.act0, 16, 0}, n.g1b, nullptr, 0,
+                                nullptr, s)))
+    return rc;
+  return layer_wgrad(n, 0, nb, n.g1b, s);
 }
 
 // ---- preconditioner encoding ---------------------------------------------------------
@@ -485,13 +491,9 @@ int q1_unet_create(q1_unet **out, int D, int H, int W, int batch, uint64_t seed,
     L.nchunks = (L.ngroups + 3) / 4;
     L.ngroups_b = 27 * L.s.cout / 8;
     L.nchunks_b = (L.ngroups_b + 3) / 4;
-    const int f = 1 << (L.s.level - 1);
     ConvWArgs w;
-    w.B = batch;
-    w.D = D / f;
-    w.H = H / f;
-    w.W = W / f;
-    w.ca = L.s.cin;
+    w.g = n.grid(L.s.level, batch);
+    w.cin = L.s.cin;
     w.cout = L.s.cout;
     const int nch = wgrad_chunks(w);
     part_cap = std::max(part_cap, size_t(nch) * 27 * L.s.cin_real * L.s.cout);
@@ -511,28 +513,36 @@ int q1_unet_create(q1_unet **out, int D, int H, int W, int batch, uint64_t seed,
     Layer &L = n.L[l];
     A(&L.wp, size_t(L.nchunks) * 4 * L.s.cout * 8);
     if (l > 0) A(&L.wq, size_t(L.nchunks_b) * 4 * L.s.cin * 8);
-    A(&n.act[l], size_t(n.vox(L.s.level)) * L.s.cout);
   }
-  A(&n.p1, size_t(n.vox(2)) * 16);
-  A(&n.p2, size_t(n.vox(3)) * 32);
-  A(&n.g1a, size_t(n.vox(1)) * 16);
-  A(&n.g1b, size_t(n.vox(1)) * 16);
-  A(&n.g2a, size_t(n.vox(2)) * 32);
-  A(&n.g2b, size_t(n.vox(2)) * 32);
-  A(&n.g3a, size_t(n.vox(3)) * 64);
-  A(&n.g3b, size_t(n.vox(3)) * 64);
-  A(&n.gup1, size_t(n.vox(1)) * 32);
-  A(&n.gskip1, size_t(n.vox(1)) * 16);
-  A(&n.gup2, size_t(n.vox(2)) * 64);
-  A(&n.gskip2, size_t(n.vox(2)) * 32);
-  A(&n.gp2, size_t(n.vox(3)) * 32);
-  A(&n.gp1, size_t(n.vox(2)) * 16);
+  const size_t v1 = size_t(n.grid(1, batch).voxels()), v2 = size_t(n.grid(2, batch).voxels()),
+               v3 = size_t(n.grid(3, batch).voxels());
+  A(&n.xin, v1 * kInC);
+  A(&n.act0, v1 * 16);
+  A(&n.act2, v2 * 32);
+  A(&n.act4, v3 * 64);
+  A(&n.act6, v2 * 32);
+  A(&n.act8, v1 * 16);
+  A(&n.act9, v1 * 16);
+  A(&n.cat1, v1 * 48);
+  A(&n.cat2, v2 * 96);
+  A(&n.p1, v2 * 16);
+  A(&n.p2, v3 * 32);
+  A(&n.g1a, v1 * 16);
+  A(&n.g1b, v1 * 16);
+  A(&n.g2a, v2 * 32);
+  A(&n.g2b, v2 * 32);
+  A(&n.g3a, v3 * 64);
+  A(&n.g3b, v3 * 64);
+  A(&n.gup1, v1 * 32);
+  A(&n.gskip1, v1 * 16);
+  A(&n.gup2, v2 * 64);
+  A(&n.gskip2, v2 * 32);
+  A(&n.gp2, v3 * 32);
+  A(&n.gp1, v2 * 16);
   A(&n.part, part_cap);
   A(&n.bpart, bpart_cap);
   A(&n.hpart, size_t(1024) * 17);
   A(&n.mpart, size_t(1024) * 2);
-  n.part_cap = part_cap;
-  n.bpart_cap = bpart_cap;
   if (!rc) {
     // He-normal weights (std sqrt(2 / fan_in)), zero biases, zero moments
     std::vector<float> th(size_t(n.nparams), 0.f);
@@ -660,30 +670,31 @@ int q1_conv3d_forward(int B, int D, int H, int W, const uint16_t *a_d, int ca, i
   Q1_CHECK(!up_a || (D % 2 == 0 && H % 2 == 0 && W % 2 == 0), Q1_EINVAL,
            "q1_conv3d_forward: upsampled input needs an even grid");
   Q1_CHECK(conv_cout_ok(cout), Q1_EUNSUPPORTED, "q1_conv3d_forward: cout %d", cout);
+  Q1_CHECK(ca + cb <= 96, Q1_EUNSUPPORTED, "q1_conv3d_forward: more than 96 input channels");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int cin = ca + cb, ngroups = 27 * cin / 8, nchunks = (ngroups + 3) / 4;
-  TmpBuf wp;
+  const PGrid g(B, D, H, W);
+  TmpBuf wp, xp, yp;
   Q1_HIP(hipMalloc(&wp.p, size_t(nchunks) * 4 * cout * 8 * sizeof(bf16)));
+  Q1_HIP(hipMalloc(&xp.p, size_t(g.voxels()) * cin * sizeof(bf16)));
+  Q1_HIP(hipMalloc(&yp.p, size_t(g.voxels()) * cout * sizeof(float)));
+  Q1_HIP(hipMemsetAsync(xp.p, 0, size_t(g.voxels()) * cin * sizeof(bf16), s));
   int rc = pack_forward(w_d, cin, cin, cout, nchunks * 4, static_cast<bf16 *>(wp.p), s);
+  if (!rc) rc = gather_padded(a_d, ca, up_a, b_d, cb, g, static_cast<bf16 *>(xp.p), s);
   if (rc) return rc;
   ConvArgs c;
-  c.a = a_d;
-  c.ca = ca;
-  c.up_a = up_a;
-  c.b = b_d;
-  c.cb = cb;
-  c.B = B;
-  c.D = D;
-  c.H = H;
-  c.W = W;
+  c.x = static_cast<bf16 *>(xp.p);
+  c.cin = cin;
+  c.g = g;
   c.wp = static_cast<bf16 *>(wp.p);
   c.ngroups = ngroups;
   c.nchunks = nchunks;
   c.cout = cout;
   c.bias = bias_d;
   c.relu = relu;
-  c.out_f32 = y_d;
+  c.o32 = static_cast<float *>(yp.p);
   if ((rc = conv_forward(c, s))) return rc;
+  if ((rc = unpad_f32(static_cast<float *>(yp.p), g, cout, y_d, s))) return rc;
   Q1_HIP(hipStreamSynchronize(s));
   return Q1_OK;
 }
@@ -691,28 +702,31 @@ int q1_conv3d_forward(int B, int D, int H, int W, const uint16_t *a_d, int ca, i
 int q1_conv3d_backward_data(int B, int D, int H, int W, const uint16_t *gy_d, int cout,
                             const float *w_d, int cin, float *gx_d, void *stream) {
   Q1_CHECK(gy_d && w_d && gx_d, Q1_EINVAL, "q1_conv3d_backward_data: NULL argument");
-  Q1_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1 && cout % 8 == 0 && cout >= 8, Q1_EINVAL,
-           "q1_conv3d_backward_data: bad sizes");
+  Q1_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1 && cout % 8 == 0 && cout >= 8 && cout <= 96,
+           Q1_EINVAL, "q1_conv3d_backward_data: bad sizes");
   Q1_CHECK(conv_cout_ok(cin), Q1_EUNSUPPORTED, "q1_conv3d_backward_data: cin %d", cin);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ngroups = 27 * cout / 8, nchunks = (ngroups + 3) / 4;
-  TmpBuf wq;
+  const PGrid g(B, D, H, W);
+  TmpBuf wq, gp, xp;
   Q1_HIP(hipMalloc(&wq.p, size_t(nchunks) * 4 * cin * 8 * sizeof(bf16)));
+  Q1_HIP(hipMalloc(&gp.p, size_t(g.voxels()) * cout * sizeof(bf16)));
+  Q1_HIP(hipMalloc(&xp.p, size_t(g.voxels()) * cin * sizeof(float)));
+  Q1_HIP(hipMemsetAsync(gp.p, 0, size_t(g.voxels()) * cout * sizeof(bf16), s));
   int rc = pack_backward(w_d, cin, cout, nchunks * 4, static_cast<bf16 *>(wq.p), s);
+  if (!rc) rc = gather_padded(gy_d, cout, 0, nullptr, 0, g, static_cast<bf16 *>(gp.p), s);
   if (rc) return rc;
   ConvArgs c;
-  c.a = gy_d;
-  c.ca = cout;
-  c.B = B;
-  c.D = D;
-  c.H = H;
-  c.W = W;
+  c.x = static_cast<bf16 *>(gp.p);
+  c.cin = cout;
+  c.g = g;
   c.wp = static_cast<bf16 *>(wq.p);
   c.ngroups = ngroups;
   c.nchunks = nchunks;
   c.cout = cin;
-  c.out_f32 = gx_d;
+  c.o32 = static_cast<float *>(xp.p);
   if ((rc = conv_forward(c, s))) return rc;
+  if ((rc = unpad_f32(static_cast<float *>(xp.p), g, cin, gx_d, s))) return rc;
   Q1_HIP(hipStreamSynchronize(s));
   return Q1_OK;
 }
@@ -723,32 +737,34 @@ int q1_conv3d_backward_weight(int B, int D, int H, int W, const uint16_t *a_d, i
   Q1_CHECK(a_d && gy_d && gw_d && gb_d && (cb == 0 || b_d), Q1_EINVAL,
            "q1_conv3d_backward_weight: NULL argument");
   Q1_CHECK(B >= 1 && D >= 1 && H >= 1 && W >= 1 && ca >= 8 && ca % 8 == 0 && cb >= 0 &&
-               cb % 8 == 0 && cout % 16 == 0 && cout >= 16,
+               cb % 8 == 0 && cout % 16 == 0 && cout >= 16 && cout <= 96,
            Q1_EINVAL, "q1_conv3d_backward_weight: bad sizes");
   Q1_CHECK(!up_a || (D % 2 == 0 && H % 2 == 0 && W % 2 == 0), Q1_EINVAL,
            "q1_conv3d_backward_weight: upsampled input needs an even grid");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const int cin = ca + cb;
+  const PGrid g(B, D, H, W);
   ConvWArgs w;
-  w.a = a_d;
-  w.ca = ca;
-  w.up_a = up_a;
-  w.b = b_d;
-  w.cb = cb;
-  w.B = B;
-  w.D = D;
-  w.H = H;
-  w.W = W;
-  w.g = gy_d;
+  w.cin = cin;
+  w.g = g;
   w.cout = cout;
-  w.cin_real = ca + cb;
+  w.cin_real = cin;
   w.nchunks = wgrad_chunks(w);
-  TmpBuf part, bpart;
-  Q1_HIP(hipMalloc(&part.p, size_t(w.nchunks) * 27 * w.cin_real * cout * sizeof(float)));
+  TmpBuf xp, gp, part, bpart;
+  Q1_HIP(hipMalloc(&xp.p, size_t(g.voxels()) * cin * sizeof(bf16)));
+  Q1_HIP(hipMalloc(&gp.p, size_t(g.voxels()) * cout * sizeof(bf16)));
+  Q1_HIP(hipMalloc(&part.p, size_t(w.nchunks) * 27 * cin * cout * sizeof(float)));
   Q1_HIP(hipMalloc(&bpart.p, size_t(w.nchunks) * cout * sizeof(float)));
+  Q1_HIP(hipMemsetAsync(xp.p, 0, size_t(g.voxels()) * cin * sizeof(bf16), s));
+  Q1_HIP(hipMemsetAsync(gp.p, 0, size_t(g.voxels()) * cout * sizeof(bf16), s));
+  int rc = gather_padded(a_d, ca, up_a, b_d, cb, g, static_cast<bf16 *>(xp.p), s);
+  if (!rc) rc = gather_padded(gy_d, cout, 0, nullptr, 0, g, static_cast<bf16 *>(gp.p), s);
+  if (rc) return rc;
+  w.x = static_cast<bf16 *>(xp.p);
+  w.gy = static_cast<bf16 *>(gp.p);
   w.part = static_cast<float *>(part.p);
   w.bpart = static_cast<float *>(bpart.p);
-  int rc = conv_wgrad(w, gw_d, gb_d, s);
-  if (rc) return rc;
+  if ((rc = conv_wgrad(w, gw_d, gb_d, s))) return rc;
   Q1_HIP(hipStreamSynchronize(s));
   return Q1_OK;
 }

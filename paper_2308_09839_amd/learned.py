@@ -67,10 +67,12 @@ def snapshot_iters(kmax: int, count: int) -> list[int]:
 
 
 def harvest(n: int, seeds, per_solve: int, rtol: float = 1e-10, sigma: float = 2.0,
-            log=print):
+            omega: float | None = 0.6, log=print):
     """Residual -> error pairs from Jacobi-PCG trajectories.  Returns a dict of
     device tensors r, e (FP32 [npairs, nn]), field index per pair, and the
-    problems (for the coefficient channel)."""
+    problems (for the coefficient channel).  With omega, each pair is taken
+    after one damped-Jacobi step, as the two-level preconditioner presents it
+    to the network: e1 = e - omega D^-1 r and r1 = A e1."""
     import torch
     probs, rs, es, fld = [], [], [], []
     t0 = time.perf_counter()
@@ -81,10 +83,17 @@ def harvest(n: int, seeds, per_solve: int, rtol: float = 1e-10, sigma: float = 2
         its = snapshot_iters(max(1, int(st["iters"] * 0.9)), per_solve)
         snaps = [torch.empty_like(P.b) for _ in its]
         q1_pcg_trace(P.op, Q1_PC_JACOBI, P.b, x, rtol, 100000, its, snaps)
+        if omega is not None:
+            dinv = torch.empty_like(P.b)
+            P.op.diag(dinv)
+            dinv = 1.0 / dinv
         for s in snaps:
             e = x - s
             r = torch.empty_like(e)
             P.op.apply(e, r)
+            if omega is not None:
+                e = e - omega * dinv * r
+                P.op.apply(e, r)
             rs.append(r.float())
             es.append(e.float())
             fld.append(j)
