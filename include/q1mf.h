@@ -92,11 +92,15 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
 /* Scatter strategies of the apply (Section 3, third step):
  *   ATOMIC   one thread per element, global atomic adds (the paper's
  *            one-thread-per-element strategy, Section 6);
- *   LDS_TILE element tiles with their nodes staged in LDS, accumulation in LDS,
- *            global atomics only for nodes shared with other tiles;
+ *   LDS_TILE element tiles, one wavefront each: corners gathered from memory,
+ *            accumulation in LDS, global atomics only for nodes shared with
+ *            other tiles;
+ *   BLOCK    larger tiles, one workgroup of four wavefronts each: the tile's
+ *            node records (coordinates, input) are staged in LDS once,
+ *            per-wavefront LDS accumulators added in a fixed order;
  *   AUTO     the fastest measured strategy for the operator;
  *   CSR      the assembled matrix (made by q1_csr_create only). */
-enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_LDS_TILE = 3, Q1_V_CSR = 4 };
+enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_LDS_TILE = 3, Q1_V_CSR = 4, Q1_V_BLOCK = 5 };
 
 /* Create an operator over caller-owned device arrays.  The arrays are
  * referenced, not copied: they must stay valid and unchanged until
@@ -181,6 +185,15 @@ typedef int (*q1_precond_fn)(void *ctx, const void *r_d, void *z_d, void *stream
  * (0 = off), the solve continues with Jacobi; st->fallback_at records when. */
 int q1_fpcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,
             int maxit, int safeguard_m, q1_stats *st, void *stream);
+/* Flexible CG with truncated orthogonalisation, FCG(m) (Notay): the new
+ * direction is z = M(r) made A-orthogonal to the last trunc_m directions
+ * (1 <= trunc_m <= 8), and alpha = p^T r / p^T A p.  trunc_m = 1 is q1_fpcg.
+ * A preconditioner that changes from one call to the next (a network, an
+ * inner iteration) keeps the energy norm of the error decreasing; for a fixed
+ * SPD M every trunc_m gives the PCG iterates.  Safeguards and stats as
+ * q1_fpcg.  Keeps 2 * trunc_m extra vectors. */
+int q1_fcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,
+           int maxit, int safeguard_m, int trunc_m, q1_stats *st, void *stream);
 
 /* Jacobi preconditioner object, usable as the ctx of q1_precond_jacobi. */
 typedef struct q1_jacobi q1_jacobi;

@@ -17,7 +17,7 @@ from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32,
                    Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
-    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_trace", "q1_batched_pcg", "q1_mpcg", "q1_fpcg", "q1_ir_solve", "Jacobi",
+    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_trace", "q1_batched_pcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
     "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
@@ -268,10 +268,10 @@ def q1_jacobi_create(op: Op, stream=None) -> Jacobi:
 
 
 def q1_fpcg(op: Op, precond, b, x, rtol: float, maxit: int, safeguard_m: int = 0,
-            stream=None) -> dict:
+            stream=None, trunc_m: int = 1) -> dict:
     """precond: a Jacobi/learned preconditioner object with .fn and .handle, a
     (function pointer, ctx) pair, or a Python callable f(r_ptr, z_ptr, stream_ptr) -> int
-    that enqueues z = M(r) on the stream."""
+    that enqueues z = M(r) on the stream.  trunc_m > 1 runs FCG(trunc_m) (q1_fcg)."""
     keep = None
     if hasattr(precond, "fn") and hasattr(precond, "handle"):
         fn, ctx = precond.fn, precond.handle
@@ -288,10 +288,20 @@ def q1_fpcg(op: Op, precond, b, x, rtol: float, maxit: int, safeguard_m: int = 0
         keep = PRECOND_FN(_cb)
         fn, ctx = ctypes.cast(keep, ctypes.c_void_p), None
     st = Q1Stats()
-    _solve_rc(lib().q1_fpcg(op.handle, fn, ctx, _dptr(b), _dptr(x), rtol, maxit, safeguard_m,
-                            ctypes.byref(st), _stream(stream)))
+    if trunc_m == 1:
+        _solve_rc(lib().q1_fpcg(op.handle, fn, ctx, _dptr(b), _dptr(x), rtol, maxit, safeguard_m,
+                                ctypes.byref(st), _stream(stream)))
+    else:
+        _solve_rc(lib().q1_fcg(op.handle, fn, ctx, _dptr(b), _dptr(x), rtol, maxit, safeguard_m,
+                               trunc_m, ctypes.byref(st), _stream(stream)))
     del keep
     return st.as_dict()
+
+
+def q1_fcg(op: Op, precond, b, x, rtol: float, maxit: int, safeguard_m: int = 0,
+           trunc_m: int = 4, stream=None) -> dict:
+    """Flexible CG with truncated orthogonalisation against the last trunc_m directions."""
+    return q1_fpcg(op, precond, b, x, rtol, maxit, safeguard_m, stream, trunc_m)
 
 
 def q1_mpcg(op64: Op, op32: Op, b, x, rtol: float, delta: float = 0.1, maxit: int = 50000,

@@ -27,6 +27,7 @@ Q1_V_AUTO = 0
 Q1_V_ATOMIC = 1
 Q1_V_LDS_TILE = 3
 Q1_V_CSR = 4
+Q1_V_BLOCK = 5
 
 Q1_PC_NONE = 0
 Q1_PC_JACOBI = 1
@@ -87,6 +88,8 @@ PROTOTYPES = {
     "q1_pcg_trace": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_int, c_vp, c_vp, P(Q1Stats),
                              c_vp]),
     "q1_fpcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),
+    "q1_fcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_int, c_int, c_int, P(Q1Stats),
+                       c_vp]),
     "q1_jacobi_create": (c_int, [P(c_vp), c_vp, c_vp]),
     "q1_precond_jacobi": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "q1_jacobi_destroy": (c_int, [c_vp]),

@@ -219,6 +219,7 @@ int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop)
       return op.physics == 1 ? apply_atomic<float, 1>(op, x, y, s, stop)
                              : apply_atomic<float, 3>(op, x, y, s, stop);
     case Q1_V_LDS_TILE:
+    case Q1_V_BLOCK:
       return launch_apply_tile(op, x, y, s, stop);
     case Q1_V_CSR:
       return launch_spmv(op, x, y, s, stop);

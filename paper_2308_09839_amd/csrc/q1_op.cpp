@@ -43,7 +43,8 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
   Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_ELASTICITY, Q1_EINVAL,
            "q1_op_create: physics must be 1 (Laplace) or 3 (elasticity), got %d", physics);
   Q1_CHECK(dtype == Q1_F64 || dtype == Q1_F32, Q1_EINVAL, "q1_op_create: bad dtype %d", dtype);
-  Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC || variant == Q1_V_LDS_TILE,
+  Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC || variant == Q1_V_LDS_TILE ||
+               variant == Q1_V_BLOCK,
            Q1_EINVAL, "q1_op_create: bad variant %d", variant);
   Q1_CHECK(n_nodes > 0 && n_nodes < (int64_t(1) << 31) && n_elems >= 0 &&
                n_elems < (int64_t(1) << 31),
@@ -79,7 +80,7 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
     if (hipGetDeviceProperties(&prop, op->device) == hipSuccess)
       op->num_cus = prop.multiProcessorCount;
   }
-  if (op->variant == Q1_V_LDS_TILE) {
+  if (op->variant == Q1_V_LDS_TILE || op->variant == Q1_V_BLOCK) {
     rc = build_tiles(*op, static_cast<hipStream_t>(stream));
     if (rc) {
       free_tiles(*op);

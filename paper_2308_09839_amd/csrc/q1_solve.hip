@@ -299,6 +299,121 @@ __global__ __launch_bounds__(kRT) void k_refresh_residual(int64_t n, const doubl
 }
 __global__ void k_clear_done(Status *st) { st->done = 0; st->status = 0; }
 
+
+// ---- flexible CG with truncated orthogonalisation (FCG(m)) ------------------------
+constexpr int kMaxTrunc = 8;
+
+struct DirSet {  // window of previous directions p_j, q_j = A p_j and the partials of p_j.q_j
+  const void *p[kMaxTrunc];
+  const void *q[kMaxTrunc];
+  const double *pq[kMaxTrunc];
+};
+
+// partials of z.q_j for the m directions of the window
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_multi_dot(int64_t n, const T *__restrict__ z, DirSet d,
+                                                   int m, double *__restrict__ part /*[m][kMaxRB]*/,
+                                                   const Status *__restrict__ st) {
+  if (st->done) return;
+  const Range rg = block_range(n);
+  double v[kMaxTrunc];
+#pragma unroll
+  for (int j = 0; j < kMaxTrunc; ++j) v[j] = 0.0;
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    const double zi = double(z[i]);
+#pragma unroll
+    for (int j = 0; j < kMaxTrunc; ++j)
+      if (j < m) v[j] += zi * double(static_cast<const T *>(d.q[j])[i]);
+  }
+  block_sum<kMaxTrunc>(v);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < m; ++j) part[j * kMaxRB + blockIdx.x] = v[j];
+}
+
+// p = z - sum_j (z.q_j / p_j.q_j) p_j
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_fcg_direction(int64_t n, const T *__restrict__ z,
+                                                       DirSet d, int m,
+                                                       const double *__restrict__ part_zq,
+                                                       T *__restrict__ p,
+                                                       const Status *__restrict__ st) {
+  if (st->done) return;
+  const int nb = gridDim.x;
+  double c[kMaxTrunc];
+#pragma unroll
+  for (int j = 0; j < kMaxTrunc; ++j) {
+    c[j] = 0.0;
+    if (j < m) {
+      const double zq = sum_partials(part_zq + j * kMaxRB, nb);
+      const double pq = sum_partials(d.pq[j], nb);
+      c[j] = pq > 0.0 ? zq / pq : 0.0;
+    }
+  }
+  const Range rg = block_range(n);
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    double v = double(z[i]);
+#pragma unroll
+    for (int j = 0; j < kMaxTrunc; ++j)
+      if (j < m) v -= c[j] * double(static_cast<const T *>(d.p[j])[i]);
+    p[i] = T(v);
+  }
+}
+
+// partials of p.q and p.r
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_dot_pq_pr(int64_t n, const T *__restrict__ p,
+                                                   const T *__restrict__ q, const T *__restrict__ r,
+                                                   double *__restrict__ part_pq,
+                                                   double *__restrict__ part_pr,
+                                                   const Status *__restrict__ st) {
+  if (st->done) return;
+  const Range rg = block_range(n);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    const double pi = double(p[i]);
+    v[0] += pi * double(q[i]);
+    v[1] += pi * double(r[i]);
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    part_pq[blockIdx.x] = v[0];
+    part_pr[blockIdx.x] = v[1];
+  }
+}
+
+// alpha = p.r / p.q; x += alpha p; r -= alpha q; partials of r.r
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_fcg_update(int64_t n, const T *__restrict__ p,
+                                                    const T *__restrict__ q, T *__restrict__ x,
+                                                    T *__restrict__ r,
+                                                    const double *__restrict__ part_pq,
+                                                    const double *__restrict__ part_pr,
+                                                    double *__restrict__ part_rr,
+                                                    Status *__restrict__ st) {
+  if (st->done) return;
+  const int nb = gridDim.x;
+  const double pq = sum_partials(part_pq, nb);
+  const double pr = sum_partials(part_pr, nb);
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(pr)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->done = 1;
+      st->status = Q1_EBREAKDOWN;
+    }
+    return;
+  }
+  const double alpha = pr / pq;
+  const Range rg = block_range(n);
+  double v[1] = {0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
+    const T rn = T(double(r[i]) - alpha * double(q[i]));
+    x[i] = T(double(x[i]) + alpha * double(p[i]));
+    r[i] = rn;
+    v[0] += double(rn) * double(rn);
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = v[0];
+}
+
 // ---- host drivers ------------------------------------------------------------
 
 namespace {
@@ -472,29 +587,49 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
   return status;
 }
 
-// Flexible PCG with a caller preconditioner z = M(r); falls back to Jacobi
+// Flexible CG with a caller preconditioner z = M(r) and truncated
+// orthogonalisation: the new direction is z made A-orthogonal to the last m
+// directions (m = 1 is the Polak-Ribiere flexible PCG).  Falls back to Jacobi
 // for the rest of the solve when M fails, gives z.r <= 0 or a non-finite
 // value, or when the residual has not dropped below its value safeguard_m
 // iterations earlier.
 template <typename T>
 int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, int maxit,
-           int safeguard_m, q1_stats *stats, hipStream_t s) {
+           int safeguard_m, int m, q1_stats *stats, hipStream_t s) {
   const int64_t n = op.n_nodes * op.physics;
   Work W;
   int rc = alloc_work<T>(W, n, true);
   if (rc) return rc;
+  // direction window: m slots of p and q, and the p.q partials of every slot
+  void *dirs = nullptr;
+  double *pq_parts = nullptr, *zq_parts = nullptr;
+  struct Free {
+    void **a;
+    double **b, **c;
+    ~Free() {
+      if (*a) (void)hipFree(*a);
+      if (*b) (void)hipFree(*b);
+      if (*c) (void)hipFree(*c);
+    }
+  } fr{&dirs, &pq_parts, &zq_parts};
+  const size_t vb = size_t(std::max<int64_t>(n, 1)) * sizeof(T);
+  Q1_HIP(hipMalloc(&dirs, 2 * size_t(m) * vb));
+  Q1_HIP(hipMalloc(&pq_parts, size_t(m) * kMaxRB * sizeof(double)));
+  Q1_HIP(hipMalloc(&zq_parts, size_t(kMaxTrunc) * kMaxRB * sizeof(double)));
+  auto P = [&](int j) { return reinterpret_cast<T *>(static_cast<char *>(dirs) + size_t(j) * vb); };
+  auto Qv = [&](int j) {
+    return reinterpret_cast<T *>(static_cast<char *>(dirs) + size_t(m + j) * vb);
+  };
   const auto t0 = std::chrono::steady_clock::now();
   if ((rc = setup_diag<T>(op, W, Q1_PC_JACOBI, s))) return rc;
   const int nb = nblocks_for(n);
-  double *P = W.part;
-  double *part_rho[2] = {P, P + kMaxRB};
-  double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB,
-         *part_num = P + 5 * kMaxRB;
-  T *r = static_cast<T *>(W.r), *p = static_cast<T *>(W.p), *q = static_cast<T *>(W.q),
-    *w = static_cast<T *>(W.w), *ro = static_cast<T *>(W.r_old), *z = static_cast<T *>(W.z);
+  double *Pp = W.part;
+  double *part_rho = Pp, *part_pr = Pp + kMaxRB, *part_rr = Pp + 3 * kMaxRB,
+         *part_bb = Pp + 4 * kMaxRB;
+  T *r = static_cast<T *>(W.r), *w = static_cast<T *>(W.w), *z = static_cast<T *>(W.z);
   Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
-  hipLaunchKernelGGL((k_pcg_init<T>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r, p, part_rho[0],
-                     part_bb, 0);
+  hipLaunchKernelGGL((k_pcg_init<T>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r,
+                     static_cast<T *>(W.p), part_rho, part_bb, 0);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
   Q1_HIP(hipGetLastError());
   if ((rc = read_status(W, s))) return rc;
@@ -503,13 +638,12 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
   double rr = bb;
   std::vector<double> hist;
   hist.push_back(bb);
-  // z_0 = M(r_0); p_0 = z_0
   auto precondition = [&](int k) -> int {
     bool ok = fallback_at < 0 && M != nullptr;
     if (ok) ok = M(ctx, r, z, s) == Q1_OK;
     if (ok) {
-      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, part_rho[k & 1], W.st);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rho[k & 1], nb, &W.st->aux);
+      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, part_rho, W.st);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rho, nb, &W.st->aux);
       Q1_HIP(hipGetLastError());
       int rc2 = read_status(W, s);
       if (rc2) return rc2;
@@ -519,7 +653,6 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
       if (fallback_at < 0) fallback_at = k;
       (void)hipGetLastError();
       hipLaunchKernelGGL((k_jacobi<T>), grid1(n), dim3(256), 0, s, n, w, r, z);
-      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, part_rho[k & 1], W.st);
       Q1_HIP(hipGetLastError());
     }
     return Q1_OK;
@@ -527,13 +660,30 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
   if (bb > 0.0) {
     const double tol2 = rtol * rtol;
     status = Q1_ENOCONV;
-    if ((rc = precondition(0))) return rc;
-    Q1_HIP(hipMemcpyAsync(p, z, n * sizeof(T), hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < maxit; ++k) {
-      if ((rc = launch_apply(op, p, q, s, &W.st->done))) return rc;
-      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
-      hipLaunchKernelGGL((k_pcg_update<T, true>), dim3(nb), dim3(kRT), 0, s, n, p, q, w, x, r,
-                         ro, part_pq, part_rho[k & 1], nullptr, part_rr, W.st);
+      if ((rc = precondition(k))) return rc;
+      // window: the previous min(k, m) directions, oldest first
+      const int cur = k % m, nwin = std::min(k, m);
+      DirSet d{};
+      for (int j = 0; j < nwin; ++j) {
+        const int sl = (k - nwin + j) % m;
+        d.p[j] = P(sl);
+        d.q[j] = Qv(sl);
+        d.pq[j] = pq_parts + size_t(sl) * kMaxRB;
+      }
+      if (nwin > 0) {
+        hipLaunchKernelGGL((k_multi_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin, zq_parts,
+                           W.st);
+        hipLaunchKernelGGL((k_fcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin,
+                           zq_parts, P(cur), W.st);
+      } else {
+        Q1_HIP(hipMemcpyAsync(P(cur), z, size_t(n) * sizeof(T), hipMemcpyDeviceToDevice, s));
+      }
+      if ((rc = launch_apply(op, P(cur), Qv(cur), s, &W.st->done))) return rc;
+      hipLaunchKernelGGL((k_dot_pq_pr<T>), dim3(nb), dim3(kRT), 0, s, n, P(cur), Qv(cur), r,
+                         pq_parts + size_t(cur) * kMaxRB, part_pr, W.st);
+      hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kRT), 0, s, n, P(cur), Qv(cur), x, r,
+                         pq_parts + size_t(cur) * kMaxRB, part_pr, part_rr, W.st);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rr, nb, &W.st->rr);
       Q1_HIP(hipGetLastError());
       if ((rc = read_status(W, s))) return rc;
@@ -545,19 +695,10 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
         status = Q1_OK;
         break;
       }
-      if (iters >= maxit) break;
       // stagnation safeguard
       if (safeguard_m > 0 && fallback_at < 0 && int(hist.size()) > safeguard_m &&
           !(rr < hist[hist.size() - 1 - safeguard_m]))
         fallback_at = iters;
-      if ((rc = precondition(k + 1))) return rc;
-      hipLaunchKernelGGL((k_fpcg_dots<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, ro,
-                         part_rho[(k + 1) & 1], part_num, W.st);
-      // beta = z_{k+1}.(r_{k+1} - r_k) / rho_k ; p = z + beta p
-      hipLaunchKernelGGL((k_pcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, r, w, z, p,
-                         part_num, part_rho[k & 1], part_rr, part_bb, 0.0, k + 1, maxit + 1,
-                         W.st);
-      Q1_HIP(hipGetLastError());
     }
     if (W.hst->done && W.hst->status == Q1_EBREAKDOWN) status = Q1_EBREAKDOWN;
   }
@@ -750,17 +891,24 @@ int q1_pcg_trace(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int
                       maxit, st, s, true, sn);
 }
 
-int q1_fpcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,
-            int maxit, int safeguard_m, q1_stats *st, void *stream) {
-  Q1_CHECK(op && b_d && x_d, Q1_EINVAL, "q1_fpcg: NULL argument");
-  Q1_CHECK(rtol >= 0 && maxit >= 0, Q1_EINVAL, "q1_fpcg: need rtol >= 0 and maxit >= 0");
+int q1_fcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,
+           int maxit, int safeguard_m, int trunc_m, q1_stats *st, void *stream) {
+  Q1_CHECK(op && b_d && x_d, Q1_EINVAL, "q1_fcg: NULL argument");
+  Q1_CHECK(rtol >= 0 && maxit >= 0, Q1_EINVAL, "q1_fcg: need rtol >= 0 and maxit >= 0");
+  Q1_CHECK(trunc_m >= 1 && trunc_m <= kMaxTrunc, Q1_EINVAL, "q1_fcg: trunc_m %d not in [1, %d]",
+           trunc_m, kMaxTrunc);
   Op &o = *reinterpret_cast<Op *>(op);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (o.dtype == Q1_F64)
-    return fpcg_t<double>(o, M, ctx, static_cast<const double *>(b_d),
-                          static_cast<double *>(x_d), rtol, maxit, safeguard_m, st, s);
+    return fpcg_t<double>(o, M, ctx, static_cast<const double *>(b_d), static_cast<double *>(x_d),
+                          rtol, maxit, safeguard_m, trunc_m, st, s);
   return fpcg_t<float>(o, M, ctx, static_cast<const float *>(b_d), static_cast<float *>(x_d),
-                       rtol, maxit, safeguard_m, st, s);
+                       rtol, maxit, safeguard_m, trunc_m, st, s);
+}
+
+int q1_fpcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,
+            int maxit, int safeguard_m, q1_stats *st, void *stream) {
+  return q1_fcg(op, M, ctx, b_d, x_d, rtol, maxit, safeguard_m, 1, st, stream);
 }
 
 int q1_jacobi_create(q1_jacobi **out, q1_op *op, void *stream) {

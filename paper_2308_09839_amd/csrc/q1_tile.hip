@@ -24,7 +24,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <numeric>
 #include <vector>
 
@@ -163,6 +166,125 @@ __global__ __launch_bounds__(64) void k_apply_tile(
     } else {
 #pragma unroll
       for (int j = 0; j < DPN; ++j) y[gg * DPN + j] = sV[j * max_nodes + i];
+    }
+  }
+}
+
+// Block-staged variant: one workgroup of four wavefronts per tile.  The
+// tile's node records (coordinates and input values; zero input on Dirichlet
+// nodes) are loaded once into LDS with bulk loads, so the element loop reads
+// corners from LDS instead of gathering them from memory.  Wave w takes the
+// tile's steps w, w + 4, ... and accumulates into its own LDS copy; the copies
+// are added in a fixed order when the tile's nodes are written.
+template <typename T, int DPN, bool LDS_ATOMIC>
+__global__ __launch_bounds__(256) void k_apply_block(
+    int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
+    const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
+    const uint4 *__restrict__ lconn, const T *__restrict__ coef_t, int64_t coef_stride,
+    const T *__restrict__ xyz, const T *__restrict__ x, T *__restrict__ y,
+    const int *__restrict__ stop) {
+  if (stop && *stop) return;
+  constexpr int NR = 3 + DPN;  // x, y, z, u[DPN], stored field by field
+  constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][max_nodes]
+  T *sV = sR + size_t(NR) * max_nodes;       // [4][DPN][max_nodes]
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tile = xcd_block_t(blockIdx.x, gridDim.x);
+  const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
+  const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
+  // stage the node records: all loads of a round are issued before any LDS write
+  for (int base = 0; base < nm; base += KN * 256) {
+    uint32_t raw[KN];
+    T rec[KN][NR];
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+      const int i = base + k * 256 + tid;
+      raw[k] = i < nm ? nodes[n0 + i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+      const int i = base + k * 256 + tid;
+      if (i < nm) {
+        const int64_t g = raw[k] & kIdMask;
+        const bool fixed = (raw[k] & kFixedBit) != 0;
+        rec[k][0] = xyz[g];
+        rec[k][1] = xyz[nn + g];
+        rec[k][2] = xyz[2 * nn + g];
+#pragma unroll
+        for (int j = 0; j < DPN; ++j) rec[k][3 + j] = fixed ? T(0) : x[g * DPN + j];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+      const int i = base + k * 256 + tid;
+      if (i < nm) {
+#pragma unroll
+        for (int f = 0; f < NR; ++f) sR[size_t(f) * max_nodes + i] = rec[k][f];
+#pragma unroll
+        for (int c = 0; c < 4 * DPN; ++c) sV[size_t(c) * max_nodes + i] = T(0);
+      }
+    }
+  }
+  __syncthreads();
+  T *myV = sV + size_t(w) * DPN * max_nodes;
+  int s = s0 + w;
+  uint4 pk_n = make_uint4(0xffffffffu, 0u, 0u, 0u);
+  T c0_n = T(0), c1_n = T(0);
+  if (s < s1) {
+    const int64_t slot = int64_t(s) * kLanes + lane;
+    pk_n = lconn[slot];
+    c0_n = coef_t[slot];
+    if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
+  }
+  for (; s < s1; s += 4) {
+    const uint4 pk = pk_n;
+    const T c0 = c0_n, c1 = c1_n;
+    {  // prefetch this wave's next step (clamped to the current one)
+      const int64_t slot = int64_t(s + 4 < s1 ? s + 4 : s) * kLanes + lane;
+      pk_n = lconn[slot];
+      c0_n = coef_t[slot];
+      if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
+    }
+    if (pk.x == 0xffffffffu) continue;  // empty lane
+    const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16),
+                       int(pk.z & 0xffff), int(pk.z >> 16), int(pk.w & 0xffff), int(pk.w >> 16)};
+    T X[3][8], u[DPN][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const T *r = sR + lc[a];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) X[k][a] = r[size_t(k) * max_nodes];
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(3 + j) * max_nodes];
+    }
+    if constexpr (DPN == 1) {
+      T v[8];
+      laplace_element<T>(X, u[0], c0, v);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) acc_add<T, LDS_ATOMIC>(&myV[lc[a]], v[a]);
+    } else {
+      T v[3][8];
+      elasticity_element<T>(X, u, c0, c1, v);
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc_add<T, LDS_ATOMIC>(&myV[j * max_nodes + lc[a]], v[j][a]);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < nm; i += 256) {
+    const uint32_t raw = nodes[n0 + i];
+    if (raw & kFixedBit) continue;  // y = x written by the reset kernel
+    const int64_t gg = raw & kIdMask;
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) {
+      const size_t o = size_t(j) * max_nodes + i, cs = size_t(DPN) * max_nodes;
+      const T v = (sV[o] + sV[cs + o]) + (sV[2 * cs + o] + sV[3 * cs + o]);
+      if (raw & kSharedBit)
+        gbl_add(&y[gg * DPN + j], v);
+      else
+        y[gg * DPN + j] = v;
     }
   }
 }
@@ -336,6 +458,12 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   return Q1_OK;
 }
 
+// LDS of the block-staged variant: node records, then four accumulator copies
+size_t block_lds_bytes(const Op &op) {
+  const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
+  return size_t(op.tiles.max_nodes) * rb * size_t(3 + op.physics + 4 * op.physics);
+}
+
 template <typename T, int DPN>
 int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
   const TileMap &tm = op.tiles;
@@ -344,9 +472,12 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   if (tm.n_reset > 0)
     hipLaunchKernelGGL((k_reset_nodes<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
                        s, tm.n_reset, tm.reset, op.mask, x, y, stop);
-  const size_t lds = size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
-  auto kern = tm.lds_atomic ? k_apply_tile<T, DPN, true> : k_apply_tile<T, DPN, false>;
-  hipLaunchKernelGGL(kern, dim3(tm.n_tiles), dim3(kLanes), lds, s, tm.max_nodes, op.n_nodes,
+  const bool block = op.variant == Q1_V_BLOCK;
+  const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
+  auto kern = block ? (tm.lds_atomic ? k_apply_block<T, DPN, true> : k_apply_block<T, DPN, false>)
+                    : (tm.lds_atomic ? k_apply_tile<T, DPN, true> : k_apply_tile<T, DPN, false>);
+  hipLaunchKernelGGL(kern, dim3(tm.n_tiles), dim3(block ? 256 : kLanes), lds, s, tm.max_nodes,
+                     op.n_nodes,
                      tm.node_ptr, tm.nodes, tm.tile_step,
                      reinterpret_cast<const uint4 *>(tm.lconn),
                      static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
@@ -363,15 +494,39 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
 static int tile_layers(const Op &op) { return op.physics == 1 ? 4 : 2; }
 static int tile_patch_x(const Op &) { return 32; }
 
+// Block-staged tiles: 16 x 4 elements per layer (one wavefront step), 8 layers
+// for scalar problems and 4 for elasticity (LDS); Q1_BLOCK_SHAPE="px,py,layers"
+// overrides the shape.
+static void block_shape(const Op &op, int &px, int &py, int &layers) {
+  px = 16;
+  py = 4;
+  layers = op.physics == 1 ? 8 : 4;
+  if (const char *e = std::getenv("Q1_BLOCK_SHAPE")) {
+    int a = 0, b = 0, c = 0;
+    if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a > 0 && b > 0 && c > 0) {
+      px = a;
+      py = b;
+      layers = c;
+    }
+  }
+}
+
 int build_tiles(Op &op, hipStream_t s) {
   Q1_CHECK(op.n_elems > 0, Q1_EUNSUPPORTED, "LDS-tile variant needs at least one element");
-  const int layers = tile_layers(op);
-  const int px = tile_patch_x(op), py = kLanes / px;
+  int px, py, layers;
+  if (op.variant == Q1_V_BLOCK) {
+    block_shape(op, px, py, layers);
+  } else {
+    layers = tile_layers(op);
+    px = tile_patch_x(op);
+    py = kLanes / px;
+  }
   int rc = op.dtype == Q1_F64 ? build_tiles_t<double>(op, s, px, py, layers)
                               : build_tiles_t<float>(op, s, px, py, layers);
   if (rc) return rc;
-  const size_t lds = size_t(op.tiles.max_nodes) *
-                     (op.physics * (op.dtype == Q1_F64 ? 8 : 4) + 4);
+  const size_t lds = op.variant == Q1_V_BLOCK
+                         ? block_lds_bytes(op)
+                         : size_t(op.tiles.max_nodes) * (op.physics * (op.dtype == Q1_F64 ? 8 : 4) + 4);
   Q1_CHECK(lds <= 64 * 1024, Q1_EUNSUPPORTED, "tile needs %zu B of LDS", lds);
   return Q1_OK;
 }

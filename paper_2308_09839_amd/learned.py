@@ -155,7 +155,7 @@ class Trainer:
 
 
 def evaluate(net: UNet, n: int, seeds, rtol: float = 1e-8, sigma: float = 2.0,
-             safeguard_m: int = 50, omega: float | None = 0.6, log=print):
+             safeguard_m: int = 50, omega: float | None = 0.6, trunc_m: int = 1, log=print):
     """Flexible PCG with the network against Jacobi-PCG on held-out fields:
     iterations and wall time (every network inference included).  omega:
     damping of the two-level form's Jacobi smoothing, None for z = N(r)."""
@@ -172,10 +172,10 @@ def evaluate(net: UNet, n: int, seeds, rtol: float = 1e-8, sigma: float = 2.0,
         t0 = time.perf_counter()
         sj = q1_pcg(P.op, Q1_PC_JACOBI, P.b, x, rtol, 100000)
         tj = time.perf_counter() - t0
-        q1_fpcg(P.op, pc, P.b, x, rtol, 5, safeguard_m)  # warm-up
+        q1_fpcg(P.op, pc, P.b, x, rtol, 5, safeguard_m, trunc_m=trunc_m)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sn = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m)
+        sn = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m, trunc_m=trunc_m)
         tn = time.perf_counter() - t0
         rows.append({"seed": seed, "jacobi_iters": sj["iters"], "jacobi_s": tj,
                      "jacobi_true_rel_res": sj["true_rel_res"], "nn_iters": sn["iters"],

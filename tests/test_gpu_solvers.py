@@ -153,6 +153,33 @@ def test_fpcg_with_jacobi_equals_pcg(q1, orc):
     assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
 
 
+@pytest.mark.parametrize("m", [2, 8])
+def test_fcg_with_jacobi_equals_pcg(q1, orc, m):
+    """For a fixed SPD preconditioner the extra orthogonalisations of FCG(m)
+    vanish: the iterates are the PCG iterates."""
+    import torch
+    print(f"\n[fcg({m}) = pcg]", flush=True)
+    pr = problem(1, (12, 10, 8), 0.1, 73, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 73)
+    op = make_op(pr, 0, 0)
+    J = q1.q1_jacobi_create(op)
+    for k in (1, 3, 12):
+        bd = dev(b, torch.float64)
+        xd = torch.empty_like(bd)
+        st = q1.q1_fcg(op, J, bd, xd, 0.0, k, trunc_m=m)
+        ref = orc.pcg(A, b, rtol=0.0, maxit=k)
+        assert st["iters"] == k and st["fallback_at"] == -1
+        assert np.linalg.norm(xd.cpu().numpy() - ref.x) <= 1e-10 * np.linalg.norm(ref.x), k
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    st = q1.q1_fcg(op, J, bd, xd, 1e-8, 5000, trunc_m=m)
+    assert st["status"] == 0
+    assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
+    with pytest.raises(q1.Q1Error):
+        q1.q1_fcg(op, J, bd, xd, 1e-8, 10, trunc_m=9)
+
+
 def test_fpcg_safeguard_fallback(q1, orc):
     import torch
     print("\n[fpcg safeguard]", flush=True)
