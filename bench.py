@@ -23,6 +23,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per apply measured with FETCH_SIZE and WRITE_SIZE (each scaled by what the counter
+# reads for a plain 256 MB device copy: x2 and x1), keyed by (variant, dtype, elements per
+# edge) of the kernel they were taken on; profiles/laplace128_fp64_apply_counters.md.  A kernel
+# changed since its counters were taken gets no entry (traffic null).
+MEASURED_TRAFFIC = {(3, 0, 128): 176.5e6}
 FP64_PEAK_TFS = 78.6
 
 
@@ -215,7 +220,7 @@ def bench_batched(q1, si, n, seed, args):
         k = si.field_lognormal(m ** 3, 0.0, 1.0, s3 + 1000 * i)[None]
         mask = si.face_mask(m, m, m, "z0")
         pr = dict(xyz=xyz, conn=conn, coef=k, mask=mask)
-        ops.append(q1.q1_op_create(1, 0, 0, *upload(pr, 0)))
+        ops.append(q1.q1_op_create(1, 0, 3, *upload(pr, 0)))  # one-wave tiles
         nn = xyz.shape[1]
         ndof += nn
         row = []
@@ -302,7 +307,7 @@ def bench_learned(q1, si, n, seed, args):
     tr = Lm.Trainer(net, data, B, seed=1)
     hist, t_train = tr.train(args.nn_steps, lr=1e-3, log=quiet, log_every=100)
     rows = Lm.evaluate(net, n4, [Lm.EVAL_SEED0 + j for j in range(args.nn_eval)], omega=0.6,
-                       log=quiet)
+                       trunc_m=8, log=quiet)
     jt = sum(r["jacobi_s"] for r in rows) / len(rows)
     nt = sum(r["nn_s"] for r in rows) / len(rows)
     res.update({"nn_pairs": int(data["r"].shape[0]), "nn_train_steps": args.nn_steps,
@@ -326,8 +331,8 @@ def main() -> int:
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 atomic, 3 LDS tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
-    ap.add_argument("--nn-fields", type=int, default=24, help="training fields of the learned leg")
-    ap.add_argument("--nn-steps", type=int, default=400, help="Adam steps of the learned leg")
+    ap.add_argument("--nn-fields", type=int, default=64, help="training fields of the learned leg")
+    ap.add_argument("--nn-steps", type=int, default=3000, help="Adam steps of the learned leg")
     ap.add_argument("--nn-eval", type=int, default=2, help="held-out fields of the learned leg")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MB (counter calibration)")
@@ -441,7 +446,7 @@ def main() -> int:
                    "n_elems": n ** 3, "n_dof": ndof, "variant": info["variant"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": MEASURED_TRAFFIC.get((info["variant"], 0, n)),
                      "algorithmic_bytes_per_apply": alg_bytes},
         "cpu_baseline": cpu,
         "extra": extras,

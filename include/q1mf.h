@@ -98,7 +98,8 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
  *   BLOCK    larger tiles, one workgroup of four wavefronts each: the tile's
  *            node records (coordinates, input) are staged in LDS once,
  *            per-wavefront LDS accumulators added in a fixed order;
- *   AUTO     the fastest measured strategy for the operator;
+ *   AUTO     the fastest measured strategy: BLOCK, else LDS_TILE when the tile
+ *            does not fit in LDS, else ATOMIC;
  *   CSR      the assembled matrix (made by q1_csr_create only). */
 enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_LDS_TILE = 3, Q1_V_CSR = 4, Q1_V_BLOCK = 5 };
 
@@ -222,7 +223,7 @@ int q1_mpcg(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rto
             double delta, int maxit, q1_stats *st, void *stream);
 
 /* Batched persistent Jacobi-PCG: nprob independent scalar-Laplace problems
- * (FP64 operators created with Q1_V_LDS_TILE or AUTO), each with nrhs
+ * (FP64 operators created with Q1_V_LDS_TILE), each with nrhs
  * right-hand sides (1..4), solved by ONE cooperative kernel launch.  b_d and
  * x_d hold nprob*nrhs device vectors (problem-major, FP64); st, if not NULL,
  * nprob*nrhs records.  Each problem gets a share of the co-resident

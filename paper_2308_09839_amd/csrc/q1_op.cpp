@@ -66,8 +66,8 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
   Q1_CHECK(op, Q1_ENOMEM, "q1_op_create: out of host memory");
   op->physics = physics;
   op->dtype = dtype;
-  // AUTO: the LDS-tiled apply (fastest measured), else the atomic one
-  op->variant = variant == Q1_V_AUTO ? (n_elems > 0 ? Q1_V_LDS_TILE : Q1_V_ATOMIC) : variant;
+  // AUTO: the block-staged tiles (fastest measured), else the one-wave tiles, else atomics
+  op->variant = variant == Q1_V_AUTO ? (n_elems > 0 ? Q1_V_BLOCK : Q1_V_ATOMIC) : variant;
   op->n_nodes = n_nodes;
   op->n_elems = n_elems;
   op->xyz = xyz_d;
@@ -82,6 +82,11 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
   }
   if (op->variant == Q1_V_LDS_TILE || op->variant == Q1_V_BLOCK) {
     rc = build_tiles(*op, static_cast<hipStream_t>(stream));
+    if (rc && variant == Q1_V_AUTO && rc == Q1_EUNSUPPORTED && op->variant == Q1_V_BLOCK) {
+      free_tiles(*op);  // tiles too large for LDS: one-wave tiles
+      op->variant = Q1_V_LDS_TILE;
+      rc = build_tiles(*op, static_cast<hipStream_t>(stream));
+    }
     if (rc) {
       free_tiles(*op);
       if (variant == Q1_V_AUTO && rc == Q1_EUNSUPPORTED) {

@@ -38,7 +38,7 @@ def rhs_set(pr, seed, nrhs):
 
 def run(q1, probs, bs, rtol, maxit):
     import torch
-    ops = [make_op(pr, 0, 0) for pr in probs]
+    ops = [make_op(pr, 0, 3) for pr in probs]  # one-wave tile maps
     bd = [[dev(b, torch.float64) for b in row] for row in bs]
     xd = [[torch.empty_like(b) for b in row] for row in bd]
     st = q1.q1_batched_pcg(ops, bd, xd, rtol, maxit)
