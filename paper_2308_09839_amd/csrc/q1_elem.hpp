@@ -47,7 +47,7 @@ __device__ __forceinline__ float rcp(float d) {
 
 // nodal -> unscaled modal (in place)
 template <typename T>
-__device__ __forceinline__ void butterfly_fwd(T v[8]) {
+__host__ __device__ __forceinline__ void butterfly_fwd(T v[8]) {
 #pragma unroll
   for (int a = 0; a < 8; a += 2) {
     T s = v[a] + v[a + 1], d = v[a + 1] - v[a];
@@ -121,7 +121,7 @@ __device__ __forceinline__ T dot3(const T a[3], const T b[3]) {
 // Coordinates are affine images of the reference cube (a parallelepiped)
 // exactly when the bilinear and trilinear coordinate modes vanish.
 template <typename T>
-__device__ __forceinline__ bool is_affine(const T X[3][8]) {
+__host__ __device__ __forceinline__ bool is_affine(const T X[3][8]) {
   bool z = true;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -207,6 +207,41 @@ __device__ __forceinline__ void laplace_element(T X[3][8], const T u_in[8], T k,
     w[4] = r0; w[5] += r1; w[6] += r2; w[7] += r3;
     w[0] = T(0);
   }
+  butterfly_bwd(w);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) v[a] = w[a];
+}
+
+// Scalar Laplace on an element already known to be a parallelepiped (the
+// bilinear and trilinear coordinate modes vanish, checked once at set-up):
+// the constant Jacobian comes from the three edges at corner 0, E_c = X_c - X_0
+// for c = 1, 2, 4 (J' = 4 E), so D = k / (16 det E) adj(E) adj(E)^T and the
+// modal action is the closed form of laplace_element's affine branch.  Reads
+// corners 0, 1, 2, 4 of X only.
+template <typename T>
+__device__ __forceinline__ void laplace_element_parallelepiped(const T X[3][8], const T u_in[8],
+                                                               T k, T v[8]) {
+  T u[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) u[a] = u_in[a];
+  butterfly_fwd(u);
+  const T E1[3] = {X[0][1] - X[0][0], X[1][1] - X[1][0], X[2][1] - X[2][0]};
+  const T E2[3] = {X[0][2] - X[0][0], X[1][2] - X[1][0], X[2][2] - X[2][0]};
+  const T E4[3] = {X[0][4] - X[0][0], X[1][4] - X[1][0], X[2][4] - X[2][0]};
+  T a0[3], a1[3], a2[3];
+  cross(E2, E4, a0); cross(E4, E1, a1); cross(E1, E2, a2);
+  const T s = k * rcp(T(16) * dot3(E1, a0));
+  const T D00 = s * dot3(a0, a0), D01 = s * dot3(a0, a1), D02 = s * dot3(a0, a2);
+  const T D11 = s * dot3(a1, a1), D12 = s * dot3(a1, a2), D22 = s * dot3(a2, a2);
+  T w[8];
+  w[0] = T(0);
+  w[1] = D00 * u[1] + D01 * u[2] + D02 * u[4];
+  w[2] = D01 * u[1] + D11 * u[2] + D12 * u[4];
+  w[4] = D02 * u[1] + D12 * u[2] + D22 * u[4];
+  w[3] = C<T>::third * ((D00 + D11) * u[3] + D02 * u[6] + D12 * u[5]);
+  w[5] = C<T>::third * ((D00 + D22) * u[5] + D01 * u[6] + D12 * u[3]);
+  w[6] = C<T>::third * ((D11 + D22) * u[6] + D01 * u[5] + D02 * u[3]);
+  w[7] = C<T>::ninth * (D00 + D11 + D22) * u[7];
   butterfly_bwd(w);
 #pragma unroll
   for (int a = 0; a < 8; ++a) v[a] = w[a];

@@ -41,6 +41,7 @@ struct TileMap {
   int64_t n_reset = 0;            // shared or Dirichlet nodes, reset before each apply
   int32_t *reset = nullptr;
   bool lds_atomic = false;        // corners collide within a step: accumulate with LDS atomics
+  uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
   size_t bytes = 0;
 };
 

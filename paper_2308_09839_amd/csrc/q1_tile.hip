@@ -176,13 +176,71 @@ __global__ __launch_bounds__(64) void k_apply_tile(
 // corners from LDS instead of gathering them from memory.  Wave w takes the
 // tile's steps w, w + 4, ... and accumulates into its own LDS copy; the copies
 // are added in a fixed order when the tile's nodes are written.
+// One wave's steps of a tile: corners from the staged records, element product,
+// accumulation into the wave's LDS copy.  PAR: every element is known to be a
+// parallelepiped (scalar problems), so only corners 0, 1, 2, 4 give geometry.
+template <typename T, int DPN, bool LDS_ATOMIC, bool PAR>
+__device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nodes,
+                                            const T *__restrict__ sR, T *__restrict__ myV,
+                                            const uint4 *__restrict__ lconn,
+                                            const T *__restrict__ coef_t, int64_t coef_stride) {
+  uint4 pk_n = make_uint4(0xffffffffu, 0u, 0u, 0u);
+  T c0_n = T(0), c1_n = T(0);
+  if (s < s1) {
+    const int64_t slot = int64_t(s) * kLanes + lane;
+    pk_n = lconn[slot];
+    c0_n = coef_t[slot];
+    if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
+  }
+  for (; s < s1; s += 4) {
+    const uint4 pk = pk_n;
+    const T c0 = c0_n, c1 = c1_n;
+    {  // prefetch this wave's next step (clamped to the current one)
+      const int64_t slot = int64_t(s + 4 < s1 ? s + 4 : s) * kLanes + lane;
+      pk_n = lconn[slot];
+      c0_n = coef_t[slot];
+      if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
+    }
+    if (pk.x == 0xffffffffu) continue;  // empty lane
+    const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16),
+                       int(pk.z & 0xffff), int(pk.z >> 16), int(pk.w & 0xffff), int(pk.w >> 16)};
+    T X[3][8], u[DPN][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const T *r = sR + lc[a];
+      if (!PAR || a == 0 || a == 1 || a == 2 || a == 4) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k][a] = r[size_t(k) * max_nodes];
+      }
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(3 + j) * max_nodes];
+    }
+    if constexpr (DPN == 1) {
+      T v[8];
+      if constexpr (PAR)
+        laplace_element_parallelepiped<T>(X, u[0], c0, v);
+      else
+        laplace_element<T>(X, u[0], c0, v);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) acc_add<T, LDS_ATOMIC>(&myV[lc[a]], v[a]);
+    } else {
+      T v[3][8];
+      elasticity_element<T>(X, u, c0, c1, v);
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc_add<T, LDS_ATOMIC>(&myV[j * max_nodes + lc[a]], v[j][a]);
+    }
+  }
+}
+
 template <typename T, int DPN, bool LDS_ATOMIC>
 __global__ __launch_bounds__(256) void k_apply_block(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
     const uint4 *__restrict__ lconn, const T *__restrict__ coef_t, int64_t coef_stride,
     const T *__restrict__ xyz, const T *__restrict__ x, T *__restrict__ y,
-    const int *__restrict__ stop) {
+    const int *__restrict__ stop, const uint8_t *__restrict__ tile_affine) {
   if (stop && *stop) return;
   constexpr int NR = 3 + DPN;  // x, y, z, u[DPN], stored field by field
   constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
@@ -226,50 +284,12 @@ __global__ __launch_bounds__(256) void k_apply_block(
   }
   __syncthreads();
   T *myV = sV + size_t(w) * DPN * max_nodes;
-  int s = s0 + w;
-  uint4 pk_n = make_uint4(0xffffffffu, 0u, 0u, 0u);
-  T c0_n = T(0), c1_n = T(0);
-  if (s < s1) {
-    const int64_t slot = int64_t(s) * kLanes + lane;
-    pk_n = lconn[slot];
-    c0_n = coef_t[slot];
-    if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
-  }
-  for (; s < s1; s += 4) {
-    const uint4 pk = pk_n;
-    const T c0 = c0_n, c1 = c1_n;
-    {  // prefetch this wave's next step (clamped to the current one)
-      const int64_t slot = int64_t(s + 4 < s1 ? s + 4 : s) * kLanes + lane;
-      pk_n = lconn[slot];
-      c0_n = coef_t[slot];
-      if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
-    }
-    if (pk.x == 0xffffffffu) continue;  // empty lane
-    const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16),
-                       int(pk.z & 0xffff), int(pk.z >> 16), int(pk.w & 0xffff), int(pk.w >> 16)};
-    T X[3][8], u[DPN][8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const T *r = sR + lc[a];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) X[k][a] = r[size_t(k) * max_nodes];
-#pragma unroll
-      for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(3 + j) * max_nodes];
-    }
-    if constexpr (DPN == 1) {
-      T v[8];
-      laplace_element<T>(X, u[0], c0, v);
-#pragma unroll
-      for (int a = 0; a < 8; ++a) acc_add<T, LDS_ATOMIC>(&myV[lc[a]], v[a]);
-    } else {
-      T v[3][8];
-      elasticity_element<T>(X, u, c0, c1, v);
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc_add<T, LDS_ATOMIC>(&myV[j * max_nodes + lc[a]], v[j][a]);
-    }
-  }
+  if (DPN == 1 && tile_affine[tile])
+    block_steps<T, DPN, LDS_ATOMIC, true>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+                                          coef_stride);
+  else
+    block_steps<T, DPN, LDS_ATOMIC, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+                                           coef_stride);
   __syncthreads();
   for (int i = tid; i < nm; i += 256) {
     const uint32_t raw = nodes[n0 + i];
@@ -296,6 +316,7 @@ struct HostTiles {
   std::vector<int32_t> step_elem;  // element of each lane slot (-1 = empty)
   int max_nodes = 0;
   bool corner_collision = false;   // two lanes of a step share a node at one corner
+  std::vector<uint8_t> tile_affine;  // every element of the tile is a parallelepiped
 };
 
 // Group elements into tiles and steps; record node lists and corner indices.
@@ -402,6 +423,16 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
       j = je;
     }
     H.tile_step.push_back(int32_t(H.step_elem.size() / kLanes));
+    bool aff = true;  // the kernel's own exact test, in the operator's precision
+    for (int64_t k = tb[t]; k < tb[t + 1] && aff; ++k) {
+      T X[3][8];
+      for (int r = 0; r < 3; ++r) {
+        for (int a = 0; a < 8; ++a) X[r][a] = xyz[r * nn + conn[a * ne + order[k]]];
+        butterfly_fwd(X[r]);
+      }
+      aff = is_affine(X);
+    }
+    H.tile_affine.push_back(aff ? 1 : 0);
     for (int32_t g : list) local[g] = -1;
   }
   return Q1_OK;
@@ -450,7 +481,8 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   T *coef_dev = nullptr;
   if ((rc = up(&tm.node_ptr, H.node_ptr)) || (rc = up(&tm.nodes, H.nodes)) ||
       (rc = up(&tm.tile_step, H.tile_step)) || (rc = up(&tm.lconn, H.lconn)) ||
-      (rc = up(&tm.reset, H.reset)) || (rc = up(&coef_dev, coef_t)))
+      (rc = up(&tm.reset, H.reset)) || (rc = up(&coef_dev, coef_t)) ||
+      (rc = up(&tm.tile_affine, H.tile_affine)))
     return rc;
   tm.coef_t = coef_dev;
   return Q1_OK;
@@ -472,9 +504,18 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
                        s, tm.n_reset, tm.reset, op.mask, x, y, stop);
   const bool block = op.variant == Q1_V_BLOCK;
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
-  auto kern = block ? (tm.lds_atomic ? k_apply_block<T, DPN, true> : k_apply_block<T, DPN, false>)
-                    : (tm.lds_atomic ? k_apply_tile<T, DPN, true> : k_apply_tile<T, DPN, false>);
-  hipLaunchKernelGGL(kern, dim3(tm.n_tiles), dim3(block ? 256 : kLanes), lds, s, tm.max_nodes,
+  if (block) {
+    auto kb = tm.lds_atomic ? k_apply_block<T, DPN, true> : k_apply_block<T, DPN, false>;
+    hipLaunchKernelGGL(kb, dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes, op.n_nodes,
+                       tm.node_ptr, tm.nodes, tm.tile_step,
+                       reinterpret_cast<const uint4 *>(tm.lconn),
+                       static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
+                       static_cast<const T *>(op.xyz), x, y, stop, tm.tile_affine);
+    Q1_HIP(hipGetLastError());
+    return Q1_OK;
+  }
+  auto kern = tm.lds_atomic ? k_apply_tile<T, DPN, true> : k_apply_tile<T, DPN, false>;
+  hipLaunchKernelGGL(kern, dim3(tm.n_tiles), dim3(kLanes), lds, s, tm.max_nodes,
                      op.n_nodes,
                      tm.node_ptr, tm.nodes, tm.tile_step,
                      reinterpret_cast<const uint4 *>(tm.lconn),
@@ -492,13 +533,14 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
 static int tile_layers(const Op &op) { return op.physics == 1 ? 4 : 2; }
 static int tile_patch_x(const Op &) { return 32; }
 
-// Block-staged tiles: 16 x 8 x 4 elements for scalar problems (two wavefront
-// steps per layer; measured on 128^3 FP64: 60.0 us against 61.5 for 16x4x8,
-// 70.3 for 8x8x8 and 73.6 for 32x2x8) and 16 x 4 x 4 for elasticity (LDS);
-// Q1_BLOCK_SHAPE="px,py,layers" overrides the shape.
+// Block-staged tiles: 32 x 4 x 4 elements for scalar problems (two wavefront
+// steps per layer; measured on 128^3: FP64 58.8 us and FP32 41.2 us, against
+// 62.0 / 45.2 for 16x8x4, 64.0 / 47.3 for 16x4x8 and 71.6 / 46.0 for 16x16x2)
+// and 16 x 4 x 4 for elasticity (LDS); Q1_BLOCK_SHAPE="px,py,layers"
+// overrides the shape.
 static void block_shape(const Op &op, int &px, int &py, int &layers) {
-  px = 16;
-  py = op.physics == 1 ? 8 : 4;
+  px = op.physics == 1 ? 32 : 16;
+  py = 4;
   layers = 4;
   if (const char *e = std::getenv("Q1_BLOCK_SHAPE")) {
     int a = 0, b = 0, c = 0;
@@ -540,7 +582,7 @@ int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *
 
 void free_tiles(Op &op) {
   TileMap &t = op.tiles;
-  void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset, t.coef_t};
+  void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset, t.coef_t, t.tile_affine};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   t = TileMap{};
