@@ -308,7 +308,7 @@ def bench_learned(q1, si, n, seed, args):
     tr = Lm.Trainer(net, data, B, seed=1)
     hist, t_train = tr.train(args.nn_steps, lr=1e-3, log=quiet, log_every=100)
     rows = Lm.evaluate(net, n4, [Lm.EVAL_SEED0 + j for j in range(args.nn_eval)], omega=0.6,
-                       trunc_m=8, log=quiet)
+                       trunc_m=8, smoothing_baseline=True, log=quiet)
     jt = sum(r["jacobi_s"] for r in rows) / len(rows)
     nt = sum(r["nn_s"] for r in rows) / len(rows)
     res.update({"nn_pairs": int(data["r"].shape[0]), "nn_train_steps": args.nn_steps,
@@ -316,6 +316,7 @@ def bench_learned(q1, si, n, seed, args):
                 "nn_loss_last": hist[-1][1],
                 "nn_eval_jacobi_iters": [r["jacobi_iters"] for r in rows],
                 "nn_eval_fpcg_iters": [r["nn_iters"] for r in rows],
+                "nn_eval_smoothing_only_iters": [r["smoothing_iters"] for r in rows],
                 "nn_eval_jacobi_ms": round(jt * 1e3, 2), "nn_eval_fpcg_ms": round(nt * 1e3, 2),
                 "nn_eval_fpcg_true_rel_res": max(r["nn_true_rel_res"] for r in rows),
                 "nn_eval_fallback_at": [r["nn_fallback_at"] for r in rows],

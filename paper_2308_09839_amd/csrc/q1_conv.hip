@@ -53,7 +53,7 @@ __device__ __forceinline__ bf16x8 ld8(const bf16 *p) {
 constexpr int kZB = 4;                   // z-slices per wavefront tile (tile: 4 x 4 x kZB)
 constexpr int kMaxGroups = 27 * 96 / 8;  // largest K / 8 (96 input channels)
 
-template <int NB>  // NB = Cout / 16
+template <int NB>  // NB = 16-channel row blocks per wavefront (Cout / 16, or fewer when split)
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
   __shared__ int goff[kMaxGroups + 4];
   const PGrid g = a.g;
@@ -72,8 +72,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int TX = (g.W + 3) >> 2, TY = (g.H + 3) >> 2, TZ = (g.D + kZB - 1) / kZB;
   const int64_t ntiles = int64_t(g.B) * TZ * TY * TX;
-  if (wave >= ntiles) return;
-  int64_t t = wave;
+  const int nrg = a.cout / (16 * NB);  // row groups per tile, one wavefront each
+  if (wave >= ntiles * nrg) return;
+  const int rg = int(wave % nrg);
+  int64_t t = wave / nrg;
   const int tx = int(t % TX);
   t /= TX;
   const int ty = int(t % TY);
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
   const int vx = tx * 4 + (j & 3), vy = ty * 4 + (j >> 2), z0 = tz * kZB;
   const bf16 *xb = a.x + g.at(b, z0, vy, vx) * a.cin;
   const int zstep = g.Hp * g.Wp * a.cin;
-  const bf16 *wrow = a.wp + (size_t(kg) * a.cout + j) * 8;
+  const bf16 *wrow = a.wp + (size_t(kg) * a.cout + rg * NB * 16 + j) * 8;
   const int wstep = 4 * a.cout * 8;
   f32x4 acc[NB][kZB];
 #pragma unroll
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
     const int64_t vox = g.at(b, z, vy, vx);
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
-      const int c0 = r * 16 + kg * 4;
+      const int c0 = (rg * NB + r) * 16 + kg * 4;
       float v[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -225,19 +227,51 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWArgs a) {
   }
 }
 
-// out[k] = sum over c < nparts of part[c * n + k]: a block covers 64 consecutive k, its
-// four wavefronts add every fourth part, and the four sums are combined in a fixed order
-__global__ __launch_bounds__(256) void k_sum_parts(const float *__restrict__ part, int nparts,
-                                                   int64_t n, float *__restrict__ out) {
+// Fixed-order sums over parts: out[k] = sum_c part[c * n + k], in two stages.
+// Stage 1: block (kb, grp) adds the parts of group grp (kGrp consecutive parts)
+// for 64 consecutive k, its four wavefronts taking every fourth part, and
+// writes the group sum over the group's first part (read by no other block).
+// Stage 2 adds the group sums the same way.
+constexpr int kGrp = 64;
+
+__device__ __forceinline__ float sum4_fixed(float (&sh)[4][64], int lane, float v, int w) {
+  sh[w][lane] = v;
+  __syncthreads();
+  return (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts_grp(float *__restrict__ part, int nparts,
+                                                       int64_t n) {
+  __shared__ float sh[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t k = int64_t(blockIdx.x) * 64 + lane;
+  const int c0 = blockIdx.y * kGrp, c1 = min(nparts, c0 + kGrp);
+  float s = 0.f;
+  if (k < n)
+    for (int c = c0 + w; c < c1; c += 4) s += part[c * n + k];
+  const float t = sum4_fixed(sh, lane, s, w);
+  if (w == 0 && k < n) part[c0 * n + k] = t;
+}
+
+__global__ __launch_bounds__(256) void k_sum_groups(const float *__restrict__ part, int nparts,
+                                                    int64_t n, float *__restrict__ out) {
   __shared__ float sh[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t k = int64_t(blockIdx.x) * 64 + lane;
   float s = 0.f;
   if (k < n)
-    for (int c = w; c < nparts; c += 4) s += part[c * n + k];
-  sh[w][lane] = s;
-  __syncthreads();
-  if (w == 0 && k < n) out[k] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+    for (int c = w * kGrp; c < nparts; c += 4 * kGrp) s += part[c * n + k];
+  const float t = sum4_fixed(sh, lane, s, w);
+  if (w == 0 && k < n) out[k] = t;
+}
+
+// out = fixed-order sum of the nparts partial vectors of length n (part is overwritten)
+static int sum_parts(float *part, int nparts, int64_t n, float *out, hipStream_t s) {
+  const unsigned kb = unsigned((n + 63) / 64), ng = unsigned((nparts + kGrp - 1) / kGrp);
+  hipLaunchKernelGGL(k_sum_parts_grp, dim3(kb, ng), dim3(256), 0, s, part, nparts, n);
+  hipLaunchKernelGGL(k_sum_groups, dim3(kb), dim3(256), 0, s, part, nparts, n, out);
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
 }
 
 // ---- weight packing ----------------------------------------------------------------------
@@ -500,14 +534,28 @@ int conv_forward(const ConvArgs &a, hipStream_t s) {
            "conv: %d input channels", a.cin);
   const int64_t ntiles = int64_t(a.g.B) * ((a.g.D + kZB - 1) / kZB) * ((a.g.H + 3) / 4) *
                          ((a.g.W + 3) / 4);
-  const dim3 grid(unsigned((ntiles + 3) / 4)), block(256);
-  switch (a.cout) {
-    case 16: hipLaunchKernelGGL(k_conv_fwd<1>, grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_conv_fwd<2>, grid, block, 0, s, a); break;
-    case 48: hipLaunchKernelGGL(k_conv_fwd<3>, grid, block, 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_conv_fwd<4>, grid, block, 0, s, a); break;
-    case 96: hipLaunchKernelGGL(k_conv_fwd<6>, grid, block, 0, s, a); break;
-    default: return fail(Q1_EUNSUPPORTED, "conv: %d output channels (16, 32, 48, 64, 96)", a.cout);
+  // The coarsest grids have far fewer tiles than the GPU has SIMDs: give each
+  // wavefront one 16-channel row block (more waves, each input tile read once per
+  // block).  Measured at batch 1 on 68^3: the 17^3 level gains (64->64: 50.6 ->
+  // 33.4 us), the 34^3 level loses (96->32: 34.5 -> 50.5 us), hence 512 tiles.
+  const bool split = ntiles < 512;
+  auto launch = [&](auto kern, int nb) {
+    const int64_t waves = ntiles * (a.cout / (16 * nb));
+    hipLaunchKernelGGL(kern, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, s, a);
+  };
+  if (split) {
+    Q1_CHECK(a.cout % 16 == 0 && a.cout <= 96, Q1_EUNSUPPORTED, "conv: %d output channels",
+             a.cout);
+    launch(k_conv_fwd<1>, 1);
+  } else {
+    switch (a.cout) {
+      case 16: launch(k_conv_fwd<1>, 1); break;
+      case 32: launch(k_conv_fwd<2>, 2); break;
+      case 48: launch(k_conv_fwd<3>, 3); break;
+      case 64: launch(k_conv_fwd<4>, 4); break;
+      case 96: launch(k_conv_fwd<6>, 6); break;
+      default: return fail(Q1_EUNSUPPORTED, "conv: %d output channels (16, 32, 48, 64, 96)", a.cout);
+    }
   }
   Q1_HIP(hipGetLastError());
   return Q1_OK;
@@ -523,11 +571,9 @@ int conv_wgrad(ConvWArgs a, float *gw, float *gb, hipStream_t s) {
   const int64_t waves = int64_t(a.nchunks) * (a.cout / 16) * ((a.cin + 15) / 16);
   hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, s, a);
   const int64_t nk = int64_t(27) * a.cin_real * a.cout;
-  hipLaunchKernelGGL(k_sum_parts, g1(nk, 64), dim3(256), 0, s, a.part, a.nchunks, nk, gw);
-  hipLaunchKernelGGL(k_sum_parts, g1(a.cout, 64), dim3(256), 0, s, a.bpart, a.nchunks,
-                     int64_t(a.cout), gb);
   Q1_HIP(hipGetLastError());
-  return Q1_OK;
+  int rc = sum_parts(a.part, a.nchunks, nk, gw, s);
+  return rc ? rc : sum_parts(a.bpart, a.nchunks, int64_t(a.cout), gb, s);
 }
 
 int pack_forward(const float *W, int cin_real, int cin_pad, int cout, int ngroups_pad, bf16 *wp,
@@ -590,9 +636,8 @@ int head_forward(const bf16 *t, const PGrid &g, const float *wh, float *out, hip
 int head_backward(const float *dout, const bf16 *t, const PGrid &g, const float *wh, bf16 *gpre,
                   float *part, int nblk, float *gwh, hipStream_t s) {
   hipLaunchKernelGGL(k_head_bwd, dim3(nblk), dim3(kHB), 0, s, dout, t, g, wh, gpre, part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, nblk, int64_t(17), gwh);
   Q1_HIP(hipGetLastError());
-  return Q1_OK;
+  return sum_parts(part, nblk, int64_t(17), gwh, s);
 }
 
 int mse(const float *out, const float *tgt, const float *wgt, int64_t n, double *part, int nblk,

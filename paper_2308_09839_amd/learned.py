@@ -155,12 +155,16 @@ class Trainer:
 
 
 def evaluate(net: UNet, n: int, seeds, rtol: float = 1e-8, sigma: float = 2.0,
-             safeguard_m: int = 50, omega: float | None = 0.6, trunc_m: int = 1, log=print):
+             safeguard_m: int = 50, omega: float | None = 0.6, trunc_m: int = 1,
+             smoothing_baseline: bool = False, log=print):
     """Flexible PCG with the network against Jacobi-PCG on held-out fields:
     iterations and wall time (every network inference included).  omega:
-    damping of the two-level form's Jacobi smoothing, None for z = N(r)."""
+    damping of the two-level form's Jacobi smoothing, None for z = N(r).
+    smoothing_baseline: also run the same solver with the network's weights
+    set to zero (the two-level form without its learned correction)."""
     import torch
     rows = []
+    zero = torch.zeros(net.nparams, dtype=torch.float32, device="cuda") if smoothing_baseline else None
     for seed in seeds:
         P = Problem(n, seed, sigma)
         pc = UNetPrecond(net, n, n, n, P.k, P.mask)
@@ -177,10 +181,17 @@ def evaluate(net: UNet, n: int, seeds, rtol: float = 1e-8, sigma: float = 2.0,
         t0 = time.perf_counter()
         sn = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m, trunc_m=trunc_m)
         tn = time.perf_counter() - t0
-        rows.append({"seed": seed, "jacobi_iters": sj["iters"], "jacobi_s": tj,
-                     "jacobi_true_rel_res": sj["true_rel_res"], "nn_iters": sn["iters"],
-                     "nn_s": tn, "nn_true_rel_res": sn["true_rel_res"],
-                     "nn_status": sn["status"], "nn_fallback_at": sn["fallback_at"]})
+        row = {"seed": seed, "jacobi_iters": sj["iters"], "jacobi_s": tj,
+               "jacobi_true_rel_res": sj["true_rel_res"], "nn_iters": sn["iters"],
+               "nn_s": tn, "nn_true_rel_res": sn["true_rel_res"],
+               "nn_status": sn["status"], "nn_fallback_at": sn["fallback_at"]}
+        if zero is not None:
+            theta = net.get(0)
+            net.set_params(zero)
+            s0 = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m, trunc_m=trunc_m)
+            net.set_params(theta)
+            row["smoothing_iters"] = s0["iters"]
+        rows.append(row)
         log(f"eval seed {seed}: Jacobi-PCG {sj['iters']} it {tj * 1e3:.1f} ms | "
             f"NN-FPCG {sn['iters']} it {tn * 1e3:.1f} ms (fallback at {sn['fallback_at']})")
     return rows
