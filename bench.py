@@ -237,6 +237,10 @@ def bench_batched(q1, si, n, seed, args):
     st = q1.q1_batched_pcg(ops, bd, xd, 1e-8, 20000)
     t_batched = time.perf_counter() - t0
     iters = sum(s_["iters"] for s_ in st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stm = q1.q1_batched_mpcg(ops, bd, xd, 1e-8, 20000, 0.1)
+    t_mixed = time.perf_counter() - t0
     t0 = time.perf_counter()
     it_loop = 0
     for i in range(32):
@@ -247,7 +251,13 @@ def bench_batched(q1, si, n, seed, args):
             "batched_loop_pcg_s": round(t_loop, 4), "batched_total_iters": iters,
             "batched_loop_iters": it_loop, "batched_ndof_x4": 4 * ndof,
             "batched_all_converged": all(s_["status"] == 0 for s_ in st),
-            "batched_gdofs": round(4 * ndof * iters / 128 / st[0]["seconds"] / 1e9, 3)}
+            "batched_gdofs": round(4 * ndof * iters / 128 / st[0]["seconds"] / 1e9, 3),
+            "batched_mixed_s": round(t_mixed, 4),
+            "batched_mixed_kernel_s": round(stm[0]["seconds"], 4),
+            "batched_mixed_total_iters": sum(s_["iters"] for s_ in stm),
+            "batched_mixed_refreshes": sum(s_["outer_iters"] for s_ in stm),
+            "batched_mixed_all_converged": all(s_["status"] == 0 for s_ in stm),
+            "batched_mixed_max_true_rel_res": max(s_["rel_res"] for s_ in stm)}
 
 
 def unet_forward_flops(D: int, H: int, W: int) -> float:
@@ -333,6 +343,9 @@ def main() -> int:
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 atomic, 3 LDS tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated solver extras to run (csr, cg16, cg_elasticity96, "
+                         "learned64, batched32) or 'all'")
     ap.add_argument("--nn-fields", type=int, default=64, help="training fields of the learned leg")
     ap.add_argument("--nn-steps", type=int, default=3000, help="Adam steps of the learned leg")
     ap.add_argument("--nn-eval", type=int, default=2, help="held-out fields of the learned leg")
@@ -417,6 +430,8 @@ def main() -> int:
         for name, fn in (("csr", bench_csr), ("cg16", bench_cg16), ("cg_elasticity96", bench_ir96),
                          ("learned64", bench_learned),
                          ("batched32", bench_batched)):
+            if args.extras != "all" and name not in args.extras.split(","):
+                continue
             try:
                 log(f"[bench] {name}")
                 extras.update(fn(q1, si, n, seed, args))

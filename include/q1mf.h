@@ -234,6 +234,23 @@ int q1_mpcg(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rto
 int q1_batched_pcg(int nprob, q1_op *const *ops, int nrhs, const double *const *b_d,
                    double *const *x_d, double rtol, int maxit, q1_stats *st, void *stream);
 
+/* Mixed-precision form of q1_batched_pcg (same operators, one launch; the
+ * reliable-update scheme of q1_mpcg inside the persistent kernel).  Inside the one kernel the Krylov applies use FP32 copies of each
+ * operator's coordinates and coefficients and FP32 search directions p, q,
+ * while x, r and every dot product stay FP64.  When the recurrence residual
+ * of a right-hand side has fallen by the factor delta (0 < delta < 1, e.g.
+ * 0.1) since its last refresh, or below rtol/sqrt(2) relative to ||b||, or
+ * at maxit, the kernel recomputes r = b - A x with the FP64 operator and
+ * decides convergence on that true residual; otherwise the recurrences
+ * continue from it with p kept.  st[k].outer_iters counts the refreshes and
+ * st[k].rel_res is the true relative residual of the last refresh.  Extra
+ * device memory per problem: FP32 copies of the geometry and coefficients
+ * and nrhs*(2 FP32 + 1 FP64) vectors, allocated and freed by the call.
+ * Returns Q1_EINVAL for delta outside (0, 1); otherwise as q1_batched_pcg. */
+int q1_batched_mpcg(int nprob, q1_op *const *ops, int nrhs, const double *const *b_d,
+                    double *const *x_d, double rtol, double delta, int maxit, q1_stats *st,
+                    void *stream);
+
 /* ---- learned preconditioner --------------------------------------------------
  * The paper lists learned preconditioning only as an outlook beside its future
  * matrix-free preconditioners (Section 6) and fixes no network.  This library

@@ -17,7 +17,7 @@ from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32,
                    Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
-    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_trace", "q1_batched_pcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
+    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
     "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
@@ -333,6 +333,23 @@ def q1_batched_pcg(ops, b, x, rtol: float, maxit: int, stream=None) -> list[dict
     _solve_rc(lib().q1_batched_pcg(nprob, ctypes.cast(opa, VP), nrhs, ctypes.cast(ba, VP),
                                    ctypes.cast(xa, VP), rtol, maxit, ctypes.cast(st, VP),
                                    _stream(stream)))
+    return [s_.as_dict() for s_ in st]
+
+
+def q1_batched_mpcg(ops, b, x, rtol: float, maxit: int, delta: float = 0.1,
+                    stream=None) -> list[dict]:
+    """Mixed-precision batched PCG (FP32 applies and directions, FP64 x, r,
+    dots and true-residual refreshes), same layout as q1_batched_pcg."""
+    nprob = len(ops)
+    nrhs = len(b[0])
+    VP = ctypes.c_void_p
+    opa = (VP * nprob)(*[o.handle for o in ops])
+    ba = (VP * (nprob * nrhs))(*[_dptr(v) for row in b for v in row])
+    xa = (VP * (nprob * nrhs))(*[_dptr(v) for row in x for v in row])
+    st = (Q1Stats * (nprob * nrhs))()
+    _solve_rc(lib().q1_batched_mpcg(nprob, ctypes.cast(opa, VP), nrhs, ctypes.cast(ba, VP),
+                                    ctypes.cast(xa, VP), rtol, delta, maxit, ctypes.cast(st, VP),
+                                    _stream(stream)))
     return [s_.as_dict() for s_ in st]
 
 

@@ -98,3 +98,81 @@ def test_batched_full_workload(q1, orc):
         A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
         for c in range(4):
             assert orc.true_rel_res(A, xs[i][c], bs[i][c]) <= 1e-8 * (1 + 1e-3)
+
+
+# ---- mixed precision: FP32 applies and directions, FP64 x, r, dots and refreshes
+
+def run_mixed(q1, probs, bs, rtol, maxit, delta=0.1):
+    import torch
+    ops = [make_op(pr, 0, 3) for pr in probs]
+    bd = [[dev(b, torch.float64) for b in row] for row in bs]
+    xd = [[torch.empty_like(b) for b in row] for row in bd]
+    st = q1.q1_batched_mpcg(ops, bd, xd, rtol, maxit, delta)
+    return [[x.cpu().numpy() for x in row] for row in xd], st
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 4])
+def test_batched_mixed_meets_tolerance(q1, orc, nrhs):
+    """Convergence is decided on the FP64 true residual, so every solve meets
+    the tolerance under the oracle's operator; the reported residual is that
+    true residual, and the FP32 recurrences cost at most a few more
+    iterations than FP64 PCG."""
+    print(f"\n[batched mixed] nrhs={nrhs}", flush=True)
+    sizes = [4, 9, 6, 12, 3]
+    probs = [laplace_box(n, 700 + i) for i, n in enumerate(sizes)]
+    bs = [rhs_set(pr, 800 + i, nrhs) for i, pr in enumerate(probs)]
+    xs, st = run_mixed(q1, probs, bs, 1e-8, 5000)
+    for i, pr in enumerate(probs):
+        A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+        for c in range(nrhs):
+            s = st[i * nrhs + c]
+            ref = orc.pcg(A, bs[i][c], rtol=1e-8)
+            tr = orc.true_rel_res(A, xs[i][c], bs[i][c])
+            assert s["status"] == 0, (i, c, s)
+            assert tr <= 1e-8 * (1 + 1e-3), (i, c, tr)
+            assert abs(s["rel_res"] - tr) <= 1e-3 * tr + 1e-15, (s["rel_res"], tr)
+            assert s["outer_iters"] >= 1
+            assert s["iters"] <= 1.25 * ref.iters + 5, (s["iters"], ref.iters)
+
+
+def test_batched_mixed_zero_rhs_and_limit(q1, orc):
+    print("\n[batched mixed zero rhs / maxit]", flush=True)
+    probs = [laplace_box(4, 17), laplace_box(6, 18)]
+    bs = [[np.zeros(pr["xyz"].shape[1]), rhs_set(pr, 19, 1)[0]] for pr in probs]
+    xs, st = run_mixed(q1, probs, bs, 1e-8, 3)
+    for i, pr in enumerate(probs):
+        assert st[2 * i]["status"] == 0 and st[2 * i]["iters"] == 0
+        assert np.all(xs[i][0] == 0)
+        # three iterations cannot reach 1e-8: stopped at the limit after a true-residual refresh
+        A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+        s = st[2 * i + 1]
+        assert s["status"] == -4 and s["iters"] == 3 and s["outer_iters"] >= 1
+        tr = orc.true_rel_res(A, xs[i][1], bs[i][1])
+        assert abs(s["rel_res"] - tr) <= 1e-6 * tr
+
+
+def test_batched_mixed_bad_delta(q1):
+    import torch
+    pr = laplace_box(3, 1)
+    op = make_op(pr, 0, 3)
+    b = dev(rhs_set(pr, 2, 1)[0], torch.float64)
+    x = torch.empty_like(b)
+    for d in (0.0, 1.0, -0.5):
+        with pytest.raises(Exception):
+            q1.q1_batched_mpcg([op], [[b]], [[x]], 1e-8, 10, d)
+
+
+def test_batched_mixed_full_workload(q1, orc):
+    """32 problems with edges U{16..64}, 4 right-hand sides each, to 1e-8 in
+    the mixed form; every solution checked against the oracle's operator."""
+    print("\n[batched mixed full workload]", flush=True)
+    seed = si.seed_for(3)
+    sizes = si.batch_sizes(32, seed)
+    probs = [laplace_box(int(n), seed + 1000 * i) for i, n in enumerate(sizes)]
+    bs = [rhs_set(pr, seed + 2000 * i, 4) for i, pr in enumerate(probs)]
+    xs, st = run_mixed(q1, probs, bs, 1e-8, 20000)
+    assert all(s["status"] == 0 for s in st)
+    for i, pr in enumerate(probs):
+        A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+        for c in range(4):
+            assert orc.true_rel_res(A, xs[i][c], bs[i][c]) <= 1e-8 * (1 + 1e-3)
