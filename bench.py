@@ -398,7 +398,7 @@ def main() -> int:
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     extras = {}
     if not args.no_extras:
-        for v in (1, 3, 5):
+        for v in (1, 2, 3, 5):
             if v == info["variant"]:
                 continue
             opv = q1.q1_op_create(1, 0, v, *upload(pr, 0))

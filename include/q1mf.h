@@ -92,16 +92,24 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
 /* Scatter strategies of the apply (Section 3, third step):
  *   ATOMIC   one thread per element, global atomic adds (the paper's
  *            one-thread-per-element strategy, Section 6);
+ *   COLOR    one thread per element, elements split at set-up into colour
+ *            classes that share no node (greedy first-fit; 8 classes on a
+ *            lexicographic lattice); one launch per class with plain
+ *            read-add-write scatter, no atomics; connectivity and
+ *            coefficients are copied in class order (set-up synchronises);
+ *            Q1_EUNSUPPORTED if more than 64 classes would be needed;
  *   LDS_TILE element tiles, one wavefront each: corners gathered from memory,
  *            accumulation in LDS, global atomics only for nodes shared with
  *            other tiles;
  *   BLOCK    larger tiles, one workgroup of four wavefronts each: the tile's
  *            node records (coordinates, input) are staged in LDS once,
- *            per-wavefront LDS accumulators added in a fixed order;
+ *            accumulation into one LDS copy with LDS atomics (FP64) or into
+ *            per-wavefront copies added in a fixed order (FP32);
  *   AUTO     the fastest measured strategy: BLOCK, else LDS_TILE when the tile
  *            does not fit in LDS, else ATOMIC;
  *   CSR      the assembled matrix (made by q1_csr_create only). */
-enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_LDS_TILE = 3, Q1_V_CSR = 4, Q1_V_BLOCK = 5 };
+enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_COLOR = 2, Q1_V_LDS_TILE = 3, Q1_V_CSR = 4,
+       Q1_V_BLOCK = 5 };
 
 /* Create an operator over caller-owned device arrays.  The arrays are
  * referenced, not copied: they must stay valid and unchanged until

@@ -25,6 +25,7 @@ Q1_F64 = 0
 Q1_F32 = 1
 Q1_V_AUTO = 0
 Q1_V_ATOMIC = 1
+Q1_V_COLOR = 2
 Q1_V_LDS_TILE = 3
 Q1_V_CSR = 4
 Q1_V_BLOCK = 5

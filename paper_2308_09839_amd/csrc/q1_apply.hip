@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "q1_elem.hpp"
 #include "q1_internal.hpp"
@@ -83,6 +84,53 @@ __global__ __launch_bounds__(256) void k_apply_atomic(
       if (!fixed[a])
 #pragma unroll
         for (int j = 0; j < 3; ++j) atomic_add(&y[int64_t(nid[a]) * 3 + j], v[j][a]);
+  }
+}
+
+// One thread per element of one colour class [e0, e1) of the colour order: no
+// two elements of a class share a node, so the scatter is a plain
+// read-add-write; kernel boundaries order the classes.
+template <typename T, int DPN, bool MASKED>
+__global__ __launch_bounds__(256) void k_apply_color(
+    int64_t e0, int64_t e1, int64_t ne, int64_t nn, const T *__restrict__ xyz,
+    const int32_t *__restrict__ conn, const T *__restrict__ coef,
+    const uint8_t *__restrict__ mask, const T *__restrict__ x, T *__restrict__ y,
+    const int *__restrict__ stop) {
+  if (stop && *stop) return;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t e = e0 + int64_t(blk) * blockDim.x + threadIdx.x;
+  if (e >= e1) return;
+  int32_t nid[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) nid[a] = conn[a * ne + e];
+  T X[3][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + nid[a]];
+  bool fixed[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) fixed[a] = MASKED ? (mask[nid[a]] != 0) : false;
+  if constexpr (DPN == 1) {
+    T u[8], v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[a] = fixed[a] ? T(0) : x[nid[a]];
+    laplace_element<T>(X, u, coef[e], v);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!fixed[a]) y[nid[a]] += v[a];
+  } else {
+    T u[3][8], v[3][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * 3 + j];
+    elasticity_element<T>(X, u, coef[e], coef[ne + e], v);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!fixed[a])
+#pragma unroll
+        for (int j = 0; j < 3; ++j) y[int64_t(nid[a]) * 3 + j] += v[j][a];
   }
 }
 
@@ -188,6 +236,31 @@ int apply_atomic(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
 }
 
 template <typename T, int DPN>
+int apply_color(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
+  const T *x = static_cast<const T *>(xv);
+  T *y = static_cast<T *>(yv);
+  const int64_t ndof = op.n_nodes * DPN;
+  hipLaunchKernelGGL((k_init_masked<T, DPN>), dim3(grid_for(ndof, kBlock)), dim3(kBlock), 0, s,
+                     op.n_nodes, op.mask, x, y, stop);
+  const ColorMap &cm = op.colors;
+  const T *xyz = static_cast<const T *>(op.xyz);
+  const T *coef = static_cast<const T *>(cm.coef);
+  for (int c = 0; c < cm.n_colors; ++c) {
+    const int64_t e0 = cm.ptr[c], e1 = cm.ptr[c + 1];
+    if (e1 <= e0) continue;
+    const dim3 grid(grid_for(e1 - e0, kBlock));
+    if (op.mask)
+      hipLaunchKernelGGL((k_apply_color<T, DPN, true>), grid, dim3(kBlock), 0, s, e0, e1,
+                         op.n_elems, op.n_nodes, xyz, cm.conn, coef, op.mask, x, y, stop);
+    else
+      hipLaunchKernelGGL((k_apply_color<T, DPN, false>), grid, dim3(kBlock), 0, s, e0, e1,
+                         op.n_elems, op.n_nodes, xyz, cm.conn, coef, op.mask, x, y, stop);
+  }
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+template <typename T, int DPN>
 int diag_impl(Op &op, void *dv, hipStream_t s) {
   T *d = static_cast<T *>(dv);
   const int64_t ndof = op.n_nodes * DPN;
@@ -218,6 +291,12 @@ int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop)
                                : apply_atomic<double, 3>(op, x, y, s, stop);
       return op.physics == 1 ? apply_atomic<float, 1>(op, x, y, s, stop)
                              : apply_atomic<float, 3>(op, x, y, s, stop);
+    case Q1_V_COLOR:
+      if (op.dtype == Q1_F64)
+        return op.physics == 1 ? apply_color<double, 1>(op, x, y, s, stop)
+                               : apply_color<double, 3>(op, x, y, s, stop);
+      return op.physics == 1 ? apply_color<float, 1>(op, x, y, s, stop)
+                             : apply_color<float, 3>(op, x, y, s, stop);
     case Q1_V_LDS_TILE:
     case Q1_V_BLOCK:
       return launch_apply_tile(op, x, y, s, stop);
@@ -226,6 +305,64 @@ int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop)
     default:
       return fail(Q1_EUNSUPPORTED, "apply variant %d not available", op.variant);
   }
+}
+
+// Greedy first-fit colouring in element order: each element takes the lowest
+// colour not yet used by an element sharing one of its nodes (per-node
+// bitmasks of used colours).  On a lattice numbered lexicographically this
+// gives the 8 parity classes.  Connectivity and coefficients are copied in
+// colour order so that each class is read contiguously.
+int build_colors(Op &op, hipStream_t s) {
+  const int64_t ne = op.n_elems, nn = op.n_nodes;
+  const int ncoef = op.physics == 1 ? 1 : 2;
+  const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
+  Q1_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> conn(size_t(8) * ne);
+  std::vector<unsigned char> coef(size_t(ncoef) * ne * rb);
+  Q1_HIP(hipMemcpy(conn.data(), op.conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  Q1_HIP(hipMemcpy(coef.data(), op.coef, coef.size(), hipMemcpyDeviceToHost));
+  std::vector<uint64_t> used(nn, 0);
+  std::vector<int> color(ne);
+  int n_colors = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    uint64_t taken = 0;
+    for (int a = 0; a < 8; ++a) {
+      const int32_t g = conn[a * ne + e];
+      Q1_CHECK(g >= 0 && g < nn, Q1_EINVAL, "colouring: node id %d of element %lld out of range",
+               g, (long long)e);
+      taken |= used[g];
+    }
+    Q1_CHECK(~taken != 0, Q1_EUNSUPPORTED, "colouring needs more than 64 colours");
+    const int c = __builtin_ctzll(~taken);
+    color[e] = c;
+    n_colors = std::max(n_colors, c + 1);
+    for (int a = 0; a < 8; ++a) used[conn[a * ne + e]] |= uint64_t(1) << c;
+  }
+  ColorMap &cm = op.colors;
+  cm.n_colors = n_colors;
+  cm.ptr.assign(n_colors + 1, 0);
+  for (int64_t e = 0; e < ne; ++e) ++cm.ptr[color[e] + 1];
+  for (int c = 0; c < n_colors; ++c) cm.ptr[c + 1] += cm.ptr[c];
+  std::vector<int64_t> next(cm.ptr.begin(), cm.ptr.end() - 1);
+  std::vector<int32_t> pconn(conn.size());
+  std::vector<unsigned char> pcoef(coef.size());
+  for (int64_t e = 0; e < ne; ++e) {
+    const int64_t p = next[color[e]]++;
+    for (int a = 0; a < 8; ++a) pconn[a * ne + p] = conn[a * ne + e];
+    for (int k = 0; k < ncoef; ++k)
+      std::memcpy(&pcoef[(size_t(k) * ne + p) * rb], &coef[(size_t(k) * ne + e) * rb], rb);
+  }
+  Q1_HIP(hipMalloc(&cm.conn, pconn.size() * sizeof(int32_t)));
+  Q1_HIP(hipMalloc(&cm.coef, pcoef.size()));
+  Q1_HIP(hipMemcpy(cm.conn, pconn.data(), pconn.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  Q1_HIP(hipMemcpy(cm.coef, pcoef.data(), pcoef.size(), hipMemcpyHostToDevice));
+  return Q1_OK;
+}
+
+void free_colors(Op &op) {
+  if (op.colors.conn) (void)hipFree(op.colors.conn);
+  if (op.colors.coef) (void)hipFree(op.colors.coef);
+  op.colors = ColorMap{};
 }
 
 int launch_diag(Op &op, void *d, hipStream_t s) {

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "q1mf.h"
 
@@ -53,6 +54,14 @@ struct CsrData {
   void *val = nullptr;        // [nnz] of the operator's dtype
 };
 
+// Element colouring of the colour variant: elements of one colour share no node.
+struct ColorMap {
+  int n_colors = 0;
+  std::vector<int64_t> ptr;     // [n_colors+1] element ranges in colour order
+  int32_t *conn = nullptr;      // [8][n_elems] connectivity in colour order
+  void *coef = nullptr;         // [ncoef][n_elems] coefficients in colour order
+};
+
 struct Op {
   int physics = 1;  // DOF per node
   int dtype = Q1_F64;
@@ -66,6 +75,7 @@ struct Op {
   int num_cus = 256;
   TileMap tiles;
   CsrData csr;
+  ColorMap colors;
 };
 
 inline int xcd_count() { return 8; }
@@ -77,6 +87,8 @@ int launch_diag(Op &op, void *d, hipStream_t s);
 int build_tiles(Op &op, hipStream_t s);
 int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop);
 void free_tiles(Op &op);
+int build_colors(Op &op, hipStream_t s);
+void free_colors(Op &op);
 int csr_create(Op &op, hipStream_t s);
 int launch_spmv(const Op &op, const void *x, void *y, hipStream_t s, const int *stop);
 void free_csr(Op &op);

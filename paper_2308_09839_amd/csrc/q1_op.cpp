@@ -43,8 +43,8 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
   Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_ELASTICITY, Q1_EINVAL,
            "q1_op_create: physics must be 1 (Laplace) or 3 (elasticity), got %d", physics);
   Q1_CHECK(dtype == Q1_F64 || dtype == Q1_F32, Q1_EINVAL, "q1_op_create: bad dtype %d", dtype);
-  Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC || variant == Q1_V_LDS_TILE ||
-               variant == Q1_V_BLOCK,
+  Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC || variant == Q1_V_COLOR ||
+               variant == Q1_V_LDS_TILE || variant == Q1_V_BLOCK,
            Q1_EINVAL, "q1_op_create: bad variant %d", variant);
   Q1_CHECK(n_nodes > 0 && n_nodes < (int64_t(1) << 31) && n_elems >= 0 &&
                n_elems < (int64_t(1) << 31),
@@ -95,6 +95,14 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
         delete op;
         return rc;
       }
+    }
+  }
+  if (op->variant == Q1_V_COLOR && n_elems > 0) {
+    rc = build_colors(*op, static_cast<hipStream_t>(stream));
+    if (rc) {
+      free_colors(*op);
+      delete op;
+      return rc;
     }
   }
   *out = op;
@@ -150,6 +158,7 @@ int q1_op_destroy(q1_op *op) {
   if (!op) return Q1_OK;
   free_tiles(*op);
   free_csr(*op);
+  free_colors(*op);
   delete op;
   return Q1_OK;
 }
@@ -162,6 +171,7 @@ int q1_csr_create(q1_op **out, const q1_op *like, void *stream) {
   static_cast<Op &>(*op) = static_cast<const Op &>(*like);
   op->tiles = TileMap{};
   op->csr = CsrData{};
+  op->colors = ColorMap{};
   op->variant = Q1_V_CSR;
   const int rc = csr_create(*op, static_cast<hipStream_t>(stream));
   if (rc) {

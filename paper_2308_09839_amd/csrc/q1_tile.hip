@@ -174,24 +174,19 @@ __global__ __launch_bounds__(64) void k_apply_tile(
 // tile's node records (coordinates and input values; zero input on Dirichlet
 // nodes) are loaded once into LDS with bulk loads, so the element loop reads
 // corners from LDS instead of gathering them from memory.  Wave w takes the
-// tile's steps w, w + 4, ... and accumulates into its own LDS copy; the copies
-// are added in a fixed order when the tile's nodes are written.
+// tile's steps w, w + 4, ... and accumulates into LDS: in FP64 into one copy
+// shared by the four waves (LDS atomics), in FP32 into its own copy, the copies
+// being added in a fixed order when the tile's nodes are written.
 // One wave's steps of a tile: corners from the staged records, element product,
-// accumulation into the wave's LDS copy.  PAR: every element is known to be a
+// accumulation into LDS.  PAR: every element is known to be a
 // parallelepiped (scalar problems), so only corners 0, 1, 2, 4 give geometry.
 template <typename T, int DPN, bool LDS_ATOMIC, bool PAR>
 __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nodes,
                                             const T *__restrict__ sR, T *__restrict__ myV,
                                             const uint4 *__restrict__ lconn,
-                                            const T *__restrict__ coef_t, int64_t coef_stride) {
-  uint4 pk_n = make_uint4(0xffffffffu, 0u, 0u, 0u);
-  T c0_n = T(0), c1_n = T(0);
-  if (s < s1) {
-    const int64_t slot = int64_t(s) * kLanes + lane;
-    pk_n = lconn[slot];
-    c0_n = coef_t[slot];
-    if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
-  }
+                                            const T *__restrict__ coef_t, int64_t coef_stride,
+                                            uint4 pk_n, T c0_n, T c1_n) {
+  // pk_n, c0_n, c1_n: this wave's first step, loaded by the caller before staging
   for (; s < s1; s += 4) {
     const uint4 pk = pk_n;
     const T c0 = c0_n, c1 = c1_n;
@@ -234,7 +229,10 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
   }
 }
 
-template <typename T, int DPN, bool LDS_ATOMIC>
+// ONEACC: the four waves add into one LDS accumulator with LDS atomics (FP64,
+// where it frees LDS for a fourth resident block); otherwise each wave owns a
+// copy and the copies are summed in a fixed order.
+template <typename T, int DPN, bool LDS_ATOMIC, bool ONEACC>
 __global__ __launch_bounds__(256) void k_apply_block(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
@@ -246,18 +244,34 @@ __global__ __launch_bounds__(256) void k_apply_block(
   constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][max_nodes]
-  T *sV = sR + size_t(NR) * max_nodes;       // [4][DPN][max_nodes]
+  constexpr int NACC = ONEACC ? 1 : 4;
+  T *sV = sR + size_t(NR) * max_nodes;       // [NACC][DPN][max_nodes]
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int tile = xcd_block_t(blockIdx.x, gridDim.x);
   const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
   const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
+  // the wave's first step is requested before staging, so its latency overlaps it
+  uint4 pk0 = make_uint4(0xffffffffu, 0u, 0u, 0u);
+  T c00 = T(0), c10 = T(0);
+  if (s0 + w < s1) {
+    const int64_t slot = int64_t(s0 + w) * kLanes + lane;
+    pk0 = lconn[slot];
+    c00 = coef_t[slot];
+    if constexpr (DPN == 3) c10 = coef_t[coef_stride + slot];
+  }
   // stage the node records: all loads of a round are issued (unconditionally,
-  // at clamped indices) before any LDS write, so the round costs one latency
+  // at clamped indices) before any LDS write, so the round costs one latency.
+  // The first round's node words stay in registers for the write-back.
+  uint32_t keep[KN];
   for (int base = 0; base < nm; base += KN * 256) {
     uint32_t raw[KN];
     T rec[KN][NR];
 #pragma unroll
     for (int k = 0; k < KN; ++k) raw[k] = nodes[n0 + min(base + k * 256 + tid, nm - 1)];
+    if (base == 0) {
+#pragma unroll
+      for (int k = 0; k < KN; ++k) keep[k] = raw[k];
+    }
 #pragma unroll
     for (int k = 0; k < KN; ++k) {
       const int64_t g = raw[k] & kIdMask;
@@ -278,33 +292,40 @@ __global__ __launch_bounds__(256) void k_apply_block(
         for (int j = 0; j < DPN; ++j)
           sR[size_t(3 + j) * max_nodes + i] = fixed ? T(0) : rec[k][3 + j];
 #pragma unroll
-        for (int c = 0; c < 4 * DPN; ++c) sV[size_t(c) * max_nodes + i] = T(0);
+        for (int c = 0; c < NACC * DPN; ++c) sV[size_t(c) * max_nodes + i] = T(0);
       }
     }
   }
   __syncthreads();
-  T *myV = sV + size_t(w) * DPN * max_nodes;
+  T *myV = ONEACC ? sV : sV + size_t(w) * DPN * max_nodes;
   if (DPN == 1 && tile_affine[tile])
-    block_steps<T, DPN, LDS_ATOMIC, true>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
-                                          coef_stride);
+    block_steps<T, DPN, LDS_ATOMIC || ONEACC, true>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+                                          coef_stride, pk0, c00, c10);
   else
-    block_steps<T, DPN, LDS_ATOMIC, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
-                                           coef_stride);
+    block_steps<T, DPN, LDS_ATOMIC || ONEACC, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+                                           coef_stride, pk0, c00, c10);
   __syncthreads();
-  for (int i = tid; i < nm; i += 256) {
-    const uint32_t raw = nodes[n0 + i];
-    if (raw & kFixedBit) continue;  // y = x written by the reset kernel
+  auto write_node = [&](int i, uint32_t raw) {
+    if (raw & kFixedBit) return;  // y = x written by the reset kernel
     const int64_t gg = raw & kIdMask;
 #pragma unroll
     for (int j = 0; j < DPN; ++j) {
       const size_t o = size_t(j) * max_nodes + i, cs = size_t(DPN) * max_nodes;
-      const T v = (sV[o] + sV[cs + o]) + (sV[2 * cs + o] + sV[3 * cs + o]);
+      T v;
+      if constexpr (ONEACC)
+        v = sV[o];
+      else
+        v = (sV[o] + sV[cs + o]) + (sV[2 * cs + o] + sV[3 * cs + o]);
       if (raw & kSharedBit)
         gbl_add(&y[gg * DPN + j], v);
       else
         y[gg * DPN + j] = v;
     }
-  }
+  };
+#pragma unroll
+  for (int k = 0; k < KN; ++k)
+    if (k * 256 + tid < nm) write_node(k * 256 + tid, keep[k]);
+  for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, nodes[n0 + i]);
 }
 
 namespace {
@@ -360,8 +381,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
   for (int64_t e = 0; e < ne; ++e) {
     const uint64_t px = ix[e] / patch_x, py = iy[e] / patch_y, cz = lz[e] / layers;
     tkey[e] = (cz * uint64_t(npy) + py) * uint64_t(npx) + px;
-  }
-  std::vector<int32_t> order(ne);
+  }  std::vector<int32_t> order(ne);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     if (tkey[a] != tkey[b]) return tkey[a] < tkey[b];
@@ -488,10 +508,12 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   return Q1_OK;
 }
 
-// LDS of the block-staged variant: node records, then four accumulator copies
+// LDS of the block-staged variant: node records, then the accumulator copies
+// (one shared copy for FP64, one per wave for FP32)
 size_t block_lds_bytes(const Op &op) {
   const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
-  return size_t(op.tiles.max_nodes) * rb * size_t(3 + op.physics + 4 * op.physics);
+  const size_t nacc = op.dtype == Q1_F64 ? 1 : 4;
+  return size_t(op.tiles.max_nodes) * rb * size_t(3 + op.physics + nacc * op.physics);
 }
 
 template <typename T, int DPN>
@@ -505,7 +527,8 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const bool block = op.variant == Q1_V_BLOCK;
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block) {
-    auto kb = tm.lds_atomic ? k_apply_block<T, DPN, true> : k_apply_block<T, DPN, false>;
+    constexpr bool one = std::is_same<T, double>::value;
+    auto kb = tm.lds_atomic ? k_apply_block<T, DPN, true, one> : k_apply_block<T, DPN, false, one>;
     hipLaunchKernelGGL(kb, dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes, op.n_nodes,
                        tm.node_ptr, tm.nodes, tm.tile_step,
                        reinterpret_cast<const uint4 *>(tm.lconn),

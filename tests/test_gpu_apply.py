@@ -12,7 +12,7 @@ from helpers import (TOL, dev, gpu_apply, gpu_diag, make_op, problem, rel_err, r
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [1, 3, 5]  # atomic scatter, LDS tiles, block-staged tiles
+VARIANTS = [1, 2, 3, 5]  # atomic scatter, colour classes, LDS tiles, block-staged tiles
 
 
 @pytest.fixture(scope="module")
