@@ -104,7 +104,13 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
  *   BLOCK    larger tiles, one workgroup of four wavefronts each: the tile's
  *            node records (coordinates, input) are staged in LDS once,
  *            accumulation into one LDS copy with LDS atomics (FP64) or into
- *            per-wavefront copies added in a fixed order (FP32);
+ *            per-wavefront copies added in a fixed order (FP32); nodes of one
+ *            tile are stored directly, the partial sums of nodes shared
+ *            between tiles go to halo slots owned by the operator and a
+ *            second kernel adds each node's slots in tile order (no global
+ *            atomics; each entry of y is written once).  Because the halo
+ *            buffer belongs to the operator, two applies of one BLOCK
+ *            operator must not run concurrently (issue them on one stream);
  *   AUTO     the fastest measured strategy: BLOCK, else LDS_TILE when the tile
  *            does not fit in LDS, else ATOMIC;
  *   CSR      the assembled matrix (made by q1_csr_create only). */

@@ -43,6 +43,12 @@ struct TileMap {
   int32_t *reset = nullptr;
   bool lds_atomic = false;        // corners collide within a step: accumulate with LDS atomics
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
+  // block variant: partial sums of nodes shared between tiles go to halo slots
+  // (no atomics), summed per node by a second kernel in a fixed order
+  int64_t n_halo = 0;             // slots: one per (shared free node, tile touching it)
+  int32_t *slot = nullptr;        // [entries] halo slot of each node-list entry, -1 if none
+  int32_t *hptr = nullptr;        // [n_reset+1] slot range of each reset node (node-major)
+  void *halo = nullptr;           // [n_halo][dpn] partial sums, overwritten by every apply
   size_t bytes = 0;
 };
 

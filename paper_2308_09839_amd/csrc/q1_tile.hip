@@ -238,7 +238,8 @@ __global__ __launch_bounds__(256) void k_apply_block(
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
     const uint4 *__restrict__ lconn, const T *__restrict__ coef_t, int64_t coef_stride,
     const T *__restrict__ xyz, const T *__restrict__ x, T *__restrict__ y,
-    const int *__restrict__ stop, const uint8_t *__restrict__ tile_affine) {
+    const int *__restrict__ stop, const uint8_t *__restrict__ tile_affine,
+    const int32_t *__restrict__ slot, T *__restrict__ halo) {
   if (stop && *stop) return;
   constexpr int NR = 3 + DPN;  // x, y, z, u[DPN], stored field by field
   constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
@@ -263,6 +264,7 @@ __global__ __launch_bounds__(256) void k_apply_block(
   // at clamped indices) before any LDS write, so the round costs one latency.
   // The first round's node words stay in registers for the write-back.
   uint32_t keep[KN];
+  int32_t kslot[KN];
   for (int base = 0; base < nm; base += KN * 256) {
     uint32_t raw[KN];
     T rec[KN][NR];
@@ -270,7 +272,10 @@ __global__ __launch_bounds__(256) void k_apply_block(
     for (int k = 0; k < KN; ++k) raw[k] = nodes[n0 + min(base + k * 256 + tid, nm - 1)];
     if (base == 0) {
 #pragma unroll
-      for (int k = 0; k < KN; ++k) keep[k] = raw[k];
+      for (int k = 0; k < KN; ++k) {
+        keep[k] = raw[k];
+        kslot[k] = slot[n0 + min(k * 256 + tid, nm - 1)];
+      }
     }
 #pragma unroll
     for (int k = 0; k < KN; ++k) {
@@ -305,8 +310,10 @@ __global__ __launch_bounds__(256) void k_apply_block(
     block_steps<T, DPN, LDS_ATOMIC || ONEACC, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
                                            coef_stride, pk0, c00, c10);
   __syncthreads();
-  auto write_node = [&](int i, uint32_t raw) {
-    if (raw & kFixedBit) return;  // y = x written by the reset kernel
+  // nodes of this tile only: y; nodes shared with other tiles: this tile's halo
+  // slot (summed by k_halo_sum); Dirichlet nodes: written by k_halo_sum
+  auto write_node = [&](int i, uint32_t raw, int32_t sl) {
+    if (raw & kFixedBit) return;
     const int64_t gg = raw & kIdMask;
 #pragma unroll
     for (int j = 0; j < DPN; ++j) {
@@ -317,15 +324,43 @@ __global__ __launch_bounds__(256) void k_apply_block(
       else
         v = (sV[o] + sV[cs + o]) + (sV[2 * cs + o] + sV[3 * cs + o]);
       if (raw & kSharedBit)
-        gbl_add(&y[gg * DPN + j], v);
+        halo[int64_t(sl) * DPN + j] = v;
       else
         y[gg * DPN + j] = v;
     }
   };
 #pragma unroll
   for (int k = 0; k < KN; ++k)
-    if (k * 256 + tid < nm) write_node(k * 256 + tid, keep[k]);
-  for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, nodes[n0 + i]);
+    if (k * 256 + tid < nm) write_node(k * 256 + tid, keep[k], kslot[k]);
+  for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, nodes[n0 + i], slot[n0 + i]);
+}
+
+// Second pass of the block variant, one thread per node on the reset list:
+// y = x on Dirichlet nodes, otherwise the sum of the node's halo slots in slot
+// (= tile) order, so every entry of y is written exactly once.
+template <typename T, int DPN>
+__global__ void k_halo_sum(int64_t n, const int32_t *__restrict__ ids,
+                           const int32_t *__restrict__ hptr, const uint8_t *__restrict__ mask,
+                           const T *__restrict__ x, const T *__restrict__ halo,
+                           T *__restrict__ y, const int *__restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t g = ids[j];
+  if (mask && mask[g]) {
+#pragma unroll
+    for (int c = 0; c < DPN; ++c) y[g * DPN + c] = x[g * DPN + c];
+    return;
+  }
+  const int32_t k0 = hptr[j], k1 = hptr[j + 1];
+  T acc[DPN];
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) acc[c] = T(0);
+  for (int32_t k = k0; k < k1; ++k)
+#pragma unroll
+    for (int c = 0; c < DPN; ++c) acc[c] += halo[int64_t(k) * DPN + c];
+#pragma unroll
+  for (int c = 0; c < DPN; ++c) y[g * DPN + c] = acc[c];
 }
 
 namespace {
@@ -338,6 +373,7 @@ struct HostTiles {
   int max_nodes = 0;
   bool corner_collision = false;   // two lanes of a step share a node at one corner
   std::vector<uint8_t> tile_affine;  // every element of the tile is a parallelepiped
+  std::vector<int32_t> slot, hptr;   // halo slots of the block variant
 };
 
 // Group elements into tiles and steps; record node lists and corner indices.
@@ -455,6 +491,24 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
     H.tile_affine.push_back(aff ? 1 : 0);
     for (int32_t g : list) local[g] = -1;
   }
+  // halo slots, node-major: reset node j owns slots [hptr[j], hptr[j+1]), one per
+  // tile touching it, in tile order; Dirichlet nodes own none
+  const int64_t nr = int64_t(H.reset.size());
+  std::vector<int64_t> hp(nr + 1, 0);
+  for (int64_t j = 0; j < nr; ++j) {
+    const int32_t g = H.reset[j];
+    const bool fixed = !mask.empty() && mask[g];
+    hp[j + 1] = hp[j] + (fixed ? 0 : ntile[g]);
+    local[g] = int32_t(j);  // reset index (local[] is free again here)
+  }
+  if (hp[nr] >= (int64_t(1) << 31)) return fail(Q1_EUNSUPPORTED, "too many halo slots");
+  H.hptr.assign(hp.begin(), hp.end());
+  H.slot.assign(H.nodes.size(), -1);
+  std::vector<int32_t> next(H.hptr.begin(), H.hptr.end() - 1);
+  for (size_t i = 0; i < H.nodes.size(); ++i) {
+    const uint32_t v = H.nodes[i];
+    if ((v & kSharedBit) && !(v & kFixedBit)) H.slot[i] = next[local[v & kIdMask]]++;
+  }
   return Q1_OK;
 }
 
@@ -505,6 +559,13 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
       (rc = up(&tm.tile_affine, H.tile_affine)))
     return rc;
   tm.coef_t = coef_dev;
+  if (op.variant == Q1_V_BLOCK) {
+    if ((rc = up(&tm.slot, H.slot)) || (rc = up(&tm.hptr, H.hptr))) return rc;
+    tm.n_halo = H.hptr.back();
+    const size_t hb = std::max<int64_t>(1, tm.n_halo) * op.physics * sizeof(T);
+    Q1_HIP(hipMalloc(&tm.halo, hb));
+    tm.bytes += hb;
+  }
   return Q1_OK;
 }
 
@@ -521,10 +582,10 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const TileMap &tm = op.tiles;
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
-  if (tm.n_reset > 0)
+  const bool block = op.variant == Q1_V_BLOCK;
+  if (tm.n_reset > 0 && !block)
     hipLaunchKernelGGL((k_reset_nodes<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
                        s, tm.n_reset, tm.reset, op.mask, x, y, stop);
-  const bool block = op.variant == Q1_V_BLOCK;
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block) {
     constexpr bool one = std::is_same<T, double>::value;
@@ -533,7 +594,12 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
                        tm.node_ptr, tm.nodes, tm.tile_step,
                        reinterpret_cast<const uint4 *>(tm.lconn),
                        static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
-                       static_cast<const T *>(op.xyz), x, y, stop, tm.tile_affine);
+                       static_cast<const T *>(op.xyz), x, y, stop, tm.tile_affine, tm.slot,
+                       static_cast<T *>(tm.halo));
+    if (tm.n_reset > 0)
+      hipLaunchKernelGGL((k_halo_sum<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
+                         s, tm.n_reset, tm.reset, tm.hptr, op.mask, x,
+                         static_cast<const T *>(tm.halo), y, stop);
     Q1_HIP(hipGetLastError());
     return Q1_OK;
   }
@@ -605,7 +671,8 @@ int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *
 
 void free_tiles(Op &op) {
   TileMap &t = op.tiles;
-  void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset, t.coef_t, t.tile_affine};
+  void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset,
+                  t.coef_t,   t.tile_affine, t.slot, t.hptr, t.halo};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   t = TileMap{};
