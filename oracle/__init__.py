@@ -52,6 +52,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.orc_ke_laplace.argtypes = [_f64p, ctypes.c_double, _f64p]
         L.orc_ke_elasticity.argtypes = [_f64p, ctypes.c_double, ctypes.c_double, _f64p]
+        L.orc_ke_vlaplace.argtypes = [_f64p, ctypes.c_double, _f64p]
         L.orc_csr_pattern.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _i32p,
                                       _i64p, ctypes.c_void_p]
         L.orc_csr_pattern.restype = ctypes.c_int64
@@ -95,6 +96,14 @@ def ke_elasticity(X: np.ndarray, lam: float, mu: float) -> np.ndarray:
     return Ke.reshape(24, 24)
 
 
+def ke_vlaplace(X: np.ndarray, k: float = 1.0) -> np.ndarray:
+    """24x24 vector-Laplace element matrix, DOF 3*node + component."""
+    Ke = np.zeros(576)
+    if lib().orc_ke_vlaplace(np.ascontiguousarray(X, dtype=np.float64).ravel(), float(k), Ke):
+        raise ValueError("non-positive Jacobian determinant")
+    return Ke.reshape(24, 24)
+
+
 @dataclass
 class CSR:
     n: int
@@ -128,6 +137,11 @@ class CSR:
         return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
 
 
+def dpn_of(physics: int) -> int:
+    """DOF per node: 1 for scalar Laplace, 3 for vector Laplace and elasticity."""
+    return 1 if physics == 1 else 3
+
+
 def csr_pattern(dpn: int, n_nodes: int, conn: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     ne = conn.shape[1]
@@ -145,13 +159,14 @@ def assemble(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
              mask: np.ndarray | None = None) -> CSR:
     """Assembled operator with Dirichlet elimination on the masked nodes.
 
-    physics = 1 (scalar Laplace, coef [1, ne] = k) or 3 (elasticity,
-    coef [2, ne] = lambda, mu).  xyz [3, nn], conn [8, ne], mask uint8 [nn]."""
+    physics = 1 (scalar Laplace, coef [1, ne] = k), 2 (vector Laplace, 3 DOF
+    per node, coef [1, ne] = k) or 3 (elasticity, coef [2, ne] = lambda, mu).
+    xyz [3, nn], conn [8, ne], mask uint8 [nn]."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     coef = np.ascontiguousarray(coef, dtype=np.float64)
     nn, ne = xyz.shape[1], conn.shape[1]
-    rowptr, col = csr_pattern(physics, nn, conn)
+    rowptr, col = csr_pattern(dpn_of(physics), nn, conn)
     val = np.empty(col.shape[0])
     if mask is not None:
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
@@ -164,7 +179,7 @@ def assemble(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
         raise ValueError("element with non-positive Jacobian determinant")
     if rc != 0:
         raise RuntimeError(f"oracle assembly failed ({rc})")
-    return CSR(nn * physics, rowptr, col, val)
+    return CSR(nn * dpn_of(physics), rowptr, col, val)
 
 
 def apply_rows(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,

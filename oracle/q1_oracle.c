@@ -92,6 +92,43 @@ int orc_ke_laplace(const double X[24], double k, double Ke[64]) {
   return 0;
 }
 
+/* Vector Laplace (Section 2, the vector Laplace element matrix, with the cell
+ * coefficient k): [A^e]_{3a+i,3b+j} = sum_q k w_q detJ (e_i (x) grad phi_a) :
+ * (e_j (x) grad phi_b), the double contraction written out entry by entry. */
+int orc_ke_vlaplace(const double X[24], double k, double Ke[576]) {
+  double pts[8][3], w[8];
+  orc_quadrature(pts, w);
+  memset(Ke, 0, 576 * sizeof(double));
+  for (int q = 0; q < 8; ++q) {
+    double dphi[8][3], G[8][3];
+    orc_ref_grad(pts[q], dphi);
+    double det = physical_gradients(X, dphi, G);
+    if (!(det > 0.0)) return -1;
+    double s = k * w[q] * det;
+    for (int a = 0; a < 8; ++a)
+      for (int i = 0; i < 3; ++i)
+        for (int b = 0; b < 8; ++b)
+          for (int j = 0; j < 3; ++j) {
+            double c = 0.0; /* sum_rs (e_i (x) G_a)_rs (e_j (x) G_b)_rs */
+            for (int r = 0; r < 3; ++r)
+              for (int t = 0; t < 3; ++t)
+                c += (r == i ? G[a][t] : 0.0) * (r == j ? G[b][t] : 0.0);
+            Ke[24 * (3 * a + i) + 3 * b + j] += s * c;
+          }
+  }
+  return 0;
+}
+
+/* physics 1 scalar Laplace (1 DOF per node), 2 vector Laplace, 3 elasticity */
+static int dpn_of(int physics) { return physics == 1 ? 1 : 3; }
+
+static int element_matrix(int physics, const double X[24], const double *coef, int64_t ne,
+                          int64_t e, double *Ke) {
+  if (physics == 1) return orc_ke_laplace(X, coef[e], Ke);
+  if (physics == 2) return orc_ke_vlaplace(X, coef[e], Ke);
+  return orc_ke_elasticity(X, coef[e], coef[ne + e], Ke);
+}
+
 /* [A^e]_{3a+i,3b+j} = sum_q w_q detJ (e_i (x) grad phi_a) : sigma(e_j (x) grad phi_b)
  * with sigma(eps) = lambda tr(eps) I + 2 mu eps, which expands to
  * lambda G_ai G_bj + mu (delta_ij G_a.G_b + G_aj G_bi). */
@@ -208,7 +245,7 @@ static int64_t find_col(const int64_t *rowptr, const int32_t *col, int64_t row, 
 int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
                      const int32_t *conn, const double *coef, const uint8_t *mask,
                      const int64_t *rowptr, const int32_t *col, double *val) {
-  const int dpn = physics;
+  const int dpn = dpn_of(physics);
   const int nd = 8 * dpn;
   const int64_t nrows = nn * dpn;
   memset(val, 0, (size_t)rowptr[nrows] * sizeof(double));
@@ -220,8 +257,7 @@ int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
       X[3 * a + 1] = xyz[1 * nn + n];
       X[3 * a + 2] = xyz[2 * nn + n];
     }
-    int rc = (physics == 1) ? orc_ke_laplace(X, coef[e], Ke)
-                            : orc_ke_elasticity(X, coef[e], coef[ne + e], Ke);
+    int rc = element_matrix(physics, X, coef, ne, e, Ke);
     if (rc) return -1;
     for (int p = 0; p < nd; ++p) {
       int64_t row = (int64_t)conn[(p / dpn) * ne + e] * dpn + p % dpn;
@@ -248,7 +284,7 @@ int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
 int orc_apply_rows(int physics, int64_t nn, int64_t ne, const double *xyz,
                    const int32_t *conn, const double *coef, const uint8_t *mask,
                    const double *x, int64_t n_rows, const int64_t *rows, double *y) {
-  const int dpn = physics, nd = 8 * dpn;
+  const int dpn = dpn_of(physics), nd = 8 * dpn;
   /* slot[node] = 1 if any DOF of the node is selected */
   uint8_t *sel = (uint8_t *)calloc((size_t)nn, 1);
   int64_t *pos = (int64_t *)malloc((size_t)(nn * dpn) * sizeof(int64_t));
@@ -268,8 +304,7 @@ int orc_apply_rows(int physics, int64_t nn, int64_t ne, const double *xyz,
       int32_t n = conn[a * ne + e];
       for (int c = 0; c < 3; ++c) X[3 * a + c] = xyz[c * nn + n];
     }
-    int rc = (physics == 1) ? orc_ke_laplace(X, coef[e], Ke)
-                            : orc_ke_elasticity(X, coef[e], coef[ne + e], Ke);
+    int rc = element_matrix(physics, X, coef, ne, e, Ke);
     if (rc) { free(sel); free(pos); return -1; }
     for (int p = 0; p < nd; ++p) {
       int64_t row = (int64_t)conn[(p / dpn) * ne + e] * dpn + p % dpn;

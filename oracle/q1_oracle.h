@@ -37,6 +37,7 @@ void orc_ref_grad(const double xi[3], double dphi[8][3]);
  * det J <= 0 at some quadrature point. */
 int orc_ke_laplace(const double X[24], double k, double Ke[64]);
 int orc_ke_elasticity(const double X[24], double lam, double mu, double Ke[576]);
+int orc_ke_vlaplace(const double X[24], double k, double Ke[576]);
 
 /* CSR pattern of the assembled operator, columns sorted.  rowptr has
  * n_nodes*dpn + 1 entries.  With col == NULL only rowptr is filled.
