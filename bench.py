@@ -105,8 +105,14 @@ def cpu_baseline(n: int, seed: int, slab: int):
         A.matvec(x)
         reps += 1
     t_spmv = (time.perf_counter() - t0) / reps
+    # the oracle's Jacobi-PCG on the 16^3 jittered problem, for the solve-time comparison
+    prc, bc = cg16_problem(si)
+    Ac = oracle.assemble(1, prc["xyz"], prc["conn"], prc["coef"], prc["mask"])
+    t0 = time.perf_counter()
+    refc = oracle.pcg(Ac, bc, rtol=1e-8)
+    t_cg = time.perf_counter() - t0
     return dict(value=round(nn_s / t_spmv / 1e9, 4), unit="GDOF/s", cores=oracle.num_threads(),
-                kind="oracle",
+                kind="oracle", cg16_s=round(t_cg, 5), cg16_iters=refc.iters,
                 sample=(f"{n}x{n}x{slab}-element slab ({nn_s} DOF) of the {n}^3 workload; "
                         f"CSR assembled once in {t_asm:.2f} s (not in the rate), OpenMP CSR "
                         f"SpMV timed over {reps} products"),
@@ -132,38 +138,42 @@ def bench_csr(q1, si, n, seed, args):
             "csr_assembly_s": round(t_asm, 3)}
 
 
-def bench_cg16(q1, si, n, seed, args):
-    """16^3 jittered Laplace, k = exp(N(0,1)), Dirichlet on z=0: FP64 Jacobi-PCG
-    to a 1e-8 relative residual, wall time of the whole solve."""
-    import numpy as np
-    import torch
-
-    import oracle
+def cg16_problem(si):
+    """16^3 jittered Laplace, k = exp(N(0,1)), Dirichlet on z=0, b ~ U(-1, 1) on free nodes."""
     s0 = si.seed_for(0)
     pr = si.problem_laplace_jittered(16, s0)
-    nn = pr["xyz"].shape[1]
-    b = si.vec_uniform(nn, s0, si.STREAM_RHS)
+    b = si.vec_uniform(pr["xyz"].shape[1], s0, si.STREAM_RHS)
     b[pr["mask"] == 1] = 0.0
-    op = q1.q1_op_create(1, 0, 0, *upload(pr, 0))
+    return pr, b
+
+
+def bench_cg16(q1, si, n, seed, args):
+    """16^3 jittered Laplace: FP64 Jacobi-PCG to a 1e-8 relative residual, wall time of the
+    whole solve, through the launch-per-kernel driver and through the persistent kernel
+    (one cooperative launch for the whole solve)."""
+    import torch
+    pr, b = cg16_problem(si)
     bd = torch.from_numpy(b).to("cuda")
     xd = torch.empty_like(bd)
-    q1.q1_pcg(op, 1, bd, xd, 1e-8, 20000)  # warm-up
-    torch.cuda.synchronize()
-    ts = []
-    for _ in range(5):
-        t0 = time.perf_counter()
-        st = q1.q1_pcg(op, 1, bd, xd, 1e-8, 20000)
-        ts.append(time.perf_counter() - t0)
-    ts.sort()
-    oracle.build(force=False)
-    A = oracle.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
-    t0 = time.perf_counter()
-    ref = oracle.pcg(A, b, rtol=1e-8)
-    t_cpu = time.perf_counter() - t0
-    return {"cg16_gpu_s": round(ts[len(ts) // 2], 6), "cg16_iters": st["iters"],
-            "cg16_true_rel_res": st["true_rel_res"],
-            "cg16_oracle_true_rel_res": oracle.true_rel_res(A, xd.cpu().numpy(), b),
-            "cg16_cpu_oracle_s": round(t_cpu, 5), "cg16_cpu_oracle_iters": ref.iters}
+    res = {}
+    for tag, variant in (("", 0), ("_persistent", 3)):
+        op = q1.q1_op_create(1, 0, variant, *upload(pr, 0))
+        if variant == 0:
+            solve = lambda: q1.q1_pcg(op, 1, bd, xd, 1e-8, 20000)
+        else:
+            solve = lambda: q1.q1_batched_pcg([op], [[bd]], [[xd]], 1e-8, 20000)[0]
+        solve()  # warm-up
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            st = solve()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        res[f"cg16{tag}_gpu_s"] = round(ts[len(ts) // 2], 6)
+        res[f"cg16{tag}_iters"] = st["iters"]
+        res[f"cg16{tag}_rel_res"] = st["rel_res"]
+    return res
 
 
 def bench_ir96(q1, si, n, seed, args):
@@ -205,6 +215,38 @@ def bench_ir96(q1, si, n, seed, args):
             "el96_mpcg_true_rel_res": stm["true_rel_res"],
             "el96_apply_fp64_gdofs": round(3 * nn / (ms64 * 1e-3) / 1e9, 3),
             "el96_apply_fp32_gdofs": round(3 * nn / (ms32 * 1e-3) / 1e9, 3)}
+
+
+def bench_vlap96(q1, si, n, seed, args):
+    """96^3 vector Laplace (3 DOF per node, k = exp(N(0,1)) iid, Dirichlet on z=0):
+    FP64 and FP32 applies of the default variant, and FP64 Jacobi-PCG to 1e-8."""
+    import torch
+    s5 = si.seed_for(5)
+    pr = si.problem_vlaplace(96, s5)
+    nn = pr["xyz"].shape[1]
+    res = {}
+    for dt, tag in ((0, "fp64"), (1, "fp32")):
+        op = q1.q1_op_create(2, dt, 0, *upload(pr, dt))
+        t = torch.float64 if dt == 0 else torch.float32
+        x = torch.from_numpy(si.vec_uniform(3 * nn, s5, si.STREAM_X)).to("cuda", dtype=t)
+        y = torch.empty_like(x)
+        ms, _ = time_applies(op, x, y, 100, 10)
+        alg, _ = op.bytes()
+        res[f"vlap96_apply_{tag}_gdofs"] = round(3 * nn / (ms * 1e-3) / 1e9, 3)
+        res[f"vlap96_apply_{tag}_hbm_frac"] = round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        if dt == 0:
+            b = si.vec_uniform(3 * nn, s5, si.STREAM_RHS)
+            b[si.dof_mask(pr["mask"], 3) == 1] = 0.0
+            bd = torch.from_numpy(b).to("cuda")
+            xd = torch.empty_like(bd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = q1.q1_pcg(op, 1, bd, xd, 1e-8, 50000)
+            res["vlap96_pcg64_s"] = round(time.perf_counter() - t0, 4)
+            res["vlap96_pcg64_iters"] = st["iters"]
+            res["vlap96_pcg64_true_rel_res"] = st["true_rel_res"]
+        del op
+    return res
 
 
 def bench_batched(q1, si, n, seed, args):
@@ -260,12 +302,17 @@ def bench_batched(q1, si, n, seed, args):
             "batched_mixed_max_true_rel_res": max(s_["rel_res"] for s_ in stm)}
 
 
+# the network's 3x3x3 convolutions: (real input channels, output channels, level);
+# level l runs on the grid divided by 2^(l-1)
+UNET_CONVS = [(2, 16, 1), (16, 16, 1), (16, 32, 2), (32, 32, 2), (32, 64, 3), (64, 64, 3),
+              (96, 32, 2), (32, 32, 2), (48, 16, 1), (16, 16, 1)]
+
+
 def unet_forward_flops(D: int, H: int, W: int) -> float:
     """Algorithmic FLOPs of one network forward on a D x H x W grid: 2 * 27 * Cin * Cout per
     voxel and convolution (real input channels), plus the 1x1 head."""
-    from oracle import unet_oracle as U  # layer table only
     f = 0.0
-    for _, ci, co, lvl in U.LAYERS:
+    for ci, co, lvl in UNET_CONVS:
         s = 2 ** (lvl - 1)
         f += 2.0 * 27 * ci * co * (D // s) * (H // s) * (W // s)
     return f + 2.0 * 16 * D * H * W
@@ -345,7 +392,7 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
     ap.add_argument("--extras", default="all",
                     help="comma-separated solver extras to run (csr, cg16, cg_elasticity96, "
-                         "learned64, batched32) or 'all'")
+                         "vlaplace96, learned64, batched32) or 'all'")
     ap.add_argument("--nn-fields", type=int, default=64, help="training fields of the learned leg")
     ap.add_argument("--nn-steps", type=int, default=3000, help="Adam steps of the learned leg")
     ap.add_argument("--nn-eval", type=int, default=2, help="held-out fields of the learned leg")
@@ -428,7 +475,7 @@ def main() -> int:
         extras["fp64_jittered_flop_frac"] = round(alg_flops / (msj * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)
         del opj, xj, yj
         for name, fn in (("csr", bench_csr), ("cg16", bench_cg16), ("cg_elasticity96", bench_ir96),
-                         ("learned64", bench_learned),
+                         ("vlaplace96", bench_vlap96), ("learned64", bench_learned),
                          ("batched32", bench_batched)):
             if args.extras != "all" and name not in args.extras.split(","):
                 continue

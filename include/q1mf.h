@@ -22,8 +22,8 @@
  *   - Mesh layout: coordinates structure-of-arrays [3][n_nodes]; connectivity
  *     [8][n_elems] with local node a = i + 2j + 4k at reference corner
  *     (2i-1, 2j-1, 2k-1) of [-1,1]^3; DOF numbering node*dpn + component
- *     (dpn = 1 Laplace, 3 elasticity); coefficients [ncoef][n_elems]:
- *     k for Laplace, (lambda, mu) for elasticity.
+ *     (dpn = 1 scalar Laplace, 3 vector Laplace and elasticity); coefficients
+ *     [ncoef][n_elems]: k for the Laplace kinds, (lambda, mu) for elasticity.
  *   - Quadrature: 2x2x2 Gauss-Legendre (points +-1/sqrt(3), weights 1).
  *   - Dirichlet mask (uint8 per node, or NULL for none): every DOF of a masked
  *     node is eliminated symmetrically, (A x)_c = x_c, and masked DOFs are
@@ -87,7 +87,12 @@ int q1_vec_uniform(int64_t n, uint64_t seed, uint64_t stream, double lo, double 
 /* ---- operators ---------------------------------------------------------- */
 typedef struct q1_op q1_op;
 
-enum { Q1_LAPLACE = 1, Q1_ELASTICITY = 3 }; /* value = DOF per node */
+/* Physics kinds.  Q1_LAPLACE: scalar Laplace, 1 DOF per node, coefficient k.
+ * Q1_VLAPLACE: vector Laplace (Section 2, the vector Laplace element matrix
+ * with the cell coefficient k): 3 DOF per node, each component an independent
+ * scalar Laplace; coefficient k.  Q1_ELASTICITY: isotropic elasticity, 3 DOF
+ * per node, coefficients lambda and mu. */
+enum { Q1_LAPLACE = 1, Q1_VLAPLACE = 2, Q1_ELASTICITY = 3 };
 enum { Q1_F64 = 0, Q1_F32 = 1 };
 /* Scatter strategies of the apply (Section 3, third step):
  *   ATOMIC   one thread per element, global atomic adds (the paper's
@@ -376,7 +381,8 @@ int q1_unet_precond(void *ctx, const void *r_d, void *z_d, void *stream);
  * row, two vectors), 1 matrix-free (Table 2), 2 partial assembly (Table 3).
  * cache: 0 perfect caching (nodal data read once), 1 no caching (nodal data
  * read once per element touching it).  real_bytes 8 or 4; coefficient bytes
- * per element coef_bytes (the paper counts 0 for Laplace, 16 for elasticity). */
+ * per element coef_bytes (the paper counts 0 for Laplace, 16 for elasticity).
+ * physics: a physics kind (1 DOF per node for Q1_LAPLACE, 3 otherwise). */
 int q1_model_bytes(int kind, int physics, int real_bytes, int coef_bytes, int64_t n_nodes,
                    int64_t n_elems, int cache, double *bytes);
 

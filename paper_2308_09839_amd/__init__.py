@@ -13,12 +13,12 @@ import ctypes
 import numpy as np
 
 from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32, Q1_F64,
-                   Q1_LAPLACE, Q1_OK, Q1_PC_JACOBI, Q1_PC_NONE, Q1_V_ATOMIC, Q1_V_AUTO, Q1_V_COLOR,
+                   Q1_LAPLACE, Q1_OK, Q1_VLAPLACE, Q1_PC_JACOBI, Q1_PC_NONE, Q1_V_ATOMIC, Q1_V_AUTO, Q1_V_COLOR,
                    Q1_V_CSR, Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
     "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
-    "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
+    "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_VLAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_COLOR", "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
     "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_apply", "q1_op_diag",

@@ -20,6 +20,7 @@ Q1_EBREAKDOWN = -5
 Q1_EUNSUPPORTED = -6
 
 Q1_LAPLACE = 1
+Q1_VLAPLACE = 2
 Q1_ELASTICITY = 3
 Q1_F64 = 0
 Q1_F32 = 1

@@ -44,11 +44,12 @@ __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(
 
 // One thread per element, global atomics for the scatter (the paper's
 // one-thread-per-element strategy).
-template <typename T, int DPN, bool MASKED>
+template <typename T, int PH, bool MASKED>
 __global__ __launch_bounds__(256) void k_apply_atomic(
     int64_t ne, int64_t nn, const T *__restrict__ xyz, const int32_t *__restrict__ conn,
     const T *__restrict__ coef, const uint8_t *__restrict__ mask, const T *__restrict__ x,
     T *__restrict__ y, const int *__restrict__ stop) {
+  constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t e = int64_t(blk) * blockDim.x + threadIdx.x;
@@ -64,38 +65,29 @@ __global__ __launch_bounds__(256) void k_apply_atomic(
   bool fixed[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) fixed[a] = MASKED ? (mask[nid[a]] != 0) : false;
-  if constexpr (DPN == 1) {
-    T u[8], v[8];
+  T u[DPN][8], v[DPN][8];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) u[a] = fixed[a] ? T(0) : x[nid[a]];
-    laplace_element<T>(X, u, coef[e], v);
+  for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
-      if (!fixed[a]) atomic_add(&y[nid[a]], v[a]);
-  } else {
-    T u[3][8], v[3][8];
+    for (int j = 0; j < DPN; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * DPN + j];
+  element_apply<T, PH>(X, u, coef[e], PH == 3 ? coef[ne + e] : T(0), v);
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 8; ++a)
+    if (!fixed[a])
 #pragma unroll
-      for (int j = 0; j < 3; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * 3 + j];
-    elasticity_element<T>(X, u, coef[e], coef[ne + e], v);
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-      if (!fixed[a])
-#pragma unroll
-        for (int j = 0; j < 3; ++j) atomic_add(&y[int64_t(nid[a]) * 3 + j], v[j][a]);
-  }
+      for (int j = 0; j < DPN; ++j) atomic_add(&y[int64_t(nid[a]) * DPN + j], v[j][a]);
 }
 
 // One thread per element of one colour class [e0, e1) of the colour order: no
 // two elements of a class share a node, so the scatter is a plain
 // read-add-write; kernel boundaries order the classes.
-template <typename T, int DPN, bool MASKED>
+template <typename T, int PH, bool MASKED>
 __global__ __launch_bounds__(256) void k_apply_color(
     int64_t e0, int64_t e1, int64_t ne, int64_t nn, const T *__restrict__ xyz,
     const int32_t *__restrict__ conn, const T *__restrict__ coef,
     const uint8_t *__restrict__ mask, const T *__restrict__ x, T *__restrict__ y,
     const int *__restrict__ stop) {
+  constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t e = e0 + int64_t(blk) * blockDim.x + threadIdx.x;
@@ -111,39 +103,30 @@ __global__ __launch_bounds__(256) void k_apply_color(
   bool fixed[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) fixed[a] = MASKED ? (mask[nid[a]] != 0) : false;
-  if constexpr (DPN == 1) {
-    T u[8], v[8];
+  T u[DPN][8], v[DPN][8];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) u[a] = fixed[a] ? T(0) : x[nid[a]];
-    laplace_element<T>(X, u, coef[e], v);
+  for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
-      if (!fixed[a]) y[nid[a]] += v[a];
-  } else {
-    T u[3][8], v[3][8];
+    for (int j = 0; j < DPN; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * DPN + j];
+  element_apply<T, PH>(X, u, coef[e], PH == 3 ? coef[ne + e] : T(0), v);
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 8; ++a)
+    if (!fixed[a])
 #pragma unroll
-      for (int j = 0; j < 3; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * 3 + j];
-    elasticity_element<T>(X, u, coef[e], coef[ne + e], v);
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-      if (!fixed[a])
-#pragma unroll
-        for (int j = 0; j < 3; ++j) y[int64_t(nid[a]) * 3 + j] += v[j][a];
-  }
+      for (int j = 0; j < DPN; ++j) y[int64_t(nid[a]) * DPN + j] += v[j][a];
 }
 
 // Diagonal of A: d_(a,i) += sum_q w det J [element diagonal entry], i.e.
-// Laplace k |A'^T g'_a|^2 / (512 det'), elasticity
-// ((lambda + mu) t_i^2 + mu |t|^2) / (512 det') with t = A'^T g'_a.
-template <typename T, int DPN, bool MASKED>
+// Laplace (every component of the vector Laplace) k |A'^T g'_a|^2 / (512 det'),
+// elasticity ((lambda + mu) t_i^2 + mu |t|^2) / (512 det') with t = A'^T g'_a.
+template <typename T, int PH, bool MASKED>
 __global__ __launch_bounds__(256) void k_diag(int64_t ne, int64_t nn,
                                               const T *__restrict__ xyz,
                                               const int32_t *__restrict__ conn,
                                               const T *__restrict__ coef,
                                               const uint8_t *__restrict__ mask,
                                               T *__restrict__ d) {
+  constexpr int DPN = phys_dpn(PH);
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   int32_t nid[8];
@@ -168,7 +151,7 @@ __global__ __launch_bounds__(256) void k_diag(int64_t ne, int64_t nn,
 #pragma unroll
     for (int i = 0; i < DPN; ++i) acc[a][i] = T(0);
   const T c0 = coef[e];
-  const T c1 = DPN == 3 ? coef[ne + e] : T(0);
+  const T c1 = PH == 3 ? coef[ne + e] : T(0);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
@@ -192,8 +175,9 @@ __global__ __launch_bounds__(256) void k_diag(int64_t ne, int64_t nn,
 #pragma unroll
       for (int c = 0; c < 3; ++c) t[c] = g0 * a0[c] + g1 * a1[c] + g2 * a2[c];
       const T tt = dot3(t, t);
-      if constexpr (DPN == 1) {
-        acc[a][0] += c0 * s * tt;
+      if constexpr (PH != 3) {
+#pragma unroll
+        for (int i = 0; i < DPN; ++i) acc[a][i] += c0 * s * tt;
       } else {
 #pragma unroll
         for (int i = 0; i < 3; ++i) acc[a][i] += s * ((c0 + c1) * t[i] * t[i] + c1 * tt);
@@ -214,8 +198,9 @@ constexpr int kBlock = 256;
 
 inline int grid_for(int64_t n, int block) { return int((n + block - 1) / block); }
 
-template <typename T, int DPN>
+template <typename T, int PH>
 int apply_atomic(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
+  constexpr int DPN = phys_dpn(PH);
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
   const int64_t ndof = op.n_nodes * DPN;
@@ -226,17 +211,18 @@ int apply_atomic(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const T *xyz = static_cast<const T *>(op.xyz);
   const T *coef = static_cast<const T *>(op.coef);
   if (op.mask)
-    hipLaunchKernelGGL((k_apply_atomic<T, DPN, true>), grid, dim3(kBlock), 0, s, op.n_elems,
+    hipLaunchKernelGGL((k_apply_atomic<T, PH, true>), grid, dim3(kBlock), 0, s, op.n_elems,
                        op.n_nodes, xyz, op.conn, coef, op.mask, x, y, stop);
   else
-    hipLaunchKernelGGL((k_apply_atomic<T, DPN, false>), grid, dim3(kBlock), 0, s, op.n_elems,
+    hipLaunchKernelGGL((k_apply_atomic<T, PH, false>), grid, dim3(kBlock), 0, s, op.n_elems,
                        op.n_nodes, xyz, op.conn, coef, op.mask, x, y, stop);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
 
-template <typename T, int DPN>
+template <typename T, int PH>
 int apply_color(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
+  constexpr int DPN = phys_dpn(PH);
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
   const int64_t ndof = op.n_nodes * DPN;
@@ -250,18 +236,19 @@ int apply_color(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop
     if (e1 <= e0) continue;
     const dim3 grid(grid_for(e1 - e0, kBlock));
     if (op.mask)
-      hipLaunchKernelGGL((k_apply_color<T, DPN, true>), grid, dim3(kBlock), 0, s, e0, e1,
+      hipLaunchKernelGGL((k_apply_color<T, PH, true>), grid, dim3(kBlock), 0, s, e0, e1,
                          op.n_elems, op.n_nodes, xyz, cm.conn, coef, op.mask, x, y, stop);
     else
-      hipLaunchKernelGGL((k_apply_color<T, DPN, false>), grid, dim3(kBlock), 0, s, e0, e1,
+      hipLaunchKernelGGL((k_apply_color<T, PH, false>), grid, dim3(kBlock), 0, s, e0, e1,
                          op.n_elems, op.n_nodes, xyz, cm.conn, coef, op.mask, x, y, stop);
   }
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }
 
-template <typename T, int DPN>
+template <typename T, int PH>
 int diag_impl(Op &op, void *dv, hipStream_t s) {
+  constexpr int DPN = phys_dpn(PH);
   T *d = static_cast<T *>(dv);
   const int64_t ndof = op.n_nodes * DPN;
   hipLaunchKernelGGL((k_init_diag<T, DPN>), dim3(grid_for(ndof, kBlock)), dim3(kBlock), 0, s,
@@ -271,10 +258,10 @@ int diag_impl(Op &op, void *dv, hipStream_t s) {
     const T *xyz = static_cast<const T *>(op.xyz);
     const T *coef = static_cast<const T *>(op.coef);
     if (op.mask)
-      hipLaunchKernelGGL((k_diag<T, DPN, true>), grid, dim3(kBlock), 0, s, op.n_elems,
+      hipLaunchKernelGGL((k_diag<T, PH, true>), grid, dim3(kBlock), 0, s, op.n_elems,
                          op.n_nodes, xyz, op.conn, coef, op.mask, d);
     else
-      hipLaunchKernelGGL((k_diag<T, DPN, false>), grid, dim3(kBlock), 0, s, op.n_elems,
+      hipLaunchKernelGGL((k_diag<T, PH, false>), grid, dim3(kBlock), 0, s, op.n_elems,
                          op.n_nodes, xyz, op.conn, coef, op.mask, d);
   }
   Q1_HIP(hipGetLastError());
@@ -286,17 +273,13 @@ int diag_impl(Op &op, void *dv, hipStream_t s) {
 int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
   switch (op.variant) {
     case Q1_V_ATOMIC:
-      if (op.dtype == Q1_F64)
-        return op.physics == 1 ? apply_atomic<double, 1>(op, x, y, s, stop)
-                               : apply_atomic<double, 3>(op, x, y, s, stop);
-      return op.physics == 1 ? apply_atomic<float, 1>(op, x, y, s, stop)
-                             : apply_atomic<float, 3>(op, x, y, s, stop);
+      return dispatch_phys(op, [&](auto t, auto ph) {
+        return apply_atomic<decltype(t), decltype(ph)::value>(op, x, y, s, stop);
+      });
     case Q1_V_COLOR:
-      if (op.dtype == Q1_F64)
-        return op.physics == 1 ? apply_color<double, 1>(op, x, y, s, stop)
-                               : apply_color<double, 3>(op, x, y, s, stop);
-      return op.physics == 1 ? apply_color<float, 1>(op, x, y, s, stop)
-                             : apply_color<float, 3>(op, x, y, s, stop);
+      return dispatch_phys(op, [&](auto t, auto ph) {
+        return apply_color<decltype(t), decltype(ph)::value>(op, x, y, s, stop);
+      });
     case Q1_V_LDS_TILE:
     case Q1_V_BLOCK:
       return launch_apply_tile(op, x, y, s, stop);
@@ -314,7 +297,7 @@ int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop)
 // colour order so that each class is read contiguously.
 int build_colors(Op &op, hipStream_t s) {
   const int64_t ne = op.n_elems, nn = op.n_nodes;
-  const int ncoef = op.physics == 1 ? 1 : 2;
+  const int ncoef = phys_ncoef(op.physics);
   const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
   Q1_HIP(hipStreamSynchronize(s));
   std::vector<int32_t> conn(size_t(8) * ne);
@@ -366,9 +349,9 @@ void free_colors(Op &op) {
 }
 
 int launch_diag(Op &op, void *d, hipStream_t s) {
-  if (op.dtype == Q1_F64)
-    return op.physics == 1 ? diag_impl<double, 1>(op, d, s) : diag_impl<double, 3>(op, d, s);
-  return op.physics == 1 ? diag_impl<float, 1>(op, d, s) : diag_impl<float, 3>(op, d, s);
+  return dispatch_phys(op, [&](auto t, auto ph) {
+    return diag_impl<decltype(t), decltype(ph)::value>(op, d, s);
+  });
 }
 
 }  // namespace q1

@@ -34,7 +34,7 @@ __device__ __forceinline__ int find_col(const int32_t *__restrict__ col, int lo,
   return -1;
 }
 
-template <typename T, int DPN>
+template <typename T, int PH>
 __global__ __launch_bounds__(64) void k_csr_fill(int64_t ne, int64_t nn,
                                                  const T *__restrict__ xyz,
                                                  const int32_t *__restrict__ conn,
@@ -43,6 +43,7 @@ __global__ __launch_bounds__(64) void k_csr_fill(int64_t ne, int64_t nn,
                                                  const int32_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col,
                                                  T *__restrict__ val, int *__restrict__ missing) {
+  constexpr int DPN = phys_dpn(PH);
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   int32_t nid[8];
@@ -62,20 +63,12 @@ __global__ __launch_bounds__(64) void k_csr_fill(int64_t ne, int64_t nn,
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int a = 0; a < 8; ++a) X[r][a] = X0[r][a];
-      T colv[DPN][8];
-      if constexpr (DPN == 1) {
-        T u[8];
+      T colv[DPN][8], u[DPN][8];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) u[a] = a == b ? T(1) : T(0);
-        laplace_element<T>(X, u, coef[e], colv[0]);
-      } else {
-        T u[3][8];
+      for (int j = 0; j < DPN; ++j)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-          for (int a = 0; a < 8; ++a) u[j][a] = (a == b && j == jb) ? T(1) : T(0);
-        elasticity_element<T>(X, u, coef[e], coef[ne + e], colv);
-      }
+        for (int a = 0; a < 8; ++a) u[j][a] = (a == b && j == jb) ? T(1) : T(0);
+      element_apply<T, PH>(X, u, coef[e], PH == 3 ? coef[ne + e] : T(0), colv);
       const int32_t cidx = nid[b] * DPN + jb;
       for (int a = 0; a < 8; ++a) {
         if (mask && mask[nid[a]]) continue;  // eliminated row
@@ -172,7 +165,7 @@ int build_pattern(int dpn, int64_t nn, int64_t ne, const std::vector<int32_t> &c
 template <typename T>
 int csr_create_t(Op &op, hipStream_t s) {
   CsrData &m = op.csr;
-  const int dpn = op.physics;
+  const int dpn = op.dpn();
   const int64_t nn = op.n_nodes, ne = op.n_elems;
   std::vector<int32_t> conn(size_t(8) * ne), rowptr, col;
   Q1_HIP(hipStreamSynchronize(s));
@@ -194,14 +187,11 @@ int csr_create_t(Op &op, hipStream_t s) {
   Q1_HIP(hipMemsetAsync(missing, 0, sizeof(int), s));
   if (ne > 0) {
     const dim3 grid(unsigned((ne + 63) / 64));
-    if (dpn == 1)
-      hipLaunchKernelGGL((k_csr_fill<T, 1>), grid, dim3(64), 0, s, ne, nn,
-                         static_cast<const T *>(op.xyz), op.conn, static_cast<const T *>(op.coef),
-                         op.mask, m.rowptr, m.col, static_cast<T *>(m.val), missing);
-    else
-      hipLaunchKernelGGL((k_csr_fill<T, 3>), grid, dim3(64), 0, s, ne, nn,
-                         static_cast<const T *>(op.xyz), op.conn, static_cast<const T *>(op.coef),
-                         op.mask, m.rowptr, m.col, static_cast<T *>(m.val), missing);
+    auto fill = op.physics == 1 ? k_csr_fill<T, 1> : op.physics == 2 ? k_csr_fill<T, 2>
+                                                                      : k_csr_fill<T, 3>;
+    hipLaunchKernelGGL(fill, grid, dim3(64), 0, s, ne, nn, static_cast<const T *>(op.xyz),
+                       op.conn, static_cast<const T *>(op.coef), op.mask, m.rowptr, m.col,
+                       static_cast<T *>(m.val), missing);
   }
   if (op.mask) {
     const dim3 grid(unsigned((m.nrows + 255) / 256));
@@ -226,8 +216,8 @@ int spmv_t(const Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const CsrData &m = op.csr;
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
-  // 27 entries per row (scalar) -> 16 lanes; 81 (vector) -> 32 lanes
-  if (op.physics == 1) {
+  // 27 entries per row (scalar) -> 16 lanes; 81 (3 DOF per node) -> 32 lanes
+  if (op.dpn() == 1) {
     const int64_t thr = m.nrows * 16;
     hipLaunchKernelGGL((k_spmv<T, 16>), dim3(unsigned((thr + 255) / 256)), dim3(256), 0, s,
                        m.nrows, m.rowptr, m.col, static_cast<const T *>(m.val), x, y, stop);

@@ -137,17 +137,25 @@ struct QpGeom {
 };
 
 // ---------------------------------------------------------------------------
-// Scalar Laplace: X [3][8] nodal coordinates (destroyed), u [8] nodal input,
-// k cell coefficient; v [8] nodal output (v_e = A_e u_e).
+// Laplace on NC components sharing one coefficient: component c of the output
+// is the scalar Laplace action on component c of the input (NC = 1 scalar
+// Laplace, NC = 3 the vector Laplace, whose components do not couple).
+// X [3][8] nodal coordinates (destroyed), u [NC][8] nodal input, k cell
+// coefficient; v [NC][8] nodal output (v_e = A_e u_e).  The geometry is
+// evaluated once for all components.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void laplace_element(T X[3][8], const T u_in[8], T k, T v[8]) {
-  T u[8];
+template <typename T, int NC>
+__device__ __forceinline__ void laplace_element_n(T X[3][8], const T (*u_in)[8], T k,
+                                                  T (*v)[8]) {
+  T u[NC][8];
 #pragma unroll
-  for (int a = 0; a < 8; ++a) u[a] = u_in[a];
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[c][a] = u_in[c][a];
+    butterfly_fwd(u[c]);
+  }
   butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
-  butterfly_fwd(u);
-  T w[8];
+  T w[NC][8];
   if (is_affine(X)) {
     // constant Jacobian: exact modal integration of grad psi_m . D grad u
     const T C1[3] = {X[0][1], X[1][1], X[2][1]};
@@ -159,14 +167,19 @@ __device__ __forceinline__ void laplace_element(T X[3][8], const T u_in[8], T k,
     const T s = k * rcp(T(64) * det);
     const T D00 = s * dot3(a0, a0), D01 = s * dot3(a0, a1), D02 = s * dot3(a0, a2);
     const T D11 = s * dot3(a1, a1), D12 = s * dot3(a1, a2), D22 = s * dot3(a2, a2);
-    w[0] = T(0);
-    w[1] = D00 * u[1] + D01 * u[2] + D02 * u[4];
-    w[2] = D01 * u[1] + D11 * u[2] + D12 * u[4];
-    w[4] = D02 * u[1] + D12 * u[2] + D22 * u[4];
-    w[3] = C<T>::third * ((D00 + D11) * u[3] + D02 * u[6] + D12 * u[5]);
-    w[5] = C<T>::third * ((D00 + D22) * u[5] + D01 * u[6] + D12 * u[3]);
-    w[6] = C<T>::third * ((D11 + D22) * u[6] + D01 * u[5] + D02 * u[3]);
-    w[7] = C<T>::ninth * (D00 + D11 + D22) * u[7];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T *uc = u[c];
+      T *wc = w[c];
+      wc[0] = T(0);
+      wc[1] = D00 * uc[1] + D01 * uc[2] + D02 * uc[4];
+      wc[2] = D01 * uc[1] + D11 * uc[2] + D12 * uc[4];
+      wc[4] = D02 * uc[1] + D12 * uc[2] + D22 * uc[4];
+      wc[3] = C<T>::third * ((D00 + D11) * uc[3] + D02 * uc[6] + D12 * uc[5]);
+      wc[5] = C<T>::third * ((D00 + D22) * uc[5] + D01 * uc[6] + D12 * uc[3]);
+      wc[6] = C<T>::third * ((D11 + D22) * uc[6] + D01 * uc[5] + D02 * uc[3]);
+      wc[7] = C<T>::ninth * (D00 + D11 + D22) * uc[7];
+    }
   } else {
     T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
 #pragma unroll
@@ -175,11 +188,18 @@ __device__ __forceinline__ void laplace_element(T X[3][8], const T u_in[8], T k,
       eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);  // [ix][iz]
       eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);  // [ix][iy]
     }
-    T gx[2][2], gy[2][2], gz[2][2];
-    eval4(u[1], u[3], u[5], u[7], gx);
-    eval4(u[2], u[3], u[6], u[7], gy);
-    eval4(u[4], u[5], u[6], u[7], gz);
-    T Fx[2][2] = {{0, 0}, {0, 0}}, Fy[2][2] = {{0, 0}, {0, 0}}, Fz[2][2] = {{0, 0}, {0, 0}};
+    T gx[NC][2][2], gy[NC][2][2], gz[NC][2][2];
+    T Fx[NC][2][2], Fy[NC][2][2], Fz[NC][2][2];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      eval4(u[c][1], u[c][3], u[c][5], u[c][7], gx[c]);
+      eval4(u[c][2], u[c][3], u[c][6], u[c][7], gy[c]);
+      eval4(u[c][4], u[c][5], u[c][6], u[c][7], gz[c]);
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) Fx[c][p][q] = Fy[c][p][q] = Fz[c][p][q] = T(0);
+    }
     const T ks = k * T(1.0 / 512.0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -190,41 +210,56 @@ __device__ __forceinline__ void laplace_element(T X[3][8], const T u_in[8], T k,
       T a0[3], a1[3], a2[3];
       cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
       const T s = ks * rcp(dot3(jx, a0));
-      const T g0 = gx[iy][iz], g1 = gy[ix][iz], g2 = gz[ix][iy];
-      T t[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) t[c] = s * (g0 * a0[c] + g1 * a1[c] + g2 * a2[c]);
-      Fx[iy][iz] += dot3(a0, t);
-      Fy[ix][iz] += dot3(a1, t);
-      Fz[ix][iy] += dot3(a2, t);
+      for (int c = 0; c < NC; ++c) {
+        const T g0 = gx[c][iy][iz], g1 = gy[c][ix][iz], g2 = gz[c][ix][iy];
+        T t[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) t[d] = s * (g0 * a0[d] + g1 * a1[d] + g2 * a2[d]);
+        Fx[c][iy][iz] += dot3(a0, t);
+        Fy[c][ix][iz] += dot3(a1, t);
+        Fz[c][ix][iy] += dot3(a2, t);
+      }
     }
-    T r0, r1, r2, r3;
-    eval4T(Fx, r0, r1, r2, r3);
-    w[1] = r0; w[3] = r1; w[5] = r2; w[7] = r3;
-    eval4T(Fy, r0, r1, r2, r3);
-    w[2] = r0; w[3] += r1; w[6] = r2; w[7] += r3;
-    eval4T(Fz, r0, r1, r2, r3);
-    w[4] = r0; w[5] += r1; w[6] += r2; w[7] += r3;
-    w[0] = T(0);
-  }
-  butterfly_bwd(w);
 #pragma unroll
-  for (int a = 0; a < 8; ++a) v[a] = w[a];
+    for (int c = 0; c < NC; ++c) {
+      T *wc = w[c];
+      T r0, r1, r2, r3;
+      eval4T(Fx[c], r0, r1, r2, r3);
+      wc[1] = r0; wc[3] = r1; wc[5] = r2; wc[7] = r3;
+      eval4T(Fy[c], r0, r1, r2, r3);
+      wc[2] = r0; wc[3] += r1; wc[6] = r2; wc[7] += r3;
+      eval4T(Fz[c], r0, r1, r2, r3);
+      wc[4] = r0; wc[5] += r1; wc[6] += r2; wc[7] += r3;
+      wc[0] = T(0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    butterfly_bwd(w[c]);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[c][a] = w[c][a];
+  }
 }
 
-// Scalar Laplace on an element already known to be a parallelepiped (the
-// bilinear and trilinear coordinate modes vanish, checked once at set-up):
-// the constant Jacobian comes from the three edges at corner 0, E_c = X_c - X_0
-// for c = 1, 2, 4 (J' = 4 E), so D = k / (16 det E) adj(E) adj(E)^T and the
-// modal action is the closed form of laplace_element's affine branch.  Reads
-// corners 0, 1, 2, 4 of X only.
+// Scalar Laplace: X [3][8] nodal coordinates (destroyed), u [8] nodal input,
+// k cell coefficient; v [8] nodal output.
 template <typename T>
-__device__ __forceinline__ void laplace_element_parallelepiped(const T X[3][8], const T u_in[8],
-                                                               T k, T v[8]) {
-  T u[8];
-#pragma unroll
-  for (int a = 0; a < 8; ++a) u[a] = u_in[a];
-  butterfly_fwd(u);
+__device__ __forceinline__ void laplace_element(T X[3][8], const T u_in[8], T k, T v[8]) {
+  laplace_element_n<T, 1>(X, reinterpret_cast<const T(*)[8]>(u_in), k,
+                          reinterpret_cast<T(*)[8]>(v));
+}
+
+// Laplace on NC components over an element already known to be a
+// parallelepiped (the bilinear and trilinear coordinate modes vanish, checked
+// once at set-up): the constant Jacobian comes from the three edges at corner
+// 0, E_c = X_c - X_0 for c = 1, 2, 4 (J' = 4 E), so D = k / (16 det E) adj(E)
+// adj(E)^T and the modal action is the closed form of the affine branch above.
+// Reads corners 0, 1, 2, 4 of X only.
+template <typename T, int NC>
+__device__ __forceinline__ void laplace_element_parallelepiped_n(const T X[3][8],
+                                                                 const T (*u_in)[8], T k,
+                                                                 T (*v)[8]) {
   const T E1[3] = {X[0][1] - X[0][0], X[1][1] - X[1][0], X[2][1] - X[2][0]};
   const T E2[3] = {X[0][2] - X[0][0], X[1][2] - X[1][0], X[2][2] - X[2][0]};
   const T E4[3] = {X[0][4] - X[0][0], X[1][4] - X[1][0], X[2][4] - X[2][0]};
@@ -233,18 +268,32 @@ __device__ __forceinline__ void laplace_element_parallelepiped(const T X[3][8], 
   const T s = k * rcp(T(16) * dot3(E1, a0));
   const T D00 = s * dot3(a0, a0), D01 = s * dot3(a0, a1), D02 = s * dot3(a0, a2);
   const T D11 = s * dot3(a1, a1), D12 = s * dot3(a1, a2), D22 = s * dot3(a2, a2);
-  T w[8];
-  w[0] = T(0);
-  w[1] = D00 * u[1] + D01 * u[2] + D02 * u[4];
-  w[2] = D01 * u[1] + D11 * u[2] + D12 * u[4];
-  w[4] = D02 * u[1] + D12 * u[2] + D22 * u[4];
-  w[3] = C<T>::third * ((D00 + D11) * u[3] + D02 * u[6] + D12 * u[5]);
-  w[5] = C<T>::third * ((D00 + D22) * u[5] + D01 * u[6] + D12 * u[3]);
-  w[6] = C<T>::third * ((D11 + D22) * u[6] + D01 * u[5] + D02 * u[3]);
-  w[7] = C<T>::ninth * (D00 + D11 + D22) * u[7];
-  butterfly_bwd(w);
 #pragma unroll
-  for (int a = 0; a < 8; ++a) v[a] = w[a];
+  for (int c = 0; c < NC; ++c) {
+    T u[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[a] = u_in[c][a];
+    butterfly_fwd(u);
+    T w[8];
+    w[0] = T(0);
+    w[1] = D00 * u[1] + D01 * u[2] + D02 * u[4];
+    w[2] = D01 * u[1] + D11 * u[2] + D12 * u[4];
+    w[4] = D02 * u[1] + D12 * u[2] + D22 * u[4];
+    w[3] = C<T>::third * ((D00 + D11) * u[3] + D02 * u[6] + D12 * u[5]);
+    w[5] = C<T>::third * ((D00 + D22) * u[5] + D01 * u[6] + D12 * u[3]);
+    w[6] = C<T>::third * ((D11 + D22) * u[6] + D01 * u[5] + D02 * u[3]);
+    w[7] = C<T>::ninth * (D00 + D11 + D22) * u[7];
+    butterfly_bwd(w);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[c][a] = w[a];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void laplace_element_parallelepiped(const T X[3][8], const T u_in[8],
+                                                               T k, T v[8]) {
+  laplace_element_parallelepiped_n<T, 1>(X, reinterpret_cast<const T(*)[8]>(u_in), k,
+                                         reinterpret_cast<T(*)[8]>(v));
 }
 
 // ---------------------------------------------------------------------------
@@ -347,6 +396,26 @@ __device__ __forceinline__ void elasticity_element(T X[3][8], const T u_in[3][8]
 #pragma unroll
     for (int a = 0; a < 8; ++a) v[i][a] = w[a];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Physics kinds (the values of the public enum): 1 scalar Laplace, 2 vector
+// Laplace, 3 isotropic elasticity.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int phys_dpn(int ph) { return ph == 1 ? 1 : 3; }
+__host__ __device__ constexpr int phys_ncoef(int ph) { return ph == 3 ? 2 : 1; }
+
+// v_e = A_e u_e for kind PH: u, v [dpn][8]; c0 = k (Laplace kinds) or lambda,
+// c1 = mu (elasticity).  X is destroyed.
+template <typename T, int PH>
+__device__ __forceinline__ void element_apply(T X[3][8], const T (*u)[8], T c0, T c1,
+                                              T (*v)[8]) {
+  if constexpr (PH == 1)
+    laplace_element_n<T, 1>(X, u, c0, v);
+  else if constexpr (PH == 2)
+    laplace_element_n<T, 3>(X, u, c0, v);
+  else
+    elasticity_element<T>(X, u, c0, c1, v);
 }
 
 }  // namespace q1

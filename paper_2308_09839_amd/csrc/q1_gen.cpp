@@ -178,10 +178,10 @@ int q1_vec_uniform(int64_t n, uint64_t seed, uint64_t stream, double lo, double 
 /* Section 4 byte model (Tables 1-3). */
 int q1_model_bytes(int kind, int physics, int real_bytes, int coef_bytes, int64_t n_nodes,
                    int64_t n_elems, int cache, double *bytes) {
-  Q1_CHECK(bytes && (physics == 1 || physics == 3) && (real_bytes == 4 || real_bytes == 8) &&
+  Q1_CHECK(bytes && physics >= 1 && physics <= 3 && (real_bytes == 4 || real_bytes == 8) &&
                n_nodes >= 0 && n_elems >= 0 && coef_bytes >= 0 && (cache == 0 || cache == 1),
            Q1_EINVAL, "q1_model_bytes: bad arguments");
-  const double dpn = physics, R = real_bytes;
+  const double dpn = physics == 1 ? 1.0 : 3.0, R = real_bytes;
   const double ndof = double(n_nodes) * dpn;
   // nodal data read once (perfect cache) or once per element corner (no cache)
   const double node_reads = cache == 0 ? double(n_nodes) : 8.0 * double(n_elems);
@@ -197,7 +197,8 @@ int q1_model_bytes(int kind, int physics, int real_bytes, int coef_bytes, int64_
       return Q1_OK;
     }
     case 2: {  // partial assembly: node map, cell constant, 8 qp x (6 | 21) reals, vectors
-      const double per_qp = physics == 1 ? 6.0 : 21.0;
+      // (the Laplace kinds store the symmetric 3x3 geometric factor, elasticity 21 reals)
+      const double per_qp = physics == 3 ? 21.0 : 6.0;
       *bytes = double(n_elems) * (32.0 + coef_bytes) + double(n_elems) * 8.0 * per_qp * R +
                node_reads * 3.0 * dpn * R;
       return Q1_OK;

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "q1mf.h"
@@ -69,7 +70,8 @@ struct ColorMap {
 };
 
 struct Op {
-  int physics = 1;  // DOF per node
+  int physics = 1;  // kind: 1 scalar Laplace, 2 vector Laplace, 3 elasticity
+  int dpn() const { return physics == 1 ? 1 : 3; }  // DOF per node
   int dtype = Q1_F64;
   int variant = Q1_V_ATOMIC;
   int64_t n_nodes = 0, n_elems = 0;
@@ -85,6 +87,24 @@ struct Op {
 };
 
 inline int xcd_count() { return 8; }
+
+// Calls f(T{}, std::integral_constant<int, PH>{}) for the operator's dtype and
+// physics kind (1 scalar Laplace, 2 vector Laplace, 3 elasticity).
+template <typename F>
+int dispatch_phys(const Op &op, F &&f) {
+  if (op.dtype == Q1_F64) {
+    switch (op.physics) {
+      case 1: return f(double{}, std::integral_constant<int, 1>{});
+      case 2: return f(double{}, std::integral_constant<int, 2>{});
+      default: return f(double{}, std::integral_constant<int, 3>{});
+    }
+  }
+  switch (op.physics) {
+    case 1: return f(float{}, std::integral_constant<int, 1>{});
+    case 2: return f(float{}, std::integral_constant<int, 2>{});
+    default: return f(float{}, std::integral_constant<int, 3>{});
+  }
+}
 
 // launchers (defined in the .hip files)
 // stop: optional device flag; when it is non-zero at kernel start the launch does nothing

@@ -12,6 +12,9 @@ namespace {
 // (Jacobian at 8 points, adjugate and determinant, gradient, flux, transpose).
 constexpr double kFlopsLaplace = 1070.0;
 constexpr double kFlopsElasticity = 2070.0;
+// vector Laplace: the geometry (Jacobians, adjugates, determinants: 780 of the
+// scalar 1,070) once, the gradient, flux and transpose (290) per component
+constexpr double kFlopsVLaplace = 780.0 + 3.0 * 290.0;
 
 int check_device_ptr(const void *p, const char *what) {
   if (!p) return fail(Q1_EINVAL, "%s is NULL", what);
@@ -40,8 +43,10 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
                  const uint8_t *mask_d, void *stream) {
   Q1_CHECK(out, Q1_EINVAL, "q1_op_create: NULL handle pointer");
   *out = nullptr;
-  Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_ELASTICITY, Q1_EINVAL,
-           "q1_op_create: physics must be 1 (Laplace) or 3 (elasticity), got %d", physics);
+  Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_VLAPLACE || physics == Q1_ELASTICITY,
+           Q1_EINVAL,
+           "q1_op_create: physics must be 1 (Laplace), 2 (vector Laplace) or 3 (elasticity), "
+           "got %d", physics);
   Q1_CHECK(dtype == Q1_F64 || dtype == Q1_F32, Q1_EINVAL, "q1_op_create: bad dtype %d", dtype);
   Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC || variant == Q1_V_COLOR ||
                variant == Q1_V_LDS_TILE || variant == Q1_V_BLOCK,
@@ -144,13 +149,15 @@ int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
     if (flops) *flops = 2.0 * double(op->csr.nnz);
     return Q1_OK;
   }
-  const int coef_bytes = rb * (op->physics == 1 ? 1 : 2);
+  const int coef_bytes = rb * (op->physics == Q1_ELASTICITY ? 2 : 1);
   double b = 0.0;
   int rc = q1_model_bytes(1, op->physics, rb, coef_bytes, op->n_nodes, op->n_elems, 0, &b);
   if (rc) return rc;
   if (bytes) *bytes = b;
   if (flops)
-    *flops = double(op->n_elems) * (op->physics == 1 ? kFlopsLaplace : kFlopsElasticity);
+    *flops = double(op->n_elems) * (op->physics == Q1_LAPLACE     ? kFlopsLaplace
+                                    : op->physics == Q1_VLAPLACE ? kFlopsVLaplace
+                                                                 : kFlopsElasticity);
   return Q1_OK;
 }
 

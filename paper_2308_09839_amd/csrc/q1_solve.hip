@@ -460,7 +460,7 @@ int alloc_work(Work &W, int64_t n, bool flex) {
 
 template <typename T>
 int setup_diag(Op &op, Work &W, int pc, hipStream_t s) {
-  const int64_t n = op.n_nodes * op.physics;
+  const int64_t n = op.n_nodes * op.dpn();
   if (pc == Q1_PC_JACOBI) {
     const int rc = launch_diag(op, W.q, s);  // q as scratch
     if (rc) return rc;
@@ -480,7 +480,7 @@ int read_status(Work &W, hipStream_t s) {
 // ||b - A x||_2 / ||b||_2 with q and two partial rows as scratch (synchronises)
 template <typename T>
 int true_residual(Op &op, Work &W, const T *b, const T *x, double *out, hipStream_t s) {
-  const int64_t n = op.n_nodes * op.physics;
+  const int64_t n = op.n_nodes * op.dpn();
   const int nb = nblocks_for(n);
   T *q = static_cast<T *>(W.q);
   int rc = launch_apply(op, x, q, s);
@@ -512,7 +512,7 @@ struct Snapshots {
 template <typename T>
 int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *stats,
           hipStream_t s, bool true_res, const Snapshots &snap = Snapshots()) {
-  const int64_t n = op.n_nodes * op.physics;
+  const int64_t n = op.n_nodes * op.dpn();
   Work W;
   int rc = alloc_work<T>(W, n, false);
   if (rc) return rc;
@@ -596,7 +596,7 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
 template <typename T>
 int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, int maxit,
            int safeguard_m, int m, q1_stats *stats, hipStream_t s) {
-  const int64_t n = op.n_nodes * op.physics;
+  const int64_t n = op.n_nodes * op.dpn();
   Work W;
   int rc = alloc_work<T>(W, n, true);
   if (rc) return rc;
@@ -728,7 +728,7 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
 // direction is kept, so the Krylov history survives the refresh.
 int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double delta, int maxit,
            q1_stats *stats, hipStream_t s) {
-  const int64_t n = A64.n_nodes * A64.physics;
+  const int64_t n = A64.n_nodes * A64.dpn();
   Work W;  // FP32 recurrences
   int rc = alloc_work<float>(W, n, false);
   if (rc) return rc;
@@ -918,7 +918,7 @@ int q1_jacobi_create(q1_jacobi **out, q1_op *op, void *stream) {
   q1_jacobi *J = new (std::nothrow) q1_jacobi();
   Q1_CHECK(J, Q1_ENOMEM, "q1_jacobi_create: out of host memory");
   J->op = &o;
-  const int64_t n = o.n_nodes * o.physics;
+  const int64_t n = o.n_nodes * o.dpn();
   const size_t rb = o.dtype == Q1_F64 ? 8 : 4;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipMalloc(&J->w, size_t(n) * rb) != hipSuccess) {
@@ -947,7 +947,7 @@ int q1_jacobi_create(q1_jacobi **out, q1_op *op, void *stream) {
 int q1_precond_jacobi(void *ctx, const void *r_d, void *z_d, void *stream) {
   Q1_CHECK(ctx && r_d && z_d, Q1_EINVAL, "q1_precond_jacobi: NULL argument");
   q1_jacobi *J = static_cast<q1_jacobi *>(ctx);
-  const int64_t n = J->op->n_nodes * J->op->physics;
+  const int64_t n = J->op->n_nodes * J->op->dpn();
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (J->op->dtype == Q1_F64)
     hipLaunchKernelGGL((k_jacobi<double>), grid1(n), dim3(256), 0, s, n,
@@ -994,7 +994,7 @@ int q1_ir_solve(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double
   Q1_CHECK(rtol > 0 && inner_rtol > 0 && inner_rtol < 1 && max_outer > 0 && max_inner > 0,
            Q1_EINVAL, "q1_ir_solve: bad tolerances or limits");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = A64.n_nodes * A64.physics;
+  const int64_t n = A64.n_nodes * A64.dpn();
   const auto t0 = std::chrono::steady_clock::now();
   Work W;  // FP64 residual, norms
   int rc = alloc_work<double>(W, n, false);

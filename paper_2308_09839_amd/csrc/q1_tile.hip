@@ -82,7 +82,7 @@ __device__ __forceinline__ void acc_add(T *p, T v) {
     *p += v;
 }
 
-template <typename T, int DPN, bool LDS_ATOMIC>
+template <typename T, int PH, bool LDS_ATOMIC>
 __global__ __launch_bounds__(64) void k_apply_tile(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,  // [n_tiles+1]
     const uint32_t *__restrict__ nodes,                                 // ids | flags
@@ -90,6 +90,7 @@ __global__ __launch_bounds__(64) void k_apply_tile(
     const uint4 *__restrict__ lconn,                                    // [n_steps*64]
     const T *__restrict__ coef_t, int64_t coef_stride, const T *__restrict__ xyz,
     const T *__restrict__ x, T *__restrict__ y, const int *__restrict__ stop) {
+  constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sV = reinterpret_cast<T *>(smem_raw);                             // [DPN][max_nodes]
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(64) void k_apply_tile(
   // first step's corner indices and coefficients
   uint4 pk_n = lconn[int64_t(s0) * kLanes + lane];
   T c0_n = coef_t[int64_t(s0) * kLanes + lane];
-  T c1_n = DPN == 3 ? coef_t[coef_stride + int64_t(s0) * kLanes + lane] : T(0);
+  T c1_n = PH == 3 ? coef_t[coef_stride + int64_t(s0) * kLanes + lane] : T(0);
   for (int i = lane; i < nm; i += kLanes) {
     sId[i] = nodes[n0 + i];
 #pragma unroll
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(64) void k_apply_tile(
       const int64_t nslot = int64_t(min(s + 1, s1 - 1)) * kLanes + lane;
       pk_n = lconn[nslot];
       c0_n = coef_t[nslot];
-      if constexpr (DPN == 3) c1_n = coef_t[coef_stride + nslot];
+      if constexpr (PH == 3) c1_n = coef_t[coef_stride + nslot];
     }
     if (pk.x == 0xffffffffu) continue;  // empty lane
     const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16),
@@ -135,25 +136,16 @@ __global__ __launch_bounds__(64) void k_apply_tile(
       X[1][a] = xyz[nn + g[a]];
       X[2][a] = xyz[2 * nn + g[a]];
     }
-    if constexpr (DPN == 1) {
-      T u[8], v[8];
+    T u[DPN][8], v[DPN][8];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) u[a] = fixed[a] ? T(0) : x[g[a]];
-      laplace_element<T>(X, u, c0, v);
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-      for (int a = 0; a < 8; ++a) acc_add<T, LDS_ATOMIC>(&sV[lc[a]], v[a]);
-    } else {
-      T u[3][8], v[3][8];
+      for (int j = 0; j < DPN; ++j) u[j][a] = fixed[a] ? T(0) : x[g[a] * DPN + j];
+    element_apply<T, PH>(X, u, c0, c1, v);
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) u[j][a] = fixed[a] ? T(0) : x[g[a] * 3 + j];
-      elasticity_element<T>(X, u, c0, c1, v);
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc_add<T, LDS_ATOMIC>(&sV[j * max_nodes + lc[a]], v[j][a]);
-    }
+      for (int j = 0; j < DPN; ++j) acc_add<T, LDS_ATOMIC>(&sV[j * max_nodes + lc[a]], v[j][a]);
   }
   __syncthreads();
   for (int i = lane; i < nm; i += kLanes) {
@@ -179,13 +171,14 @@ __global__ __launch_bounds__(64) void k_apply_tile(
 // being added in a fixed order when the tile's nodes are written.
 // One wave's steps of a tile: corners from the staged records, element product,
 // accumulation into LDS.  PAR: every element is known to be a
-// parallelepiped (scalar problems), so only corners 0, 1, 2, 4 give geometry.
-template <typename T, int DPN, bool LDS_ATOMIC, bool PAR>
+// parallelepiped (Laplace kinds), so only corners 0, 1, 2, 4 give geometry.
+template <typename T, int PH, bool LDS_ATOMIC, bool PAR>
 __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nodes,
                                             const T *__restrict__ sR, T *__restrict__ myV,
                                             const uint4 *__restrict__ lconn,
                                             const T *__restrict__ coef_t, int64_t coef_stride,
                                             uint4 pk_n, T c0_n, T c1_n) {
+  constexpr int DPN = phys_dpn(PH);
   // pk_n, c0_n, c1_n: this wave's first step, loaded by the caller before staging
   for (; s < s1; s += 4) {
     const uint4 pk = pk_n;
@@ -194,7 +187,7 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
       const int64_t slot = int64_t(s + 4 < s1 ? s + 4 : s) * kLanes + lane;
       pk_n = lconn[slot];
       c0_n = coef_t[slot];
-      if constexpr (DPN == 3) c1_n = coef_t[coef_stride + slot];
+      if constexpr (PH == 3) c1_n = coef_t[coef_stride + slot];
     }
     if (pk.x == 0xffffffffu) continue;  // empty lane
     const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16),
@@ -210,29 +203,22 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
 #pragma unroll
       for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(3 + j) * max_nodes];
     }
-    if constexpr (DPN == 1) {
-      T v[8];
-      if constexpr (PAR)
-        laplace_element_parallelepiped<T>(X, u[0], c0, v);
-      else
-        laplace_element<T>(X, u[0], c0, v);
+    T v[DPN][8];
+    if constexpr (PAR && PH != 3)
+      laplace_element_parallelepiped_n<T, DPN>(X, u, c0, v);
+    else
+      element_apply<T, PH>(X, u, c0, c1, v);
 #pragma unroll
-      for (int a = 0; a < 8; ++a) acc_add<T, LDS_ATOMIC>(&myV[lc[a]], v[a]);
-    } else {
-      T v[3][8];
-      elasticity_element<T>(X, u, c0, c1, v);
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc_add<T, LDS_ATOMIC>(&myV[j * max_nodes + lc[a]], v[j][a]);
-    }
+      for (int j = 0; j < DPN; ++j) acc_add<T, LDS_ATOMIC>(&myV[j * max_nodes + lc[a]], v[j][a]);
   }
 }
 
 // ONEACC: the four waves add into one LDS accumulator with LDS atomics (FP64,
 // where it frees LDS for a fourth resident block); otherwise each wave owns a
 // copy and the copies are summed in a fixed order.
-template <typename T, int DPN, bool LDS_ATOMIC, bool ONEACC>
+template <typename T, int PH, bool LDS_ATOMIC, bool ONEACC>
 __global__ __launch_bounds__(256) void k_apply_block(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
@@ -240,6 +226,7 @@ __global__ __launch_bounds__(256) void k_apply_block(
     const T *__restrict__ xyz, const T *__restrict__ x, T *__restrict__ y,
     const int *__restrict__ stop, const uint8_t *__restrict__ tile_affine,
     const int32_t *__restrict__ slot, T *__restrict__ halo) {
+  constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
   constexpr int NR = 3 + DPN;  // x, y, z, u[DPN], stored field by field
   constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
@@ -258,7 +245,7 @@ __global__ __launch_bounds__(256) void k_apply_block(
     const int64_t slot = int64_t(s0 + w) * kLanes + lane;
     pk0 = lconn[slot];
     c00 = coef_t[slot];
-    if constexpr (DPN == 3) c10 = coef_t[coef_stride + slot];
+    if constexpr (PH == 3) c10 = coef_t[coef_stride + slot];
   }
   // stage the node records: all loads of a round are issued (unconditionally,
   // at clamped indices) before any LDS write, so the round costs one latency.
@@ -303,11 +290,11 @@ __global__ __launch_bounds__(256) void k_apply_block(
   }
   __syncthreads();
   T *myV = ONEACC ? sV : sV + size_t(w) * DPN * max_nodes;
-  if (DPN == 1 && tile_affine[tile])
-    block_steps<T, DPN, LDS_ATOMIC || ONEACC, true>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+  if (PH != 3 && tile_affine[tile])
+    block_steps<T, PH, LDS_ATOMIC || ONEACC, true>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
                                           coef_stride, pk0, c00, c10);
   else
-    block_steps<T, DPN, LDS_ATOMIC || ONEACC, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+    block_steps<T, PH, LDS_ATOMIC || ONEACC, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
                                            coef_stride, pk0, c00, c10);
   __syncthreads();
   // nodes of this tile only: y; nodes shared with other tiles: this tile's halo
@@ -515,7 +502,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
 template <typename T>
 int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   const int64_t ne = op.n_elems, nn = op.n_nodes;
-  const int ncoef = op.physics == 1 ? 1 : 2;
+  const int ncoef = phys_ncoef(op.physics);
   TileMap &tm = op.tiles;
   Q1_CHECK(nn <= int64_t(kIdMask), Q1_EUNSUPPORTED, "LDS-tile variant supports < 2^30 nodes");
   Q1_HIP(hipStreamSynchronize(s));
@@ -562,7 +549,7 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   if (op.variant == Q1_V_BLOCK) {
     if ((rc = up(&tm.slot, H.slot)) || (rc = up(&tm.hptr, H.hptr))) return rc;
     tm.n_halo = H.hptr.back();
-    const size_t hb = std::max<int64_t>(1, tm.n_halo) * op.physics * sizeof(T);
+    const size_t hb = std::max<int64_t>(1, tm.n_halo) * op.dpn() * sizeof(T);
     Q1_HIP(hipMalloc(&tm.halo, hb));
     tm.bytes += hb;
   }
@@ -574,11 +561,12 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
 size_t block_lds_bytes(const Op &op) {
   const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
   const size_t nacc = op.dtype == Q1_F64 ? 1 : 4;
-  return size_t(op.tiles.max_nodes) * rb * size_t(3 + op.physics + nacc * op.physics);
+  return size_t(op.tiles.max_nodes) * rb * size_t(3 + op.dpn() + nacc * op.dpn());
 }
 
-template <typename T, int DPN>
+template <typename T, int PH>
 int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
+  constexpr int DPN = phys_dpn(PH);
   const TileMap &tm = op.tiles;
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
@@ -589,7 +577,7 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block) {
     constexpr bool one = std::is_same<T, double>::value;
-    auto kb = tm.lds_atomic ? k_apply_block<T, DPN, true, one> : k_apply_block<T, DPN, false, one>;
+    auto kb = tm.lds_atomic ? k_apply_block<T, PH, true, one> : k_apply_block<T, PH, false, one>;
     hipLaunchKernelGGL(kb, dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes, op.n_nodes,
                        tm.node_ptr, tm.nodes, tm.tile_step,
                        reinterpret_cast<const uint4 *>(tm.lconn),
@@ -603,7 +591,7 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
     Q1_HIP(hipGetLastError());
     return Q1_OK;
   }
-  auto kern = tm.lds_atomic ? k_apply_tile<T, DPN, true> : k_apply_tile<T, DPN, false>;
+  auto kern = tm.lds_atomic ? k_apply_tile<T, PH, true> : k_apply_tile<T, PH, false>;
   hipLaunchKernelGGL(kern, dim3(tm.n_tiles), dim3(kLanes), lds, s, tm.max_nodes,
                      op.n_nodes,
                      tm.node_ptr, tm.nodes, tm.tile_step,
@@ -619,7 +607,7 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
 // Tile shape in elements: PATCH_X x PATCH_Y per step (one wavefront), LAYERS steps.
 // Wide-in-x patches keep each wave-wide gather on few cache lines (measured:
 // 32x2x4 beats 8x8x8 by 17% in FP64 and 32% in FP32 on a 128^3 grid).
-static int tile_layers(const Op &op) { return op.physics == 1 ? 4 : 2; }
+static int tile_layers(const Op &op) { return op.dpn() == 1 ? 4 : 2; }
 static int tile_patch_x(const Op &) { return 32; }
 
 // Block-staged tiles: 32 x 4 x 4 elements for scalar problems (two wavefront
@@ -628,7 +616,7 @@ static int tile_patch_x(const Op &) { return 32; }
 // and 16 x 4 x 4 for elasticity (LDS); Q1_BLOCK_SHAPE="px,py,layers"
 // overrides the shape.
 static void block_shape(const Op &op, int &px, int &py, int &layers) {
-  px = op.physics == 1 ? 32 : 16;
+  px = op.dpn() == 1 ? 32 : 16;
   py = 4;
   layers = 4;
   if (const char *e = std::getenv("Q1_BLOCK_SHAPE")) {
@@ -656,17 +644,15 @@ int build_tiles(Op &op, hipStream_t s) {
   if (rc) return rc;
   const size_t lds = op.variant == Q1_V_BLOCK
                          ? block_lds_bytes(op)
-                         : size_t(op.tiles.max_nodes) * (op.physics * (op.dtype == Q1_F64 ? 8 : 4) + 4);
+                         : size_t(op.tiles.max_nodes) * (op.dpn() * (op.dtype == Q1_F64 ? 8 : 4) + 4);
   Q1_CHECK(lds <= 64 * 1024, Q1_EUNSUPPORTED, "tile needs %zu B of LDS", lds);
   return Q1_OK;
 }
 
 int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
-  if (op.dtype == Q1_F64)
-    return op.physics == 1 ? apply_tile_t<double, 1>(op, x, y, s, stop)
-                           : apply_tile_t<double, 3>(op, x, y, s, stop);
-  return op.physics == 1 ? apply_tile_t<float, 1>(op, x, y, s, stop)
-                         : apply_tile_t<float, 3>(op, x, y, s, stop);
+  return dispatch_phys(op, [&](auto t, auto ph) {
+    return apply_tile_t<decltype(t), decltype(ph)::value>(op, x, y, s, stop);
+  });
 }
 
 void free_tiles(Op &op) {

@@ -207,6 +207,15 @@ def problem_laplace_layered(n: int = 128, seed: int = 2309):
     return dict(physics=1, n=(n, n, n), xyz=xyz, conn=conn, coef=k[None, :], mask=None)
 
 
+def problem_vlaplace(n: int = 96, seed: int = 2313, jitter: float = 0.0):
+    """Vector Laplace (3 DOF per node) on n^3 elements, k = exp(N(0,1)) iid
+    per cell, Dirichlet (all components) on z=0."""
+    xyz, conn = box_mesh(n, n, n, 1.0, jitter, seed)
+    k = field_lognormal(n ** 3, 0.0, 1.0, seed)
+    mask = face_mask(n, n, n, "z0")
+    return dict(physics=2, n=(n, n, n), xyz=xyz, conn=conn, coef=k[None, :], mask=mask)
+
+
 def problem_elasticity(n: int = 96, seed: int = 2310, jitter: float = 0.0):
     """Isotropic elasticity on n^3 elements, E = exp(N(ln 10,1)),
     nu ~ U(0.15,0.35) per cell, Dirichlet (all components) on z=0."""

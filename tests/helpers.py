@@ -51,7 +51,7 @@ def gpu_diag(op, n: int, dtype: int) -> np.ndarray:
 def problem(physics: int, n, jitter: float, seed: int, mask: bool = True, coef_kind="iid"):
     xyz, conn = si.box_mesh(*n, 1.0, jitter, seed)
     ne = int(np.prod(n))
-    if physics == 1:
+    if physics in (1, 2):  # scalar and vector Laplace: one coefficient k
         if coef_kind == "layered":
             coef = si.field_layered(*n, 4, 1.5, 0.5, seed)[None]
         else:
@@ -75,3 +75,8 @@ def rigid_modes(xyz):
     for w in np.eye(3):
         out.append(np.cross(np.broadcast_to(w, (nn, 3)), xyz.T).ravel())
     return out
+
+
+def dpn_of(physics: int) -> int:
+    """DOF per node of a physics kind (1 scalar Laplace, 2 vector Laplace, 3 elasticity)."""
+    return 1 if physics == 1 else 3

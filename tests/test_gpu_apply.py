@@ -32,6 +32,9 @@ CASES = [
     (3, (8, 8, 8), 0.1, True),
     (3, (13, 11, 7), 0.0, True),    # affine elasticity, ragged
     (3, (3, 2, 2), 0.1, False),
+    (2, (9, 7, 6), 0.1, True),      # vector Laplace
+    (2, (13, 11, 7), 0.0, False),   # affine vector Laplace, ragged
+    (2, (1, 1, 1), 0.1, True),
 ]
 
 
@@ -54,7 +57,7 @@ def test_apply_parity(q1, orc, physics, n, jitter, mask, dtype, variant):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("physics,n", [(1, (1, 1, 1)), (1, (2, 2, 2)), (1, (3, 2, 2)),
-                                       (3, (1, 1, 1)), (3, (2, 2, 1))])
+                                       (3, (1, 1, 1)), (3, (2, 2, 1)), (2, (2, 1, 1))])
 def test_brute_force_dense(q1, orc, physics, n, variant):
     """Apply to every unit vector: the columns form the assembled matrix."""
     print(f"\n[dense] physics={physics} n={n}", flush=True)
@@ -95,7 +98,8 @@ def test_null_spaces(q1, orc, dtype, variant):
 
 @pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("physics,n,jitter", [(1, (16, 16, 16), 0.1), (1, (7, 5, 3), 0.0),
-                                              (3, (7, 6, 5), 0.1), (3, (4, 4, 4), 0.0)])
+                                              (3, (7, 6, 5), 0.1), (3, (4, 4, 4), 0.0),
+                                              (2, (7, 6, 5), 0.1), (2, (4, 4, 4), 0.0)])
 def test_diag_parity(q1, orc, physics, n, jitter, dtype):
     print(f"\n[diag] physics={physics} n={n} dtype={dtype}", flush=True)
     pr = problem(physics, n, jitter, 45, mask=True)
@@ -144,6 +148,33 @@ def test_full_size_elasticity_sampled(q1, orc, variant):
         del op
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_size_vlaplace_sampled(q1, orc, variant):
+    """96^3 undistorted vector Laplace (the 3-DOF Laplace workload), FP64 and
+    FP32: sampled rows against the oracle's element-by-element rows, and the
+    three constant fields in the null space over the whole grid."""
+    print("\n[full-size vector laplace 96^3]", flush=True)
+    pr = si.problem_vlaplace(96, si.seed_for(5))
+    nn = pr["xyz"].shape[1]
+    x = si.vec_uniform(3 * nn, si.seed_for(5), si.STREAM_X)
+    rng = np.random.default_rng(2)
+    rows = np.unique(np.concatenate([rng.integers(0, 3 * nn, 3000), [0, 3 * nn - 1]]))
+    ref = orc.apply_rows(2, pr["xyz"], pr["conn"], pr["coef"], pr["mask"], x, rows)
+    for dtype in (0, 1):
+        op = make_op(pr, dtype, variant)
+        y = gpu_apply(op, x, dtype)
+        err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+        assert err <= TOL[dtype], (dtype, err)
+        del op
+    pr_n = dict(pr, mask=None)
+    op = make_op(pr_n, 0, variant)
+    for c in range(3):
+        u = np.zeros((nn, 3))
+        u[:, c] = 1.0
+        y = gpu_apply(op, u.ravel(), 0)
+        assert np.max(np.abs(y)) <= 1e-12 * pr["coef"].max()
+
+
 def test_empty_mesh_and_errors(q1):
     import torch
     print("\n[edge cases]", flush=True)
@@ -172,5 +203,5 @@ def test_empty_mesh_and_errors(q1):
                                    ctypes.c_void_p(dev(pr["conn"]).data_ptr()),
                                    ctypes.c_void_p(dev(pr["coef"], t).data_ptr()), None, None)
         q1._lib.check(rc)
-    with pytest.raises(q1.Q1Error):
-        q1.q1_op_create(2, 0, 1, dev(pr["xyz"], t), dev(pr["conn"]), dev(pr["coef"], t))
+    with pytest.raises(q1.Q1Error):  # no physics kind 4
+        q1.q1_op_create(4, 0, 1, dev(pr["xyz"], t), dev(pr["conn"]), dev(pr["coef"], t))

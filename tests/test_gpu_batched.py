@@ -176,3 +176,24 @@ def test_batched_mixed_full_workload(q1, orc):
         A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
         for c in range(4):
             assert orc.true_rel_res(A, xs[i][c], bs[i][c]) <= 1e-8 * (1 + 1e-3)
+
+
+def test_single_problem_persistent(q1, orc):
+    """One problem alone in the persistent kernel (every co-resident wave on it):
+    the 16^3 jittered Laplace problem with k = exp(N(0, 1)), against the oracle."""
+    import torch
+    print("\n[persistent single problem] 16^3 jittered", flush=True)
+    s0 = si.seed_for(0)
+    pr = si.problem_laplace_jittered(16, s0)
+    b = si.vec_uniform(pr["xyz"].shape[1], s0, si.STREAM_RHS)
+    b[pr["mask"] == 1] = 0.0
+    pr = dict(pr, physics=1)
+    op = make_op(pr, 0, 3)
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    st = q1.q1_batched_pcg([op], [[bd]], [[xd]], 1e-8, 20000)[0]
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    ref = orc.pcg(A, b, rtol=1e-8)
+    assert st["status"] == 0
+    assert abs(st["iters"] - ref.iters) <= 0.02 * ref.iters + 2, (st["iters"], ref.iters)
+    assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)

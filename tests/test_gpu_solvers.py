@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import seeded_inputs as si
-from helpers import TOL, dev, gpu_apply, make_op, problem, rel_err, torch_dtype
+from helpers import TOL, dev, dpn_of, gpu_apply, make_op, problem, rel_err, torch_dtype
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ def q1():
 def rhs(A, pr, seed):
     b = si.vec_uniform(A.n, seed, si.STREAM_RHS)
     if pr.get("mask") is not None:
-        b[si.dof_mask(pr["mask"], pr["physics"]) == 1] = 0.0
+        b[si.dof_mask(pr["mask"], dpn_of(pr["physics"])) == 1] = 0.0
     return b
 
 
@@ -33,7 +33,8 @@ def rhs(A, pr, seed):
 @pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("physics,n,jitter,mask", [(1, (16, 16, 16), 0.1, True),
                                                    (1, (7, 5, 3), 0.0, False),
-                                                   (3, (6, 5, 4), 0.1, True)])
+                                                   (3, (6, 5, 4), 0.1, True),
+                                                   (2, (6, 5, 4), 0.1, True)])
 def test_csr_parity(q1, orc, physics, n, jitter, mask, dtype):
     print(f"\n[csr] physics={physics} n={n} dtype={dtype}", flush=True)
     pr = problem(physics, n, jitter, 51, mask)
@@ -83,7 +84,7 @@ def test_pcg_first_iterates(q1, orc, csr):
 
 
 @pytest.mark.parametrize("physics,n,jitter", [(1, (16, 16, 16), 0.1), (1, (13, 11, 7), 0.0),
-                                              (3, (8, 8, 8), 0.1)])
+                                              (3, (8, 8, 8), 0.1), (2, (10, 9, 8), 0.1)])
 def test_pcg_converged(q1, orc, physics, n, jitter):
     print(f"\n[pcg converged] physics={physics} n={n}", flush=True)
     pr = problem(physics, n, jitter, 2308, True)
