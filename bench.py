@@ -445,12 +445,16 @@ def main() -> int:
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     extras = {}
     if not args.no_extras:
-        for v in (1, 2, 3, 5):
+        for v in (1, 2, 3, 5, 6):
             if v == info["variant"]:
                 continue
             opv = q1.q1_op_create(1, 0, v, *upload(pr, 0))
             msv, _ = time_applies(opv, x, y, args.steps, args.warmup)
             extras[f"fp64_variant{v}_gdofs"] = round(ndof / (msv * 1e-3) / 1e9, 3)
+            if v == 6:  # partial assembly: its own (Table 3) bytes
+                bv, _ = opv.bytes()
+                extras["fp64_pa_hbm_frac"] = round(bv / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                extras["fp64_pa_alg_bytes"] = bv
             del opv
         log("[bench] cold (flushed) applies")
         ms_cold = time_cold(op, x, y, 30)

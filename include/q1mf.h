@@ -116,11 +116,17 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
  *            atomics; each entry of y is written once).  Because the halo
  *            buffer belongs to the operator, two applies of one BLOCK
  *            operator must not run concurrently (issue them on one stream);
+ *   PA       "partial assembly" (Section 3; the storage of Table 3): BLOCK's
+ *            tiles and halo, but at set-up the factor k w det J J^-1 J^-T of
+ *            every element and quadrature point (6 reals, 48 per element) is
+ *            computed and stored, and the apply reads it instead of the
+ *            coordinates.  Laplace kinds only (Q1_EUNSUPPORTED for
+ *            elasticity); the stored data is 48 reals per element;
  *   AUTO     the fastest measured strategy: BLOCK, else LDS_TILE when the tile
  *            does not fit in LDS, else ATOMIC;
  *   CSR      the assembled matrix (made by q1_csr_create only). */
 enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_COLOR = 2, Q1_V_LDS_TILE = 3, Q1_V_CSR = 4,
-       Q1_V_BLOCK = 5 };
+       Q1_V_BLOCK = 5, Q1_V_PA = 6 };
 
 /* Create an operator over caller-owned device arrays.  The arrays are
  * referenced, not copied: they must stay valid and unchanged until

@@ -30,6 +30,7 @@ Q1_V_COLOR = 2
 Q1_V_LDS_TILE = 3
 Q1_V_CSR = 4
 Q1_V_BLOCK = 5
+Q1_V_PA = 6
 
 Q1_PC_NONE = 0
 Q1_PC_JACOBI = 1

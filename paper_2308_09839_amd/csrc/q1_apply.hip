@@ -282,6 +282,7 @@ int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop)
       });
     case Q1_V_LDS_TILE:
     case Q1_V_BLOCK:
+    case Q1_V_PA:
       return launch_apply_tile(op, x, y, s, stop);
     case Q1_V_CSR:
       return launch_spmv(op, x, y, s, stop);

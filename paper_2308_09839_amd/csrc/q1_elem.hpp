@@ -399,6 +399,80 @@ __device__ __forceinline__ void elasticity_element(T X[3][8], const T u_in[3][8]
 }
 
 // ---------------------------------------------------------------------------
+// Partial assembly of the Laplace kinds: at each quadrature point q the
+// symmetric factor D_q = k w det J J^-1 J^-T, in the units of the modal
+// gradients above: D_q = (k/512) A A^T / det' with A the adjugate rows of the
+// modal Jacobian J' (the quantity the general path forms on the fly).
+// qd[q] = {D00, D01, D02, D11, D12, D22}.  X is destroyed.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void laplace_qdata(T X[3][8], T k, T qd[8][6]) {
+  butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
+  T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    eval4(X[r][1], X[r][3], X[r][5], X[r][7], Jx[r]);
+    eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);
+    eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);
+  }
+  const T ks = k * T(1.0 / 512.0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+    const T jx[3] = {Jx[0][iy][iz], Jx[1][iy][iz], Jx[2][iy][iz]};
+    const T jy[3] = {Jy[0][ix][iz], Jy[1][ix][iz], Jy[2][ix][iz]};
+    const T jz[3] = {Jz[0][ix][iy], Jz[1][ix][iy], Jz[2][ix][iy]};
+    T a0[3], a1[3], a2[3];
+    cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
+    const T s = ks * rcp(dot3(jx, a0));
+    qd[q][0] = s * dot3(a0, a0); qd[q][1] = s * dot3(a0, a1); qd[q][2] = s * dot3(a0, a2);
+    qd[q][3] = s * dot3(a1, a1); qd[q][4] = s * dot3(a1, a2); qd[q][5] = s * dot3(a2, a2);
+  }
+}
+
+// Laplace on NC components from stored quadrature data (no geometry).
+template <typename T, int NC>
+__device__ __forceinline__ void laplace_element_pa_n(const T (*qd)[6], const T (*u_in)[8],
+                                                     T (*v)[8]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    T u[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[a] = u_in[c][a];
+    butterfly_fwd(u);
+    T gx[2][2], gy[2][2], gz[2][2];
+    eval4(u[1], u[3], u[5], u[7], gx);
+    eval4(u[2], u[3], u[6], u[7], gy);
+    eval4(u[4], u[5], u[6], u[7], gz);
+    T Fx[2][2], Fy[2][2], Fz[2][2];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+      const T g0 = gx[iy][iz], g1 = gy[ix][iz], g2 = gz[ix][iy];
+      const T *D = qd[q];
+      const T f0 = D[0] * g0 + D[1] * g1 + D[2] * g2;
+      const T f1 = D[1] * g0 + D[3] * g1 + D[4] * g2;
+      const T f2 = D[2] * g0 + D[4] * g1 + D[5] * g2;
+      // each (iy, iz) cell of Fx is reached by q with ix = 0 first, likewise below
+      Fx[iy][iz] = ix == 0 ? f0 : Fx[iy][iz] + f0;
+      Fy[ix][iz] = iy == 0 ? f1 : Fy[ix][iz] + f1;
+      Fz[ix][iy] = iz == 0 ? f2 : Fz[ix][iy] + f2;
+    }
+    T w[8], r0, r1, r2, r3;
+    eval4T(Fx, r0, r1, r2, r3);
+    w[1] = r0; w[3] = r1; w[5] = r2; w[7] = r3;
+    eval4T(Fy, r0, r1, r2, r3);
+    w[2] = r0; w[3] += r1; w[6] = r2; w[7] += r3;
+    eval4T(Fz, r0, r1, r2, r3);
+    w[4] = r0; w[5] += r1; w[6] += r2; w[7] += r3;
+    w[0] = T(0);
+    butterfly_bwd(w);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[c][a] = w[a];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Physics kinds (the values of the public enum): 1 scalar Laplace, 2 vector
 // Laplace, 3 isotropic elasticity.
 // ---------------------------------------------------------------------------

@@ -50,6 +50,7 @@ struct TileMap {
   int32_t *slot = nullptr;        // [entries] halo slot of each node-list entry, -1 if none
   int32_t *hptr = nullptr;        // [n_reset+1] slot range of each reset node (node-major)
   void *halo = nullptr;           // [n_halo][dpn] partial sums, overwritten by every apply
+  void *qdata = nullptr;          // partial assembly: [48][n_steps*64] quadrature data
   size_t bytes = 0;
 };
 

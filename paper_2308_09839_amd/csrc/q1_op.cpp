@@ -49,7 +49,7 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
            "got %d", physics);
   Q1_CHECK(dtype == Q1_F64 || dtype == Q1_F32, Q1_EINVAL, "q1_op_create: bad dtype %d", dtype);
   Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC || variant == Q1_V_COLOR ||
-               variant == Q1_V_LDS_TILE || variant == Q1_V_BLOCK,
+               variant == Q1_V_LDS_TILE || variant == Q1_V_BLOCK || variant == Q1_V_PA,
            Q1_EINVAL, "q1_op_create: bad variant %d", variant);
   Q1_CHECK(n_nodes > 0 && n_nodes < (int64_t(1) << 31) && n_elems >= 0 &&
                n_elems < (int64_t(1) << 31),
@@ -85,7 +85,12 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
     if (hipGetDeviceProperties(&prop, op->device) == hipSuccess)
       op->num_cus = prop.multiProcessorCount;
   }
-  if (op->variant == Q1_V_LDS_TILE || op->variant == Q1_V_BLOCK) {
+  if (op->variant == Q1_V_PA && (physics == Q1_ELASTICITY || n_elems == 0)) {
+    delete op;
+    return fail(Q1_EUNSUPPORTED,
+                "q1_op_create: partial assembly exists for the Laplace kinds with elements");
+  }
+  if (op->variant == Q1_V_LDS_TILE || op->variant == Q1_V_BLOCK || op->variant == Q1_V_PA) {
     rc = build_tiles(*op, static_cast<hipStream_t>(stream));
     if (rc && variant == Q1_V_AUTO && rc == Q1_EUNSUPPORTED && op->variant == Q1_V_BLOCK) {
       free_tiles(*op);  // tiles too large for LDS: one-wave tiles
@@ -151,7 +156,10 @@ int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
   }
   const int coef_bytes = rb * (op->physics == Q1_ELASTICITY ? 2 : 1);
   double b = 0.0;
-  int rc = q1_model_bytes(1, op->physics, rb, coef_bytes, op->n_nodes, op->n_elems, 0, &b);
+  // partial assembly: Table 3 (k folded into the quadrature data); otherwise Table 2
+  int rc = op->variant == Q1_V_PA
+               ? q1_model_bytes(2, op->physics, rb, 0, op->n_nodes, op->n_elems, 0, &b)
+               : q1_model_bytes(1, op->physics, rb, coef_bytes, op->n_nodes, op->n_elems, 0, &b);
   if (rc) return rc;
   if (bytes) *bytes = b;
   if (flops)

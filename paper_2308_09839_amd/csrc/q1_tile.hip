@@ -172,13 +172,17 @@ __global__ __launch_bounds__(64) void k_apply_tile(
 // One wave's steps of a tile: corners from the staged records, element product,
 // accumulation into LDS.  PAR: every element is known to be a
 // parallelepiped (Laplace kinds), so only corners 0, 1, 2, 4 give geometry.
-template <typename T, int PH, bool LDS_ATOMIC, bool PAR>
+// PA: partial assembly, the element's quadrature data qdata[48][coef_stride]
+// replaces its geometry (the staged records then hold the input only).
+template <typename T, int PH, bool LDS_ATOMIC, bool PAR, bool PA>
 __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nodes,
                                             const T *__restrict__ sR, T *__restrict__ myV,
                                             const uint4 *__restrict__ lconn,
                                             const T *__restrict__ coef_t, int64_t coef_stride,
-                                            uint4 pk_n, T c0_n, T c1_n) {
+                                            uint4 pk_n, T c0_n, T c1_n,
+                                            const T *__restrict__ qdata) {
   constexpr int DPN = phys_dpn(PH);
+  constexpr int UOFF = PA ? 0 : 3;  // first input field of a staged record
   // pk_n, c0_n, c1_n: this wave's first step, loaded by the caller before staging
   for (; s < s1; s += 4) {
     const uint4 pk = pk_n;
@@ -196,18 +200,27 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const T *r = sR + lc[a];
-      if (!PAR || a == 0 || a == 1 || a == 2 || a == 4) {
+      if (!PA && (!PAR || a == 0 || a == 1 || a == 2 || a == 4)) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) X[k][a] = r[size_t(k) * max_nodes];
       }
 #pragma unroll
-      for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(3 + j) * max_nodes];
+      for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(UOFF + j) * max_nodes];
     }
     T v[DPN][8];
-    if constexpr (PAR && PH != 3)
+    if constexpr (PA) {
+      const int64_t slot = int64_t(s) * kLanes + lane;
+      T qd[8][6];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) qd[q][m] = qdata[(q * 6 + m) * coef_stride + slot];
+      laplace_element_pa_n<T, DPN>(qd, u, v);
+    } else if constexpr (PAR && PH != 3) {
       laplace_element_parallelepiped_n<T, DPN>(X, u, c0, v);
-    else
+    } else {
       element_apply<T, PH>(X, u, c0, c1, v);
+    }
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -218,17 +231,18 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
 // ONEACC: the four waves add into one LDS accumulator with LDS atomics (FP64,
 // where it frees LDS for a fourth resident block); otherwise each wave owns a
 // copy and the copies are summed in a fixed order.
-template <typename T, int PH, bool LDS_ATOMIC, bool ONEACC>
+template <typename T, int PH, bool LDS_ATOMIC, bool ONEACC, bool PA>
 __global__ __launch_bounds__(256) void k_apply_block(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
     const uint4 *__restrict__ lconn, const T *__restrict__ coef_t, int64_t coef_stride,
     const T *__restrict__ xyz, const T *__restrict__ x, T *__restrict__ y,
     const int *__restrict__ stop, const uint8_t *__restrict__ tile_affine,
-    const int32_t *__restrict__ slot, T *__restrict__ halo) {
+    const int32_t *__restrict__ slot, T *__restrict__ halo, const T *__restrict__ qdata) {
   constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
-  constexpr int NR = 3 + DPN;  // x, y, z, u[DPN], stored field by field
+  constexpr int UOFF = PA ? 0 : 3;
+  constexpr int NR = UOFF + DPN;  // [x, y, z,] u[DPN], stored field by field
   constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][max_nodes]
@@ -267,11 +281,13 @@ __global__ __launch_bounds__(256) void k_apply_block(
 #pragma unroll
     for (int k = 0; k < KN; ++k) {
       const int64_t g = raw[k] & kIdMask;
-      rec[k][0] = xyz[g];
-      rec[k][1] = xyz[nn + g];
-      rec[k][2] = xyz[2 * nn + g];
+      if constexpr (!PA) {
+        rec[k][0] = xyz[g];
+        rec[k][1] = xyz[nn + g];
+        rec[k][2] = xyz[2 * nn + g];
+      }
 #pragma unroll
-      for (int j = 0; j < DPN; ++j) rec[k][3 + j] = x[g * DPN + j];
+      for (int j = 0; j < DPN; ++j) rec[k][UOFF + j] = x[g * DPN + j];
     }
 #pragma unroll
     for (int k = 0; k < KN; ++k) {
@@ -279,10 +295,10 @@ __global__ __launch_bounds__(256) void k_apply_block(
       if (i < nm) {
         const bool fixed = (raw[k] & kFixedBit) != 0;
 #pragma unroll
-        for (int f = 0; f < 3; ++f) sR[size_t(f) * max_nodes + i] = rec[k][f];
+        for (int f = 0; f < UOFF; ++f) sR[size_t(f) * max_nodes + i] = rec[k][f];
 #pragma unroll
         for (int j = 0; j < DPN; ++j)
-          sR[size_t(3 + j) * max_nodes + i] = fixed ? T(0) : rec[k][3 + j];
+          sR[size_t(UOFF + j) * max_nodes + i] = fixed ? T(0) : rec[k][UOFF + j];
 #pragma unroll
         for (int c = 0; c < NACC * DPN; ++c) sV[size_t(c) * max_nodes + i] = T(0);
       }
@@ -290,12 +306,14 @@ __global__ __launch_bounds__(256) void k_apply_block(
   }
   __syncthreads();
   T *myV = ONEACC ? sV : sV + size_t(w) * DPN * max_nodes;
-  if (PH != 3 && tile_affine[tile])
-    block_steps<T, PH, LDS_ATOMIC || ONEACC, true>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
-                                          coef_stride, pk0, c00, c10);
+  if (!PA && PH != 3 && tile_affine[tile])
+    block_steps<T, PH, LDS_ATOMIC || ONEACC, true, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
+                                                       lconn, coef_t, coef_stride, pk0, c00, c10,
+                                                       qdata);
   else
-    block_steps<T, PH, LDS_ATOMIC || ONEACC, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
-                                           coef_stride, pk0, c00, c10);
+    block_steps<T, PH, LDS_ATOMIC || ONEACC, false, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
+                                                        lconn, coef_t, coef_stride, pk0, c00, c10,
+                                                        qdata);
   __syncthreads();
   // nodes of this tile only: y; nodes shared with other tiles: this tile's halo
   // slot (summed by k_halo_sum); Dirichlet nodes: written by k_halo_sum
@@ -348,6 +366,39 @@ __global__ void k_halo_sum(int64_t n, const int32_t *__restrict__ ids,
     for (int c = 0; c < DPN; ++c) acc[c] += halo[int64_t(k) * DPN + c];
 #pragma unroll
   for (int c = 0; c < DPN; ++c) y[g * DPN + c] = acc[c];
+}
+
+// Partial-assembly set-up: the quadrature data of the element in each lane
+// slot (zero for empty slots), stored [48][n_slots] so that a step's loads are
+// contiguous.
+template <typename T>
+__global__ void k_pa_setup(int64_t n_slots, const int32_t *__restrict__ slot_elem, int64_t ne,
+                           int64_t nn, const int32_t *__restrict__ conn,
+                           const T *__restrict__ xyz, const T *__restrict__ coef,
+                           T *__restrict__ qdata) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n_slots) return;
+  const int32_t e = slot_elem[i];
+  T qd[8][6];
+  if (e < 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int m = 0; m < 6; ++m) qd[q][m] = T(0);
+  } else {
+    T X[3][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int64_t g = conn[a * ne + e];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + g];
+    }
+    laplace_qdata<T>(X, coef[e], qd);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) qdata[(q * 6 + m) * n_slots + i] = qd[q][m];
 }
 
 namespace {
@@ -546,22 +597,45 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
       (rc = up(&tm.tile_affine, H.tile_affine)))
     return rc;
   tm.coef_t = coef_dev;
-  if (op.variant == Q1_V_BLOCK) {
+  if (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) {
     if ((rc = up(&tm.slot, H.slot)) || (rc = up(&tm.hptr, H.hptr))) return rc;
     tm.n_halo = H.hptr.back();
     const size_t hb = std::max<int64_t>(1, tm.n_halo) * op.dpn() * sizeof(T);
     Q1_HIP(hipMalloc(&tm.halo, hb));
     tm.bytes += hb;
   }
+  if (op.variant == Q1_V_PA) {
+    // quadrature data of every element slot, computed once on the device
+    int32_t *d_elem = nullptr;
+    Q1_HIP(hipMalloc(&d_elem, size_t(n_slots) * sizeof(int32_t)));
+    Q1_HIP(hipMemcpy(d_elem, H.step_elem.data(), size_t(n_slots) * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+    const size_t qb = size_t(48) * n_slots * sizeof(T);
+    hipError_t e = hipMalloc(&tm.qdata, qb);
+    if (e != hipSuccess) {
+      (void)hipFree(d_elem);
+      return fail(Q1_ENOMEM, "partial assembly: %zu B of quadrature data", qb);
+    }
+    tm.bytes += qb;
+    hipLaunchKernelGGL((k_pa_setup<T>), dim3(unsigned((n_slots + 255) / 256)), dim3(256), 0, s,
+                       n_slots, d_elem, ne, nn, op.conn, static_cast<const T *>(op.xyz),
+                       static_cast<const T *>(op.coef), static_cast<T *>(tm.qdata));
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_elem);
+    if (e != hipSuccess) return fail(Q1_EHIP, "partial assembly set-up: %s", hipGetErrorString(e));
+  }
   return Q1_OK;
 }
 
-// LDS of the block-staged variant: node records, then the accumulator copies
-// (one shared copy for FP64, one per wave for FP32)
+// LDS of the block-staged variant: node records (coordinates unless partial
+// assembly, input), then the accumulator copies (one shared copy for FP64,
+// one per wave for FP32)
 size_t block_lds_bytes(const Op &op) {
   const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
   const size_t nacc = op.dtype == Q1_F64 ? 1 : 4;
-  return size_t(op.tiles.max_nodes) * rb * size_t(3 + op.dpn() + nacc * op.dpn());
+  const size_t ncoord = op.variant == Q1_V_PA ? 0 : 3;
+  return size_t(op.tiles.max_nodes) * rb * size_t(ncoord + op.dpn() + nacc * op.dpn());
 }
 
 template <typename T, int PH>
@@ -570,20 +644,25 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const TileMap &tm = op.tiles;
   const T *x = static_cast<const T *>(xv);
   T *y = static_cast<T *>(yv);
-  const bool block = op.variant == Q1_V_BLOCK;
+  const bool pa = op.variant == Q1_V_PA;
+  const bool block = op.variant == Q1_V_BLOCK || pa;
   if (tm.n_reset > 0 && !block)
     hipLaunchKernelGGL((k_reset_nodes<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
                        s, tm.n_reset, tm.reset, op.mask, x, y, stop);
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block) {
     constexpr bool one = std::is_same<T, double>::value;
-    auto kb = tm.lds_atomic ? k_apply_block<T, PH, true, one> : k_apply_block<T, PH, false, one>;
+    constexpr bool pa_ok = PH != 3;  // partial assembly exists for the Laplace kinds
+    auto kb = tm.lds_atomic ? (pa && pa_ok ? k_apply_block<T, PH, true, one, pa_ok>
+                                           : k_apply_block<T, PH, true, one, false>)
+                            : (pa && pa_ok ? k_apply_block<T, PH, false, one, pa_ok>
+                                           : k_apply_block<T, PH, false, one, false>);
     hipLaunchKernelGGL(kb, dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes, op.n_nodes,
                        tm.node_ptr, tm.nodes, tm.tile_step,
                        reinterpret_cast<const uint4 *>(tm.lconn),
                        static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
                        static_cast<const T *>(op.xyz), x, y, stop, tm.tile_affine, tm.slot,
-                       static_cast<T *>(tm.halo));
+                       static_cast<T *>(tm.halo), static_cast<const T *>(tm.qdata));
     if (tm.n_reset > 0)
       hipLaunchKernelGGL((k_halo_sum<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
                          s, tm.n_reset, tm.reset, tm.hptr, op.mask, x,
@@ -632,7 +711,7 @@ static void block_shape(const Op &op, int &px, int &py, int &layers) {
 int build_tiles(Op &op, hipStream_t s) {
   Q1_CHECK(op.n_elems > 0, Q1_EUNSUPPORTED, "LDS-tile variant needs at least one element");
   int px, py, layers;
-  if (op.variant == Q1_V_BLOCK) {
+  if (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) {
     block_shape(op, px, py, layers);
   } else {
     layers = tile_layers(op);
@@ -642,7 +721,7 @@ int build_tiles(Op &op, hipStream_t s) {
   int rc = op.dtype == Q1_F64 ? build_tiles_t<double>(op, s, px, py, layers)
                               : build_tiles_t<float>(op, s, px, py, layers);
   if (rc) return rc;
-  const size_t lds = op.variant == Q1_V_BLOCK
+  const size_t lds = op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA
                          ? block_lds_bytes(op)
                          : size_t(op.tiles.max_nodes) * (op.dpn() * (op.dtype == Q1_F64 ? 8 : 4) + 4);
   Q1_CHECK(lds <= 64 * 1024, Q1_EUNSUPPORTED, "tile needs %zu B of LDS", lds);
@@ -658,7 +737,7 @@ int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *
 void free_tiles(Op &op) {
   TileMap &t = op.tiles;
   void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset,
-                  t.coef_t,   t.tile_affine, t.slot, t.hptr, t.halo};
+                  t.coef_t,   t.tile_affine, t.slot, t.hptr, t.halo, t.qdata};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   t = TileMap{};

@@ -175,6 +175,49 @@ def test_full_size_vlaplace_sampled(q1, orc, variant):
         assert np.max(np.abs(y)) <= 1e-12 * pr["coef"].max()
 
 
+# -- partial assembly (quadrature data stored at set-up), Laplace kinds ----------
+
+PA_CASES = [c for c in CASES if c[0] != 3]
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("physics,n,jitter,mask", PA_CASES)
+def test_partial_assembly_parity(q1, orc, physics, n, jitter, mask, dtype):
+    print(f"\n[partial assembly] physics={physics} n={n} jitter={jitter} dtype={dtype}",
+          flush=True)
+    pr = problem(physics, n, jitter, 2308, mask)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    x = si.vec_uniform(A.n, 2308, si.STREAM_X)
+    ref = A.matvec(x)
+    y = gpu_apply(make_op(pr, dtype, 6), x, dtype)
+    assert rel_err(y, ref) <= TOL[dtype], rel_err(y, ref)
+
+
+def test_partial_assembly_full_size(q1, orc):
+    """128^3 layered-coefficient Laplace through partial assembly, FP64 and FP32:
+    sampled rows against the oracle, and the constant null vector."""
+    print("\n[partial assembly 128^3]", flush=True)
+    pr = si.problem_laplace_layered(128, si.seed_for(1))
+    nn = pr["xyz"].shape[1]
+    x = si.vec_uniform(nn, si.seed_for(1), si.STREAM_X)
+    rows = np.unique(np.random.default_rng(3).integers(0, nn, 3000))
+    ref = orc.apply_rows(1, pr["xyz"], pr["conn"], pr["coef"], None, x, rows)
+    for dtype in (0, 1):
+        op = make_op(pr, dtype, 6)
+        y = gpu_apply(op, x, dtype)
+        assert np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref) <= TOL[dtype]
+        y1 = gpu_apply(op, np.ones(nn), dtype)
+        assert np.max(np.abs(y1)) <= (1e-12 if dtype == 0 else 1e-4) * pr["coef"].max()
+        del op
+
+
+def test_partial_assembly_rejects_elasticity(q1):
+    pr = problem(3, (2, 2, 2), 0.0, 1, mask=False)
+    with pytest.raises(q1.Q1Error) as ei:
+        make_op(pr, 0, 6)
+    assert ei.value.code == -6
+
+
 def test_empty_mesh_and_errors(q1):
     import torch
     print("\n[edge cases]", flush=True)
