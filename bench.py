@@ -149,17 +149,19 @@ def cg16_problem(si):
 
 def bench_cg16(q1, si, n, seed, args):
     """16^3 jittered Laplace: FP64 Jacobi-PCG to a 1e-8 relative residual, wall time of the
-    whole solve, through the launch-per-kernel driver and through the persistent kernel
-    (one cooperative launch for the whole solve)."""
+    whole solve, through the launch-per-kernel driver, through the persistent batched
+    kernel (one cooperative launch) and through the fused single-workgroup kernel."""
     import torch
     pr, b = cg16_problem(si)
     bd = torch.from_numpy(b).to("cuda")
     xd = torch.empty_like(bd)
     res = {}
-    for tag, variant in (("", 0), ("_persistent", 3)):
+    for tag, variant in (("", 0), ("_persistent", 3), ("_fused", 0)):
         op = q1.q1_op_create(1, 0, variant, *upload(pr, 0))
-        if variant == 0:
+        if tag == "":
             solve = lambda: q1.q1_pcg(op, 1, bd, xd, 1e-8, 20000)
+        elif tag == "_fused":
+            solve = lambda: q1.q1_pcg_fused(op, 1, bd, xd, 1e-8, 20000)
         else:
             solve = lambda: q1.q1_batched_pcg([op], [[bd]], [[xd]], 1e-8, 20000)[0]
         solve()  # warm-up

@@ -227,6 +227,18 @@ int q1_jacobi_create(q1_jacobi **J, q1_op *op, void *stream);
 int q1_precond_jacobi(void *ctx, const void *r_d, void *z_d, void *stream);
 int q1_jacobi_destroy(q1_jacobi *J);
 
+/* Jacobi-PCG (pc as in q1_pcg) fused into ONE launch of one workgroup (8
+ * wavefronts) for small problems: apply, dot products and vector updates of
+ * every iteration (Table 4's CG operations) run back to back with workgroup
+ * barriers; q = A p is accumulated in LDS, so n_nodes * dpn * 8 B plus 512 B
+ * must fit in 64 KB (about 8,100 DOF), otherwise Q1_EUNSUPPORTED.  Same
+ * iteration and stopping rule as q1_pcg; st->true_rel_res is computed in the
+ * same launch.  FP64 operators of any variant (the kernel reads the caller's
+ * coordinates, connectivity and coefficients); b_d, x_d FP64.  Allocates a
+ * small workspace; synchronises `stream`. */
+int q1_pcg_fused(q1_op *op, int pc, const double *b_d, double *x_d, double rtol, int maxit,
+                 q1_stats *st, void *stream);
+
 /* Mixed-precision iterative refinement: r = b - A64 x in FP64; s = r/||r||
  * rounded to FP32; Jacobi-PCG with the FP32 operator, FP32 vectors and FP64
  * dots solves A32 d = s to inner_rtol (at most max_inner iterations); then

@@ -17,7 +17,7 @@ from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32,
                    Q1_V_CSR, Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
-    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
+    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_fused", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
     "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_VLAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_COLOR", "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
@@ -309,6 +309,15 @@ def q1_mpcg(op64: Op, op32: Op, b, x, rtol: float, delta: float = 0.1, maxit: in
     st = Q1Stats()
     _solve_rc(lib().q1_mpcg(op64.handle, op32.handle, _dptr(b), _dptr(x), rtol, delta, maxit,
                             ctypes.byref(st), _stream(stream)))
+    return st.as_dict()
+
+
+def q1_pcg_fused(op: Op, pc: int, b, x, rtol: float, maxit: int, stream=None) -> dict:
+    """Jacobi-PCG in one launch of one workgroup (small problems: the DOF vector
+    must fit in 64 KB of LDS)."""
+    st = Q1Stats()
+    _solve_rc(lib().q1_pcg_fused(op.handle, pc, _dptr(b), _dptr(x), rtol, maxit,
+                                 ctypes.byref(st), _stream(stream)))
     return st.as_dict()
 
 

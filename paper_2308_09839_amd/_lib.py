@@ -100,6 +100,7 @@ PROTOTYPES = {
     "q1_batched_mpcg": (c_int, [c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_dbl, c_int, c_vp,
                                 c_vp]),
     "q1_mpcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_int, P(Q1Stats), c_vp]),
+    "q1_pcg_fused": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, P(Q1Stats), c_vp]),
     "q1_ir_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),
     "q1_conv3d_forward": (c_int, [c_int, c_int, c_int, c_int, c_vp, c_int, c_int, c_vp, c_int,
                                   c_vp, c_vp, c_int, c_int, c_vp, c_vp]),

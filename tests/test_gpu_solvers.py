@@ -293,3 +293,63 @@ def test_pcg_trace_snapshots(q1, orc):
         x = s.cpu().numpy()
         assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), k
     assert torch.equal(snaps[-1], xd)
+
+
+# -- fused single-workgroup PCG (small problems) ----------------------------------
+
+def solve_fused(q1, op, b, pc=1, rtol=1e-8, maxit=20000):
+    import torch
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    st = q1.q1_pcg_fused(op, pc, bd, xd, rtol, maxit)
+    return xd.cpu().numpy(), st
+
+
+def test_fused_pcg_iterates(q1, orc):
+    """Truncated fused solves equal the oracle's PCG iterates."""
+    print("\n[fused pcg iterates] 16^3 jittered", flush=True)
+    pr = problem(1, (16, 16, 16), 0.1, 2308, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 2308)
+    op = make_op(pr, 0, 0)
+    for k in (1, 2, 5, 10):
+        ref = orc.pcg(A, b, rtol=0.0, maxit=k)
+        x, st = solve_fused(q1, op, b, rtol=0.0, maxit=k)
+        assert st["status"] == -4 and st["iters"] == k
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), k
+
+
+@pytest.mark.parametrize("physics,n,jitter", [(1, (16, 16, 16), 0.1), (2, (9, 8, 7), 0.1),
+                                              (3, (7, 6, 5), 0.1), (1, (5, 4, 3), 0.0)])
+def test_fused_pcg_converged(q1, orc, physics, n, jitter):
+    print(f"\n[fused pcg] physics={physics} n={n}", flush=True)
+    pr = problem(physics, n, jitter, 91, True)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 92)
+    ref = orc.pcg(A, b, rtol=1e-8)
+    x, st = solve_fused(q1, make_op(pr, 0, 0), b)
+    tr = orc.true_rel_res(A, x, b)
+    assert st["status"] == 0
+    assert tr <= 1e-8 * (1 + 1e-3)
+    assert abs(st["iters"] - ref.iters) <= 0.02 * ref.iters + 2, (st["iters"], ref.iters)
+    assert abs(st["true_rel_res"] - tr) <= 1e-12
+
+
+def test_fused_pcg_limits(q1):
+    import torch
+    print("\n[fused pcg limits]", flush=True)
+    pr = problem(1, (24, 24, 24), 0.0, 93, True)  # 15,625 DOF: beyond the LDS capacity
+    op = make_op(pr, 0, 0)
+    bd = torch.ones(pr["xyz"].shape[1], dtype=torch.float64, device="cuda")
+    with pytest.raises(q1.Q1Error) as ei:
+        q1.q1_pcg_fused(op, 1, bd, torch.empty_like(bd), 1e-8, 100)
+    assert ei.value.code == -6
+    pr = problem(1, (4, 4, 4), 0.0, 94, True)
+    op = make_op(pr, 0, 0)
+    bd = torch.zeros(pr["xyz"].shape[1], dtype=torch.float64, device="cuda")
+    xd = torch.full_like(bd, 3.0)
+    st = q1.q1_pcg_fused(op, 1, bd, xd, 1e-8, 100)
+    assert st["status"] == 0 and st["iters"] == 0 and torch.all(xd == 0)
+    op32 = make_op(pr, 1, 0)
+    with pytest.raises(q1.Q1Error):
+        q1.q1_pcg_fused(op32, 1, bd, xd, 1e-8, 100)
