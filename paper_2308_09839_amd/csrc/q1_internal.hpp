@@ -44,6 +44,7 @@ struct TileMap {
   int32_t *reset = nullptr;
   bool lds_atomic = false;        // corners collide within a step: accumulate with LDS atomics
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
+  uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16, or 0
   // block variant: partial sums of nodes shared between tiles go to halo slots
   // (no atomics), summed per node by a second kernel in a fixed order
   int64_t n_halo = 0;             // slots: one per (shared free node, tile touching it)

@@ -180,22 +180,37 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
                                             const uint4 *__restrict__ lconn,
                                             const T *__restrict__ coef_t, int64_t coef_stride,
                                             uint4 pk_n, T c0_n, T c1_n,
-                                            const T *__restrict__ qdata) {
+                                            const T *__restrict__ qdata, uint32_t lat,
+                                            int s_first) {
   constexpr int DPN = phys_dpn(PH);
   constexpr int UOFF = PA ? 0 : 3;  // first input field of a staged record
+  // lattice tile: corner indices from (step, lane), no corner-index loads
+  const int LA = int(lat & 0xff), LB = int((lat >> 8) & 0xff), spl = int(lat >> 16);
+  const int a1 = LA + 1, ab1 = (LA + 1) * (LB + 1);
   // pk_n, c0_n, c1_n: this wave's first step, loaded by the caller before staging
   for (; s < s1; s += 4) {
     const uint4 pk = pk_n;
     const T c0 = c0_n, c1 = c1_n;
     {  // prefetch this wave's next step (clamped to the current one)
       const int64_t slot = int64_t(s + 4 < s1 ? s + 4 : s) * kLanes + lane;
-      pk_n = lconn[slot];
+      if (!lat) pk_n = lconn[slot];
       c0_n = coef_t[slot];
       if constexpr (PH == 3) c1_n = coef_t[coef_stride + slot];
     }
-    if (pk.x == 0xffffffffu) continue;  // empty lane
-    const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16),
-                       int(pk.z & 0xffff), int(pk.z >> 16), int(pk.w & 0xffff), int(pk.w >> 16)};
+    int lc[8];
+    if (lat) {
+      const int rel = s - s_first, iz = rel / spl, e = (rel - iz * spl) * kLanes + lane;
+      if (e >= LA * LB) continue;  // empty lane
+      const int base = e % LA + a1 * (e / LA + (LB + 1) * iz);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) lc[a] = base + (a & 1) + a1 * ((a >> 1) & 1) + ab1 * (a >> 2);
+    } else {
+      if (pk.x == 0xffffffffu) continue;  // empty lane
+      lc[0] = int(pk.x & 0xffff); lc[1] = int(pk.x >> 16);
+      lc[2] = int(pk.y & 0xffff); lc[3] = int(pk.y >> 16);
+      lc[4] = int(pk.z & 0xffff); lc[5] = int(pk.z >> 16);
+      lc[6] = int(pk.w & 0xffff); lc[7] = int(pk.w >> 16);
+    }
     T X[3][8], u[DPN][8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -238,7 +253,8 @@ __global__ __launch_bounds__(256) void k_apply_block(
     const uint4 *__restrict__ lconn, const T *__restrict__ coef_t, int64_t coef_stride,
     const T *__restrict__ xyz, const T *__restrict__ x, T *__restrict__ y,
     const int *__restrict__ stop, const uint8_t *__restrict__ tile_affine,
-    const int32_t *__restrict__ slot, T *__restrict__ halo, const T *__restrict__ qdata) {
+    const int32_t *__restrict__ slot, T *__restrict__ halo, const T *__restrict__ qdata,
+    const uint32_t *__restrict__ tile_lat) {
   constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
   constexpr int UOFF = PA ? 0 : 3;
@@ -252,12 +268,13 @@ __global__ __launch_bounds__(256) void k_apply_block(
   const int tile = xcd_block_t(blockIdx.x, gridDim.x);
   const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
   const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
+  const uint32_t lat = tile_lat[tile];
   // the wave's first step is requested before staging, so its latency overlaps it
   uint4 pk0 = make_uint4(0xffffffffu, 0u, 0u, 0u);
   T c00 = T(0), c10 = T(0);
   if (s0 + w < s1) {
     const int64_t slot = int64_t(s0 + w) * kLanes + lane;
-    pk0 = lconn[slot];
+    if (!lat) pk0 = lconn[slot];
     c00 = coef_t[slot];
     if constexpr (PH == 3) c10 = coef_t[coef_stride + slot];
   }
@@ -309,11 +326,11 @@ __global__ __launch_bounds__(256) void k_apply_block(
   if (!PA && PH != 3 && tile_affine[tile])
     block_steps<T, PH, LDS_ATOMIC || ONEACC, true, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
                                                        lconn, coef_t, coef_stride, pk0, c00, c10,
-                                                       qdata);
+                                                       qdata, lat, s0);
   else
     block_steps<T, PH, LDS_ATOMIC || ONEACC, false, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
                                                         lconn, coef_t, coef_stride, pk0, c00, c10,
-                                                        qdata);
+                                                        qdata, lat, s0);
   __syncthreads();
   // nodes of this tile only: y; nodes shared with other tiles: this tile's halo
   // slot (summed by k_halo_sum); Dirichlet nodes: written by k_halo_sum
@@ -412,7 +429,42 @@ struct HostTiles {
   bool corner_collision = false;   // two lanes of a step share a node at one corner
   std::vector<uint8_t> tile_affine;  // every element of the tile is a parallelepiped
   std::vector<int32_t> slot, hptr;   // halo slots of the block variant
+  std::vector<uint32_t> tile_lat;    // lattice description of each tile (0: none)
 };
+
+// Lattice tiles: the tile's elements form an A x B x C brick, its node list is
+// the (A+1) x (B+1) x (C+1) lattice in x-fastest order, and its steps take
+// each layer's A*B elements x-fastest in runs of 64 (spl steps per layer).
+// Then the corner indices of lane l in step s follow from (s, l) alone and the
+// kernel computes them instead of loading them.  Returns A | B << 8 | spl << 16
+// when every element, corner and empty lane of tile t matches, else 0.
+uint32_t lattice_of(const HostTiles &H, int t) {
+  const int s0 = H.tile_step[t], s1 = H.tile_step[t + 1];
+  const int nm = H.node_ptr[t + 1] - H.node_ptr[t];
+  const uint16_t *L0 = &H.lconn[size_t(s0) * kLanes * 8];
+  if (L0[0] == 0xffff) return 0;
+  const int a1 = L0[2] - L0[0], ab1 = L0[4] - L0[0];  // A+1, (A+1)(B+1)
+  if (a1 < 2 || ab1 < 2 * a1 || ab1 % a1) return 0;
+  const int A = a1 - 1, B = ab1 / a1 - 1;
+  if (A > 255 || B > 255) return 0;
+  const int spl = (A * B + kLanes - 1) / kLanes;
+  if ((s1 - s0) % spl || spl > 255) return 0;
+  const int C = (s1 - s0) / spl;
+  if (nm != a1 * (B + 1) * (C + 1)) return 0;
+  for (int s = s0; s < s1; ++s)
+    for (int l = 0; l < kLanes; ++l) {
+      const uint16_t *lc = &H.lconn[(size_t(s) * kLanes + l) * 8];
+      const int rel = s - s0, iz = rel / spl, e = (rel - iz * spl) * kLanes + l;
+      if (e >= A * B) {
+        if (lc[0] != 0xffff) return 0;
+        continue;
+      }
+      const int base = e % A + a1 * (e / A + (B + 1) * iz);
+      for (int a = 0; a < 8; ++a)
+        if (lc[a] != base + (a & 1) + a1 * ((a >> 1) & 1) + ab1 * (a >> 2)) return 0;
+    }
+  return uint32_t(A) | uint32_t(B) << 8 | uint32_t(spl) << 16;
+}
 
 // Group elements into tiles and steps; record node lists and corner indices.
 template <typename T>
@@ -517,6 +569,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
       j = je;
     }
     H.tile_step.push_back(int32_t(H.step_elem.size() / kLanes));
+    H.tile_lat.push_back(lattice_of(H, t));
     bool aff = true;  // the kernel's own exact test, in the operator's precision
     for (int64_t k = tb[t]; k < tb[t + 1] && aff; ++k) {
       T X[3][8];
@@ -594,7 +647,7 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   if ((rc = up(&tm.node_ptr, H.node_ptr)) || (rc = up(&tm.nodes, H.nodes)) ||
       (rc = up(&tm.tile_step, H.tile_step)) || (rc = up(&tm.lconn, H.lconn)) ||
       (rc = up(&tm.reset, H.reset)) || (rc = up(&coef_dev, coef_t)) ||
-      (rc = up(&tm.tile_affine, H.tile_affine)))
+      (rc = up(&tm.tile_affine, H.tile_affine)) || (rc = up(&tm.tile_lat, H.tile_lat)))
     return rc;
   tm.coef_t = coef_dev;
   if (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) {
@@ -662,7 +715,8 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
                        reinterpret_cast<const uint4 *>(tm.lconn),
                        static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
                        static_cast<const T *>(op.xyz), x, y, stop, tm.tile_affine, tm.slot,
-                       static_cast<T *>(tm.halo), static_cast<const T *>(tm.qdata));
+                       static_cast<T *>(tm.halo), static_cast<const T *>(tm.qdata),
+                       tm.tile_lat);
     if (tm.n_reset > 0)
       hipLaunchKernelGGL((k_halo_sum<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
                          s, tm.n_reset, tm.reset, tm.hptr, op.mask, x,
@@ -737,7 +791,7 @@ int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *
 void free_tiles(Op &op) {
   TileMap &t = op.tiles;
   void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset,
-                  t.coef_t,   t.tile_affine, t.slot, t.hptr, t.halo, t.qdata};
+                  t.coef_t,   t.tile_affine, t.slot, t.hptr, t.halo, t.qdata, t.tile_lat};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   t = TileMap{};

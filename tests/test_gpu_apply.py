@@ -248,3 +248,26 @@ def test_empty_mesh_and_errors(q1):
         q1._lib.check(rc)
     with pytest.raises(q1.Q1Error):  # no physics kind 4
         q1.q1_op_create(4, 0, 1, dev(pr["xyz"], t), dev(pr["conn"]), dev(pr["coef"], t))
+
+
+@pytest.mark.parametrize("variant", VARIANTS + [6])
+@pytest.mark.parametrize("physics", [1, 2, 3])
+def test_apply_permuted_numbering(q1, orc, physics, variant):
+    """Nodes renumbered by a random permutation: tiles are no longer lattices in
+    id order, so the block kernels read their corner indices from the planner's
+    tables instead of computing them."""
+    if variant == 6 and physics == 3:
+        return
+    print(f"\n[permuted numbering] physics={physics} variant={variant}", flush=True)
+    pr = problem(physics, (9, 7, 6), 0.1, 47, True)
+    nn = pr["xyz"].shape[1]
+    perm = np.random.default_rng(5).permutation(nn)  # new id of old node i = perm[i]
+    inv = np.argsort(perm)
+    pp = dict(pr, xyz=pr["xyz"][:, inv], conn=perm[pr["conn"]].astype(np.int32),
+              mask=pr["mask"][inv])
+    A = orc.assemble(physics, pp["xyz"], pp["conn"], pp["coef"], pp["mask"])
+    x = si.vec_uniform(A.n, 47, si.STREAM_X)
+    ref = A.matvec(x)
+    for dtype in (0, 1):
+        y = gpu_apply(make_op(pp, dtype, variant), x, dtype)
+        assert rel_err(y, ref) <= TOL[dtype], (dtype, rel_err(y, ref))
