@@ -399,6 +399,103 @@ __device__ __forceinline__ void elasticity_element(T X[3][8], const T u_in[3][8]
 }
 
 // ---------------------------------------------------------------------------
+// Elasticity on an element known to be a parallelepiped.  With the constant
+// Jacobian, the reference-gradient products of the modes integrate exactly to
+// a block-sparse pattern: the linear modes (xi, eta, zeta) couple among
+// themselves, the bilinear modes couple through the variable they share (xi*eta
+// and xi*zeta through xi, ...), the trilinear mode only with itself.  For one
+// such group with members (mode m, adjugate row a_m), H = sum_m u_m (x) a_m is
+// the group's displacement gradient (up to scale), S = lambda tr(H) I +
+// mu (H + H^T) its stress, and member m receives alpha S a_m, with alpha =
+// 1/(16 det E), /3 for the bilinear groups and /9 for the trilinear one (the
+// squared-variable integrals).  E_c = X_c - X_0 (c = 1, 2, 4) as in the Laplace
+// parallelepiped path; reads corners 0, 1, 2, 4 of X only.
+// ---------------------------------------------------------------------------
+template <typename T, int NM>
+__device__ __forceinline__ void elas_group(const T (&u)[3][8], T (&w)[3][8],
+                                           const int (&mode)[NM], const T *const (&av)[NM],
+                                           T lam, T mu, T alpha) {
+  T H[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T h = T(0);
+#pragma unroll
+      for (int k = 0; k < NM; ++k) h += u[i][mode[k]] * av[k][j];
+      H[i][j] = h;
+    }
+  const T lt = lam * (H[0][0] + H[1][1] + H[2][2]);
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    const T *a = av[k];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T si = lt * a[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) si += mu * (H[i][j] + H[j][i]) * a[j];
+      w[i][mode[k]] += alpha * si;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void elasticity_element_parallelepiped(const T X[3][8],
+                                                                  const T (*u_in)[8], T lam,
+                                                                  T mu, T (*v)[8]) {
+  const T E1[3] = {X[0][1] - X[0][0], X[1][1] - X[1][0], X[2][1] - X[2][0]};
+  const T E2[3] = {X[0][2] - X[0][0], X[1][2] - X[1][0], X[2][2] - X[2][0]};
+  const T E4[3] = {X[0][4] - X[0][0], X[1][4] - X[1][0], X[2][4] - X[2][0]};
+  T a0[3], a1[3], a2[3];
+  cross(E2, E4, a0); cross(E4, E1, a1); cross(E1, E2, a2);
+  const T r = rcp(T(16) * dot3(E1, a0));
+  T u[3][8], w[3][8];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      u[c][a] = u_in[c][a];
+      w[c][a] = T(0);
+    }
+    butterfly_fwd(u[c]);
+  }
+  const T r3 = r * C<T>::third, r9 = r * C<T>::ninth;
+  {
+    constexpr int m[3] = {1, 2, 4};
+    const T *const a[3] = {a0, a1, a2};
+    elas_group<T, 3>(u, w, m, a, lam, mu, r);
+  }
+  {
+    constexpr int m[2] = {3, 6};  // through eta
+    const T *const a[2] = {a0, a2};
+    elas_group<T, 2>(u, w, m, a, lam, mu, r3);
+  }
+  {
+    constexpr int m[2] = {3, 5};  // through xi
+    const T *const a[2] = {a1, a2};
+    elas_group<T, 2>(u, w, m, a, lam, mu, r3);
+  }
+  {
+    constexpr int m[2] = {5, 6};  // through zeta
+    const T *const a[2] = {a0, a1};
+    elas_group<T, 2>(u, w, m, a, lam, mu, r3);
+  }
+  {
+    constexpr int m[1] = {7};
+    const T *const a_0[1] = {a0}, *const a_1[1] = {a1}, *const a_2[1] = {a2};
+    elas_group<T, 1>(u, w, m, a_0, lam, mu, r9);
+    elas_group<T, 1>(u, w, m, a_1, lam, mu, r9);
+    elas_group<T, 1>(u, w, m, a_2, lam, mu, r9);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    butterfly_bwd(w[c]);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[c][a] = w[c][a];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Partial assembly of the Laplace kinds: at each quadrature point q the
 // symmetric factor D_q = k w det J J^-1 J^-T, in the units of the modal
 // gradients above: D_q = (k/512) A A^T / det' with A the adjugate rows of the

@@ -43,6 +43,7 @@ struct TileMap {
   int64_t n_reset = 0;            // shared or Dirichlet nodes, reset before each apply
   int32_t *reset = nullptr;
   bool lds_atomic = false;        // corners collide within a step: accumulate with LDS atomics
+  bool all_affine = false;        // every tile is a parallelepiped tile
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
   uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16, or 0
   // block variant: partial sums of nodes shared between tiles go to halo slots

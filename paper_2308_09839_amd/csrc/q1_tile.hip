@@ -233,6 +233,8 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
       laplace_element_pa_n<T, DPN>(qd, u, v);
     } else if constexpr (PAR && PH != 3) {
       laplace_element_parallelepiped_n<T, DPN>(X, u, c0, v);
+    } else if constexpr (PAR) {
+      elasticity_element_parallelepiped<T>(X, u, c0, c1, v);
     } else {
       element_apply<T, PH>(X, u, c0, c1, v);
     }
@@ -246,7 +248,9 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
 // ONEACC: the four waves add into one LDS accumulator with LDS atomics (FP64,
 // where it frees LDS for a fourth resident block); otherwise each wave owns a
 // copy and the copies are summed in a fixed order.
-template <typename T, int PH, bool LDS_ATOMIC, bool ONEACC, bool PA>
+// ALLPAR: every tile of the operator is a parallelepiped tile (flagged at
+// set-up), so only the parallelepiped element is compiled in (fewer registers).
+template <typename T, int PH, bool LDS_ATOMIC, bool ONEACC, bool PA, bool ALLPAR>
 __global__ __launch_bounds__(256) void k_apply_block(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
@@ -323,14 +327,20 @@ __global__ __launch_bounds__(256) void k_apply_block(
   }
   __syncthreads();
   T *myV = ONEACC ? sV : sV + size_t(w) * DPN * max_nodes;
-  if (!PA && PH != 3 && tile_affine[tile])
-    block_steps<T, PH, LDS_ATOMIC || ONEACC, true, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
-                                                       lconn, coef_t, coef_stride, pk0, c00, c10,
-                                                       qdata, lat, s0);
-  else
-    block_steps<T, PH, LDS_ATOMIC || ONEACC, false, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
-                                                        lconn, coef_t, coef_stride, pk0, c00, c10,
-                                                        qdata, lat, s0);
+  if constexpr (ALLPAR && !PA) {
+    block_steps<T, PH, LDS_ATOMIC || ONEACC, true, false>(s0 + w, s1, lane, max_nodes, sR, myV,
+                                                          lconn, coef_t, coef_stride, pk0, c00,
+                                                          c10, qdata, lat, s0);
+  } else {
+    if (!PA && tile_affine[tile])
+      block_steps<T, PH, LDS_ATOMIC || ONEACC, true, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
+                                                         lconn, coef_t, coef_stride, pk0, c00,
+                                                         c10, qdata, lat, s0);
+    else
+      block_steps<T, PH, LDS_ATOMIC || ONEACC, false, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
+                                                          lconn, coef_t, coef_stride, pk0, c00,
+                                                          c10, qdata, lat, s0);
+  }
   __syncthreads();
   // nodes of this tile only: y; nodes shared with other tiles: this tile's halo
   // slot (summed by k_halo_sum); Dirichlet nodes: written by k_halo_sum
@@ -635,6 +645,8 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   tm.max_nodes = H.max_nodes;
   tm.n_reset = int64_t(H.reset.size());
   tm.lds_atomic = H.corner_collision;
+  tm.all_affine = std::all_of(H.tile_affine.begin(), H.tile_affine.end(),
+                              [](uint8_t a) { return a != 0; });
   auto up = [&](auto **dst, const auto &v) -> int {
     using E = typename std::remove_reference<decltype(v)>::type::value_type;
     const size_t b = std::max<size_t>(1, v.size()) * sizeof(E);
@@ -706,10 +718,13 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   if (block) {
     constexpr bool one = std::is_same<T, double>::value;
     constexpr bool pa_ok = PH != 3;  // partial assembly exists for the Laplace kinds
-    auto kb = tm.lds_atomic ? (pa && pa_ok ? k_apply_block<T, PH, true, one, pa_ok>
-                                           : k_apply_block<T, PH, true, one, false>)
-                            : (pa && pa_ok ? k_apply_block<T, PH, false, one, pa_ok>
-                                           : k_apply_block<T, PH, false, one, false>);
+    const bool allpar = tm.all_affine && !pa;
+    auto kb = pa && pa_ok ? (tm.lds_atomic ? k_apply_block<T, PH, true, one, pa_ok, false>
+                                           : k_apply_block<T, PH, false, one, pa_ok, false>)
+              : allpar    ? (tm.lds_atomic ? k_apply_block<T, PH, true, one, false, true>
+                                           : k_apply_block<T, PH, false, one, false, true>)
+                          : (tm.lds_atomic ? k_apply_block<T, PH, true, one, false, false>
+                                           : k_apply_block<T, PH, false, one, false, false>);
     hipLaunchKernelGGL(kb, dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes, op.n_nodes,
                        tm.node_ptr, tm.nodes, tm.tile_step,
                        reinterpret_cast<const uint4 *>(tm.lconn),
@@ -743,14 +758,15 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
 static int tile_layers(const Op &op) { return op.dpn() == 1 ? 4 : 2; }
 static int tile_patch_x(const Op &) { return 32; }
 
-// Block-staged tiles: 32 x 4 x 4 elements for scalar problems (two wavefront
-// steps per layer; measured on 128^3: FP64 58.8 us and FP32 41.2 us, against
-// 62.0 / 45.2 for 16x8x4, 64.0 / 47.3 for 16x4x8 and 71.6 / 46.0 for 16x16x2)
-// and 16 x 4 x 4 for elasticity (LDS); Q1_BLOCK_SHAPE="px,py,layers"
-// overrides the shape.
+// Block-staged tiles: 16 x 8 x 4 elements for scalar problems (two wavefront
+// steps per layer; measured on 128^3 with parallelepiped tiles: FP64 41.0 us
+// and FP32 30.6 us, against 43.2 / 30.2 for 32x4x4, 41.5 / 32.7 for 8x8x8 and
+// 45.2 / 34.3 for 16x16x2) and 16 x 4 x 4 for the 3-DOF kinds (96^3
+// elasticity FP64 48.4 us, against 49.5 for 16x8x2 and 49.8 for 8x8x4);
+// Q1_BLOCK_SHAPE="px,py,layers" overrides the shape.
 static void block_shape(const Op &op, int &px, int &py, int &layers) {
-  px = op.dpn() == 1 ? 32 : 16;
-  py = 4;
+  px = 16;
+  py = op.dpn() == 1 ? 8 : 4;
   layers = 4;
   if (const char *e = std::getenv("Q1_BLOCK_SHAPE")) {
     int a = 0, b = 0, c = 0;
