@@ -367,32 +367,52 @@ __global__ __launch_bounds__(256) void k_apply_block(
   for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, nodes[n0 + i], slot[n0 + i]);
 }
 
-// Second pass of the block variant, one thread per node on the reset list:
-// y = x on Dirichlet nodes, otherwise the sum of the node's halo slots in slot
-// (= tile) order, so every entry of y is written exactly once.
+// Second pass of the block variant over the reset list: y = x on Dirichlet
+// nodes, otherwise the sum of the node's halo slots in slot (= tile) order, so
+// every entry of y is written exactly once.  A free shared node owns at least
+// two slots and a Dirichlet node none, so the slot range alone tells them
+// apart.  Each thread takes kHaloNpt nodes (a block's nodes are contiguous) and
+// issues all their loads before summing.
+constexpr int kHaloNpt = 4;
 template <typename T, int DPN>
-__global__ void k_halo_sum(int64_t n, const int32_t *__restrict__ ids,
-                           const int32_t *__restrict__ hptr, const uint8_t *__restrict__ mask,
-                           const T *__restrict__ x, const T *__restrict__ halo,
-                           T *__restrict__ y, const int *__restrict__ stop) {
+__global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__restrict__ ids,
+                                                  const int32_t *__restrict__ hptr,
+                                                  const T *__restrict__ x,
+                                                  const T *__restrict__ halo,
+                                                  T *__restrict__ y,
+                                                  const int *__restrict__ stop) {
   if (stop && *stop) return;
-  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int64_t g = ids[j];
-  if (mask && mask[g]) {
+  const int64_t base = int64_t(blockIdx.x) * 256 * kHaloNpt + threadIdx.x;
+  int64_t g[kHaloNpt];
+  int32_t k0[kHaloNpt], k1[kHaloNpt];
 #pragma unroll
-    for (int c = 0; c < DPN; ++c) y[g * DPN + c] = x[g * DPN + c];
-    return;
+  for (int p = 0; p < kHaloNpt; ++p) {
+    const int64_t j = min(base + p * 256, n - 1);
+    g[p] = ids[j];
+    k0[p] = hptr[j];
+    k1[p] = hptr[j + 1];
   }
-  const int32_t k0 = hptr[j], k1 = hptr[j + 1];
-  T acc[DPN];
+  T acc[kHaloNpt][DPN];
 #pragma unroll
-  for (int c = 0; c < DPN; ++c) acc[c] = T(0);
-  for (int32_t k = k0; k < k1; ++k)
+  for (int p = 0; p < kHaloNpt; ++p)
 #pragma unroll
-    for (int c = 0; c < DPN; ++c) acc[c] += halo[int64_t(k) * DPN + c];
+    for (int c = 0; c < DPN; ++c) {
+      acc[p][c] = T(0);
+      if (k1[p] > k0[p])  // the first two slots of a shared node
+        acc[p][c] = halo[int64_t(k0[p]) * DPN + c] + halo[int64_t(k0[p] + 1) * DPN + c];
+    }
 #pragma unroll
-  for (int c = 0; c < DPN; ++c) y[g * DPN + c] = acc[c];
+  for (int p = 0; p < kHaloNpt; ++p)
+    for (int32_t k = k0[p] + 2; k < k1[p]; ++k)
+#pragma unroll
+      for (int c = 0; c < DPN; ++c) acc[p][c] += halo[int64_t(k) * DPN + c];
+#pragma unroll
+  for (int p = 0; p < kHaloNpt; ++p) {
+    if (base + p * 256 >= n) continue;
+#pragma unroll
+    for (int c = 0; c < DPN; ++c)
+      y[g[p] * DPN + c] = k1[p] > k0[p] ? acc[p][c] : x[g[p] * DPN + c];
+  }
 }
 
 // Partial-assembly set-up: the quadrature data of the element in each lane
@@ -733,8 +753,9 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
                        static_cast<T *>(tm.halo), static_cast<const T *>(tm.qdata),
                        tm.tile_lat);
     if (tm.n_reset > 0)
-      hipLaunchKernelGGL((k_halo_sum<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
-                         s, tm.n_reset, tm.reset, tm.hptr, op.mask, x,
+      hipLaunchKernelGGL((k_halo_sum<T, DPN>),
+                         dim3(int((tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt))), dim3(256),
+                         0, s, tm.n_reset, tm.reset, tm.hptr, x,
                          static_cast<const T *>(tm.halo), y, stop);
     Q1_HIP(hipGetLastError());
     return Q1_OK;
