@@ -48,9 +48,10 @@ struct TileMap {
   uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16, or 0
   // block variant: partial sums of nodes shared between tiles go to halo slots
   // (no atomics), summed per node by a second kernel in a fixed order
-  int64_t n_halo = 0;             // slots: one per (shared free node, tile touching it)
+  int64_t n_halo = 0;             // slots: 2 per reset node + one per further touching tile
   int32_t *slot = nullptr;        // [entries] halo slot of each node-list entry, -1 if none
-  int32_t *hptr = nullptr;        // [n_reset+1] slot range of each reset node (node-major)
+  int32_t *hptr = nullptr;        // [n_reset+1] extra-slot range of each reset node
+  int32_t *hnode = nullptr;       // [n_reset] node id, bit 31 set on Dirichlet nodes
   void *halo = nullptr;           // [n_halo][dpn] partial sums, overwritten by every apply
   void *qdata = nullptr;          // partial assembly: [48][n_steps*64] quadrature data
   size_t bytes = 0;

@@ -368,14 +368,13 @@ __global__ __launch_bounds__(256) void k_apply_block(
 }
 
 // Second pass of the block variant over the reset list: y = x on Dirichlet
-// nodes, otherwise the sum of the node's halo slots in slot (= tile) order, so
-// every entry of y is written exactly once.  A free shared node owns at least
-// two slots and a Dirichlet node none, so the slot range alone tells them
-// apart.  Each thread takes kHaloNpt nodes (a block's nodes are contiguous) and
-// issues all their loads before summing.
+// nodes, otherwise the sum of the node's halo slots in tile order (slots j and
+// n + j, then the extra slots of edge and corner nodes), so every entry of y
+// is written exactly once.  Each thread takes kHaloNpt nodes (a block's nodes
+// are contiguous) and issues all their loads before summing.
 constexpr int kHaloNpt = 4;
 template <typename T, int DPN>
-__global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__restrict__ ids,
+__global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__restrict__ hnode,
                                                   const int32_t *__restrict__ hptr,
                                                   const T *__restrict__ x,
                                                   const T *__restrict__ halo,
@@ -383,35 +382,33 @@ __global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__re
                                                   const int *__restrict__ stop) {
   if (stop && *stop) return;
   const int64_t base = int64_t(blockIdx.x) * 256 * kHaloNpt + threadIdx.x;
-  int64_t g[kHaloNpt];
-  int32_t k0[kHaloNpt], k1[kHaloNpt];
+  int64_t jj[kHaloNpt];
+  int32_t h[kHaloNpt], e0[kHaloNpt], e1[kHaloNpt];
 #pragma unroll
   for (int p = 0; p < kHaloNpt; ++p) {
-    const int64_t j = min(base + p * 256, n - 1);
-    g[p] = ids[j];
-    k0[p] = hptr[j];
-    k1[p] = hptr[j + 1];
+    jj[p] = min(base + p * 256, n - 1);
+    h[p] = hnode[jj[p]];
+    e0[p] = hptr[jj[p]];
+    e1[p] = hptr[jj[p] + 1];
   }
   T acc[kHaloNpt][DPN];
 #pragma unroll
   for (int p = 0; p < kHaloNpt; ++p)
 #pragma unroll
-    for (int c = 0; c < DPN; ++c) {
-      acc[p][c] = T(0);
-      if (k1[p] > k0[p])  // the first two slots of a shared node
-        acc[p][c] = halo[int64_t(k0[p]) * DPN + c] + halo[int64_t(k0[p] + 1) * DPN + c];
-    }
+    for (int c = 0; c < DPN; ++c)  // (read but unused on Dirichlet nodes)
+      acc[p][c] = halo[jj[p] * DPN + c] + halo[(n + jj[p]) * DPN + c];
 #pragma unroll
   for (int p = 0; p < kHaloNpt; ++p)
-    for (int32_t k = k0[p] + 2; k < k1[p]; ++k)
+    for (int32_t k = e0[p]; k < e1[p]; ++k)
 #pragma unroll
-      for (int c = 0; c < DPN; ++c) acc[p][c] += halo[int64_t(k) * DPN + c];
+      for (int c = 0; c < DPN; ++c) acc[p][c] += halo[(2 * n + k) * DPN + c];
 #pragma unroll
   for (int p = 0; p < kHaloNpt; ++p) {
     if (base + p * 256 >= n) continue;
+    const bool fixed = h[p] < 0;
+    const int64_t g = h[p] & 0x7fffffff;
 #pragma unroll
-    for (int c = 0; c < DPN; ++c)
-      y[g[p] * DPN + c] = k1[p] > k0[p] ? acc[p][c] : x[g[p] * DPN + c];
+    for (int c = 0; c < DPN; ++c) y[g * DPN + c] = fixed ? x[g * DPN + c] : acc[p][c];
   }
 }
 
@@ -458,7 +455,7 @@ struct HostTiles {
   int max_nodes = 0;
   bool corner_collision = false;   // two lanes of a step share a node at one corner
   std::vector<uint8_t> tile_affine;  // every element of the tile is a parallelepiped
-  std::vector<int32_t> slot, hptr;   // halo slots of the block variant
+  std::vector<int32_t> slot, hptr, hnode;  // halo slots of the block variant
   std::vector<uint32_t> tile_lat;    // lattice description of each tile (0: none)
 };
 
@@ -612,23 +609,30 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
     H.tile_affine.push_back(aff ? 1 : 0);
     for (int32_t g : list) local[g] = -1;
   }
-  // halo slots, node-major: reset node j owns slots [hptr[j], hptr[j+1]), one per
-  // tile touching it, in tile order; Dirichlet nodes own none
+  // halo slots.  Reset node j (a free node shared by c_j >= 2 tiles) receives the
+  // contributions of the tiles touching it in tile order: the first in slot j,
+  // the second in slot n_reset + j (so each tile's writes along a shared face are
+  // contiguous), the others in the extra region 2 n_reset + [hptr[j], hptr[j+1]).
+  // hnode[j] is the node id with bit 31 set on Dirichlet nodes (no slots).
   const int64_t nr = int64_t(H.reset.size());
   std::vector<int64_t> hp(nr + 1, 0);
+  H.hnode.assign(nr, 0);
   for (int64_t j = 0; j < nr; ++j) {
     const int32_t g = H.reset[j];
     const bool fixed = !mask.empty() && mask[g];
-    hp[j + 1] = hp[j] + (fixed ? 0 : ntile[g]);
+    hp[j + 1] = hp[j] + (fixed ? 0 : std::max(0, ntile[g] - 2));
+    H.hnode[j] = fixed ? int32_t(uint32_t(g) | 0x80000000u) : g;
     local[g] = int32_t(j);  // reset index (local[] is free again here)
   }
-  if (hp[nr] >= (int64_t(1) << 31)) return fail(Q1_EUNSUPPORTED, "too many halo slots");
+  if (2 * nr + hp[nr] >= (int64_t(1) << 31)) return fail(Q1_EUNSUPPORTED, "too many halo slots");
   H.hptr.assign(hp.begin(), hp.end());
   H.slot.assign(H.nodes.size(), -1);
-  std::vector<int32_t> next(H.hptr.begin(), H.hptr.end() - 1);
+  std::vector<int32_t> rank(nr, 0);
   for (size_t i = 0; i < H.nodes.size(); ++i) {
     const uint32_t v = H.nodes[i];
-    if ((v & kSharedBit) && !(v & kFixedBit)) H.slot[i] = next[local[v & kIdMask]]++;
+    if (!(v & kSharedBit) || (v & kFixedBit)) continue;
+    const int32_t jj = local[v & kIdMask], r = rank[jj]++;
+    H.slot[i] = r < 2 ? int32_t(r * nr + jj) : int32_t(2 * nr + H.hptr[jj] + (r - 2));
   }
   return Q1_OK;
 }
@@ -683,8 +687,10 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
     return rc;
   tm.coef_t = coef_dev;
   if (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) {
-    if ((rc = up(&tm.slot, H.slot)) || (rc = up(&tm.hptr, H.hptr))) return rc;
-    tm.n_halo = H.hptr.back();
+    if ((rc = up(&tm.slot, H.slot)) || (rc = up(&tm.hptr, H.hptr)) ||
+        (rc = up(&tm.hnode, H.hnode)))
+      return rc;
+    tm.n_halo = 2 * int64_t(H.reset.size()) + H.hptr.back();
     const size_t hb = std::max<int64_t>(1, tm.n_halo) * op.dpn() * sizeof(T);
     Q1_HIP(hipMalloc(&tm.halo, hb));
     tm.bytes += hb;
@@ -755,7 +761,7 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
     if (tm.n_reset > 0)
       hipLaunchKernelGGL((k_halo_sum<T, DPN>),
                          dim3(int((tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt))), dim3(256),
-                         0, s, tm.n_reset, tm.reset, tm.hptr, x,
+                         0, s, tm.n_reset, tm.hnode, tm.hptr, x,
                          static_cast<const T *>(tm.halo), y, stop);
     Q1_HIP(hipGetLastError());
     return Q1_OK;
@@ -828,7 +834,8 @@ int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *
 void free_tiles(Op &op) {
   TileMap &t = op.tiles;
   void *ptrs[] = {t.node_ptr, t.nodes, t.tile_step, t.lconn, t.reset,
-                  t.coef_t,   t.tile_affine, t.slot, t.hptr, t.halo, t.qdata, t.tile_lat};
+                  t.coef_t,   t.tile_affine, t.slot, t.hptr, t.halo, t.qdata, t.tile_lat,
+                  t.hnode};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   t = TileMap{};
