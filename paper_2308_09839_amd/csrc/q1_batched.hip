@@ -3,7 +3,7 @@
 //
 // Each problem p owns a contiguous range of single-wavefront workgroups
 // (sized in proportion to its element count).  The waves of a problem meet at
-// a barrier built from two global counters; problems never wait for each
+// a two-level barrier of global counters; problems never wait for each
 // other.  Vectors are stored interleaved [node][R] so that one gather of a
 // node serves all R right-hand sides.  Per iteration (the CG operations of
 // Table 4):
@@ -22,10 +22,11 @@
 // (and before convergence is declared) the true residual r = b - A64 x is
 // recomputed with an FP64 apply of x inside the same launch (three more
 // barriers), and the recurrences continue from it with p kept.
-// Every wave re-reduces the partials in
-// the same order, so all waves of a problem hold bit-identical scalars and
-// take the same branch.  Each barrier wait has a spin limit: past it the
-// kernel records an error and every wave returns.
+// The barrier itself sums the partials in a fixed order (per sub-group of
+// waves, then over sub-groups) and every wave reads the same totals, so all
+// waves of a problem hold bit-identical scalars and take the same branch.  Each
+// barrier wait has a spin limit: past it the kernel records an error and every
+// wave returns.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,7 +71,8 @@ struct BProb {
   float *p32, *q32;           // [nn][R]
   double *t;                  // [nn][R]
   double *part;               // [kSlots][R][nwg]
-  unsigned *bar;              // [2]: arrival count, generation
+  double *tot;                // [kSub + 1][2R] sub-group and problem totals
+  unsigned *bar;              // [kBarWords]: two-level barrier counters, generation
   int wg0, nwg;
   int *iters, *status, *nref; // [R]
   double *rr, *bb;            // [R]
@@ -82,51 +84,146 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// sum of n partials in a fixed order, returned to every lane
-__device__ __forceinline__ double reduce_partials(const double *part, int n) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kW) s += __hip_atomic_load(part + i, __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_AGENT);
-  return wave_sum64(s);
-}
-
-// barrier of the nwg waves of one problem; false when the spin limit was hit
-__device__ __forceinline__ bool problem_barrier(unsigned *bar, unsigned nwg, int *error) {
-  bool ok = true;
-  if (threadIdx.x == 0) {
-    const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // writes visible to other XCDs
-    const unsigned arrived =
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nwg - 1) {
-      __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > kSpinLimit || __hip_atomic_load(error, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT)) {
-          __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = false;
-          break;
+// Barrier of the nwg waves of one problem, optionally fused with the sum of two
+// partial-sum slots (sa, sb; sa < 0 for none) over the waves; false when the
+// spin limit was hit.  Two levels, so neither arrivals nor polling meet on one
+// address and no wave reads all nwg partials: wave me belongs to sub-group
+// me % kSub, whose counter and generation copy share a cache line of their
+// own.  The last arrival of a sub-group sums its members' partials (in member
+// order) into the sub-group's totals, resets the counter and arrives at the top
+// counter; the last top arrival sums the sub-group totals (in sub-group order),
+// writes the problem's totals, resets the top counter and writes the new
+// generation into every copy, which the waves poll.  Every wave then reads the
+// same totals, so all waves hold bit-identical scalars and take the same branch.
+// Ordering: the counters, generation copies and polls are relaxed atomics,
+// ordered by explicit fences (a release fence before each arrival, an acquire
+// fence after it is known to be complete), so each wave writes back and
+// invalidates its L2 once per barrier instead of once per poll.
+// bar: [0] top count, [32 (1 + k)] sub-counter k, [32 (1 + k) + 1] its generation.
+// tot: [kSub][2R] sub-group totals, then [2R] problem totals.
+constexpr unsigned kSub = 8;
+constexpr unsigned kBarWords = 32 * (kSub + 1);
+template <int R>
+__device__ __forceinline__ bool problem_sync(const BProb &P, unsigned me, unsigned nwg,
+                                             int *error, int sa, int sb, double (&a)[R],
+                                             double (&b)[R]) {
+  const int lane = threadIdx.x;
+  unsigned *bar = P.bar;
+  double *sub_tot = P.tot, *all_tot = P.tot + kSub * 2 * R;
+  const unsigned nsub = nwg < kSub ? nwg : kSub;  // sub-groups in use
+  const unsigned sub = me % nsub;
+  const unsigned members = (nwg - sub + nsub - 1) / nsub;
+  unsigned *sc = bar + 32 * (1 + sub);
+  unsigned gen = 0;
+  int sub_last = 0;
+  // the generation is read before the fence, which waits for the read to return
+  // and so orders it before this wave's arrival
+  if (lane == 0) gen = __hip_atomic_load(sc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's writes, all XCDs
+  if (lane == 0) {
+    sub_last = __hip_atomic_fetch_add(sc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               members - 1;
+  }
+  gen = __shfl(gen, 0);
+  sub_last = __shfl(sub_last, 0);
+  int top_last = 0;
+  if (sub_last) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (sa >= 0) {
+      double va[R], vb[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) va[c] = vb[c] = 0.0;
+      for (unsigned k = lane; k < members; k += kW) {
+        const int64_t w = sub + int64_t(k) * nsub;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          va[c] += P.part[(int64_t(sa) * R + c) * nwg + w];
+          vb[c] += P.part[(int64_t(sb) * R + c) * nwg + w];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        va[c] = wave_sum64(va[c]);
+        vb[c] = wave_sum64(vb[c]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          sub_tot[sub * 2 * R + c] = va[c];
+          sub_tot[sub * 2 * R + R + c] = vb[c];
         }
       }
     }
+    // every member has arrived: the counter is reset before the release fence,
+    // so the reset is complete before anyone can pass this barrier
+    if (lane == 0) __hip_atomic_store(sc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) {
+      top_last = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 nsub - 1;
+    }
+    top_last = __shfl(top_last, 0);
+  }
+  bool ok = true;
+  if (top_last) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (sa >= 0 && lane < 2 * R) {
+      double t = 0.0;
+      for (unsigned k = 0; k < nsub; ++k) t += sub_tot[k * 2 * R + lane];
+      all_tot[lane] = t;
+    }
+    if (lane == 0) __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // totals and reset before release
+    if (lane == 0) {
+      for (unsigned k = 0; k < nsub; ++k)
+        __hip_atomic_store(bar + 32 * (1 + k) + 1, gen + 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (lane == 0) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(sc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kSpinLimit ||
+          __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+        break;
+      }
+    }
   }
   ok = __shfl(ok ? 1 : 0, 0) != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (ok && sa >= 0) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      a[c] = __hip_atomic_load(all_tot + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      b[c] = __hip_atomic_load(all_tot + R + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
   return ok;
 }
 
+// plain barrier
+template <int R>
+__device__ __forceinline__ bool problem_barrier(const BProb &P, unsigned me, unsigned nwg,
+                                                int *error) {
+  double a[R], b[R];
+  return problem_sync<R>(P, me, nwg, error, -1, -1, a, b);
+}
+
 // q = A src over this wave's tiles (src, dst [nn][R] of type T; LDS accumulation in
-// FP64), and with ENERGY the element energies src_e^T A_e src_e.  Dirichlet
-// corners read zero; Dirichlet and shared nodes of dst are set by the caller.
-template <typename T, int R, bool ENERGY>
+// FP64), and with ENERGY the element energies src_e^T A_e src_e.  The R
+// right-hand sides are the components of one element product, so the geometry
+// is evaluated once per element; PAR: every tile of every problem is a
+// parallelepiped tile (flagged at set-up), so only corners 0, 1, 2, 4 are read
+// and the closed-form parallelepiped action is used.  Dirichlet corners read
+// zero; Dirichlet and shared nodes of dst are set by the caller; right-hand
+// sides marked skip are neither read nor written.
+template <typename T, int R, bool ENERGY, bool PAR>
 __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int lane,
                                             double *acc, uint32_t *sId, const T *xyz,
                                             const T *coef_t, const T *src, T *dst,
-                                            const bool (&done)[R], double (&energy)[R]) {
+                                            const bool (&skip)[R], double (&energy)[R]) {
   for (int t = me; t < P.n_tiles; t += nwg) {
     const int n0 = P.node_ptr[t], nm = P.node_ptr[t + 1] - n0;
     for (int i = lane; i < nm; i += kW) {
@@ -150,27 +247,30 @@ __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int
         g[a] = raw & kIdMaskB;
         fx[a] = (raw & kFixedBitB) != 0;
       }
-      T X0[3][8];
+      T X[3][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!PAR || a == 0 || a == 1 || a == 2 || a == 4)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) X[d][a] = xyz[d * P.nn + g[a]];
+      const T k = coef_t[slot];
+      T u[R][8], v[R][8];
 #pragma unroll
       for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) X0[d][a] = xyz[d * P.nn + g[a]];
-      const T k = coef_t[slot];
+        for (int c = 0; c < R; ++c) u[c][a] = (fx[a] || skip[c]) ? T(0) : src[g[a] * R + c];
+      if constexpr (PAR)
+        laplace_element_parallelepiped_n<T, R>(X, u, k, v);
+      else
+        laplace_element_n<T, R>(X, u, k, v);
 #pragma unroll
       for (int c = 0; c < R; ++c) {
-        if (done[c]) continue;
-        T X[3][8], u[8], v[8];
+        if (skip[c]) continue;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-          X[0][a] = X0[0][a]; X[1][a] = X0[1][a]; X[2][a] = X0[2][a];
-          u[a] = fx[a] ? T(0) : src[g[a] * R + c];
-        }
-        laplace_element<T>(X, u, k, v);
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          if constexpr (ENERGY) energy[c] += double(u[a]) * double(v[a]);
-          __hip_atomic_fetch_add(&acc[c * P.max_nodes + lc[a]], double(v[a]), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+          if constexpr (ENERGY) energy[c] += double(u[c][a]) * double(v[c][a]);
+          __hip_atomic_fetch_add(&acc[c * P.max_nodes + lc[a]], double(v[c][a]),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
     }
@@ -181,7 +281,7 @@ __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int
       const int64_t gg = raw & kIdMaskB;
 #pragma unroll
       for (int c = 0; c < R; ++c) {
-        if (done[c]) continue;
+        if (skip[c]) continue;
         const T vv = T(acc[c * P.max_nodes + i]);
         if (raw & kSharedBitB)
           unsafeAtomicAdd(&dst[gg * R + c], vv);
@@ -193,7 +293,7 @@ __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int
   }
 }
 
-template <int R, bool MIXED>
+template <int R, bool MIXED, bool PAR>
 __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ probs, int nprob,
                                                     const int *__restrict__ wg_prob, double tol2,
                                                     int maxit, double delta2, int *error) {
@@ -262,15 +362,13 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
       }
     }
   }
-  if (!problem_barrier(P.bar, nwg, error)) return;
   double rho[R], bb[R];
+  if (!problem_sync<R>(P, unsigned(me), unsigned(nwg), error, kRho0, kBB, rho, bb)) return;
   bool done[R];
   int it_done[R], st[R], nref[R];
   double rr_last[R], rr_ref[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) {
-    rho[c] = reduce_partials(part(kRho0, c), nwg);
-    bb[c] = reduce_partials(part(kBB, c), nwg);
     done[c] = !(bb[c] > 0.0);
     it_done[c] = 0;
     st[c] = Q1_OK;
@@ -287,23 +385,23 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
 #pragma unroll
     for (int c = 0; c < R; ++c) energy[c] = 0.0;
     if constexpr (MIXED)
-      apply_phase<float, R, true>(P, me, nwg, lane, acc, sId, P.xyz32, P.coef32, P.p32, P.q32,
+      apply_phase<float, R, true, PAR>(P, me, nwg, lane, acc, sId, P.xyz32, P.coef32, P.p32, P.q32,
                                   done, energy);
     else
-      apply_phase<double, R, true>(P, me, nwg, lane, acc, sId, P.xyz, P.coef_t, P.p, P.q, done,
+      apply_phase<double, R, true, PAR>(P, me, nwg, lane, acc, sId, P.xyz, P.coef_t, P.p, P.q, done,
                                    energy);
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       const double e = wave_sum64(energy[c]);
       if (lane == 0) part(kEnergy, c)[me] = e;
     }
-    if (!problem_barrier(P.bar, nwg, error)) return;
+    double alpha[R], en[R], mp[R];
+    if (!problem_sync<R>(P, unsigned(me), unsigned(nwg), error, kEnergy, kMp2, en, mp)) return;
 
     // ---- P2: alpha, x, r; partials rho', r.r
-    double alpha[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
-      const double pq = reduce_partials(part(kEnergy, c), nwg) + reduce_partials(part(kMp2, c), nwg);
+      const double pq = en[c] + mp[c];
       alpha[c] = 0.0;
       if (!done[c]) {
         if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho[c])) {
@@ -349,10 +447,10 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
         }
       }
     }
-    if (!problem_barrier(P.bar, nwg, error)) return;
+    double beta[R], rho_n[R], rr_n[R];
+    if (!problem_sync<R>(P, unsigned(me), unsigned(nwg), error, kRho, kRR, rho_n, rr_n)) return;
 
     // ---- P3: convergence, beta, p; reset q on shared and Dirichlet nodes
-    double beta[R];
     bool refresh[R];
     bool any_refresh = false;
 #pragma unroll
@@ -360,8 +458,8 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
       beta[c] = 0.0;
       refresh[c] = false;
       if (done[c]) continue;
-      const double rho1 = reduce_partials(part(kRho, c), nwg);
-      const double rr = reduce_partials(part(kRR, c), nwg);
+      const double rho1 = rho_n[c];
+      const double rr = rr_n[c];
       rr_last[c] = rr;
       if constexpr (MIXED) {
         // the recurrence only triggers a refresh; convergence is decided on b - A64 x
@@ -394,9 +492,9 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
         double unused[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) skip[c] = !refresh[c];
-        apply_phase<double, R, false>(P, me, nwg, lane, acc, sId, P.xyz, P.coef_t, P.x, P.t,
+        apply_phase<double, R, false, PAR>(P, me, nwg, lane, acc, sId, P.xyz, P.coef_t, P.x, P.t,
                                       skip, unused);
-        if (!problem_barrier(P.bar, nwg, error)) return;
+        if (!problem_barrier<R>(P, unsigned(me), unsigned(nwg), error)) return;
         // R2: r = b - A64 x (Dirichlet rows are the identity); partials rho', r.r
         double v_rho[R], v_rr[R];
 #pragma unroll
@@ -422,13 +520,14 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
             part(kRR, c)[me] = bq;
           }
         }
-        if (!problem_barrier(P.bar, nwg, error)) return;
+        if (!problem_sync<R>(P, unsigned(me), unsigned(nwg), error, kRho, kRR, rho_n, rr_n))
+          return;
         // R3: decide on the true residual; otherwise continue from it with p kept
 #pragma unroll
         for (int c = 0; c < R; ++c) {
           if (!refresh[c]) continue;
-          const double rho1 = reduce_partials(part(kRho, c), nwg);
-          const double rr = reduce_partials(part(kRR, c), nwg);
+          const double rho1 = rho_n[c];
+          const double rr = rr_n[c];
           rr_last[c] = rr;
           ++nref[c];
           if (rr <= tol2 * bb[c] || !isfinite(rr) || it >= maxit) {
@@ -502,7 +601,7 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
           P.q[g * R + c] = 0.0;
       }
     }
-    if (!problem_barrier(P.bar, nwg, error)) return;
+    if (!problem_barrier<R>(P, unsigned(me), unsigned(nwg), error)) return;
   }
   if (me == 0 && lane == 0) {
 #pragma unroll
@@ -537,7 +636,7 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ src, float *__res
   if (i < n) dst[i] = float(src[i]);
 }
 
-template <int R, bool MIXED>
+template <int R, bool MIXED, bool PAR>
 int run_batched(const std::vector<BProb> &hp, const std::vector<int> &wg_prob, double tol2,
                 int maxit, double delta2, size_t lds, hipStream_t s, int *d_error) {
   BProb *dp = nullptr;
@@ -549,8 +648,8 @@ int run_batched(const std::vector<BProb> &hp, const std::vector<int> &wg_prob, d
   int nprob = int(hp.size());
   void *args[] = {&dp, &nprob, &dwg, &tol2, &maxit, &delta2, &d_error};
   hipError_t e = hipLaunchCooperativeKernel(
-      reinterpret_cast<const void *>(k_batched_pcg<R, MIXED>), dim3(unsigned(wg_prob.size())),
-      dim3(kW), args, unsigned(lds), s);
+      reinterpret_cast<const void *>(k_batched_pcg<R, MIXED, PAR>),
+      dim3(unsigned(wg_prob.size())), dim3(kW), args, unsigned(lds), s);
   hipError_t e2 = hipStreamSynchronize(s);
   (void)hipFree(dp);
   (void)hipFree(dwg);
@@ -559,11 +658,11 @@ int run_batched(const std::vector<BProb> &hp, const std::vector<int> &wg_prob, d
   return Q1_OK;
 }
 
-template <int R, bool MIXED>
+template <int R, bool MIXED, bool PAR>
 int max_coresident(size_t lds) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(k_batched_pcg<R, MIXED>), kW, lds) !=
+          &per_cu, reinterpret_cast<const void *>(k_batched_pcg<R, MIXED, PAR>), kW, lds) !=
       hipSuccess)
     return 0;
   int dev = 0, cus = 0;
@@ -572,24 +671,24 @@ int max_coresident(size_t lds) {
   return per_cu * cus;
 }
 
-template <bool MIXED>
+template <bool MIXED, bool PAR>
 int coresident_for(int nrhs, size_t lds) {
   switch (nrhs) {
-    case 1: return max_coresident<1, MIXED>(lds);
-    case 2: return max_coresident<2, MIXED>(lds);
-    case 3: return max_coresident<3, MIXED>(lds);
-    default: return max_coresident<4, MIXED>(lds);
+    case 1: return max_coresident<1, MIXED, PAR>(lds);
+    case 2: return max_coresident<2, MIXED, PAR>(lds);
+    case 3: return max_coresident<3, MIXED, PAR>(lds);
+    default: return max_coresident<4, MIXED, PAR>(lds);
   }
 }
 
-template <bool MIXED>
+template <bool MIXED, bool PAR>
 int run_for(int nrhs, const std::vector<BProb> &hp, const std::vector<int> &wg_prob, double tol2,
             int maxit, double delta2, size_t lds, hipStream_t s, int *d_error) {
   switch (nrhs) {
-    case 1: return run_batched<1, MIXED>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
-    case 2: return run_batched<2, MIXED>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
-    case 3: return run_batched<3, MIXED>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
-    default: return run_batched<4, MIXED>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
+    case 1: return run_batched<1, MIXED, PAR>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
+    case 2: return run_batched<2, MIXED, PAR>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
+    case 3: return run_batched<3, MIXED, PAR>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
+    default: return run_batched<4, MIXED, PAR>(hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
   }
 }
 
@@ -615,15 +714,26 @@ int batched_impl(const char *name, bool mixed, int nprob, q1_op *const *ops, int
     max_nodes = std::max(max_nodes, o->tiles.max_nodes);
   }
   const size_t lds = size_t(max_nodes) * (size_t(nrhs) * sizeof(double) + sizeof(uint32_t));
-  const int cap = mixed ? coresident_for<true>(nrhs, lds) : coresident_for<false>(nrhs, lds);
+  bool par = true;  // every tile of every problem a parallelepiped tile
+  for (int p = 0; p < nprob; ++p) par = par && reinterpret_cast<const Op *>(ops[p])->tiles.all_affine;
+  const int cap = mixed ? (par ? coresident_for<true, true>(nrhs, lds)
+                               : coresident_for<true, false>(nrhs, lds))
+                        : (par ? coresident_for<false, true>(nrhs, lds)
+                               : coresident_for<false, false>(nrhs, lds));
   Q1_CHECK(cap >= nprob, Q1_EUNSUPPORTED, "%s: %d problems need %d co-resident waves", name,
            nprob, nprob);
-  // waves per problem in proportion to its elements, at least one each
+  // waves per problem in proportion to its expected work, at least one each:
+  // elements times iterations, and Jacobi-PCG iterations on an n^3 grid grow
+  // like n, so the weight is n_elems^(4/3)
   std::vector<int> nwg(nprob, 1);
   int spare = cap - nprob;
+  double wsum = 0.0;
+  for (int p = 0; p < nprob; ++p)
+    wsum += std::pow(double(reinterpret_cast<const Op *>(ops[p])->n_elems), 4.0 / 3.0);
   for (int p = 0; p < nprob; ++p) {
     const Op *o = reinterpret_cast<const Op *>(ops[p]);
-    const int extra = int(double(spare) * double(o->n_elems) / double(std::max<int64_t>(1, total_elems)));
+    const double wp = std::pow(double(o->n_elems), 4.0 / 3.0);
+    const int extra = int(double(spare) * wp / std::max(1.0, wsum));
     nwg[p] += std::min(extra, std::max(0, o->tiles.n_tiles - 1));
   }
   // device workspace per problem
@@ -706,8 +816,10 @@ int batched_impl(const char *name, bool mixed, int nprob, q1_op *const *ops, int
     if ((rc = dalloc(reinterpret_cast<void **>(&B.part), size_t(kSlots) * nrhs * nwg[p] *
                                                              sizeof(double))))
       return rc;
-    if ((rc = dalloc(reinterpret_cast<void **>(&B.bar), 2 * sizeof(unsigned)))) return rc;
-    Q1_HIP(hipMemsetAsync(B.bar, 0, 2 * sizeof(unsigned), s));
+    if ((rc = dalloc(reinterpret_cast<void **>(&B.bar), kBarWords * sizeof(unsigned)))) return rc;
+    if ((rc = dalloc(reinterpret_cast<void **>(&B.tot), (kSub + 1) * 2 * nrhs * sizeof(double))))
+      return rc;
+    Q1_HIP(hipMemsetAsync(B.bar, 0, kBarWords * sizeof(unsigned), s));
     B.wg0 = int(wg_prob.size());
     B.nwg = nwg[p];
     for (int k = 0; k < nwg[p]; ++k) wg_prob.push_back(p);
@@ -721,8 +833,11 @@ int batched_impl(const char *name, bool mixed, int nprob, q1_op *const *ops, int
   Q1_HIP(hipStreamSynchronize(s));
   const auto t_setup = std::chrono::steady_clock::now();
   const double tol2 = rtol * rtol, delta2 = delta * delta;
-  rc = mixed ? run_for<true>(nrhs, hp, wg_prob, tol2, maxit, delta2, lds, s, d_error)
-             : run_for<false>(nrhs, hp, wg_prob, tol2, maxit, delta2, lds, s, d_error);
+  rc = mixed ? (par ? run_for<true, true>(nrhs, hp, wg_prob, tol2, maxit, delta2, lds, s, d_error)
+                    : run_for<true, false>(nrhs, hp, wg_prob, tol2, maxit, delta2, lds, s, d_error))
+             : (par ? run_for<false, true>(nrhs, hp, wg_prob, tol2, maxit, delta2, lds, s, d_error)
+                    : run_for<false, false>(nrhs, hp, wg_prob, tol2, maxit, delta2, lds, s,
+                                            d_error));
   if (rc) return rc;
   const auto t_solve = std::chrono::steady_clock::now();
   int h_error = 0;
