@@ -9,12 +9,11 @@
 // Table 4):
 //   P1  q = A p through the operator's LDS tiles (as in q1_tile.hip), and the
 //       partial sums of p^T A p as element energies sum_e p_e^T A_e p_e
-//   P2  alpha = rho / p^T A p; x += alpha p; r -= alpha q; partials of
-//       rho' = r^T D^{-1} r and r^T r
+//   P2  alpha = rho / p^T A p; x += alpha p; r -= alpha q; q = 0 once read;
+//       partials of rho' = r^T D^{-1} r and r^T r
 //   P3  convergence test; beta = rho'/rho; p = D^{-1} r + beta p; q = p on
-//       Dirichlet nodes (their rows of A p) and q = 0 on nodes shared between
-//       tiles, ready for the next P1; partials of sum p_c^2 over Dirichlet
-//       nodes
+//       Dirichlet nodes (their rows of A p), ready for the next P1; partials
+//       of sum p_c^2 over Dirichlet nodes
 // with one barrier after each phase.  In the mixed-precision form the search
 // directions p, q and the applies of P1 are FP32 (the FP32 operator's
 // coordinates and coefficients), while x, r and every dot product stay FP64;
@@ -48,6 +47,11 @@ constexpr uint32_t kSharedBitB = 0x80000000u;
 constexpr uint32_t kFixedBitB = 0x40000000u;
 constexpr uint32_t kIdMaskB = 0x3fffffffu;
 constexpr unsigned kSpinLimit = 1u << 26;  // barrier polls before giving up
+// Nodes per lane per round in the vector phases: every load of a round is
+// issued before its stores (gfx9 waits for loads and stores on one counter, so
+// a round costs one load and one store latency whatever kU is).
+constexpr int kU = 4;
+constexpr int kStage = 8;  // node ids per lane per staging round of a tile
 
 // partial-sum slots per problem: [slot][rhs][nwg]
 enum { kEnergy = 0, kMp2 = 1, kRho = 2, kRR = 3, kBB = 4, kRho0 = 5, kSlots = 6 };
@@ -226,15 +230,39 @@ __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int
                                             const bool (&skip)[R], double (&energy)[R]) {
   for (int t = me; t < P.n_tiles; t += nwg) {
     const int n0 = P.node_ptr[t], nm = P.node_ptr[t + 1] - n0;
-    for (int i = lane; i < nm; i += kW) {
-      sId[i] = P.nodes[n0 + i];
+    const int s0 = P.tile_step[t], s1 = P.tile_step[t + 1];
+    // the first step's corner words and coefficient are requested with the staging
+    // loads, and each later step's one step ahead, so a step waits for one memory
+    // latency (its gathers) instead of two
+    uint4 pk_next = make_uint4(0xffffffffu, 0, 0, 0);
+    T k_next = T(0);
+    if (s0 < s1) {
+      pk_next = P.lconn[int64_t(s0) * kW + lane];
+      k_next = coef_t[int64_t(s0) * kW + lane];
+    }
+    // node ids staged kStage per lane per round, all loads of a round issued first
+    for (int ib = lane; ib < nm; ib += kStage * kW) {
+      uint32_t id[kStage];
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc[c * P.max_nodes + i] = 0.0;
+      for (int u = 0; u < kStage; ++u) id[u] = ib + u * kW < nm ? P.nodes[n0 + ib + u * kW] : 0u;
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int i = ib + u * kW;
+        if (i >= nm) continue;
+        sId[i] = id[u];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c * P.max_nodes + i] = 0.0;
+      }
     }
     __syncthreads();
-    for (int s = P.tile_step[t]; s < P.tile_step[t + 1]; ++s) {
+    for (int s = s0; s < s1; ++s) {
       const int64_t slot = int64_t(s) * kW + lane;
-      const uint4 pk = P.lconn[slot];
+      const uint4 pk = pk_next;
+      const T k = k_next;
+      if (s + 1 < s1) {
+        pk_next = P.lconn[slot + kW];
+        k_next = coef_t[slot + kW];
+      }
       if (pk.x == 0xffffffffu) continue;
       const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff),
                          int(pk.y >> 16),    int(pk.z & 0xffff), int(pk.z >> 16),
@@ -253,7 +281,6 @@ __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int
         if (!PAR || a == 0 || a == 1 || a == 2 || a == 4)
 #pragma unroll
           for (int d = 0; d < 3; ++d) X[d][a] = xyz[d * P.nn + g[a]];
-      const T k = coef_t[slot];
       T u[R][8], v[R][8];
 #pragma unroll
       for (int a = 0; a < 8; ++a)
@@ -417,25 +444,49 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
       double v_rho[R], v_rr[R];
 #pragma unroll
       for (int c = 0; c < R; ++c) v_rho[c] = v_rr[c] = 0.0;
-      for (int64_t i = i0 + lane; i < i1; i += kW) {
-        const double wi = P.w[i];
+      for (int64_t ib = i0 + lane; ib < i1; ib += kU * kW) {
+        double wv[kU], po[kU][R], qo[kU][R], xo[kU][R], ro[kU][R];
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-          if (done[c]) continue;
-          const int64_t o = i * R + c;
-          double po, qo;
-          if constexpr (MIXED) {
-            po = double(P.p32[o]);
-            qo = double(P.q32[o]);
-          } else {
-            po = P.p[o];
-            qo = P.q[o];
+        for (int u = 0; u < kU; ++u) {
+          const int64_t i = ib + u * kW;
+          const bool in = i < i1;
+          wv[u] = in ? P.w[i] : 0.0;
+#pragma unroll
+          for (int c = 0; c < R; ++c) {
+            const int64_t o = i * R + c;
+            const bool ld = in && !done[c];
+            if constexpr (MIXED) {
+              po[u][c] = ld ? double(P.p32[o]) : 0.0;
+              qo[u][c] = ld ? double(P.q32[o]) : 0.0;
+            } else {
+              po[u][c] = ld ? P.p[o] : 0.0;
+              qo[u][c] = ld ? P.q[o] : 0.0;
+            }
+            xo[u][c] = ld ? P.x[o] : 0.0;
+            ro[u][c] = ld ? P.r[o] : 0.0;
           }
-          P.x[o] += alpha[c] * po;
-          const double rn = P.r[o] - alpha[c] * qo;
-          P.r[o] = rn;
-          v_rho[c] += rn * wi * rn;
-          v_rr[c] += rn * rn;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int64_t i = ib + u * kW;
+          if (i >= i1) continue;
+#pragma unroll
+          for (int c = 0; c < R; ++c) {
+            if (done[c]) continue;
+            const int64_t o = i * R + c;
+            P.x[o] = xo[u][c] + alpha[c] * po[u][c];
+            const double rn = ro[u][c] - alpha[c] * qo[u][c];
+            P.r[o] = rn;
+            // q was last read here: zero it for the next P1, whose tiles store
+            // their private nodes and add into shared ones (P3 then sets the
+            // Dirichlet rows)
+            if constexpr (MIXED)
+              P.q32[o] = 0.0f;
+            else
+              P.q[o] = 0.0;
+            v_rho[c] += rn * wv[u] * rn;
+            v_rr[c] += rn * rn;
+          }
         }
       }
 #pragma unroll
@@ -450,7 +501,7 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
     double beta[R], rho_n[R], rr_n[R];
     if (!problem_sync<R>(P, unsigned(me), unsigned(nwg), error, kRho, kRR, rho_n, rr_n)) return;
 
-    // ---- P3: convergence, beta, p; reset q on shared and Dirichlet nodes
+    // ---- P3: convergence, beta, p; q on Dirichlet nodes
     bool refresh[R];
     bool any_refresh = false;
 #pragma unroll
@@ -558,26 +609,48 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
       double v_mp[R];
 #pragma unroll
       for (int c = 0; c < R; ++c) v_mp[c] = 0.0;
-      for (int64_t i = i0 + lane; i < i1; i += kW) {
-        const double wi = P.w[i];
-        const bool fx = P.mask && P.mask[i];
+      for (int64_t ib = i0 + lane; ib < i1; ib += kU * kW) {
+        double wv[kU], ro[kU][R], po[kU][R];
+        bool fx[kU];
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-          if (done[c]) continue;
-          const int64_t o = i * R + c;
-          if constexpr (MIXED) {
-            const float pn = float(wi * P.r[o] + beta[c] * double(P.p32[o]));
-            P.p32[o] = pn;
-            if (fx) {
-              P.q32[o] = pn;  // Dirichlet rows of A p: the entry itself
-              v_mp[c] += double(pn) * double(pn);
-            }
-          } else {
-            const double pn = wi * P.r[o] + beta[c] * P.p[o];
-            P.p[o] = pn;
-            if (fx) {
-              P.q[o] = pn;  // Dirichlet rows of A p: the entry itself
-              v_mp[c] += pn * pn;
+        for (int u = 0; u < kU; ++u) {
+          const int64_t i = ib + u * kW;
+          const bool in = i < i1;
+          wv[u] = in ? P.w[i] : 0.0;
+          fx[u] = in && P.mask && P.mask[i];
+#pragma unroll
+          for (int c = 0; c < R; ++c) {
+            const int64_t o = i * R + c;
+            const bool ld = in && !done[c];
+            ro[u][c] = ld ? P.r[o] : 0.0;
+            if constexpr (MIXED)
+              po[u][c] = ld ? double(P.p32[o]) : 0.0;
+            else
+              po[u][c] = ld ? P.p[o] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int64_t i = ib + u * kW;
+          if (i >= i1) continue;
+#pragma unroll
+          for (int c = 0; c < R; ++c) {
+            if (done[c]) continue;
+            const int64_t o = i * R + c;
+            if constexpr (MIXED) {
+              const float pn = float(wv[u] * ro[u][c] + beta[c] * po[u][c]);
+              P.p32[o] = pn;
+              if (fx[u]) {
+                P.q32[o] = pn;  // Dirichlet rows of A p: the entry itself
+                v_mp[c] += double(pn) * double(pn);
+              }
+            } else {
+              const double pn = wv[u] * ro[u][c] + beta[c] * po[u][c];
+              P.p[o] = pn;
+              if (fx[u]) {
+                P.q[o] = pn;  // Dirichlet rows of A p: the entry itself
+                v_mp[c] += pn * pn;
+              }
             }
           }
         }
@@ -586,19 +659,6 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
       for (int c = 0; c < R; ++c) {
         const double m = wave_sum64(v_mp[c]);
         if (lane == 0) part(kMp2, c)[me] = m;
-      }
-    }
-    // shared nodes of q start the next P1 at zero (their values were last read in P2)
-    for (int64_t j = j0 + lane; j < j1; j += kW) {
-      const int64_t g = P.reset[j];
-      if (P.mask && P.mask[g]) continue;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (done[c]) continue;
-        if constexpr (MIXED)
-          P.q32[g * R + c] = 0.0f;
-        else
-          P.q[g * R + c] = 0.0;
       }
     }
     if (!problem_barrier<R>(P, unsigned(me), unsigned(nwg), error)) return;
