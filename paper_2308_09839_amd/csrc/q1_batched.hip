@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <cmath>
 #include <new>
@@ -81,6 +82,85 @@ struct BProb {
   int *iters, *status, *nref; // [R]
   double *rr, *bb;            // [R]
 };
+
+// The problem records are read from memory, so the compiler cannot tell that
+// their pointers address global memory and would access them with flat
+// instructions, which also count on the LDS counter: every LDS wait of the
+// apply (node ids, accumulator atomics) would then wait for all outstanding
+// memory loads.  The kernel therefore reads each record through a twin whose
+// pointers are typed as global-address-space pointers; converting those to
+// ordinary pointers keeps the fact that they address global memory, and the
+// compiler emits global instructions for every access made through them.
+#define Q1_GLB __attribute__((address_space(1)))
+struct BProbG {
+  int64_t nn;
+  int n_tiles, max_nodes;
+  const Q1_GLB int32_t *node_ptr;
+  const Q1_GLB uint32_t *nodes;
+  const Q1_GLB int32_t *tile_step;
+  const Q1_GLB uint4 *lconn;
+  const Q1_GLB double *coef_t;
+  const Q1_GLB double *xyz;
+  const Q1_GLB int32_t *reset;
+  int64_t n_reset;
+  const Q1_GLB uint8_t *mask;
+  Q1_GLB double *b, *x, *r, *p, *q;
+  const Q1_GLB double *w;
+  const Q1_GLB float *xyz32, *coef32;
+  Q1_GLB float *p32, *q32;
+  Q1_GLB double *t;
+  Q1_GLB double *part;
+  Q1_GLB double *tot;
+  Q1_GLB unsigned *bar;
+  int wg0, nwg;
+  Q1_GLB int *iters, *status, *nref;
+  Q1_GLB double *rr, *bb;
+};
+static_assert(sizeof(BProbG) == sizeof(BProb) && offsetof(BProbG, bb) == offsetof(BProb, bb) &&
+                  offsetof(BProbG, n_reset) == offsetof(BProb, n_reset) &&
+                  offsetof(BProbG, wg0) == offsetof(BProb, wg0),
+              "BProbG must mirror BProb");
+
+__device__ __forceinline__ BProb load_problem(const BProb *src) {
+  BProbG G;
+  __builtin_memcpy(&G, src, sizeof(G));
+  BProb P;
+  P.nn = G.nn;
+  P.n_tiles = G.n_tiles;
+  P.max_nodes = G.max_nodes;
+  P.node_ptr = (const int32_t *)G.node_ptr;
+  P.nodes = (const uint32_t *)G.nodes;
+  P.tile_step = (const int32_t *)G.tile_step;
+  P.lconn = (const uint4 *)G.lconn;
+  P.coef_t = (const double *)G.coef_t;
+  P.xyz = (const double *)G.xyz;
+  P.reset = (const int32_t *)G.reset;
+  P.n_reset = G.n_reset;
+  P.mask = (const uint8_t *)G.mask;
+  P.b = (double *)G.b;
+  P.x = (double *)G.x;
+  P.r = (double *)G.r;
+  P.p = (double *)G.p;
+  P.q = (double *)G.q;
+  P.w = (const double *)G.w;
+  P.xyz32 = (const float *)G.xyz32;
+  P.coef32 = (const float *)G.coef32;
+  P.p32 = (float *)G.p32;
+  P.q32 = (float *)G.q32;
+  P.t = (double *)G.t;
+  P.part = (double *)G.part;
+  P.tot = (double *)G.tot;
+  P.bar = (unsigned *)G.bar;
+  P.wg0 = G.wg0;
+  P.nwg = G.nwg;
+  P.iters = (int *)G.iters;
+  P.status = (int *)G.status;
+  P.nref = (int *)G.nref;
+  P.rr = (double *)G.rr;
+  P.bb = (double *)G.bb;
+  return P;
+}
+#undef Q1_GLB
 
 __device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll
@@ -326,7 +406,7 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
                                                     int maxit, double delta2, int *error) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x;
-  const BProb P = probs[wg_prob[blockIdx.x]];
+  const BProb P = load_problem(probs + wg_prob[blockIdx.x]);
   const int me = int(blockIdx.x) - P.wg0;
   const int nwg = P.nwg;
   double *acc = reinterpret_cast<double *>(smem_raw);                        // [R][max_nodes]
