@@ -2,24 +2,27 @@
 // each with up to four right-hand sides, solved by ONE cooperative launch.
 //
 // Each problem p owns a contiguous range of single-wavefront workgroups
-// (sized in proportion to its element count).  The waves of a problem meet at
+// (sized in proportion to its expected work).  The waves of a problem meet at
 // a two-level barrier of global counters; problems never wait for each
 // other.  Vectors are stored interleaved [node][R] so that one gather of a
 // node serves all R right-hand sides.  Per iteration (the CG operations of
-// Table 4):
-//   P1  q = A p through the operator's LDS tiles (as in q1_tile.hip), and the
-//       partial sums of p^T A p as element energies sum_e p_e^T A_e p_e
+// Table 4, regrouped):
+//   P1  over the operator's LDS tiles (as in q1_tile.hip): the direction
+//       update p = D^{-1} r + beta p_old on each tile's nodes into LDS (the
+//       node's writer entry also stores it, and q = p on Dirichlet nodes,
+//       their rows of A p), then q = A p from the staged p, with the partials
+//       of p^T A p (element energies sum_e p_e^T A_e p_e and p^2 on Dirichlet
+//       nodes).  p alternates between two buffers, so reading p_old and
+//       writing p needs no barrier in between.
 //   P2  alpha = rho / p^T A p; x += alpha p; r -= alpha q; q = 0 once read;
-//       partials of rho' = r^T D^{-1} r and r^T r
-//   P3  convergence test; beta = rho'/rho; p = D^{-1} r + beta p; q = p on
-//       Dirichlet nodes (their rows of A p), ready for the next P1; partials
-//       of sum p_c^2 over Dirichlet nodes
+//       partials of rho' = r^T D^{-1} r and r^T r; then the convergence test
+//       and beta = rho'/rho for the next P1
 // with one barrier after each phase.  In the mixed-precision form the search
 // directions p, q and the applies of P1 are FP32 (the FP32 operator's
 // coordinates and coefficients), while x, r and every dot product stay FP64;
 // whenever the recurrence residual has fallen by delta since the last refresh
 // (and before convergence is declared) the true residual r = b - A64 x is
-// recomputed with an FP64 apply of x inside the same launch (three more
+// recomputed with an FP64 apply of x inside the same launch (two more
 // barriers), and the recurrences continue from it with p kept.
 // The barrier itself sums the partials in a fixed order (per sub-group of
 // waves, then over sub-groups) and every wave reads the same totals, so all
@@ -29,10 +32,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstddef>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
+#include <cstdint>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "q1_elem.hpp"
@@ -47,6 +52,11 @@ constexpr int kRmax = 4;
 constexpr uint32_t kSharedBitB = 0x80000000u;
 constexpr uint32_t kFixedBitB = 0x40000000u;
 constexpr uint32_t kIdMaskB = 0x3fffffffu;
+// In the per-problem copy of the tile node lists the search-direction phase
+// reads, bit 29 marks the one entry (in the first tile holding the node) that
+// writes the node's new direction; ids are then below 2^29.
+constexpr uint32_t kOwnBitB = 0x20000000u;
+constexpr uint32_t kIdMaskOwnB = 0x1fffffffu;
 constexpr unsigned kSpinLimit = 1u << 26;  // barrier polls before giving up
 // Nodes per lane per round in the vector phases: every load of a round is
 // issued before its stores (gfx9 waits for loads and stores on one counter, so
@@ -62,6 +72,7 @@ struct BProb {
   int n_tiles, max_nodes;
   const int32_t *node_ptr;
   const uint32_t *nodes;
+  const uint32_t *onodes;     // the node lists with the writer bit
   const int32_t *tile_step;
   const uint4 *lconn;
   const double *coef_t;
@@ -69,11 +80,12 @@ struct BProb {
   const int32_t *reset;
   int64_t n_reset;
   const uint8_t *mask;
-  double *b, *x, *r, *p, *q;  // [nn][R]
+  double *b, *x, *r, *q;      // [nn][R]
+  double *p[2];               // [nn][R]: directions of odd and even iterations
   const double *w;            // inverse diagonal [nn]
   // mixed precision: FP32 geometry, coefficients and directions; FP64 refresh output
   const float *xyz32, *coef32;
-  float *p32, *q32;           // [nn][R]
+  float *p32[2], *q32;        // [nn][R]
   double *t;                  // [nn][R]
   double *part;               // [kSlots][R][nwg]
   double *tot;                // [kSub + 1][2R] sub-group and problem totals
@@ -97,6 +109,7 @@ struct BProbG {
   int n_tiles, max_nodes;
   const Q1_GLB int32_t *node_ptr;
   const Q1_GLB uint32_t *nodes;
+  const Q1_GLB uint32_t *onodes;
   const Q1_GLB int32_t *tile_step;
   const Q1_GLB uint4 *lconn;
   const Q1_GLB double *coef_t;
@@ -104,10 +117,11 @@ struct BProbG {
   const Q1_GLB int32_t *reset;
   int64_t n_reset;
   const Q1_GLB uint8_t *mask;
-  Q1_GLB double *b, *x, *r, *p, *q;
+  Q1_GLB double *b, *x, *r, *q;
+  Q1_GLB double *p[2];
   const Q1_GLB double *w;
   const Q1_GLB float *xyz32, *coef32;
-  Q1_GLB float *p32, *q32;
+  Q1_GLB float *p32[2], *q32;
   Q1_GLB double *t;
   Q1_GLB double *part;
   Q1_GLB double *tot;
@@ -130,6 +144,7 @@ __device__ __forceinline__ BProb load_problem(const BProb *src) {
   P.max_nodes = G.max_nodes;
   P.node_ptr = (const int32_t *)G.node_ptr;
   P.nodes = (const uint32_t *)G.nodes;
+  P.onodes = (const uint32_t *)G.onodes;
   P.tile_step = (const int32_t *)G.tile_step;
   P.lconn = (const uint4 *)G.lconn;
   P.coef_t = (const double *)G.coef_t;
@@ -140,12 +155,14 @@ __device__ __forceinline__ BProb load_problem(const BProb *src) {
   P.b = (double *)G.b;
   P.x = (double *)G.x;
   P.r = (double *)G.r;
-  P.p = (double *)G.p;
+  P.p[0] = (double *)G.p[0];
+  P.p[1] = (double *)G.p[1];
   P.q = (double *)G.q;
   P.w = (const double *)G.w;
   P.xyz32 = (const float *)G.xyz32;
   P.coef32 = (const float *)G.coef32;
-  P.p32 = (float *)G.p32;
+  P.p32[0] = (float *)G.p32[0];
+  P.p32[1] = (float *)G.p32[1];
   P.q32 = (float *)G.q32;
   P.t = (double *)G.t;
   P.part = (double *)G.part;
@@ -400,6 +417,138 @@ __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int
   }
 }
 
+// The direction update and q = A p in one pass over this wave's tiles.  For
+// each tile node the new direction p = D^-1 r + beta p_old (p = D^-1 r on the
+// first iteration) is computed into LDS, where the element loop reads it (zero
+// on Dirichlet corners and for finished right-hand sides); the node's writer
+// entry also stores it to pnew and, on a Dirichlet node, sets q = p there (its
+// row of A p) and adds p^2 to mp.  A node held by several tiles is computed
+// by each from the same values, so every copy agrees.  Reading p_old from one
+// buffer and writing pnew to the other lets the update run without a barrier
+// before the apply.  With the element energies p_e^T A_e p_e (energy), mp
+// completes p^T A p.  T is the precision of p, q and the element arithmetic.
+template <typename T, int R, bool PAR>
+__device__ __forceinline__ void update_apply_phase(const BProb &P, int me, int nwg, int lane,
+                                                   double *acc, uint32_t *sId, T *sP,
+                                                   const T *xyz, const T *coef_t, const T *pold,
+                                                   T *pnew, T *q, const bool (&done)[R],
+                                                   const double (&beta)[R], bool first,
+                                                   double (&energy)[R], double (&mp)[R]) {
+  const int M = P.max_nodes;
+  for (int t = me; t < P.n_tiles; t += nwg) {
+    const int n0 = P.node_ptr[t], nm = P.node_ptr[t + 1] - n0;
+    const int s0 = P.tile_step[t], s1 = P.tile_step[t + 1];
+    uint4 pk_next = make_uint4(0xffffffffu, 0, 0, 0);
+    T k_next = T(0);
+    if (s0 < s1) {
+      pk_next = P.lconn[int64_t(s0) * kW + lane];
+      k_next = coef_t[int64_t(s0) * kW + lane];
+    }
+    for (int ib = lane; ib < nm; ib += kStage * kW) {
+      uint32_t id[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u)
+        id[u] = ib + u * kW < nm ? P.onodes[n0 + ib + u * kW] : 0u;
+      double wv[kStage], rv[kStage][R], pv[kStage][R];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const bool in = ib + u * kW < nm;
+        const int64_t g = id[u] & kIdMaskOwnB;
+        wv[u] = in ? P.w[g] : 0.0;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          const bool ld = in && !done[c];
+          rv[u][c] = ld ? P.r[g * R + c] : 0.0;
+          pv[u][c] = (ld && !first) ? double(pold[g * R + c]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int i = ib + u * kW;
+        if (i >= nm) continue;
+        const uint32_t raw = id[u];
+        const bool fixed = (raw & kFixedBitB) != 0, own = (raw & kOwnBitB) != 0;
+        const int64_t g = raw & kIdMaskOwnB;
+        sId[i] = raw;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          acc[c * M + i] = 0.0;
+          if (done[c]) {
+            sP[c * M + i] = T(0);
+            continue;
+          }
+          const T pn = T(wv[u] * rv[u][c] + beta[c] * pv[u][c]);
+          sP[c * M + i] = fixed ? T(0) : pn;
+          if (own) {
+            pnew[g * R + c] = pn;
+            if (fixed) {
+              q[g * R + c] = pn;  // Dirichlet rows of A p: the entry itself
+              mp[c] += double(pn) * double(pn);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int s = s0; s < s1; ++s) {
+      const int64_t slot = int64_t(s) * kW + lane;
+      const uint4 pk = pk_next;
+      const T k = k_next;
+      if (s + 1 < s1) {
+        pk_next = P.lconn[slot + kW];
+        k_next = coef_t[slot + kW];
+      }
+      if (pk.x == 0xffffffffu) continue;
+      const int lc[8] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff),
+                         int(pk.y >> 16),    int(pk.z & 0xffff), int(pk.z >> 16),
+                         int(pk.w & 0xffff), int(pk.w >> 16)};
+      T X[3][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!PAR || a == 0 || a == 1 || a == 2 || a == 4) {
+          const int64_t g = sId[lc[a]] & kIdMaskOwnB;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) X[d][a] = xyz[d * P.nn + g];
+        }
+      T u[R][8], v[R][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < R; ++c) u[c][a] = sP[c * M + lc[a]];
+      if constexpr (PAR)
+        laplace_element_parallelepiped_n<T, R>(X, u, k, v);
+      else
+        laplace_element_n<T, R>(X, u, k, v);
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (done[c]) continue;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          energy[c] += double(u[c][a]) * double(v[c][a]);
+          __hip_atomic_fetch_add(&acc[c * M + lc[a]], double(v[c][a]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i < nm; i += kW) {
+      const uint32_t raw = sId[i];
+      if (raw & kFixedBitB) continue;  // set above by the writer entry
+      const int64_t gg = raw & kIdMaskOwnB;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (done[c]) continue;
+        const T vv = T(acc[c * M + i]);
+        if (raw & kSharedBitB)
+          unsafeAtomicAdd(&q[gg * R + c], vv);
+        else
+          q[gg * R + c] = vv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int R, bool MIXED, bool PAR>
 __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ probs, int nprob,
                                                     const int *__restrict__ wg_prob, double tol2,
@@ -409,8 +558,10 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
   const BProb P = load_problem(probs + wg_prob[blockIdx.x]);
   const int me = int(blockIdx.x) - P.wg0;
   const int nwg = P.nwg;
-  double *acc = reinterpret_cast<double *>(smem_raw);                        // [R][max_nodes]
-  uint32_t *sId = reinterpret_cast<uint32_t *>(acc + R * P.max_nodes);       // [max_nodes]
+  using TP = typename std::conditional<MIXED, float, double>::type;  // precision of p, q
+  double *acc = reinterpret_cast<double *>(smem_raw);                  // [R][max_nodes]
+  TP *sP = reinterpret_cast<TP *>(acc + R * P.max_nodes);              // [R][max_nodes]
+  uint32_t *sId = reinterpret_cast<uint32_t *>(sP + R * P.max_nodes);  // [max_nodes]
   auto part = [&](int slot, int r) { return P.part + (int64_t(slot) * R + r) * nwg; };
   // node range of this wave for the vector phases
   const int64_t chunk = (P.nn + nwg - 1) / nwg;
@@ -418,54 +569,49 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
   const int64_t rchunk = (P.n_reset + nwg - 1) / nwg;
   const int64_t j0 = min(P.n_reset, int64_t(me) * rchunk), j1 = min(P.n_reset, j0 + rchunk);
 
-  // ---- init: x = 0, r = b, p = w b, q reset; partials rho_0, b.b, Dirichlet p^2
+  // ---- init: x = 0, r = b, both direction buffers 0 (nodes in no tile keep p = 0),
+  // q = 0 on shared nodes; partials rho_0 = b^T D^-1 b, b.b
   {
-    double v_rho[R], v_bb[R], v_mp[R];
+    double v_rho[R], v_bb[R];
 #pragma unroll
-    for (int c = 0; c < R; ++c) v_rho[c] = v_bb[c] = v_mp[c] = 0.0;
+    for (int c = 0; c < R; ++c) v_rho[c] = v_bb[c] = 0.0;
     for (int64_t i = i0 + lane; i < i1; i += kW) {
       const double wi = P.w[i];
-      const bool fx = P.mask && P.mask[i];
 #pragma unroll
       for (int c = 0; c < R; ++c) {
         const double bi = P.b[i * R + c];
-        double zi = wi * bi;
         P.x[i * R + c] = 0.0;
         P.r[i * R + c] = bi;
         if constexpr (MIXED) {
-          const float zf = float(zi);
-          P.p32[i * R + c] = zf;
-          v_rho[c] += bi * zi;
-          zi = double(zf);
+          P.p32[0][i * R + c] = 0.0f;
+          P.p32[1][i * R + c] = 0.0f;
         } else {
-          P.p[i * R + c] = zi;
-          v_rho[c] += bi * zi;
+          P.p[0][i * R + c] = 0.0;
+          P.p[1][i * R + c] = 0.0;
         }
+        v_rho[c] += bi * (wi * bi);
         v_bb[c] += bi * bi;
-        if (fx) v_mp[c] += zi * zi;
       }
     }
     for (int64_t j = j0 + lane; j < j1; j += kW) {
       const int64_t g = P.reset[j];
-      const bool fx = P.mask && P.mask[g];
+      if (P.mask && P.mask[g]) continue;  // Dirichlet rows: set by the first update
 #pragma unroll
       for (int c = 0; c < R; ++c) {
-        const double qg = fx ? P.w[g] * P.b[g * R + c] : 0.0;
         if constexpr (MIXED) {
-          P.q32[g * R + c] = float(qg);
-          if (!fx) P.t[g * R + c] = 0.0;  // shared nodes of the refresh apply
+          P.q32[g * R + c] = 0.0f;
+          P.t[g * R + c] = 0.0;  // shared nodes of the refresh apply
         } else {
-          P.q[g * R + c] = qg;
+          P.q[g * R + c] = 0.0;
         }
       }
     }
 #pragma unroll
     for (int c = 0; c < R; ++c) {
-      const double a = wave_sum64(v_rho[c]), bq = wave_sum64(v_bb[c]), m = wave_sum64(v_mp[c]);
+      const double a = wave_sum64(v_rho[c]), bq = wave_sum64(v_bb[c]);
       if (lane == 0) {
         part(kRho0, c)[me] = a;
         part(kBB, c)[me] = bq;
-        part(kMp2, c)[me] = m;
       }
     }
   }
@@ -485,22 +631,38 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
   bool all_done = true;
 #pragma unroll
   for (int c = 0; c < R; ++c) all_done = all_done && done[c];
+  double beta[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) beta[c] = 0.0;
 
   for (int it = 1; it <= maxit && !all_done; ++it) {
-    // ---- P1: q = A p over this wave's tiles, element energies p_e^T A_e p_e
-    double energy[R];
+    // ---- P1: p = D^-1 r + beta p_old and q = A p over this wave's tiles, with the
+    // partials of p^T A p (element energies, Dirichlet p^2)
+    // this iteration's direction buffer and the previous one (selected, not
+    // indexed, so that the problem record stays in registers)
+    const bool odd = (it & 1) != 0;
+    double *const p64 = odd ? P.p[1] : P.p[0];
+    double *const p64_old = odd ? P.p[0] : P.p[1];
+    float *const p32 = odd ? P.p32[1] : P.p32[0];
+    float *const p32_old = odd ? P.p32[0] : P.p32[1];
+    double energy[R], v_mp[R];
 #pragma unroll
-    for (int c = 0; c < R; ++c) energy[c] = 0.0;
+    for (int c = 0; c < R; ++c) energy[c] = v_mp[c] = 0.0;
     if constexpr (MIXED)
-      apply_phase<float, R, true, PAR>(P, me, nwg, lane, acc, sId, P.xyz32, P.coef32, P.p32, P.q32,
-                                  done, energy);
+      update_apply_phase<float, R, PAR>(P, me, nwg, lane, acc, sId, sP, P.xyz32, P.coef32,
+                                        p32_old, p32, P.q32, done, beta, it == 1,
+                                        energy, v_mp);
     else
-      apply_phase<double, R, true, PAR>(P, me, nwg, lane, acc, sId, P.xyz, P.coef_t, P.p, P.q, done,
-                                   energy);
+      update_apply_phase<double, R, PAR>(P, me, nwg, lane, acc, sId, sP, P.xyz, P.coef_t,
+                                         p64_old, p64, P.q, done, beta, it == 1, energy,
+                                         v_mp);
 #pragma unroll
     for (int c = 0; c < R; ++c) {
-      const double e = wave_sum64(energy[c]);
-      if (lane == 0) part(kEnergy, c)[me] = e;
+      const double e = wave_sum64(energy[c]), m = wave_sum64(v_mp[c]);
+      if (lane == 0) {
+        part(kEnergy, c)[me] = e;
+        part(kMp2, c)[me] = m;
+      }
     }
     double alpha[R], en[R], mp[R];
     if (!problem_sync<R>(P, unsigned(me), unsigned(nwg), error, kEnergy, kMp2, en, mp)) return;
@@ -536,10 +698,10 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
             const int64_t o = i * R + c;
             const bool ld = in && !done[c];
             if constexpr (MIXED) {
-              po[u][c] = ld ? double(P.p32[o]) : 0.0;
+              po[u][c] = ld ? double(p32[o]) : 0.0;
               qo[u][c] = ld ? double(P.q32[o]) : 0.0;
             } else {
-              po[u][c] = ld ? P.p[o] : 0.0;
+              po[u][c] = ld ? p64[o] : 0.0;
               qo[u][c] = ld ? P.q[o] : 0.0;
             }
             xo[u][c] = ld ? P.x[o] : 0.0;
@@ -578,10 +740,10 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
         }
       }
     }
-    double beta[R], rho_n[R], rr_n[R];
+    double rho_n[R], rr_n[R];
     if (!problem_sync<R>(P, unsigned(me), unsigned(nwg), error, kRho, kRR, rho_n, rr_n)) return;
 
-    // ---- P3: convergence, beta, p; q on Dirichlet nodes
+    // ---- convergence and beta (the direction update runs with the next apply)
     bool refresh[R];
     bool any_refresh = false;
 #pragma unroll
@@ -685,63 +847,6 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
 #pragma unroll
     for (int c = 0; c < R; ++c) all_done = all_done && done[c];
     if (all_done) break;
-    {
-      double v_mp[R];
-#pragma unroll
-      for (int c = 0; c < R; ++c) v_mp[c] = 0.0;
-      for (int64_t ib = i0 + lane; ib < i1; ib += kU * kW) {
-        double wv[kU], ro[kU][R], po[kU][R];
-        bool fx[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int64_t i = ib + u * kW;
-          const bool in = i < i1;
-          wv[u] = in ? P.w[i] : 0.0;
-          fx[u] = in && P.mask && P.mask[i];
-#pragma unroll
-          for (int c = 0; c < R; ++c) {
-            const int64_t o = i * R + c;
-            const bool ld = in && !done[c];
-            ro[u][c] = ld ? P.r[o] : 0.0;
-            if constexpr (MIXED)
-              po[u][c] = ld ? double(P.p32[o]) : 0.0;
-            else
-              po[u][c] = ld ? P.p[o] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int64_t i = ib + u * kW;
-          if (i >= i1) continue;
-#pragma unroll
-          for (int c = 0; c < R; ++c) {
-            if (done[c]) continue;
-            const int64_t o = i * R + c;
-            if constexpr (MIXED) {
-              const float pn = float(wv[u] * ro[u][c] + beta[c] * po[u][c]);
-              P.p32[o] = pn;
-              if (fx[u]) {
-                P.q32[o] = pn;  // Dirichlet rows of A p: the entry itself
-                v_mp[c] += double(pn) * double(pn);
-              }
-            } else {
-              const double pn = wv[u] * ro[u][c] + beta[c] * po[u][c];
-              P.p[o] = pn;
-              if (fx[u]) {
-                P.q[o] = pn;  // Dirichlet rows of A p: the entry itself
-                v_mp[c] += pn * pn;
-              }
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        const double m = wave_sum64(v_mp[c]);
-        if (lane == 0) part(kMp2, c)[me] = m;
-      }
-    }
-    if (!problem_barrier<R>(P, unsigned(me), unsigned(nwg), error)) return;
   }
   if (me == 0 && lane == 0) {
 #pragma unroll
@@ -774,6 +879,27 @@ __global__ void k_invert(int64_t n, double *__restrict__ d) {
 __global__ void k_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = float(src[i]);
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t *__restrict__ a, int32_t v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// first[g] = the smallest entry index of node g over the tile node lists
+__global__ void k_first_entry(int64_t nent, const uint32_t *__restrict__ nodes,
+                              int32_t *__restrict__ first) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < nent) atomicMin(&first[nodes[e] & kIdMaskB], int32_t(e));
+}
+
+// the node lists with the writer bit set on each node's first entry
+__global__ void k_mark_writers(int64_t nent, const uint32_t *__restrict__ nodes,
+                               const int32_t *__restrict__ first, uint32_t *__restrict__ onodes) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nent) return;
+  const uint32_t raw = nodes[e];
+  onodes[e] = raw | (first[raw & kIdMaskB] == int32_t(e) ? kOwnBitB : 0u);
 }
 
 template <int R, bool MIXED, bool PAR>
@@ -853,7 +979,11 @@ int batched_impl(const char *name, bool mixed, int nprob, q1_op *const *ops, int
     total_elems += o->n_elems;
     max_nodes = std::max(max_nodes, o->tiles.max_nodes);
   }
-  const size_t lds = size_t(max_nodes) * (size_t(nrhs) * sizeof(double) + sizeof(uint32_t));
+  // LDS per wave: FP64 accumulators, the staged directions (FP32 in the mixed form)
+  // and the node words
+  const size_t lds = size_t(max_nodes) * (size_t(nrhs) * sizeof(double) +
+                                          size_t(nrhs) * (mixed ? sizeof(float) : sizeof(double)) +
+                                          sizeof(uint32_t));
   bool par = true;  // every tile of every problem a parallelepiped tile
   for (int p = 0; p < nprob; ++p) par = par && reinterpret_cast<const Op *>(ops[p])->tiles.all_affine;
   const int cap = mixed ? (par ? coresident_for<true, true>(nrhs, lds)
@@ -923,18 +1053,35 @@ int batched_impl(const char *name, bool mixed, int nprob, q1_op *const *ops, int
     B.reset = tm.reset;
     B.n_reset = tm.n_reset;
     B.mask = o.mask;
+    Q1_CHECK(n < int64_t(kIdMaskOwnB), Q1_EUNSUPPORTED, "%s: operator %d has %lld nodes (at most %u)",
+             name, p, (long long)n, kIdMaskOwnB);
+    // the node lists with the writer bit on each node's first entry (first tile in order)
+    {
+      const int64_t nent = tm.n_entries;
+      int32_t *first = nullptr;
+      uint32_t *onodes = nullptr;
+      if ((rc = dalloc(reinterpret_cast<void **>(&first), size_t(n) * sizeof(int32_t))) ||
+          (rc = dalloc(reinterpret_cast<void **>(&onodes), size_t(nent) * sizeof(uint32_t))))
+        return rc;
+      hipLaunchKernelGGL(k_fill_i32, grid(n), dim3(256), 0, s, n, first, INT32_MAX);
+      hipLaunchKernelGGL(k_first_entry, grid(nent), dim3(256), 0, s, nent, tm.nodes, first);
+      hipLaunchKernelGGL(k_mark_writers, grid(nent), dim3(256), 0, s, nent, tm.nodes, first,
+                         onodes);
+      B.onodes = onodes;
+    }
     const size_t nv = size_t(n) * nrhs;
-    double *vec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    for (int v = 0; v < 5; ++v) {
+    double *vec[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int v = 0; v < 6; ++v) {
       if (mixed && v >= 3) continue;  // p, q are FP32 in the mixed form
       if ((rc = dalloc(reinterpret_cast<void **>(&vec[v]), nv * sizeof(double)))) return rc;
     }
-    B.b = vec[0]; B.x = vec[1]; B.r = vec[2]; B.p = vec[3]; B.q = vec[4];
+    B.b = vec[0]; B.x = vec[1]; B.r = vec[2]; B.q = vec[3]; B.p[0] = vec[4]; B.p[1] = vec[5];
     if (mixed) {
       // FP32 copies of the geometry and of the lane-ordered coefficients: the FP32 operator
       float *xyz32 = nullptr, *coef32 = nullptr;
       const int64_t ncoef = tm.n_steps * kW;
-      if ((rc = dalloc(reinterpret_cast<void **>(&B.p32), nv * sizeof(float))) ||
+      if ((rc = dalloc(reinterpret_cast<void **>(&B.p32[0]), nv * sizeof(float))) ||
+          (rc = dalloc(reinterpret_cast<void **>(&B.p32[1]), nv * sizeof(float))) ||
           (rc = dalloc(reinterpret_cast<void **>(&B.q32), nv * sizeof(float))) ||
           (rc = dalloc(reinterpret_cast<void **>(&B.t), nv * sizeof(double))) ||
           (rc = dalloc(reinterpret_cast<void **>(&xyz32), size_t(3 * n) * sizeof(float))) ||

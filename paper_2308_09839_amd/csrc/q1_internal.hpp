@@ -37,6 +37,7 @@ struct TileMap {
   int max_nodes = 0;              // LDS accumulator entries per tile
   int32_t *node_ptr = nullptr;    // [n_tiles+1] node list of each tile
   uint32_t *nodes = nullptr;      // global node ids | shared bit 31 | Dirichlet bit 30
+  int64_t n_entries = 0;          // entries of nodes (node_ptr[n_tiles])
   int32_t *tile_step = nullptr;   // [n_tiles+1] step range of each tile
   uint16_t *lconn = nullptr;      // [n_steps*64][8] corner indices into the tile list (0xffff: empty)
   void *coef_t = nullptr;         // cell coefficients in lane order [ncoef][n_steps*64]

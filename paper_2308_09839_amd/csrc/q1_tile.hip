@@ -668,6 +668,7 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   tm.n_steps = n_slots / kLanes;
   tm.max_nodes = H.max_nodes;
   tm.n_reset = int64_t(H.reset.size());
+  tm.n_entries = int64_t(H.nodes.size());
   tm.lds_atomic = H.corner_collision;
   tm.all_affine = std::all_of(H.tile_affine.begin(), H.tile_affine.end(),
                               [](uint8_t a) { return a != 0; });
