@@ -312,19 +312,18 @@ __device__ __forceinline__ bool problem_barrier(const BProb &P, unsigned me, uns
   return problem_sync<R>(P, me, nwg, error, -1, -1, a, b);
 }
 
-// q = A src over this wave's tiles (src, dst [nn][R] of type T; LDS accumulation in
-// FP64), and with ENERGY the element energies src_e^T A_e src_e.  The R
-// right-hand sides are the components of one element product, so the geometry
+// dst = A src over this wave's tiles (src, dst [nn][R] of type T; LDS accumulation
+// in FP64), used by the FP64 refresh of the mixed form.  The R right-hand sides are the components of one element product, so the geometry
 // is evaluated once per element; PAR: every tile of every problem is a
 // parallelepiped tile (flagged at set-up), so only corners 0, 1, 2, 4 are read
 // and the closed-form parallelepiped action is used.  Dirichlet corners read
 // zero; Dirichlet and shared nodes of dst are set by the caller; right-hand
 // sides marked skip are neither read nor written.
-template <typename T, int R, bool ENERGY, bool PAR>
+template <typename T, int R, bool PAR>
 __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int lane,
                                             double *acc, uint32_t *sId, const T *xyz,
                                             const T *coef_t, const T *src, T *dst,
-                                            const bool (&skip)[R], double (&energy)[R]) {
+                                            const bool (&skip)[R]) {
   for (int t = me; t < P.n_tiles; t += nwg) {
     const int n0 = P.node_ptr[t], nm = P.node_ptr[t + 1] - n0;
     const int s0 = P.tile_step[t], s1 = P.tile_step[t + 1];
@@ -392,7 +391,6 @@ __device__ __forceinline__ void apply_phase(const BProb &P, int me, int nwg, int
         if (skip[c]) continue;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-          if constexpr (ENERGY) energy[c] += double(u[c][a]) * double(v[c][a]);
           __hip_atomic_fetch_add(&acc[c * P.max_nodes + lc[a]], double(v[c][a]),
                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
@@ -782,11 +780,9 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
       if (any_refresh) {
         // R1: t = A64 x for the refreshed right-hand sides (FP64 geometry and coefficients)
         bool skip[R];
-        double unused[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) skip[c] = !refresh[c];
-        apply_phase<double, R, false, PAR>(P, me, nwg, lane, acc, sId, P.xyz, P.coef_t, P.x, P.t,
-                                      skip, unused);
+        apply_phase<double, R, PAR>(P, me, nwg, lane, acc, sId, P.xyz, P.coef_t, P.x, P.t, skip);
         if (!problem_barrier<R>(P, unsigned(me), unsigned(nwg), error)) return;
         // R2: r = b - A64 x (Dirichlet rows are the identity); partials rho', r.r
         double v_rho[R], v_rr[R];
