@@ -371,8 +371,9 @@ __global__ __launch_bounds__(256) void k_apply_block(
 // nodes, otherwise the sum of the node's halo slots in tile order (slots j and
 // n + j, then the extra slots of edge and corner nodes), so every entry of y
 // is written exactly once.  Each thread takes kHaloNpt nodes (a block's nodes
-// are contiguous) and issues all their loads before summing.
-constexpr int kHaloNpt = 4;
+// are contiguous) and issues all their loads before summing; two per thread
+// measured faster than four (more waves in flight for the one memory round).
+constexpr int kHaloNpt = 2;
 template <typename T, int DPN>
 __global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__restrict__ hnode,
                                                   const int32_t *__restrict__ hptr,
