@@ -248,14 +248,16 @@ int q1_pcg_fused(q1_op *op, int pc, const double *b_d, double *x_d, double rtol,
 int q1_ir_solve(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
                 double inner_rtol, int max_outer, int max_inner, q1_stats *st, void *stream);
 
-/* Mixed-precision Jacobi-PCG with reliable updates: the recurrences use the
- * FP32 operator, FP32 vectors and FP64 dots; x (FP64) accumulates the FP32
- * corrections.  Each time the recurrence residual has fallen by the factor
- * delta (e.g. 0.1) since the last refresh, the correction is added to x in
- * FP64, the true residual b - A64 x is recomputed with the FP64 operator and
- * rounded into the recurrence, and the search direction is kept.  Stops when
- * the FP64 true residual satisfies ||r|| <= rtol ||b||.  st->iters counts
- * Krylov iterations, st->outer_iters the refreshes.  b_d, x_d: FP64. */
+/* Mixed-precision Jacobi-PCG with reliable updates: the search directions p
+ * and q = A p are FP32 (q from the FP32 operator), while x, the residual r,
+ * the inverse diagonal and every dot product are FP64.  Each time the
+ * recurrence residual has fallen by the factor delta (0 < delta < 1, e.g. 0.1)
+ * since the last refresh, or below rtol/sqrt(2) relative to ||b||, the true
+ * residual r = b - A64 x is recomputed with the FP64 operator; convergence is
+ * decided on it, and otherwise the recurrences continue from it with the
+ * search direction kept.  Stops when the FP64 true residual satisfies
+ * ||r|| <= rtol ||b||.  st->iters counts Krylov iterations, st->outer_iters
+ * the refreshes.  b_d, x_d: FP64.  Workspace allocated and freed by the call. */
 int q1_mpcg(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rtol,
             double delta, int maxit, q1_stats *st, void *stream);
 

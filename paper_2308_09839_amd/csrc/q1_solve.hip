@@ -136,10 +136,11 @@ __global__ __launch_bounds__(kRT) void k_dot(int64_t n, const T *__restrict__ a,
 
 // alpha = rho_k / p.q; x += alpha p; r -= alpha q; partials rho_{k+1}, r.r.
 // FLEX (flexible PCG): keeps r_k in r_old and leaves rho_{k+1} to the
-// preconditioner step.
-template <typename T, bool FLEX>
+// preconditioner step.  TP, the type of p and q, is float in the mixed-precision
+// solver (FP32 operator), whose x, r and w stay in double.
+template <typename T, bool FLEX, typename TP = T>
 __global__ __launch_bounds__(kRT) void k_pcg_update(
-    int64_t n, const T *__restrict__ p, const T *__restrict__ q, const T *__restrict__ w,
+    int64_t n, const TP *__restrict__ p, const TP *__restrict__ q, const T *__restrict__ w,
     T *__restrict__ x, T *__restrict__ r, T *__restrict__ r_old,
     const double *__restrict__ part_pq, const double *__restrict__ part_rho_k,
     double *__restrict__ part_rho_k1, double *__restrict__ part_rr, Status *__restrict__ st) {
@@ -174,11 +175,12 @@ __global__ __launch_bounds__(kRT) void k_pcg_update(
 }
 
 // Convergence test after iteration `it`; beta = rho_{k+1} / rho_k;
-// p = z + beta p with z = w r (PCG) or the stored z (flexible PCG).
-template <typename T>
+// p = z + beta p with z = w r (PCG) or the stored z (flexible PCG); p of type TP
+// (rounded to it).
+template <typename T, typename TP = T>
 __global__ __launch_bounds__(kRT) void k_pcg_direction(
     int64_t n, const T *__restrict__ r, const T *__restrict__ w, const T *__restrict__ z,
-    T *__restrict__ p, const double *__restrict__ part_num, const double *__restrict__ part_den,
+    TP *__restrict__ p, const double *__restrict__ part_num, const double *__restrict__ part_den,
     const double *__restrict__ part_rr, const double *__restrict__ part_bb, double tol2, int it,
     int maxit, Status *__restrict__ st) {
   if (st->done) return;
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(kRT) void k_pcg_direction(
     const Range rg = block_range(n);
     for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
       const T zi = z ? z[i] : T(w[i] * r[i]);
-      p[i] = T(double(zi) + beta * double(p[i]));
+      p[i] = TP(double(zi) + beta * double(p[i]));
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -269,27 +271,23 @@ __global__ void k_ir_update(int64_t n, const float *__restrict__ d,
   if (i < n) x[i] += sqrt(*nrm2) * double(d[i]);
 }
 
-// Reliable update of the mixed-precision CG: x64 += x32, x32 = 0
-__global__ void k_fold_correction(int64_t n, float *__restrict__ x32, double *__restrict__ x64) {
+// Mixed-precision PCG: p = (float) (w r) from the FP64 residual
+__global__ void k_direction_start(int64_t n, const double *__restrict__ w,
+                                  const double *__restrict__ r, float *__restrict__ p) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) {
-    x64[i] += double(x32[i]);
-    x32[i] = 0.0f;
-  }
+  if (i < n) p[i] = float(w[i] * r[i]);
 }
-// r32 = (float) r64 with partials of rho = r32.(w r32) and r32.r32
-__global__ __launch_bounds__(kRT) void k_refresh_residual(int64_t n, const double *__restrict__ r64,
-                                                          const float *__restrict__ w,
-                                                          float *__restrict__ r32,
-                                                          double *__restrict__ part_rho,
-                                                          double *__restrict__ part_rr) {
+// partials of rho = r.(w r) and of r.r
+__global__ __launch_bounds__(kRT) void k_rho_rr(int64_t n, const double *__restrict__ r,
+                                                const double *__restrict__ w,
+                                                double *__restrict__ part_rho,
+                                                double *__restrict__ part_rr) {
   const Range rg = block_range(n);
   double v[2] = {0.0, 0.0};
   for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
-    const float ri = float(r64[i]);
-    r32[i] = ri;
-    v[0] += double(ri) * double(w[i] * ri);
-    v[1] += double(ri) * double(ri);
+    const double ri = r[i];
+    v[0] += ri * (w[i] * ri);
+    v[1] += ri * ri;
   }
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -720,45 +718,42 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
   return status;
 }
 
-// Mixed-precision PCG with reliable updates.  The Krylov recurrences run on
-// the FP32 operator with FP32 vectors and FP64 dots; x is the FP64 sum of FP32
-// corrections.  Whenever the recurrence residual has fallen by delta since the
-// last refresh, the correction is folded into the FP64 x, the true residual
-// b - A64 x is recomputed in FP64 and rounded into the recurrence; the search
-// direction is kept, so the Krylov history survives the refresh.
+// Mixed-precision PCG with reliable updates.  The search directions p and
+// q = A p are FP32 and q comes from the FP32 operator; x, the residual r, the
+// inverse diagonal and every dot product stay FP64, so the recurrences lose
+// only what the FP32 apply and directions round away.  Whenever the recurrence
+// residual has fallen by delta since the last refresh (or below rtol / sqrt 2),
+// r = b - A64 x is recomputed with the FP64 operator and convergence is decided
+// on it; otherwise the recurrences continue from it with the search direction
+// kept (beta = rho(new r) / rho_{k-1}), so the Krylov history survives.
 int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double delta, int maxit,
            q1_stats *stats, hipStream_t s) {
   const int64_t n = A64.n_nodes * A64.dpn();
-  Work W;  // FP32 recurrences
-  int rc = alloc_work<float>(W, n, false);
+  Work W;  // FP64 residual and inverse diagonal, partials and status
+  int rc = alloc_work<double>(W, n, false);
   if (rc) return rc;
-  float *x32 = nullptr;
-  double *r64 = nullptr;
+  float *p = nullptr, *q = nullptr;  // FP32 directions
   struct Free {
-    float **a;
-    double **b;
+    float **a, **b;
     ~Free() {
       if (*a) (void)hipFree(*a);
       if (*b) (void)hipFree(*b);
     }
-  } fr{&x32, &r64};
-  Q1_HIP(hipMalloc(&x32, size_t(n) * sizeof(float)));
-  Q1_HIP(hipMalloc(&r64, size_t(n) * sizeof(double)));
+  } fr{&p, &q};
+  Q1_HIP(hipMalloc(&p, size_t(n) * sizeof(float)));
+  Q1_HIP(hipMalloc(&q, size_t(n) * sizeof(float)));
   const auto t0 = std::chrono::steady_clock::now();
-  if ((rc = setup_diag<float>(A32, W, Q1_PC_JACOBI, s))) return rc;
+  if ((rc = setup_diag<double>(A64, W, Q1_PC_JACOBI, s))) return rc;
   const int nb = nblocks_for(n);
   double *P = W.part;
   double *part_rho[2] = {P, P + kMaxRB};
   double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB;
-  float *r = static_cast<float *>(W.r), *p = static_cast<float *>(W.p),
-        *q = static_cast<float *>(W.q), *w = static_cast<float *>(W.w);
+  double *r = static_cast<double *>(W.r), *w = static_cast<double *>(W.w);
   Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
-  Q1_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
-  Q1_HIP(hipMemsetAsync(x32, 0, size_t(n) * sizeof(float), s));
-  hipLaunchKernelGGL((k_dot<double>), dim3(nb), dim3(kRT), 0, s, n, b, b, part_bb, nullptr);
-  hipLaunchKernelGGL(k_refresh_residual, dim3(nb), dim3(kRT), 0, s, n, b, w, r, part_rho[0],
-                     part_rr);
-  hipLaunchKernelGGL((k_jacobi<float>), grid1(n), dim3(256), 0, s, n, w, r, p);
+  // x = 0, r = b, partials of rho_0 = b.(w b) and b.b; p = (float) (w b)
+  hipLaunchKernelGGL((k_pcg_init<double>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r, nullptr,
+                     part_rho[0], part_bb, 0);
+  hipLaunchKernelGGL(k_direction_start, grid1(n), dim3(256), 0, s, n, w, r, p);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
   Q1_HIP(hipGetLastError());
   if ((rc = read_status(W, s))) return rc;
@@ -769,7 +764,7 @@ int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double del
     const double tol2 = rtol * rtol;
     status = Q1_ENOCONV;
     while (k < maxit) {
-      // inner recurrences until the residual fell by delta (or to the tolerance)
+      // recurrences until the residual fell by delta (or to the tolerance)
       const double thr = std::max(delta * delta * rr_ref, 0.5 * tol2 * bb);
       int batch = 1;
       bool stop = false;
@@ -778,12 +773,12 @@ int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double del
         for (int j = 0; j < m; ++j, ++k) {
           if ((rc = launch_apply(A32, p, q, s, &W.st->done))) return rc;
           hipLaunchKernelGGL((k_dot<float>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
-          hipLaunchKernelGGL((k_pcg_update<float, false>), dim3(nb), dim3(kRT), 0, s, n, p, q, w,
-                             x32, r, nullptr, part_pq, part_rho[k & 1], part_rho[(k + 1) & 1],
-                             part_rr, W.st);
-          hipLaunchKernelGGL((k_pcg_direction<float>), dim3(nb), dim3(kRT), 0, s, n, r, w,
-                             nullptr, p, part_rho[(k + 1) & 1], part_rho[k & 1], part_rr, part_bb,
-                             thr / bb, k + 1, maxit, W.st);
+          hipLaunchKernelGGL((k_pcg_update<double, false, float>), dim3(nb), dim3(kRT), 0, s, n,
+                             p, q, w, x, r, nullptr, part_pq, part_rho[k & 1],
+                             part_rho[(k + 1) & 1], part_rr, W.st);
+          hipLaunchKernelGGL((k_pcg_direction<double, float>), dim3(nb), dim3(kRT), 0, s, n, r,
+                             w, nullptr, p, part_rho[(k + 1) & 1], part_rho[k & 1], part_rr,
+                             part_bb, thr / bb, k + 1, maxit, W.st);
         }
         Q1_HIP(hipGetLastError());
         if ((rc = read_status(W, s))) return rc;
@@ -796,13 +791,11 @@ int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double del
       }
       // the loop ran k iterations; the last direction step was skipped if it stopped early
       k = W.hst->iter;
-      // reliable update: fold the correction, recompute the residual in FP64
-      hipLaunchKernelGGL(k_fold_correction, grid1(n), dim3(256), 0, s, n, x32, x);
-      if ((rc = launch_apply(A64, x, r64, s))) return rc;
-      hipLaunchKernelGGL((k_residual<double>), grid1(n), dim3(256), 0, s, n, b, r64);
-      hipLaunchKernelGGL((k_dot<double>), dim3(nb), dim3(kRT), 0, s, n, r64, r64,
-                         P + 6 * kMaxRB, nullptr);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, P + 6 * kMaxRB, nb, &W.st->aux);
+      // reliable update: r = b - A64 x, with the partials of rho(r) and r.r
+      if ((rc = launch_apply(A64, x, r, s))) return rc;
+      hipLaunchKernelGGL((k_residual<double>), grid1(n), dim3(256), 0, s, n, b, r);
+      hipLaunchKernelGGL(k_rho_rr, dim3(nb), dim3(kRT), 0, s, n, r, w, part_rho[k & 1], part_rr);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rr, nb, &W.st->aux);
       Q1_HIP(hipGetLastError());
       if ((rc = read_status(W, s))) return rc;
       rr_true = W.hst->aux;
@@ -813,14 +806,11 @@ int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double del
       }
       if (k >= maxit) break;
       rr_ref = rr_true;
-      // continue the recurrences from the true residual, keeping p
-      hipLaunchKernelGGL(k_refresh_residual, dim3(nb), dim3(kRT), 0, s, n, r64, w, r,
-                         part_rho[k & 1], part_rr);
+      // continue from the true residual, keeping p: beta = rho(new r) / rho_{k-1}
       hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(1), 0, s, W.st);
-      // beta = rho(new r) / rho_{k-1}; p = w r + beta p
-      hipLaunchKernelGGL((k_pcg_direction<float>), dim3(nb), dim3(kRT), 0, s, n, r, w, nullptr, p,
-                         part_rho[k & 1], part_rho[(k + 1) & 1], part_rr, part_bb, 0.0, k,
-                         maxit + 1, W.st);
+      hipLaunchKernelGGL((k_pcg_direction<double, float>), dim3(nb), dim3(kRT), 0, s, n, r, w,
+                         nullptr, p, part_rho[k & 1], part_rho[(k + 1) & 1], part_rr, part_bb,
+                         0.0, k, maxit + 1, W.st);
       Q1_HIP(hipGetLastError());
     }
   }
