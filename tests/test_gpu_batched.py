@@ -100,6 +100,43 @@ def test_batched_full_workload(q1, orc):
             assert orc.true_rel_res(A, xs[i][c], bs[i][c]) <= 1e-8 * (1 + 1e-3)
 
 
+def laplace_jittered_box(n, seed):
+    pr = laplace_box(n, seed)
+    pr["xyz"], _ = si.box_mesh(n, n, n, 1.0, 0.1, seed)
+    return pr
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_general_hexahedra(q1, orc, mixed):
+    """A jittered problem in the batch makes the kernel take its instance for
+    general hexahedra (the parallelepiped instance needs every tile of every
+    problem to be a parallelepiped tile): three right-hand sides per problem to
+    1e-8 under the oracle's operator, and in FP64 the first iterates equal the
+    oracle's."""
+    print(f"\n[batched general hexahedra] mixed={mixed}", flush=True)
+    probs = [laplace_box(6, 700), laplace_jittered_box(7, 701), laplace_jittered_box(5, 702)]
+    bs = [rhs_set(pr, 710 + i, 3) for i, pr in enumerate(probs)]
+    As = [orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"]) for pr in probs]
+    xs, st = (run_mixed if mixed else run)(q1, probs, bs, 1e-8, 5000)
+    for i, A in enumerate(As):
+        for c in range(3):
+            s = st[i * 3 + c]
+            assert s["status"] == 0, (i, c, s)
+            assert orc.true_rel_res(A, xs[i][c], bs[i][c]) <= 1e-8 * (1 + 1e-3)
+            ref = orc.pcg(A, bs[i][c], rtol=1e-8)
+            slack = 0.1 if mixed else 0.02
+            assert abs(s["iters"] - ref.iters) <= slack * ref.iters + 2, (s["iters"], ref.iters)
+    if mixed:
+        return
+    for k in (1, 4):
+        xs, st = run(q1, probs, bs, 0.0, k)
+        for i, A in enumerate(As):
+            for c in range(3):
+                ref = orc.pcg(A, bs[i][c], rtol=0.0, maxit=k)
+                assert st[i * 3 + c]["status"] == -4 and st[i * 3 + c]["iters"] == k
+                assert np.linalg.norm(xs[i][c] - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
 # ---- mixed precision: FP32 applies and directions, FP64 x, r, dots and refreshes
 
 def run_mixed(q1, probs, bs, rtol, maxit, delta=0.1):
