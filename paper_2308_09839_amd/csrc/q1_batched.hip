@@ -635,9 +635,9 @@ __global__ __launch_bounds__(kW) void k_batched_pcg(const BProb *__restrict__ pr
 
   for (int it = 1; it <= maxit && !all_done; ++it) {
     // ---- P1: p = D^-1 r + beta p_old and q = A p over this wave's tiles, with the
-    // partials of p^T A p (element energies, Dirichlet p^2)
-    // this iteration's direction buffer and the previous one (selected, not
-    // indexed, so that the problem record stays in registers)
+    // partials of p^T A p (element energies, Dirichlet p^2).  The direction
+    // buffers of this iteration and the previous one are selected, not indexed,
+    // so that the problem record stays in registers.
     const bool odd = (it & 1) != 0;
     double *const p64 = odd ? P.p[1] : P.p[0];
     double *const p64_old = odd ? P.p[0] : P.p[1];
