@@ -986,8 +986,8 @@ int batched_impl(const char *name, bool mixed, int nprob, q1_op *const *ops, int
                                : coresident_for<true, false>(nrhs, lds))
                         : (par ? coresident_for<false, true>(nrhs, lds)
                                : coresident_for<false, false>(nrhs, lds));
-  Q1_CHECK(cap >= nprob, Q1_EUNSUPPORTED, "%s: %d problems need %d co-resident waves", name,
-           nprob, nprob);
+  Q1_CHECK(cap >= nprob, Q1_EUNSUPPORTED,
+           "%s: %d problems need one co-resident wave each, but only %d fit", name, nprob, cap);
   // waves per problem in proportion to its expected work, at least one each:
   // elements times iterations, and Jacobi-PCG iterations on an n^3 grid grow
   // like n, so the weight is n_elems^(4/3)
