@@ -64,13 +64,20 @@ def time_applies(op, x, y, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def time_cold(op, x, y, reps):
-    """Each apply after writing a 1 GiB buffer (evicts L2 and the MALL)."""
+def time_cold(op, x, y, reps, mode="write"):
+    """Each apply after touching a 1 GiB buffer, which evicts the operator's data from L2 and
+    the MALL (256 MB): mode "write" fills it (the apply then also competes with the write-back
+    of the dirty lines), mode "read" sums it (clean lines; the apply reads from HBM)."""
     import torch
-    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     ts = []
     for i in range(reps):
-        flush.fill_(float(i))
+        if mode == "write":
+            flush.fill_(float(i))
+        else:
+            flush.sum()
+        torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
@@ -465,6 +472,11 @@ def main() -> int:
         ms_cold = time_cold(op, x, y, 30)
         extras["fp64_cold_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)
         extras["fp64_cold_ms"] = round(ms_cold, 5)
+        ms_cold_r = time_cold(op, x, y, 30, "read")
+        extras["fp64_cold_read_gdofs"] = round(ndof / (ms_cold_r * 1e-3) / 1e9, 3)
+        extras["fp64_cold_read_ms"] = round(ms_cold_r, 5)
+        extras["fp64_cold_read_hbm_frac"] = round(alg_bytes / (ms_cold_r * 1e-3) / 1e9 /
+                                                  HBM_PEAK_GBS, 4)
         del op, x, y
         log("[bench] FP32 applies")
         op32, x32, y32 = make(pr, 1)
