@@ -472,6 +472,7 @@ def main() -> int:
         ms_cold = time_cold(op, x, y, 30)
         extras["fp64_cold_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)
         extras["fp64_cold_ms"] = round(ms_cold, 5)
+        extras["fp64_cold_hbm_frac"] = round(alg_bytes / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         ms_cold_r = time_cold(op, x, y, 30, "read")
         extras["fp64_cold_read_gdofs"] = round(ndof / (ms_cold_r * 1e-3) / 1e9, 3)
         extras["fp64_cold_read_ms"] = round(ms_cold_r, 5)
@@ -532,7 +533,12 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": MEASURED_TRAFFIC.get((info["variant"], 0, n)),
-                     "algorithmic_bytes_per_apply": alg_bytes},
+                     "algorithmic_bytes_per_apply": alg_bytes,
+                     # achieved/frac: back-to-back applies (the timed steps), whose data
+                     # partly stays in the 256 MB MALL; cold: one apply after evicting L2
+                     # and the MALL by writing (or reading) a 1 GiB buffer
+                     "cold_frac": extras.get("fp64_cold_hbm_frac"),
+                     "cold_frac_read_flush": extras.get("fp64_cold_read_hbm_frac")},
         "cpu_baseline": cpu,
         "extra": extras,
     }
