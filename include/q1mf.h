@@ -266,10 +266,13 @@ int q1_mpcg(q1_op *op64, q1_op *op32, const double *b_d, double *x_d, double rto
  * right-hand sides (1..4), solved by ONE cooperative kernel launch.  b_d and
  * x_d hold nprob*nrhs device vectors (problem-major, FP64); st, if not NULL,
  * nprob*nrhs records.  Each problem gets a share of the co-resident
- * wavefronts in proportion to its elements and synchronises them with its own
- * barrier; p^T A p comes from element energies inside the apply.  Returns the
- * worst status over all solves; Q1_EUNSUPPORTED for other operators or when
- * more problems than co-resident wavefronts are given.  Synchronises `stream`. */
+ * wavefronts in proportion to its expected work (elements^(4/3)) and
+ * synchronises them with its own barrier, two per iteration: the direction
+ * update runs inside the apply and p^T A p comes from element energies.
+ * Workspace (per problem: nrhs * 6 FP64 vectors, tile bookkeeping) is
+ * allocated and freed by the call.  Returns the worst status over all solves;
+ * Q1_EUNSUPPORTED for other operators or when more problems than co-resident
+ * wavefronts are given.  Synchronises `stream`. */
 int q1_batched_pcg(int nprob, q1_op *const *ops, int nrhs, const double *const *b_d,
                    double *const *x_d, double rtol, int maxit, q1_stats *st, void *stream);
 
@@ -282,9 +285,10 @@ int q1_batched_pcg(int nprob, q1_op *const *ops, int nrhs, const double *const *
  * at maxit, the kernel recomputes r = b - A x with the FP64 operator and
  * decides convergence on that true residual; otherwise the recurrences
  * continue from it with p kept.  st[k].outer_iters counts the refreshes and
- * st[k].rel_res is the true relative residual of the last refresh.  Extra
- * device memory per problem: FP32 copies of the geometry and coefficients
- * and nrhs*(2 FP32 + 1 FP64) vectors, allocated and freed by the call.
+ * st[k].rel_res is the true relative residual of the last refresh.  Device
+ * memory per problem: FP32 copies of the geometry and coefficients, and per
+ * right-hand side three FP32 vectors (two direction buffers, q) and four FP64
+ * ones (b, x, r, the refresh apply's output), allocated and freed by the call.
  * Returns Q1_EINVAL for delta outside (0, 1); otherwise as q1_batched_pcg. */
 int q1_batched_mpcg(int nprob, q1_op *const *ops, int nrhs, const double *const *b_d,
                     double *const *x_d, double rtol, double delta, int maxit, q1_stats *st,
