@@ -65,9 +65,10 @@ def time_applies(op, x, y, steps, warmup):
 
 
 def time_cold(op, x, y, reps, mode="write"):
-    """Each apply after touching a 1 GiB buffer, which evicts the operator's data from L2 and
-    the MALL (256 MB): mode "write" fills it (the apply then also competes with the write-back
-    of the dirty lines), mode "read" sums it (clean lines; the apply reads from HBM)."""
+    """Median of `reps` applies, each timed alone after touching a 1 GiB buffer, which evicts
+    the operator's data from L2 and the MALL (256 MB): mode "write" fills it (the apply then
+    also competes with the write-back of the dirty lines), mode "read" sums it (clean lines;
+    the apply reads from HBM)."""
     import torch
     flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
@@ -469,11 +470,11 @@ def main() -> int:
                 extras["fp64_pa_alg_bytes"] = bv
             del opv
         log("[bench] cold (flushed) applies")
-        ms_cold = time_cold(op, x, y, 30)
+        ms_cold = time_cold(op, x, y, 100)
         extras["fp64_cold_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)
         extras["fp64_cold_ms"] = round(ms_cold, 5)
         extras["fp64_cold_hbm_frac"] = round(alg_bytes / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        ms_cold_r = time_cold(op, x, y, 30, "read")
+        ms_cold_r = time_cold(op, x, y, 100, "read")
         extras["fp64_cold_read_gdofs"] = round(ndof / (ms_cold_r * 1e-3) / 1e9, 3)
         extras["fp64_cold_read_ms"] = round(ms_cold_r, 5)
         extras["fp64_cold_read_hbm_frac"] = round(alg_bytes / (ms_cold_r * 1e-3) / 1e9 /
