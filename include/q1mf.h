@@ -46,7 +46,7 @@ extern "C" {
 #define Q1_EHIP (-3)         /* HIP runtime error; text in q1_last_error() */
 #define Q1_ENOCONV (-4)      /* iteration limit reached; x holds the last iterate */
 #define Q1_EBREAKDOWN (-5)   /* p^T A p <= 0, non-finite scalar, bad element */
-#define Q1_EUNSUPPORTED (-6) /* valid request that this build does not support */
+#define Q1_EUNSUPPORTED (-6) /* valid request that the library does not support */
 
 /* Text of the last error raised on the calling thread ("" if none). */
 const char *q1_last_error(void);
