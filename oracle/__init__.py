@@ -70,7 +70,11 @@ def lib():
         L.orc_fpcg.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p,
                                ctypes.c_double, ctypes.c_int, PRECOND_FN, ctypes.c_void_p,
                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
-                               ctypes.c_void_p]
+                               ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_fcg.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p,
+                              ctypes.c_double, ctypes.c_int, ctypes.c_int, PRECOND_FN,
+                              ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -225,11 +229,12 @@ def pcg(A: CSR, b: np.ndarray, rtol: float = 1e-8, maxit: int = 20000,
     return SolveResult(x, int(st), it.value, rr.value, hist[: it.value + 1].copy())
 
 
-def fpcg(A: CSR, b: np.ndarray, precond, rtol: float = 1e-8, maxit: int = 20000) -> SolveResult:
-    """Flexible PCG; ``precond(r) -> z`` is any Python callable on numpy arrays."""
-    b = np.ascontiguousarray(b, dtype=np.float64)
-    x = np.zeros(A.n)
+@dataclass
+class FlexResult(SolveResult):
+    iterates: np.ndarray | None = None  # [iters+1, n] when recorded
 
+
+def _precond_cb(precond):
     def _cb(_ctx, n, rp, zp):
         try:
             r = np.ctypeslib.as_array(rp, shape=(n,))
@@ -238,15 +243,43 @@ def fpcg(A: CSR, b: np.ndarray, precond, rtol: float = 1e-8, maxit: int = 20000)
             return 0 if np.all(np.isfinite(z)) else 1
         except Exception:  # a failing preconditioner is a breakdown
             return 1
+    return PRECOND_FN(_cb)
 
-    cb = PRECOND_FN(_cb)
+
+def _flex(which: str, A: CSR, b, precond, rtol: float, maxit: int, m: int,
+          record: bool) -> FlexResult:
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n)
+    cb = _precond_cb(precond)
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
     hist = np.zeros(maxit + 1)
-    st = lib().orc_fpcg(A.n, A.rowptr, A.col, A.val, b, x, float(rtol), int(maxit), cb, None,
-                        ctypes.byref(it), ctypes.byref(rr),
-                        hist.ctypes.data_as(ctypes.c_void_p))
-    return SolveResult(x, int(st), it.value, rr.value, hist[: it.value + 1].copy())
+    xh = np.zeros((maxit + 1, A.n)) if record else None
+    xh_p = xh.ctypes.data_as(ctypes.c_void_p) if record else None
+    hp = hist.ctypes.data_as(ctypes.c_void_p)
+    if which == "fpcg":
+        st = lib().orc_fpcg(A.n, A.rowptr, A.col, A.val, b, x, float(rtol), int(maxit), cb, None,
+                            ctypes.byref(it), ctypes.byref(rr), hp, xh_p)
+    else:
+        st = lib().orc_fcg(A.n, A.rowptr, A.col, A.val, b, x, float(rtol), int(maxit), int(m),
+                           cb, None, ctypes.byref(it), ctypes.byref(rr), hp, xh_p)
+    k = it.value
+    return FlexResult(x, int(st), k, rr.value, hist[: k + 1].copy(),
+                      xh[: k + 1].copy() if record else None)
+
+
+def fpcg(A: CSR, b: np.ndarray, precond, rtol: float = 1e-8, maxit: int = 20000,
+         record: bool = False) -> FlexResult:
+    """Flexible PCG (Golub-Ye beta); ``precond(r) -> z`` is any Python callable
+    on numpy arrays, called once per iteration in order.  ``record`` keeps the
+    iterates x_0 .. x_k."""
+    return _flex("fpcg", A, b, precond, rtol, maxit, 1, record)
+
+
+def fcg(A: CSR, b: np.ndarray, precond, m: int, rtol: float = 1e-8, maxit: int = 20000,
+        record: bool = False) -> FlexResult:
+    """FCG(m): flexible CG with A-orthogonalisation against the last m directions."""
+    return _flex("fcg", A, b, precond, rtol, maxit, m, record)
 
 
 def true_rel_res(A: CSR, x: np.ndarray, b: np.ndarray) -> float:

@@ -406,7 +406,7 @@ done:
 
 int orc_fpcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
              const double *b, double *x, double rtol, int maxit, orc_precond_fn M, void *ctx,
-             int *iters, double *rel_res, double *res_hist) {
+             int *iters, double *rel_res, double *res_hist, double *x_hist) {
   double *r = (double *)malloc((size_t)n * sizeof(double));
   double *rold = (double *)malloc((size_t)n * sizeof(double));
   double *z = (double *)malloc((size_t)n * sizeof(double));
@@ -416,6 +416,7 @@ int orc_fpcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
     free(r); free(rold); free(z); free(p); free(q); return -2;
   }
   for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+  if (x_hist) memcpy(x_hist, x, (size_t)n * sizeof(double));
   const double bnorm = sqrt(dot(n, b, b));
   int status = -4, k = 0;
   double rnorm = bnorm;
@@ -434,6 +435,7 @@ int orc_fpcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double 
     ++k;
     rnorm = sqrt(dot(n, r, r));
     if (res_hist) res_hist[k] = rnorm;
+    if (x_hist) memcpy(x_hist + (size_t)k * (size_t)n, x, (size_t)n * sizeof(double));
     if (rnorm <= rtol * bnorm) { status = 0; break; }
     if (M(ctx, n, r, z)) { status = -5; break; }
     double num = 0.0;
@@ -446,5 +448,68 @@ done:
   if (iters) *iters = k;
   if (rel_res) *rel_res = bnorm > 0.0 ? rnorm / bnorm : 0.0;
   free(r); free(rold); free(z); free(p); free(q);
+  return status;
+}
+
+/* Flexible CG with truncated orthogonalisation, FCG(m) (Notay, SIAM J. Sci.
+ * Comput. 22, 2000).  Iteration k: z_k = M(r_k); the direction p_k is z_k
+ * minus its A-projections on the previous min(k, m) directions,
+ *   p_k = z_k - sum_j (z_k^T A p_j / p_j^T A p_j) p_j,
+ * then alpha_k = p_k^T r_k / p_k^T A p_k, x += alpha_k p_k,
+ * r -= alpha_k A p_k.  The directions p_j and their products A p_j are
+ * kept, so no extra apply is needed. */
+int orc_fcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+            const double *b, double *x, double rtol, int maxit, int m, orc_precond_fn M,
+            void *ctx, int *iters, double *rel_res, double *res_hist, double *x_hist) {
+  if (m < 1) return -1;
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  double *z = (double *)malloc((size_t)n * sizeof(double));
+  double *P = (double *)malloc((size_t)m * (size_t)n * sizeof(double));
+  double *Q = (double *)malloc((size_t)m * (size_t)n * sizeof(double));
+  double *pAp = (double *)malloc((size_t)m * sizeof(double));
+  double *c = (double *)malloc((size_t)m * sizeof(double));
+  if (!r || !z || !P || !Q || !pAp || !c) {
+    free(r); free(z); free(P); free(Q); free(pAp); free(c); return -2;
+  }
+  for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+  if (x_hist) memcpy(x_hist, x, (size_t)n * sizeof(double));
+  const double bnorm = sqrt(dot(n, b, b));
+  int status = -4, k = 0;
+  double rnorm = bnorm;
+  if (res_hist) res_hist[0] = rnorm;
+  if (bnorm == 0.0) { status = 0; goto done; }
+  for (k = 0; k < maxit;) {
+    if (M(ctx, n, r, z)) { status = -5; break; }
+    /* slot of direction j is j mod m; the window holds directions
+     * k - nwin .. k - 1 */
+    const int nwin = k < m ? k : m;
+    for (int t = 0; t < nwin; ++t) {
+      const int j = k - nwin + t;
+      const double *qj = Q + (size_t)(j % m) * (size_t)n;
+      c[t] = dot(n, z, qj) / pAp[j % m];
+    }
+    double *pk = P + (size_t)(k % m) * (size_t)n;
+    double *qk = Q + (size_t)(k % m) * (size_t)n;
+    for (int64_t i = 0; i < n; ++i) {
+      double v = z[i];
+      for (int t = 0; t < nwin; ++t) v -= c[t] * P[(size_t)((k - nwin + t) % m) * (size_t)n + i];
+      pk[i] = v;
+    }
+    orc_spmv(n, rowptr, col, val, pk, qk);
+    const double pq = dot(n, pk, qk);
+    if (!(pq > 0.0) || !isfinite(pq)) { status = -5; break; }
+    pAp[k % m] = pq;
+    const double alpha = dot(n, pk, r) / pq;
+    for (int64_t i = 0; i < n; ++i) { x[i] += alpha * pk[i]; r[i] -= alpha * qk[i]; }
+    ++k;
+    rnorm = sqrt(dot(n, r, r));
+    if (res_hist) res_hist[k] = rnorm;
+    if (x_hist) memcpy(x_hist + (size_t)k * (size_t)n, x, (size_t)n * sizeof(double));
+    if (rnorm <= rtol * bnorm) { status = 0; break; }
+  }
+done:
+  if (iters) *iters = k;
+  if (rel_res) *rel_res = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  free(r); free(z); free(P); free(Q); free(pAp); free(c);
   return status;
 }

@@ -78,12 +78,23 @@ int orc_pcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *
             int *iters, double *rel_res, double *res_hist);
 
 /* Flexible PCG with a variable preconditioner z = M(r):
- * beta = z_{k+1}^T (r_{k+1} - r_k) / (r_k^T z_k).  Same stopping rule and
- * return codes as orc_pcg. */
+ * beta = z_{k+1}^T (r_{k+1} - r_k) / (r_k^T z_k) (Golub and Ye's inexact
+ * PCG).  Same stopping rule and return codes as orc_pcg.  x_hist, if not
+ * NULL, receives the iterates x_0 .. x_iters ([iters+1][n], maxit+1 rows
+ * must fit). */
 typedef int (*orc_precond_fn)(void *ctx, int64_t n, const double *r, double *z);
 int orc_fpcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
              const double *b, double *x, double rtol, int maxit, orc_precond_fn M, void *ctx,
-             int *iters, double *rel_res, double *res_hist);
+             int *iters, double *rel_res, double *res_hist, double *x_hist);
+
+/* Flexible CG with truncated orthogonalisation FCG(m) (Notay 2000): the new
+ * direction is z = M(r) made A-orthogonal to the previous min(k, m)
+ * directions, alpha = p^T r / p^T A p.  m >= 1; with m >= maxit every
+ * direction is A-orthogonalised against all earlier ones.  Same outputs and
+ * return codes as orc_fpcg (-1 for m < 1). */
+int orc_fcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+            const double *b, double *x, double rtol, int maxit, int m, orc_precond_fn M,
+            void *ctx, int *iters, double *rel_res, double *res_hist, double *x_hist);
 
 #ifdef __cplusplus
 }

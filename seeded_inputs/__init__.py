@@ -17,7 +17,8 @@ C library's host generators):
 
 Streams: 0 node jitter, 1 cell coefficient (k or E), 2 second cell field
 (Poisson ratio, or the per-cell factor of a layered field), 3 apply input x,
-4 right-hand side / body force, 5 batch problem sizes.
+4 right-hand side / body force, 5 batch problem sizes, 6 the factors of a
+preconditioner that changes from one call to the next (solver tests).
 
 Mesh numbering (the paper's Cartesian example grids, Section 4): node
 id = i + (nx+1)(j + (ny+1)k); element e = ex + nx(ey + ny ez); local node
@@ -41,6 +42,7 @@ STREAM_COEF2 = 2
 STREAM_X = 3
 STREAM_RHS = 4
 STREAM_BATCH = 5
+STREAM_PC = 6
 
 
 def splitmix64(z: np.ndarray) -> np.ndarray:
@@ -174,6 +176,13 @@ def batch_sizes(nprob: int, seed: int, lo: int = 16, hi: int = 64) -> np.ndarray
     """Edge sizes n_p ~ U{lo..hi} inclusive (stream 5)."""
     u = uniform(seed, STREAM_BATCH, np.arange(nprob, dtype=np.uint64))
     return (lo + np.floor(u * (hi - lo + 1))).astype(np.int64)
+
+
+def varying_factors(n: int, call: int, seed: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:
+    """Per-entry factors U(lo, hi) for the call-th use (from 0) of a
+    preconditioner that changes between calls: stream 6, counters call*n + i."""
+    idx = np.uint64(call) * np.uint64(n) + np.arange(n, dtype=np.uint64)
+    return lo + (hi - lo) * uniform(seed, STREAM_PC, idx)
 
 
 def dof_mask(mask_nodes: np.ndarray, dpn: int) -> np.ndarray:

@@ -80,3 +80,47 @@ def rigid_modes(xyz):
 def dpn_of(physics: int) -> int:
     """DOF per node of a physics kind (1 scalar Laplace, 2 vector Laplace, 3 elasticity)."""
     return 1 if physics == 1 else 3
+
+
+_HIP = None
+
+
+def hip_runtime():
+    """The HIP runtime already loaded in the process (by torch), through ctypes."""
+    global _HIP
+    if _HIP is None:
+        import ctypes
+        import torch  # noqa: F401  (loads libamdhip64 first)
+        L = ctypes.CDLL("libamdhip64.so.7")
+        L.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_int, ctypes.c_void_p]
+        L.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+        _HIP = L
+    return _HIP
+
+
+class HostPrecond:
+    """A preconditioner callback for the device flexible solvers whose z = f(r)
+    is computed on the host by a numpy callable: r is copied to the host,
+    f applied, z copied back (test code: the solvers see an ordinary callback
+    that enqueues nothing asynchronous)."""
+
+    def __init__(self, f, n: int):
+        self.f, self.n, self.calls = f, n, 0
+
+    def __call__(self, r_ptr, z_ptr, stream):
+        import ctypes
+        L = hip_runtime()
+        h2d, d2h = 1, 2
+        r = np.empty(self.n)
+        if L.hipStreamSynchronize(stream):
+            return 1
+        if L.hipMemcpyAsync(r.ctypes.data, r_ptr, r.nbytes, d2h, stream):
+            return 1
+        if L.hipStreamSynchronize(stream):
+            return 1
+        z = np.ascontiguousarray(self.f(r), dtype=np.float64)
+        self.calls += 1
+        rc = L.hipMemcpyAsync(z_ptr, z.ctypes.data, z.nbytes, h2d, stream)
+        rc = rc or L.hipStreamSynchronize(stream)
+        return 1 if rc else 0

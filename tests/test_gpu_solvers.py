@@ -1,14 +1,16 @@
 """GPU parity of the CSR comparison path and the Krylov solvers against the
 CPU oracle: pattern bit-equal, values and SpMV to 1e-13/1e-12, the first PCG
 iterates to 1e-10, converged solves judged by the oracle's operator,
-flexible PCG reducing to PCG for a fixed SPD preconditioner, iterative
+flexible PCG reducing to PCG for a fixed SPD preconditioner and following the
+oracle's flexible PCG and FCG(m) for one that changes between calls, iterative
 refinement to 1e-10, and the failure paths (zero right-hand side, breakdown,
 iteration limit, failing preconditioner)."""
 import numpy as np
 import pytest
 
 import seeded_inputs as si
-from helpers import TOL, dev, dpn_of, gpu_apply, make_op, problem, rel_err, torch_dtype
+from helpers import (TOL, HostPrecond, dev, dpn_of, gpu_apply, make_op, problem, rel_err,
+                     torch_dtype)
 
 pytestmark = pytest.mark.gpu
 
@@ -179,6 +181,50 @@ def test_fcg_with_jacobi_equals_pcg(q1, orc, m):
     assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
     with pytest.raises(q1.Q1Error):
         q1.q1_fcg(op, J, bd, xd, 1e-8, 10, trunc_m=9)
+
+
+def _varying(d, seed):
+    """Jacobi scaled per entry by seeded factors that change at every call."""
+    calls = [0]
+
+    def f(r):
+        k = calls[0]
+        calls[0] += 1
+        return si.varying_factors(r.shape[0], k, seed) * r / d
+
+    return f
+
+
+@pytest.mark.parametrize("m", [1, 2, 8])
+def test_fcg_varying_preconditioner_matches_oracle(q1, orc, m):
+    """With a preconditioner that changes between calls, q1_fpcg (m = 1) and
+    q1_fcg(m) follow the oracle's Golub-Ye FPCG and FCG(m) iterates."""
+    import torch
+    print(f"\n[fcg({m}) varying preconditioner]", flush=True)
+    pr = problem(1, (12, 10, 8), 0.1, 74, True)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = rhs(A, pr, 74)
+    d = A.diag()
+    op = make_op(pr, 0, 0)
+    for k in (1, 4, 10):
+        bd = dev(b, torch.float64)
+        xd = torch.empty_like(bd)
+        M = HostPrecond(_varying(d, 81), A.n)
+        st = q1.q1_fcg(op, M, bd, xd, 0.0, k, trunc_m=m)
+        if m == 1:
+            ref = orc.fpcg(A, b, _varying(d, 81), rtol=0.0, maxit=k)
+        else:
+            ref = orc.fcg(A, b, _varying(d, 81), m, rtol=0.0, maxit=k)
+        assert st["iters"] == k and st["fallback_at"] == -1 and M.calls == k
+        x = xd.cpu().numpy()
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), (m, k)
+    bd = dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    st = q1.q1_fcg(op, HostPrecond(_varying(d, 82), A.n), bd, xd, 1e-8, 5000, trunc_m=m)
+    ref = orc.fcg(A, b, _varying(d, 82), m, rtol=1e-8, maxit=5000)
+    assert st["status"] == 0 and st["fallback_at"] == -1
+    assert abs(st["iters"] - ref.iters) <= 0.02 * ref.iters + 2
+    assert orc.true_rel_res(A, xd.cpu().numpy(), b) <= 1e-8 * (1 + 1e-3)
 
 
 def test_fpcg_safeguard_fallback(q1, orc):
