@@ -131,8 +131,12 @@ enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_COLOR = 2, Q1_V_LDS_TILE = 3, Q1_V_C
 /* Create an operator over caller-owned device arrays.  The arrays are
  * referenced, not copied: they must stay valid and unchanged until
  * q1_op_destroy.  coef_d holds k [n_elems] (Laplace) or lambda then mu
- * [2][n_elems] (elasticity).  mask_d may be NULL.  Set-up work (tile maps)
- * runs on `stream` and is complete when the call returns. */
+ * [2][n_elems] (elasticity).  mask_d may be NULL.  Every connectivity entry
+ * is checked on the device to lie in [0, n_nodes) (Q1_EINVAL otherwise).
+ * Set-up work (that check, tile maps) runs on `stream` and is complete when
+ * the call returns.  A node that no element references has a zero row:
+ * every variant writes y = 0 there (y = x when it is masked), its diagonal is
+ * 0 (1 when masked) and the Jacobi weight of the solvers is 0 there. */
 int q1_op_create(q1_op **op, int physics, int dtype, int variant, int64_t n_nodes,
                  int64_t n_elems, const void *xyz_d, const int32_t *conn_d, const void *coef_d,
                  const uint8_t *mask_d, void *stream);
@@ -295,9 +299,9 @@ int q1_batched_mpcg(int nprob, q1_op *const *ops, int nrhs, const double *const 
                     void *stream);
 
 /* ---- learned preconditioner --------------------------------------------------
- * The paper lists learned preconditioning only as an outlook beside its future
- * matrix-free preconditioners (Section 6) and fixes no network.  This library
- * defines one: a 3-level 3-D convolutional U-Net on the node grid (16/32/64
+ * The paper's conclusions (Section 7) name matrix-free preconditioners as
+ * future work and say nothing of learned ones; the learned preconditioner is
+ * this project's own addition, and this library defines its network: a 3-level 3-D convolutional U-Net on the node grid (16/32/64
  * channels; per level two 3x3x3 zero-padded convolutions with bias and ReLU;
  * 2x2x2 average pooling down; nearest 2x upsampling concatenated with the
  * skip tensor up; a 1x1 head), trained with Adam on residual -> error pairs,

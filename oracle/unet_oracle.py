@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
 of the benchmark use it; the product library never imports or calls it, and
 nothing here calls the product library.
 
-The paper names a learned preconditioner only as an outlook beside the
-matrix-free preconditioners of its future work (Section 6); it fixes no
-network.  What is computed here is the network this project defines for it:
+The paper's conclusions (Section 7) name matrix-free preconditioners as
+future work and say nothing of learned ones: the learned preconditioner is
+this project's own addition.  What is computed here is the network this
+project defines for it:
 
 * a 3-level 3-D convolutional U-Net on the node grid, channels 16/32/64,
   3x3x3 zero-padded convolutions with bias, ReLU after every 3x3x3

@@ -145,6 +145,10 @@ class Op:
             q1_op_destroy(self)
 
     def __del__(self):
+        # at interpreter shutdown the process releases device memory itself:
+        # no library call is made from a finaliser then
+        if not _can_release():
+            return
         try:
             self.destroy()
         except Exception:
@@ -254,11 +258,16 @@ class Jacobi:
         self._op = op
         self.fn = ctypes.cast(lib().q1_precond_jacobi, ctypes.c_void_p)
 
+    def destroy(self):
+        if self.handle:
+            lib().q1_jacobi_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
     def __del__(self):
+        if not _can_release():
+            return
         try:
-            if self.handle:
-                lib().q1_jacobi_destroy(self.handle)
-                self.handle = ctypes.c_void_p()
+            self.destroy()
         except Exception:
             pass
 
@@ -445,14 +454,19 @@ class UNet:
     def adam_step(self, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
         check(lib().q1_unet_adam_step(self.handle, lr, b1, b2, eps, step, _stream(stream)))
 
-    def __del__(self):
+    def destroy(self):
         h = getattr(self, "handle", None)
-        try:
-            if h is not None and h.value and _lib_loaded():
-                lib().q1_unet_destroy(h)
-        except Exception:  # interpreter shutdown
-            pass
+        if h is not None and h.value:
+            lib().q1_unet_destroy(h)
         self.handle = None
+
+    def __del__(self):
+        if not _can_release():
+            return
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def q1_unet_create(D, H, W, batch, seed=0, stream=None) -> UNet:
@@ -481,14 +495,19 @@ class UNetPrecond:
         check(lib().q1_unet_encode_target(self.handle, _dptr(e), _dptr(target), _dptr(weight),
                                           _stream(stream)))
 
-    def __del__(self):
+    def destroy(self):
         h = getattr(self, "handle", None)
-        try:
-            if h is not None and h.value and _lib_loaded():
-                lib().q1_unet_pc_destroy(h)
-        except Exception:  # interpreter shutdown
-            pass
+        if h is not None and h.value:
+            lib().q1_unet_pc_destroy(h)
         self.handle = None
+
+    def __del__(self):
+        if not _can_release():
+            return
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def q1_unet_pc_create(net, nx, ny, nz, k, mask=None, stream=None) -> UNetPrecond:
@@ -498,4 +517,12 @@ def q1_unet_pc_create(net, nx, ny, nz, k, mask=None, stream=None) -> UNetPrecond
 def _lib_loaded() -> bool:
     from . import _lib as L
     return L._lib is not None
+
+
+def _can_release() -> bool:
+    """Whether a finaliser may call into the library: not during interpreter
+    shutdown (the HIP runtime may already be tearing down), and only once the
+    library is loaded."""
+    import sys
+    return not sys.is_finalizing() and _lib_loaded()
 

@@ -349,6 +349,34 @@ void free_colors(Op &op) {
   op.colors = ColorMap{};
 }
 
+// bad[0] = 1 when some connectivity entry is outside [0, nn)
+__global__ void k_check_conn(int64_t n, const int32_t *__restrict__ conn, int64_t nn,
+                             int *__restrict__ bad) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n && (conn[i] < 0 || conn[i] >= nn)) bad[0] = 1;
+}
+
+int validate_conn(const Op &op, hipStream_t s) {
+  if (op.n_elems == 0) return Q1_OK;
+  int *bad = nullptr;
+  Q1_HIP(hipMalloc(&bad, sizeof(int)));
+  struct Free {
+    int *p;
+    ~Free() { (void)hipFree(p); }
+  } fr{bad};
+  const int64_t n = 8 * op.n_elems;
+  int h = 0;
+  Q1_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_check_conn, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, op.conn,
+                     op.n_nodes, bad);
+  Q1_HIP(hipGetLastError());
+  Q1_HIP(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  Q1_HIP(hipStreamSynchronize(s));
+  Q1_CHECK(h == 0, Q1_EINVAL, "connectivity holds a node id outside [0, %lld)",
+           (long long)op.n_nodes);
+  return Q1_OK;
+}
+
 int launch_diag(Op &op, void *d, hipStream_t s) {
   return dispatch_phys(op, [&](auto t, auto ph) {
     return diag_impl<decltype(t), decltype(ph)::value>(op, d, s);

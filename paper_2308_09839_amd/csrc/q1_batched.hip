@@ -869,7 +869,7 @@ __global__ void k_deinterleave(int64_t n, int R, int c, const double *__restrict
 }
 __global__ void k_invert(int64_t n, double *__restrict__ d) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = 1.0 / d[i];
+  if (i < n) d[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;  // 0 on zero rows (unreferenced nodes)
 }
 
 __global__ void k_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst) {

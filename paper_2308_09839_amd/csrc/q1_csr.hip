@@ -120,6 +120,8 @@ namespace {
 
 int build_pattern(int dpn, int64_t nn, int64_t ne, const std::vector<int32_t> &conn,
                   std::vector<int32_t> &rowptr, std::vector<int32_t> &col) {
+  for (size_t i = 0; i < conn.size(); ++i)
+    Q1_CHECK(conn[i] >= 0 && conn[i] < nn, Q1_EINVAL, "CSR pattern: connectivity entry %zu out of range", i);
   std::vector<int64_t> nptr(nn + 1, 0);
   for (int a = 0; a < 8; ++a)
     for (int64_t e = 0; e < ne; ++e) nptr[conn[a * ne + e] + 1]++;
@@ -133,7 +135,7 @@ int build_pattern(int dpn, int64_t nn, int64_t ne, const std::vector<int32_t> &c
   // count
   std::vector<int32_t> cnt(nn);
   for (int64_t n = 0; n < nn; ++n) {
-    nb.clear();
+    nb.assign(1, int32_t(n));  // the diagonal, also for a node no element references
     for (int64_t t = nptr[n]; t < nptr[n + 1]; ++t)
       for (int a = 0; a < 8; ++a) nb.push_back(conn[a * ne + nel[t]]);
     std::sort(nb.begin(), nb.end());
@@ -148,7 +150,7 @@ int build_pattern(int dpn, int64_t nn, int64_t ne, const std::vector<int32_t> &c
     }
   col.resize(nnz);
   for (int64_t n = 0; n < nn; ++n) {
-    nb.clear();
+    nb.assign(1, int32_t(n));  // the diagonal, also for a node no element references
     for (int64_t t = nptr[n]; t < nptr[n + 1]; ++t)
       for (int a = 0; a < 8; ++a) nb.push_back(conn[a * ne + nel[t]]);
     std::sort(nb.begin(), nb.end());

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_fused(FusedArgs A) {
 
 __global__ void k_inv(int64_t n, double *__restrict__ d) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = 1.0 / d[i];
+  if (i < n) d[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;  // 0 on zero rows (unreferenced nodes)
 }
 
 }  // namespace

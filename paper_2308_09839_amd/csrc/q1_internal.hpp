@@ -115,6 +115,8 @@ int dispatch_phys(const Op &op, F &&f) {
 // stop: optional device flag; when it is non-zero at kernel start the launch does nothing
 int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop = nullptr);
 int launch_diag(Op &op, void *d, hipStream_t s);
+// Q1_EINVAL unless every connectivity entry is in [0, n_nodes) (synchronises s).
+int validate_conn(const Op &op, hipStream_t s);
 int build_tiles(Op &op, hipStream_t s);
 int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop);
 void free_tiles(Op &op);

@@ -85,6 +85,10 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
     if (hipGetDeviceProperties(&prop, op->device) == hipSuccess)
       op->num_cus = prop.multiProcessorCount;
   }
+  if ((rc = validate_conn(*op, static_cast<hipStream_t>(stream)))) {
+    delete op;
+    return rc;
+  }
   if (op->variant == Q1_V_PA && (physics == Q1_ELASTICITY || n_elems == 0)) {
     delete op;
     return fail(Q1_EUNSUPPORTED,

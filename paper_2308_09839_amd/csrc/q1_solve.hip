@@ -89,11 +89,11 @@ __device__ __forceinline__ Range block_range(int64_t n) {
 
 // ---- kernels ---------------------------------------------------------------
 
-// w = 1/d (Jacobi) or 1
+// w = 1/d (Jacobi) or 1; 0 on a zero row (a node that no element references)
 template <typename T>
 __global__ void k_inv_diag(int64_t n, const T *__restrict__ d, T *__restrict__ w, int jacobi) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) w[i] = jacobi ? T(1) / d[i] : T(1);
+  if (i < n) w[i] = jacobi ? (d[i] != T(0) ? T(1) / d[i] : T(0)) : T(1);
 }
 
 // x = 0, r = b, p = w b; partials rho_0 = b.(w b) and b.b

@@ -368,7 +368,8 @@ __global__ __launch_bounds__(256) void k_apply_block(
 }
 
 // Second pass of the block variant over the reset list: y = x on Dirichlet
-// nodes, otherwise the sum of the node's halo slots in tile order (slots j and
+// nodes, 0 on nodes that no element references, otherwise the sum of the
+// node's halo slots in tile order (slots j and
 // n + j, then the extra slots of edge and corner nodes), so every entry of y
 // is written exactly once.  Each thread takes kHaloNpt nodes (a block's nodes
 // are contiguous) and issues all their loads before summing; two per thread
@@ -406,10 +407,11 @@ __global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__re
 #pragma unroll
   for (int p = 0; p < kHaloNpt; ++p) {
     if (base + p * 256 >= n) continue;
-    const bool fixed = h[p] < 0;
-    const int64_t g = h[p] & 0x7fffffff;
+    const bool fixed = h[p] < 0, orphan = (h[p] & 0x40000000) != 0;
+    const int64_t g = h[p] & 0x3fffffff;
 #pragma unroll
-    for (int c = 0; c < DPN; ++c) y[g * DPN + c] = fixed ? x[g * DPN + c] : acc[p][c];
+    for (int c = 0; c < DPN; ++c)
+      y[g * DPN + c] = fixed ? x[g * DPN + c] : orphan ? T(0) : acc[p][c];
   }
 }
 
@@ -557,7 +559,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
         if (stamp[g] != t) { stamp[g] = t; ++ntile[g]; }
       }
   for (int64_t n = 0; n < nn; ++n)
-    if (ntile[n] > 1 || (!mask.empty() && mask[n])) H.reset.push_back(int32_t(n));
+    if (ntile[n] != 1 || (!mask.empty() && mask[n])) H.reset.push_back(int32_t(n));
   std::vector<int32_t> local(nn, -1), list;
   for (int t = 0; t < n_tiles; ++t) {
     list.clear();
@@ -614,7 +616,9 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
   // contributions of the tiles touching it in tile order: the first in slot j,
   // the second in slot n_reset + j (so each tile's writes along a shared face are
   // contiguous), the others in the extra region 2 n_reset + [hptr[j], hptr[j+1]).
-  // hnode[j] is the node id with bit 31 set on Dirichlet nodes (no slots).
+  // hnode[j] is the node id with bit 31 set on Dirichlet nodes (y = x) and
+  // bit 30 set on free nodes that no element references (y = 0); neither
+  // kind has slots written.
   const int64_t nr = int64_t(H.reset.size());
   std::vector<int64_t> hp(nr + 1, 0);
   H.hnode.assign(nr, 0);
@@ -622,7 +626,9 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
     const int32_t g = H.reset[j];
     const bool fixed = !mask.empty() && mask[g];
     hp[j + 1] = hp[j] + (fixed ? 0 : std::max(0, ntile[g] - 2));
-    H.hnode[j] = fixed ? int32_t(uint32_t(g) | 0x80000000u) : g;
+    H.hnode[j] = fixed            ? int32_t(uint32_t(g) | 0x80000000u)
+                 : ntile[g] == 0 ? int32_t(uint32_t(g) | 0x40000000u)
+                                 : g;
     local[g] = int32_t(j);  // reset index (local[] is free again here)
   }
   if (2 * nr + hp[nr] >= (int64_t(1) << 31)) return fail(Q1_EUNSUPPORTED, "too many halo slots");

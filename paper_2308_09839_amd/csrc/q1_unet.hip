@@ -2,9 +2,9 @@
 // grid (channels 16/32/64, two 3x3x3 convolutions with ReLU per level, 2x2x2
 // average pooling down, nearest upsampling and concatenation with the skip
 // tensor up, 1x1 head), trained with Adam on residual -> error pairs and used
-// as z = N(r) inside flexible PCG.  The paper names learned preconditioning
-// only as an outlook next to its future matrix-free preconditioners
-// (Section 6); the network, its encoding and its training are this library's.
+// as z = N(r) inside flexible PCG.  The paper's conclusions (Section 7) name
+// matrix-free preconditioners as future work and say nothing of learned
+// ones: the network, its encoding and its training are this project's own.
 //
 // Storage: BF16 activations and packed BF16 weights for the matrix cores,
 // FP32 master weights, gradients and Adam moments in one flat vector whose
@@ -379,7 +379,7 @@ __global__ void k_decode(const float *__restrict__ out, const uint8_t *__restric
 
 __global__ void k_inv(int64_t n, const double *__restrict__ d, double *__restrict__ w) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) w[i] = 1.0 / d[i];
+  if (i < n) w[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;  // 0 on zero rows (unreferenced nodes)
 }
 // z1 = omega w r ; (w = 1 / diag A)
 __global__ void k_smooth(int64_t n, const double *__restrict__ w, const double *__restrict__ r,

@@ -271,3 +271,60 @@ def test_apply_permuted_numbering(q1, orc, physics, variant):
     for dtype in (0, 1):
         y = gpu_apply(make_op(pp, dtype, variant), x, dtype)
         assert rel_err(y, ref) <= TOL[dtype], (dtype, rel_err(y, ref))
+
+
+def _with_orphan(pr, masked: bool):
+    """The problem with one extra node, numbered in the middle, that no element
+    references."""
+    nn = pr["xyz"].shape[1]
+    k = nn // 2
+    out = dict(pr)
+    out["xyz"] = np.insert(pr["xyz"], k, np.array([0.5, 0.5, 0.5]), axis=1)
+    out["conn"] = (pr["conn"] + (pr["conn"] >= k)).astype(np.int32)
+    out["mask"] = np.insert(pr["mask"], k, np.uint8(1 if masked else 0))
+    return out, k
+
+
+@pytest.mark.parametrize("masked", [False, True])
+@pytest.mark.parametrize("variant", VARIANTS + [6])
+@pytest.mark.parametrize("physics", [1, 3])
+def test_unreferenced_node(q1, orc, physics, variant, masked):
+    """A node no element references has a zero row: every variant writes y = 0
+    there (y = x when masked), whatever y held before; diag 0 (1 if masked)."""
+    import torch
+    if variant == 6 and physics == 3:
+        pytest.skip("partial assembly is built for the Laplace kinds only")
+    print(f"\n[orphan] physics={physics} variant={variant} masked={masked}", flush=True)
+    pr = problem(physics, (6, 5, 4), 0.1, 2308, True)
+    dpn = 1 if physics == 1 else 3
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    pr2, k = _with_orphan(pr, masked)
+    n2 = pr2["xyz"].shape[1] * dpn
+    x2 = si.vec_uniform(n2, 2308, si.STREAM_X)
+    x = np.delete(x2, np.arange(k * dpn, (k + 1) * dpn))
+    ref = np.insert(A.matvec(x), k * dpn, x2[k * dpn:(k + 1) * dpn] if masked else 0.0)
+    dref = np.insert(A.diag(), k * dpn, np.full(dpn, 1.0 if masked else 0.0))
+    op = make_op(pr2, 0, variant)
+    xd = dev(x2, torch.float64)
+    yd = torch.full_like(xd, float("nan"))
+    op.apply(xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    assert np.all(np.isfinite(y))
+    assert np.array_equal(y[k * dpn:(k + 1) * dpn], ref[k * dpn:(k + 1) * dpn])
+    assert rel_err(y, ref) <= TOL[0]
+    d = gpu_diag(op, n2, 0)
+    assert np.max(np.abs(d - dref)) <= 1e-13 * np.max(np.abs(dref))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 5, 6])
+def test_connectivity_out_of_range_rejected(q1, variant):
+    """q1_op_create checks every connectivity entry on the device."""
+    pr = problem(1, (4, 3, 2), 0.0, 7, True)
+    nn = pr["xyz"].shape[1]
+    for bad in (-1, nn, 2 ** 31 - 1):
+        conn = pr["conn"].copy()
+        conn[3, 5] = bad
+        with pytest.raises(q1.Q1Error) as ei:
+            make_op(dict(pr, conn=conn), 0, variant)
+        assert ei.value.code == -1, (variant, bad, str(ei.value))
