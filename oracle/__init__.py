@@ -58,11 +58,25 @@ def lib():
         L.orc_csr_pattern.restype = ctypes.c_int64
         L.orc_csr_assemble.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _f64p,
                                        _i32p, _f64p, ctypes.c_void_p, _i64p, _i32p, _f64p]
+        L.orc_csr_pattern_n.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                        ctypes.c_int64, _i32p, _i64p, ctypes.c_void_p]
+        L.orc_csr_pattern_n.restype = ctypes.c_int64
+        L.orc_csr_assemble_n.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                         ctypes.c_int64, _f64p, _i32p, _f64p, ctypes.c_void_p,
+                                         _i64p, _i32p, _f64p]
+        L.orc_apply_rows_n.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                       ctypes.c_int64, _f64p, _i32p, _f64p, ctypes.c_void_p,
+                                       _f64p, ctypes.c_int64, _i64p, _f64p]
+        L.orc_ke_tet_laplace.argtypes = [_f64p, ctypes.c_double, _f64p]
+        L.orc_ke_tet_elasticity.argtypes = [_f64p, ctypes.c_double, ctypes.c_double, _f64p]
+        L.orc_ke_q2_laplace.argtypes = [_f64p, ctypes.c_double, _f64p]
+        L.orc_ke_q2_elasticity.argtypes = [_f64p, ctypes.c_double, ctypes.c_double, _f64p]
         L.orc_apply_rows.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _f64p, _i32p,
                                      _f64p, ctypes.c_void_p, _f64p, ctypes.c_int64, _i64p, _f64p]
         L.orc_spmv.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p]
         L.orc_diag.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_pcg.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p,
                               ctypes.c_double, ctypes.c_int, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
@@ -81,6 +95,10 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 def ke_laplace(X: np.ndarray, k: float = 1.0) -> np.ndarray:
@@ -106,6 +124,38 @@ def ke_vlaplace(X: np.ndarray, k: float = 1.0) -> np.ndarray:
     if lib().orc_ke_vlaplace(np.ascontiguousarray(X, dtype=np.float64).ravel(), float(k), Ke):
         raise ValueError("non-positive Jacobian determinant")
     return Ke.reshape(24, 24)
+
+
+def ke_tet(physics: int, X: np.ndarray, c0: float, c1: float = 0.0) -> np.ndarray:
+    """Linear-tetrahedron element matrix (X[4,3]): physics 1 (4x4, k = c0) or 3
+    (12x12, lambda = c0, mu = c1)."""
+    X = np.ascontiguousarray(X, dtype=np.float64).ravel()
+    if physics == 1:
+        Ke = np.zeros(16)
+        rc = lib().orc_ke_tet_laplace(X, float(c0), Ke)
+    else:
+        Ke = np.zeros(144)
+        rc = lib().orc_ke_tet_elasticity(X, float(c0), float(c1), Ke)
+    if rc:
+        raise ValueError("non-positive Jacobian determinant")
+    m = 4 if physics == 1 else 12
+    return Ke.reshape(m, m)
+
+
+def ke_q2(physics: int, X: np.ndarray, c0: float, c1: float = 0.0) -> np.ndarray:
+    """Triquadratic-hexahedron element matrix (X[27,3], local node i + 3j + 9k):
+    physics 1 (27x27) or 3 (81x81)."""
+    X = np.ascontiguousarray(X, dtype=np.float64).ravel()
+    if physics == 1:
+        Ke = np.zeros(729)
+        rc = lib().orc_ke_q2_laplace(X, float(c0), Ke)
+    else:
+        Ke = np.zeros(6561)
+        rc = lib().orc_ke_q2_elasticity(X, float(c0), float(c1), Ke)
+    if rc:
+        raise ValueError("non-positive Jacobian determinant")
+    m = 27 if physics == 1 else 81
+    return Ke.reshape(m, m)
 
 
 @dataclass
@@ -147,15 +197,16 @@ def dpn_of(physics: int) -> int:
 
 
 def csr_pattern(dpn: int, n_nodes: int, conn: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Pattern for the connectivity conn [nloc, n_elems] (nloc 8, 4 or 27)."""
     conn = np.ascontiguousarray(conn, dtype=np.int32)
-    ne = conn.shape[1]
+    nloc, ne = conn.shape
     rowptr = np.zeros(n_nodes * dpn + 1, dtype=np.int64)
-    nnz = lib().orc_csr_pattern(dpn, n_nodes, ne, conn.ravel(), rowptr, None)
+    nnz = lib().orc_csr_pattern_n(dpn, nloc, n_nodes, ne, conn.ravel(), rowptr, None)
     if nnz < 0:
         raise MemoryError("oracle pattern allocation failed")
     col = np.empty(nnz, dtype=np.int32)
-    lib().orc_csr_pattern(dpn, n_nodes, ne, conn.ravel(), rowptr,
-                          col.ctypes.data_as(ctypes.c_void_p))
+    lib().orc_csr_pattern_n(dpn, nloc, n_nodes, ne, conn.ravel(), rowptr,
+                            col.ctypes.data_as(ctypes.c_void_p))
     return rowptr, col
 
 
@@ -165,7 +216,8 @@ def assemble(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
 
     physics = 1 (scalar Laplace, coef [1, ne] = k), 2 (vector Laplace, 3 DOF
     per node, coef [1, ne] = k) or 3 (elasticity, coef [2, ne] = lambda, mu).
-    xyz [3, nn], conn [8, ne], mask uint8 [nn]."""
+    xyz [3, nn], conn [nloc, ne] with nloc 8 (trilinear hexahedra), 4 (linear
+    tetrahedra) or 27 (triquadratic hexahedra), mask uint8 [nn]."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -177,8 +229,8 @@ def assemble(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
         mptr = mask.ctypes.data_as(ctypes.c_void_p)
     else:
         mptr = None
-    rc = lib().orc_csr_assemble(physics, nn, ne, xyz.ravel(), conn.ravel(), coef.ravel(),
-                                mptr, rowptr, col, val)
+    rc = lib().orc_csr_assemble_n(conn.shape[0], physics, nn, ne, xyz.ravel(), conn.ravel(),
+                                  coef.ravel(), mptr, rowptr, col, val)
     if rc == -1:
         raise ValueError("element with non-positive Jacobian determinant")
     if rc != 0:
@@ -200,8 +252,9 @@ def apply_rows(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray
     if mask is not None:
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         mptr = mask.ctypes.data_as(ctypes.c_void_p)
-    rc = lib().orc_apply_rows(physics, xyz.shape[1], conn.shape[1], xyz.ravel(), conn.ravel(),
-                              coef.ravel(), mptr, x, rows.shape[0], rows, y)
+    rc = lib().orc_apply_rows_n(conn.shape[0], physics, xyz.shape[1], conn.shape[1],
+                                xyz.ravel(), conn.ravel(), coef.ravel(), mptr, x, rows.shape[0],
+                                rows, y)
     if rc:
         raise RuntimeError(f"oracle apply_rows failed ({rc})")
     return y

@@ -155,6 +155,174 @@ int orc_ke_elasticity(const double X[24], double lam, double mu, double Ke[576])
   return 0;
 }
 
+/* ---- linear tetrahedra (the paper's conclusions, Section 7: simplicial
+ * elements) ------------------------------------------------------------- */
+
+/* Reference tetrahedron with vertices (0,0,0), (1,0,0), (0,1,0), (0,0,1);
+ * phi_0 = 1 - xi - eta - zeta, phi_a = xi_a (a = 1, 2, 3).  The gradients are
+ * constant, so the stiffness integrand is constant and the one-point rule at
+ * the centroid (weight 1/6, the reference volume) is exact.  Returns det J. */
+static double tet_gradients(const double X[12], double G[4][3]) {
+  static const double dphi[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  double J[3][3] = {{0}};
+  for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] += X[3 * a + r] * dphi[a][c];
+  double C[3][3];
+  C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  C[0][1] = -(J[1][0] * J[2][2] - J[1][2] * J[2][0]);
+  C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  C[1][0] = -(J[0][1] * J[2][2] - J[0][2] * J[2][1]);
+  C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  C[1][2] = -(J[0][0] * J[2][1] - J[0][1] * J[2][0]);
+  C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  C[2][1] = -(J[0][0] * J[1][2] - J[0][2] * J[1][0]);
+  C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+  for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < 3; ++r) {
+      double v = 0.0; /* (J^{-T} grad_hat phi_a)_r = sum_c dphi[a][c] Jinv[c][r] */
+      for (int c = 0; c < 3; ++c) v += dphi[a][c] * C[r][c] / det;
+      G[a][r] = v;
+    }
+  return det;
+}
+
+/* [A^e]_ab = k |T| grad phi_a . grad phi_b with |T| = det J / 6. */
+int orc_ke_tet_laplace(const double X[12], double k, double Ke[16]) {
+  double G[4][3];
+  const double det = tet_gradients(X, G);
+  if (!(det > 0.0)) return -1;
+  const double s = k * det / 6.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      Ke[4 * a + b] = s * (G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2]);
+  return 0;
+}
+
+/* [A^e]_{3a+i,3b+j} = |T| (lambda G_ai G_bj + mu (delta_ij G_a.G_b + G_aj G_bi)). */
+int orc_ke_tet_elasticity(const double X[12], double lam, double mu, double Ke[144]) {
+  double G[4][3];
+  const double det = tet_gradients(X, G);
+  if (!(det > 0.0)) return -1;
+  const double s = det / 6.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          Ke[12 * (3 * a + i) + 3 * b + j] =
+              s * (lam * G[a][i] * G[b][j] + mu * ((i == j ? gg : 0.0) + G[a][j] * G[b][i]));
+    }
+  return 0;
+}
+
+/* ---- triquadratic (Q2) hexahedra (Section 7: quadratic elements) ------- */
+
+/* Reference cube [-1,1]^3 with the 27 nodes at (t_i, t_j, t_k), t = (-1, 0, 1),
+ * local node a = i + 3j + 9k; phi_a = L_i(xi) L_j(eta) L_k(zeta) with the 1-D
+ * quadratic Lagrange basis L_0 = t(t-1)/2, L_1 = 1 - t^2, L_2 = t(t+1)/2.
+ * Quadrature: 3x3x3 Gauss-Legendre, points 0, +-sqrt(3/5), weights 8/9, 5/9
+ * (exact for the stiffness of elements with a trilinear geometry). */
+static double lq(int i, double t) {
+  return i == 0 ? 0.5 * t * (t - 1.0) : i == 1 ? 1.0 - t * t : 0.5 * t * (t + 1.0);
+}
+static double dlq(int i, double t) { return i == 0 ? t - 0.5 : i == 1 ? -2.0 * t : t + 0.5; }
+
+void orc_q2_quadrature(double pts[27][3], double w[27]) {
+  const double g = sqrt(0.6), gp[3] = {-g, 0.0, g}, gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+  for (int q = 0; q < 27; ++q) {
+    const int i = q % 3, j = (q / 3) % 3, k = q / 9;
+    pts[q][0] = gp[i]; pts[q][1] = gp[j]; pts[q][2] = gp[k];
+    w[q] = gw[i] * gw[j] * gw[k];
+  }
+}
+
+void orc_q2_ref_grad(const double xi[3], double dphi[27][3]) {
+  for (int a = 0; a < 27; ++a) {
+    const int i = a % 3, j = (a / 3) % 3, k = a / 9;
+    dphi[a][0] = dlq(i, xi[0]) * lq(j, xi[1]) * lq(k, xi[2]);
+    dphi[a][1] = lq(i, xi[0]) * dlq(j, xi[1]) * lq(k, xi[2]);
+    dphi[a][2] = lq(i, xi[0]) * lq(j, xi[1]) * dlq(k, xi[2]);
+  }
+}
+
+/* J, its cofactor inverse and the physical gradients of the 27 functions */
+static double q2_gradients(const double X[81], const double dphi[27][3], double G[27][3]) {
+  double J[3][3] = {{0}};
+  for (int a = 0; a < 27; ++a)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] += X[3 * a + r] * dphi[a][c];
+  double C[3][3];
+  C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  C[0][1] = -(J[1][0] * J[2][2] - J[1][2] * J[2][0]);
+  C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  C[1][0] = -(J[0][1] * J[2][2] - J[0][2] * J[2][1]);
+  C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  C[1][2] = -(J[0][0] * J[2][1] - J[0][1] * J[2][0]);
+  C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  C[2][1] = -(J[0][0] * J[1][2] - J[0][2] * J[1][0]);
+  C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+  for (int a = 0; a < 27; ++a)
+    for (int r = 0; r < 3; ++r) {
+      double v = 0.0;
+      for (int c = 0; c < 3; ++c) v += dphi[a][c] * C[r][c] / det;
+      G[a][r] = v;
+    }
+  return det;
+}
+
+int orc_ke_q2_laplace(const double X[81], double k, double Ke[729]) {
+  double pts[27][3], w[27];
+  orc_q2_quadrature(pts, w);
+  memset(Ke, 0, 729 * sizeof(double));
+  for (int q = 0; q < 27; ++q) {
+    double dphi[27][3], G[27][3];
+    orc_q2_ref_grad(pts[q], dphi);
+    const double det = q2_gradients(X, dphi, G);
+    if (!(det > 0.0)) return -1;
+    const double s = k * w[q] * det;
+    for (int a = 0; a < 27; ++a)
+      for (int b = 0; b < 27; ++b)
+        Ke[27 * a + b] += s * (G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2]);
+  }
+  return 0;
+}
+
+int orc_ke_q2_elasticity(const double X[81], double lam, double mu, double Ke[6561]) {
+  double pts[27][3], w[27];
+  orc_q2_quadrature(pts, w);
+  memset(Ke, 0, 6561 * sizeof(double));
+  for (int q = 0; q < 27; ++q) {
+    double dphi[27][3], G[27][3];
+    orc_q2_ref_grad(pts[q], dphi);
+    const double det = q2_gradients(X, dphi, G);
+    if (!(det > 0.0)) return -1;
+    const double s = w[q] * det;
+    for (int a = 0; a < 27; ++a)
+      for (int b = 0; b < 27; ++b) {
+        const double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            Ke[81 * (3 * a + i) + 3 * b + j] +=
+                s * (lam * G[a][i] * G[b][j] + mu * ((i == j ? gg : 0.0) + G[a][j] * G[b][i]));
+      }
+  }
+  return 0;
+}
+
+static int element_matrix_n(int nloc, int physics, const double *X, const double *coef,
+                            int64_t ne, int64_t e, double *Ke) {
+  if (nloc == 8) return element_matrix(physics, X, coef, ne, e, Ke);
+  const double c1 = physics == 3 ? coef[ne + e] : 0.0;
+  if (nloc == 4)
+    return physics == 1 ? orc_ke_tet_laplace(X, coef[e], Ke)
+                        : orc_ke_tet_elasticity(X, coef[e], c1, Ke);
+  return physics == 1 ? orc_ke_q2_laplace(X, coef[e], Ke)
+                      : orc_ke_q2_elasticity(X, coef[e], c1, Ke);
+}
+
 /* ---- CSR pattern ------------------------------------------------------- */
 
 static int cmp_i32(const void *p, const void *q) {
@@ -163,19 +331,19 @@ static int cmp_i32(const void *p, const void *q) {
 }
 
 /* node -> element incidence lists */
-static int node_elems(int64_t nn, int64_t ne, const int32_t *conn, int64_t **ptr_out,
+static int node_elems(int nloc, int64_t nn, int64_t ne, const int32_t *conn, int64_t **ptr_out,
                       int64_t **lst_out) {
   int64_t *ptr = (int64_t *)calloc((size_t)nn + 1, sizeof(int64_t));
-  int64_t *lst = (int64_t *)malloc((size_t)(8 * ne + 1) * sizeof(int64_t));
+  int64_t *lst = (int64_t *)malloc((size_t)(nloc * ne + 1) * sizeof(int64_t));
   if (!ptr || !lst) { free(ptr); free(lst); return -1; }
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < nloc; ++a)
     for (int64_t e = 0; e < ne; ++e) ptr[conn[a * ne + e] + 1]++;
   for (int64_t n = 0; n < nn; ++n) ptr[n + 1] += ptr[n];
   int64_t *fill = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
   if (!fill) { free(ptr); free(lst); return -1; }
   memcpy(fill, ptr, (size_t)nn * sizeof(int64_t));
   for (int64_t e = 0; e < ne; ++e)
-    for (int a = 0; a < 8; ++a) {
+    for (int a = 0; a < nloc; ++a) {
       int32_t n = conn[a * ne + e];
       /* an element lists a node once even if (degenerately) repeated */
       int dup = 0;
@@ -198,23 +366,29 @@ static int node_elems(int64_t nn, int64_t ne, const int32_t *conn, int64_t **ptr
 
 int64_t orc_csr_pattern(int dpn, int64_t nn, int64_t ne, const int32_t *conn,
                         int64_t *rowptr, int32_t *col) {
+  return orc_csr_pattern_n(dpn, 8, nn, ne, conn, rowptr, col);
+}
+
+int64_t orc_csr_pattern_n(int dpn, int nloc, int64_t nn, int64_t ne, const int32_t *conn,
+                          int64_t *rowptr, int32_t *col) {
   int64_t *nptr, *nlst;
-  if (node_elems(nn, ne, conn, &nptr, &nlst)) return -1;
+  if (node_elems(nloc, nn, ne, conn, &nptr, &nlst)) return -1;
   int64_t cap = 64;
   int32_t *buf = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
   if (!buf) { free(nptr); free(nlst); return -1; }
   int64_t nnz = 0;
   rowptr[0] = 0;
   for (int64_t n = 0; n < nn; ++n) {
-    int64_t m = 0, need = 8 * (nptr[n + 1] - nptr[n]);
+    int64_t m = 0, need = nloc * (nptr[n + 1] - nptr[n]) + 1;
     if (need > cap) {
       cap = need;
       int32_t *nb = (int32_t *)realloc(buf, (size_t)cap * sizeof(int32_t));
       if (!nb) { free(buf); free(nptr); free(nlst); return -1; }
       buf = nb;
     }
+    buf[m++] = (int32_t)n; /* the diagonal, also for a node no element references */
     for (int64_t t = nptr[n]; t < nptr[n + 1]; ++t)
-      for (int a = 0; a < 8; ++a) buf[m++] = conn[a * ne + nlst[t]];
+      for (int a = 0; a < nloc; ++a) buf[m++] = conn[a * ne + nlst[t]];
     qsort(buf, (size_t)m, sizeof(int32_t), cmp_i32);
     int64_t u = 0;
     for (int64_t t = 0; t < m; ++t)
@@ -245,30 +419,41 @@ static int64_t find_col(const int64_t *rowptr, const int32_t *col, int64_t row, 
 int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
                      const int32_t *conn, const double *coef, const uint8_t *mask,
                      const int64_t *rowptr, const int32_t *col, double *val) {
+  return orc_csr_assemble_n(8, physics, nn, ne, xyz, conn, coef, mask, rowptr, col, val);
+}
+
+int orc_csr_assemble_n(int nloc, int physics, int64_t nn, int64_t ne, const double *xyz,
+                       const int32_t *conn, const double *coef, const uint8_t *mask,
+                       const int64_t *rowptr, const int32_t *col, double *val) {
+  if (nloc != 8 && nloc != 4 && nloc != 27) return -3;
+  if (nloc != 8 && physics == 2) return -3;
   const int dpn = dpn_of(physics);
-  const int nd = 8 * dpn;
+  const int nd = nloc * dpn;
   const int64_t nrows = nn * dpn;
   memset(val, 0, (size_t)rowptr[nrows] * sizeof(double));
-  double X[24], Ke[576];
+  double X[81];
+  double *Ke = (double *)malloc((size_t)nd * nd * sizeof(double));
+  if (!Ke) return -2;
   for (int64_t e = 0; e < ne; ++e) {
-    for (int a = 0; a < 8; ++a) {
+    for (int a = 0; a < nloc; ++a) {
       int32_t n = conn[a * ne + e];
       X[3 * a + 0] = xyz[0 * nn + n];
       X[3 * a + 1] = xyz[1 * nn + n];
       X[3 * a + 2] = xyz[2 * nn + n];
     }
-    int rc = element_matrix(physics, X, coef, ne, e, Ke);
-    if (rc) return -1;
+    int rc = element_matrix_n(nloc, physics, X, coef, ne, e, Ke);
+    if (rc) { free(Ke); return -1; }
     for (int p = 0; p < nd; ++p) {
       int64_t row = (int64_t)conn[(p / dpn) * ne + e] * dpn + p % dpn;
       for (int s = 0; s < nd; ++s) {
         int32_t c = conn[(s / dpn) * ne + e] * dpn + s % dpn;
         int64_t t = find_col(rowptr, col, row, c);
-        if (t < 0) return -2;
+        if (t < 0) { free(Ke); return -2; }
         val[t] += Ke[nd * p + s];
       }
     }
   }
+  free(Ke);
   if (mask) {
     for (int64_t row = 0; row < nrows; ++row) {
       int rfix = mask[row / dpn] != 0;
@@ -284,7 +469,15 @@ int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
 int orc_apply_rows(int physics, int64_t nn, int64_t ne, const double *xyz,
                    const int32_t *conn, const double *coef, const uint8_t *mask,
                    const double *x, int64_t n_rows, const int64_t *rows, double *y) {
-  const int dpn = dpn_of(physics), nd = 8 * dpn;
+  return orc_apply_rows_n(8, physics, nn, ne, xyz, conn, coef, mask, x, n_rows, rows, y);
+}
+
+int orc_apply_rows_n(int nloc, int physics, int64_t nn, int64_t ne, const double *xyz,
+                     const int32_t *conn, const double *coef, const uint8_t *mask,
+                     const double *x, int64_t n_rows, const int64_t *rows, double *y) {
+  if (nloc != 8 && nloc != 4 && nloc != 27) return -3;
+  if (nloc != 8 && physics == 2) return -3;
+  const int dpn = dpn_of(physics), nd = nloc * dpn;
   /* slot[node] = 1 if any DOF of the node is selected */
   uint8_t *sel = (uint8_t *)calloc((size_t)nn, 1);
   int64_t *pos = (int64_t *)malloc((size_t)(nn * dpn) * sizeof(int64_t));
@@ -295,17 +488,19 @@ int orc_apply_rows(int physics, int64_t nn, int64_t ne, const double *xyz,
     pos[rows[r]] = r;
     y[r] = 0.0;
   }
-  double X[24], Ke[576];
+  double X[81];
+  double *Ke = (double *)malloc((size_t)nd * nd * sizeof(double));
+  if (!Ke) { free(sel); free(pos); return -2; }
   for (int64_t e = 0; e < ne; ++e) {
     int touch = 0;
-    for (int a = 0; a < 8; ++a) touch |= sel[conn[a * ne + e]];
+    for (int a = 0; a < nloc; ++a) touch |= sel[conn[a * ne + e]];
     if (!touch) continue;
-    for (int a = 0; a < 8; ++a) {
+    for (int a = 0; a < nloc; ++a) {
       int32_t n = conn[a * ne + e];
       for (int c = 0; c < 3; ++c) X[3 * a + c] = xyz[c * nn + n];
     }
-    int rc = element_matrix(physics, X, coef, ne, e, Ke);
-    if (rc) { free(sel); free(pos); return -1; }
+    int rc = element_matrix_n(nloc, physics, X, coef, ne, e, Ke);
+    if (rc) { free(sel); free(pos); free(Ke); return -1; }
     for (int p = 0; p < nd; ++p) {
       int64_t row = (int64_t)conn[(p / dpn) * ne + e] * dpn + p % dpn;
       if (pos[row] < 0) continue;
@@ -321,7 +516,7 @@ int orc_apply_rows(int physics, int64_t nn, int64_t ne, const double *xyz,
   if (mask)
     for (int64_t r = 0; r < n_rows; ++r)
       if (mask[rows[r] / dpn]) y[r] = x[rows[r]];
-  free(sel); free(pos);
+  free(sel); free(pos); free(Ke);
   return 0;
 }
 
@@ -351,6 +546,14 @@ int orc_num_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }
 

@@ -39,11 +39,26 @@ int orc_ke_laplace(const double X[24], double k, double Ke[64]);
 int orc_ke_elasticity(const double X[24], double lam, double mu, double Ke[576]);
 int orc_ke_vlaplace(const double X[24], double k, double Ke[576]);
 
+/* Linear tetrahedra: X is [4][3]; reference vertices (0,0,0), (1,0,0),
+ * (0,1,0), (0,0,1).  Triquadratic hexahedra: X is [27][3], local node
+ * a = i + 3j + 9k at (t_i, t_j, t_k), t = (-1, 0, 1); 3x3x3 Gauss rule.
+ * Return 0, or -1 when det J <= 0 (at some quadrature point). */
+int orc_ke_tet_laplace(const double X[12], double k, double Ke[16]);
+int orc_ke_tet_elasticity(const double X[12], double lam, double mu, double Ke[144]);
+void orc_q2_quadrature(double pts[27][3], double w[27]);
+void orc_q2_ref_grad(const double xi[3], double dphi[27][3]);
+int orc_ke_q2_laplace(const double X[81], double k, double Ke[729]);
+int orc_ke_q2_elasticity(const double X[81], double lam, double mu, double Ke[6561]);
+
 /* CSR pattern of the assembled operator, columns sorted.  rowptr has
  * n_nodes*dpn + 1 entries.  With col == NULL only rowptr is filled.
  * Returns nnz, or -1 on allocation failure. */
 int64_t orc_csr_pattern(int dpn, int64_t n_nodes, int64_t n_elems, const int32_t *conn,
                         int64_t *rowptr, int32_t *col);
+/* The same for elements of nloc nodes (connectivity [nloc][n_elems]).  Every
+ * row holds its diagonal entry. */
+int64_t orc_csr_pattern_n(int dpn, int nloc, int64_t n_nodes, int64_t n_elems,
+                          const int32_t *conn, int64_t *rowptr, int32_t *col);
 
 /* Fill values: element loop in element order, column found by binary search,
  * then Dirichlet elimination.  physics = 1 (Laplace) or 3 (elasticity).
@@ -51,6 +66,12 @@ int64_t orc_csr_pattern(int dpn, int64_t n_nodes, int64_t n_elems, const int32_t
 int orc_csr_assemble(int physics, int64_t n_nodes, int64_t n_elems, const double *xyz,
                      const int32_t *conn, const double *coef, const uint8_t *mask_nodes,
                      const int64_t *rowptr, const int32_t *col, double *val);
+/* nloc = 8 (trilinear hexahedra), 4 (linear tetrahedra) or 27 (triquadratic
+ * hexahedra; physics 1 or 3 for the last two).  -3 for other kinds. */
+int orc_csr_assemble_n(int nloc, int physics, int64_t n_nodes, int64_t n_elems,
+                       const double *xyz, const int32_t *conn, const double *coef,
+                       const uint8_t *mask_nodes, const int64_t *rowptr, const int32_t *col,
+                       double *val);
 
 /* Selected rows of y = A x computed from element matrices without forming A:
  * for each element touching a selected node, its element matrix is computed
@@ -60,14 +81,19 @@ int orc_csr_assemble(int physics, int64_t n_nodes, int64_t n_elems, const double
 int orc_apply_rows(int physics, int64_t n_nodes, int64_t n_elems, const double *xyz,
                    const int32_t *conn, const double *coef, const uint8_t *mask_nodes,
                    const double *x, int64_t n_rows, const int64_t *rows, double *y_rows);
+int orc_apply_rows_n(int nloc, int physics, int64_t n_nodes, int64_t n_elems,
+                     const double *xyz, const int32_t *conn, const double *coef,
+                     const uint8_t *mask_nodes, const double *x, int64_t n_rows,
+                     const int64_t *rows, double *y_rows);
 
 /* y = A x, rows in parallel (OpenMP), each row summed in column order. */
 void orc_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
               const double *x, double *y);
 void orc_diag(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
               double *d);
-/* Number of threads the OpenMP regions use. */
+/* Number of threads the OpenMP regions use, and a way to set it. */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* Preconditioned CG (Hestenes-Stiefel), x0 = 0, stop when ||r||_2 <= rtol ||b||_2
  * on the recurrence residual.  jacobi != 0 uses z = D^{-1} r.  res_hist, if

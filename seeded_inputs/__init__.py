@@ -115,6 +115,85 @@ def box_mesh(nx: int, ny: int, nz: int, h: float = 1.0, jitter_frac: float = 0.0
     return xyz, conn
 
 
+# The six tetrahedra of the Kuhn (Freudenthal) split of a hexahedron, as local
+# corners a = di + 2 dj + 4 dk: each follows one path of unit steps from corner 0
+# to corner 7 (x, y, z in some order), so neighbouring hexahedra split their
+# shared faces the same way.  Listed with positive orientation on the unit cube.
+KUHN_TETS = ((0, 1, 3, 7), (0, 5, 1, 7), (0, 3, 2, 7), (0, 2, 6, 7), (0, 6, 4, 7),
+             (0, 4, 5, 7))
+
+
+def tet_mesh(nx: int, ny: int, nz: int, h: float = 1.0, jitter_frac: float = 0.0,
+             seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Linear tetrahedra: every hexahedron of box_mesh (same nodes, same jitter)
+    split into the six Kuhn tetrahedra; tetrahedron t of hexahedron e is element
+    6 e + t.  Returns xyz [3, n_nodes] and conn int32 [4, 6 n_hex]."""
+    xyz, hconn = box_mesh(nx, ny, nz, h, jitter_frac, seed)
+    ne = hconn.shape[1]
+    conn = np.empty((4, 6 * ne), dtype=np.int32)
+    for t, corners in enumerate(KUHN_TETS):
+        for v, a in enumerate(corners):
+            conn[v, t::6] = hconn[a]
+    return xyz, conn
+
+
+def q2_box_sizes(nx: int, ny: int, nz: int) -> tuple[int, int]:
+    return (2 * nx + 1) * (2 * ny + 1) * (2 * nz + 1), nx * ny * nz
+
+
+def q2_box_mesh(nx: int, ny: int, nz: int, h: float = 1.0, jitter_frac: float = 0.0,
+                seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Triquadratic hexahedra on the box of nx*ny*nz elements.
+
+    Nodes lie on the doubled lattice, id = I + (2nx+1)(J + (2ny+1)K).  The
+    element vertices (even I, J, K) are box_mesh's nodes, jitter included; every
+    other node sits at the trilinear interpolation of its element's vertices
+    (at local coordinate 1/2 along each odd index), so each element is the
+    trilinear image of the reference cube.  Local node a = di + 3 dj + 9 dk of
+    element e = ex + nx(ey + ny ez) is lattice node (2ex+di, 2ey+dj, 2ez+dk).
+    Returns xyz [3, n_nodes] and conn int32 [27, n_elems]."""
+    vxyz, _ = box_mesh(nx, ny, nz, h, jitter_frac, seed)
+    NX, NY, NZ = 2 * nx + 1, 2 * ny + 1, 2 * nz + 1
+    K, J, I = np.meshgrid(np.arange(NZ), np.arange(NY), np.arange(NX), indexing="ij")
+    I = I.ravel(); J = J.ravel(); K = K.ravel()
+    xyz = np.zeros((3, NX * NY * NZ))
+
+    def vid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    # the vertex of the lower corner and the parity (odd = halfway) per axis
+    i0, j0, k0 = I // 2, J // 2, K // 2
+    oi, oj, ok = I % 2, J % 2, K % 2
+    for di in (0, 1):
+        wi = np.where(oi == 1, 0.5, 1.0 - di)
+        for dj in (0, 1):
+            wj = np.where(oj == 1, 0.5, 1.0 - dj)
+            for dk in (0, 1):
+                wk = np.where(ok == 1, 0.5, 1.0 - dk)
+                w = wi * wj * wk
+                sel = w > 0
+                v = vid(np.minimum(i0 + di, nx), np.minimum(j0 + dj, ny), np.minimum(k0 + dk, nz))
+                xyz[:, sel] += w[sel] * vxyz[:, v[sel]]
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex = ex.ravel(); ey = ey.ravel(); ez = ez.ravel()
+    conn = np.empty((27, nx * ny * nz), dtype=np.int32)
+    for a in range(27):
+        di, dj, dk = a % 3, (a // 3) % 3, a // 9
+        conn[a] = (2 * ex + di) + NX * ((2 * ey + dj) + NY * (2 * ez + dk))
+    return xyz, conn
+
+
+def q2_face_mask(nx: int, ny: int, nz: int, face: int | str) -> np.ndarray:
+    """uint8 per node of q2_box_mesh: 1 on the chosen face of the box."""
+    if isinstance(face, str):
+        face = FACES[face]
+    NX, NY, NZ = 2 * nx + 1, 2 * ny + 1, 2 * nz + 1
+    K, J, I = np.meshgrid(np.arange(NZ), np.arange(NY), np.arange(NX), indexing="ij")
+    sel = [I.ravel() == 0, I.ravel() == NX - 1, J.ravel() == 0, J.ravel() == NY - 1,
+           K.ravel() == 0, K.ravel() == NZ - 1][face]
+    return sel.astype(np.uint8)
+
+
 FACES = {"x0": 0, "x1": 1, "y0": 2, "y1": 3, "z0": 4, "z1": 5}
 
 
