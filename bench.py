@@ -4,15 +4,23 @@
 Workload: scalar Laplace, trilinear hexahedra on an undistorted 128^3-element
 grid (2,146,689 DOF), layered coefficient (one lognormal(0, 1.5) value per
 4-cell z-layer times iid lognormal(0, 0.5) per cell), FP64, no boundary
-condition.  A step is one y = A x apply with all inputs resident in HBM.
+condition.  Every element of the undistorted grid is a parallelepiped, so the
+apply takes the exact constant-Jacobian (affine) element path; the jittered
+grid (general hexahedra) is reported beside it.  A step is one y = A x apply
+with all inputs resident in HBM.  The timed steps rotate over four resident
+copies of the operator and its vectors (about 0.75 GB together, three times
+the 256 MB MALL), so every apply streams its data from HBM; back-to-back
+applies of one copy (warm, partly served from the MALL) and single applies
+after a 1 GiB cache flush (cold) are reported beside it.
 
 Prints one JSON line with the roofline of the apply (algorithmic bytes per
 apply / event-timed apply duration against 8 TB/s) and the CPU oracle
-(assembled CSR, OpenMP SpMV) timed on a slab of the same workload.
+(assembled CSR, OpenMP SpMV) timed on the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,13 +31,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per apply measured with FETCH_SIZE and WRITE_SIZE (each scaled by what the counter
-# reads for a plain 256 MB device copy: x2 and x1), keyed by (variant, dtype, elements per
-# edge) of the apply they were taken on (both kernels of the block variant: the tile kernel
-# and the halo sum); profiles/laplace128_fp64_block.md, laplace128_fp64_apply_counters.md.  A kernel
-# changed since its counters were taken gets no entry (traffic null).
-MEASURED_TRAFFIC = {(5, 0, 128): 180.3e6}  # tile kernel 151.0 MB, halo sum 29.2 MB
 FP64_PEAK_TFS = 78.6
+ROTATE = 4  # resident copies the timed applies rotate over
+# HBM bytes per apply measured with rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by what
+# the counter reads for a plain device copy of known size, see profiles/), keyed by the
+# hash of the apply's kernel sources and the grid edge.  A kernel changed since its counters
+# were taken hashes differently, so its traffic is reported as null.
+KERNEL_SOURCES = ("paper_2308_09839_amd/csrc/q1_tile.hip", "paper_2308_09839_amd/csrc/q1_elem.hpp")
+MEASURED_TRAFFIC: dict = {}
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg: str) -> None:
@@ -64,6 +81,46 @@ def time_applies(op, x, y, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def time_rotating(copies, steps, warmup):
+    """Applies rotating over resident copies (op, x, y) of the workload on the current
+    stream; events on that stream bracket the K steps.  Returns ms per apply."""
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    R = len(copies)
+    for i in range(warmup):
+        op, x, y = copies[i % R]
+        op.apply(x, y, st)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        op, x, y = copies[i % R]
+        op.apply(x, y, st)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_each(fn, reps, warmup=10):
+    """Median of `reps` calls of fn, each bracketed by its own events (launch-bound sizes)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 def time_cold(op, x, y, reps, mode="write"):
     """Median of `reps` applies, each timed alone after touching a 1 GiB buffer, which evicts
     the operator's data from L2 and the MALL (256 MB): mode "write" fills it (the apply then
@@ -90,42 +147,50 @@ def time_cold(op, x, y, reps, mode="write"):
     return ts[len(ts) // 2]
 
 
-def cpu_baseline(n: int, seed: int, slab: int):
-    """The oracle as it stands on a slab (first `slab` element layers) of the
-    same workload: CSR assembly once, then the OpenMP SpMV timed."""
+def cpu_baseline(n: int, seed: int):
+    """The oracle as it stands on the whole headline workload: CSR assembly once
+    (timed apart), then the OpenMP CSR SpMV timed with all host threads and with
+    one; plus the oracle's Jacobi-PCG on the 16^3 jittered problem."""
     import numpy as np
 
     import oracle
     import seeded_inputs as si
     oracle.build(force=False)
     pr = si.problem_laplace_layered(n, seed)
-    nn_s = (n + 1) * (n + 1) * (slab + 1)
-    ne_s = n * n * slab
-    xyz = np.ascontiguousarray(pr["xyz"][:, :nn_s])
-    conn = np.ascontiguousarray(pr["conn"][:, :ne_s])
-    coef = np.ascontiguousarray(pr["coef"][:, :ne_s])
+    nn = pr["xyz"].shape[1]
     t0 = time.perf_counter()
-    A = oracle.assemble(1, xyz, conn, coef)
+    A = oracle.assemble(1, pr["xyz"], pr["conn"], pr["coef"])
     t_asm = time.perf_counter() - t0
-    x = si.vec_uniform(nn_s, seed, si.STREAM_X)
-    A.matvec(x)
-    reps, t0 = 0, time.perf_counter()
-    while reps < 5 or time.perf_counter() - t0 < 3.0:
+    x = si.vec_uniform(nn, seed, si.STREAM_X)
+
+    def spmv_time(min_s):
         A.matvec(x)
-        reps += 1
-    t_spmv = (time.perf_counter() - t0) / reps
+        reps, t0 = 0, time.perf_counter()
+        while reps < 3 or time.perf_counter() - t0 < min_s:
+            A.matvec(x)
+            reps += 1
+        return (time.perf_counter() - t0) / reps, reps
+
+    threads = oracle.num_threads()
+    t_all, reps = spmv_time(4.0)
+    oracle.set_num_threads(1)
+    t_one, reps1 = spmv_time(4.0)
+    oracle.set_num_threads(threads)
     # the oracle's Jacobi-PCG on the 16^3 jittered problem, for the solve-time comparison
     prc, bc = cg16_problem(si)
     Ac = oracle.assemble(1, prc["xyz"], prc["conn"], prc["coef"], prc["mask"])
     t0 = time.perf_counter()
     refc = oracle.pcg(Ac, bc, rtol=1e-8)
     t_cg = time.perf_counter() - t0
-    return dict(value=round(nn_s / t_spmv / 1e9, 4), unit="GDOF/s", cores=oracle.num_threads(),
-                kind="oracle", cg16_s=round(t_cg, 5), cg16_iters=refc.iters,
-                sample=(f"{n}x{n}x{slab}-element slab ({nn_s} DOF) of the {n}^3 workload; "
-                        f"CSR assembled once in {t_asm:.2f} s (not in the rate), OpenMP CSR "
-                        f"SpMV timed over {reps} products"),
-                assembly_s=round(t_asm, 3), spmv_ms=round(t_spmv * 1e3, 3))
+    del A
+    return dict(value=round(nn / t_all / 1e9, 4), unit="GDOF/s", cores=threads,
+                kind="oracle", single_thread_value=round(nn / t_one / 1e9, 4),
+                cg16_s=round(t_cg, 5), cg16_iters=refc.iters,
+                sample=(f"the whole {n}^3 workload ({nn} DOF): CSR assembled once in "
+                        f"{t_asm:.2f} s (not in the rate), OpenMP CSR SpMV timed over {reps} "
+                        f"products on {threads} threads and {reps1} on one thread"),
+                assembly_s=round(t_asm, 3), spmv_ms=round(t_all * 1e3, 3),
+                spmv_single_thread_ms=round(t_one * 1e3, 3))
 
 
 def bench_csr(q1, si, n, seed, args):
@@ -157,14 +222,20 @@ def cg16_problem(si):
 
 
 def bench_cg16(q1, si, n, seed, args):
-    """16^3 jittered Laplace: FP64 Jacobi-PCG to a 1e-8 relative residual, wall time of the
-    whole solve, through the launch-per-kernel driver, through the persistent batched
-    kernel (one cooperative launch) and through the fused single-workgroup kernel."""
+    """16^3 jittered Laplace (launch-latency bound): microseconds per apply (median of
+    100 individually timed applies after 10 warm-up ones) and FP64 Jacobi-PCG to a 1e-8
+    relative residual (wall time of the whole solve and per iteration) through the
+    launch-per-kernel driver, the persistent batched kernel (one cooperative launch),
+    and the fused single-workgroup kernel."""
     import torch
     pr, b = cg16_problem(si)
     bd = torch.from_numpy(b).to("cuda")
     xd = torch.empty_like(bd)
     res = {}
+    op = q1.q1_op_create(1, 0, 0, *upload(pr, 0))
+    yd = torch.empty_like(bd)
+    res["cg16_apply_us"] = round(1e3 * time_each(lambda: op.apply(bd, yd), 100, 10), 2)
+    op.destroy()
     for tag, variant in (("", 0), ("_persistent", 3), ("_fused", 0)):
         op = q1.q1_op_create(1, 0, variant, *upload(pr, 0))
         if tag == "":
@@ -181,10 +252,158 @@ def bench_cg16(q1, si, n, seed, args):
             st = solve()
             ts.append(time.perf_counter() - t0)
         ts.sort()
-        res[f"cg16{tag}_gpu_s"] = round(ts[len(ts) // 2], 6)
+        t = ts[len(ts) // 2]
+        res[f"cg16{tag}_gpu_s"] = round(t, 6)
         res[f"cg16{tag}_iters"] = st["iters"]
+        res[f"cg16{tag}_us_per_iter"] = round(1e6 * t / max(1, st["iters"]), 2)
         res[f"cg16{tag}_rel_res"] = st["rel_res"]
+        op.destroy()
+    torch.cuda.synchronize()
     return res
+
+
+def bench_cg128(q1, si, n, seed, args):
+    """The paper's CG studies on the 128^3 workload with Dirichlet u = 0 on z = 0:
+    FP64 Jacobi-PCG throughput (N_dof x iterations / time) beside the apply alone, the
+    per-iteration time split into apply, dot products and vector updates, and the two
+    dot-product implementations (two-stage deterministic, single-pass atomic) over
+    block counts."""
+    import torch
+    pr = si.problem_laplace_layered(n, seed)
+    pr["mask"] = si.face_mask(n, n, n, "z0")
+    nn = pr["xyz"].shape[1]
+    op = q1.q1_op_create(1, 0, 0, *upload(pr, 0))
+    b = si.vec_uniform(nn, seed, si.STREAM_RHS)
+    b[pr["mask"] == 1] = 0.0
+    bd = torch.from_numpy(b).to("cuda")
+    xd = torch.empty_like(bd)
+    yd = torch.empty_like(bd)
+    res = {}
+    ms_apply, _ = time_applies(op, bd, yd, 200, 50)
+    q1.q1_pcg(op, 1, bd, xd, 0.0, 20)  # warm-up
+    torch.cuda.synchronize()
+    K = 400
+    t0 = time.perf_counter()
+    st = q1.q1_pcg(op, 1, bd, xd, 0.0, K)
+    t_pcg = time.perf_counter() - t0
+    us_iter = 1e6 * t_pcg / st["iters"]
+    res["cg128_iters_timed"] = st["iters"]
+    res["cg128_us_per_iter"] = round(us_iter, 2)
+    res["cg128_gdofs"] = round(nn * st["iters"] / t_pcg / 1e9, 3)
+    res["cg128_apply_us"] = round(1e3 * ms_apply, 2)
+    res["cg128_apply_gdofs"] = round(nn / (ms_apply * 1e-3) / 1e9, 3)
+    # dot products: the two implementations over block counts
+    work = torch.empty(1024, dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    s_ = torch.cuda.current_stream().cuda_stream
+    for name, variant in (("twostage", q1.Q1_DOT_TWO_STAGE), ("atomic", q1.Q1_DOT_ATOMIC)):
+        for nb in (256, 1024):
+            ms, _ = time_applies(_DotOp(q1, bd, yd, out, variant, nb, work), None, None, 500, 50)
+            res[f"dot128_{name}_nb{nb}_us"] = round(1e3 * ms, 2)
+            res[f"dot128_{name}_nb{nb}_gbs"] = round(2 * 8 * nn / (ms * 1e-3) / 1e9, 1)
+    ms_dot, _ = time_applies(_DotOp(q1, bd, yd, out, q1.Q1_DOT_TWO_STAGE, 0, work), None, None,
+                             500, 50)
+    # per iteration: one apply, the p.q dot, the update (x, r, two dots) and the direction
+    res["cg128_split_us"] = {"apply": round(1e3 * ms_apply, 2),
+                             "dot_pq": round(1e3 * ms_dot, 2),
+                             "update_direction_and_their_dots": round(
+                                 us_iter - 1e3 * (ms_apply + ms_dot), 2)}
+    op.destroy()
+    torch.cuda.synchronize()
+    return res
+
+
+def bench_family(q1, si, n, seed, args):
+    """The element families of the paper's conclusions: linear tetrahedra (the
+    Kuhn split of the headline 128^3 grid, 12,582,912 tetrahedra, each with its
+    hexahedron's coefficient) and triquadratic hexahedra (a 64^3-element box,
+    2,146,689 nodes, coefficient layered per 2 cells): FP64 and FP32 applies of
+    scalar Laplace, FP64 elasticity applies, and Jacobi-PCG to 1e-8 with
+    Dirichlet u = 0 on z = 0."""
+    import numpy as np
+    import torch
+    res = {}
+
+    def up(a, dt=None):
+        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=dt)
+
+    def make(elem, physics, dtype, xyz, conn, coef, mask=None):
+        t = torch.float64 if dtype == 0 else torch.float32
+        return q1.q1_op_create_elem(elem, physics, dtype, 0, up(xyz, t), up(conn.astype(np.int32)),
+                                    up(coef, t), up(mask.astype(np.uint8)) if mask is not None
+                                    else None)
+
+    for elem, tag in ((q1.Q1_TET4, "tet"), (q1.Q1_HEX27, "q2")):
+        if elem == q1.Q1_TET4:
+            m = n
+            xyz, conn = si.tet_mesh(m, m, m)
+            k = np.repeat(si.field_layered(m, m, m, 4, 1.5, 0.5, seed), 6)[None]
+            me = n // 2
+            xyz_e, conn_e = si.tet_mesh(me, me, me)
+            mask_e = si.face_mask(me, me, me, "z0")
+        else:
+            m = n // 2
+            xyz, conn = si.q2_box_mesh(m, m, m)
+            k = si.field_layered(m, m, m, 2, 1.5, 0.5, seed)[None]
+            me = n // 4
+            xyz_e, conn_e = si.q2_box_mesh(me, me, me)
+            mask_e = si.q2_face_mask(me, me, me, "z0")
+        nn = xyz.shape[1]
+        for dt, dtag in ((0, "fp64"), (1, "fp32")):
+            op = make(elem, 1, dt, xyz, conn, k)
+            t = torch.float64 if dt == 0 else torch.float32
+            x = up(si.vec_uniform(nn, seed, si.STREAM_X), t)
+            y = torch.empty_like(x)
+            ms, _ = time_applies(op, x, y, 200, 20)
+            b, f = op.bytes()
+            res[f"{tag}_laplace_{dtag}_gdofs"] = round(nn / (ms * 1e-3) / 1e9, 3)
+            res[f"{tag}_laplace_{dtag}_us"] = round(1e3 * ms, 2)
+            res[f"{tag}_laplace_{dtag}_hbm_frac"] = round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            if dt == 0:
+                res[f"{tag}_laplace_fp64_flop_frac"] = round(f / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)
+                res[f"{tag}_laplace_n_elems"] = conn.shape[1]
+                res[f"{tag}_laplace_n_dof"] = nn
+            op.destroy()
+        # elasticity apply and Jacobi-PCG on the smaller grid
+        ne_e = conn_e.shape[1]
+        E, nu = si.field_elastic(ne_e, seed)
+        coef_e = np.stack(si.lame_from_E_nu(E, nu))
+        op = make(elem, 3, 0, xyz_e, conn_e, coef_e, mask_e)
+        nd = 3 * xyz_e.shape[1]
+        x = up(si.vec_uniform(nd, seed, si.STREAM_X))
+        y = torch.empty_like(x)
+        ms, _ = time_applies(op, x, y, 200, 20)
+        res[f"{tag}_elasticity_fp64_gdofs"] = round(nd / (ms * 1e-3) / 1e9, 3)
+        res[f"{tag}_elasticity_n_dof"] = nd
+        op.destroy()
+        kp = si.field_lognormal(conn_e.shape[1], 0.0, 1.0, seed)[None]
+        op = make(elem, 1, 0, xyz_e, conn_e, kp, mask_e)
+        bb = si.vec_uniform(xyz_e.shape[1], seed, si.STREAM_RHS)
+        bb[mask_e == 1] = 0.0
+        bd = up(bb)
+        xd = torch.empty_like(bd)
+        q1.q1_pcg(op, 1, bd, xd, 1e-8, 5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = q1.q1_pcg(op, 1, bd, xd, 1e-8, 50000)
+        tp = time.perf_counter() - t0
+        res[f"{tag}_pcg_s"] = round(tp, 4)
+        res[f"{tag}_pcg_iters"] = st["iters"]
+        res[f"{tag}_pcg_true_rel_res"] = st["true_rel_res"]
+        res[f"{tag}_pcg_n_dof"] = int(xyz_e.shape[1])
+        op.destroy()
+    torch.cuda.synchronize()
+    return res
+
+
+class _DotOp:
+    """q1_dot behind the apply(x, y, stream) interface of the timing helpers."""
+
+    def __init__(self, q1, a, b, out, variant, nb, work):
+        self.q1, self.a, self.b, self.out, self.v, self.nb, self.w = q1, a, b, out, variant, nb, work
+
+    def apply(self, _x, _y, stream=None):
+        self.q1.q1_dot(self.a, self.b, self.out, self.v, self.nb, self.w, stream)
 
 
 def bench_ir96(q1, si, n, seed, args):
@@ -216,7 +435,20 @@ def bench_ir96(q1, si, n, seed, args):
     xx = torch.empty(3 * nn, dtype=torch.float64, device="cuda")
     yy = torch.empty_like(xx)
     ms64, _ = time_applies(op64, xx, yy, 50, 5)
-    return {"el96_pcg64_s": round(t64, 4), "el96_pcg64_iters": st64["iters"],
+    b64, _ = op64.bytes()
+    # partial assembly (scaled adjugate stored per point) against the matrix-free apply
+    pa = {}
+    for dt, tag, xv, yv in ((0, "fp64", xx, yy), (1, "fp32", x32, y32)):
+        oppa = q1.q1_op_create(3, dt, 6, *upload(pr, dt))
+        mspa, _ = time_applies(oppa, xv, yv, 50, 5)
+        bpa, _ = oppa.bytes()
+        pa[f"el96_pa_{tag}_gdofs"] = round(3 * nn / (mspa * 1e-3) / 1e9, 3)
+        pa[f"el96_pa_{tag}_hbm_frac"] = round(bpa / (mspa * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        pa[f"el96_pa_{tag}_alg_bytes"] = bpa
+        oppa.destroy()
+    op64.destroy()
+    op32.destroy()
+    return {**pa, "el96_apply_fp64_hbm_frac": round(b64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),"el96_pcg64_s": round(t64, 4), "el96_pcg64_iters": st64["iters"],
             "el96_pcg64_status": st64["status"], "el96_pcg64_true_rel_res": st64["true_rel_res"],
             "el96_ir_s": round(tir, 4), "el96_ir_inner_iters": sti["iters"],
             "el96_ir_outer": sti["outer_iters"], "el96_ir_status": sti["status"],
@@ -372,23 +604,34 @@ def bench_learned(q1, si, n, seed, args):
     res["nn_train_step_b4_ms"] = round(ms, 3)
     res["nn_train_step_b4_tflops"] = round(3 * B * unet_forward_flops(G, G, G) / (ms * 1e-3) / 1e12, 2)
     quiet = lambda m: log(m)
-    data = Lm.harvest(n4, [Lm.TRAIN_SEED0 + j for j in range(args.nn_fields)], 16, log=quiet)
+    data = Lm.harvest(n4, [Lm.TRAIN_SEED0 + j for j in range(args.nn_fields)], args.nn_per_field,
+                      log=quiet)
     tr = Lm.Trainer(net, data, B, seed=1)
-    hist, t_train = tr.train(args.nn_steps, lr=1e-3, log=quiet, log_every=100)
+    hist, t_train = tr.train(args.nn_steps, lr=1e-3, log=quiet, log_every=500)
+    periods = (1, 4, 16, 64)
+    per = Lm.choose_period(net, n4, periods, nval=2, trunc_m=8, log=quiet)
     rows = Lm.evaluate(net, n4, [Lm.EVAL_SEED0 + j for j in range(args.nn_eval)], omega=0.6,
-                       trunc_m=8, smoothing_baseline=True, log=quiet)
+                       trunc_m=8, periods=sorted({1, per}), smoothing_baseline=True, log=quiet)
     jt = sum(r["jacobi_s"] for r in rows) / len(rows)
-    nt = sum(r["nn_s"] for r in rows) / len(rows)
-    res.update({"nn_pairs": int(data["r"].shape[0]), "nn_train_steps": args.nn_steps,
+    nt = sum(r["periods"][per]["nn_s"] for r in rows) / len(rows)
+    n1 = sum(r["periods"][1]["nn_s"] for r in rows) / len(rows)
+    res.update({"nn_pairs": int(data["r"].shape[0]), "nn_train_fields": args.nn_fields,
+                "nn_train_steps": args.nn_steps,
                 "nn_train_s": round(t_train, 2), "nn_loss_first": hist[0][1],
-                "nn_loss_last": hist[-1][1],
+                "nn_loss_last": hist[-1][1], "nn_eval_fields": len(rows),
+                "nn_schedule_period": per,
                 "nn_eval_jacobi_iters": [r["jacobi_iters"] for r in rows],
-                "nn_eval_fpcg_iters": [r["nn_iters"] for r in rows],
-                "nn_eval_smoothing_only_iters": [r["smoothing_iters"] for r in rows],
-                "nn_eval_jacobi_ms": round(jt * 1e3, 2), "nn_eval_fpcg_ms": round(nt * 1e3, 2),
-                "nn_eval_fpcg_true_rel_res": max(r["nn_true_rel_res"] for r in rows),
-                "nn_eval_fallback_at": [r["nn_fallback_at"] for r in rows],
+                "nn_eval_fcg_iters": [r["periods"][per]["nn_iters"] for r in rows],
+                "nn_eval_smoothing_only_iters": [r["periods"][per]["smoothing_iters"] for r in rows],
+                "nn_eval_fcg_every_call_iters": [r["periods"][1]["nn_iters"] for r in rows],
+                "nn_eval_jacobi_ms": [round(r["jacobi_s"] * 1e3, 2) for r in rows],
+                "nn_eval_fcg_ms": [round(r["periods"][per]["nn_s"] * 1e3, 2) for r in rows],
+                "nn_eval_fcg_every_call_ms": round(n1 * 1e3, 2),
+                "nn_eval_fcg_true_rel_res": max(r["periods"][per]["nn_true_rel_res"] for r in rows),
+                "nn_eval_fallback_at": [r["periods"][per]["nn_fallback_at"] for r in rows],
                 "nn_wall_speedup_vs_jacobi": round(jt / nt, 3)})
+    del data
+    torch.cuda.synchronize()
     return res
 
 
@@ -404,11 +647,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated solver extras to run (csr, cg16, cg_elasticity96, "
-                         "vlaplace96, learned64, batched32) or 'all'")
-    ap.add_argument("--nn-fields", type=int, default=64, help="training fields of the learned leg")
+                    help="comma-separated solver extras to run (csr, cg16, cg128, "
+                         "cg_elasticity96, vlaplace96, family, learned64, batched32) or 'all'")
+    ap.add_argument("--nn-fields", type=int, default=500, help="training fields of the learned leg")
+    ap.add_argument("--nn-per-field", type=int, default=40, help="pairs per training field")
     ap.add_argument("--nn-steps", type=int, default=3000, help="Adam steps of the learned leg")
-    ap.add_argument("--nn-eval", type=int, default=2, help="held-out fields of the learned leg")
+    ap.add_argument("--nn-eval", type=int, default=8, help="held-out fields of the learned leg")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="also run one plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -420,7 +664,6 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_2308_09839_amd as q1
@@ -449,15 +692,41 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    op, x, y = make(pr, 0)
+    copies = [make(pr, 0) for _ in range(ROTATE)]
+    op, x, y = copies[0]
     info = op.info()
     alg_bytes, alg_flops = op.bytes()
-    log(f"[bench] timing {args.steps} FP64 applies (variant {info['variant']})")
-    ms, wall = time_applies(op, x, y, args.steps, args.warmup)
+    # untimed applies for about 60 ms first, so that the timed ones (and the warm-up the
+    # command line asks for) run at settled clocks even when K and W are small
+    for i in range(1500):
+        c = copies[i % ROTATE]
+        c[0].apply(c[1], c[2])
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} FP64 applies rotating over {ROTATE} copies "
+        f"(variant {info['variant']})")
+    ms = time_rotating(copies, args.steps, args.warmup)
     gdofs = ndof / (ms * 1e-3) / 1e9
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     extras = {}
+    ms_warm, _ = time_applies(op, x, y, args.steps, args.warmup)
+    extras["fp64_warm_gdofs"] = round(ndof / (ms_warm * 1e-3) / 1e9, 3)
+    extras["fp64_warm_ms"] = round(ms_warm, 5)
+    extras["fp64_warm_hbm_frac"] = round(alg_bytes / (ms_warm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    for c in copies[1:]:
+        c[0].destroy()
+    del copies
     if not args.no_extras:
+        log("[bench] cold (flushed) applies")
+        ms_cold = time_cold(op, x, y, 100)
+        extras["fp64_cold_write_flush_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)
+        extras["fp64_cold_write_flush_ms"] = round(ms_cold, 5)
+        extras["fp64_cold_write_flush_hbm_frac"] = round(
+            alg_bytes / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        ms_cold_r = time_cold(op, x, y, 100, "read")
+        extras["fp64_cold_read_flush_gdofs"] = round(ndof / (ms_cold_r * 1e-3) / 1e9, 3)
+        extras["fp64_cold_read_flush_ms"] = round(ms_cold_r, 5)
+        extras["fp64_cold_read_flush_hbm_frac"] = round(alg_bytes / (ms_cold_r * 1e-3) / 1e9 /
+                                                        HBM_PEAK_GBS, 4)
         for v in (1, 2, 3, 5, 6):
             if v == info["variant"]:
                 continue
@@ -468,37 +737,37 @@ def main() -> int:
                 bv, _ = opv.bytes()
                 extras["fp64_pa_hbm_frac"] = round(bv / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                 extras["fp64_pa_alg_bytes"] = bv
-            del opv
-        log("[bench] cold (flushed) applies")
-        ms_cold = time_cold(op, x, y, 100)
-        extras["fp64_cold_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)
-        extras["fp64_cold_ms"] = round(ms_cold, 5)
-        extras["fp64_cold_hbm_frac"] = round(alg_bytes / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        ms_cold_r = time_cold(op, x, y, 100, "read")
-        extras["fp64_cold_read_gdofs"] = round(ndof / (ms_cold_r * 1e-3) / 1e9, 3)
-        extras["fp64_cold_read_ms"] = round(ms_cold_r, 5)
-        extras["fp64_cold_read_hbm_frac"] = round(alg_bytes / (ms_cold_r * 1e-3) / 1e9 /
-                                                  HBM_PEAK_GBS, 4)
+            opv.destroy()
+        op.destroy()
         del op, x, y
         log("[bench] FP32 applies")
-        op32, x32, y32 = make(pr, 1)
-        ms32, _ = time_applies(op32, x32, y32, args.steps, args.warmup)
-        b32, _ = op32.bytes()
+        copies = [make(pr, 1) for _ in range(ROTATE)]
+        ms32 = time_rotating(copies, args.steps, args.warmup)
+        b32, _ = copies[0][0].bytes()
         extras["fp32_gdofs"] = round(ndof / (ms32 * 1e-3) / 1e9, 3)
         extras["fp32_ms"] = round(ms32, 5)
         extras["fp32_hbm_frac"] = round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        del op32, x32, y32
+        ms32w, _ = time_applies(*copies[0], args.steps, args.warmup)
+        extras["fp32_warm_gdofs"] = round(ndof / (ms32w * 1e-3) / 1e9, 3)
+        for c in copies:
+            c[0].destroy()
+        del copies
         log("[bench] jittered (general-hexahedron) FP64 applies")
         prj = dict(pr)
         prj["xyz"], _ = si.box_mesh(n, n, n, 1.0, 0.1, seed)
-        opj, xj, yj = make(prj, 0)
-        msj, _ = time_applies(opj, xj, yj, args.steps, args.warmup)
+        copies = [make(prj, 0) for _ in range(ROTATE)]
+        msj = time_rotating(copies, args.steps, args.warmup)
         extras["fp64_jittered_gdofs"] = round(ndof / (msj * 1e-3) / 1e9, 3)
         extras["fp64_jittered_ms"] = round(msj, 5)
         extras["fp64_jittered_flop_frac"] = round(alg_flops / (msj * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)
-        del opj, xj, yj
-        for name, fn in (("csr", bench_csr), ("cg16", bench_cg16), ("cg_elasticity96", bench_ir96),
-                         ("vlaplace96", bench_vlap96), ("learned64", bench_learned),
+        extras["fp64_jittered_hbm_frac"] = round(alg_bytes / (msj * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        for c in copies:
+            c[0].destroy()
+        del copies
+        torch.cuda.synchronize()
+        for name, fn in (("csr", bench_csr), ("cg16", bench_cg16), ("cg128", bench_cg128),
+                         ("cg_elasticity96", bench_ir96), ("vlaplace96", bench_vlap96),
+                         ("family", bench_family), ("learned64", bench_learned),
                          ("batched32", bench_batched)):
             if args.extras != "all" and name not in args.extras.split(","):
                 continue
@@ -508,12 +777,15 @@ def main() -> int:
             except Exception as exc:  # an extra must not take down the headline line
                 log(f"[bench] {name} failed: {exc!r}")
                 extras[f"{name}_error"] = repr(exc)
+            torch.cuda.synchronize()
+    else:
+        op.destroy()
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(n, seed, 16)
-        cpu["value"] = cpu["value"]
+        cpu = cpu_baseline(n, seed)
     torch.cuda.synchronize()
+    traffic = MEASURED_TRAFFIC.get((kernel_hash(), n)) if info["variant"] == 5 else None
     out = {
         "metric": "GDOF/s per matrix-free apply",
         "value": round(gdofs, 3),
@@ -528,18 +800,20 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"scalar Laplace Q1, {n}^3 undistorted hexahedra "
-                               f"({ndof} DOF), layered lognormal coefficient, FP64 "
-                               "matrix-free apply",
-                   "n_elems": n ** 3, "n_dof": ndof, "variant": info["variant"]},
+                               f"({ndof} DOF; every element a parallelepiped, so the exact "
+                               "constant-Jacobian element path), layered lognormal "
+                               "coefficient, FP64 matrix-free apply; the timed applies rotate "
+                               f"over {ROTATE} resident copies so each streams from HBM",
+                   "n_elems": n ** 3, "n_dof": ndof, "variant": info["variant"],
+                   "element_path": "parallelepiped"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC.get((info["variant"], 0, n)),
+                     "traffic": traffic,
+                     "kernel": "k_apply_block + k_halo_sum (one apply)",
                      "algorithmic_bytes_per_apply": alg_bytes,
-                     # achieved/frac: back-to-back applies (the timed steps), whose data
-                     # partly stays in the 256 MB MALL; cold: one apply after evicting L2
-                     # and the MALL by writing (or reading) a 1 GiB buffer
-                     "cold_frac": extras.get("fp64_cold_hbm_frac"),
-                     "cold_frac_read_flush": extras.get("fp64_cold_read_hbm_frac")},
+                     "warm_frac": extras.get("fp64_warm_hbm_frac"),
+                     "cold_frac_read_flush": extras.get("fp64_cold_read_flush_hbm_frac"),
+                     "cold_frac_write_flush": extras.get("fp64_cold_write_flush_hbm_frac")},
         "cpu_baseline": cpu,
         "extra": extras,
     }

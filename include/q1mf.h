@@ -117,11 +117,14 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
  *            buffer belongs to the operator, two applies of one BLOCK
  *            operator must not run concurrently (issue them on one stream);
  *   PA       "partial assembly" (Section 3; the storage of Table 3): BLOCK's
- *            tiles and halo, but at set-up the factor k w det J J^-1 J^-T of
- *            every element and quadrature point (6 reals, 48 per element) is
- *            computed and stored, and the apply reads it instead of the
- *            coordinates.  Laplace kinds only (Q1_EUNSUPPORTED for
- *            elasticity); the stored data is 48 reals per element;
+ *            tiles and halo, but at set-up quadrature data of every element
+ *            and point is computed and stored, and the apply reads it instead
+ *            of the coordinates.  Laplace kinds: the symmetric factor
+ *            k w det J J^-1 J^-T (6 reals per point, 48 per element).
+ *            Elasticity: the 9 entries of sqrt(w det J) J^-1 per point (72
+ *            per element; lambda and mu stay per cell), from which the flux
+ *            w det J sigma J^-T follows exactly (Table 3 counts 21 values per
+ *            point for isotropic elasticity without defining them);
  *   AUTO     the fastest measured strategy: BLOCK, else LDS_TILE when the tile
  *            does not fit in LDS, else ATOMIC;
  *   CSR      the assembled matrix (made by q1_csr_create only). */
@@ -140,6 +143,29 @@ enum { Q1_V_AUTO = 0, Q1_V_ATOMIC = 1, Q1_V_COLOR = 2, Q1_V_LDS_TILE = 3, Q1_V_C
 int q1_op_create(q1_op **op, int physics, int dtype, int variant, int64_t n_nodes,
                  int64_t n_elems, const void *xyz_d, const int32_t *conn_d, const void *coef_d,
                  const uint8_t *mask_d, void *stream);
+/* Element families.  The paper's elements are trilinear hexahedra
+ * (Q1_HEX8, the layout described at the top of this header); its conclusions
+ * (Section 7) name simplicial and quadratic elements as the next cases for the
+ * matrix-free algorithm, built here with the same physics:
+ *   Q1_TET4   linear tetrahedra: connectivity [4][n_elems], reference vertices
+ *             (0,0,0), (1,0,0), (0,1,0), (0,0,1) (positive orientation), the
+ *             exact one-point rule (constant gradients);
+ *   Q1_HEX27  triquadratic (Q2) hexahedra: connectivity [27][n_elems], local
+ *             node a = i + 3j + 9k at (t_i, t_j, t_k) with t = (-1, 0, 1) of
+ *             the reference cube, isoparametric geometry from the 27 nodes,
+ *             3x3x3 Gauss-Legendre quadrature.
+ * The enum values are the nodes per element. */
+enum { Q1_HEX8 = 8, Q1_TET4 = 4, Q1_HEX27 = 27 };
+/* q1_op_create for an element family.  Q1_HEX8 is q1_op_create.  Q1_TET4 and
+ * Q1_HEX27: physics Q1_LAPLACE or Q1_ELASTICITY, variants Q1_V_AUTO or
+ * Q1_V_ATOMIC (one thread per tetrahedron, 27 threads per triquadratic element
+ * with the element's nodes staged in LDS; global atomic scatter); other
+ * variants and physics give Q1_EUNSUPPORTED.  The apply, diagonal, byte model
+ * and the Krylov solvers accept these operators; q1_csr_create, the fused and
+ * the batched solvers do not (Q1_EUNSUPPORTED). */
+int q1_op_create_elem(q1_op **op, int elem, int physics, int dtype, int variant,
+                      int64_t n_nodes, int64_t n_elems, const void *xyz_d, const int32_t *conn_d,
+                      const void *coef_d, const uint8_t *mask_d, void *stream);
 /* y = A x (overwrites y; x and y must not alias).  Both have n_nodes*dpn
  * entries of the operator's dtype. */
 int q1_op_apply(q1_op *op, const void *x_d, void *y_d, void *stream);
@@ -191,6 +217,25 @@ typedef struct {
   int outer_iters;     /* iterative refinement: outer steps */
 } q1_stats;
 enum { Q1_PC_NONE = 0, Q1_PC_JACOBI = 1 };
+
+/* Dot product of two device vectors of n reals (dtype Q1_F64 or Q1_F32),
+ * accumulated in FP64 and written to the device double out_d: the reduction of
+ * Table 4's ddot operations, exposed so that implementations can be compared
+ * (the paper's Section 6 finds the dot product's implementation decisive for CG
+ * on AMD hardware).  Variants:
+ *   Q1_DOT_TWO_STAGE  each block writes its partial (fixed-order wave64 and
+ *                     block sums), then one block adds the partials in a fixed
+ *                     order: bitwise reproducible; the reduction the solvers use;
+ *   Q1_DOT_ATOMIC     one pass: each block adds its partial to out_d with an
+ *                     FP64 atomic (out_d is cleared first by the call); the
+ *                     order, and so the last bits, vary from run to run.
+ * nblocks: blocks of 256 threads (1..1024; 0 = the solvers' choice, one block
+ * per 2,048 entries up to 1024); work_d: device workspace of at least nblocks
+ * (1024 for nblocks = 0) doubles for Q1_DOT_TWO_STAGE, may be NULL for
+ * Q1_DOT_ATOMIC.  Asynchronous on `stream`. */
+enum { Q1_DOT_TWO_STAGE = 0, Q1_DOT_ATOMIC = 1 };
+int q1_dot(int64_t n, int dtype, const void *a_d, const void *b_d, double *out_d, int variant,
+           int nblocks, double *work_d, void *stream);
 
 /* Preconditioned CG (Hestenes-Stiefel) with z = D^{-1} r (Jacobi, D the
  * matrix-free diagonal) or z = r. */
@@ -389,6 +434,22 @@ int q1_unet_pc_create(q1_unet_pc **pc, q1_unet *net, int nx, int ny, int nz, con
  * correction, its scale chosen to minimise the energy norm of the error.
  * Costs two operator applies per use.  op must outlive the context. */
 int q1_unet_pc_two_level(q1_unet_pc *pc, q1_op *op, double omega, void *stream);
+/* Schedule of the network inside a solve: the network is evaluated on calls
+ * 0, period, 2 period, ... counted from this call, and the plain Jacobi step
+ * z = D^-1 r is taken on the others (a preconditioner that changes between
+ * calls, for the flexible solvers).  period > 1 needs the two-level form (its
+ * Jacobi weights).  Call it again before each solve to restart the count. */
+int q1_unet_pc_schedule(q1_unet_pc *pc, int period);
+/* Training pairs of the learned preconditioner from one Jacobi-PCG trajectory
+ * of the FP64 scalar-Laplace operator op: for each recorded iterate x_k
+ * (device FP64 vectors xk_d[i], host array of npairs pointers) and the
+ * converged x*, the error e = x* - x_k and the residual r = A e; with
+ * omega > 0 the pair is moved through one damped-Jacobi step as the two-level
+ * preconditioner presents it to the network, e1 = e - omega D^-1 r, r1 = A e1.
+ * Writes FP32 copies to e_d[i] and r_d[i] (n_nodes each).  Allocates three
+ * FP64 vectors of workspace; synchronises `stream`. */
+int q1_unet_pairs(q1_op *op, const double *xstar_d, int npairs, const double *const *xk_d,
+                  double omega, float *const *e_d, float *const *r_d, void *stream);
 int q1_unet_pc_destroy(q1_unet_pc *pc);
 /* Network input of a nodal FP64 vector r: channel 0 = r on free nodes scaled
  * to unit RMS over them (0 on Dirichlet nodes), channel 1 = half the mean of

@@ -9,22 +9,25 @@ the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 
+from . import _lib as _libmod
 from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32, Q1_F64,
+                   Q1_HEX8, Q1_HEX27, Q1_TET4,
                    Q1_LAPLACE, Q1_OK, Q1_VLAPLACE, Q1_PC_JACOBI, Q1_PC_NONE, Q1_V_ATOMIC, Q1_V_AUTO, Q1_V_COLOR,
                    Q1_V_CSR, Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
-    "Q1_PC_NONE", "Q1_PC_JACOBI", "Q1Stats", "q1_pcg", "q1_pcg_fused", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
+    "Q1_PC_NONE", "Q1_PC_JACOBI", "q1_dot", "Q1_DOT_TWO_STAGE", "Q1_DOT_ATOMIC", "Q1Stats", "q1_pcg", "q1_pcg_fused", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
     "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_VLAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_COLOR", "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
-    "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_apply", "q1_op_diag",
+    "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_create_elem", "Q1_HEX8", "Q1_TET4", "Q1_HEX27", "q1_op_apply", "q1_op_diag",
     "q1_op_info", "q1_op_bytes", "q1_op_destroy", "q1_model_bytes", "Op",
     "q1_conv3d_forward", "q1_conv3d_backward_data", "q1_conv3d_backward_weight", "UNet",
-    "q1_unet_create", "UNetPrecond", "q1_unet_pc_create",
+    "q1_unet_create", "UNetPrecond", "q1_unet_pc_create", "q1_unet_pairs",
 ]
 
 
@@ -167,6 +170,19 @@ def q1_op_create(physics: int, dtype: int, variant: int, xyz, conn, coef, mask=N
     return Op(h, (xyz, conn, coef, mask))
 
 
+def q1_op_create_elem(elem: int, physics: int, dtype: int, variant: int, xyz, conn, coef,
+                      mask=None, stream=None) -> Op:
+    """Operator of an element family: Q1_HEX8 (conn [8, n_elems]), Q1_TET4
+    (conn [4, n_elems]) or Q1_HEX27 (conn [27, n_elems])."""
+    h = ctypes.c_void_p()
+    n_nodes = xyz.shape[-1]
+    n_elems = conn.shape[-1]
+    check(lib().q1_op_create_elem(ctypes.byref(h), elem, physics, dtype, variant, n_nodes, n_elems,
+                                  _dptr(xyz), _dptr(conn), _dptr(coef), _dptr(mask),
+                                  _stream(stream)))
+    return Op(h, (xyz, conn, coef, mask))
+
+
 def q1_op_apply(op: Op, x, y, stream=None) -> None:
     check(lib().q1_op_apply(op.handle, _dptr(x), _dptr(y), _stream(stream)))
 
@@ -228,6 +244,20 @@ def _solve_rc(rc: int) -> int:
     if rc not in (Q1_OK, Q1_ENOCONV, Q1_EBREAKDOWN):
         check(rc)
     return rc
+
+
+Q1_DOT_TWO_STAGE = 0
+Q1_DOT_ATOMIC = 1
+
+
+def q1_dot(a, b, out, variant: int = Q1_DOT_TWO_STAGE, nblocks: int = 0, work=None,
+           stream=None) -> None:
+    """out (device FP64 scalar tensor) = a.b for device vectors a, b (FP64 or FP32);
+    work: device FP64 buffer of >= 1024 entries for the two-stage variant."""
+    import torch
+    dtype = Q1_F64 if a.dtype == torch.float64 else Q1_F32
+    check(lib().q1_dot(a.numel(), dtype, _dptr(a), _dptr(b), _dptr(out), variant, nblocks,
+                       _dptr(work), _stream(stream)))
 
 
 def q1_pcg(op: Op, pc: int, b, x, rtol: float, maxit: int, stream=None) -> dict:
@@ -488,6 +518,11 @@ class UNetPrecond:
         self.op = op
         check(lib().q1_unet_pc_two_level(self.handle, op.handle, omega, _stream(stream)))
 
+    def schedule(self, period: int):
+        """Network on every period-th call from now on, the Jacobi step otherwise
+        (call before each solve to restart the count)."""
+        check(lib().q1_unet_pc_schedule(self.handle, int(period)))
+
     def encode(self, r, inp, stream=None):
         check(lib().q1_unet_encode(self.handle, _dptr(r), _dptr(inp), _stream(stream)))
 
@@ -514,15 +549,28 @@ def q1_unet_pc_create(net, nx, ny, nz, k, mask=None, stream=None) -> UNetPrecond
     return UNetPrecond(net, nx, ny, nz, k, mask, stream)
 
 
+def q1_unet_pairs(op: Op, xstar, iterates, omega: float, e_out, r_out, stream=None) -> None:
+    """Training pairs (FP32 e, r written to the device vectors e_out[i], r_out[i])
+    from the FP64 iterates of one Jacobi-PCG trajectory and its converged xstar."""
+    n = len(iterates)
+    VP = ctypes.c_void_p
+    xa = (VP * max(n, 1))(*[_dptr(v) for v in iterates])
+    ea = (VP * max(n, 1))(*[_dptr(v) for v in e_out])
+    ra = (VP * max(n, 1))(*[_dptr(v) for v in r_out])
+    check(lib().q1_unet_pairs(op.handle, _dptr(xstar), n, ctypes.cast(xa, VP), omega,
+                              ctypes.cast(ea, VP), ctypes.cast(ra, VP), _stream(stream)))
+
+
 def _lib_loaded() -> bool:
-    from . import _lib as L
-    return L._lib is not None
+    return _libmod._lib is not None
 
 
 def _can_release() -> bool:
     """Whether a finaliser may call into the library: not during interpreter
     shutdown (the HIP runtime may already be tearing down), and only once the
     library is loaded."""
-    import sys
-    return not sys.is_finalizing() and _lib_loaded()
+    try:
+        return not sys.is_finalizing() and _lib_loaded()
+    except Exception:  # module state already torn down
+        return False
 

@@ -31,6 +31,9 @@ Q1_V_LDS_TILE = 3
 Q1_V_CSR = 4
 Q1_V_BLOCK = 5
 Q1_V_PA = 6
+Q1_HEX8 = 8
+Q1_TET4 = 4
+Q1_HEX27 = 27
 
 Q1_PC_NONE = 0
 Q1_PC_JACOBI = 1
@@ -78,6 +81,8 @@ PROTOTYPES = {
     "q1_vec_uniform": (c_int, [c_i64, c_u64, c_u64, c_dbl, c_dbl, c_vp]),
     "q1_op_create": (c_int, [P(c_vp), c_int, c_int, c_int, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp,
                              c_vp]),
+    "q1_op_create_elem": (c_int, [P(c_vp), c_int, c_int, c_int, c_int, c_i64, c_i64, c_vp, c_vp,
+                                  c_vp, c_vp, c_vp]),
     "q1_op_apply": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "q1_op_diag": (c_int, [c_vp, c_vp, c_vp]),
     "q1_op_info": (c_int, [c_vp, P(c_int), P(c_int), P(c_int), P(c_i64), P(c_i64)]),
@@ -100,6 +105,7 @@ PROTOTYPES = {
     "q1_batched_mpcg": (c_int, [c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_dbl, c_int, c_vp,
                                 c_vp]),
     "q1_mpcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_int, P(Q1Stats), c_vp]),
+    "q1_dot": (c_int, [c_i64, c_int, c_vp, c_vp, c_vp, c_int, c_int, c_vp, c_vp]),
     "q1_pcg_fused": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, P(Q1Stats), c_vp]),
     "q1_ir_solve": (c_int, [c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),
     "q1_conv3d_forward": (c_int, [c_int, c_int, c_int, c_int, c_vp, c_int, c_int, c_vp, c_int,
@@ -124,6 +130,8 @@ PROTOTYPES = {
     "q1_unet_encode": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "q1_unet_encode_target": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "q1_unet_precond": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "q1_unet_pc_schedule": (c_int, [c_vp, c_int]),
+    "q1_unet_pairs": (c_int, [c_vp, c_vp, c_int, c_vp, c_dbl, c_vp, c_vp, c_vp]),
 }
 
 

@@ -271,6 +271,7 @@ int diag_impl(Op &op, void *dv, hipStream_t s) {
 }  // namespace
 
 int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
+  if (op.elem != Q1_HEX8) return launch_apply_family(op, x, y, s, stop);
   switch (op.variant) {
     case Q1_V_ATOMIC:
       return dispatch_phys(op, [&](auto t, auto ph) {
@@ -364,7 +365,7 @@ int validate_conn(const Op &op, hipStream_t s) {
     int *p;
     ~Free() { (void)hipFree(p); }
   } fr{bad};
-  const int64_t n = 8 * op.n_elems;
+  const int64_t n = int64_t(op.nloc()) * op.n_elems;
   int h = 0;
   Q1_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_check_conn, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, op.conn,
@@ -378,6 +379,7 @@ int validate_conn(const Op &op, hipStream_t s) {
 }
 
 int launch_diag(Op &op, void *d, hipStream_t s) {
+  if (op.elem != Q1_HEX8) return launch_diag_family(op, d, s);
   return dispatch_phys(op, [&](auto t, auto ph) {
     return diag_impl<decltype(t), decltype(ph)::value>(op, d, s);
   });

@@ -570,6 +570,112 @@ __device__ __forceinline__ void laplace_element_pa_n(const T (*qd)[6], const T (
 }
 
 // ---------------------------------------------------------------------------
+// Partial assembly of isotropic elasticity: at each quadrature point q the
+// nine entries of B_q = sqrt(s) A' (A' the adjugate rows of the modal Jacobian
+// J', s = 1/(512 det')), row-major.  With the cell's lambda, mu these give the
+// flux exactly: H~ = G' B = sqrt(s) G' A', S~ = lambda tr(H~) I + mu (H~ + H~^T)
+// = sqrt(s) sigma'(G' A'), and S~ B^T = s sigma'(G' A') A'^T, the flux of the
+// general path.  X is destroyed.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void elasticity_qdata(T X[3][8], T qd[8][9]) {
+  butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
+  T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    eval4(X[r][1], X[r][3], X[r][5], X[r][7], Jx[r]);
+    eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);
+    eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+    const T jx[3] = {Jx[0][iy][iz], Jx[1][iy][iz], Jx[2][iy][iz]};
+    const T jy[3] = {Jy[0][ix][iz], Jy[1][ix][iz], Jy[2][ix][iz]};
+    const T jz[3] = {Jz[0][ix][iy], Jz[1][ix][iy], Jz[2][ix][iy]};
+    T a0[3], a1[3], a2[3];
+    cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
+    const T r = sqrt(rcp(T(512) * dot3(jx, a0)));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      qd[q][c] = r * a0[c];
+      qd[q][3 + c] = r * a1[c];
+      qd[q][6 + c] = r * a2[c];
+    }
+  }
+}
+
+// Elasticity from stored quadrature data: qd(q, m) returns entry m of B_q
+// (loaded where the point is reached).  The reference gradients are evaluated
+// from the modes at each point and the point's flux is added straight into the
+// output modes (the transposed evaluation), so only the input and output modes
+// stay live across points.
+template <typename T, typename QD>
+__device__ __forceinline__ void elasticity_element_pa(QD qd, const T (*u_in)[8], T lam, T mu,
+                                                      T (*v)[8]) {
+  T u[3][8], w[3][8];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      u[j][a] = u_in[j][a];
+      w[j][a] = T(0);
+    }
+    butterfly_fwd(u[j]);
+  }
+  const T g = C<T>::g, g2 = C<T>::g2;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const T sx = (q & 1) ? g : -g, sy = (q & 2) ? g : -g, sz = (q & 4) ? g : -g;
+    const T sxy = (((q & 1) != 0) == ((q & 2) != 0)) ? g2 : -g2;
+    const T sxz = (((q & 1) != 0) == ((q & 4) != 0)) ? g2 : -g2;
+    const T syz = (((q & 2) != 0) == ((q & 4) != 0)) ? g2 : -g2;
+    T B[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) B[m] = qd(q, m);
+    T H[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T g0 = u[j][1] + sy * u[j][3] + sz * u[j][5] + syz * u[j][7];
+      const T g1 = u[j][2] + sx * u[j][3] + sz * u[j][6] + sxz * u[j][7];
+      const T g4 = u[j][4] + sx * u[j][5] + sy * u[j][6] + sxy * u[j][7];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) H[j][kk] = g0 * B[kk] + g1 * B[3 + kk] + g4 * B[6 + kk];
+    }
+    const T ltr = lam * (H[0][0] + H[1][1] + H[2][2]);
+    T S[3][3];
+    S[0][0] = ltr + T(2) * mu * H[0][0];
+    S[1][1] = ltr + T(2) * mu * H[1][1];
+    S[2][2] = ltr + T(2) * mu * H[2][2];
+    S[0][1] = S[1][0] = mu * (H[0][1] + H[1][0]);
+    S[0][2] = S[2][0] = mu * (H[0][2] + H[2][0]);
+    S[1][2] = S[2][1] = mu * (H[1][2] + H[2][1]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T f0 = S[i][0] * B[0] + S[i][1] * B[1] + S[i][2] * B[2];
+      const T f1 = S[i][0] * B[3] + S[i][1] * B[4] + S[i][2] * B[5];
+      const T f2 = S[i][0] * B[6] + S[i][1] * B[7] + S[i][2] * B[8];
+      w[i][1] += f0;
+      w[i][2] += f1;
+      w[i][4] += f2;
+      w[i][3] += sy * f0 + sx * f1;
+      w[i][5] += sz * f0 + sx * f2;
+      w[i][6] += sz * f1 + sy * f2;
+      w[i][7] += syz * f0 + sxz * f1 + sxy * f2;
+    }
+    // keep the next points' data loads below this point: hoisted together, the 72
+    // loads alone would hold 144 registers
+    if (q & 1) __asm__ volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    butterfly_bwd(w[i]);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[i][a] = w[i][a];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Physics kinds (the values of the public enum): 1 scalar Laplace, 2 vector
 // Laplace, 3 isotropic elasticity.
 // ---------------------------------------------------------------------------

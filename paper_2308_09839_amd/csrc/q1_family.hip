@@ -1,0 +1,486 @@
+// Element families beyond the trilinear hexahedron, named in the paper's
+// conclusions (Section 7) as the next cases for its matrix-free algorithm:
+// linear tetrahedra (simplicial elements) and triquadratic hexahedra
+// (quadratic elements).  The operators are the same scalar Laplace and
+// isotropic elasticity with cell-wise coefficients (Section 2), applied
+// without a matrix by the gather / local product / scatter-add of Section 3.
+//
+// Linear tetrahedra: one thread per element.  With E_c = X_c - X_0 (c = 1, 2,
+// 3) the cross products c_1 = E_2 x E_3, c_2 = E_3 x E_1, c_3 = E_1 x E_2 and
+// c_0 = -(c_1 + c_2 + c_3) are det J times the (constant) physical gradients
+// of the four basis functions, det J = E_1 . c_1 and the volume det J / 6, so
+//   Laplace      v_a = k (c_a . g) / (6 det J),  g = sum_b c_b u_b,
+//   elasticity   v_a = S c_a / (6 det J),  S = lambda tr(H) I + mu (H + H^T),
+//                H = sum_b u_b (x) c_b (= det J grad u).
+// Triquadratic hexahedra: 27 threads per element (a block holds 9 elements).
+// Thread r stages node r (coordinates, input) in LDS, then evaluates
+// quadrature point r of the 3x3x3 Gauss rule: the Jacobian J, its adjugate A
+// (rows the cross products of the columns, so J^-1 = A / det J) and the
+// reference gradients g of the input; it leaves in LDS the reference flux f,
+// with v_a = sum_q grad_hat phi_a(q) . f(q):
+//   Laplace      f = k w A (sum_c g_c A_c) / det J,
+//   elasticity   f_i = w S_i A^T / det J,  H = G A (det J grad u, rows of G
+//                the reference gradients of the components), S as above;
+// finally thread r gathers v_r for node r.  Both element kinds scatter with
+// global atomics (the paper's one-thread-per-element strategy), after
+// y = x on Dirichlet nodes and 0 elsewhere.
+#include <hip/hip_runtime.h>
+
+#include "q1_elem.hpp"
+#include "q1_internal.hpp"
+
+namespace q1 {
+namespace {
+
+constexpr int kFB = 256;  // threads per block
+constexpr int kQ2E = 9;   // triquadratic elements per block (27 threads each)
+
+__device__ __forceinline__ void gadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gadd(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// y = x on Dirichlet nodes, 0 elsewhere (before the atomic scatter); the same
+// with 1 for the diagonal
+template <typename T, int DPN>
+__global__ void k_fam_init(int64_t nn, const uint8_t *__restrict__ mask,
+                           const T *__restrict__ x, T *__restrict__ y,
+                           const int *__restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nn * DPN) return;
+  const bool fx = mask && mask[i / DPN];
+  y[i] = fx ? (x ? x[i] : T(1)) : T(0);
+}
+
+// ---- linear tetrahedra -----------------------------------------------------
+
+template <typename T>
+struct TetGeom {
+  T c[4][3];  // det J times the physical gradients
+  T s;        // 1 / (6 det J)
+};
+
+template <typename T>
+__device__ __forceinline__ TetGeom<T> tet_geom(const T X[3][4]) {
+  TetGeom<T> G;
+  const T E1[3] = {X[0][1] - X[0][0], X[1][1] - X[1][0], X[2][1] - X[2][0]};
+  const T E2[3] = {X[0][2] - X[0][0], X[1][2] - X[1][0], X[2][2] - X[2][0]};
+  const T E3[3] = {X[0][3] - X[0][0], X[1][3] - X[1][0], X[2][3] - X[2][0]};
+  cross(E2, E3, G.c[1]);
+  cross(E3, E1, G.c[2]);
+  cross(E1, E2, G.c[3]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) G.c[0][r] = -(G.c[1][r] + G.c[2][r] + G.c[3][r]);
+  G.s = rcp(T(6) * dot3(E1, G.c[1]));
+  return G;
+}
+
+template <typename T, int PH, bool MASKED>
+__global__ __launch_bounds__(kFB) void k_tet_apply(int64_t ne, int64_t nn,
+                                                   const T *__restrict__ xyz,
+                                                   const int32_t *__restrict__ conn,
+                                                   const T *__restrict__ coef,
+                                                   const uint8_t *__restrict__ mask,
+                                                   const T *__restrict__ x, T *__restrict__ y,
+                                                   const int *__restrict__ stop) {
+  constexpr int DPN = phys_dpn(PH);
+  if (stop && *stop) return;
+  const int64_t e = int64_t(blockIdx.x) * kFB + threadIdx.x;
+  if (e >= ne) return;
+  int32_t nid[4];
+  bool fixed[4];
+  T X[3][4], u[DPN][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) nid[a] = conn[a * ne + e];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    fixed[a] = MASKED && mask[nid[a]] != 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + nid[a]];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * DPN + j];
+  }
+  const TetGeom<T> G = tet_geom(X);
+  T v[DPN][4];
+  if constexpr (PH == 1) {
+    T g[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      g[r] = G.c[0][r] * u[0][0] + G.c[1][r] * u[0][1] + G.c[2][r] * u[0][2] + G.c[3][r] * u[0][3];
+    const T ks = coef[e] * G.s;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) v[0][a] = ks * dot3(G.c[a], g);
+  } else {
+    const T lam = coef[e], mu = coef[ne + e];
+    T H[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        H[i][j] = u[i][0] * G.c[0][j] + u[i][1] * G.c[1][j] + u[i][2] * G.c[2][j] +
+                  u[i][3] * G.c[3][j];
+    const T ltr = lam * (H[0][0] + H[1][1] + H[2][2]);
+    T S[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) S[i][j] = G.s * (mu * (H[i][j] + H[j][i]) + (i == j ? ltr : T(0)));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) v[i][a] = dot3(S[i], G.c[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    if (!fixed[a])
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) gadd(&y[int64_t(nid[a]) * DPN + j], v[j][a]);
+}
+
+// diag: Laplace k |c_a|^2 / (6 det J); elasticity ((lambda + mu) c_ai^2 + mu |c_a|^2) / (6 det J)
+template <typename T, int PH, bool MASKED>
+__global__ __launch_bounds__(kFB) void k_tet_diag(int64_t ne, int64_t nn,
+                                                  const T *__restrict__ xyz,
+                                                  const int32_t *__restrict__ conn,
+                                                  const T *__restrict__ coef,
+                                                  const uint8_t *__restrict__ mask,
+                                                  T *__restrict__ d) {
+  constexpr int DPN = phys_dpn(PH);
+  const int64_t e = int64_t(blockIdx.x) * kFB + threadIdx.x;
+  if (e >= ne) return;
+  int32_t nid[4];
+  T X[3][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    nid[a] = conn[a * ne + e];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + nid[a]];
+  }
+  const TetGeom<T> G = tet_geom(X);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (MASKED && mask[nid[a]]) continue;
+    const T cc = dot3(G.c[a], G.c[a]);
+    if constexpr (PH == 1) {
+      gadd(&d[nid[a]], coef[e] * G.s * cc);
+    } else {
+      const T lam = coef[e], mu = coef[ne + e];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        gadd(&d[int64_t(nid[a]) * 3 + i], G.s * ((lam + mu) * G.c[a][i] * G.c[a][i] + mu * cc));
+    }
+  }
+}
+
+// ---- triquadratic hexahedra ------------------------------------------------
+
+// 1-D quadratic Lagrange basis on [-1, 1] (nodes -1, 0, 1) and its derivative
+template <typename T>
+__device__ __forceinline__ T lq(int i, T t) {
+  return i == 0 ? T(0.5) * t * (t - T(1)) : i == 1 ? T(1) - t * t : T(0.5) * t * (t + T(1));
+}
+template <typename T>
+__device__ __forceinline__ T dlq(int i, T t) {
+  return i == 0 ? t - T(0.5) : i == 1 ? T(-2) * t : t + T(0.5);
+}
+// 3-point Gauss-Legendre point and weight
+template <typename T>
+__device__ __forceinline__ T gpt(int q) {
+  return q == 0 ? -T(0.77459666924148337703585307995648) : q == 1 ? T(0) : T(0.77459666924148337703585307995648);
+}
+template <typename T>
+__device__ __forceinline__ T gwt(int q) {
+  return q == 1 ? T(8) / T(9) : T(5) / T(9);
+}
+
+// The per-thread 1-D tables: basis and derivative of functions 0..2 at one
+// point (phase 2), or of one function at the points 0..2 (phase 3).
+template <typename T>
+struct Tab1 {
+  T b[3], d[3];
+};
+template <typename T>
+__device__ __forceinline__ Tab1<T> at_point(int q) {
+  Tab1<T> t;
+  const T p = gpt<T>(q);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    t.b[i] = lq<T>(i, p);
+    t.d[i] = dlq<T>(i, p);
+  }
+  return t;
+}
+template <typename T>
+__device__ __forceinline__ Tab1<T> of_function(int i) {
+  Tab1<T> t;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    t.b[q] = lq<T>(i, gpt<T>(q));
+    t.d[q] = dlq<T>(i, gpt<T>(q));
+  }
+  return t;
+}
+
+// Phase 2 at quadrature point r of a staged element: the Jacobian's
+// adjugate rows A (A[0] = j1 x j2, A[1] = j2 x j0, A[2] = j0 x j1), det J, and
+// the reference gradients G of NF staged fields.
+template <typename T, int NF>
+__device__ __forceinline__ T q2_point(int r, const T (*sX)[27], const T (*sU)[27], T A[3][3],
+                                      T G[NF][3]) {
+  const Tab1<T> tx = at_point<T>(r % 3), ty = at_point<T>((r / 3) % 3), tz = at_point<T>(r / 9);
+  T J[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) J[c][d] = T(0);
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) G[f][d] = T(0);
+#pragma unroll
+  for (int a = 0; a < 27; ++a) {
+    const int i = a % 3, j = (a / 3) % 3, k = a / 9;
+    const T d0 = tx.d[i] * ty.b[j] * tz.b[k];
+    const T d1 = tx.b[i] * ty.d[j] * tz.b[k];
+    const T d2 = tx.b[i] * ty.b[j] * tz.d[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T xc = sX[c][a];
+      J[c][0] += xc * d0;
+      J[c][1] += xc * d1;
+      J[c][2] += xc * d2;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const T uf = sU[f][a];
+      G[f][0] += uf * d0;
+      G[f][1] += uf * d1;
+      G[f][2] += uf * d2;
+    }
+  }
+  const T j0[3] = {J[0][0], J[1][0], J[2][0]};
+  const T j1[3] = {J[0][1], J[1][1], J[2][1]};
+  const T j2[3] = {J[0][2], J[1][2], J[2][2]};
+  cross(j1, j2, A[0]);
+  cross(j2, j0, A[1]);
+  cross(j0, j1, A[2]);
+  return dot3(j0, A[0]);
+}
+
+template <typename T, int PH, bool MASKED>
+__global__ __launch_bounds__(kFB) void k_q2_apply(int64_t ne, int64_t nn,
+                                                  const T *__restrict__ xyz,
+                                                  const int32_t *__restrict__ conn,
+                                                  const T *__restrict__ coef,
+                                                  const uint8_t *__restrict__ mask,
+                                                  const T *__restrict__ x, T *__restrict__ y,
+                                                  const int *__restrict__ stop) {
+  constexpr int DPN = phys_dpn(PH);
+  if (stop && *stop) return;
+  __shared__ T sX[kQ2E][3][27];
+  __shared__ T sU[kQ2E][DPN][27];
+  __shared__ T sF[kQ2E][DPN][3][27];  // reference flux: [component][direction][point]
+  const int le = int(threadIdx.x) / 27, r = int(threadIdx.x) - 27 * le;
+  const int64_t e = int64_t(blockIdx.x) * kQ2E + le;
+  const bool active = le < kQ2E && e < ne;
+  int64_t g = 0;
+  bool fixed = true;
+  if (active) {  // phase 1: node r
+    g = conn[int64_t(r) * ne + e];
+    fixed = MASKED && mask[g] != 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sX[le][c][r] = xyz[c * nn + g];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) sU[le][j][r] = fixed ? T(0) : x[g * DPN + j];
+  }
+  __syncthreads();
+  if (active) {  // phase 2: quadrature point r
+    T A[3][3], G[DPN][3];
+    const T det = q2_point<T, DPN>(r, sX[le], sU[le], A, G);
+    const T s = gwt<T>(r % 3) * gwt<T>((r / 3) % 3) * gwt<T>(r / 9) * rcp(det);
+    if constexpr (PH == 1) {
+      T p[3];  // det J times the physical gradient
+#pragma unroll
+      for (int m = 0; m < 3; ++m) p[m] = G[0][0] * A[0][m] + G[0][1] * A[1][m] + G[0][2] * A[2][m];
+      const T ks = coef[e] * s;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sF[le][0][d][r] = ks * dot3(A[d], p);
+    } else {
+      const T lam = coef[e], mu = coef[ne + e];
+      T H[3][3];  // det J times the displacement gradient
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) H[i][j] = G[i][0] * A[0][j] + G[i][1] * A[1][j] + G[i][2] * A[2][j];
+      const T ltr = lam * (H[0][0] + H[1][1] + H[2][2]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T Si[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Si[j] = mu * (H[i][j] + H[j][i]) + (i == j ? ltr : T(0));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sF[le][i][d][r] = s * dot3(Si, A[d]);
+      }
+    }
+  }
+  __syncthreads();
+  if (active && !fixed) {  // phase 3: node r gathers the test-function products
+    const Tab1<T> fx = of_function<T>(r % 3), fy = of_function<T>((r / 3) % 3),
+                  fz = of_function<T>(r / 9);
+    T v[DPN];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) v[j] = T(0);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+      const T d0 = fx.d[qx] * fy.b[qy] * fz.b[qz];
+      const T d1 = fx.b[qx] * fy.d[qy] * fz.b[qz];
+      const T d2 = fx.b[qx] * fy.b[qy] * fz.d[qz];
+#pragma unroll
+      for (int j = 0; j < DPN; ++j)
+        v[j] += d0 * sF[le][j][0][q] + d1 * sF[le][j][1][q] + d2 * sF[le][j][2][q];
+    }
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) gadd(&y[g * DPN + j], v[j]);
+  }
+}
+
+// diag: Laplace sum_q k w |t|^2 / det J, elasticity
+// sum_q w ((lambda + mu) t_i^2 + mu |t|^2) / det J, with t = sum_c dphi_c A[c]
+// (det J times the physical gradient of the node's basis function)
+template <typename T, int PH, bool MASKED>
+__global__ __launch_bounds__(kFB) void k_q2_diag(int64_t ne, int64_t nn,
+                                                 const T *__restrict__ xyz,
+                                                 const int32_t *__restrict__ conn,
+                                                 const T *__restrict__ coef,
+                                                 const uint8_t *__restrict__ mask,
+                                                 T *__restrict__ dg) {
+  constexpr int DPN = phys_dpn(PH);
+  __shared__ T sX[kQ2E][3][27];
+  __shared__ T sA[kQ2E][10][27];  // adjugate rows and w / det J per point
+  const int le = int(threadIdx.x) / 27, r = int(threadIdx.x) - 27 * le;
+  const int64_t e = int64_t(blockIdx.x) * kQ2E + le;
+  const bool active = le < kQ2E && e < ne;
+  int64_t g = 0;
+  bool fixed = true;
+  if (active) {
+    g = conn[int64_t(r) * ne + e];
+    fixed = MASKED && mask[g] != 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sX[le][c][r] = xyz[c * nn + g];
+  }
+  __syncthreads();
+  if (active) {
+    T A[3][3], G[1][3];  // (the coordinate field stands in for the unused input)
+    const T det = q2_point<T, 1>(r, sX[le], sX[le], A, G);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) sA[le][3 * c + m][r] = A[c][m];
+    sA[le][9][r] = gwt<T>(r % 3) * gwt<T>((r / 3) % 3) * gwt<T>(r / 9) * rcp(det);
+  }
+  __syncthreads();
+  if (active && !fixed) {
+    const Tab1<T> fx = of_function<T>(r % 3), fy = of_function<T>((r / 3) % 3),
+                  fz = of_function<T>(r / 9);
+    T acc[DPN];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) acc[j] = T(0);
+    const T c0 = coef[e], c1 = PH == 3 ? coef[ne + e] : T(0);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+      const T d0 = fx.d[qx] * fy.b[qy] * fz.b[qz];
+      const T d1 = fx.b[qx] * fy.d[qy] * fz.b[qz];
+      const T d2 = fx.b[qx] * fy.b[qy] * fz.d[qz];
+      T t[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        t[m] = d0 * sA[le][m][q] + d1 * sA[le][3 + m][q] + d2 * sA[le][6 + m][q];
+      const T tt = dot3(t, t), s = sA[le][9][q];
+      if constexpr (PH == 1) {
+        acc[0] += c0 * s * tt;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[i] += s * ((c0 + c1) * t[i] * t[i] + c1 * tt);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) gadd(&dg[g * DPN + j], acc[j]);
+  }
+}
+
+template <typename T, int PH>
+int family_apply_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
+  constexpr int DPN = phys_dpn(PH);
+  const T *x = static_cast<const T *>(xv);
+  T *y = static_cast<T *>(yv);
+  const int64_t ndof = op.n_nodes * DPN;
+  hipLaunchKernelGGL((k_fam_init<T, DPN>), dim3(unsigned((ndof + kFB - 1) / kFB)), dim3(kFB), 0,
+                     s, op.n_nodes, op.mask, x, y, stop);
+  if (op.n_elems > 0) {
+    const T *xyz = static_cast<const T *>(op.xyz), *coef = static_cast<const T *>(op.coef);
+    const bool m = op.mask != nullptr;
+    if (op.elem == Q1_TET4) {
+      const dim3 grid(unsigned((op.n_elems + kFB - 1) / kFB));
+      hipLaunchKernelGGL((m ? k_tet_apply<T, PH, true> : k_tet_apply<T, PH, false>), grid,
+                         dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask,
+                         x, y, stop);
+    } else {
+      const dim3 grid(unsigned((op.n_elems + kQ2E - 1) / kQ2E));
+      hipLaunchKernelGGL((m ? k_q2_apply<T, PH, true> : k_q2_apply<T, PH, false>), grid,
+                         dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask,
+                         x, y, stop);
+    }
+  }
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+template <typename T, int PH>
+int family_diag_t(Op &op, void *dv, hipStream_t s) {
+  constexpr int DPN = phys_dpn(PH);
+  T *d = static_cast<T *>(dv);
+  const int64_t ndof = op.n_nodes * DPN;
+  hipLaunchKernelGGL((k_fam_init<T, DPN>), dim3(unsigned((ndof + kFB - 1) / kFB)), dim3(kFB), 0,
+                     s, op.n_nodes, op.mask, static_cast<const T *>(nullptr), d,
+                     static_cast<const int *>(nullptr));
+  if (op.n_elems > 0) {
+    const T *xyz = static_cast<const T *>(op.xyz), *coef = static_cast<const T *>(op.coef);
+    const bool m = op.mask != nullptr;
+    if (op.elem == Q1_TET4) {
+      const dim3 grid(unsigned((op.n_elems + kFB - 1) / kFB));
+      hipLaunchKernelGGL((m ? k_tet_diag<T, PH, true> : k_tet_diag<T, PH, false>), grid,
+                         dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask, d);
+    } else {
+      const dim3 grid(unsigned((op.n_elems + kQ2E - 1) / kQ2E));
+      hipLaunchKernelGGL((m ? k_q2_diag<T, PH, true> : k_q2_diag<T, PH, false>), grid,
+                         dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask, d);
+    }
+  }
+  Q1_HIP(hipGetLastError());
+  return Q1_OK;
+}
+
+}  // namespace
+
+int launch_apply_family(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
+  const bool f64 = op.dtype == Q1_F64;
+  if (op.physics == Q1_LAPLACE)
+    return f64 ? family_apply_t<double, 1>(op, x, y, s, stop)
+               : family_apply_t<float, 1>(op, x, y, s, stop);
+  if (op.physics == Q1_ELASTICITY)
+    return f64 ? family_apply_t<double, 3>(op, x, y, s, stop)
+               : family_apply_t<float, 3>(op, x, y, s, stop);
+  return fail(Q1_EUNSUPPORTED, "element family %d: physics %d", op.elem, op.physics);
+}
+
+int launch_diag_family(Op &op, void *d, hipStream_t s) {
+  const bool f64 = op.dtype == Q1_F64;
+  if (op.physics == Q1_LAPLACE)
+    return f64 ? family_diag_t<double, 1>(op, d, s) : family_diag_t<float, 1>(op, d, s);
+  if (op.physics == Q1_ELASTICITY)
+    return f64 ? family_diag_t<double, 3>(op, d, s) : family_diag_t<float, 3>(op, d, s);
+  return fail(Q1_EUNSUPPORTED, "element family %d: physics %d", op.elem, op.physics);
+}
+
+}  // namespace q1

@@ -208,6 +208,7 @@ extern "C" int q1_pcg_fused(q1_op *opv, int pc, const double *b_d, double *x_d, 
   Q1_CHECK(rtol >= 0 && maxit >= 0, Q1_EINVAL, "q1_pcg_fused: need rtol >= 0 and maxit >= 0");
   Op &op = *reinterpret_cast<Op *>(opv);
   Q1_CHECK(op.dtype == Q1_F64, Q1_EUNSUPPORTED, "q1_pcg_fused: needs an FP64 operator");
+  Q1_CHECK(op.elem == Q1_HEX8, Q1_EUNSUPPORTED, "q1_pcg_fused: needs trilinear hexahedra");
   const int64_t n = op.n_nodes * op.dpn();
   const size_t lds = kRedBytes + size_t(n) * sizeof(double);
   Q1_CHECK(lds <= kLdsLimit, Q1_EUNSUPPORTED,

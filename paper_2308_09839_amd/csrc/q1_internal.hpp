@@ -77,6 +77,8 @@ struct ColorMap {
 struct Op {
   int physics = 1;  // kind: 1 scalar Laplace, 2 vector Laplace, 3 elasticity
   int dpn() const { return physics == 1 ? 1 : 3; }  // DOF per node
+  int elem = Q1_HEX8;  // element family; its value is the nodes per element
+  int nloc() const { return elem; }
   int dtype = Q1_F64;
   int variant = Q1_V_ATOMIC;
   int64_t n_nodes = 0, n_elems = 0;
@@ -115,6 +117,9 @@ int dispatch_phys(const Op &op, F &&f) {
 // stop: optional device flag; when it is non-zero at kernel start the launch does nothing
 int launch_apply(Op &op, const void *x, void *y, hipStream_t s, const int *stop = nullptr);
 int launch_diag(Op &op, void *d, hipStream_t s);
+// linear tetrahedra and triquadratic hexahedra (q1_family.hip)
+int launch_apply_family(Op &op, const void *x, void *y, hipStream_t s, const int *stop);
+int launch_diag_family(Op &op, void *d, hipStream_t s);
 // Q1_EINVAL unless every connectivity entry is in [0, n_nodes) (synchronises s).
 int validate_conn(const Op &op, hipStream_t s);
 int build_tiles(Op &op, hipStream_t s);

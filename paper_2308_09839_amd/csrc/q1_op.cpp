@@ -15,6 +15,16 @@ constexpr double kFlopsElasticity = 2070.0;
 // vector Laplace: the geometry (Jacobians, adjugates, determinants: 780 of the
 // scalar 1,070) once, the gradient, flux and transpose (290) per component
 constexpr double kFlopsVLaplace = 780.0 + 3.0 * 290.0;
+// linear tetrahedra: edges, the three cross products, det; then the gradient
+// and the four flux products (Laplace) or H, S and S c_a (elasticity)
+constexpr double kFlopsTetLaplace = 100.0;
+constexpr double kFlopsTetElasticity = 220.0;
+// triquadratic hexahedra, sum-factorised model: 1,296 FLOPs per field for the
+// reference gradients at the 27 points (3 coordinates + the input components)
+// and as many per component for the transposed evaluation, plus the per-point
+// adjugate, determinant and flux (about 70 Laplace, 150 elasticity)
+constexpr double kFlopsQ2Laplace = 4 * 1296.0 + 1296.0 + 27 * 70.0;
+constexpr double kFlopsQ2Elasticity = 6 * 1296.0 + 3 * 1296.0 + 27 * 150.0;
 
 int check_device_ptr(const void *p, const char *what) {
   if (!p) return fail(Q1_EINVAL, "%s is NULL", what);
@@ -41,8 +51,17 @@ extern "C" {
 int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nodes,
                  int64_t n_elems, const void *xyz_d, const int32_t *conn_d, const void *coef_d,
                  const uint8_t *mask_d, void *stream) {
+  return q1_op_create_elem(out, Q1_HEX8, physics, dtype, variant, n_nodes, n_elems, xyz_d, conn_d,
+                           coef_d, mask_d, stream);
+}
+
+int q1_op_create_elem(q1_op **out, int elem, int physics, int dtype, int variant,
+                      int64_t n_nodes, int64_t n_elems, const void *xyz_d, const int32_t *conn_d,
+                      const void *coef_d, const uint8_t *mask_d, void *stream) {
   Q1_CHECK(out, Q1_EINVAL, "q1_op_create: NULL handle pointer");
   *out = nullptr;
+  Q1_CHECK(elem == Q1_HEX8 || elem == Q1_TET4 || elem == Q1_HEX27, Q1_EINVAL,
+           "q1_op_create: element family must be 8, 4 or 27, got %d", elem);
   Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_VLAPLACE || physics == Q1_ELASTICITY,
            Q1_EINVAL,
            "q1_op_create: physics must be 1 (Laplace), 2 (vector Laplace) or 3 (elasticity), "
@@ -55,6 +74,12 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
                n_elems < (int64_t(1) << 31),
            Q1_EINVAL, "q1_op_create: bad sizes n_nodes=%lld n_elems=%lld", (long long)n_nodes,
            (long long)n_elems);
+  if (elem != Q1_HEX8) {
+    Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_ELASTICITY, Q1_EUNSUPPORTED,
+             "q1_op_create: element family %d supports scalar Laplace and elasticity", elem);
+    Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC, Q1_EUNSUPPORTED,
+             "q1_op_create: element family %d supports the atomic-scatter apply only", elem);
+  }
   int rc;
   if ((rc = check_device_ptr(xyz_d, "xyz"))) return rc;
   if (n_elems > 0) {
@@ -70,9 +95,11 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
   q1_op *op = new (std::nothrow) q1_op();
   Q1_CHECK(op, Q1_ENOMEM, "q1_op_create: out of host memory");
   op->physics = physics;
+  op->elem = elem;
   op->dtype = dtype;
   // AUTO: the block-staged tiles (fastest measured), else the one-wave tiles, else atomics
-  op->variant = variant == Q1_V_AUTO ? (n_elems > 0 ? Q1_V_BLOCK : Q1_V_ATOMIC) : variant;
+  op->variant = variant == Q1_V_AUTO ? (n_elems > 0 && elem == Q1_HEX8 ? Q1_V_BLOCK : Q1_V_ATOMIC)
+                                     : variant;
   op->n_nodes = n_nodes;
   op->n_elems = n_elems;
   op->xyz = xyz_d;
@@ -89,10 +116,9 @@ int q1_op_create(q1_op **out, int physics, int dtype, int variant, int64_t n_nod
     delete op;
     return rc;
   }
-  if (op->variant == Q1_V_PA && (physics == Q1_ELASTICITY || n_elems == 0)) {
+  if (op->variant == Q1_V_PA && n_elems == 0) {
     delete op;
-    return fail(Q1_EUNSUPPORTED,
-                "q1_op_create: partial assembly exists for the Laplace kinds with elements");
+    return fail(Q1_EUNSUPPORTED, "q1_op_create: partial assembly needs elements");
   }
   if (op->variant == Q1_V_LDS_TILE || op->variant == Q1_V_BLOCK || op->variant == Q1_V_PA) {
     rc = build_tiles(*op, static_cast<hipStream_t>(stream));
@@ -159,11 +185,31 @@ int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
     return Q1_OK;
   }
   const int coef_bytes = rb * (op->physics == Q1_ELASTICITY ? 2 : 1);
+  if (op->elem != Q1_HEX8) {  // Table 2's convention with 4 B per node id of the element
+    const double dpn = op->dpn();
+    if (bytes)
+      *bytes = double(op->n_elems) * (4.0 * op->nloc() + coef_bytes) +
+               double(op->n_nodes) * (3.0 * rb + 3.0 * dpn * rb);
+    const bool lap = op->physics == Q1_LAPLACE;
+    if (flops)
+      *flops = double(op->n_elems) * (op->elem == Q1_TET4
+                                          ? (lap ? kFlopsTetLaplace : kFlopsTetElasticity)
+                                          : (lap ? kFlopsQ2Laplace : kFlopsQ2Elasticity));
+    return Q1_OK;
+  }
   double b = 0.0;
-  // partial assembly: Table 3 (k folded into the quadrature data); otherwise Table 2
-  int rc = op->variant == Q1_V_PA
-               ? q1_model_bytes(2, op->physics, rb, 0, op->n_nodes, op->n_elems, 0, &b)
-               : q1_model_bytes(1, op->physics, rb, coef_bytes, op->n_nodes, op->n_elems, 0, &b);
+  // partial assembly: Table 3's convention (node map, cell constant, stored point data,
+  // three vector streams) with this library's stored data: 6 reals per point with k folded
+  // in for the Laplace kinds, 9 per point plus (lambda, mu) per cell for elasticity;
+  // otherwise Table 2
+  int rc = Q1_OK;
+  if (op->variant == Q1_V_PA && op->physics == Q1_ELASTICITY)
+    b = double(op->n_elems) * (32.0 + coef_bytes + 8.0 * 9.0 * rb) +
+        double(op->n_nodes) * 3.0 * 3.0 * rb;
+  else if (op->variant == Q1_V_PA)
+    rc = q1_model_bytes(2, op->physics, rb, 0, op->n_nodes, op->n_elems, 0, &b);
+  else
+    rc = q1_model_bytes(1, op->physics, rb, coef_bytes, op->n_nodes, op->n_elems, 0, &b);
   if (rc) return rc;
   if (bytes) *bytes = b;
   if (flops)
@@ -185,6 +231,8 @@ int q1_op_destroy(q1_op *op) {
 int q1_csr_create(q1_op **out, const q1_op *like, void *stream) {
   Q1_CHECK(out && like, Q1_EINVAL, "q1_csr_create: NULL argument");
   *out = nullptr;
+  Q1_CHECK(like->elem == Q1_HEX8, Q1_EUNSUPPORTED,
+           "q1_csr_create: the CSR comparison is built for trilinear hexahedra");
   q1_op *op = new (std::nothrow) q1_op();
   Q1_CHECK(op, Q1_ENOMEM, "q1_csr_create: out of host memory");
   static_cast<Op &>(*op) = static_cast<const Op &>(*like);

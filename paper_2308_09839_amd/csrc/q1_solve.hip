@@ -35,8 +35,8 @@
 
 namespace q1 {
 
-constexpr int kRT = 256;     // threads per reduction block
-constexpr int kMaxRB = 256;  // partial sums per reduction (at most one per thread)
+constexpr int kRT = 256;      // threads per reduction block
+constexpr int kMaxRB = 1024;  // partial sums per reduction (4 blocks per compute unit)
 
 // Device status record, read by the host every few iterations.
 struct Status {
@@ -71,9 +71,12 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
   }
 }
 
-// Re-reduce nb partials written by an earlier kernel (same value in every block).
+// Re-reduce nb <= kMaxRB partials written by an earlier kernel: thread t adds
+// partials t, t + 256, ... in order, then the fixed block sum (same value in
+// every block).
 __device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb) {
-  double v[1] = {int(threadIdx.x) < nb ? part[threadIdx.x] : 0.0};
+  double v[1] = {0.0};
+  for (int j = int(threadIdx.x); j < nb; j += kRT) v[0] += part[j];
   block_sum<1>(v);
   return v[0];
 }
@@ -257,6 +260,20 @@ __global__ __launch_bounds__(kRT) void k_finalize(const double *__restrict__ par
   if (threadIdx.x == 0) *out = s;
 }
 
+// the single-pass dot of the dot-product study: block partials added to *out
+// with FP64 atomics (order, and so the last bits, vary from run to run)
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_dot_atomic(int64_t n, const T *__restrict__ a,
+                                                    const T *__restrict__ c,
+                                                    double *__restrict__ out) {
+  const Range rg = block_range(n);
+  double v[1] = {0.0};
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) v[0] += double(a[i]) * double(c[i]);
+  block_sum<1>(v);
+  if (threadIdx.x == 0) unsafeAtomicAdd(out, v[0]);
+}
+__global__ void k_zero1(double *out) { *out = 0.0; }
+
 // Iterative refinement helpers
 // s = (float) (r / scale) with scale = sqrt(*nrm2)
 __global__ void k_scale_to_f32(int64_t n, const double *__restrict__ r,
@@ -410,6 +427,56 @@ __global__ __launch_bounds__(kRT) void k_fcg_update(int64_t n, const T *__restri
   }
   block_sum<1>(v);
   if (threadIdx.x == 0) part_rr[blockIdx.x] = v[0];
+}
+
+// Flexible CG guard: every block re-sums the z.r partials; when the sum is not
+// positive and finite, or a fallback is recorded, z = D^-1 r (w r) on the
+// block's range, and block 0 records the first fallback iteration.
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_fcg_guard(int64_t n, const T *__restrict__ w,
+                                                   const T *__restrict__ r, T *__restrict__ z,
+                                                   const double *__restrict__ part_zr,
+                                                   int *__restrict__ fb, int k,
+                                                   const Status *__restrict__ st) {
+  if (st->done) return;
+  const double zr = sum_partials(part_zr, gridDim.x);
+  const bool was = fb[0] != 0;
+  if (was || (zr > 0.0 && isfinite(zr))) {
+    if (!was) return;
+  }
+  const Range rg = block_range(n);
+  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) z[i] = w[i] * r[i];
+  if (!was && blockIdx.x == 0 && threadIdx.x == 0) {
+    fb[0] = 1;
+    fb[1] = k;
+  }
+}
+
+// fb = (flag, iteration)
+__global__ void k_set_fallback(int *fb, int flag, int k) {
+  if (fb[0] == 0 || flag == 0) {
+    fb[0] = flag;
+    fb[1] = k;
+  }
+}
+
+// After iteration `it` of flexible CG: r.r from the partials into the history
+// and the status; convergence, breakdown or the iteration limit end the solve.
+__global__ __launch_bounds__(kRT) void k_fcg_check(const double *__restrict__ part_rr, int nb,
+                                                   double *__restrict__ hist, double tol2, int it,
+                                                   int maxit, Status *__restrict__ st) {
+  if (st->done) return;
+  const double rr = sum_partials(part_rr, nb);
+  if (threadIdx.x == 0) {
+    hist[it] = rr;
+    st->rr = rr;
+    st->iter = it;
+    const bool conv = rr <= tol2 * st->bb, bad = !isfinite(rr);
+    if (conv || bad || it >= maxit) {
+      st->done = 1;
+      st->status = conv ? Q1_OK : (bad ? Q1_EBREAKDOWN : Q1_ENOCONV);
+    }
+  }
 }
 
 // ---- host drivers ------------------------------------------------------------
@@ -589,8 +656,12 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
 // orthogonalisation: the new direction is z made A-orthogonal to the last m
 // directions (m = 1 is the Polak-Ribiere flexible PCG).  Falls back to Jacobi
 // for the rest of the solve when M fails, gives z.r <= 0 or a non-finite
-// value, or when the residual has not dropped below its value safeguard_m
-// iterations earlier.
+// value (both checked on the device, which then replaces z by D^-1 r), or when
+// the residual has not dropped below its value safeguard_m iterations earlier
+// (checked by the host at its status reads).  Like pcg_t the host reads the
+// device status only every few iterations: each batch is sized from the
+// observed convergence rate so that few iterations are queued past
+// convergence (their kernels return at once, but the callback M still runs).
 template <typename T>
 int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, int maxit,
            int safeguard_m, int m, q1_stats *stats, hipStream_t s) {
@@ -598,22 +669,29 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
   Work W;
   int rc = alloc_work<T>(W, n, true);
   if (rc) return rc;
-  // direction window: m slots of p and q, and the p.q partials of every slot
+  // direction window: m slots of p and q, and the p.q partials of every slot;
+  // the fallback record and the residual history
   void *dirs = nullptr;
-  double *pq_parts = nullptr, *zq_parts = nullptr;
+  double *pq_parts = nullptr, *zq_parts = nullptr, *hist_d = nullptr;
+  int *fb = nullptr;
   struct Free {
-    void **a;
-    double **b, **c;
+    void *p[5];
     ~Free() {
-      if (*a) (void)hipFree(*a);
-      if (*b) (void)hipFree(*b);
-      if (*c) (void)hipFree(*c);
+      for (void *v : p)
+        if (v) (void)hipFree(v);
     }
-  } fr{&dirs, &pq_parts, &zq_parts};
+  };
   const size_t vb = size_t(std::max<int64_t>(n, 1)) * sizeof(T);
   Q1_HIP(hipMalloc(&dirs, 2 * size_t(m) * vb));
+  Free fr0{{dirs, nullptr, nullptr, nullptr, nullptr}};
   Q1_HIP(hipMalloc(&pq_parts, size_t(m) * kMaxRB * sizeof(double)));
+  fr0.p[1] = pq_parts;
   Q1_HIP(hipMalloc(&zq_parts, size_t(kMaxTrunc) * kMaxRB * sizeof(double)));
+  fr0.p[2] = zq_parts;
+  Q1_HIP(hipMalloc(&hist_d, size_t(maxit + 1) * sizeof(double)));
+  fr0.p[3] = hist_d;
+  Q1_HIP(hipMalloc(&fb, 2 * sizeof(int)));
+  fr0.p[4] = fb;
   auto P = [&](int j) { return reinterpret_cast<T *>(static_cast<char *>(dirs) + size_t(j) * vb); };
   auto Qv = [&](int j) {
     return reinterpret_cast<T *>(static_cast<char *>(dirs) + size_t(m + j) * vb);
@@ -626,6 +704,7 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
          *part_bb = Pp + 4 * kMaxRB;
   T *r = static_cast<T *>(W.r), *w = static_cast<T *>(W.w), *z = static_cast<T *>(W.z);
   Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
+  hipLaunchKernelGGL(k_set_fallback, dim3(1), dim3(1), 0, s, fb, 0, -1);
   hipLaunchKernelGGL((k_pcg_init<T>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r,
                      static_cast<T *>(W.p), part_rho, part_bb, 0);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
@@ -633,72 +712,97 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
   if ((rc = read_status(W, s))) return rc;
   const double bb = W.hst->bb;
   int status = Q1_OK, iters = 0, fallback_at = -1;
+  bool fallback = false;  // known to the host: M is no longer called
   double rr = bb;
-  std::vector<double> hist;
-  hist.push_back(bb);
-  auto precondition = [&](int k) -> int {
-    bool ok = fallback_at < 0 && M != nullptr;
-    if (ok) ok = M(ctx, r, z, s) == Q1_OK;
-    if (ok) {
-      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, part_rho, W.st);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rho, nb, &W.st->aux);
-      Q1_HIP(hipGetLastError());
-      int rc2 = read_status(W, s);
-      if (rc2) return rc2;
-      ok = std::isfinite(W.hst->aux) && W.hst->aux > 0.0;
-    }
-    if (!ok) {
-      if (fallback_at < 0) fallback_at = k;
-      (void)hipGetLastError();
-      hipLaunchKernelGGL((k_jacobi<T>), grid1(n), dim3(256), 0, s, n, w, r, z);
-      Q1_HIP(hipGetLastError());
-    }
+  std::vector<double> hist(1, bb);
+  auto start_fallback = [&](int k) -> int {
+    fallback = true;
+    fallback_at = k;
+    hipLaunchKernelGGL(k_set_fallback, dim3(1), dim3(1), 0, s, fb, 1, k);
+    Q1_HIP(hipGetLastError());
     return Q1_OK;
   };
+  if (!M) {
+    if ((rc = start_fallback(0))) return rc;
+  }
   if (bb > 0.0) {
     const double tol2 = rtol * rtol;
     status = Q1_ENOCONV;
-    for (int k = 0; k < maxit; ++k) {
-      if ((rc = precondition(k))) return rc;
-      // window: the previous min(k, m) directions, oldest first
-      const int cur = k % m, nwin = std::min(k, m);
-      DirSet d{};
-      for (int j = 0; j < nwin; ++j) {
-        const int sl = (k - nwin + j) % m;
-        d.p[j] = P(sl);
-        d.q[j] = Qv(sl);
-        d.pq[j] = pq_parts + size_t(sl) * kMaxRB;
+    int launched = 0, batch = 1;
+    int hfb[2] = {0, -1};
+    while (launched < maxit) {
+      const int mm = std::min(batch, maxit - launched);
+      for (int j = 0; j < mm; ++j) {
+        const int k = launched + j;
+        if (!fallback && M(ctx, r, z, s) != Q1_OK) {
+          (void)hipGetLastError();
+          if ((rc = start_fallback(k))) return rc;
+        }
+        // z.r > 0 and finite, else z = D^-1 r from here on (decided on the device)
+        hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, r, part_rho, W.st);
+        hipLaunchKernelGGL((k_fcg_guard<T>), dim3(nb), dim3(kRT), 0, s, n, w, r, z, part_rho, fb,
+                           k, W.st);
+        // window: the previous min(k, m) directions, oldest first
+        const int cur = k % m, nwin = std::min(k, m);
+        DirSet d{};
+        for (int t = 0; t < nwin; ++t) {
+          const int sl = (k - nwin + t) % m;
+          d.p[t] = P(sl);
+          d.q[t] = Qv(sl);
+          d.pq[t] = pq_parts + size_t(sl) * kMaxRB;
+        }
+        if (nwin > 0) {
+          hipLaunchKernelGGL((k_multi_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin, zq_parts,
+                             W.st);
+          hipLaunchKernelGGL((k_fcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin,
+                             zq_parts, P(cur), W.st);
+        } else {
+          Q1_HIP(hipMemcpyAsync(P(cur), z, size_t(n) * sizeof(T), hipMemcpyDeviceToDevice, s));
+        }
+        if ((rc = launch_apply(op, P(cur), Qv(cur), s, &W.st->done))) return rc;
+        hipLaunchKernelGGL((k_dot_pq_pr<T>), dim3(nb), dim3(kRT), 0, s, n, P(cur), Qv(cur), r,
+                           pq_parts + size_t(cur) * kMaxRB, part_pr, W.st);
+        hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kRT), 0, s, n, P(cur), Qv(cur), x, r,
+                           pq_parts + size_t(cur) * kMaxRB, part_pr, part_rr, W.st);
+        hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(kRT), 0, s, part_rr, nb, hist_d, tol2, k + 1,
+                           maxit, W.st);
       }
-      if (nwin > 0) {
-        hipLaunchKernelGGL((k_multi_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin, zq_parts,
-                           W.st);
-        hipLaunchKernelGGL((k_fcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin,
-                           zq_parts, P(cur), W.st);
-      } else {
-        Q1_HIP(hipMemcpyAsync(P(cur), z, size_t(n) * sizeof(T), hipMemcpyDeviceToDevice, s));
-      }
-      if ((rc = launch_apply(op, P(cur), Qv(cur), s, &W.st->done))) return rc;
-      hipLaunchKernelGGL((k_dot_pq_pr<T>), dim3(nb), dim3(kRT), 0, s, n, P(cur), Qv(cur), r,
-                         pq_parts + size_t(cur) * kMaxRB, part_pr, W.st);
-      hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kRT), 0, s, n, P(cur), Qv(cur), x, r,
-                         pq_parts + size_t(cur) * kMaxRB, part_pr, part_rr, W.st);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_rr, nb, &W.st->rr);
       Q1_HIP(hipGetLastError());
+      const int first = launched + 1;
+      launched += mm;
+      Q1_HIP(hipMemcpyAsync(hfb, fb, sizeof(hfb), hipMemcpyDeviceToHost, s));
       if ((rc = read_status(W, s))) return rc;
-      if (W.hst->done) break;  // breakdown
-      iters = k + 1;
-      rr = W.hst->rr;
-      hist.push_back(rr);
-      if (rr <= tol2 * bb) {
-        status = Q1_OK;
-        break;
+      const int done_it = W.hst->done ? W.hst->iter : launched;
+      if (done_it >= first) {
+        hist.resize(size_t(done_it) + 1);
+        Q1_HIP(hipMemcpy(&hist[first], hist_d + first, size_t(done_it - first + 1) * sizeof(double),
+                         hipMemcpyDeviceToHost));
       }
-      // stagnation safeguard
-      if (safeguard_m > 0 && fallback_at < 0 && int(hist.size()) > safeguard_m &&
-          !(rr < hist[hist.size() - 1 - safeguard_m]))
-        fallback_at = iters;
+      if (!fallback && hfb[0]) {  // the device replaced z: stop calling M
+        fallback = true;
+        fallback_at = hfb[1];
+      }
+      if (W.hst->done) break;
+      // stagnation: ||r|| not below its value safeguard_m iterations earlier
+      if (safeguard_m > 0 && !fallback)
+        for (int it = std::max(first, safeguard_m); it <= launched; ++it)
+          if (!(hist[it] < hist[it - safeguard_m])) {
+            if ((rc = start_fallback(launched))) return rc;
+            break;
+          }
+      // next batch: about half the iterations the observed rate still needs
+      int next = std::min(batch * 2, 32);
+      const double now = hist[launched], before = hist[first - 1];
+      if (now > 0.0 && before > now && launched >= first) {
+        const double rate = std::log(now / before) / double(launched - first + 1);
+        const double need = std::log(tol2 * bb / now) / rate;  // both logs negative
+        if (std::isfinite(need)) next = std::max(1, std::min(next, int(need / 2)));
+      }
+      batch = next;
     }
-    if (W.hst->done && W.hst->status == Q1_EBREAKDOWN) status = Q1_EBREAKDOWN;
+    iters = W.hst->iter;
+    rr = W.hst->rr;
+    if (W.hst->done) status = W.hst->status;
   }
   const auto t1 = std::chrono::steady_clock::now();
   if (stats) {
@@ -894,6 +998,33 @@ int q1_fcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, do
                           rtol, maxit, safeguard_m, trunc_m, st, s);
   return fpcg_t<float>(o, M, ctx, static_cast<const float *>(b_d), static_cast<float *>(x_d),
                        rtol, maxit, safeguard_m, trunc_m, st, s);
+}
+
+int q1_dot(int64_t n, int dtype, const void *a_d, const void *b_d, double *out_d, int variant,
+           int nblocks, double *work_d, void *stream) {
+  Q1_CHECK(a_d && b_d && out_d && n >= 0, Q1_EINVAL, "q1_dot: NULL argument or n < 0");
+  Q1_CHECK(dtype == Q1_F64 || dtype == Q1_F32, Q1_EINVAL, "q1_dot: bad dtype %d", dtype);
+  Q1_CHECK(variant == Q1_DOT_TWO_STAGE || variant == Q1_DOT_ATOMIC, Q1_EINVAL,
+           "q1_dot: bad variant %d", variant);
+  Q1_CHECK(nblocks >= 0 && nblocks <= kMaxRB, Q1_EINVAL, "q1_dot: nblocks %d not in [0, %d]",
+           nblocks, kMaxRB);
+  Q1_CHECK(variant != Q1_DOT_TWO_STAGE || work_d, Q1_EINVAL, "q1_dot: two-stage needs work_d");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = nblocks > 0 ? nblocks : nblocks_for(n);
+  auto run = [&](auto t) -> int {
+    using T = decltype(t);
+    const T *a = static_cast<const T *>(a_d), *c = static_cast<const T *>(b_d);
+    if (variant == Q1_DOT_TWO_STAGE) {
+      hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, a, c, work_d, nullptr);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, work_d, nb, out_d);
+    } else {
+      hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, s, out_d);
+      hipLaunchKernelGGL((k_dot_atomic<T>), dim3(nb), dim3(kRT), 0, s, n, a, c, out_d);
+    }
+    Q1_HIP(hipGetLastError());
+    return Q1_OK;
+  };
+  return dtype == Q1_F64 ? run(double{}) : run(float{});
 }
 
 int q1_fpcg(q1_op *op, q1_precond_fn M, void *ctx, const void *b_d, void *x_d, double rtol,

@@ -172,8 +172,9 @@ __global__ __launch_bounds__(64) void k_apply_tile(
 // One wave's steps of a tile: corners from the staged records, element product,
 // accumulation into LDS.  PAR: every element is known to be a
 // parallelepiped (Laplace kinds), so only corners 0, 1, 2, 4 give geometry.
-// PA: partial assembly, the element's quadrature data qdata[48][coef_stride]
-// replaces its geometry (the staged records then hold the input only).
+// PA: partial assembly, the element's quadrature data (qdata[8 * 6][coef_stride]
+// for the Laplace kinds, qdata[8 * 9][coef_stride] for elasticity) replaces its
+// geometry (the staged records then hold the input only).
 template <typename T, int PH, bool LDS_ATOMIC, bool PAR, bool PA>
 __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nodes,
                                             const T *__restrict__ sR, T *__restrict__ myV,
@@ -223,7 +224,11 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
       for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(UOFF + j) * max_nodes];
     }
     T v[DPN][8];
-    if constexpr (PA) {
+    if constexpr (PA && PH == 3) {
+      const T *qs = qdata + int64_t(s) * kLanes + lane;
+      elasticity_element_pa<T>(
+          [&](int q, int m) { return qs[(q * 9 + m) * coef_stride]; }, u, c0, c1, v);
+    } else if constexpr (PA) {
       const int64_t slot = int64_t(s) * kLanes + lane;
       T qd[8][6];
 #pragma unroll
@@ -416,9 +421,10 @@ __global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__re
 }
 
 // Partial-assembly set-up: the quadrature data of the element in each lane
-// slot (zero for empty slots), stored [48][n_slots] so that a step's loads are
-// contiguous.
-template <typename T>
+// slot (zero for empty slots), stored [8 * NQ][n_slots] so that a step's loads
+// are contiguous: NQ = 6 (Laplace kinds, the cell coefficient folded in) or 9
+// (elasticity, the scaled adjugate; lambda and mu stay per cell).
+template <typename T, int NQ>
 __global__ void k_pa_setup(int64_t n_slots, const int32_t *__restrict__ slot_elem, int64_t ne,
                            int64_t nn, const int32_t *__restrict__ conn,
                            const T *__restrict__ xyz, const T *__restrict__ coef,
@@ -426,12 +432,12 @@ __global__ void k_pa_setup(int64_t n_slots, const int32_t *__restrict__ slot_ele
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n_slots) return;
   const int32_t e = slot_elem[i];
-  T qd[8][6];
+  T qd[8][NQ];
   if (e < 0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int m = 0; m < 6; ++m) qd[q][m] = T(0);
+      for (int m = 0; m < NQ; ++m) qd[q][m] = T(0);
   } else {
     T X[3][8];
 #pragma unroll
@@ -440,12 +446,15 @@ __global__ void k_pa_setup(int64_t n_slots, const int32_t *__restrict__ slot_ele
 #pragma unroll
       for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + g];
     }
-    laplace_qdata<T>(X, coef[e], qd);
+    if constexpr (NQ == 6)
+      laplace_qdata<T>(X, coef[e], qd);
+    else
+      elasticity_qdata<T>(X, qd);
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q)
 #pragma unroll
-    for (int m = 0; m < 6; ++m) qdata[(q * 6 + m) * n_slots + i] = qd[q][m];
+    for (int m = 0; m < NQ; ++m) qdata[(q * NQ + m) * n_slots + i] = qd[q][m];
 }
 
 namespace {
@@ -709,15 +718,17 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
     Q1_HIP(hipMalloc(&d_elem, size_t(n_slots) * sizeof(int32_t)));
     Q1_HIP(hipMemcpy(d_elem, H.step_elem.data(), size_t(n_slots) * sizeof(int32_t),
                      hipMemcpyHostToDevice));
-    const size_t qb = size_t(48) * n_slots * sizeof(T);
+    const int nq = op.physics == Q1_ELASTICITY ? 9 : 6;
+    const size_t qb = size_t(8 * nq) * n_slots * sizeof(T);
     hipError_t e = hipMalloc(&tm.qdata, qb);
     if (e != hipSuccess) {
       (void)hipFree(d_elem);
       return fail(Q1_ENOMEM, "partial assembly: %zu B of quadrature data", qb);
     }
     tm.bytes += qb;
-    hipLaunchKernelGGL((k_pa_setup<T>), dim3(unsigned((n_slots + 255) / 256)), dim3(256), 0, s,
-                       n_slots, d_elem, ne, nn, op.conn, static_cast<const T *>(op.xyz),
+    hipLaunchKernelGGL((nq == 9 ? k_pa_setup<T, 9> : k_pa_setup<T, 6>),
+                       dim3(unsigned((n_slots + 255) / 256)), dim3(256), 0, s, n_slots, d_elem,
+                       ne, nn, op.conn, static_cast<const T *>(op.xyz),
                        static_cast<const T *>(op.coef), static_cast<T *>(tm.qdata));
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -751,10 +762,9 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block) {
     constexpr bool one = std::is_same<T, double>::value;
-    constexpr bool pa_ok = PH != 3;  // partial assembly exists for the Laplace kinds
     const bool allpar = tm.all_affine && !pa;
-    auto kb = pa && pa_ok ? (tm.lds_atomic ? k_apply_block<T, PH, true, one, pa_ok, false>
-                                           : k_apply_block<T, PH, false, one, pa_ok, false>)
+    auto kb = pa          ? (tm.lds_atomic ? k_apply_block<T, PH, true, one, true, false>
+                                           : k_apply_block<T, PH, false, one, true, false>)
               : allpar    ? (tm.lds_atomic ? k_apply_block<T, PH, true, one, false, true>
                                            : k_apply_block<T, PH, false, one, false, true>)
                           : (tm.lds_atomic ? k_apply_block<T, PH, true, one, false, false>

@@ -88,6 +88,10 @@ struct UNetPC {
   Op *op = nullptr;
   double omega = 0.0;
   double *w = nullptr, *z1 = nullptr, *r1 = nullptr, *d = nullptr, *q = nullptr;
+  // schedule: the network on calls 0, period, 2 period, ... since the last
+  // reset; the plain Jacobi step z = w r on the others
+  int period = 1;
+  int64_t calls = 0;
   ~UNetPC() {
     for (void *p : {(void *)in, (void *)out, (void *)kap, (void *)part, (void *)w, (void *)z1,
                     (void *)r1, (void *)d, (void *)q})
@@ -375,6 +379,36 @@ __global__ void k_decode(const float *__restrict__ out, const uint8_t *__restric
   const int x = int(id % (nx + 1)), y = int((id / (nx + 1)) % (ny + 1)),
             zz = int(id / (int64_t(nx + 1) * (ny + 1)));
   z[id] = (mask && mask[id]) ? 0.0 : double(out[(int64_t(zz) * H + y) * W + x]);
+}
+
+// z = w r
+__global__ void k_jacobi_step(int64_t n, const double *__restrict__ w, const double *__restrict__ r,
+                              double *__restrict__ z) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = w[i] * r[i];
+}
+// training pair from an iterate: e = xs - xk (the error)
+__global__ void k_pair_error(int64_t n, const double *__restrict__ xs,
+                             const double *__restrict__ xk, double *__restrict__ e) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) e[i] = xs[i] - xk[i];
+}
+// e -= omega w r (one damped-Jacobi step on the error)
+__global__ void k_pair_smooth(int64_t n, const double *__restrict__ w,
+                              const double *__restrict__ r, double omega,
+                              double *__restrict__ e) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) e[i] -= omega * w[i] * r[i];
+}
+// FP32 copies of the pair
+__global__ void k_pair_store(int64_t n, const double *__restrict__ e,
+                             const double *__restrict__ r, float *__restrict__ eo,
+                             float *__restrict__ ro) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    eo[i] = float(e[i]);
+    ro[i] = float(r[i]);
+  }
 }
 
 __global__ void k_inv(int64_t n, const double *__restrict__ d, double *__restrict__ w) {
@@ -839,6 +873,55 @@ int q1_unet_pc_two_level(q1_unet_pc *pc, q1_op *op, double omega, void *stream) 
   return Q1_OK;
 }
 
+int q1_unet_pc_schedule(q1_unet_pc *pc, int period) {
+  Q1_CHECK(pc && period >= 1, Q1_EINVAL, "q1_unet_pc_schedule: need a context and period >= 1");
+  Q1_CHECK(period == 1 || pc->op, Q1_EINVAL,
+           "q1_unet_pc_schedule: a period above 1 needs the two-level form (its Jacobi weights)");
+  pc->period = period;
+  pc->calls = 0;
+  return Q1_OK;
+}
+
+int q1_unet_pairs(q1_op *op, const double *xstar_d, int npairs, const double *const *xk_d,
+                  double omega, float *const *e_d, float *const *r_d, void *stream) {
+  Q1_CHECK(op && xstar_d && npairs >= 0 && (npairs == 0 || (xk_d && e_d && r_d)), Q1_EINVAL,
+           "q1_unet_pairs: NULL argument");
+  Op &o = *reinterpret_cast<Op *>(op);
+  Q1_CHECK(o.physics == Q1_LAPLACE && o.dtype == Q1_F64, Q1_EINVAL,
+           "q1_unet_pairs: needs an FP64 scalar-Laplace operator");
+  Q1_CHECK(omega >= 0.0 && omega < 2.0, Q1_EINVAL, "q1_unet_pairs: omega %g", omega);
+  for (int i = 0; i < npairs; ++i)
+    Q1_CHECK(xk_d[i] && e_d[i] && r_d[i], Q1_EINVAL, "q1_unet_pairs: NULL vector %d", i);
+  if (npairs == 0) return Q1_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = o.n_nodes;
+  double *ws = nullptr;  // e, r and (with omega) the Jacobi weights
+  Q1_HIP(hipMalloc(&ws, size_t(3 * n) * sizeof(double)));
+  struct Free {
+    double *p;
+    ~Free() { (void)hipFree(p); }
+  } fr{ws};
+  double *e = ws, *r = ws + n, *w = ws + 2 * n;
+  const dim3 g = grid_for(n);
+  int rc;
+  if (omega > 0.0) {
+    if ((rc = launch_diag(o, r, s))) return rc;
+    hipLaunchKernelGGL(k_inv, g, dim3(256), 0, s, n, r, w);
+  }
+  for (int i = 0; i < npairs; ++i) {
+    hipLaunchKernelGGL(k_pair_error, g, dim3(256), 0, s, n, xstar_d, xk_d[i], e);
+    if ((rc = launch_apply(o, e, r, s))) return rc;
+    if (omega > 0.0) {
+      hipLaunchKernelGGL(k_pair_smooth, g, dim3(256), 0, s, n, w, r, omega, e);
+      if ((rc = launch_apply(o, e, r, s))) return rc;
+    }
+    hipLaunchKernelGGL(k_pair_store, g, dim3(256), 0, s, n, e, r, e_d[i], r_d[i]);
+  }
+  Q1_HIP(hipGetLastError());
+  Q1_HIP(hipStreamSynchronize(s));  // the workspace is freed on return
+  return Q1_OK;
+}
+
 int q1_unet_pc_destroy(q1_unet_pc *pc) {
   delete pc;
   return Q1_OK;
@@ -871,6 +954,12 @@ int q1_unet_precond(void *ctx, const void *r_d, void *z_d, void *stream) {
   double *z = static_cast<double *>(z_d);
   const dim3 g = grid_for(pc.nn);
   int rc;
+  const bool net_call = pc.calls++ % pc.period == 0;
+  if (!net_call) {  // the scheduled plain Jacobi step
+    hipLaunchKernelGGL(k_jacobi_step, g, dim3(256), 0, s, pc.nn, pc.w, r, z);
+    Q1_HIP(hipGetLastError());
+    return Q1_OK;
+  }
   if (!pc.op) {  // z = N(r)
     if ((rc = pc_encode(pc, r, pc.in, s))) return rc;
     if ((rc = unet_forward(*pc.net, pc.in, pc.out, 1, s))) return rc;

@@ -1,10 +1,11 @@
 """Training and evaluation of the learned preconditioner.
 
 Every numerical step runs in libq1mf: the Jacobi-PCG solves that generate
-the training pairs (q1_pcg_trace), the operator applies that turn errors
-into residuals, the encoding, the network's forward and backward passes, the
-loss and Adam.  This module only schedules them and keeps the pairs in
-device memory (torch tensors as plain buffers).
+the training pairs (q1_pcg_trace), the pair arithmetic (error, residual and
+smoothing step: q1_unet_pairs), the encoding, the network's forward and
+backward passes, the loss and Adam.  This module only schedules them and keeps
+the pairs in device memory (torch tensors as plain buffers, touched only by
+copies).
 
 Problem family: scalar Laplace on an n^3-element unit-spacing box,
 k = exp(N(0, sigma^2)) iid per cell, u = 0 on the z = 0 face, right-hand side
@@ -27,7 +28,8 @@ import numpy as np
 
 import seeded_inputs as si
 
-from . import Q1_PC_JACOBI, UNet, UNetPrecond, q1_fpcg, q1_op_create, q1_pcg, q1_pcg_trace
+from . import (Q1_PC_JACOBI, UNet, UNetPrecond, q1_fpcg, q1_op_create, q1_pcg, q1_pcg_trace,
+               q1_unet_pairs)
 
 TRAIN_SEED0 = 10000
 EVAL_SEED0 = 90000
@@ -66,15 +68,29 @@ def snapshot_iters(kmax: int, count: int) -> list[int]:
     return sorted(set(int(v) for v in np.concatenate([lo, hi]) if 1 <= v <= kmax))
 
 
+class Field:
+    """What training keeps of a harvested problem: its size, coefficients and mask
+    (the network's coefficient channel and the encoding need nothing else)."""
+
+    def __init__(self, P: Problem):
+        self.n, self.k, self.mask = P.n, P.k, P.mask
+
+
 def harvest(n: int, seeds, per_solve: int, rtol: float = 1e-10, sigma: float = 2.0,
             omega: float | None = 0.6, log=print):
-    """Residual -> error pairs from Jacobi-PCG trajectories.  Returns a dict of
-    device tensors r, e (FP32 [npairs, nn]), field index per pair, and the
-    problems (for the coefficient channel).  With omega, each pair is taken
-    after one damped-Jacobi step, as the two-level preconditioner presents it
-    to the network: e1 = e - omega D^-1 r and r1 = A e1."""
+    """Residual -> error pairs from Jacobi-PCG trajectories, written by the
+    library (q1_unet_pairs) into preallocated FP32 banks on the device.  Returns
+    a dict of the banks r, e ([npairs, nn]), the field index per pair and the
+    fields (for the coefficient channel).  With omega, each pair is taken after
+    one damped-Jacobi step, as the two-level preconditioner presents it to the
+    network: e1 = e - omega D^-1 r and r1 = A e1."""
     import torch
-    probs, rs, es, fld = [], [], [], []
+    nn = (n + 1) ** 3
+    cap = len(seeds) * per_solve
+    rb = torch.empty((cap, nn), dtype=torch.float32, device="cuda")
+    eb = torch.empty((cap, nn), dtype=torch.float32, device="cuda")
+    fld = np.empty(cap, dtype=np.int64)
+    fields, count = [], 0
     t0 = time.perf_counter()
     for j, seed in enumerate(seeds):
         P = Problem(n, seed, sigma)
@@ -83,24 +99,18 @@ def harvest(n: int, seeds, per_solve: int, rtol: float = 1e-10, sigma: float = 2
         its = snapshot_iters(max(1, int(st["iters"] * 0.9)), per_solve)
         snaps = [torch.empty_like(P.b) for _ in its]
         q1_pcg_trace(P.op, Q1_PC_JACOBI, P.b, x, rtol, 100000, its, snaps)
-        if omega is not None:
-            dinv = torch.empty_like(P.b)
-            P.op.diag(dinv)
-            dinv = 1.0 / dinv
-        for s in snaps:
-            e = x - s
-            r = torch.empty_like(e)
-            P.op.apply(e, r)
-            if omega is not None:
-                e = e - omega * dinv * r
-                P.op.apply(e, r)
-            rs.append(r.float())
-            es.append(e.float())
-            fld.append(j)
-        probs.append(P)
+        m = len(its)
+        q1_unet_pairs(P.op, x, snaps, omega or 0.0, [eb[count + i] for i in range(m)],
+                      [rb[count + i] for i in range(m)])
+        fld[count:count + m] = j
+        count += m
+        fields.append(Field(P))
+        P.op.destroy()
+        if (j + 1) % 100 == 0:
+            log(f"harvest: {count} pairs from {j + 1} solves ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
-    log(f"harvest: {len(rs)} pairs from {len(probs)} solves in {time.perf_counter() - t0:.2f} s")
-    return {"r": torch.stack(rs), "e": torch.stack(es), "field": np.array(fld), "probs": probs}
+    log(f"harvest: {count} pairs from {len(fields)} solves in {time.perf_counter() - t0:.2f} s")
+    return {"r": rb[:count], "e": eb[:count], "field": fld[:count], "probs": fields}
 
 
 class Trainer:
@@ -154,14 +164,19 @@ class Trainer:
         return hist, time.perf_counter() - t0
 
 
+VAL_SEED0 = 80000
+
+
 def evaluate(net: UNet, n: int, seeds, rtol: float = 1e-8, sigma: float = 2.0,
              safeguard_m: int = 50, omega: float | None = 0.6, trunc_m: int = 1,
-             smoothing_baseline: bool = False, log=print):
-    """Flexible PCG with the network against Jacobi-PCG on held-out fields:
-    iterations and wall time (every network inference included).  omega:
-    damping of the two-level form's Jacobi smoothing, None for z = N(r).
-    smoothing_baseline: also run the same solver with the network's weights
-    set to zero (the two-level form without its learned correction)."""
+             periods=(1,), smoothing_baseline: bool = False, log=print):
+    """Flexible CG with the network against Jacobi-PCG on held-out fields:
+    iterations and wall time (every network inference included), for each
+    schedule period p (the network on every p-th preconditioner call, the
+    Jacobi step on the others).  omega: damping of the two-level form's Jacobi
+    smoothing, None for z = N(r) (period 1 only).  smoothing_baseline: also run
+    the same solver with the network's weights set to zero (the two-level form
+    without its learned correction)."""
     import torch
     rows = []
     zero = torch.zeros(net.nparams, dtype=torch.float32, device="cuda") if smoothing_baseline else None
@@ -176,22 +191,39 @@ def evaluate(net: UNet, n: int, seeds, rtol: float = 1e-8, sigma: float = 2.0,
         t0 = time.perf_counter()
         sj = q1_pcg(P.op, Q1_PC_JACOBI, P.b, x, rtol, 100000)
         tj = time.perf_counter() - t0
-        q1_fpcg(P.op, pc, P.b, x, rtol, 5, safeguard_m, trunc_m=trunc_m)  # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sn = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m, trunc_m=trunc_m)
-        tn = time.perf_counter() - t0
         row = {"seed": seed, "jacobi_iters": sj["iters"], "jacobi_s": tj,
-               "jacobi_true_rel_res": sj["true_rel_res"], "nn_iters": sn["iters"],
-               "nn_s": tn, "nn_true_rel_res": sn["true_rel_res"],
-               "nn_status": sn["status"], "nn_fallback_at": sn["fallback_at"]}
-        if zero is not None:
-            theta = net.get(0)
-            net.set_params(zero)
-            s0 = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m, trunc_m=trunc_m)
-            net.set_params(theta)
-            row["smoothing_iters"] = s0["iters"]
+               "jacobi_true_rel_res": sj["true_rel_res"], "periods": {}}
+        for per in periods:
+            pc.schedule(per)
+            q1_fpcg(P.op, pc, P.b, x, rtol, 5, safeguard_m, trunc_m=trunc_m)  # warm-up
+            torch.cuda.synchronize()
+            pc.schedule(per)
+            t0 = time.perf_counter()
+            sn = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m, trunc_m=trunc_m)
+            tn = time.perf_counter() - t0
+            r = {"nn_iters": sn["iters"], "nn_s": tn, "nn_true_rel_res": sn["true_rel_res"],
+                 "nn_status": sn["status"], "nn_fallback_at": sn["fallback_at"]}
+            if zero is not None:
+                theta = net.get(0)
+                net.set_params(zero)
+                pc.schedule(per)
+                s0 = q1_fpcg(P.op, pc, P.b, x, rtol, 20000, safeguard_m, trunc_m=trunc_m)
+                net.set_params(theta)
+                r["smoothing_iters"] = s0["iters"]
+            row["periods"][per] = r
+            log(f"eval seed {seed}: Jacobi-PCG {sj['iters']} it {tj * 1e3:.1f} ms | "
+                f"NN-FCG period {per}: {sn['iters']} it {tn * 1e3:.1f} ms "
+                f"(fallback at {sn['fallback_at']})")
         rows.append(row)
-        log(f"eval seed {seed}: Jacobi-PCG {sj['iters']} it {tj * 1e3:.1f} ms | "
-            f"NN-FPCG {sn['iters']} it {tn * 1e3:.1f} ms (fallback at {sn['fallback_at']})")
+        pc.destroy()
+        P.op.destroy()
     return rows
+
+
+def choose_period(net: UNet, n: int, periods, nval: int = 2, trunc_m: int = 8, log=print) -> int:
+    """The schedule period with the least mean wall time on validation fields
+    (seeds 80000 + j, neither training nor held-out fields)."""
+    rows = evaluate(net, n, [VAL_SEED0 + j for j in range(nval)], periods=periods,
+                    trunc_m=trunc_m, log=log)
+    mean = {p: sum(r["periods"][p]["nn_s"] for r in rows) / len(rows) for p in periods}
+    return min(mean, key=mean.get)

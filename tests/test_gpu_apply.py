@@ -76,7 +76,7 @@ def test_brute_force_dense(q1, orc, physics, n, variant):
     assert np.max(np.abs(cols - A)) <= 1e-13 * np.max(np.abs(A))
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS + [6])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_null_spaces(q1, orc, dtype, variant):
     print(f"\n[null spaces] dtype={dtype}", flush=True)
@@ -175,9 +175,9 @@ def test_full_size_vlaplace_sampled(q1, orc, variant):
         assert np.max(np.abs(y)) <= 1e-12 * pr["coef"].max()
 
 
-# -- partial assembly (quadrature data stored at set-up), Laplace kinds ----------
+# -- partial assembly (quadrature data stored at set-up) ----------------------------
 
-PA_CASES = [c for c in CASES if c[0] != 3]
+PA_CASES = CASES
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
@@ -211,11 +211,29 @@ def test_partial_assembly_full_size(q1, orc):
         del op
 
 
-def test_partial_assembly_rejects_elasticity(q1):
-    pr = problem(3, (2, 2, 2), 0.0, 1, mask=False)
-    with pytest.raises(q1.Q1Error) as ei:
-        make_op(pr, 0, 6)
-    assert ei.value.code == -6
+def test_partial_assembly_elasticity_full_size(q1, orc):
+    """96^3 elasticity through partial assembly (the scaled adjugate per point),
+    FP64 and FP32, undistorted and jittered: sampled rows against the oracle's
+    element-by-element rows, and the six rigid-body modes in the kernel of the
+    pure-Neumann operator."""
+    print("\n[partial assembly elasticity 96^3]", flush=True)
+    rng = np.random.default_rng(4)
+    for jitter in (0.0, 0.1):
+        pr = si.problem_elasticity(96, si.seed_for(2), jitter=jitter)
+        nn = pr["xyz"].shape[1]
+        x = si.vec_uniform(3 * nn, si.seed_for(2), si.STREAM_X)
+        rows = np.unique(rng.integers(0, 3 * nn, 3000))
+        ref = orc.apply_rows(3, pr["xyz"], pr["conn"], pr["coef"], pr["mask"], x, rows)
+        prn = dict(pr, mask=None)
+        for dtype in (0, 1):
+            y = gpu_apply(make_op(pr, dtype, 6), x, dtype)
+            assert np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref) <= TOL[dtype], (jitter,
+                                                                                      dtype)
+        opn = make_op(prn, 0, 6)
+        scale = pr["coef"].max() * 8
+        for m in rigid_modes(pr["xyz"]):
+            ym = gpu_apply(opn, m, 0)
+            assert np.max(np.abs(ym)) <= 1e-10 * scale * max(1.0, np.max(np.abs(m)))
 
 
 def test_empty_mesh_and_errors(q1):
@@ -256,8 +274,6 @@ def test_apply_permuted_numbering(q1, orc, physics, variant):
     """Nodes renumbered by a random permutation: tiles are no longer lattices in
     id order, so the block kernels read their corner indices from the planner's
     tables instead of computing them."""
-    if variant == 6 and physics == 3:
-        return
     print(f"\n[permuted numbering] physics={physics} variant={variant}", flush=True)
     pr = problem(physics, (9, 7, 6), 0.1, 47, True)
     nn = pr["xyz"].shape[1]
@@ -292,8 +308,6 @@ def test_unreferenced_node(q1, orc, physics, variant, masked):
     """A node no element references has a zero row: every variant writes y = 0
     there (y = x when masked), whatever y held before; diag 0 (1 if masked)."""
     import torch
-    if variant == 6 and physics == 3:
-        pytest.skip("partial assembly is built for the Laplace kinds only")
     print(f"\n[orphan] physics={physics} variant={variant} masked={masked}", flush=True)
     pr = problem(physics, (6, 5, 4), 0.1, 2308, True)
     dpn = 1 if physics == 1 else 3
@@ -302,7 +316,8 @@ def test_unreferenced_node(q1, orc, physics, variant, masked):
     n2 = pr2["xyz"].shape[1] * dpn
     x2 = si.vec_uniform(n2, 2308, si.STREAM_X)
     x = np.delete(x2, np.arange(k * dpn, (k + 1) * dpn))
-    ref = np.insert(A.matvec(x), k * dpn, x2[k * dpn:(k + 1) * dpn] if masked else 0.0)
+    ref = np.insert(A.matvec(x), k * dpn,
+                    x2[k * dpn:(k + 1) * dpn] if masked else np.zeros(dpn))
     dref = np.insert(A.diag(), k * dpn, np.full(dpn, 1.0 if masked else 0.0))
     op = make_op(pr2, 0, variant)
     xd = dev(x2, torch.float64)

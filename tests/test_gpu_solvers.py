@@ -399,3 +399,40 @@ def test_fused_pcg_limits(q1):
     op32 = make_op(pr, 1, 0)
     with pytest.raises(q1.Q1Error):
         q1.q1_pcg_fused(op32, 1, bd, xd, 1e-8, 100)
+
+
+# -- the dot-product study ------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 255, 4913, 2_146_689])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_dot_variants(q1, n, dtype):
+    """Both dot implementations against an exact-enough host sum (math.fsum of
+    the FP64 products); the two-stage one is bitwise reproducible."""
+    import math
+
+    import torch
+    print(f"\n[dot] n={n} dtype={dtype}", flush=True)
+    a = si.vec_uniform(n, 11, si.STREAM_X)
+    b = si.vec_uniform(n, 12, si.STREAM_X)
+    t = torch_dtype(dtype)
+    ad, bd = dev(a, t), dev(b, t)
+    ah, bh = ad.double().cpu().numpy(), bd.double().cpu().numpy()  # the rounded operands
+    ref = math.fsum(ah * bh)
+    scale = float(np.abs(ah) @ np.abs(bh))
+    work = torch.empty(1024, dtype=torch.float64, device="cuda")
+    outs = []
+    for variant in (q1.Q1_DOT_TWO_STAGE, q1.Q1_DOT_ATOMIC):
+        for nb in (0, 1, 7, 1024):
+            out = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+            q1.q1_dot(ad, bd, out, variant, nb, work)
+            torch.cuda.synchronize()
+            v = float(out.item())
+            assert abs(v - ref) <= 1e-13 * scale + 1e-300, (variant, nb, v, ref)
+            if variant == q1.Q1_DOT_TWO_STAGE and nb == 0:
+                outs.append(v)
+    out = torch.empty((1,), dtype=torch.float64, device="cuda")
+    q1.q1_dot(ad, bd, out, q1.Q1_DOT_TWO_STAGE, 0, work)
+    torch.cuda.synchronize()
+    assert float(out.item()) == outs[0]
+    with pytest.raises(q1.Q1Error):
+        q1.q1_dot(ad, bd, out, q1.Q1_DOT_TWO_STAGE, 1025, work)

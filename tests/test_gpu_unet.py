@@ -335,3 +335,72 @@ def test_two_level_precond(q1, orc):
     zr = z1 + c * d + omega * w * (r1 - c * Ad)
     assert normrel(host(z), zr) <= 2e-3
     assert np.all(host(z)[~free] == 0)
+
+
+def test_two_level_schedule(q1, orc):
+    """With schedule period 3 the context evaluates the network on calls 0, 3, ...
+    and the plain Jacobi step D^-1 r (the oracle's diagonal) on the others."""
+    import torch
+    from helpers import make_op
+    nx, ny, nz = 6, 5, 4
+    xyz, conn = si.box_mesh(nx, ny, nz)
+    k = si.field_lognormal(nx * ny * nz, 0.0, 2.0, 85)
+    mask = si.face_mask(nx, ny, nz, "z0")
+    A = orc.assemble(1, xyz, conn, k[None], mask)
+    r = si.vec_uniform(A.n, 86, si.STREAM_RHS)
+    r[mask == 1] = 0.0
+    net = q1.UNet(8, 8, 8, 1, seed=7)
+    op = make_op(dict(physics=1, xyz=xyz, conn=conn, coef=k[None], mask=mask), 0, 0)
+    pc = q1.UNetPrecond(net, nx, ny, nz, torch.from_numpy(k).cuda(),
+                        torch.from_numpy(mask.astype(np.uint8)).cuda())
+    with pytest.raises(q1.Q1Error):  # a period above 1 needs the two-level form
+        pc.schedule(3)
+    pc.two_level(op, 0.6)
+    rd = torch.from_numpy(r).cuda()
+    outs = []
+    for per in (1, 3):
+        pc.schedule(per)
+        for _ in range(4):
+            z = torch.empty_like(rd)
+            assert q1.lib().q1_unet_precond(pc.handle, q1._dptr(rd), q1._dptr(z),
+                                            q1._stream(None)) == 0
+            outs.append(host(z))
+    net_z = outs[0]
+    assert all(np.array_equal(o, net_z) for o in outs[1:4])  # period 1: the network each call
+    jac = r / A.diag()
+    assert np.array_equal(outs[4], net_z) and np.array_equal(outs[7], net_z)
+    for o in (outs[5], outs[6]):
+        assert np.max(np.abs(o - jac)) <= 1e-15 * np.max(np.abs(jac))
+
+
+def test_unet_pairs(q1, orc):
+    """The training pairs against the oracle: e = x* - x_k, r = A e, then one
+    damped-Jacobi step e1 = e - omega D^-1 r, r1 = A e1 (FP32 outputs)."""
+    import torch
+    from helpers import make_op
+    n = 9
+    xyz, conn = si.box_mesh(n, n, n)
+    k = si.field_lognormal(n ** 3, 0.0, 2.0, 87)
+    mask = si.face_mask(n, n, n, "z0")
+    A = orc.assemble(1, xyz, conn, k[None], mask)
+    b = si.vec_uniform(A.n, 88, si.STREAM_RHS)
+    b[mask == 1] = 0.0
+    op = make_op(dict(physics=1, xyz=xyz, conn=conn, coef=k[None], mask=mask), 0, 0)
+    bd = torch.from_numpy(b).cuda()
+    xs = torch.empty_like(bd)
+    its = [1, 5, 20]
+    snaps = [torch.empty_like(bd) for _ in its]
+    q1.q1_pcg_trace(op, 1, bd, xs, 1e-12, 10000, its, snaps)
+    for omega in (0.0, 0.6):
+        e_out = [torch.empty(A.n, dtype=torch.float32, device="cuda") for _ in its]
+        r_out = [torch.empty_like(e_out[0]) for _ in its]
+        q1.q1_unet_pairs(op, xs, snaps, omega, e_out, r_out)
+        torch.cuda.synchronize()
+        for i in range(len(its)):
+            e = xs.cpu().numpy() - snaps[i].cpu().numpy()
+            r = A.matvec(e)
+            if omega > 0:
+                e = e - omega * r / A.diag()
+                r = A.matvec(e)
+            assert maxrel(host(e_out[i]), e) <= 1e-6
+            assert normrel(host(r_out[i]), r) <= 1e-6
