@@ -175,6 +175,13 @@ int q1_op_diag(q1_op *op, void *d_d, void *stream);
 /* Properties: physics, dtype, variant actually used, n_nodes, n_elems. */
 int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t *n_nodes,
                int64_t *n_elems);
+/* *reproducible = 1 when repeated applies and diagonals of this operator on
+ * identical inputs give bitwise-identical results (the block and partial-
+ * assembly variants on tiles that admit the split accumulation: every node
+ * takes its LDS additions from one wavefront per pass, in a fixed order, and
+ * shared nodes are summed in tile order; no floating-point atomics), else 0
+ * (the atomic scatter variants, and tiles that fall back to LDS atomics). */
+int q1_op_reproducible(const q1_op *op, int *reproducible);
 /* Algorithmic bytes and FLOPs of one apply under the Table 2 convention with
  * perfect caching: 32 B of node ids and the cell coefficients per element;
  * the coordinates plus three vector streams (x read, y read, y write) per

@@ -25,7 +25,7 @@ __all__ = [
     "Q1_V_COLOR", "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
     "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_create_elem", "Q1_HEX8", "Q1_TET4", "Q1_HEX27", "q1_op_apply", "q1_op_diag",
-    "q1_op_info", "q1_op_bytes", "q1_op_destroy", "q1_model_bytes", "Op",
+    "q1_op_info", "q1_op_bytes", "q1_op_reproducible", "q1_op_destroy", "q1_model_bytes", "Op",
     "q1_conv3d_forward", "q1_conv3d_backward_data", "q1_conv3d_backward_weight", "UNet",
     "q1_unet_create", "UNetPrecond", "q1_unet_pc_create", "q1_unet_pairs",
 ]
@@ -143,6 +143,9 @@ class Op:
     def bytes(self):
         return q1_op_bytes(self)
 
+    def reproducible(self) -> bool:
+        return q1_op_reproducible(self)
+
     def destroy(self):
         if self.handle:
             q1_op_destroy(self)
@@ -204,6 +207,12 @@ def q1_op_bytes(op: Op) -> tuple[float, float]:
     b, f = ctypes.c_double(), ctypes.c_double()
     check(lib().q1_op_bytes(op.handle, ctypes.byref(b), ctypes.byref(f)))
     return b.value, f.value
+
+
+def q1_op_reproducible(op: Op) -> bool:
+    r = ctypes.c_int()
+    check(lib().q1_op_reproducible(op.handle, ctypes.byref(r)))
+    return bool(r.value)
 
 
 def q1_op_destroy(op: Op) -> None:

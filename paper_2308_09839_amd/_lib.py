@@ -87,6 +87,7 @@ PROTOTYPES = {
     "q1_op_diag": (c_int, [c_vp, c_vp, c_vp]),
     "q1_op_info": (c_int, [c_vp, P(c_int), P(c_int), P(c_int), P(c_i64), P(c_i64)]),
     "q1_op_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
+    "q1_op_reproducible": (c_int, [c_vp, P(c_int)]),
     "q1_op_destroy": (c_int, [c_vp]),
     "q1_model_bytes": (c_int, [c_int, c_int, c_int, c_int, c_i64, c_i64, c_int, P(c_dbl)]),
     "q1_csr_create": (c_int, [P(c_vp), c_vp, c_vp]),

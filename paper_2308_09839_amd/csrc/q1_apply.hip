@@ -116,9 +116,8 @@ __global__ __launch_bounds__(256) void k_apply_color(
       for (int j = 0; j < DPN; ++j) y[int64_t(nid[a]) * DPN + j] += v[j][a];
 }
 
-// Diagonal of A: d_(a,i) += sum_q w det J [element diagonal entry], i.e.
-// Laplace (every component of the vector Laplace) k |A'^T g'_a|^2 / (512 det'),
-// elasticity ((lambda + mu) t_i^2 + mu |t|^2) / (512 det') with t = A'^T g'_a.
+// Diagonal of A: d_(a,i) += the element diagonal entries (element_diag),
+// added with global atomics (order of additions varies between runs).
 template <typename T, int PH, bool MASKED>
 __global__ __launch_bounds__(256) void k_diag(int64_t ne, int64_t nn,
                                               const T *__restrict__ xyz,
@@ -137,58 +136,13 @@ __global__ __launch_bounds__(256) void k_diag(int64_t ne, int64_t nn,
 #pragma unroll
     for (int r = 0; r < 3; ++r) X[r][a] = xyz[r * nn + nid[a]];
   }
-  butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
-  T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    eval4(X[r][1], X[r][3], X[r][5], X[r][7], Jx[r]);
-    eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);
-    eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);
-  }
-  T acc[8][DPN];
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int i = 0; i < DPN; ++i) acc[a][i] = T(0);
-  const T c0 = coef[e];
-  const T c1 = PH == 3 ? coef[ne + e] : T(0);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
-    const T jx[3] = {Jx[0][iy][iz], Jx[1][iy][iz], Jx[2][iy][iz]};
-    const T jy[3] = {Jy[0][ix][iz], Jy[1][ix][iz], Jy[2][ix][iz]};
-    const T jz[3] = {Jz[0][ix][iy], Jz[1][ix][iy], Jz[2][ix][iy]};
-    T a0[3], a1[3], a2[3];
-    cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
-    const T s = rcp(T(512) * dot3(jx, a0));
-    const T xi = (2 * ix - 1) * C<T>::g, eta = (2 * iy - 1) * C<T>::g,
-            zeta = (2 * iz - 1) * C<T>::g;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const T si = T(2 * (a & 1) - 1), sj = T(2 * ((a >> 1) & 1) - 1),
-              sk = T(2 * ((a >> 2) & 1) - 1);
-      // 8 * reference gradient of phi_a
-      const T g0 = si * (T(1) + sj * eta) * (T(1) + sk * zeta);
-      const T g1 = sj * (T(1) + si * xi) * (T(1) + sk * zeta);
-      const T g2 = sk * (T(1) + si * xi) * (T(1) + sj * eta);
-      T t[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) t[c] = g0 * a0[c] + g1 * a1[c] + g2 * a2[c];
-      const T tt = dot3(t, t);
-      if constexpr (PH != 3) {
-#pragma unroll
-        for (int i = 0; i < DPN; ++i) acc[a][i] += c0 * s * tt;
-      } else {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) acc[a][i] += s * ((c0 + c1) * t[i] * t[i] + c1 * tt);
-      }
-    }
-  }
+  T acc[DPN][8];
+  element_diag<T, PH>(X, coef[e], PH == 3 ? coef[ne + e] : T(0), acc);
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     if (MASKED && mask[nid[a]]) continue;
 #pragma unroll
-    for (int i = 0; i < DPN; ++i) atomic_add(&d[int64_t(nid[a]) * DPN + i], acc[a][i]);
+    for (int i = 0; i < DPN; ++i) atomic_add(&d[int64_t(nid[a]) * DPN + i], acc[i][a]);
   }
 }
 
@@ -380,6 +334,8 @@ int validate_conn(const Op &op, hipStream_t s) {
 
 int launch_diag(Op &op, void *d, hipStream_t s) {
   if (op.elem != Q1_HEX8) return launch_diag_family(op, d, s);
+  if ((op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) && op.tiles.split)
+    return launch_diag_tile(op, d, s);
   return dispatch_phys(op, [&](auto t, auto ph) {
     return diag_impl<decltype(t), decltype(ph)::value>(op, d, s);
   });

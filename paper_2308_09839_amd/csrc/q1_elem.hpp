@@ -695,4 +695,57 @@ __device__ __forceinline__ void element_apply(T X[3][8], const T (*u)[8], T c0, 
     elasticity_element<T>(X, u, c0, c1, v);
 }
 
+// Diagonal entries of the element matrix of kind PH, acc[i][a] for DOF i of
+// node a: sum over the 8 Gauss points of, with t = A'^T g'_a (A' the adjugate
+// of the scaled Jacobian, g'_a = 8 times the reference gradient of phi_a) and
+// det' its determinant, Laplace kinds k |t|^2 / (512 det') (every component),
+// elasticity ((lambda + mu) t_i^2 + mu |t|^2) / (512 det').  X is destroyed.
+template <typename T, int PH>
+__device__ __forceinline__ void element_diag(T X[3][8], T c0, T c1, T (*acc)[8]) {
+  constexpr int DPN = phys_dpn(PH);
+  butterfly_fwd(X[0]); butterfly_fwd(X[1]); butterfly_fwd(X[2]);
+  T Jx[3][2][2], Jy[3][2][2], Jz[3][2][2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    eval4(X[r][1], X[r][3], X[r][5], X[r][7], Jx[r]);
+    eval4(X[r][2], X[r][3], X[r][6], X[r][7], Jy[r]);
+    eval4(X[r][4], X[r][5], X[r][6], X[r][7], Jz[r]);
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int i = 0; i < DPN; ++i) acc[i][a] = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ix = q & 1, iy = (q >> 1) & 1, iz = (q >> 2) & 1;
+    const T jx[3] = {Jx[0][iy][iz], Jx[1][iy][iz], Jx[2][iy][iz]};
+    const T jy[3] = {Jy[0][ix][iz], Jy[1][ix][iz], Jy[2][ix][iz]};
+    const T jz[3] = {Jz[0][ix][iy], Jz[1][ix][iy], Jz[2][ix][iy]};
+    T a0[3], a1[3], a2[3];
+    cross(jy, jz, a0); cross(jz, jx, a1); cross(jx, jy, a2);
+    const T s = rcp(T(512) * dot3(jx, a0));
+    const T xi = (2 * ix - 1) * C<T>::g, eta = (2 * iy - 1) * C<T>::g,
+            zeta = (2 * iz - 1) * C<T>::g;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const T si = T(2 * (a & 1) - 1), sj = T(2 * ((a >> 1) & 1) - 1),
+              sk = T(2 * ((a >> 2) & 1) - 1);
+      const T g0 = si * (T(1) + sj * eta) * (T(1) + sk * zeta);
+      const T g1 = sj * (T(1) + si * xi) * (T(1) + sk * zeta);
+      const T g2 = sk * (T(1) + si * xi) * (T(1) + sj * eta);
+      T t[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t[c] = g0 * a0[c] + g1 * a1[c] + g2 * a2[c];
+      const T tt = dot3(t, t);
+      if constexpr (PH != 3) {
+#pragma unroll
+        for (int i = 0; i < DPN; ++i) acc[i][a] += c0 * s * tt;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[i][a] += s * ((c0 + c1) * t[i] * t[i] + c1 * tt);
+      }
+    }
+  }
+}
+
 }  // namespace q1

@@ -44,6 +44,7 @@ struct TileMap {
   int64_t n_reset = 0;            // shared or Dirichlet nodes, reset before each apply
   int32_t *reset = nullptr;
   bool lds_atomic = false;        // corners collide within a step: accumulate with LDS atomics
+  bool split = false;             // block variants: bitwise-reproducible split accumulation
   bool all_affine = false;        // every tile is a parallelepiped tile
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
   uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16, or 0
@@ -124,6 +125,7 @@ int launch_diag_family(Op &op, void *d, hipStream_t s);
 int validate_conn(const Op &op, hipStream_t s);
 int build_tiles(Op &op, hipStream_t s);
 int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop);
+int launch_diag_tile(Op &op, void *d, hipStream_t s);
 void free_tiles(Op &op);
 int build_colors(Op &op, hipStream_t s);
 void free_colors(Op &op);

@@ -175,6 +175,13 @@ int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t 
   return Q1_OK;
 }
 
+int q1_op_reproducible(const q1_op *op, int *reproducible) {
+  Q1_CHECK(op && reproducible, Q1_EINVAL, "q1_op_reproducible: NULL argument");
+  const bool block = op->variant == Q1_V_BLOCK || op->variant == Q1_V_PA;
+  *reproducible = op->elem == Q1_HEX8 && block && op->tiles.split ? 1 : 0;
+  return Q1_OK;
+}
+
 int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
   Q1_CHECK(op, Q1_EINVAL, "q1_op_bytes: NULL handle");
   const int rb = op->dtype == Q1_F64 ? 8 : 4;

@@ -40,6 +40,24 @@ constexpr int kLanes = 64;
 constexpr uint32_t kSharedBit = 0x80000000u;
 constexpr uint32_t kFixedBit = 0x40000000u;
 constexpr uint32_t kIdMask = 0x3fffffffu;
+// steps per wave of the split accumulation (held in registers): two for the
+// scalar kind's 16 x 8 x 4 tiles, one for the 3-DOF kinds' 16 x 4 x 4
+__host__ __device__ constexpr int split_steps(int dpn) { return dpn == 1 ? 2 : 1; }
+
+// Corner indices of lane `lane` at position `rel` of a lattice tile (the
+// interleaved layout; see lattice_of); false for an empty lane.
+__host__ __device__ inline bool corner_lattice(uint32_t lat, int rel, int lane, int (&lc)[8]) {
+  const int A = int(lat & 0xff), B = int((lat >> 8) & 0xff), spl = int((lat >> 16) & 0xff),
+            C = int(lat >> 24);
+  const int w = rel & 3, k = rel >> 2, kl = k / spl;
+  const int iz = w + 4 * kl, e = (k - kl * spl) * kLanes + lane;
+  if (iz >= C || e >= A * B) return false;
+  const int a1 = A + 1, ab1 = (A + 1) * (B + 1);
+  const int base = e % A + a1 * (e / A) + ab1 * iz;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) lc[a] = base + (a & 1) + a1 * ((a >> 1) & 1) + ab1 * (a >> 2);
+  return true;
+}
 
 __device__ __forceinline__ int xcd_block_t(int bid, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
@@ -169,12 +187,64 @@ __global__ __launch_bounds__(64) void k_apply_tile(
 // tile's steps w, w + 4, ... and accumulates into LDS: in FP64 into one copy
 // shared by the four waves (LDS atomics), in FP32 into its own copy, the copies
 // being added in a fixed order when the tile's nodes are written.
-// One wave's steps of a tile: corners from the staged records, element product,
-// accumulation into LDS.  PAR: every element is known to be a
-// parallelepiped (Laplace kinds), so only corners 0, 1, 2, 4 give geometry.
-// PA: partial assembly, the element's quadrature data (qdata[8 * 6][coef_stride]
-// for the Laplace kinds, qdata[8 * 9][coef_stride] for elasticity) replaces its
-// geometry (the staged records then hold the input only).
+// One element step of a wave: corners from the staged records, element
+// product.  PAR: the element is known to be a parallelepiped, so only corners
+// 0, 1, 2, 4 give geometry.  PA: partial assembly, the element's quadrature
+// data (qdata[8 * 6][coef_stride] for the Laplace kinds, qdata[8 * 9][coef_stride]
+// for elasticity) replaces its geometry (the staged records then hold the
+// input only).  Returns false for an empty lane.
+template <typename T, int PH, bool PAR, bool PA>
+__device__ __forceinline__ bool step_element(int s, int lane, int max_nodes,
+                                             const T *__restrict__ sR, uint4 pk, T c0, T c1,
+                                             int64_t coef_stride, const T *__restrict__ qdata,
+                                             uint32_t lat, int s_first, int (&lc)[8],
+                                             T (&v)[phys_dpn(PH)][8]) {
+  constexpr int DPN = phys_dpn(PH);
+  constexpr int UOFF = PA ? 0 : 3;  // first input field of a staged record
+  if (lat) {  // lattice tile: corner indices from (step, lane), no corner-index loads
+    if (!corner_lattice(lat, s - s_first, lane, lc)) return false;
+  } else {
+    if (pk.x == 0xffffffffu) return false;
+    lc[0] = int(pk.x & 0xffff); lc[1] = int(pk.x >> 16);
+    lc[2] = int(pk.y & 0xffff); lc[3] = int(pk.y >> 16);
+    lc[4] = int(pk.z & 0xffff); lc[5] = int(pk.z >> 16);
+    lc[6] = int(pk.w & 0xffff); lc[7] = int(pk.w >> 16);
+  }
+  T X[3][8], u[DPN][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T *r = sR + lc[a];
+    if (!PA && (!PAR || a == 0 || a == 1 || a == 2 || a == 4)) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) X[k][a] = r[size_t(k) * max_nodes];
+    }
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(UOFF + j) * max_nodes];
+  }
+  if constexpr (PA && PH == 3) {
+    const T *qs = qdata + int64_t(s) * kLanes + lane;
+    elasticity_element_pa<T>(
+        [&](int q, int m) { return qs[(q * 9 + m) * coef_stride]; }, u, c0, c1, v);
+  } else if constexpr (PA) {
+    const int64_t slot = int64_t(s) * kLanes + lane;
+    T qd[8][6];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int m = 0; m < 6; ++m) qd[q][m] = qdata[(q * 6 + m) * coef_stride + slot];
+    laplace_element_pa_n<T, DPN>(qd, u, v);
+  } else if constexpr (PAR && PH != 3) {
+    laplace_element_parallelepiped_n<T, DPN>(X, u, c0, v);
+  } else if constexpr (PAR) {
+    elasticity_element_parallelepiped<T>(X, u, c0, c1, v);
+  } else {
+    element_apply<T, PH>(X, u, c0, c1, v);
+  }
+  return true;
+}
+
+// A wave's steps s, s + 4, ... < s1 of a tile, each added into the LDS
+// accumulator myV at once (LDS_ATOMIC: with LDS atomics).
 template <typename T, int PH, bool LDS_ATOMIC, bool PAR, bool PA>
 __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nodes,
                                             const T *__restrict__ sR, T *__restrict__ myV,
@@ -184,10 +254,6 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
                                             const T *__restrict__ qdata, uint32_t lat,
                                             int s_first) {
   constexpr int DPN = phys_dpn(PH);
-  constexpr int UOFF = PA ? 0 : 3;  // first input field of a staged record
-  // lattice tile: corner indices from (step, lane), no corner-index loads
-  const int LA = int(lat & 0xff), LB = int((lat >> 8) & 0xff), spl = int(lat >> 16);
-  const int a1 = LA + 1, ab1 = (LA + 1) * (LB + 1);
   // pk_n, c0_n, c1_n: this wave's first step, loaded by the caller before staging
   for (; s < s1; s += 4) {
     const uint4 pk = pk_n;
@@ -199,50 +265,10 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
       if constexpr (PH == 3) c1_n = coef_t[coef_stride + slot];
     }
     int lc[8];
-    if (lat) {
-      const int rel = s - s_first, iz = rel / spl, e = (rel - iz * spl) * kLanes + lane;
-      if (e >= LA * LB) continue;  // empty lane
-      const int base = e % LA + a1 * (e / LA + (LB + 1) * iz);
-#pragma unroll
-      for (int a = 0; a < 8; ++a) lc[a] = base + (a & 1) + a1 * ((a >> 1) & 1) + ab1 * (a >> 2);
-    } else {
-      if (pk.x == 0xffffffffu) continue;  // empty lane
-      lc[0] = int(pk.x & 0xffff); lc[1] = int(pk.x >> 16);
-      lc[2] = int(pk.y & 0xffff); lc[3] = int(pk.y >> 16);
-      lc[4] = int(pk.z & 0xffff); lc[5] = int(pk.z >> 16);
-      lc[6] = int(pk.w & 0xffff); lc[7] = int(pk.w >> 16);
-    }
-    T X[3][8], u[DPN][8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const T *r = sR + lc[a];
-      if (!PA && (!PAR || a == 0 || a == 1 || a == 2 || a == 4)) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) X[k][a] = r[size_t(k) * max_nodes];
-      }
-#pragma unroll
-      for (int j = 0; j < DPN; ++j) u[j][a] = r[size_t(UOFF + j) * max_nodes];
-    }
     T v[DPN][8];
-    if constexpr (PA && PH == 3) {
-      const T *qs = qdata + int64_t(s) * kLanes + lane;
-      elasticity_element_pa<T>(
-          [&](int q, int m) { return qs[(q * 9 + m) * coef_stride]; }, u, c0, c1, v);
-    } else if constexpr (PA) {
-      const int64_t slot = int64_t(s) * kLanes + lane;
-      T qd[8][6];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int m = 0; m < 6; ++m) qd[q][m] = qdata[(q * 6 + m) * coef_stride + slot];
-      laplace_element_pa_n<T, DPN>(qd, u, v);
-    } else if constexpr (PAR && PH != 3) {
-      laplace_element_parallelepiped_n<T, DPN>(X, u, c0, v);
-    } else if constexpr (PAR) {
-      elasticity_element_parallelepiped<T>(X, u, c0, c1, v);
-    } else {
-      element_apply<T, PH>(X, u, c0, c1, v);
-    }
+    if (!step_element<T, PH, PAR, PA>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride, qdata,
+                                      lat, s_first, lc, v))
+      continue;
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -250,12 +276,85 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
   }
 }
 
-// ONEACC: the four waves add into one LDS accumulator with LDS atomics (FP64,
-// where it frees LDS for a fourth resident block); otherwise each wave owns a
-// copy and the copies are summed in a fixed order.
+// The split accumulation (bitwise reproducible; the planner's split_ok): the
+// wave's steps s0 + w + 4k, k < split_steps(dpn), add their lower corners (a < 4)
+// into sV at once and keep the upper ones in registers; after a barrier of
+// the whole workgroup they are added in the same order.  All four waves call
+// this (it contains the barrier).  par_tile: the tile's elements are all
+// parallelepipeds (taken only where PAR_OK; GEN_OK: the general element is
+// compiled in).
+template <typename T, int PH, bool PAR_OK, bool GEN_OK, bool PA>
+__device__ __forceinline__ void block_steps_split(int s0, int s1, int w, int lane, int max_nodes,
+                                                  const T *__restrict__ sR, T *__restrict__ sV,
+                                                  const uint4 *__restrict__ lconn,
+                                                  const T *__restrict__ coef_t,
+                                                  int64_t coef_stride, uint4 pk_n, T c0_n, T c1_n,
+                                                  const T *__restrict__ qdata, uint32_t lat,
+                                                  bool par_tile) {
+  constexpr int DPN = phys_dpn(PH);
+  constexpr int kSplitSteps = split_steps(DPN);
+  T hold[kSplitSteps][4][DPN];
+  int hidx[kSplitSteps][4];
+#pragma unroll
+  for (int k = 0; k < kSplitSteps; ++k) {
+    const int s = s0 + w + 4 * k;
+    const uint4 pk = pk_n;
+    const T c0 = c0_n, c1 = c1_n;
+    if (k + 1 < kSplitSteps && s + 4 < s1) {  // prefetch the wave's next step
+      const int64_t slot = int64_t(s + 4) * kLanes + lane;
+      if (!lat) pk_n = lconn[slot];
+      c0_n = coef_t[slot];
+      if constexpr (PH == 3) c1_n = coef_t[coef_stride + slot];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) hidx[k][a] = -1;
+    if (s >= s1) continue;
+    int lc[8];
+    T v[DPN][8];
+    bool live;
+    if constexpr (PA)
+      live = step_element<T, PH, false, true>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
+                                              qdata, lat, s0, lc, v);
+    else if constexpr (!GEN_OK)
+      live = step_element<T, PH, true, false>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
+                                              qdata, lat, s0, lc, v);
+    else if (PAR_OK && par_tile)
+      live = step_element<T, PH, true, false>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
+                                              qdata, lat, s0, lc, v);
+    else
+      live = step_element<T, PH, false, false>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
+                                               qdata, lat, s0, lc, v);
+    if (!live) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) sV[j * max_nodes + lc[a]] += v[j][a];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      hidx[k][a] = lc[4 + a];
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) hold[k][a][j] = v[j][4 + a];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSplitSteps; ++k)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (hidx[k][a] >= 0)
+#pragma unroll
+        for (int j = 0; j < DPN; ++j) sV[j * max_nodes + hidx[k][a]] += hold[k][a][j];
+}
+
+// Accumulation modes of the block kernel: kAccSplit, one LDS accumulator
+// filled in two race-free passes (bitwise reproducible; every tile must pass
+// split_ok); kAccShared, one accumulator that the four waves add into with
+// LDS atomics (FP64 fallback: order of additions varies); kAccCopies, one
+// copy per wave, the copies summed in a fixed order (FP32 fallback).
 // ALLPAR: every tile of the operator is a parallelepiped tile (flagged at
 // set-up), so only the parallelepiped element is compiled in (fewer registers).
-template <typename T, int PH, bool LDS_ATOMIC, bool ONEACC, bool PA, bool ALLPAR>
+constexpr int kAccSplit = 0, kAccShared = 1, kAccCopies = 2;
+template <typename T, int PH, bool LDS_ATOMIC, int ACC, bool PA, bool ALLPAR>
 __global__ __launch_bounds__(256) void k_apply_block(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
@@ -271,6 +370,7 @@ __global__ __launch_bounds__(256) void k_apply_block(
   constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][max_nodes]
+  constexpr bool ONEACC = ACC != kAccCopies;
   constexpr int NACC = ONEACC ? 1 : 4;
   T *sV = sR + size_t(NR) * max_nodes;       // [NACC][DPN][max_nodes]
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -331,20 +431,24 @@ __global__ __launch_bounds__(256) void k_apply_block(
     }
   }
   __syncthreads();
-  T *myV = ONEACC ? sV : sV + size_t(w) * DPN * max_nodes;
-  if constexpr (ALLPAR && !PA) {
-    block_steps<T, PH, LDS_ATOMIC || ONEACC, true, false>(s0 + w, s1, lane, max_nodes, sR, myV,
-                                                          lconn, coef_t, coef_stride, pk0, c00,
-                                                          c10, qdata, lat, s0);
+  if constexpr (ACC == kAccSplit) {
+    block_steps_split<T, PH, !PA, !ALLPAR, PA>(s0, s1, w, lane, max_nodes, sR, sV, lconn,
+                                               coef_t, coef_stride, pk0, c00, c10, qdata, lat,
+                                               !PA && !ALLPAR && tile_affine[tile]);
   } else {
-    if (!PA && tile_affine[tile])
-      block_steps<T, PH, LDS_ATOMIC || ONEACC, true, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
-                                                         lconn, coef_t, coef_stride, pk0, c00,
-                                                         c10, qdata, lat, s0);
-    else
-      block_steps<T, PH, LDS_ATOMIC || ONEACC, false, PA>(s0 + w, s1, lane, max_nodes, sR, myV,
-                                                          lconn, coef_t, coef_stride, pk0, c00,
-                                                          c10, qdata, lat, s0);
+    constexpr bool AT = LDS_ATOMIC || ACC == kAccShared;
+    T *myV = ONEACC ? sV : sV + size_t(w) * DPN * max_nodes;
+    if constexpr (ALLPAR && !PA) {
+      block_steps<T, PH, AT, true, false>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+                                          coef_stride, pk0, c00, c10, qdata, lat, s0);
+    } else {
+      if (!PA && tile_affine[tile])
+        block_steps<T, PH, AT, true, PA>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+                                         coef_stride, pk0, c00, c10, qdata, lat, s0);
+      else
+        block_steps<T, PH, AT, false, PA>(s0 + w, s1, lane, max_nodes, sR, myV, lconn, coef_t,
+                                          coef_stride, pk0, c00, c10, qdata, lat, s0);
+    }
   }
   __syncthreads();
   // nodes of this tile only: y; nodes shared with other tiles: this tile's halo
@@ -372,8 +476,101 @@ __global__ __launch_bounds__(256) void k_apply_block(
   for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, nodes[n0 + i], slot[n0 + i]);
 }
 
+// Diagonal of A on the block variants' tiles with the split accumulation
+// (bitwise reproducible): one workgroup per tile stages the coordinates,
+// each element's diagonal entries (element_diag) are added into LDS in the
+// two race-free passes of the apply, and the tile's nodes are written like
+// the apply's (tile-private nodes to d, shared ones to halo slots summed by
+// k_halo_sum, which writes 1 on Dirichlet nodes).
+template <typename T, int PH>
+__global__ __launch_bounds__(256) void k_diag_block(
+    int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
+    const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
+    const uint4 *__restrict__ lconn, const T *__restrict__ coef_t, int64_t coef_stride,
+    const T *__restrict__ xyz, T *__restrict__ d, const int32_t *__restrict__ slot,
+    T *__restrict__ halo, const uint32_t *__restrict__ tile_lat) {
+  constexpr int DPN = phys_dpn(PH);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sR = reinterpret_cast<T *>(smem_raw);  // [3][max_nodes]
+  T *sV = sR + size_t(3) * max_nodes;       // [DPN][max_nodes]
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tile = blockIdx.x;
+  const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
+  const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
+  const uint32_t lat = tile_lat[tile];
+  for (int i = tid; i < nm; i += 256) {
+    const int64_t g = nodes[n0 + i] & kIdMask;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) sR[size_t(r) * max_nodes + i] = xyz[r * nn + g];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) sV[size_t(j) * max_nodes + i] = T(0);
+  }
+  __syncthreads();
+  constexpr int kSplitSteps = split_steps(DPN);
+  T hold[kSplitSteps][4][DPN];
+  int hidx[kSplitSteps][4];
+#pragma unroll
+  for (int k = 0; k < kSplitSteps; ++k) {
+    const int s = s0 + w + 4 * k;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) hidx[k][a] = -1;
+    if (s >= s1) continue;
+    const int64_t sl = int64_t(s) * kLanes + lane;
+    int lc[8];
+    if (lat) {
+      if (!corner_lattice(lat, s - s0, lane, lc)) continue;
+    } else {
+      const uint4 pk = lconn[sl];
+      if (pk.x == 0xffffffffu) continue;
+      lc[0] = int(pk.x & 0xffff); lc[1] = int(pk.x >> 16);
+      lc[2] = int(pk.y & 0xffff); lc[3] = int(pk.y >> 16);
+      lc[4] = int(pk.z & 0xffff); lc[5] = int(pk.z >> 16);
+      lc[6] = int(pk.w & 0xffff); lc[7] = int(pk.w >> 16);
+    }
+    T X[3][8], v[DPN][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) X[r][a] = sR[size_t(r) * max_nodes + lc[a]];
+    element_diag<T, PH>(X, coef_t[sl], PH == 3 ? coef_t[coef_stride + sl] : T(0), v);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) sV[j * max_nodes + lc[a]] += v[j][a];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      hidx[k][a] = lc[4 + a];
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) hold[k][a][j] = v[j][4 + a];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSplitSteps; ++k)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (hidx[k][a] >= 0)
+#pragma unroll
+        for (int j = 0; j < DPN; ++j) sV[j * max_nodes + hidx[k][a]] += hold[k][a][j];
+  __syncthreads();
+  for (int i = tid; i < nm; i += 256) {
+    const uint32_t raw = nodes[n0 + i];
+    if (raw & kFixedBit) continue;
+    const int64_t g = raw & kIdMask;
+    const int32_t sl = slot[n0 + i];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) {
+      const T v = sV[size_t(j) * max_nodes + i];
+      if (raw & kSharedBit)
+        halo[int64_t(sl) * DPN + j] = v;
+      else
+        d[g * DPN + j] = v;
+    }
+  }
+}
+
 // Second pass of the block variant over the reset list: y = x on Dirichlet
-// nodes, 0 on nodes that no element references, otherwise the sum of the
+// nodes (1 when x is NULL: the diagonal), 0 on nodes that no element references, otherwise the sum of the
 // node's halo slots in tile order (slots j and
 // n + j, then the extra slots of edge and corner nodes), so every entry of y
 // is written exactly once.  Each thread takes kHaloNpt nodes (a block's nodes
@@ -416,7 +613,7 @@ __global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__re
     const int64_t g = h[p] & 0x3fffffff;
 #pragma unroll
     for (int c = 0; c < DPN; ++c)
-      y[g * DPN + c] = fixed ? x[g * DPN + c] : orphan ? T(0) : acc[p][c];
+      y[g * DPN + c] = fixed ? (x ? x[g * DPN + c] : T(1)) : orphan ? T(0) : acc[p][c];
   }
 }
 
@@ -469,14 +666,17 @@ struct HostTiles {
   std::vector<uint8_t> tile_affine;  // every element of the tile is a parallelepiped
   std::vector<int32_t> slot, hptr, hnode;  // halo slots of the block variant
   std::vector<uint32_t> tile_lat;    // lattice description of each tile (0: none)
+  bool split = true;                 // every tile admits the split accumulation
 };
 
 // Lattice tiles: the tile's elements form an A x B x C brick, its node list is
-// the (A+1) x (B+1) x (C+1) lattice in x-fastest order, and its steps take
-// each layer's A*B elements x-fastest in runs of 64 (spl steps per layer).
-// Then the corner indices of lane l in step s follow from (s, l) alone and the
-// kernel computes them instead of loading them.  Returns A | B << 8 | spl << 16
-// when every element, corner and empty lane of tile t matches, else 0.
+// the (A+1) x (B+1) x (C+1) lattice in x-fastest order, and each layer's A*B
+// elements are taken x-fastest in runs of 64 (spl steps per layer) in the
+// interleaved layout (layer l on wave l mod 4, wave w's k-th step at position
+// 4k + w).  Then the corner indices of lane l at position p follow from (p, l)
+// alone (corner_lattice) and the kernel computes them instead of loading
+// them.  Returns A | B << 8 | spl << 16 | C << 24 when every element, corner
+// and empty lane of tile t matches, else 0.
 uint32_t lattice_of(const HostTiles &H, int t) {
   const int s0 = H.tile_step[t], s1 = H.tile_step[t + 1];
   const int nm = H.node_ptr[t + 1] - H.node_ptr[t];
@@ -487,29 +687,57 @@ uint32_t lattice_of(const HostTiles &H, int t) {
   const int A = a1 - 1, B = ab1 / a1 - 1;
   if (A > 255 || B > 255) return 0;
   const int spl = (A * B + kLanes - 1) / kLanes;
-  if ((s1 - s0) % spl || spl > 255) return 0;
-  const int C = (s1 - s0) / spl;
-  if (nm != a1 * (B + 1) * (C + 1)) return 0;
+  if (nm % ab1) return 0;
+  const int C = nm / ab1 - 1;
+  if (spl > 255 || C < 1 || C > 255) return 0;
+  if (s1 - s0 != 4 * spl * ((C + 3) / 4)) return 0;
+  const uint32_t lat = uint32_t(A) | uint32_t(B) << 8 | uint32_t(spl) << 16 | uint32_t(C) << 24;
   for (int s = s0; s < s1; ++s)
     for (int l = 0; l < kLanes; ++l) {
       const uint16_t *lc = &H.lconn[(size_t(s) * kLanes + l) * 8];
-      const int rel = s - s0, iz = rel / spl, e = (rel - iz * spl) * kLanes + l;
-      if (e >= A * B) {
+      int want[8];
+      if (!corner_lattice(lat, s - s0, l, want)) {
         if (lc[0] != 0xffff) return 0;
         continue;
       }
-      const int base = e % A + a1 * (e / A + (B + 1) * iz);
       for (int a = 0; a < 8; ++a)
-        if (lc[a] != base + (a & 1) + a1 * ((a >> 1) & 1) + ab1 * (a >> 2)) return 0;
+        if (lc[a] != want[a]) return 0;
     }
-  return uint32_t(A) | uint32_t(B) << 8 | uint32_t(spl) << 16;
+  return lat;
+}
+
+// The split accumulation of the block variants (bitwise reproducible): in a
+// first pass every wave adds the lower corners (local a = 0..3) of its
+// elements into the tile's LDS accumulator, in a second pass (after a
+// barrier) the upper corners (a = 4..7), which it kept in registers.  Each
+// pass is race-free, and its order fixed, when every node of the tile receives
+// lower-corner additions from one wave at most and upper-corner additions
+// from one wave at most, a wave has at most split_steps(dpn) steps (its registers),
+// and no two lanes of a step share a node at one corner (checked separately).
+bool split_ok(const HostTiles &H, int t, int nm, int dpn) {
+  const int s0 = H.tile_step[t], s1 = H.tile_step[t + 1];
+  if (s1 - s0 > 4 * split_steps(dpn)) return false;
+  std::vector<int8_t> lo(nm, -1), hi(nm, -1);
+  for (int s = s0; s < s1; ++s) {
+    const int8_t w = int8_t((s - s0) & 3);
+    for (int l = 0; l < kLanes; ++l) {
+      const uint16_t *lc = &H.lconn[(size_t(s) * kLanes + l) * 8];
+      if (lc[0] == 0xffff) continue;
+      for (int a = 0; a < 8; ++a) {
+        int8_t &o = a < 4 ? lo[lc[a]] : hi[lc[a]];
+        if (o >= 0 && o != w) return false;
+        o = w;
+      }
+    }
+  }
+  return true;
 }
 
 // Group elements into tiles and steps; record node lists and corner indices.
 template <typename T>
 int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
                const std::vector<uint8_t> &mask, int64_t nn, int64_t ne, int patch_x,
-               int patch_y, int layers, HostTiles &H) {
+               int patch_y, int layers, bool interleave, int dpn, HostTiles &H) {
   std::vector<double> cen(size_t(3) * ne);
   double lo[3] = {1e300, 1e300, 1e300};
   for (int64_t e = 0; e < ne; ++e)
@@ -587,28 +815,54 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
       H.nodes.push_back(v);
     }
     H.node_ptr.push_back(int32_t(H.nodes.size()));
-    for (int64_t j = tb[t]; j < tb[t + 1];) {
+    // steps: runs of one layer, at most 64 elements; (first, end, layer) with
+    // the layer counted within the tile
+    struct Run {
+      int64_t j, je;
+      int layer;
+    };
+    std::vector<Run> runs;
+    for (int64_t j = tb[t], layer = -1; j < tb[t + 1];) {
       int64_t je = j;
       while (je < tb[t + 1] && lz[order[je]] == lz[order[j]] && je - j < kLanes) ++je;
+      if (j == tb[t] || lz[order[j]] != lz[order[j - 1]]) ++layer;
+      runs.push_back({j, je, int(layer)});
       for (int a = 0; a < 8 && !H.corner_collision; ++a) {
         std::vector<int32_t> cs;
         for (int64_t k = j; k < je; ++k) cs.push_back(conn[a * ne + order[k]]);
         std::sort(cs.begin(), cs.end());
         H.corner_collision = std::adjacent_find(cs.begin(), cs.end()) != cs.end();
       }
-      for (int64_t k = j; k < j + kLanes; ++k) {
-        if (k < je) {
-          H.step_elem.push_back(order[k]);
-          for (int a = 0; a < 8; ++a) H.lconn.push_back(uint16_t(local[conn[a * ne + order[k]]]));
+      j = je;
+    }
+    // interleaved layout (block variants): the steps of layer l belong to
+    // wave l mod 4, and wave w's k-th step sits at position 4k + w (padded
+    // with empty steps)
+    std::vector<int> pos_run;  // run of each position, -1 = empty step
+    if (interleave) {
+      std::vector<int> per_wave[4];
+      for (size_t r = 0; r < runs.size(); ++r) per_wave[runs[r].layer & 3].push_back(int(r));
+      size_t kmax = 0;
+      for (auto &v : per_wave) kmax = std::max(kmax, v.size());
+      for (size_t k = 0; k < kmax; ++k)
+        for (int w = 0; w < 4; ++w) pos_run.push_back(k < per_wave[w].size() ? per_wave[w][k] : -1);
+    } else {
+      for (size_t r = 0; r < runs.size(); ++r) pos_run.push_back(int(r));
+    }
+    for (int r : pos_run)
+      for (int64_t k = 0; k < kLanes; ++k) {
+        if (r >= 0 && runs[r].j + k < runs[r].je) {
+          const int32_t e = order[runs[r].j + k];
+          H.step_elem.push_back(e);
+          for (int a = 0; a < 8; ++a) H.lconn.push_back(uint16_t(local[conn[a * ne + e]]));
         } else {
           H.step_elem.push_back(-1);
           for (int a = 0; a < 8; ++a) H.lconn.push_back(0xffff);
         }
       }
-      j = je;
-    }
     H.tile_step.push_back(int32_t(H.step_elem.size() / kLanes));
-    H.tile_lat.push_back(lattice_of(H, t));
+    H.tile_lat.push_back(interleave ? lattice_of(H, t) : 0u);
+    if (interleave && !split_ok(H, t, int(list.size()), dpn)) H.split = false;
     bool aff = true;  // the kernel's own exact test, in the operator's precision
     for (int64_t k = tb[t]; k < tb[t + 1] && aff; ++k) {
       T X[3][8];
@@ -673,7 +927,8 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   for (size_t i = 0; i < conn.size(); ++i)
     Q1_CHECK(conn[i] >= 0 && conn[i] < nn, Q1_EINVAL, "connectivity entry %zu out of range", i);
   HostTiles H;
-  int rc = plan_tiles<T>(conn, xyz, mask, nn, ne, patch_x, patch_y, layers, H);
+  const bool block = op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA;
+  int rc = plan_tiles<T>(conn, xyz, mask, nn, ne, patch_x, patch_y, layers, block, op.dpn(), H);
   if (rc) return rc;
   const int64_t n_slots = int64_t(H.step_elem.size());
   std::vector<T> coef_t(size_t(ncoef) * n_slots, T(0));
@@ -686,6 +941,7 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   tm.n_reset = int64_t(H.reset.size());
   tm.n_entries = int64_t(H.nodes.size());
   tm.lds_atomic = H.corner_collision;
+  tm.split = block && H.split && !H.corner_collision;
   tm.all_affine = std::all_of(H.tile_affine.begin(), H.tile_affine.end(),
                               [](uint8_t a) { return a != 0; });
   auto up = [&](auto **dst, const auto &v) -> int {
@@ -743,7 +999,7 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
 // one per wave for FP32)
 size_t block_lds_bytes(const Op &op) {
   const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
-  const size_t nacc = op.dtype == Q1_F64 ? 1 : 4;
+  const size_t nacc = op.tiles.split || op.dtype == Q1_F64 ? 1 : 4;
   const size_t ncoord = op.variant == Q1_V_PA ? 0 : 3;
   return size_t(op.tiles.max_nodes) * rb * size_t(ncoord + op.dpn() + nacc * op.dpn());
 }
@@ -761,14 +1017,18 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
                        s, tm.n_reset, tm.reset, op.mask, x, y, stop);
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block) {
-    constexpr bool one = std::is_same<T, double>::value;
+    // fallback accumulation when some tile does not admit the split one
+    constexpr int FB = std::is_same<T, double>::value ? kAccShared : kAccCopies;
     const bool allpar = tm.all_affine && !pa;
-    auto kb = pa          ? (tm.lds_atomic ? k_apply_block<T, PH, true, one, true, false>
-                                           : k_apply_block<T, PH, false, one, true, false>)
-              : allpar    ? (tm.lds_atomic ? k_apply_block<T, PH, true, one, false, true>
-                                           : k_apply_block<T, PH, false, one, false, true>)
-                          : (tm.lds_atomic ? k_apply_block<T, PH, true, one, false, false>
-                                           : k_apply_block<T, PH, false, one, false, false>);
+    auto pick = [&](auto pa_c, auto allpar_c) {
+      constexpr bool P = decltype(pa_c)::value, AP = decltype(allpar_c)::value;
+      return tm.split        ? k_apply_block<T, PH, false, kAccSplit, P, AP>
+             : tm.lds_atomic ? k_apply_block<T, PH, true, FB, P, AP>
+                             : k_apply_block<T, PH, false, FB, P, AP>;
+    };
+    using tt = std::true_type;
+    using ff = std::false_type;
+    auto kb = pa ? pick(tt{}, ff{}) : allpar ? pick(ff{}, tt{}) : pick(ff{}, ff{});
     hipLaunchKernelGGL(kb, dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes, op.n_nodes,
                        tm.node_ptr, tm.nodes, tm.tile_step,
                        reinterpret_cast<const uint4 *>(tm.lconn),
@@ -841,6 +1101,34 @@ int build_tiles(Op &op, hipStream_t s) {
                          : size_t(op.tiles.max_nodes) * (op.dpn() * (op.dtype == Q1_F64 ? 8 : 4) + 4);
   Q1_CHECK(lds <= 64 * 1024, Q1_EUNSUPPORTED, "tile needs %zu B of LDS", lds);
   return Q1_OK;
+}
+
+// The diagonal through the tiles (block variants whose tiles admit the split
+// accumulation; Q1_EUNSUPPORTED otherwise).
+int launch_diag_tile(Op &op, void *dv, hipStream_t s) {
+  const TileMap &tm = op.tiles;
+  const bool block = op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA;
+  Q1_CHECK(block && tm.split, Q1_EUNSUPPORTED, "tile diagonal needs the split accumulation");
+  return dispatch_phys(op, [&](auto t, auto ph) -> int {
+    using T = decltype(t);
+    constexpr int PH = decltype(ph)::value;
+    constexpr int DPN = phys_dpn(PH);
+    T *d = static_cast<T *>(dv);
+    const size_t lds = size_t(tm.max_nodes) * sizeof(T) * (3 + DPN);
+    hipLaunchKernelGGL((k_diag_block<T, PH>), dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes,
+                       op.n_nodes, tm.node_ptr, tm.nodes, tm.tile_step,
+                       reinterpret_cast<const uint4 *>(tm.lconn),
+                       static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
+                       static_cast<const T *>(op.xyz), d, tm.slot, static_cast<T *>(tm.halo),
+                       tm.tile_lat);
+    if (tm.n_reset > 0)
+      hipLaunchKernelGGL((k_halo_sum<T, DPN>),
+                         dim3(int((tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt))), dim3(256),
+                         0, s, tm.n_reset, tm.hnode, tm.hptr, static_cast<const T *>(nullptr),
+                         static_cast<const T *>(tm.halo), d, static_cast<const int *>(nullptr));
+    Q1_HIP(hipGetLastError());
+    return Q1_OK;
+  });
 }
 
 int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {

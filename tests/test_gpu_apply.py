@@ -343,3 +343,42 @@ def test_connectivity_out_of_range_rejected(q1, variant):
         with pytest.raises(q1.Q1Error) as ei:
             make_op(dict(pr, conn=conn), 0, variant)
         assert ei.value.code == -1, (variant, bad, str(ei.value))
+
+
+REPRO_CASES = [
+    # physics, elements, jitter, variant
+    (1, (16, 16, 16), 0.1, 5),  # general hexahedra
+    (1, (37, 19, 11), 0.0, 5),  # parallelepipeds, ragged tiles on every side
+    (2, (9, 7, 6), 0.1, 5),
+    (3, (8, 8, 8), 0.1, 5),
+    (3, (21, 9, 7), 0.0, 5),
+    (1, (13, 11, 7), 0.1, 6),   # partial assembly
+    (3, (8, 8, 8), 0.1, 6),
+]
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("physics,n,jitter,variant", REPRO_CASES)
+def test_block_apply_bitwise_reproducible(q1, orc, physics, n, jitter, variant, dtype):
+    """The block and partial-assembly variants add every node's contributions in a
+    fixed order (split accumulation, halo slots summed in tile order): repeated
+    applies and diagonals are bitwise identical, and still match the oracle."""
+    print(f"\n[reproducible] physics={physics} n={n} variant={variant} dtype={dtype}", flush=True)
+    pr = problem(physics, n, jitter, 2308, True)
+    A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    op = make_op(pr, dtype, variant)
+    assert op.reproducible()
+    x = si.vec_uniform(A.n, 2309, si.STREAM_X)
+    ys = [gpu_apply(op, x, dtype) for _ in range(4)]
+    assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    assert rel_err(ys[0], A.matvec(x)) <= TOL[dtype]
+    ds = [gpu_diag(op, A.n, dtype) for _ in range(3)]
+    assert all(np.array_equal(ds[0], d) for d in ds[1:])
+    assert rel_err(ds[0], A.diag()) <= TOL[dtype]
+
+
+def test_atomic_variant_not_reproducible_flag(q1):
+    pr = problem(1, (4, 4, 4), 0.1, 2308, True)
+    assert not make_op(pr, 0, 1).reproducible()
+    assert not make_op(pr, 0, 3).reproducible()
+    assert make_op(pr, 0, 0).reproducible()  # the default is the block variant

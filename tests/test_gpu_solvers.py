@@ -436,3 +436,29 @@ def test_dot_variants(q1, n, dtype):
     assert float(out.item()) == outs[0]
     with pytest.raises(q1.Q1Error):
         q1.q1_dot(ad, bd, out, q1.Q1_DOT_TWO_STAGE, 1025, work)
+
+
+def test_solves_bitwise_reproducible(q1, orc):
+    """On the default (block) operators two identical solves take the same
+    iterations and return bitwise-identical iterates: the apply, the diagonal and
+    every reduction add in a fixed order."""
+    import torch
+    for physics, n in ((1, (16, 16, 16)), (3, (10, 10, 10))):
+        print(f"\n[reproducible solve] physics={physics} n={n}", flush=True)
+        pr = problem(physics, n, 0.1, 83, True)
+        A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+        b = rhs(A, pr, 83)
+        op64, op32 = make_op(pr, 0, 0), make_op(pr, 1, 0)
+        assert op64.reproducible() and op32.reproducible()
+        bd = dev(b, torch.float64)
+        for solve in (lambda x: q1.q1_pcg(op64, 1, bd, x, 1e-10, 20000),
+                      lambda x: q1.q1_mpcg(op64, op32, bd, x, 1e-10, 0.1, 20000)):
+            xs, its = [], []
+            for _ in range(2):
+                xd = torch.empty_like(bd)
+                st = solve(xd)
+                assert st["status"] == 0
+                its.append(st["iters"])
+                xs.append(xd.cpu().numpy())
+            assert its[0] == its[1]
+            assert np.array_equal(xs[0], xs[1])
