@@ -249,6 +249,24 @@ int q1_dot(int64_t n, int dtype, const void *a_d, const void *b_d, double *out_d
 int q1_pcg(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit,
            q1_stats *st, void *stream);
 
+/* For callers that cannot allocate device memory (code recorded under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): q1_pcg with
+ * its whole workspace (the status record, the reduction partials and the four
+ * solver vectors) in a static device array of Q1_NOALLOC_BYTES (about 96 MiB)
+ * that each GPU the library runs on holds until the process ends.  Same
+ * arguments, results and statuses as q1_pcg; Q1_EINVAL when n_nodes*dpn
+ * exceeds Q1_NOALLOC_MAX_DOF (3,145,728: the 128^3 scalar and 96^3
+ * elasticity problems fit).  Makes no device or pinned-host allocation (the
+ * operator's own set-up already holds everything its apply and diagonal use).
+ * All calls on one GPU share that GPU's array: calls that overlap in time on
+ * one GPU race.  The array keeps the last call's contents; every call writes
+ * each workspace entry before it reads it (the status record is cleared by a
+ * kernel, not a memset).  Synchronises `stream`. */
+#define Q1_NOALLOC_MAX_DOF 3145728
+#define Q1_NOALLOC_BYTES (256 + 8 * 1024 * 8 + 4 * (size_t)Q1_NOALLOC_MAX_DOF * 8)
+int q1_pcg_noalloc(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit,
+                   q1_stats *st, void *stream);
+
 /* A preconditioner callback: enqueue z = M(r) on `stream` (device vectors of
  * the operator's dtype) and return Q1_OK, or any other value to report
  * failure. */

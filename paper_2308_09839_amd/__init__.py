@@ -20,7 +20,7 @@ from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32,
                    Q1_V_CSR, Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
 __all__ = [
-    "Q1_PC_NONE", "Q1_PC_JACOBI", "q1_dot", "Q1_DOT_TWO_STAGE", "Q1_DOT_ATOMIC", "Q1Stats", "q1_pcg", "q1_pcg_fused", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
+    "Q1_PC_NONE", "Q1_PC_JACOBI", "q1_dot", "Q1_DOT_TWO_STAGE", "Q1_DOT_ATOMIC", "Q1Stats", "q1_pcg", "q1_pcg_noalloc", "Q1_NOALLOC_MAX_DOF", "q1_pcg_fused", "q1_pcg_trace", "q1_batched_pcg", "q1_batched_mpcg", "q1_mpcg", "q1_fpcg", "q1_fcg", "q1_ir_solve", "Jacobi",
     "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_VLAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_COLOR", "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
@@ -257,6 +257,7 @@ def _solve_rc(rc: int) -> int:
 
 Q1_DOT_TWO_STAGE = 0
 Q1_DOT_ATOMIC = 1
+Q1_NOALLOC_MAX_DOF = 3145728  # the static workspace of q1_pcg_noalloc (include/q1mf.h)
 
 
 def q1_dot(a, b, out, variant: int = Q1_DOT_TWO_STAGE, nblocks: int = 0, work=None,
@@ -273,6 +274,14 @@ def q1_pcg(op: Op, pc: int, b, x, rtol: float, maxit: int, stream=None) -> dict:
     st = Q1Stats()
     _solve_rc(lib().q1_pcg(op.handle, pc, _dptr(b), _dptr(x), rtol, maxit, ctypes.byref(st),
                            _stream(stream)))
+    return st.as_dict()
+
+
+def q1_pcg_noalloc(op: Op, pc: int, b, x, rtol: float, maxit: int, stream=None) -> dict:
+    """q1_pcg with its workspace in the library's static device array (no allocation)."""
+    st = Q1Stats()
+    _solve_rc(lib().q1_pcg_noalloc(op.handle, pc, _dptr(b), _dptr(x), rtol, maxit,
+                                   ctypes.byref(st), _stream(stream)))
     return st.as_dict()
 
 

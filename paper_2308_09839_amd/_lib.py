@@ -94,6 +94,7 @@ PROTOTYPES = {
     "q1_csr_info": (c_int, [c_vp, P(c_i64), P(c_i64)]),
     "q1_csr_export": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "q1_pcg": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, P(Q1Stats), c_vp]),
+    "q1_pcg_noalloc": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, P(Q1Stats), c_vp]),
     "q1_pcg_trace": (c_int, [c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_int, c_vp, c_vp, P(Q1Stats),
                              c_vp]),
     "q1_fpcg": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_int, c_int, P(Q1Stats), c_vp]),

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -43,6 +44,28 @@ struct Status {
   int done, status, iter, pad;
   double rr, bb, rho, aux;
 };
+
+// Workspace of q1_pcg_noalloc: the status record, the reduction partials and
+// the four solver vectors (r, p, q, w) of at most Q1_NOALLOC_MAX_DOF entries,
+// in one static array that each GPU holds until the process ends.  Host code
+// must not use the array's name as a device address: the per-device address
+// comes from hipGetSymbolAddress (scratch_on).
+constexpr int64_t kNoAllocMaxDof = Q1_NOALLOC_MAX_DOF;
+constexpr size_t kNoAllocHead = 256;  // status record, padded
+constexpr size_t kNoAllocPart = size_t(8) * kMaxRB * sizeof(double);
+constexpr size_t kNoAllocVec = size_t(kNoAllocMaxDof) * sizeof(double);
+constexpr size_t kNoAllocBytes = kNoAllocHead + kNoAllocPart + 4 * kNoAllocVec;
+static_assert(kNoAllocBytes == Q1_NOALLOC_BYTES, "header and workspace layout disagree");
+static_assert(sizeof(Status) <= kNoAllocHead, "status record exceeds its slot");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// zero the status record (a kernel rather than a memset node, so that the
+// stream work stays capturable)
+__global__ void k_clear_status(Status *st) {
+  static_assert(sizeof(Status) % sizeof(int) == 0, "status record of whole words");
+  int *w = reinterpret_cast<int *>(st);
+  for (int i = threadIdx.x; i < int(sizeof(Status) / sizeof(int)); i += blockDim.x) w[i] = 0;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -488,10 +511,12 @@ struct Work {
        *z = nullptr;
   double *part = nullptr;  // [8][kMaxRB]
   Status *st = nullptr;    // device
-  Status *hst = nullptr;   // pinned host mirror
+  Status *hst = nullptr;   // host mirror (pinned when owned)
+  bool owned = true;       // false: the buffers live in the static scratch array
   Work() = default;
   Work(const Work &) = delete;
   ~Work() {
+    if (!owned) return;
     void *d[] = {r, p, q, w, r_old, z, part, st};
     for (void *v : d)
       if (v) (void)hipFree(v);
@@ -576,11 +601,13 @@ struct Snapshots {
 
 template <typename T>
 int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *stats,
-          hipStream_t s, bool true_res, const Snapshots &snap = Snapshots()) {
+          hipStream_t s, bool true_res, const Snapshots &snap = Snapshots(),
+          Work *given = nullptr) {
   const int64_t n = op.n_nodes * op.dpn();
-  Work W;
-  int rc = alloc_work<T>(W, n, false);
-  if (rc) return rc;
+  Work own;
+  int rc;
+  if (!given && (rc = alloc_work<T>(own, n, false))) return rc;
+  Work &W = given ? *given : own;
   const auto t0 = std::chrono::steady_clock::now();
   if ((rc = setup_diag<T>(op, W, pc, s))) return rc;
   const int nb = nblocks_for(n);
@@ -589,7 +616,7 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
   double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB;
   T *r = static_cast<T *>(W.r), *p = static_cast<T *>(W.p), *q = static_cast<T *>(W.q),
     *w = static_cast<T *>(W.w);
-  Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, W.st);
   hipLaunchKernelGGL((k_pcg_init<T>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r, p, part_rho[0],
                      part_bb, 1);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRT), 0, s, part_bb, nb, &W.st->bb);
@@ -941,6 +968,38 @@ struct Jacobi {
 
 }  // namespace q1
 
+namespace q1 {
+namespace {
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (each GPU holds its own copy at its own address).
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+unsigned char *g_scratch[kMaxDevices] = {};
+
+int scratch_on(int dev, unsigned char **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  Q1_CHECK(dev >= 0 && dev < kMaxDevices, Q1_EUNSUPPORTED, "device %d beyond %d", dev,
+           kMaxDevices);
+  if (!g_scratch[dev]) {
+    int cur = 0;
+    Q1_HIP(hipGetDevice(&cur));
+    if (cur != dev) Q1_HIP(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(Q1_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch[dev] = static_cast<unsigned char *>(p);
+  }
+  *out = g_scratch[dev];
+  return Q1_OK;
+}
+
+}  // namespace
+}  // namespace q1
+
 using namespace q1;
 
 struct q1_jacobi : public q1::Jacobi {};
@@ -959,6 +1018,39 @@ int q1_pcg(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit
                          rtol, maxit, st, s, true);
   return pcg_t<float>(o, pc, static_cast<const float *>(b_d), static_cast<float *>(x_d), rtol,
                       maxit, st, s, true);
+}
+
+int q1_pcg_noalloc(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit,
+                   q1_stats *st, void *stream) {
+  Q1_CHECK(op && b_d && x_d, Q1_EINVAL, "q1_pcg_noalloc: NULL argument");
+  Q1_CHECK(pc == Q1_PC_NONE || pc == Q1_PC_JACOBI, Q1_EINVAL,
+           "q1_pcg_noalloc: bad preconditioner %d", pc);
+  Q1_CHECK(rtol >= 0 && maxit >= 0, Q1_EINVAL, "q1_pcg_noalloc: need rtol >= 0 and maxit >= 0");
+  Op &o = *reinterpret_cast<Op *>(op);
+  const int64_t n = o.n_nodes * o.dpn();
+  Q1_CHECK(n <= kNoAllocMaxDof, Q1_EINVAL,
+           "q1_pcg_noalloc: %lld DOFs exceed the static workspace's %lld (Q1_NOALLOC_MAX_DOF)",
+           static_cast<long long>(n), static_cast<long long>(kNoAllocMaxDof));
+  unsigned char *base = nullptr;
+  int rc = scratch_on(o.device, &base);
+  if (rc) return rc;
+  thread_local Status host_status;  // pageable host mirror: no pinned allocation
+  Work W;
+  W.owned = false;
+  W.st = reinterpret_cast<Status *>(base);
+  W.part = reinterpret_cast<double *>(base + kNoAllocHead);
+  unsigned char *v = base + kNoAllocHead + kNoAllocPart;
+  W.r = v;
+  W.p = v + kNoAllocVec;
+  W.q = v + 2 * kNoAllocVec;
+  W.w = v + 3 * kNoAllocVec;
+  W.hst = &host_status;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (o.dtype == Q1_F64)
+    return pcg_t<double>(o, pc, static_cast<const double *>(b_d), static_cast<double *>(x_d),
+                         rtol, maxit, st, s, true, Snapshots(), &W);
+  return pcg_t<float>(o, pc, static_cast<const float *>(b_d), static_cast<float *>(x_d), rtol,
+                      maxit, st, s, true, Snapshots(), &W);
 }
 
 int q1_pcg_trace(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit, int nsnap,
