@@ -207,6 +207,9 @@ def bench_csr(q1, si, n, seed, args):
     ms, _ = time_applies(csr, x, y, args.steps, args.warmup)
     b, _ = csr.bytes()
     nnz = q1.q1_csr_info(csr)[1]
+    torch.cuda.synchronize()
+    csr.destroy()
+    op.destroy()
     return {"csr_spmv_gdofs": round(nn / (ms * 1e-3) / 1e9, 3), "csr_spmv_ms": round(ms, 5),
             "csr_hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "csr_nnz": nnz,
             "csr_assembly_s": round(t_asm, 3)}
@@ -435,7 +438,13 @@ def bench_ir96(q1, si, n, seed, args):
     xx = torch.empty(3 * nn, dtype=torch.float64, device="cuda")
     yy = torch.empty_like(xx)
     ms64, _ = time_applies(op64, xx, yy, 50, 5)
-    b64, _ = op64.bytes()
+    b64, f64 = op64.bytes()
+    # the general-hexahedron instance: the same problem on the jittered grid
+    prj = dict(pr)
+    prj["xyz"], _ = si.box_mesh(96, 96, 96, 1.0, 0.1, s2)
+    opj = q1.q1_op_create(3, 0, 0, *upload(prj, 0))
+    msj, _ = time_applies(opj, xx, yy, 50, 5)
+    opj.destroy()
     # partial assembly (scaled adjugate stored per point) against the matrix-free apply
     pa = {}
     for dt, tag, xv, yv in ((0, "fp64", xx, yy), (1, "fp32", x32, y32)):
@@ -448,7 +457,10 @@ def bench_ir96(q1, si, n, seed, args):
         oppa.destroy()
     op64.destroy()
     op32.destroy()
-    return {**pa, "el96_apply_fp64_hbm_frac": round(b64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),"el96_pcg64_s": round(t64, 4), "el96_pcg64_iters": st64["iters"],
+    return {**pa, "el96_apply_fp64_hbm_frac": round(b64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "el96_jittered_fp64_gdofs": round(3 * nn / (msj * 1e-3) / 1e9, 3),
+            "el96_jittered_fp64_flop_frac": round(f64 / (msj * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+            "el96_pcg64_s": round(t64, 4), "el96_pcg64_iters": st64["iters"],
             "el96_pcg64_status": st64["status"], "el96_pcg64_true_rel_res": st64["true_rel_res"],
             "el96_ir_s": round(tir, 4), "el96_ir_inner_iters": sti["iters"],
             "el96_ir_outer": sti["outer_iters"], "el96_ir_status": sti["status"],
@@ -488,7 +500,8 @@ def bench_vlap96(q1, si, n, seed, args):
             res["vlap96_pcg64_s"] = round(time.perf_counter() - t0, 4)
             res["vlap96_pcg64_iters"] = st["iters"]
             res["vlap96_pcg64_true_rel_res"] = st["true_rel_res"]
-        del op
+        torch.cuda.synchronize()
+        op.destroy()
     return res
 
 
@@ -532,6 +545,9 @@ def bench_batched(q1, si, n, seed, args):
         for c in range(4):
             it_loop += q1.q1_pcg(ops[i], 1, bd[i][c], xd[i][c], 1e-8, 20000)["iters"]
     t_loop = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    for o in ops:
+        o.destroy()
     return {"batched_s": round(t_batched, 4), "batched_kernel_s": round(st[0]["seconds"], 4),
             "batched_loop_pcg_s": round(t_loop, 4), "batched_total_iters": iters,
             "batched_loop_iters": it_loop, "batched_ndof_x4": 4 * ndof,
@@ -632,6 +648,7 @@ def bench_learned(q1, si, n, seed, args):
                 "nn_wall_speedup_vs_jacobi": round(jt / nt, 3)})
     del data
     torch.cuda.synchronize()
+    net.destroy()
     return res
 
 
@@ -646,6 +663,9 @@ def main() -> int:
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 atomic, 3 LDS tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/jittered/cold extras")
+    ap.add_argument("--only-extras", action="store_true",
+                    help="skip the cold, variant, FP32 and jittered applies (run the headline "
+                         "and the solver extras named by --extras only; for profiling a leg)")
     ap.add_argument("--extras", default="all",
                     help="comma-separated solver extras to run (csr, cg16, cg128, "
                          "cg_elasticity96, vlaplace96, family, learned64, batched32) or 'all'")
@@ -715,7 +735,10 @@ def main() -> int:
     for c in copies[1:]:
         c[0].destroy()
     del copies
-    if not args.no_extras:
+    if not args.no_extras and args.only_extras:
+        op.destroy()
+        del op, x, y
+    elif not args.no_extras:
         log("[bench] cold (flushed) applies")
         ms_cold = time_cold(op, x, y, 100)
         extras["fp64_cold_write_flush_gdofs"] = round(ndof / (ms_cold * 1e-3) / 1e9, 3)
@@ -764,6 +787,9 @@ def main() -> int:
         for c in copies:
             c[0].destroy()
         del copies
+    else:
+        op.destroy()
+    if not args.no_extras:
         torch.cuda.synchronize()
         for name, fn in (("csr", bench_csr), ("cg16", bench_cg16), ("cg128", bench_cg128),
                          ("cg_elasticity96", bench_ir96), ("vlaplace96", bench_vlap96),
@@ -778,8 +804,6 @@ def main() -> int:
                 log(f"[bench] {name} failed: {exc!r}")
                 extras[f"{name}_error"] = repr(exc)
             torch.cuda.synchronize()
-    else:
-        op.destroy()
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")

@@ -47,7 +47,10 @@ struct TileMap {
   bool split = false;             // block variants: bitwise-reproducible split accumulation
   bool all_affine = false;        // every tile is a parallelepiped tile
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
-  uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16, or 0
+  uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16 | C << 24, or 0
+  uint32_t *tile_addr = nullptr;  // [n_tiles] lattice addressing: valid bit | shared-face bits, or 0
+  int32_t *tile_g0 = nullptr;     // [n_tiles] global id of entry 0 of a lattice-addressed tile
+  int64_t sy = 0, sz = 0;         // mesh strides of lattice addressing
   // block variant: partial sums of nodes shared between tiles go to halo slots
   // (no atomics), summed per node by a second kernel in a fixed order
   int64_t n_halo = 0;             // slots: 2 per reset node + one per further touching tile

@@ -62,10 +62,17 @@ class Problem:
 
 
 def snapshot_iters(kmax: int, count: int) -> list[int]:
-    """count iterations in [1, kmax], half log-spaced, half evenly spaced."""
+    """min(count, kmax) distinct iterations in [1, kmax]: half log-spaced, half
+    evenly spaced, and where those coincide, further evenly spaced ones."""
     lo = np.unique(np.round(np.geomspace(1, max(kmax, 2), count // 2)).astype(int))
     hi = np.unique(np.linspace(1, kmax, count - count // 2).astype(int))
-    return sorted(set(int(v) for v in np.concatenate([lo, hi]) if 1 <= v <= kmax))
+    chosen = set(int(v) for v in np.concatenate([lo, hi]) if 1 <= v <= kmax)
+    rest = [v for v in range(1, kmax + 1) if v not in chosen]
+    need = min(count - len(chosen), len(rest))
+    if need > 0:  # spacing >= 1 between the picks, so they are distinct
+        pick = np.round(np.linspace(0, len(rest) - 1, need)).astype(int)
+        chosen.update(rest[i] for i in pick)
+    return sorted(chosen)
 
 
 class Field:

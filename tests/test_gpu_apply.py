@@ -175,6 +175,59 @@ def test_full_size_vlaplace_sampled(q1, orc, variant):
         assert np.max(np.abs(y)) <= 1e-12 * pr["coef"].max()
 
 
+@pytest.mark.parametrize("jitter", [0.0, 0.1])
+def test_full_size_laplace_full_vector(q1, orc, jitter):
+    """128^3 layered-coefficient Laplace in the benchmark's launch configuration
+    (default operator), FP64 and FP32, undistorted (parallelepiped element path)
+    and jittered (general hexahedra): every entry of y against the oracle's
+    assembled CSR matrix (57,066,625 non-zeros)."""
+    print(f"\n[full-vector laplace 128^3] jitter={jitter}", flush=True)
+    seed = si.seed_for(1)
+    pr = si.problem_laplace_layered(128, seed)
+    if jitter:
+        pr["xyz"], _ = si.box_mesh(128, 128, 128, 1.0, jitter, seed)
+    nn = pr["xyz"].shape[1]
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"])
+    assert A.nnz == 385 ** 3
+    x = si.vec_uniform(nn, seed, si.STREAM_X)
+    ref = A.matvec(x)
+    del A
+    for dtype in (0, 1):
+        op = make_op(pr, dtype, 0)
+        y = gpu_apply(op, x, dtype)
+        op.destroy()
+        assert rel_err(y, ref) <= TOL[dtype], (dtype, rel_err(y, ref))
+        assert np.max(np.abs(y - ref)) <= 10 * TOL[dtype] * np.max(np.abs(ref))
+
+
+def test_full_size_elasticity_jittered(q1, orc):
+    """96^3 jittered elasticity (the general-hexahedron instance), FP64 and FP32:
+    sampled rows against the oracle's element-by-element rows, and, without the
+    Dirichlet condition, the six rigid-body modes in the null space over the
+    whole grid."""
+    print("\n[full-size jittered elasticity 96^3]", flush=True)
+    seed = si.seed_for(2)
+    pr = si.problem_elasticity(96, seed)
+    pr["xyz"], _ = si.box_mesh(96, 96, 96, 1.0, 0.1, seed)
+    nn = pr["xyz"].shape[1]
+    x = si.vec_uniform(3 * nn, seed, si.STREAM_X)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([rng.integers(0, 3 * nn, 3000), [0, 3 * nn - 1]]))
+    ref = orc.apply_rows(3, pr["xyz"], pr["conn"], pr["coef"], pr["mask"], x, rows)
+    for dtype in (0, 1):
+        op = make_op(pr, dtype, 0)
+        y = gpu_apply(op, x, dtype)
+        op.destroy()
+        err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+        assert err <= TOL[dtype], (dtype, err)
+    op = make_op(dict(pr, mask=None), 0, 0)
+    scale = np.max(pr["coef"]) * 1.0
+    for m in rigid_modes(pr["xyz"]):
+        y = gpu_apply(op, m, 0)
+        assert np.max(np.abs(y)) <= 1e-10 * scale * max(1.0, np.max(np.abs(m)))
+    op.destroy()
+
+
 # -- partial assembly (quadrature data stored at set-up) ----------------------------
 
 PA_CASES = CASES
