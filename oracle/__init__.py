@@ -71,6 +71,8 @@ def lib():
         L.orc_ke_tet_elasticity.argtypes = [_f64p, ctypes.c_double, ctypes.c_double, _f64p]
         L.orc_ke_q2_laplace.argtypes = [_f64p, ctypes.c_double, _f64p]
         L.orc_ke_q2_elasticity.argtypes = [_f64p, ctypes.c_double, ctypes.c_double, _f64p]
+        L.orc_ke_q3_laplace.argtypes = [_f64p, ctypes.c_double, _f64p]
+        L.orc_ke_q3_elasticity.argtypes = [_f64p, ctypes.c_double, ctypes.c_double, _f64p]
         L.orc_apply_rows.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _f64p, _i32p,
                                      _f64p, ctypes.c_void_p, _f64p, ctypes.c_int64, _i64p, _f64p]
         L.orc_spmv.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p]
@@ -158,6 +160,22 @@ def ke_q2(physics: int, X: np.ndarray, c0: float, c1: float = 0.0) -> np.ndarray
     return Ke.reshape(m, m)
 
 
+def ke_q3(physics: int, X: np.ndarray, c0: float, c1: float = 0.0) -> np.ndarray:
+    """Tricubic-hexahedron element matrix (X[64,3], local node i + 4j + 16k):
+    physics 1 (64x64) or 3 (192x192)."""
+    X = np.ascontiguousarray(X, dtype=np.float64).ravel()
+    if physics == 1:
+        Ke = np.zeros(4096)
+        rc = lib().orc_ke_q3_laplace(X, float(c0), Ke)
+    else:
+        Ke = np.zeros(36864)
+        rc = lib().orc_ke_q3_elasticity(X, float(c0), float(c1), Ke)
+    if rc:
+        raise ValueError("non-positive Jacobian determinant")
+    m = 64 if physics == 1 else 192
+    return Ke.reshape(m, m)
+
+
 @dataclass
 class CSR:
     n: int
@@ -197,7 +215,7 @@ def dpn_of(physics: int) -> int:
 
 
 def csr_pattern(dpn: int, n_nodes: int, conn: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
-    """Pattern for the connectivity conn [nloc, n_elems] (nloc 8, 4 or 27)."""
+    """Pattern for the connectivity conn [nloc, n_elems] (nloc 8, 4, 27 or 64)."""
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     nloc, ne = conn.shape
     rowptr = np.zeros(n_nodes * dpn + 1, dtype=np.int64)
@@ -217,7 +235,8 @@ def assemble(physics: int, xyz: np.ndarray, conn: np.ndarray, coef: np.ndarray,
     physics = 1 (scalar Laplace, coef [1, ne] = k), 2 (vector Laplace, 3 DOF
     per node, coef [1, ne] = k) or 3 (elasticity, coef [2, ne] = lambda, mu).
     xyz [3, nn], conn [nloc, ne] with nloc 8 (trilinear hexahedra), 4 (linear
-    tetrahedra) or 27 (triquadratic hexahedra), mask uint8 [nn]."""
+    tetrahedra), 27 (triquadratic hexahedra) or 64 (tricubic hexahedra), mask
+    uint8 [nn]."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     coef = np.ascontiguousarray(coef, dtype=np.float64)

@@ -312,6 +312,119 @@ int orc_ke_q2_elasticity(const double X[81], double lam, double mu, double Ke[65
   return 0;
 }
 
+/* ---- tricubic (Q3) hexahedra (Section 7: higher-order elements) -------- */
+
+/* Reference cube [-1,1]^3 with the 64 nodes at (t_i, t_j, t_k), t_m = -1 +
+ * 2m/3, local node a = i + 4j + 16k; phi_a = L_i(xi) L_j(eta) L_k(zeta) with
+ * the 1-D cubic Lagrange polynomials of those nodes, written as products.
+ * Quadrature: 4x4x4 Gauss-Legendre, points +-sqrt(3/7 -+ (2/7) sqrt(6/5)),
+ * weights (18 +- sqrt(30)) / 36 (exact for the stiffness of elements with a
+ * trilinear geometry and for the polynomial degree of an affine element). */
+static double lc_node(int m) { return -1.0 + 2.0 * m / 3.0; }
+static double lc(int i, double t) {
+  double v = 1.0;
+  for (int m = 0; m < 4; ++m)
+    if (m != i) v *= (t - lc_node(m)) / (lc_node(i) - lc_node(m));
+  return v;
+}
+static double dlc(int i, double t) {
+  double d = 0.0;
+  for (int l = 0; l < 4; ++l) {
+    if (l == i) continue;
+    double v = 1.0 / (lc_node(i) - lc_node(l));
+    for (int m = 0; m < 4; ++m)
+      if (m != i && m != l) v *= (t - lc_node(m)) / (lc_node(i) - lc_node(m));
+    d += v;
+  }
+  return d;
+}
+
+void orc_q3_quadrature(double pts[64][3], double w[64]) {
+  const double a = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(6.0 / 5.0));
+  const double b = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(6.0 / 5.0));
+  const double wa = (18.0 + sqrt(30.0)) / 36.0, wb = (18.0 - sqrt(30.0)) / 36.0;
+  const double gp[4] = {-b, -a, a, b}, gw[4] = {wb, wa, wa, wb};
+  for (int q = 0; q < 64; ++q) {
+    const int i = q % 4, j = (q / 4) % 4, k = q / 16;
+    pts[q][0] = gp[i]; pts[q][1] = gp[j]; pts[q][2] = gp[k];
+    w[q] = gw[i] * gw[j] * gw[k];
+  }
+}
+
+void orc_q3_ref_grad(const double xi[3], double dphi[64][3]) {
+  for (int a = 0; a < 64; ++a) {
+    const int i = a % 4, j = (a / 4) % 4, k = a / 16;
+    dphi[a][0] = dlc(i, xi[0]) * lc(j, xi[1]) * lc(k, xi[2]);
+    dphi[a][1] = lc(i, xi[0]) * dlc(j, xi[1]) * lc(k, xi[2]);
+    dphi[a][2] = lc(i, xi[0]) * lc(j, xi[1]) * dlc(k, xi[2]);
+  }
+}
+
+/* J, its cofactor inverse and the physical gradients of the 64 functions */
+static double q3_gradients(const double X[192], const double dphi[64][3], double G[64][3]) {
+  double J[3][3] = {{0}};
+  for (int a = 0; a < 64; ++a)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] += X[3 * a + r] * dphi[a][c];
+  double C[3][3];
+  C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  C[0][1] = -(J[1][0] * J[2][2] - J[1][2] * J[2][0]);
+  C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  C[1][0] = -(J[0][1] * J[2][2] - J[0][2] * J[2][1]);
+  C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  C[1][2] = -(J[0][0] * J[2][1] - J[0][1] * J[2][0]);
+  C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  C[2][1] = -(J[0][0] * J[1][2] - J[0][2] * J[1][0]);
+  C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+  for (int a = 0; a < 64; ++a)
+    for (int r = 0; r < 3; ++r) {
+      double v = 0.0;
+      for (int c = 0; c < 3; ++c) v += dphi[a][c] * C[r][c] / det;
+      G[a][r] = v;
+    }
+  return det;
+}
+
+int orc_ke_q3_laplace(const double X[192], double k, double Ke[4096]) {
+  double pts[64][3], w[64];
+  orc_q3_quadrature(pts, w);
+  memset(Ke, 0, 4096 * sizeof(double));
+  for (int q = 0; q < 64; ++q) {
+    double dphi[64][3], G[64][3];
+    orc_q3_ref_grad(pts[q], dphi);
+    const double det = q3_gradients(X, dphi, G);
+    if (!(det > 0.0)) return -1;
+    const double s = k * w[q] * det;
+    for (int a = 0; a < 64; ++a)
+      for (int b = 0; b < 64; ++b)
+        Ke[64 * a + b] += s * (G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2]);
+  }
+  return 0;
+}
+
+int orc_ke_q3_elasticity(const double X[192], double lam, double mu, double Ke[36864]) {
+  double pts[64][3], w[64];
+  orc_q3_quadrature(pts, w);
+  memset(Ke, 0, 36864 * sizeof(double));
+  for (int q = 0; q < 64; ++q) {
+    double dphi[64][3], G[64][3];
+    orc_q3_ref_grad(pts[q], dphi);
+    const double det = q3_gradients(X, dphi, G);
+    if (!(det > 0.0)) return -1;
+    const double s = w[q] * det;
+    for (int a = 0; a < 64; ++a)
+      for (int b = 0; b < 64; ++b) {
+        const double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            Ke[192 * (3 * a + i) + 3 * b + j] +=
+                s * (lam * G[a][i] * G[b][j] + mu * ((i == j ? gg : 0.0) + G[a][j] * G[b][i]));
+      }
+  }
+  return 0;
+}
+
 static int element_matrix_n(int nloc, int physics, const double *X, const double *coef,
                             int64_t ne, int64_t e, double *Ke) {
   if (nloc == 8) return element_matrix(physics, X, coef, ne, e, Ke);
@@ -319,8 +432,11 @@ static int element_matrix_n(int nloc, int physics, const double *X, const double
   if (nloc == 4)
     return physics == 1 ? orc_ke_tet_laplace(X, coef[e], Ke)
                         : orc_ke_tet_elasticity(X, coef[e], c1, Ke);
-  return physics == 1 ? orc_ke_q2_laplace(X, coef[e], Ke)
-                      : orc_ke_q2_elasticity(X, coef[e], c1, Ke);
+  if (nloc == 27)
+    return physics == 1 ? orc_ke_q2_laplace(X, coef[e], Ke)
+                        : orc_ke_q2_elasticity(X, coef[e], c1, Ke);
+  return physics == 1 ? orc_ke_q3_laplace(X, coef[e], Ke)
+                      : orc_ke_q3_elasticity(X, coef[e], c1, Ke);
 }
 
 /* ---- CSR pattern ------------------------------------------------------- */
@@ -425,13 +541,13 @@ int orc_csr_assemble(int physics, int64_t nn, int64_t ne, const double *xyz,
 int orc_csr_assemble_n(int nloc, int physics, int64_t nn, int64_t ne, const double *xyz,
                        const int32_t *conn, const double *coef, const uint8_t *mask,
                        const int64_t *rowptr, const int32_t *col, double *val) {
-  if (nloc != 8 && nloc != 4 && nloc != 27) return -3;
+  if (nloc != 8 && nloc != 4 && nloc != 27 && nloc != 64) return -3;
   if (nloc != 8 && physics == 2) return -3;
   const int dpn = dpn_of(physics);
   const int nd = nloc * dpn;
   const int64_t nrows = nn * dpn;
   memset(val, 0, (size_t)rowptr[nrows] * sizeof(double));
-  double X[81];
+  double X[192];
   double *Ke = (double *)malloc((size_t)nd * nd * sizeof(double));
   if (!Ke) return -2;
   for (int64_t e = 0; e < ne; ++e) {
@@ -475,7 +591,7 @@ int orc_apply_rows(int physics, int64_t nn, int64_t ne, const double *xyz,
 int orc_apply_rows_n(int nloc, int physics, int64_t nn, int64_t ne, const double *xyz,
                      const int32_t *conn, const double *coef, const uint8_t *mask,
                      const double *x, int64_t n_rows, const int64_t *rows, double *y) {
-  if (nloc != 8 && nloc != 4 && nloc != 27) return -3;
+  if (nloc != 8 && nloc != 4 && nloc != 27 && nloc != 64) return -3;
   if (nloc != 8 && physics == 2) return -3;
   const int dpn = dpn_of(physics), nd = nloc * dpn;
   /* slot[node] = 1 if any DOF of the node is selected */
@@ -488,7 +604,7 @@ int orc_apply_rows_n(int nloc, int physics, int64_t nn, int64_t ne, const double
     pos[rows[r]] = r;
     y[r] = 0.0;
   }
-  double X[81];
+  double X[192];
   double *Ke = (double *)malloc((size_t)nd * nd * sizeof(double));
   if (!Ke) { free(sel); free(pos); return -2; }
   for (int64_t e = 0; e < ne; ++e) {

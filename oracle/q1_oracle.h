@@ -49,6 +49,12 @@ void orc_q2_quadrature(double pts[27][3], double w[27]);
 void orc_q2_ref_grad(const double xi[3], double dphi[27][3]);
 int orc_ke_q2_laplace(const double X[81], double k, double Ke[729]);
 int orc_ke_q2_elasticity(const double X[81], double lam, double mu, double Ke[6561]);
+/* Tricubic hexahedra: X is [64][3], local node a = i + 4j + 16k at
+ * (t_i, t_j, t_k), t_m = -1 + 2m/3; 4x4x4 Gauss rule. */
+void orc_q3_quadrature(double pts[64][3], double w[64]);
+void orc_q3_ref_grad(const double xi[3], double dphi[64][3]);
+int orc_ke_q3_laplace(const double X[192], double k, double Ke[4096]);
+int orc_ke_q3_elasticity(const double X[192], double lam, double mu, double Ke[36864]);
 
 /* CSR pattern of the assembled operator, columns sorted.  rowptr has
  * n_nodes*dpn + 1 entries.  With col == NULL only rowptr is filled.

@@ -194,6 +194,64 @@ def q2_face_mask(nx: int, ny: int, nz: int, face: int | str) -> np.ndarray:
     return sel.astype(np.uint8)
 
 
+def q3_box_sizes(nx: int, ny: int, nz: int) -> tuple[int, int]:
+    return (3 * nx + 1) * (3 * ny + 1) * (3 * nz + 1), nx * ny * nz
+
+
+def q3_box_mesh(nx: int, ny: int, nz: int, h: float = 1.0, jitter_frac: float = 0.0,
+                seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """Tricubic hexahedra on the box of nx*ny*nz elements.
+
+    Nodes lie on the tripled lattice, id = I + (3nx+1)(J + (3ny+1)K).  The
+    element vertices (I, J, K multiples of 3) are box_mesh's nodes, jitter
+    included; every other node sits at the trilinear interpolation of its
+    element's vertices at local coordinate (I mod 3)/3 (and likewise in y, z),
+    so each element is the trilinear image of the reference cube.  Local node
+    a = di + 4 dj + 16 dk of element e = ex + nx(ey + ny ez) is lattice node
+    (3ex+di, 3ey+dj, 3ez+dk).  Returns xyz [3, n_nodes] and conn int32
+    [64, n_elems]."""
+    vxyz, _ = box_mesh(nx, ny, nz, h, jitter_frac, seed)
+    NX, NY, NZ = 3 * nx + 1, 3 * ny + 1, 3 * nz + 1
+    K, J, I = np.meshgrid(np.arange(NZ), np.arange(NY), np.arange(NX), indexing="ij")
+    I = I.ravel(); J = J.ravel(); K = K.ravel()
+    xyz = np.zeros((3, NX * NY * NZ))
+
+    def vid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    # the vertex of the lower corner and the local coordinate per axis
+    i0, j0, k0 = I // 3, J // 3, K // 3
+    ti, tj, tk = (I % 3) / 3.0, (J % 3) / 3.0, (K % 3) / 3.0
+    for di in (0, 1):
+        wi = ti if di else 1.0 - ti
+        for dj in (0, 1):
+            wj = tj if dj else 1.0 - tj
+            for dk in (0, 1):
+                wk = tk if dk else 1.0 - tk
+                w = wi * wj * wk
+                sel = w > 0
+                v = vid(np.minimum(i0 + di, nx), np.minimum(j0 + dj, ny), np.minimum(k0 + dk, nz))
+                xyz[:, sel] += w[sel] * vxyz[:, v[sel]]
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex = ex.ravel(); ey = ey.ravel(); ez = ez.ravel()
+    conn = np.empty((64, nx * ny * nz), dtype=np.int32)
+    for a in range(64):
+        di, dj, dk = a % 4, (a // 4) % 4, a // 16
+        conn[a] = (3 * ex + di) + NX * ((3 * ey + dj) + NY * (3 * ez + dk))
+    return xyz, conn
+
+
+def q3_face_mask(nx: int, ny: int, nz: int, face: int | str) -> np.ndarray:
+    """uint8 per node of q3_box_mesh: 1 on the chosen face of the box."""
+    if isinstance(face, str):
+        face = FACES[face]
+    NX, NY, NZ = 3 * nx + 1, 3 * ny + 1, 3 * nz + 1
+    K, J, I = np.meshgrid(np.arange(NZ), np.arange(NY), np.arange(NX), indexing="ij")
+    sel = [I.ravel() == 0, I.ravel() == NX - 1, J.ravel() == 0, J.ravel() == NY - 1,
+           K.ravel() == 0, K.ravel() == NZ - 1][face]
+    return sel.astype(np.uint8)
+
+
 FACES = {"x0": 0, "x1": 1, "y0": 2, "y1": 3, "z0": 4, "z1": 5}
 
 
