@@ -319,8 +319,9 @@ def bench_cg128(q1, si, n, seed, args):
 def bench_family(q1, si, n, seed, args):
     """The element families of the paper's conclusions: linear tetrahedra (the
     Kuhn split of the headline 128^3 grid, 12,582,912 tetrahedra, each with its
-    hexahedron's coefficient) and triquadratic hexahedra (a 64^3-element box,
-    2,146,689 nodes, coefficient layered per 2 cells): FP64 and FP32 applies of
+    hexahedron's coefficient), triquadratic hexahedra (a 64^3-element box,
+    2,146,689 nodes, coefficient layered per 2 cells) and tricubic hexahedra
+    (a 42^3-element box, 2,048,383 nodes, layered per cell): FP64 and FP32 applies of
     scalar Laplace, FP64 elasticity applies, and Jacobi-PCG to 1e-8 with
     Dirichlet u = 0 on z = 0."""
     import numpy as np
@@ -336,7 +337,7 @@ def bench_family(q1, si, n, seed, args):
                                     up(coef, t), up(mask.astype(np.uint8)) if mask is not None
                                     else None)
 
-    for elem, tag in ((q1.Q1_TET4, "tet"), (q1.Q1_HEX27, "q2")):
+    for elem, tag in ((q1.Q1_TET4, "tet"), (q1.Q1_HEX27, "q2"), (q1.Q1_HEX64, "q3")):
         if elem == q1.Q1_TET4:
             m = n
             xyz, conn = si.tet_mesh(m, m, m)
@@ -344,13 +345,20 @@ def bench_family(q1, si, n, seed, args):
             me = n // 2
             xyz_e, conn_e = si.tet_mesh(me, me, me)
             mask_e = si.face_mask(me, me, me, "z0")
-        else:
+        elif elem == q1.Q1_HEX27:
             m = n // 2
             xyz, conn = si.q2_box_mesh(m, m, m)
             k = si.field_layered(m, m, m, 2, 1.5, 0.5, seed)[None]
             me = n // 4
             xyz_e, conn_e = si.q2_box_mesh(me, me, me)
             mask_e = si.q2_face_mask(me, me, me, "z0")
+        else:
+            m = n // 3
+            xyz, conn = si.q3_box_mesh(m, m, m)
+            k = si.field_layered(m, m, m, 1, 1.5, 0.5, seed)[None]
+            me = n // 6
+            xyz_e, conn_e = si.q3_box_mesh(me, me, me)
+            mask_e = si.q3_face_mask(me, me, me, "z0")
         nn = xyz.shape[1]
         for dt, dtag in ((0, "fp64"), (1, "fp32")):
             op = make(elem, 1, dt, xyz, conn, k)

@@ -145,21 +145,26 @@ int q1_op_create(q1_op **op, int physics, int dtype, int variant, int64_t n_node
                  const uint8_t *mask_d, void *stream);
 /* Element families.  The paper's elements are trilinear hexahedra
  * (Q1_HEX8, the layout described at the top of this header); its conclusions
- * (Section 7) name simplicial and quadratic elements as the next cases for the
- * matrix-free algorithm, built here with the same physics:
+ * (Section 7) name simplicial and higher-order elements as the next cases for
+ * the matrix-free algorithm, built here with the same physics:
  *   Q1_TET4   linear tetrahedra: connectivity [4][n_elems], reference vertices
  *             (0,0,0), (1,0,0), (0,1,0), (0,0,1) (positive orientation), the
  *             exact one-point rule (constant gradients);
  *   Q1_HEX27  triquadratic (Q2) hexahedra: connectivity [27][n_elems], local
  *             node a = i + 3j + 9k at (t_i, t_j, t_k) with t = (-1, 0, 1) of
  *             the reference cube, isoparametric geometry from the 27 nodes,
- *             3x3x3 Gauss-Legendre quadrature.
+ *             3x3x3 Gauss-Legendre quadrature;
+ *   Q1_HEX64  tricubic (Q3) hexahedra: connectivity [64][n_elems], local node
+ *             a = i + 4j + 16k at (t_i, t_j, t_k) with t_m = -1 + 2m/3,
+ *             isoparametric geometry from the 64 nodes, 4x4x4 Gauss-Legendre
+ *             quadrature.
  * The enum values are the nodes per element. */
-enum { Q1_HEX8 = 8, Q1_TET4 = 4, Q1_HEX27 = 27 };
-/* q1_op_create for an element family.  Q1_HEX8 is q1_op_create.  Q1_TET4 and
- * Q1_HEX27: physics Q1_LAPLACE or Q1_ELASTICITY, variants Q1_V_AUTO or
- * Q1_V_ATOMIC (one thread per tetrahedron, 27 threads per triquadratic element
- * with the element's nodes staged in LDS; global atomic scatter); other
+enum { Q1_HEX8 = 8, Q1_TET4 = 4, Q1_HEX27 = 27, Q1_HEX64 = 64 };
+/* q1_op_create for an element family.  Q1_HEX8 is q1_op_create.  Q1_TET4,
+ * Q1_HEX27 and Q1_HEX64: physics Q1_LAPLACE or Q1_ELASTICITY, variants
+ * Q1_V_AUTO or Q1_V_ATOMIC (one thread per tetrahedron, one thread per node
+ * and quadrature point of a triquadratic or tricubic element with the
+ * element's nodes staged in LDS; global atomic scatter); other
  * variants and physics give Q1_EUNSUPPORTED.  The apply, diagonal, byte model
  * and the Krylov solvers accept these operators; q1_csr_create, the fused and
  * the batched solvers do not (Q1_EUNSUPPORTED). */

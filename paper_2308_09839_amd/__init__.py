@@ -15,7 +15,7 @@ import numpy as np
 
 from . import _lib as _libmod
 from ._lib import (PRECOND_FN, Q1_EBREAKDOWN, Q1_ELASTICITY, Q1_ENOCONV, Q1_F32, Q1_F64,
-                   Q1_HEX8, Q1_HEX27, Q1_TET4,
+                   Q1_HEX8, Q1_HEX27, Q1_HEX64, Q1_TET4,
                    Q1_LAPLACE, Q1_OK, Q1_VLAPLACE, Q1_PC_JACOBI, Q1_PC_NONE, Q1_V_ATOMIC, Q1_V_AUTO, Q1_V_COLOR,
                    Q1_V_CSR, Q1_V_LDS_TILE, Q1Error, Q1Stats, check, last_error, lib)
 
@@ -24,7 +24,7 @@ __all__ = [
     "q1_jacobi_create", "Q1_OK", "Q1_ENOCONV", "Q1_EBREAKDOWN", "Q1Error", "Q1_LAPLACE", "Q1_VLAPLACE", "Q1_ELASTICITY", "Q1_F64", "Q1_F32", "Q1_V_AUTO", "Q1_V_ATOMIC",
     "Q1_V_COLOR", "Q1_V_LDS_TILE", "Q1_V_CSR", "q1_csr_create", "q1_csr_info", "q1_csr_export", "lib", "last_error", "q1_version", "q1_box_sizes", "q1_box_mesh",
     "q1_face_mask", "q1_field_lognormal", "q1_field_layered", "q1_field_elastic",
-    "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_create_elem", "Q1_HEX8", "Q1_TET4", "Q1_HEX27", "q1_op_apply", "q1_op_diag",
+    "q1_lame_from_E_nu", "q1_vec_uniform", "q1_op_create", "q1_op_create_elem", "Q1_HEX8", "Q1_TET4", "Q1_HEX27", "Q1_HEX64", "q1_op_apply", "q1_op_diag",
     "q1_op_info", "q1_op_bytes", "q1_op_reproducible", "q1_op_destroy", "q1_model_bytes", "Op",
     "q1_conv3d_forward", "q1_conv3d_backward_data", "q1_conv3d_backward_weight", "UNet",
     "q1_unet_create", "UNetPrecond", "q1_unet_pc_create", "q1_unet_pairs",
@@ -176,7 +176,7 @@ def q1_op_create(physics: int, dtype: int, variant: int, xyz, conn, coef, mask=N
 def q1_op_create_elem(elem: int, physics: int, dtype: int, variant: int, xyz, conn, coef,
                       mask=None, stream=None) -> Op:
     """Operator of an element family: Q1_HEX8 (conn [8, n_elems]), Q1_TET4
-    (conn [4, n_elems]) or Q1_HEX27 (conn [27, n_elems])."""
+    (conn [4, n_elems]), Q1_HEX27 (conn [27, n_elems]) or Q1_HEX64 (conn [64, n_elems])."""
     h = ctypes.c_void_p()
     n_nodes = xyz.shape[-1]
     n_elems = conn.shape[-1]

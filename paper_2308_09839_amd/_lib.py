@@ -34,6 +34,7 @@ Q1_V_PA = 6
 Q1_HEX8 = 8
 Q1_TET4 = 4
 Q1_HEX27 = 27
+Q1_HEX64 = 64
 
 Q1_PC_NONE = 0
 Q1_PC_JACOBI = 1

@@ -748,4 +748,53 @@ __device__ __forceinline__ void element_diag(T X[3][8], T c0, T c1, T (*acc)[8])
   }
 }
 
+// Linear tetrahedron of kind PH (scalar Laplace or elasticity): X[3][4] the
+// vertex coordinates, u[DPN][4] the input, v[DPN][4] the output.  With
+// E_c = X_c - X_0 the cross products c_1 = E_2 x E_3, c_2 = E_3 x E_1,
+// c_3 = E_1 x E_2, c_0 = -(c_1 + c_2 + c_3) are det J times the constant
+// physical gradients, det J = E_1 . c_1, the volume det J / 6:
+//   Laplace      v_a = k (c_a . g) / (6 det J),  g = sum_b c_b u_b,
+//   elasticity   v_a = S c_a / (6 det J),  S = lambda tr(H) I + mu (H + H^T),
+//                H = sum_b u_b (x) c_b.
+template <typename T, int PH>
+__device__ __forceinline__ void tet_element(const T X[3][4], const T (*u)[4], T c0, T c1,
+                                            T (*v)[4]) {
+  const T E1[3] = {X[0][1] - X[0][0], X[1][1] - X[1][0], X[2][1] - X[2][0]};
+  const T E2[3] = {X[0][2] - X[0][0], X[1][2] - X[1][0], X[2][2] - X[2][0]};
+  const T E3[3] = {X[0][3] - X[0][0], X[1][3] - X[1][0], X[2][3] - X[2][0]};
+  T c[4][3];
+  cross(E2, E3, c[1]);
+  cross(E3, E1, c[2]);
+  cross(E1, E2, c[3]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) c[0][r] = -(c[1][r] + c[2][r] + c[3][r]);
+  const T s = rcp(T(6) * dot3(E1, c[1]));
+  if constexpr (PH == 1) {
+    T g[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      g[r] = c[0][r] * u[0][0] + c[1][r] * u[0][1] + c[2][r] * u[0][2] + c[3][r] * u[0][3];
+    const T ks = c0 * s;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) v[0][a] = ks * dot3(c[a], g);
+  } else {
+    T H[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        H[i][j] = u[i][0] * c[0][j] + u[i][1] * c[1][j] + u[i][2] * c[2][j] + u[i][3] * c[3][j];
+    const T ltr = c0 * (H[0][0] + H[1][1] + H[2][2]);
+    T S[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) S[i][j] = s * (c1 * (H[i][j] + H[j][i]) + (i == j ? ltr : T(0)));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) v[i][a] = dot3(S[i], c[a]);
+  }
+}
+
 }  // namespace q1

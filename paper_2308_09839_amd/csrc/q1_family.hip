@@ -1,7 +1,7 @@
 // Element families beyond the trilinear hexahedron, named in the paper's
 // conclusions (Section 7) as the next cases for its matrix-free algorithm:
-// linear tetrahedra (simplicial elements) and triquadratic hexahedra
-// (quadratic elements).  The operators are the same scalar Laplace and
+// linear tetrahedra (simplicial elements) and triquadratic and tricubic
+// hexahedra (higher-order elements).  The operators are the same scalar Laplace and
 // isotropic elasticity with cell-wise coefficients (Section 2), applied
 // without a matrix by the gather / local product / scatter-add of Section 3.
 //
@@ -12,9 +12,10 @@
 //   Laplace      v_a = k (c_a . g) / (6 det J),  g = sum_b c_b u_b,
 //   elasticity   v_a = S c_a / (6 det J),  S = lambda tr(H) I + mu (H + H^T),
 //                H = sum_b u_b (x) c_b (= det J grad u).
-// Triquadratic hexahedra: 27 threads per element (a block holds 9 elements).
-// Thread r stages node r (coordinates, input) in LDS, then evaluates
-// quadrature point r of the 3x3x3 Gauss rule: the Jacobian J, its adjugate A
+// Hexahedra of order P = 2 (27 nodes) and 3 (64 nodes): (P+1)^3 threads per
+// element (a block holds 9 or 4 elements).  Thread r stages node r
+// (coordinates, input) in LDS, then evaluates quadrature point r of the
+// (P+1)^3 Gauss rule: the Jacobian J, its adjugate A
 // (rows the cross products of the columns, so J^-1 = A / det J) and the
 // reference gradients g of the input; it leaves in LDS the reference flux f,
 // with v_a = sum_q grad_hat phi_a(q) . f(q):
@@ -33,7 +34,6 @@ namespace q1 {
 namespace {
 
 constexpr int kFB = 256;  // threads per block
-constexpr int kQ2E = 9;   // triquadratic elements per block (27 threads each)
 
 __device__ __forceinline__ void gadd(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void gadd(float *p, float v) { unsafeAtomicAdd(p, v); }
@@ -99,36 +99,8 @@ __global__ __launch_bounds__(kFB) void k_tet_apply(int64_t ne, int64_t nn,
 #pragma unroll
     for (int j = 0; j < DPN; ++j) u[j][a] = fixed[a] ? T(0) : x[int64_t(nid[a]) * DPN + j];
   }
-  const TetGeom<T> G = tet_geom(X);
   T v[DPN][4];
-  if constexpr (PH == 1) {
-    T g[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-      g[r] = G.c[0][r] * u[0][0] + G.c[1][r] * u[0][1] + G.c[2][r] * u[0][2] + G.c[3][r] * u[0][3];
-    const T ks = coef[e] * G.s;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) v[0][a] = ks * dot3(G.c[a], g);
-  } else {
-    const T lam = coef[e], mu = coef[ne + e];
-    T H[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        H[i][j] = u[i][0] * G.c[0][j] + u[i][1] * G.c[1][j] + u[i][2] * G.c[2][j] +
-                  u[i][3] * G.c[3][j];
-    const T ltr = lam * (H[0][0] + H[1][1] + H[2][2]);
-    T S[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) S[i][j] = G.s * (mu * (H[i][j] + H[j][i]) + (i == j ? ltr : T(0)));
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) v[i][a] = dot3(S[i], G.c[a]);
-  }
+  tet_element<T, PH>(X, u, coef[e], PH == 3 ? coef[ne + e] : T(0), v);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
     if (!fixed[a])
@@ -171,51 +143,97 @@ __global__ __launch_bounds__(kFB) void k_tet_diag(int64_t ne, int64_t nn,
   }
 }
 
-// ---- triquadratic hexahedra ------------------------------------------------
+// ---- triquadratic and tricubic hexahedra ------------------------------------
+//
+// Order P = 2 (27 nodes) or 3 (64 nodes): nodes at t_m = -1 + 2m/P per
+// direction, local node a = i + (P+1) j + (P+1)^2 k, P+1 Gauss points per
+// direction.  A block holds 256 / (P+1)^3 elements, thread r of an element
+// staging node r and then evaluating quadrature point r.
 
-// 1-D quadratic Lagrange basis on [-1, 1] (nodes -1, 0, 1) and its derivative
-template <typename T>
-__device__ __forceinline__ T lq(int i, T t) {
-  return i == 0 ? T(0.5) * t * (t - T(1)) : i == 1 ? T(1) - t * t : T(0.5) * t * (t + T(1));
-}
-template <typename T>
-__device__ __forceinline__ T dlq(int i, T t) {
-  return i == 0 ? t - T(0.5) : i == 1 ? T(-2) * t : t + T(0.5);
-}
-// 3-point Gauss-Legendre point and weight
-template <typename T>
-__device__ __forceinline__ T gpt(int q) {
-  return q == 0 ? -T(0.77459666924148337703585307995648) : q == 1 ? T(0) : T(0.77459666924148337703585307995648);
-}
-template <typename T>
-__device__ __forceinline__ T gwt(int q) {
-  return q == 1 ? T(8) / T(9) : T(5) / T(9);
-}
-
-// The per-thread 1-D tables: basis and derivative of functions 0..2 at one
-// point (phase 2), or of one function at the points 0..2 (phase 3).
-template <typename T>
-struct Tab1 {
-  T b[3], d[3];
+template <int P>
+struct QP {
+  static constexpr int N = P + 1;          // nodes (and Gauss points) per direction
+  static constexpr int NPTS = N * N * N;   // nodes (and points) per element
+  static constexpr int E = 256 / NPTS;     // elements per block
 };
-template <typename T>
-__device__ __forceinline__ Tab1<T> at_point(int q) {
-  Tab1<T> t;
-  const T p = gpt<T>(q);
+
+// 1-D Lagrange basis of order P on [-1, 1] and its derivative (quadratic: the
+// closed forms; cubic: the product formula over the other nodes)
+template <typename T, int P>
+__device__ __forceinline__ T lag(int i, T t) {
+  if constexpr (P == 2) {
+    return i == 0 ? T(0.5) * t * (t - T(1)) : i == 1 ? T(1) - t * t : T(0.5) * t * (t + T(1));
+  } else {
+    T v = T(1);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    t.b[i] = lq<T>(i, p);
-    t.d[i] = dlq<T>(i, p);
+    for (int m = 0; m <= P; ++m)
+      if (m != i) v *= (t - (T(-1) + T(2 * m) / T(P))) / (T(2 * (i - m)) / T(P));
+    return v;
+  }
+}
+template <typename T, int P>
+__device__ __forceinline__ T dlag(int i, T t) {
+  if constexpr (P == 2) {
+    return i == 0 ? t - T(0.5) : i == 1 ? T(-2) * t : t + T(0.5);
+  } else {
+    T d = T(0);
+#pragma unroll
+    for (int l = 0; l <= P; ++l) {
+      if (l == i) continue;
+      T v = T(1) / (T(2 * (i - l)) / T(P));
+#pragma unroll
+      for (int m = 0; m <= P; ++m)
+        if (m != i && m != l) v *= (t - (T(-1) + T(2 * m) / T(P))) / (T(2 * (i - m)) / T(P));
+      d += v;
+    }
+    return d;
+  }
+}
+// Gauss-Legendre points and weights with P + 1 points
+template <typename T, int P>
+__device__ __forceinline__ T gpt(int q) {
+  if constexpr (P == 2) {
+    return q == 0 ? -T(0.77459666924148337703585307995648)
+                  : q == 1 ? T(0) : T(0.77459666924148337703585307995648);
+  } else {  // +-sqrt(3/7 +- (2/7) sqrt(6/5))
+    const T a = T(0.33998104358485626480266575910324), b = T(0.86113631159405257522394648889281);
+    return q == 0 ? -b : q == 1 ? -a : q == 2 ? a : b;
+  }
+}
+template <typename T, int P>
+__device__ __forceinline__ T gwt(int q) {
+  if constexpr (P == 2) {
+    return q == 1 ? T(8) / T(9) : T(5) / T(9);
+  } else {  // (18 +- sqrt(30)) / 36
+    const T wa = T(0.65214515486254614262693605077800), wb = T(0.34785484513745385737306394922200);
+    return q == 0 || q == 3 ? wb : wa;
+  }
+}
+
+// The per-thread 1-D tables: basis and derivative of the functions at one
+// point (phase 2), or of one function at the points (phase 3).
+template <typename T, int P>
+struct Tab1 {
+  T b[P + 1], d[P + 1];
+};
+template <typename T, int P>
+__device__ __forceinline__ Tab1<T, P> at_point(int q) {
+  Tab1<T, P> t;
+  const T p = gpt<T, P>(q);
+#pragma unroll
+  for (int i = 0; i <= P; ++i) {
+    t.b[i] = lag<T, P>(i, p);
+    t.d[i] = dlag<T, P>(i, p);
   }
   return t;
 }
-template <typename T>
-__device__ __forceinline__ Tab1<T> of_function(int i) {
-  Tab1<T> t;
+template <typename T, int P>
+__device__ __forceinline__ Tab1<T, P> of_function(int i) {
+  Tab1<T, P> t;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    t.b[q] = lq<T>(i, gpt<T>(q));
-    t.d[q] = dlq<T>(i, gpt<T>(q));
+  for (int q = 0; q <= P; ++q) {
+    t.b[q] = lag<T, P>(i, gpt<T, P>(q));
+    t.d[q] = dlag<T, P>(i, gpt<T, P>(q));
   }
   return t;
 }
@@ -223,10 +241,12 @@ __device__ __forceinline__ Tab1<T> of_function(int i) {
 // Phase 2 at quadrature point r of a staged element: the Jacobian's
 // adjugate rows A (A[0] = j1 x j2, A[1] = j2 x j0, A[2] = j0 x j1), det J, and
 // the reference gradients G of NF staged fields.
-template <typename T, int NF>
-__device__ __forceinline__ T q2_point(int r, const T (*sX)[27], const T (*sU)[27], T A[3][3],
-                                      T G[NF][3]) {
-  const Tab1<T> tx = at_point<T>(r % 3), ty = at_point<T>((r / 3) % 3), tz = at_point<T>(r / 9);
+template <typename T, int P, int NF>
+__device__ __forceinline__ T qp_point(int r, const T (*sX)[QP<P>::NPTS],
+                                      const T (*sU)[QP<P>::NPTS], T A[3][3], T G[NF][3]) {
+  constexpr int N = QP<P>::N, NPTS = QP<P>::NPTS;
+  const Tab1<T, P> tx = at_point<T, P>(r % N), ty = at_point<T, P>((r / N) % N),
+                   tz = at_point<T, P>(r / (N * N));
   T J[3][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -237,8 +257,8 @@ __device__ __forceinline__ T q2_point(int r, const T (*sX)[27], const T (*sU)[27
 #pragma unroll
     for (int d = 0; d < 3; ++d) G[f][d] = T(0);
 #pragma unroll
-  for (int a = 0; a < 27; ++a) {
-    const int i = a % 3, j = (a / 3) % 3, k = a / 9;
+  for (int a = 0; a < NPTS; ++a) {
+    const int i = a % N, j = (a / N) % N, k = a / (N * N);
     const T d0 = tx.d[i] * ty.b[j] * tz.b[k];
     const T d1 = tx.b[i] * ty.d[j] * tz.b[k];
     const T d2 = tx.b[i] * ty.b[j] * tz.d[k];
@@ -266,8 +286,8 @@ __device__ __forceinline__ T q2_point(int r, const T (*sX)[27], const T (*sU)[27
   return dot3(j0, A[0]);
 }
 
-template <typename T, int PH, bool MASKED>
-__global__ __launch_bounds__(kFB) void k_q2_apply(int64_t ne, int64_t nn,
+template <typename T, int PH, bool MASKED, int P>
+__global__ __launch_bounds__(kFB) void k_qp_apply(int64_t ne, int64_t nn,
                                                   const T *__restrict__ xyz,
                                                   const int32_t *__restrict__ conn,
                                                   const T *__restrict__ coef,
@@ -275,13 +295,14 @@ __global__ __launch_bounds__(kFB) void k_q2_apply(int64_t ne, int64_t nn,
                                                   const T *__restrict__ x, T *__restrict__ y,
                                                   const int *__restrict__ stop) {
   constexpr int DPN = phys_dpn(PH);
+  constexpr int N = QP<P>::N, NPTS = QP<P>::NPTS, E = QP<P>::E;
   if (stop && *stop) return;
-  __shared__ T sX[kQ2E][3][27];
-  __shared__ T sU[kQ2E][DPN][27];
-  __shared__ T sF[kQ2E][DPN][3][27];  // reference flux: [component][direction][point]
-  const int le = int(threadIdx.x) / 27, r = int(threadIdx.x) - 27 * le;
-  const int64_t e = int64_t(blockIdx.x) * kQ2E + le;
-  const bool active = le < kQ2E && e < ne;
+  __shared__ T sX[E][3][NPTS];
+  __shared__ T sU[E][DPN][NPTS];
+  __shared__ T sF[E][DPN][3][NPTS];  // reference flux: [component][direction][point]
+  const int le = int(threadIdx.x) / NPTS, r = int(threadIdx.x) - NPTS * le;
+  const int64_t e = int64_t(blockIdx.x) * E + le;
+  const bool active = le < E && e < ne;
   int64_t g = 0;
   bool fixed = true;
   if (active) {  // phase 1: node r
@@ -295,8 +316,8 @@ __global__ __launch_bounds__(kFB) void k_q2_apply(int64_t ne, int64_t nn,
   __syncthreads();
   if (active) {  // phase 2: quadrature point r
     T A[3][3], G[DPN][3];
-    const T det = q2_point<T, DPN>(r, sX[le], sU[le], A, G);
-    const T s = gwt<T>(r % 3) * gwt<T>((r / 3) % 3) * gwt<T>(r / 9) * rcp(det);
+    const T det = qp_point<T, P, DPN>(r, sX[le], sU[le], A, G);
+    const T s = gwt<T, P>(r % N) * gwt<T, P>((r / N) % N) * gwt<T, P>(r / (N * N)) * rcp(det);
     if constexpr (PH == 1) {
       T p[3];  // det J times the physical gradient
 #pragma unroll
@@ -324,14 +345,14 @@ __global__ __launch_bounds__(kFB) void k_q2_apply(int64_t ne, int64_t nn,
   }
   __syncthreads();
   if (active && !fixed) {  // phase 3: node r gathers the test-function products
-    const Tab1<T> fx = of_function<T>(r % 3), fy = of_function<T>((r / 3) % 3),
-                  fz = of_function<T>(r / 9);
+    const Tab1<T, P> fx = of_function<T, P>(r % N), fy = of_function<T, P>((r / N) % N),
+                     fz = of_function<T, P>(r / (N * N));
     T v[DPN];
 #pragma unroll
     for (int j = 0; j < DPN; ++j) v[j] = T(0);
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-      const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+    for (int q = 0; q < NPTS; ++q) {
+      const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
       const T d0 = fx.d[qx] * fy.b[qy] * fz.b[qz];
       const T d1 = fx.b[qx] * fy.d[qy] * fz.b[qz];
       const T d2 = fx.b[qx] * fy.b[qy] * fz.d[qz];
@@ -347,19 +368,20 @@ __global__ __launch_bounds__(kFB) void k_q2_apply(int64_t ne, int64_t nn,
 // diag: Laplace sum_q k w |t|^2 / det J, elasticity
 // sum_q w ((lambda + mu) t_i^2 + mu |t|^2) / det J, with t = sum_c dphi_c A[c]
 // (det J times the physical gradient of the node's basis function)
-template <typename T, int PH, bool MASKED>
-__global__ __launch_bounds__(kFB) void k_q2_diag(int64_t ne, int64_t nn,
+template <typename T, int PH, bool MASKED, int P>
+__global__ __launch_bounds__(kFB) void k_qp_diag(int64_t ne, int64_t nn,
                                                  const T *__restrict__ xyz,
                                                  const int32_t *__restrict__ conn,
                                                  const T *__restrict__ coef,
                                                  const uint8_t *__restrict__ mask,
                                                  T *__restrict__ dg) {
   constexpr int DPN = phys_dpn(PH);
-  __shared__ T sX[kQ2E][3][27];
-  __shared__ T sA[kQ2E][10][27];  // adjugate rows and w / det J per point
-  const int le = int(threadIdx.x) / 27, r = int(threadIdx.x) - 27 * le;
-  const int64_t e = int64_t(blockIdx.x) * kQ2E + le;
-  const bool active = le < kQ2E && e < ne;
+  constexpr int N = QP<P>::N, NPTS = QP<P>::NPTS, E = QP<P>::E;
+  __shared__ T sX[E][3][NPTS];
+  __shared__ T sA[E][10][NPTS];  // adjugate rows and w / det J per point
+  const int le = int(threadIdx.x) / NPTS, r = int(threadIdx.x) - NPTS * le;
+  const int64_t e = int64_t(blockIdx.x) * E + le;
+  const bool active = le < E && e < ne;
   int64_t g = 0;
   bool fixed = true;
   if (active) {
@@ -371,24 +393,24 @@ __global__ __launch_bounds__(kFB) void k_q2_diag(int64_t ne, int64_t nn,
   __syncthreads();
   if (active) {
     T A[3][3], G[1][3];  // (the coordinate field stands in for the unused input)
-    const T det = q2_point<T, 1>(r, sX[le], sX[le], A, G);
+    const T det = qp_point<T, P, 1>(r, sX[le], sX[le], A, G);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int m = 0; m < 3; ++m) sA[le][3 * c + m][r] = A[c][m];
-    sA[le][9][r] = gwt<T>(r % 3) * gwt<T>((r / 3) % 3) * gwt<T>(r / 9) * rcp(det);
+    sA[le][9][r] = gwt<T, P>(r % N) * gwt<T, P>((r / N) % N) * gwt<T, P>(r / (N * N)) * rcp(det);
   }
   __syncthreads();
   if (active && !fixed) {
-    const Tab1<T> fx = of_function<T>(r % 3), fy = of_function<T>((r / 3) % 3),
-                  fz = of_function<T>(r / 9);
+    const Tab1<T, P> fx = of_function<T, P>(r % N), fy = of_function<T, P>((r / N) % N),
+                     fz = of_function<T, P>(r / (N * N));
     T acc[DPN];
 #pragma unroll
     for (int j = 0; j < DPN; ++j) acc[j] = T(0);
     const T c0 = coef[e], c1 = PH == 3 ? coef[ne + e] : T(0);
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-      const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+    for (int q = 0; q < NPTS; ++q) {
+      const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
       const T d0 = fx.d[qx] * fy.b[qy] * fz.b[qz];
       const T d1 = fx.b[qx] * fy.d[qy] * fz.b[qz];
       const T d2 = fx.b[qx] * fy.b[qy] * fz.d[qz];
@@ -425,9 +447,14 @@ int family_apply_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *s
       hipLaunchKernelGGL((m ? k_tet_apply<T, PH, true> : k_tet_apply<T, PH, false>), grid,
                          dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask,
                          x, y, stop);
+    } else if (op.elem == Q1_HEX27) {
+      const dim3 grid(unsigned((op.n_elems + QP<2>::E - 1) / QP<2>::E));
+      hipLaunchKernelGGL((m ? k_qp_apply<T, PH, true, 2> : k_qp_apply<T, PH, false, 2>), grid,
+                         dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask,
+                         x, y, stop);
     } else {
-      const dim3 grid(unsigned((op.n_elems + kQ2E - 1) / kQ2E));
-      hipLaunchKernelGGL((m ? k_q2_apply<T, PH, true> : k_q2_apply<T, PH, false>), grid,
+      const dim3 grid(unsigned((op.n_elems + QP<3>::E - 1) / QP<3>::E));
+      hipLaunchKernelGGL((m ? k_qp_apply<T, PH, true, 3> : k_qp_apply<T, PH, false, 3>), grid,
                          dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask,
                          x, y, stop);
     }
@@ -451,9 +478,13 @@ int family_diag_t(Op &op, void *dv, hipStream_t s) {
       const dim3 grid(unsigned((op.n_elems + kFB - 1) / kFB));
       hipLaunchKernelGGL((m ? k_tet_diag<T, PH, true> : k_tet_diag<T, PH, false>), grid,
                          dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask, d);
+    } else if (op.elem == Q1_HEX27) {
+      const dim3 grid(unsigned((op.n_elems + QP<2>::E - 1) / QP<2>::E));
+      hipLaunchKernelGGL((m ? k_qp_diag<T, PH, true, 2> : k_qp_diag<T, PH, false, 2>), grid,
+                         dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask, d);
     } else {
-      const dim3 grid(unsigned((op.n_elems + kQ2E - 1) / kQ2E));
-      hipLaunchKernelGGL((m ? k_q2_diag<T, PH, true> : k_q2_diag<T, PH, false>), grid,
+      const dim3 grid(unsigned((op.n_elems + QP<3>::E - 1) / QP<3>::E));
+      hipLaunchKernelGGL((m ? k_qp_diag<T, PH, true, 3> : k_qp_diag<T, PH, false, 3>), grid,
                          dim3(kFB), 0, s, op.n_elems, op.n_nodes, xyz, op.conn, coef, op.mask, d);
     }
   }
@@ -464,6 +495,7 @@ int family_diag_t(Op &op, void *dv, hipStream_t s) {
 }  // namespace
 
 int launch_apply_family(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
+  if (op.variant == Q1_V_BLOCK) return launch_apply_tile(op, x, y, s, stop);  // tetrahedra
   const bool f64 = op.dtype == Q1_F64;
   if (op.physics == Q1_LAPLACE)
     return f64 ? family_apply_t<double, 1>(op, x, y, s, stop)

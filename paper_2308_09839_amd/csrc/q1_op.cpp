@@ -25,6 +25,10 @@ constexpr double kFlopsTetElasticity = 220.0;
 // adjugate, determinant and flux (about 70 Laplace, 150 elasticity)
 constexpr double kFlopsQ2Laplace = 4 * 1296.0 + 1296.0 + 27 * 70.0;
 constexpr double kFlopsQ2Elasticity = 6 * 1296.0 + 3 * 1296.0 + 27 * 150.0;
+// tricubic hexahedra, the same model with 4 points per direction: 16 x 4^4 =
+// 4,096 FLOPs per field and pass, plus the per-point work at 64 points
+constexpr double kFlopsQ3Laplace = 4 * 4096.0 + 4096.0 + 64 * 70.0;
+constexpr double kFlopsQ3Elasticity = 6 * 4096.0 + 3 * 4096.0 + 64 * 150.0;
 
 int check_device_ptr(const void *p, const char *what) {
   if (!p) return fail(Q1_EINVAL, "%s is NULL", what);
@@ -60,8 +64,8 @@ int q1_op_create_elem(q1_op **out, int elem, int physics, int dtype, int variant
                       const void *coef_d, const uint8_t *mask_d, void *stream) {
   Q1_CHECK(out, Q1_EINVAL, "q1_op_create: NULL handle pointer");
   *out = nullptr;
-  Q1_CHECK(elem == Q1_HEX8 || elem == Q1_TET4 || elem == Q1_HEX27, Q1_EINVAL,
-           "q1_op_create: element family must be 8, 4 or 27, got %d", elem);
+  Q1_CHECK(elem == Q1_HEX8 || elem == Q1_TET4 || elem == Q1_HEX27 || elem == Q1_HEX64, Q1_EINVAL,
+           "q1_op_create: element family must be 8, 4, 27 or 64, got %d", elem);
   Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_VLAPLACE || physics == Q1_ELASTICITY,
            Q1_EINVAL,
            "q1_op_create: physics must be 1 (Laplace), 2 (vector Laplace) or 3 (elasticity), "
@@ -77,8 +81,11 @@ int q1_op_create_elem(q1_op **out, int elem, int physics, int dtype, int variant
   if (elem != Q1_HEX8) {
     Q1_CHECK(physics == Q1_LAPLACE || physics == Q1_ELASTICITY, Q1_EUNSUPPORTED,
              "q1_op_create: element family %d supports scalar Laplace and elasticity", elem);
-    Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC, Q1_EUNSUPPORTED,
-             "q1_op_create: element family %d supports the atomic-scatter apply only", elem);
+    Q1_CHECK(variant == Q1_V_AUTO || variant == Q1_V_ATOMIC ||
+                 (elem == Q1_TET4 && variant == Q1_V_BLOCK),
+             Q1_EUNSUPPORTED,
+             "q1_op_create: element family %d supports the atomic-scatter apply (and "
+             "tetrahedra the block tiles) only", elem);
   }
   int rc;
   if ((rc = check_device_ptr(xyz_d, "xyz"))) return rc;
@@ -98,8 +105,10 @@ int q1_op_create_elem(q1_op **out, int elem, int physics, int dtype, int variant
   op->elem = elem;
   op->dtype = dtype;
   // AUTO: the block-staged tiles (fastest measured), else the one-wave tiles, else atomics
-  op->variant = variant == Q1_V_AUTO ? (n_elems > 0 && elem == Q1_HEX8 ? Q1_V_BLOCK : Q1_V_ATOMIC)
-                                     : variant;
+  op->variant = variant == Q1_V_AUTO
+                    ? (n_elems > 0 && (elem == Q1_HEX8 || elem == Q1_TET4) ? Q1_V_BLOCK
+                                                                           : Q1_V_ATOMIC)
+                    : variant;
   op->n_nodes = n_nodes;
   op->n_elems = n_elems;
   op->xyz = xyz_d;
@@ -122,7 +131,8 @@ int q1_op_create_elem(q1_op **out, int elem, int physics, int dtype, int variant
   }
   if (op->variant == Q1_V_LDS_TILE || op->variant == Q1_V_BLOCK || op->variant == Q1_V_PA) {
     rc = build_tiles(*op, static_cast<hipStream_t>(stream));
-    if (rc && variant == Q1_V_AUTO && rc == Q1_EUNSUPPORTED && op->variant == Q1_V_BLOCK) {
+    if (rc && variant == Q1_V_AUTO && rc == Q1_EUNSUPPORTED && op->variant == Q1_V_BLOCK &&
+        elem == Q1_HEX8) {
       free_tiles(*op);  // tiles too large for LDS: one-wave tiles
       op->variant = Q1_V_LDS_TILE;
       rc = build_tiles(*op, static_cast<hipStream_t>(stream));
@@ -201,7 +211,9 @@ int q1_op_bytes(const q1_op *op, double *bytes, double *flops) {
     if (flops)
       *flops = double(op->n_elems) * (op->elem == Q1_TET4
                                           ? (lap ? kFlopsTetLaplace : kFlopsTetElasticity)
-                                          : (lap ? kFlopsQ2Laplace : kFlopsQ2Elasticity));
+                                          : op->elem == Q1_HEX27
+                                                ? (lap ? kFlopsQ2Laplace : kFlopsQ2Elasticity)
+                                                : (lap ? kFlopsQ3Laplace : kFlopsQ3Elasticity));
     return Q1_OK;
   }
   double b = 0.0;

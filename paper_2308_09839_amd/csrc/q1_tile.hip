@@ -44,16 +44,25 @@ constexpr uint32_t kIdMask = 0x3fffffffu;
 // scalar kind's 16 x 8 x 4 tiles, one for the 3-DOF kinds' 16 x 4 x 4
 __host__ __device__ constexpr int split_steps(int dpn) { return dpn == 1 ? 2 : 1; }
 
+// i / d for 0 <= i < 2^16 and 0 < d < 2^16: the single-precision quotient is
+// within one of the exact one, and one correction each way makes it exact.
+__host__ __device__ inline int div_small(int i, int d) {
+  int q = int(float(i) * (1.0f / float(d)));
+  q -= q * d > i ? 1 : 0;
+  q += (q + 1) * d <= i ? 1 : 0;
+  return q;
+}
+
 // Corner indices of lane `lane` at position `rel` of a lattice tile (the
 // interleaved layout; see lattice_of); false for an empty lane.
 __host__ __device__ inline bool corner_lattice(uint32_t lat, int rel, int lane, int (&lc)[8]) {
   const int A = int(lat & 0xff), B = int((lat >> 8) & 0xff), spl = int((lat >> 16) & 0xff),
             C = int(lat >> 24);
-  const int w = rel & 3, k = rel >> 2, kl = k / spl;
+  const int w = rel & 3, k = rel >> 2, kl = div_small(k, spl);
   const int iz = w + 4 * kl, e = (k - kl * spl) * kLanes + lane;
   if (iz >= C || e >= A * B) return false;
-  const int a1 = A + 1, ab1 = (A + 1) * (B + 1);
-  const int base = e % A + a1 * (e / A) + ab1 * iz;
+  const int a1 = A + 1, ab1 = (A + 1) * (B + 1), ey = div_small(e, A);
+  const int base = (e - ey * A) + a1 * ey + ab1 * iz;
 #pragma unroll
   for (int a = 0; a < 8; ++a) lc[a] = base + (a & 1) + a1 * ((a >> 1) & 1) + ab1 * (a >> 2);
   return true;
@@ -66,14 +75,6 @@ __host__ __device__ inline bool corner_lattice(uint32_t lat, int rel, int lane, 
 // x-low, x-high, y-low, y-high, z-low, z-high), so the node words are not
 // loaded.  i = ix + (A+1)(iy + (B+1) iz).
 constexpr uint32_t kAddrValid = 0x80000000u;
-// i / d for 0 <= i < 2^16 and 0 < d < 2^16: the single-precision quotient is
-// within one of the exact one, and one correction each way makes it exact.
-__host__ __device__ inline int div_small(int i, int d) {
-  int q = int(float(i) * (1.0f / float(d)));
-  q -= q * d > i ? 1 : 0;
-  q += (q + 1) * d <= i ? 1 : 0;
-  return q;
-}
 __host__ __device__ inline uint32_t lattice_word(int i, uint32_t lat, uint32_t addr, int64_t g0,
                                                  int64_t sy, int64_t sz) {
   const int A = int(lat & 0xff), B = int((lat >> 8) & 0xff), C = int(lat >> 24);
@@ -510,6 +511,76 @@ __global__ __launch_bounds__(256) void k_apply_block(
   for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, word(i), slot[n0 + i]);
 }
 
+// Block apply of linear tetrahedra: the block kernel's staging, write-back
+// and halo slots with the tetrahedron's element (tet_element); a tile is a
+// brick of cells' tetrahedra, wave w takes its steps w, w + 4, ... and adds
+// each tetrahedron's 4 corner contributions into one LDS accumulator with LDS
+// atomics (the order of those additions varies).
+template <typename T, int PH>
+__global__ __launch_bounds__(256) void k_apply_block_tet(
+    int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
+    const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
+    const uint4 *__restrict__ lconn, const T *__restrict__ coef_t, int64_t coef_stride,
+    const T *__restrict__ xyz, const T *__restrict__ x, T *__restrict__ y,
+    const int *__restrict__ stop, const int32_t *__restrict__ slot, T *__restrict__ halo) {
+  constexpr int DPN = phys_dpn(PH);
+  if (stop && *stop) return;
+  constexpr int NR = 3 + DPN;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][max_nodes]
+  T *sV = sR + size_t(NR) * max_nodes;       // [DPN][max_nodes]
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tile = xcd_block_t(blockIdx.x, gridDim.x);
+  const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
+  const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
+  for (int i = tid; i < nm; i += 256) {
+    const uint32_t raw = nodes[n0 + i];
+    const int64_t g = raw & kIdMask;
+    const bool fixed = (raw & kFixedBit) != 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) sR[size_t(r) * max_nodes + i] = xyz[r * nn + g];
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) {
+      sR[size_t(3 + j) * max_nodes + i] = fixed ? T(0) : x[g * DPN + j];
+      sV[size_t(j) * max_nodes + i] = T(0);
+    }
+  }
+  __syncthreads();
+  for (int s = s0 + w; s < s1; s += 4) {
+    const int64_t sl = int64_t(s) * kLanes + lane;
+    const uint4 pk = lconn[sl];
+    if (pk.x == 0xffffffffu) continue;  // empty lane
+    const int lc[4] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16)};
+    T X[3][4], u[DPN][4], v[DPN][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) X[r][a] = sR[size_t(r) * max_nodes + lc[a]];
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) u[j][a] = sR[size_t(3 + j) * max_nodes + lc[a]];
+    }
+    tet_element<T, PH>(X, u, coef_t[sl], PH == 3 ? coef_t[coef_stride + sl] : T(0), v);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) lds_add(&sV[size_t(j) * max_nodes + lc[a]], v[j][a]);
+  }
+  __syncthreads();
+  for (int i = tid; i < nm; i += 256) {
+    const uint32_t raw = nodes[n0 + i];
+    if (raw & kFixedBit) continue;  // y = x written by k_halo_sum
+    const int64_t g = raw & kIdMask;
+#pragma unroll
+    for (int j = 0; j < DPN; ++j) {
+      const T v = sV[size_t(j) * max_nodes + i];
+      if (raw & kSharedBit)
+        halo[int64_t(slot[n0 + i]) * DPN + j] = v;
+      else
+        y[g * DPN + j] = v;
+    }
+  }
+}
+
 // Diagonal of A on the block variants' tiles with the split accumulation
 // (bitwise reproducible): one workgroup per tile stages the coordinates,
 // each element's diagonal entries (element_diag) are added into LDS in the
@@ -772,16 +843,20 @@ bool split_ok(const HostTiles &H, int t, int nm, int dpn) {
 
 // Group elements into tiles and steps; record node lists and corner indices.
 template <typename T>
+// nloc: nodes per element (8 hexahedra, 4 tetrahedra; a tetrahedron's corner
+// indices fill the first 4 of its 8 lane entries); cell_elems: elements per
+// cell of the size estimate (6 for tetrahedra, as in a cube's split).
 int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
                const std::vector<uint8_t> &mask, int64_t nn, int64_t ne, int patch_x,
-               int patch_y, int layers, bool interleave, int dpn, HostTiles &H) {
+               int patch_y, int layers, bool interleave, int dpn, HostTiles &H, int nloc = 8,
+               double cell_elems = 1.0) {
   std::vector<double> cen(size_t(3) * ne);
   double lo[3] = {1e300, 1e300, 1e300};
   for (int64_t e = 0; e < ne; ++e)
     for (int r = 0; r < 3; ++r) {
       double c = 0;
-      for (int a = 0; a < 8; ++a) c += double(xyz[r * nn + conn[a * ne + e]]);
-      c *= 0.125;
+      for (int a = 0; a < nloc; ++a) c += double(xyz[r * nn + conn[a * ne + e]]);
+      c /= nloc;
       cen[3 * e + r] = c;
       lo[r] = std::min(lo[r], c);
     }
@@ -796,7 +871,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
     }
     if (nhi > nlo) { vol *= nhi - nlo; ++live; }
   }
-  double h = live ? std::pow(vol / double(ne), 1.0 / live) : 1.0;
+  double h = live ? std::pow(vol * cell_elems / double(ne), 1.0 / live) : 1.0;
   if (!(h > 0)) h = 1.0;
   std::vector<int32_t> lz(ne), iy(ne), ix(ne);
   int64_t npx = 1, npy = 1;
@@ -828,7 +903,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
   std::vector<int32_t> stamp(nn, -1), ntile(nn, 0);
   for (int t = 0; t < n_tiles; ++t)
     for (int64_t k = tb[t]; k < tb[t + 1]; ++k)
-      for (int a = 0; a < 8; ++a) {
+      for (int a = 0; a < nloc; ++a) {
         const int32_t g = conn[a * ne + order[k]];
         if (stamp[g] != t) { stamp[g] = t; ++ntile[g]; }
       }
@@ -838,7 +913,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
   for (int t = 0; t < n_tiles; ++t) {
     list.clear();
     for (int64_t k = tb[t]; k < tb[t + 1]; ++k)
-      for (int a = 0; a < 8; ++a) list.push_back(conn[a * ne + order[k]]);
+      for (int a = 0; a < nloc; ++a) list.push_back(conn[a * ne + order[k]]);
     std::sort(list.begin(), list.end());
     list.erase(std::unique(list.begin(), list.end()), list.end());
     if (list.size() >= 65535) return fail(Q1_EUNSUPPORTED, "tile with %zu nodes", list.size());
@@ -864,7 +939,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
       while (je < tb[t + 1] && lz[order[je]] == lz[order[j]] && je - j < kLanes) ++je;
       if (j == tb[t] || lz[order[j]] != lz[order[j - 1]]) ++layer;
       runs.push_back({j, je, int(layer)});
-      for (int a = 0; a < 8 && !H.corner_collision; ++a) {
+      for (int a = 0; a < nloc && !H.corner_collision; ++a) {
         std::vector<int32_t> cs;
         for (int64_t k = j; k < je; ++k) cs.push_back(conn[a * ne + order[k]]);
         std::sort(cs.begin(), cs.end());
@@ -891,7 +966,8 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
         if (r >= 0 && runs[r].j + k < runs[r].je) {
           const int32_t e = order[runs[r].j + k];
           H.step_elem.push_back(e);
-          for (int a = 0; a < 8; ++a) H.lconn.push_back(uint16_t(local[conn[a * ne + e]]));
+          for (int a = 0; a < 8; ++a)
+            H.lconn.push_back(a < nloc ? uint16_t(local[conn[a * ne + e]]) : uint16_t(0));
         } else {
           H.step_elem.push_back(-1);
           for (int a = 0; a < 8; ++a) H.lconn.push_back(0xffff);
@@ -900,7 +976,7 @@ int plan_tiles(const std::vector<int32_t> &conn, const std::vector<T> &xyz,
     H.tile_step.push_back(int32_t(H.step_elem.size() / kLanes));
     H.tile_lat.push_back(interleave ? lattice_of(H, t) : 0u);
     if (interleave && !split_ok(H, t, int(list.size()), dpn)) H.split = false;
-    bool aff = true;  // the kernel's own exact test, in the operator's precision
+    bool aff = nloc == 8;  // the kernel's own exact test, in the operator's precision
     for (int64_t k = tb[t]; k < tb[t + 1] && aff; ++k) {
       T X[3][8];
       for (int r = 0; r < 3; ++r) {
@@ -999,7 +1075,8 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   TileMap &tm = op.tiles;
   Q1_CHECK(nn <= int64_t(kIdMask), Q1_EUNSUPPORTED, "LDS-tile variant supports < 2^30 nodes");
   Q1_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> conn(size_t(8) * ne);
+  const int nloc = op.nloc();
+  std::vector<int32_t> conn(size_t(nloc) * ne);
   std::vector<T> xyz(size_t(3) * nn), coef(size_t(ncoef) * ne);
   std::vector<uint8_t> mask;
   Q1_HIP(hipMemcpy(conn.data(), op.conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1013,12 +1090,14 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
     Q1_CHECK(conn[i] >= 0 && conn[i] < nn, Q1_EINVAL, "connectivity entry %zu out of range", i);
   HostTiles H;
   const bool block = op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA;
-  int rc = plan_tiles<T>(conn, xyz, mask, nn, ne, patch_x, patch_y, layers, block, op.dpn(), H);
+  const bool hex = op.elem == Q1_HEX8;
+  int rc = plan_tiles<T>(conn, xyz, mask, nn, ne, patch_x, patch_y, layers, block && hex,
+                         op.dpn(), H, nloc, hex ? 1.0 : 6.0);
   if (rc) return rc;
   // lattice addressing for the scalar kind only: measured on 128^3 Laplace FP64
   // (applies streaming from HBM) 46.8 against 44.9 GDOF/s, while the 3-DOF kinds
   // (fewer nodes per element, more arithmetic per node) ran 3-5% slower with it
-  if (block && op.dpn() == 1) plan_addressing(H);
+  if (block && hex && op.dpn() == 1) plan_addressing(H);
   else {
     H.tile_addr.assign(H.tile_lat.size(), 0u);
     H.tile_g0.assign(H.tile_lat.size(), 0);
@@ -1036,7 +1115,7 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   tm.n_reset = int64_t(H.reset.size());
   tm.n_entries = int64_t(H.nodes.size());
   tm.lds_atomic = H.corner_collision;
-  tm.split = block && H.split && !H.corner_collision;
+  tm.split = block && hex && H.split && !H.corner_collision;
   tm.all_affine = std::all_of(H.tile_affine.begin(), H.tile_affine.end(),
                               [](uint8_t a) { return a != 0; });
   auto up = [&](auto **dst, const auto &v) -> int {
@@ -1095,7 +1174,7 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
 // one per wave for FP32)
 size_t block_lds_bytes(const Op &op) {
   const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
-  const size_t nacc = op.tiles.split || op.dtype == Q1_F64 ? 1 : 4;
+  const size_t nacc = op.tiles.split || op.dtype == Q1_F64 || op.elem == Q1_TET4 ? 1 : 4;
   const size_t ncoord = op.variant == Q1_V_PA ? 0 : 3;
   return size_t(op.tiles.max_nodes) * rb * size_t(ncoord + op.dpn() + nacc * op.dpn());
 }
@@ -1112,6 +1191,25 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
     hipLaunchKernelGGL((k_reset_nodes<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
                        s, tm.n_reset, tm.reset, op.mask, x, y, stop);
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
+  if (block && op.elem == Q1_TET4) {
+    if constexpr (PH != 2) {
+      const size_t tl = size_t(tm.max_nodes) * sizeof(T) * (3 + 2 * DPN);
+      hipLaunchKernelGGL((k_apply_block_tet<T, PH>), dim3(tm.n_tiles), dim3(256), tl, s,
+                         tm.max_nodes, op.n_nodes, tm.node_ptr, tm.nodes, tm.tile_step,
+                         reinterpret_cast<const uint4 *>(tm.lconn),
+                         static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
+                         static_cast<const T *>(op.xyz), x, y, stop, tm.slot,
+                         static_cast<T *>(tm.halo));
+      if (tm.n_reset > 0)
+        hipLaunchKernelGGL((k_halo_sum<T, DPN>),
+                           dim3(int((tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt))),
+                           dim3(256), 0, s, tm.n_reset, tm.hnode, tm.hptr, x,
+                           static_cast<const T *>(tm.halo), y, stop);
+      Q1_HIP(hipGetLastError());
+      return Q1_OK;
+    }
+    return fail(Q1_EUNSUPPORTED, "tetrahedra: scalar Laplace and elasticity");
+  }
   if (block) {
     // fallback accumulation when some tile does not admit the split one
     constexpr int FB = std::is_same<T, double>::value ? kAccShared : kAccCopies;

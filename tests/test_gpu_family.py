@@ -1,4 +1,4 @@
-"""GPU parity of the linear-tetrahedron and triquadratic-hexahedron operators
+"""GPU parity of the linear-tetrahedron, triquadratic- and tricubic-hexahedron operators
 (q1_op_create_elem) against the CPU oracle's assembled matrices: applies and
 diagonals at 1e-12 (FP64) and 2e-5 (FP32), null spaces, full-size sampled
 rows, Jacobi-PCG through the generic solvers, and the unsupported requests."""
@@ -23,9 +23,12 @@ def family_problem(elem, physics, n, jitter, seed, mask=True, h=1.0):
     if elem == 4:
         xyz, conn = si.tet_mesh(*n, h, jitter, seed)
         m = si.face_mask(*n, "z0") if mask else None
-    else:
+    elif elem == 27:
         xyz, conn = si.q2_box_mesh(*n, h, jitter, seed)
         m = si.q2_face_mask(*n, "z0") if mask else None
+    else:
+        xyz, conn = si.q3_box_mesh(*n, h, jitter, seed)
+        m = si.q3_face_mask(*n, "z0") if mask else None
     ne = conn.shape[1]
     if physics == 1:
         coef = si.field_lognormal(ne, 0.0, 1.0, seed)[None]
@@ -60,18 +63,24 @@ CASES = [
     (27, 1, (5, 2, 1), 0.0, False),  # 10 elements: one full block of 9 and one of 1
     (27, 3, (3, 3, 2), 0.1, True),
     (27, 3, (1, 1, 1), 0.1, False),
+    (64, 1, (3, 3, 2), 0.1, True),
+    (64, 1, (3, 2, 1), 0.0, False),  # 6 elements: one full block of 4 and one of 2
+    (64, 3, (2, 2, 2), 0.1, True),
+    (64, 3, (1, 1, 1), 0.1, False),
 ]
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("elem,physics,n,jitter,mask", CASES)
-def test_family_apply_parity(q1, orc, elem, physics, n, jitter, mask, dtype):
-    print(f"\n[family apply] elem={elem} physics={physics} n={n} dtype={dtype}", flush=True)
+def test_family_apply_parity(q1, orc, elem, physics, n, jitter, mask, dtype, variant):
+    print(f"\n[family apply] elem={elem} physics={physics} n={n} dtype={dtype} "
+          f"variant={variant}", flush=True)
     pr = family_problem(elem, physics, n, jitter, 2308, mask)
     A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
     x = si.vec_uniform(A.n, 2308, si.STREAM_X)
     ref = A.matvec(x)
-    op = make_family_op(q1, pr, dtype)
+    op = make_family_op(q1, pr, dtype, variant)
     y = apply(op, x, dtype)
     assert rel_err(y, ref) <= TOL[dtype], rel_err(y, ref)
     assert np.max(np.abs(y - ref)) <= 10 * TOL[dtype] * np.max(np.abs(ref))
@@ -81,7 +90,8 @@ def test_family_apply_parity(q1, orc, elem, physics, n, jitter, mask, dtype):
     torch.cuda.synchronize()
     dref = A.diag()
     assert np.max(np.abs(d.double().cpu().numpy() - dref)) <= 10 * TOL[dtype] * np.max(np.abs(dref))
-    assert op.info()["variant"] == 1
+    # the default: block tiles for tetrahedra, the atomic scatter for the hexahedra
+    assert op.info()["variant"] == (5 if elem == 4 and variant == 0 else 1)
 
 
 def torch_empty(n, dtype):
@@ -89,12 +99,13 @@ def torch_empty(n, dtype):
     return torch.empty(n, dtype=torch_dtype(dtype), device="cuda")
 
 
-@pytest.mark.parametrize("elem", [4, 27])
+@pytest.mark.parametrize("elem", [4, 27, 64])
 def test_family_dense(q1, orc, elem):
     """Apply to every unit vector: the columns are the assembled matrix."""
     import torch
     for physics in (1, 3):
-        pr = family_problem(elem, physics, (2, 1, 2) if elem == 4 else (1, 2, 1), 0.1, 41)
+        n = {4: (2, 1, 2), 27: (1, 2, 1), 64: (1, 1, 1)}[elem]
+        pr = family_problem(elem, physics, n, 0.1, 41)
         Ad = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"]).to_dense()
         op = make_family_op(q1, pr)
         N = Ad.shape[0]
@@ -109,15 +120,15 @@ def test_family_dense(q1, orc, elem):
         assert np.max(np.abs(cols - Ad)) <= 1e-13 * np.max(np.abs(Ad))
 
 
-@pytest.mark.parametrize("elem", [4, 27])
+@pytest.mark.parametrize("elem", [4, 27, 64])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_family_null_spaces(q1, orc, elem, dtype):
     bound = 1e-13 if dtype == 0 else 2e-6
-    pr = family_problem(elem, 1, (4, 3, 3), 0.1, 43, mask=False)
+    pr = family_problem(elem, 1, (4, 3, 3) if elem != 64 else (3, 2, 2), 0.1, 43, mask=False)
     A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"])
     y = apply(make_family_op(q1, pr, dtype), np.ones(pr["xyz"].shape[1]), dtype)
     assert np.max(np.abs(y)) <= bound * np.max(np.abs(A.val)) * 30
-    pr = family_problem(elem, 3, (3, 3, 2), 0.1, 44, mask=False)
+    pr = family_problem(elem, 3, (3, 3, 2) if elem != 64 else (2, 2, 1), 0.1, 44, mask=False)
     A = orc.assemble(3, pr["xyz"], pr["conn"], pr["coef"])
     op = make_family_op(q1, pr, dtype)
     for u in rigid_modes(pr["xyz"]):
@@ -125,36 +136,43 @@ def test_family_null_spaces(q1, orc, elem, dtype):
         assert np.max(np.abs(y)) <= bound * np.max(np.abs(A.val)) * np.max(np.abs(u)) * 30
 
 
-@pytest.mark.parametrize("elem", [4, 27])
+@pytest.mark.parametrize("elem", [4, 27, 64])
 def test_family_full_size_rows(q1, orc, elem):
     """The benchmark sizes (Kuhn-split 128^3 box, 12,582,912 tetrahedra;
-    64^3 triquadratic box, 2,146,689 nodes) with the layered coefficient, FP64
-    and FP32: sampled rows against the oracle's element-by-element rows."""
+    64^3 triquadratic box, 2,146,689 nodes; 42^3 tricubic box, 2,048,383
+    nodes) with the layered coefficient, FP64 and FP32: sampled rows against
+    the oracle's element-by-element rows."""
     print(f"\n[family full size] elem={elem}", flush=True)
     if elem == 4:
         n = 128
         xyz, conn = si.tet_mesh(n, n, n)
         k = np.repeat(si.field_layered(n, n, n, 4, 1.5, 0.5, si.seed_for(1)), 6)
-    else:
+    elif elem == 27:
         n = 64
         xyz, conn = si.q2_box_mesh(n, n, n)
         k = si.field_layered(n, n, n, 2, 1.5, 0.5, si.seed_for(1))
+    else:
+        n = 42
+        xyz, conn = si.q3_box_mesh(n, n, n)
+        k = si.field_layered(n, n, n, 1, 1.5, 0.5, si.seed_for(1))
     pr = dict(elem=elem, physics=1, xyz=xyz, conn=conn, coef=k[None], mask=None)
     nn = xyz.shape[1]
     x = si.vec_uniform(nn, si.seed_for(1), si.STREAM_X)
     rows = np.unique(np.random.default_rng(6).integers(0, nn, 2000))
     ref = orc.apply_rows(1, xyz, conn, pr["coef"], None, x, rows)
     for dtype in (0, 1):
-        y = apply(make_family_op(q1, pr, dtype), x, dtype)
-        assert np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref) <= TOL[dtype], dtype
+        for variant in ((0, 1) if elem == 4 else (0,)):
+            y = apply(make_family_op(q1, pr, dtype, variant), x, dtype)
+            assert np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref) <= TOL[dtype], dtype
 
 
-@pytest.mark.parametrize("elem,physics", [(4, 1), (4, 3), (27, 1), (27, 3)])
+@pytest.mark.parametrize("elem,physics", [(4, 1), (4, 3), (27, 1), (27, 3), (64, 1), (64, 3)])
 def test_family_pcg(q1, orc, elem, physics):
     """Jacobi-PCG through the generic solver: the first iterates are the oracle's,
     the converged solution has the requested residual under the oracle's matrix."""
     import torch
-    pr = family_problem(elem, physics, (6, 5, 4) if elem == 4 else (3, 3, 3), 0.1, 61)
+    n = {4: (6, 5, 4), 27: (3, 3, 3), 64: (2, 2, 2)}[elem]
+    pr = family_problem(elem, physics, n, 0.1, 61)
     A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
     b = si.vec_uniform(A.n, 61, si.STREAM_RHS)
     b[si.dof_mask(pr["mask"], 1 if physics == 1 else 3) == 1] = 0.0
@@ -174,9 +192,14 @@ def test_family_pcg(q1, orc, elem, physics):
 
 def test_family_unsupported_and_invalid(q1):
     pr = family_problem(4, 1, (2, 2, 2), 0.0, 1)
-    for variant in (2, 3, 5, 6):
+    for variant in (2, 3, 6):
         with pytest.raises(q1.Q1Error) as ei:
             make_family_op(q1, pr, 0, variant)
+        assert ei.value.code == -6
+    pr27 = family_problem(27, 1, (2, 2, 2), 0.0, 1)
+    for variant in (2, 3, 5, 6):
+        with pytest.raises(q1.Q1Error) as ei:
+            make_family_op(q1, pr27, 0, variant)
         assert ei.value.code == -6
     with pytest.raises(q1.Q1Error) as ei:
         make_family_op(q1, dict(pr, physics=2, coef=pr["coef"]))
