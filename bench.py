@@ -636,6 +636,9 @@ def bench_learned(q1, si, n, seed, args):
     per = Lm.choose_period(net, n4, periods, nval=2, trunc_m=8, log=quiet)
     rows = Lm.evaluate(net, n4, [Lm.EVAL_SEED0 + j for j in range(args.nn_eval)], omega=0.6,
                        trunc_m=8, periods=sorted({1, per}), smoothing_baseline=True, log=quiet)
+    # FCG(1) (the flexible PCG beta alone) against FCG(8), the network on every call
+    rows1 = Lm.evaluate(net, n4, [Lm.EVAL_SEED0 + j for j in range(min(2, args.nn_eval))],
+                        omega=0.6, trunc_m=1, periods=(1,), log=quiet)
     jt = sum(r["jacobi_s"] for r in rows) / len(rows)
     nt = sum(r["periods"][per]["nn_s"] for r in rows) / len(rows)
     n1 = sum(r["periods"][1]["nn_s"] for r in rows) / len(rows)
@@ -651,6 +654,11 @@ def bench_learned(q1, si, n, seed, args):
                 "nn_eval_jacobi_ms": [round(r["jacobi_s"] * 1e3, 2) for r in rows],
                 "nn_eval_fcg_ms": [round(r["periods"][per]["nn_s"] * 1e3, 2) for r in rows],
                 "nn_eval_fcg_every_call_ms": round(n1 * 1e3, 2),
+                "nn_eval_fcg1_every_call_iters": [r["periods"][1]["nn_iters"] for r in rows1],
+                "nn_eval_fcg1_every_call_ms": [round(r["periods"][1]["nn_s"] * 1e3, 2)
+                                               for r in rows1],
+                "nn_eval_fcg8_every_call_iters_same_fields":
+                    [r["periods"][1]["nn_iters"] for r in rows[:len(rows1)]],
                 "nn_eval_fcg_true_rel_res": max(r["periods"][per]["nn_true_rel_res"] for r in rows),
                 "nn_eval_fallback_at": [r["periods"][per]["nn_fallback_at"] for r in rows],
                 "nn_wall_speedup_vs_jacobi": round(jt / nt, 3)})

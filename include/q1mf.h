@@ -394,8 +394,8 @@ int q1_batched_mpcg(int nprob, q1_op *const *ops, int nrhs, const double *const 
  * up_a, a lives on the half grid D/2 x H/2 x W/2 and is read at the parent
  * voxel, i.e. nearest 2x upsampling) and b (cb channels, may be 0 and NULL).
  * w_d is [27][ca+cb][cout]; bias_d may be NULL; relu != 0 applies max(0, .);
- * y_d is FP32 [B][D][H][W][cout].  cout is 16, 32, 48, 64 or 96, otherwise
- * Q1_EUNSUPPORTED. */
+ * y_d is FP32 [B][D][H][W][cout].  cout is 16, 32, 48, 64 or 96 and ca + cb
+ * is 8 or a multiple of 16 up to 96, otherwise Q1_EUNSUPPORTED. */
 int q1_conv3d_forward(int B, int D, int H, int W, const uint16_t *a_d, int ca, int up_a,
                       const uint16_t *b_d, int cb, const float *w_d, const float *bias_d,
                       int cout, int relu, float *y_d, void *stream);

@@ -49,73 +49,125 @@ __device__ __forceinline__ bf16x8 ld8(const bf16 *p) {
 }
 
 // ---- convolution forward / backward-data ---------------------------------------
+//
+// A workgroup of four wavefronts computes an 8 x 8 x 4 voxel tile for 16 NB
+// output channels; wavefront w owns the 4 x 4 x 4 sub-tile at
+// (4 (w & 1), 4 (w >> 1)).  The input channels are taken in chunks of CC (16,
+// or 8 for an 8-channel input): the chunk's 10 x 10 x 6 halo tile (600 voxels
+// x CC channels, zero outside the padded grid) is staged in LDS once, and all
+// 27 taps of the chunk read their shifted voxels from there, so each input
+// voxel is loaded from memory once per chunk instead of once per tap; the
+// chunk's weights of the block's row group are staged beside it, so the K
+// loop issues no global loads.  K is
+// ordered chunk-major: chunk cc, then tap, then the 8-channel half h of the
+// chunk; each chunk's 27 (CC/8) groups are padded to whole K-steps of 4
+// groups with zero weights (conv_pack_* writes the matching layout).
 
-constexpr int kZB = 4;                   // z-slices per wavefront tile (tile: 4 x 4 x kZB)
-constexpr int kMaxGroups = 27 * 96 / 8;  // largest K / 8 (96 input channels)
+constexpr int kTX = 8, kTY = 8, kTZ = 4;                 // output tile of a workgroup
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;  // its halo tile
+constexpr int kHV = kHX * kHY * kHZ;                     // 600 voxels
 
-template <int NB>  // NB = 16-channel row blocks per wavefront (Cout / 16, or fewer when split)
+template <int NB, int CC>  // NB = 16-channel row blocks per wavefront, CC = staged channels
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
-  __shared__ int goff[kMaxGroups + 4];
+  constexpr int HG = CC / 8;                  // 8-channel groups per voxel and chunk
+  constexpr int KSC = (27 * HG + 3) / 4;      // K-steps per chunk
+  constexpr int ITEMS = (kHV * HG + 255) / 256;  // 16-byte input staging items per thread
+  constexpr int WROWS = 16 * NB;              // weight rows (output channels) of the block
+  constexpr int WITEMS = (KSC * 4 * WROWS + 255) / 256;  // 16-byte weight items per thread
+  __shared__ __align__(16) bf16 sx[kHV * CC];
+  __shared__ __align__(16) bf16 sw[KSC * 4 * WROWS * 8];  // the chunk's weights [ks][kg][row][8]
   const PGrid g = a.g;
-  const int CG = a.cin >> 3;
-  for (int i = threadIdx.x; i < a.nchunks * 4; i += blockDim.x) {
-    int off = 0;  // padding groups have zero weights; any finite input will do
-    if (i < a.ngroups) {
-      const int tap = i / CG, cg = i - tap * CG;
-      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-      off = ((dz * g.Hp + dy) * g.Wp + dx) * a.cin + cg * 8;
-    }
-    goff[i] = off;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int TX = (g.W + 3) >> 2, TY = (g.H + 3) >> 2, TZ = (g.D + kZB - 1) / kZB;
-  const int64_t ntiles = int64_t(g.B) * TZ * TY * TX;
-  const int nrg = a.cout / (16 * NB);  // row groups per tile, one wavefront each
-  if (wave >= ntiles * nrg) return;
-  const int rg = int(wave % nrg);
-  int64_t t = wave / nrg;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int TX = (g.W + kTX - 1) / kTX, TY = (g.H + kTY - 1) / kTY, TZ = (g.D + kTZ - 1) / kTZ;
+  const int nrg = a.cout / (16 * NB);
+  int64_t t = blockIdx.x;
+  const int rg = int(t % nrg);
+  t /= nrg;
   const int tx = int(t % TX);
   t /= TX;
   const int ty = int(t % TY);
   t /= TY;
   const int tz = int(t % TZ);
   const int b = int(t / TZ);
+  if (b >= g.B) return;
+  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;  // logical origin; halo (0,0,0) is
+                                                          // padded voxel (z0, y0, x0)
   const int kg = lane >> 4, j = lane & 15;
-  const int vx = tx * 4 + (j & 3), vy = ty * 4 + (j >> 2), z0 = tz * kZB;
-  const bf16 *xb = a.x + g.at(b, z0, vy, vx) * a.cin;
-  const int zstep = g.Hp * g.Wp * a.cin;
-  const bf16 *wrow = a.wp + (size_t(kg) * a.cout + rg * NB * 16 + j) * 8;
-  const int wstep = 4 * a.cout * 8;
-  f32x4 acc[NB][kZB];
+  const int vx = (w & 1) * 4 + (j & 3), vy = (w >> 1) * 4 + (j >> 2);  // in the tile
+
+  f32x4 acc[NB][kTZ];
 #pragma unroll
   for (int r = 0; r < NB; ++r)
 #pragma unroll
-    for (int z = 0; z < kZB; ++z) acc[r][z] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int z = 0; z < kTZ; ++z) acc[r][z] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nchunk = a.cin / CC;
+  for (int cc = 0; cc < nchunk; ++cc) {
+    if (cc) __syncthreads();  // the previous chunk's reads are done
+    u16x8 stage[ITEMS], wst[WITEMS];
+#pragma unroll
+    for (int k = 0; k < WITEMS; ++k) {  // the chunk's weights of this row group
+      const int it = k * 256 + tid;
+      wst[k] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (it < KSC * 4 * WROWS) {
+        const int row = it % WROWS, q = it / WROWS;  // q = ks * 4 + kg
+        wst[k] = *reinterpret_cast<const u16x8 *>(
+            a.wp + ((size_t(cc) * KSC * 4 + q) * a.cout + rg * WROWS + row) * 8);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {  // all loads issued before any LDS write
+      const int it = k * 256 + tid;
+      stage[k] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (it < kHV * HG) {
+        const int v = it / HG, h = it - v * HG;
+        const int hx = v % kHX, hy = (v / kHX) % kHY, hz = v / (kHX * kHY);
+        const int px = x0 + hx, py = y0 + hy, pz = z0 + hz;
+        if (px < g.Wp && py < g.Hp && pz < g.Dp)
+          stage[k] = *reinterpret_cast<const u16x8 *>(
+              a.x + (((int64_t(b) * g.Dp + pz) * g.Hp + py) * g.Wp + px) * a.cin + cc * CC + h * 8);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int it = k * 256 + tid;
+      if (it < kHV * HG) *reinterpret_cast<u16x8 *>(sx + it * 8) = stage[k];
+    }
+#pragma unroll
+    for (int k = 0; k < WITEMS; ++k) {
+      const int it = k * 256 + tid;
+      if (it < KSC * 4 * WROWS) *reinterpret_cast<u16x8 *>(sw + it * 8) = wst[k];
+    }
+    __syncthreads();
 #pragma unroll 2
-  for (int c = 0; c < a.nchunks; ++c) {
-    const int off = goff[4 * c + kg];
-    bf16x8 wv[NB], xv[kZB];
+    for (int ks = 0; ks < KSC; ++ks) {
+      const int G = 4 * ks + kg;
+      const bool real = G < 27 * HG;  // padding groups have zero weights
+      const int tap = real ? G / HG : 13, h = real ? G - (G / HG) * HG : 0;
+      const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+      bf16x8 wv[NB], xv[kTZ];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) wv[r] = ld8(wrow + c * wstep + r * 128);
+      for (int r = 0; r < NB; ++r)
+        wv[r] = *reinterpret_cast<const bf16x8 *>(sw + ((ks * 4 + kg) * WROWS + r * 16 + j) * 8);
 #pragma unroll
-    for (int zb = 0; zb < kZB; ++zb) xv[zb] = ld8(xb + zb * zstep + off);
+      for (int zb = 0; zb < kTZ; ++zb)
+        xv[zb] = *reinterpret_cast<const bf16x8 *>(
+            sx + (((zb + dz) * kHY + (vy + dy)) * kHX + (vx + dx)) * CC + h * 8);
 #pragma unroll
-    for (int r = 0; r < NB; ++r)
+      for (int r = 0; r < NB; ++r)
 #pragma unroll
-      for (int zb = 0; zb < kZB; ++zb)
-        acc[r][zb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[r], xv[zb], acc[r][zb], 0, 0, 0);
+        for (int zb = 0; zb < kTZ; ++zb)
+          acc[r][zb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[r], xv[zb], acc[r][zb], 0, 0, 0);
+    }
   }
-  // epilogue: lane holds output channels r*16 + 4*kg + i of voxel (vx, vy, z0 + zb)
-  if (vx >= g.W || vy >= g.H) return;
+  // epilogue: lane holds output channels r*16 + 4*kg + i of voxel (x, y, z0 + zb)
+  const int ox = x0 + vx, oy = y0 + vy;
+  if (ox >= g.W || oy >= g.H) return;
   const PGrid f = g.twice();
 #pragma unroll
-  for (int zb = 0; zb < kZB; ++zb) {
+  for (int zb = 0; zb < kTZ; ++zb) {
     const int z = z0 + zb;
     if (z >= g.D) break;
-    const int64_t vox = g.at(b, z, vy, vx);
-#pragma unroll
+    const int64_t vox = g.at(b, z, oy, ox);
     for (int r = 0; r < NB; ++r) {
       const int c0 = (rg * NB + r) * 16 + kg * 4;
       float v[4];
@@ -137,7 +189,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs a) {
         } else {
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            const int64_t fv = f.at(b, 2 * z + (k >> 2), 2 * vy + ((k >> 1) & 1), 2 * vx + (k & 1));
+            const int64_t fv = f.at(b, 2 * z + (k >> 2), 2 * oy + ((k >> 1) & 1), 2 * ox + (k & 1));
             *reinterpret_cast<ushort4 *>(a.out.p + fv * a.out.cs + a.out.co + c0) = o;
           }
         }
@@ -276,8 +328,29 @@ static int sum_parts(float *part, int nparts, int64_t n, float *out, hipStream_t
 
 // ---- weight packing ----------------------------------------------------------------------
 
-// forward: wp[g][co][jj] = W[tap][cg*8 + jj][co] with g = tap*CG + cg; zero past the
-// real groups and channels.  W is [27][cin_real][cout] FP32.
+// The chunk-major K order of k_conv_fwd for an input of cin channels: global
+// group q = (cc * KSC + ks) * 4 + kg; within the chunk G = 4 ks + kg, tap =
+// G / HG, half h = G % HG (channel cc CC + 8 h + jj); G >= 27 HG is padding.
+struct KOrder {
+  int CC, HG, KSC;
+  __host__ __device__ explicit KOrder(int cin)
+      : CC(cin < 16 ? 8 : 16), HG(cin < 16 ? 1 : 2), KSC((27 * (cin < 16 ? 1 : 2) + 3) / 4) {}
+  // tap (27 = padding) and first channel of group q
+  __host__ __device__ void group(int q, int &tap, int &c) const {
+    const int cc = q / (4 * KSC), G = q - cc * 4 * KSC;
+    tap = G < 27 * HG ? G / HG : 27;
+    c = cc * CC + (G - (G / HG) * HG) * 8;
+  }
+};
+
+int conv_ksteps(int cin) {
+  const KOrder k(cin);
+  return (cin / k.CC) * k.KSC;
+}
+
+// forward: wp[q][co][jj] = W[tap][c + jj][co] for group q = (tap, c) of the
+// chunk-major order over cin_pad channels; zero for padding groups and
+// channels past cin_real.  W is [27][cin_real][cout] FP32.
 __global__ void k_pack_fwd(const float *__restrict__ W, int cin_real, int cin_pad, int cout,
                            int ngroups_pad, bf16 *__restrict__ wp) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -285,15 +358,17 @@ __global__ void k_pack_fwd(const float *__restrict__ W, int cin_real, int cin_pa
   if (i >= n) return;
   const int jj = int(i & 7);
   const int co = int((i >> 3) % cout);
-  const int g = int((i >> 3) / cout);
-  const int CG = cin_pad >> 3;
-  const int tap = g / CG, c = (g % CG) * 8 + jj;
+  const int q = int((i >> 3) / cout);
+  int tap, c;
+  KOrder(cin_pad).group(q, tap, c);
+  c += jj;
   const float v = (tap < 27 && c < cin_real) ? W[(size_t(tap) * cin_real + c) * cout + co] : 0.f;
   wp[i] = f2bf(v);
 }
 
-// backward-data: the correlation with reversed taps and swapped channels,
-// wq[g][ci][jj] = W[26 - tap][ci][cg*8 + jj] with g = tap*(cout/8) + cg.
+// backward-data: the correlation with reversed taps and swapped channels over
+// an input of cout channels (the forward's outputs), output ci:
+// wq[q][ci][jj] = W[26 - tap][ci][c + jj] for group q = (tap, c).
 __global__ void k_pack_bwd(const float *__restrict__ W, int cin, int cout, int ngroups_pad,
                            bf16 *__restrict__ wq) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -301,10 +376,11 @@ __global__ void k_pack_bwd(const float *__restrict__ W, int cin, int cout, int n
   if (i >= n) return;
   const int jj = int(i & 7);
   const int ci = int((i >> 3) % cin);
-  const int g = int((i >> 3) / cin);
-  const int CG = cout >> 3;
-  const int tap = g / CG, co = (g % CG) * 8 + jj;
-  const float v = tap < 27 ? W[(size_t(26 - tap) * cin + ci) * cout + co] : 0.f;
+  const int q = int((i >> 3) / cin);
+  int tap, c;
+  KOrder(cout).group(q, tap, c);
+  c += jj;
+  const float v = tap < 27 ? W[(size_t(26 - tap) * cin + ci) * cout + c] : 0.f;
   wq[i] = f2bf(v);
 }
 
@@ -530,33 +606,30 @@ static inline dim3 g1(int64_t n, int bs = 256) { return dim3(unsigned((n + bs - 
 static inline int64_t logical(const PGrid &g) { return int64_t(g.B) * g.D * g.H * g.W; }
 
 int conv_forward(const ConvArgs &a, hipStream_t s) {
-  Q1_CHECK(a.cin % 8 == 0 && a.nchunks * 4 <= kMaxGroups + 4, Q1_EUNSUPPORTED,
-           "conv: %d input channels", a.cin);
-  const int64_t ntiles = int64_t(a.g.B) * ((a.g.D + kZB - 1) / kZB) * ((a.g.H + 3) / 4) *
-                         ((a.g.W + 3) / 4);
-  // The coarsest grids have far fewer tiles than the GPU has SIMDs: give each
-  // wavefront one 16-channel row block (more waves, each input tile read once per
-  // block).  Measured at batch 1 on 68^3: the 17^3 level gains (64->64: 50.6 ->
-  // 33.4 us), the 34^3 level loses (96->32: 34.5 -> 50.5 us), hence 512 tiles.
-  const bool split = ntiles < 512;
-  auto launch = [&](auto kern, int nb) {
-    const int64_t waves = ntiles * (a.cout / (16 * nb));
-    hipLaunchKernelGGL(kern, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, s, a);
+  Q1_CHECK(a.cin % 8 == 0 && a.cin >= 8 && (a.cin == 8 || a.cin % 16 == 0) && a.cin <= 96,
+           Q1_EUNSUPPORTED, "conv: %d input channels", a.cin);
+  Q1_CHECK(a.nchunks == conv_ksteps(a.cin), Q1_EINVAL, "conv: %d K-steps for %d channels",
+           a.nchunks, a.cin);
+  Q1_CHECK(a.cout % 16 == 0 && a.cout >= 16 && a.cout <= 96, Q1_EUNSUPPORTED,
+           "conv: %d output channels (16, 32, 48, 64, 96)", a.cout);
+  const int64_t tiles = int64_t(a.g.B) * ((a.g.D + kTZ - 1) / kTZ) * ((a.g.H + kTY - 1) / kTY) *
+                        ((a.g.W + kTX - 1) / kTX);
+  // row blocks per wavefront: all of them when that still gives 512 workgroups,
+  // else fewer (more workgroups, each staging its input tile once more)
+  // (the chunk's weights of two row blocks fill 28 KB of LDS beside the 19 KB input tile)
+  const int rb = a.cout / 16;
+  const int nb = rb % 2 == 0 && tiles * (rb / 2) >= 512 ? 2 : 1;
+  const unsigned blocks = unsigned(tiles * (rb / nb));
+  auto launch = [&](auto k8, auto k16) {
+    if (a.cin == 8)
+      hipLaunchKernelGGL(k8, dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(k16, dim3(blocks), dim3(256), 0, s, a);
   };
-  if (split) {
-    Q1_CHECK(a.cout % 16 == 0 && a.cout <= 96, Q1_EUNSUPPORTED, "conv: %d output channels",
-             a.cout);
-    launch(k_conv_fwd<1>, 1);
-  } else {
-    switch (a.cout) {
-      case 16: launch(k_conv_fwd<1>, 1); break;
-      case 32: launch(k_conv_fwd<2>, 2); break;
-      case 48: launch(k_conv_fwd<3>, 3); break;
-      case 64: launch(k_conv_fwd<4>, 4); break;
-      case 96: launch(k_conv_fwd<6>, 6); break;
-      default: return fail(Q1_EUNSUPPORTED, "conv: %d output channels (16, 32, 48, 64, 96)", a.cout);
-    }
-  }
+  if (nb == 2)
+    launch(k_conv_fwd<2, 8>, k_conv_fwd<2, 16>);
+  else
+    launch(k_conv_fwd<1, 8>, k_conv_fwd<1, 16>);
   Q1_HIP(hipGetLastError());
   return Q1_OK;
 }

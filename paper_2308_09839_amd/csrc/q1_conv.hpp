@@ -42,8 +42,8 @@ struct ConvArgs {
   const bf16 *x = nullptr;
   int cin = 0;
   PGrid g;                    // input and output grid
-  const bf16 *wp = nullptr;   // packed weights [nchunks*4][cout][8]
-  int ngroups = 0, nchunks = 0, cout = 0;
+  const bf16 *wp = nullptr;   // packed weights [nchunks*4][cout][8], chunk-major K order
+  int ngroups = 0, nchunks = 0, cout = 0;  // nchunks: K-steps (conv_ksteps(cin))
   const float *bias = nullptr;  // [cout] or null
   int relu = 0;
   Slice mask;                   // outputs where mask <= 0 become 0 (same grid), or p == null
@@ -69,6 +69,9 @@ struct ConvWArgs {
 };
 
 int conv_forward(const ConvArgs &a, hipStream_t s);
+// K-steps (4 groups of 8 channels each) of a convolution over cin input
+// channels in the chunk-major order of the packed weights
+int conv_ksteps(int cin);
 int wgrad_chunks(const ConvWArgs &a);
 int conv_wgrad(ConvWArgs a, float *gw, float *gb, hipStream_t s);
 int pack_forward(const float *W, int cin_real, int cin_pad, int cout, int ngroups_pad, bf16 *wp,

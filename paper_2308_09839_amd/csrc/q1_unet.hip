@@ -522,9 +522,9 @@ int q1_unet_create(q1_unet **out, int D, int H, int W, int batch, uint64_t seed,
     L.bo = off + int64_t(27) * L.s.cin_real * L.s.cout;
     off = L.bo + L.s.cout;
     L.ngroups = 27 * L.s.cin / 8;
-    L.nchunks = (L.ngroups + 3) / 4;
+    L.nchunks = conv_ksteps(L.s.cin);
     L.ngroups_b = 27 * L.s.cout / 8;
-    L.nchunks_b = (L.ngroups_b + 3) / 4;
+    L.nchunks_b = conv_ksteps(L.s.cout);
     ConvWArgs w;
     w.g = n.grid(L.s.level, batch);
     w.cin = L.s.cin;
@@ -706,7 +706,7 @@ int q1_conv3d_forward(int B, int D, int H, int W, const uint16_t *a_d, int ca, i
   Q1_CHECK(conv_cout_ok(cout), Q1_EUNSUPPORTED, "q1_conv3d_forward: cout %d", cout);
   Q1_CHECK(ca + cb <= 96, Q1_EUNSUPPORTED, "q1_conv3d_forward: more than 96 input channels");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int cin = ca + cb, ngroups = 27 * cin / 8, nchunks = (ngroups + 3) / 4;
+  const int cin = ca + cb, ngroups = 27 * cin / 8, nchunks = conv_ksteps(cin);
   const PGrid g(B, D, H, W);
   TmpBuf wp, xp, yp;
   Q1_HIP(hipMalloc(&wp.p, size_t(nchunks) * 4 * cout * 8 * sizeof(bf16)));
@@ -740,7 +740,7 @@ int q1_conv3d_backward_data(int B, int D, int H, int W, const uint16_t *gy_d, in
            Q1_EINVAL, "q1_conv3d_backward_data: bad sizes");
   Q1_CHECK(conv_cout_ok(cin), Q1_EUNSUPPORTED, "q1_conv3d_backward_data: cin %d", cin);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int ngroups = 27 * cout / 8, nchunks = (ngroups + 3) / 4;
+  const int ngroups = 27 * cout / 8, nchunks = conv_ksteps(cout);
   const PGrid g(B, D, H, W);
   TmpBuf wq, gp, xp;
   Q1_HIP(hipMalloc(&wq.p, size_t(nchunks) * 4 * cin * 8 * sizeof(bf16)));
