@@ -104,6 +104,20 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return v[0];
 }
 
+// Several partial rows re-reduced at once: out[r] is what sum_partials gives
+// for row r (the same order of additions), with one block reduction instead
+// of one per row.
+template <int R>
+__device__ __forceinline__ void sum_partials_n(const double *const (&rows)[R], int nb,
+                                               double (&out)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[r] = 0.0;
+  for (int j = int(threadIdx.x); j < nb; j += kRT)
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] += rows[r][j];
+  block_sum<R>(out);
+}
+
 struct Range {
   int64_t i0, i1;
 };
@@ -172,8 +186,9 @@ __global__ __launch_bounds__(kRT) void k_pcg_update(
     double *__restrict__ part_rho_k1, double *__restrict__ part_rr, Status *__restrict__ st) {
   if (st->done) return;
   const int nb = gridDim.x;
-  const double pq = sum_partials(part_pq, nb);
-  const double rho = sum_partials(part_rho_k, nb);
+  double t[2];
+  sum_partials_n<2>({part_pq, part_rho_k}, nb, t);
+  const double pq = t[0], rho = t[1];
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->done = 1;
@@ -211,10 +226,9 @@ __global__ __launch_bounds__(kRT) void k_pcg_direction(
     int maxit, Status *__restrict__ st) {
   if (st->done) return;
   const int nb = gridDim.x;
-  const double num = sum_partials(part_num, nb);
-  const double den = sum_partials(part_den, nb);
-  const double rr = sum_partials(part_rr, nb);
-  const double bb = sum_partials(part_bb, nb);
+  double t[4];
+  sum_partials_n<4>({part_num, part_den, part_rr, part_bb}, nb, t);
+  const double num = t[0], den = t[1], rr = t[2], bb = t[3];
   const bool conv = rr <= tol2 * bb;
   const bool bad = !isfinite(rr);
   const bool stop = conv || bad || it >= maxit;
@@ -377,15 +391,24 @@ __global__ __launch_bounds__(kRT) void k_fcg_direction(int64_t n, const T *__res
                                                        const Status *__restrict__ st) {
   if (st->done) return;
   const int nb = gridDim.x;
+  // all 2m partial rows in one fixed-order block reduction (the order of
+  // sum_partials on each row)
+  double v[2 * kMaxTrunc];
+#pragma unroll
+  for (int j = 0; j < 2 * kMaxTrunc; ++j) v[j] = 0.0;
+  for (int i = int(threadIdx.x); i < nb; i += kRT)
+#pragma unroll
+    for (int j = 0; j < kMaxTrunc; ++j)
+      if (j < m) {
+        v[j] += part_zq[j * kMaxRB + i];
+        v[kMaxTrunc + j] += d.pq[j][i];
+      }
+  block_sum<2 * kMaxTrunc>(v);
   double c[kMaxTrunc];
 #pragma unroll
   for (int j = 0; j < kMaxTrunc; ++j) {
-    c[j] = 0.0;
-    if (j < m) {
-      const double zq = sum_partials(part_zq + j * kMaxRB, nb);
-      const double pq = sum_partials(d.pq[j], nb);
-      c[j] = pq > 0.0 ? zq / pq : 0.0;
-    }
+    const double zq = v[j], pq = v[kMaxTrunc + j];
+    c[j] = j < m && pq > 0.0 ? zq / pq : 0.0;
   }
   const Range rg = block_range(n);
   for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
@@ -430,8 +453,9 @@ __global__ __launch_bounds__(kRT) void k_fcg_update(int64_t n, const T *__restri
                                                     Status *__restrict__ st) {
   if (st->done) return;
   const int nb = gridDim.x;
-  const double pq = sum_partials(part_pq, nb);
-  const double pr = sum_partials(part_pr, nb);
+  double t[2];
+  sum_partials_n<2>({part_pq, part_pr}, nb, t);
+  const double pq = t[0], pr = t[1];
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(pr)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->done = 1;
