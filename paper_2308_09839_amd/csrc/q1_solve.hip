@@ -382,34 +382,47 @@ __global__ __launch_bounds__(kRT) void k_multi_dot(int64_t n, const T *__restric
     for (int j = 0; j < m; ++j) part[j * kMaxRB + blockIdx.x] = v[j];
 }
 
-// p = z - sum_j (z.q_j / p_j.q_j) p_j
-template <typename T>
-__global__ __launch_bounds__(kRT) void k_fcg_direction(int64_t n, const T *__restrict__ z,
-                                                       DirSet d, int m,
-                                                       const double *__restrict__ part_zq,
-                                                       T *__restrict__ p,
-                                                       const Status *__restrict__ st) {
+// c_j = z.q_j / p_j.q_j for the m directions of the window, from the nz
+// partials of z.q_j (k_multi_dot) and the np partials of p_j.q_j, in one
+// block (a fixed-order reduction of all 2m rows)
+__global__ __launch_bounds__(kRT) void k_fcg_coef(const double *__restrict__ part_zq, int nz,
+                                                  DirSet d, int np, int m,
+                                                  double *__restrict__ coef,
+                                                  const Status *__restrict__ st) {
   if (st->done) return;
-  const int nb = gridDim.x;
-  // all 2m partial rows in one fixed-order block reduction (the order of
-  // sum_partials on each row)
   double v[2 * kMaxTrunc];
 #pragma unroll
   for (int j = 0; j < 2 * kMaxTrunc; ++j) v[j] = 0.0;
-  for (int i = int(threadIdx.x); i < nb; i += kRT)
+  for (int i = int(threadIdx.x); i < nz; i += kRT)
 #pragma unroll
     for (int j = 0; j < kMaxTrunc; ++j)
-      if (j < m) {
-        v[j] += part_zq[j * kMaxRB + i];
-        v[kMaxTrunc + j] += d.pq[j][i];
-      }
+      if (j < m) v[j] += part_zq[j * kMaxRB + i];
+  for (int i = int(threadIdx.x); i < np; i += kRT)
+#pragma unroll
+    for (int j = 0; j < kMaxTrunc; ++j)
+      if (j < m) v[kMaxTrunc + j] += d.pq[j][i];
   block_sum<2 * kMaxTrunc>(v);
+  if (threadIdx.x < kMaxTrunc) {
+    const int j = int(threadIdx.x);
+    double c = 0.0;
+#pragma unroll
+    for (int t = 0; t < kMaxTrunc; ++t)
+      if (t == j && t < m) c = v[kMaxTrunc + t] > 0.0 ? v[t] / v[kMaxTrunc + t] : 0.0;
+    coef[j] = c;
+  }
+}
+
+// p = z - sum_j c_j p_j with the coefficients of k_fcg_coef
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_fcg_direction(int64_t n, const T *__restrict__ z,
+                                                       DirSet d, int m,
+                                                       const double *__restrict__ coef,
+                                                       T *__restrict__ p,
+                                                       const Status *__restrict__ st) {
+  if (st->done) return;
   double c[kMaxTrunc];
 #pragma unroll
-  for (int j = 0; j < kMaxTrunc; ++j) {
-    const double zq = v[j], pq = v[kMaxTrunc + j];
-    c[j] = j < m && pq > 0.0 ? zq / pq : 0.0;
-  }
+  for (int j = 0; j < kMaxTrunc; ++j) c[j] = j < m ? coef[j] : 0.0;
   const Range rg = block_range(n);
   for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
     double v = double(z[i]);
@@ -737,7 +750,9 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
   Free fr0{{dirs, nullptr, nullptr, nullptr, nullptr}};
   Q1_HIP(hipMalloc(&pq_parts, size_t(m) * kMaxRB * sizeof(double)));
   fr0.p[1] = pq_parts;
-  Q1_HIP(hipMalloc(&zq_parts, size_t(kMaxTrunc) * kMaxRB * sizeof(double)));
+  Q1_HIP(hipMalloc(&zq_parts, size_t(kMaxTrunc + 1) * kMaxRB * sizeof(double)));
+  double *coef_d = zq_parts + size_t(kMaxTrunc) * kMaxRB;  // the window's coefficients
+  const int nbw = int(std::max<int64_t>(1, std::min<int64_t>(kMaxRB, (n + kRT - 1) / kRT)));
   fr0.p[2] = zq_parts;
   Q1_HIP(hipMalloc(&hist_d, size_t(maxit + 1) * sizeof(double)));
   fr0.p[3] = hist_d;
@@ -803,10 +818,15 @@ int fpcg_t(Op &op, q1_precond_fn M, void *ctx, const T *b, T *x, double rtol, in
           d.pq[t] = pq_parts + size_t(sl) * kMaxRB;
         }
         if (nwin > 0) {
-          hipLaunchKernelGGL((k_multi_dot<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin, zq_parts,
-                             W.st);
-          hipLaunchKernelGGL((k_fcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, z, d, nwin,
-                             zq_parts, P(cur), W.st);
+          // the window's dot products and the new direction: memory-bound passes
+          // over m + 1 vectors, so launched on up to kMaxRB blocks; the
+          // coefficients are reduced once, by one block
+          hipLaunchKernelGGL((k_multi_dot<T>), dim3(nbw), dim3(kRT), 0, s, n, z, d, nwin,
+                             zq_parts, W.st);
+          hipLaunchKernelGGL(k_fcg_coef, dim3(1), dim3(kRT), 0, s, zq_parts, nbw, d, nb, nwin,
+                             coef_d, W.st);
+          hipLaunchKernelGGL((k_fcg_direction<T>), dim3(nbw), dim3(kRT), 0, s, n, z, d, nwin,
+                             coef_d, P(cur), W.st);
         } else {
           Q1_HIP(hipMemcpyAsync(P(cur), z, size_t(n) * sizeof(T), hipMemcpyDeviceToDevice, s));
         }
