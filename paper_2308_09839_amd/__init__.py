@@ -152,11 +152,11 @@ class Op:
 
     def __del__(self):
         # at interpreter shutdown the process releases device memory itself:
-        # no library call is made from a finaliser then
-        if not _can_release():
-            return
+        # no library call is made from a finaliser then (and once the module's
+        # globals are cleared, the check itself raises and is ignored)
         try:
-            self.destroy()
+            if _can_release():
+                self.destroy()
         except Exception:
             pass
 
@@ -312,10 +312,9 @@ class Jacobi:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
-        if not _can_release():
-            return
         try:
-            self.destroy()
+            if _can_release():
+                self.destroy()
         except Exception:
             pass
 
@@ -509,10 +508,9 @@ class UNet:
         self.handle = None
 
     def __del__(self):
-        if not _can_release():
-            return
         try:
-            self.destroy()
+            if _can_release():
+                self.destroy()
         except Exception:
             pass
 
@@ -555,10 +553,9 @@ class UNetPrecond:
         self.handle = None
 
     def __del__(self):
-        if not _can_release():
-            return
         try:
-            self.destroy()
+            if _can_release():
+                self.destroy()
         except Exception:
             pass
 

@@ -46,6 +46,7 @@ struct TileMap {
   bool lds_atomic = false;        // corners collide within a step: accumulate with LDS atomics
   bool split = false;             // block variants: bitwise-reproducible split accumulation
   bool all_affine = false;        // every tile is a parallelepiped tile
+  bool fixed = false;             // every tile is the default 16 x 8 x 4 scalar lattice tile
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
   uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16 | C << 24, or 0
   uint32_t *tile_addr = nullptr;  // [n_tiles] lattice addressing: valid bit | shared-face bits, or 0

@@ -390,17 +390,27 @@ __global__ __launch_bounds__(kRT) void k_fcg_coef(const double *__restrict__ par
                                                   double *__restrict__ coef,
                                                   const Status *__restrict__ st) {
   if (st->done) return;
+  // every load of the block is issued before the first addition (one memory
+  // latency instead of one per round); the additions keep the order of
+  // sum_partials: thread t adds partials t, t + 256, ... of each row
+  constexpr int kRounds = kMaxRB / kRT;
+  double a[kRounds][2 * kMaxTrunc];
+#pragma unroll
+  for (int k = 0; k < kRounds; ++k) {
+    const int i = int(threadIdx.x) + k * kRT;
+#pragma unroll
+    for (int j = 0; j < kMaxTrunc; ++j) {
+      a[k][j] = j < m && i < nz ? part_zq[j * kMaxRB + i] : 0.0;
+      a[k][kMaxTrunc + j] = j < m && i < np ? d.pq[j][i] : 0.0;
+    }
+  }
   double v[2 * kMaxTrunc];
 #pragma unroll
-  for (int j = 0; j < 2 * kMaxTrunc; ++j) v[j] = 0.0;
-  for (int i = int(threadIdx.x); i < nz; i += kRT)
+  for (int j = 0; j < 2 * kMaxTrunc; ++j) {
+    v[j] = 0.0;
 #pragma unroll
-    for (int j = 0; j < kMaxTrunc; ++j)
-      if (j < m) v[j] += part_zq[j * kMaxRB + i];
-  for (int i = int(threadIdx.x); i < np; i += kRT)
-#pragma unroll
-    for (int j = 0; j < kMaxTrunc; ++j)
-      if (j < m) v[kMaxTrunc + j] += d.pq[j][i];
+    for (int k = 0; k < kRounds; ++k) v[j] += a[k][j];
+  }
   block_sum<2 * kMaxTrunc>(v);
   if (threadIdx.x < kMaxTrunc) {
     const int j = int(threadIdx.x);

@@ -86,6 +86,50 @@ __host__ __device__ inline uint32_t lattice_word(int i, uint32_t lat, uint32_t a
   return uint32_t(g0 + ix + iy * sy + iz * sz) | (sh ? kSharedBit : 0u);
 }
 
+// The default tile of each kind as compile-time constants: 16 x 8 x 4
+// elements (765 nodes, two steps per layer) for the scalar kind, 16 x 4 x 4
+// (425 nodes, one step per layer) for the 3-DOF kinds.  When every tile of an
+// operator is that lattice tile, a kernel instance with the shape built in
+// computes corner indices, LDS offsets and lattice addresses from constants
+// (the LDS reads of an element share one address register and differ by
+// immediate offsets), which removes most of the integer work per element.
+template <int DPN>
+struct FxTile {
+  static constexpr int A = 16, B = DPN == 1 ? 8 : 4, C = 4;
+  static constexpr int SPL = A * B / 64;  // steps per layer; one layer per wave
+  static constexpr int STEPS = C * SPL;
+  static constexpr int NODES = (A + 1) * (B + 1) * (C + 1);
+  static constexpr uint32_t LAT =
+      uint32_t(A) | uint32_t(B) << 8 | uint32_t(SPL) << 16 | uint32_t(C) << 24;
+  static_assert(A == 16 && A * B == SPL * 64 && C == 4 && SPL == split_steps(DPN),
+                "one layer per wave, whole steps");
+};
+
+// corner_lattice for the fixed tile: position rel = 4k + w is step k of layer w
+template <int DPN>
+__host__ __device__ inline void corner_fixed(int rel, int lane, int (&lc)[8]) {
+  using F = FxTile<DPN>;
+  constexpr int a1 = F::A + 1, ab1 = (F::A + 1) * (F::B + 1);
+  const int e = (rel >> 2) * 64 + lane;
+  const int base = (e & (F::A - 1)) + a1 * (e >> 4) + ab1 * (rel & 3);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) lc[a] = base + (a & 1) + a1 * ((a >> 1) & 1) + ab1 * (a >> 2);
+}
+
+// lattice_word for the fixed tile (ids below 2^30, so 32-bit arithmetic gives them exactly)
+template <int DPN>
+__host__ __device__ inline uint32_t lattice_word_fixed(int i, uint32_t addr, int64_t g0,
+                                                       int64_t sy, int64_t sz) {
+  using F = FxTile<DPN>;
+  constexpr unsigned a1 = F::A + 1, ab1 = (F::A + 1) * (F::B + 1);
+  const unsigned ui = unsigned(i);
+  const unsigned iz = ui / ab1, r = ui - iz * ab1, iy = r / a1, ix = r - iy * a1;
+  const bool sh = (ix == 0 && (addr & 1)) || (ix == unsigned(F::A) && (addr & 2)) ||
+                  (iy == 0 && (addr & 4)) || (iy == unsigned(F::B) && (addr & 8)) ||
+                  (iz == 0 && (addr & 16)) || (iz == unsigned(F::C) && (addr & 32));
+  return (uint32_t(g0) + ix + iy * uint32_t(sy) + iz * uint32_t(sz)) | (sh ? kSharedBit : 0u);
+}
+
 __device__ __forceinline__ int xcd_block_t(int bid, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
   const int x = bid & 7, local = bid >> 3;
@@ -119,6 +163,15 @@ __global__ void k_reset_nodes(int64_t n, const int32_t *__restrict__ ids,
 // atomics; otherwise corner by corner with plain read-add-write, which the
 // set-up allows only when no two lanes of a step share a node at the same
 // local corner (true on any consistently numbered structured grid).
+// The plain read-add-write accumulation relies on one property: within one
+// corner's instruction no two lanes touch the same node, while the next
+// corner's instruction of the same wavefront may touch nodes that other lanes
+// have just written.  A wavefront's LDS instructions execute in order, so the
+// only thing to prevent is the compiler moving a later corner's read above an
+// earlier corner's write (it may, where the addresses differ within one
+// lane).  This is that compiler-only barrier; it emits no instruction.
+__device__ __forceinline__ void lane_order() { asm volatile("" ::: "memory"); }
+
 template <typename T, bool LDS_ATOMIC>
 __device__ __forceinline__ void acc_add(T *p, T v) {
   if constexpr (LDS_ATOMIC)
@@ -188,9 +241,11 @@ __global__ __launch_bounds__(64) void k_apply_tile(
       for (int j = 0; j < DPN; ++j) u[j][a] = fixed[a] ? T(0) : x[g[a] * DPN + j];
     element_apply<T, PH>(X, u, c0, c1, v);
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < 8; ++a) {
 #pragma unroll
       for (int j = 0; j < DPN; ++j) acc_add<T, LDS_ATOMIC>(&sV[j * max_nodes + lc[a]], v[j][a]);
+      if constexpr (!LDS_ATOMIC) lane_order();
+    }
   }
   __syncthreads();
   for (int i = lane; i < nm; i += kLanes) {
@@ -220,7 +275,7 @@ __global__ __launch_bounds__(64) void k_apply_tile(
 // data (qdata[8 * 6][coef_stride] for the Laplace kinds, qdata[8 * 9][coef_stride]
 // for elasticity) replaces its geometry (the staged records then hold the
 // input only).  Returns false for an empty lane.
-template <typename T, int PH, bool PAR, bool PA>
+template <typename T, int PH, bool PAR, bool PA, bool FX = false>
 __device__ __forceinline__ bool step_element(int s, int lane, int max_nodes,
                                              const T *__restrict__ sR, uint4 pk, T c0, T c1,
                                              int64_t coef_stride, const T *__restrict__ qdata,
@@ -228,7 +283,9 @@ __device__ __forceinline__ bool step_element(int s, int lane, int max_nodes,
                                              T (&v)[phys_dpn(PH)][8]) {
   constexpr int DPN = phys_dpn(PH);
   constexpr int UOFF = PA ? 0 : 3;  // first input field of a staged record
-  if (lat) {  // lattice tile: corner indices from (step, lane), no corner-index loads
+  if constexpr (FX) {  // the fixed tile: no empty lanes
+    corner_fixed<DPN>(s - s_first, lane, lc);
+  } else if (lat) {  // lattice tile: corner indices from (step, lane), no corner-index loads
     if (!corner_lattice(lat, s - s_first, lane, lc)) return false;
   } else {
     if (pk.x == 0xffffffffu) return false;
@@ -297,9 +354,11 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
                                       lat, s_first, lc, v))
       continue;
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < 8; ++a) {
 #pragma unroll
       for (int j = 0; j < DPN; ++j) acc_add<T, LDS_ATOMIC>(&myV[j * max_nodes + lc[a]], v[j][a]);
+      if constexpr (!LDS_ATOMIC) lane_order();
+    }
   }
 }
 
@@ -310,7 +369,7 @@ __device__ __forceinline__ void block_steps(int s, int s1, int lane, int max_nod
 // this (it contains the barrier).  par_tile: the tile's elements are all
 // parallelepipeds (taken only where PAR_OK; GEN_OK: the general element is
 // compiled in).
-template <typename T, int PH, bool PAR_OK, bool GEN_OK, bool PA>
+template <typename T, int PH, bool PAR_OK, bool GEN_OK, bool PA, bool FX = false>
 __device__ __forceinline__ void block_steps_split(int s0, int s1, int w, int lane, int max_nodes,
                                                   const T *__restrict__ sR, T *__restrict__ sV,
                                                   const uint4 *__restrict__ lconn,
@@ -327,8 +386,8 @@ __device__ __forceinline__ void block_steps_split(int s0, int s1, int w, int lan
     const int s = s0 + w + 4 * k;
     const uint4 pk = pk_n;
     const T c0 = c0_n, c1 = c1_n;
-    if (k + 1 < kSplitSteps && s + 4 < s1) {  // prefetch the wave's next step
-      const int64_t slot = int64_t(s + 4) * kLanes + lane;
+    if (k + 1 < kSplitSteps) {  // prefetch the wave's next step (clamped, unconditional)
+      const int64_t slot = int64_t(min(s + 4, s1 - 1)) * kLanes + lane;
       if (!lat) pk_n = lconn[slot];
       c0_n = coef_t[slot];
       if constexpr (PH == 3) c1_n = coef_t[coef_stride + slot];
@@ -343,19 +402,21 @@ __device__ __forceinline__ void block_steps_split(int s0, int s1, int w, int lan
       live = step_element<T, PH, false, true>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
                                               qdata, lat, s0, lc, v);
     else if constexpr (!GEN_OK)
-      live = step_element<T, PH, true, false>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
-                                              qdata, lat, s0, lc, v);
+      live = step_element<T, PH, true, false, FX>(s, lane, max_nodes, sR, pk, c0, c1,
+                                                  coef_stride, qdata, lat, s0, lc, v);
     else if (PAR_OK && par_tile)
-      live = step_element<T, PH, true, false>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
-                                              qdata, lat, s0, lc, v);
+      live = step_element<T, PH, true, false, FX>(s, lane, max_nodes, sR, pk, c0, c1,
+                                                  coef_stride, qdata, lat, s0, lc, v);
     else
-      live = step_element<T, PH, false, false>(s, lane, max_nodes, sR, pk, c0, c1, coef_stride,
-                                               qdata, lat, s0, lc, v);
+      live = step_element<T, PH, false, false, FX>(s, lane, max_nodes, sR, pk, c0, c1,
+                                                   coef_stride, qdata, lat, s0, lc, v);
     if (!live) continue;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
 #pragma unroll
       for (int j = 0; j < DPN; ++j) sV[j * max_nodes + lc[a]] += v[j][a];
+      lane_order();
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       hidx[k][a] = lc[4 + a];
@@ -368,9 +429,11 @@ __device__ __forceinline__ void block_steps_split(int s0, int s1, int w, int lan
   for (int k = 0; k < kSplitSteps; ++k)
 #pragma unroll
     for (int a = 0; a < 4; ++a)
-      if (hidx[k][a] >= 0)
+      if (hidx[k][a] >= 0) {
 #pragma unroll
         for (int j = 0; j < DPN; ++j) sV[j * max_nodes + hidx[k][a]] += hold[k][a][j];
+        lane_order();
+      }
 }
 
 // Accumulation modes of the block kernel: kAccSplit, one LDS accumulator
@@ -380,8 +443,10 @@ __device__ __forceinline__ void block_steps_split(int s0, int s1, int w, int lan
 // copy per wave, the copies summed in a fixed order (FP32 fallback).
 // ALLPAR: every tile of the operator is a parallelepiped tile (flagged at
 // set-up), so only the parallelepiped element is compiled in (fewer registers).
+// FX: every tile is the kind's fixed lattice tile (FxTile, with the split
+// accumulation), whose shape is built in.
 constexpr int kAccSplit = 0, kAccShared = 1, kAccCopies = 2;
-template <typename T, int PH, bool LDS_ATOMIC, int ACC, bool PA, bool ALLPAR>
+template <typename T, int PH, bool LDS_ATOMIC, int ACC, bool PA, bool ALLPAR, bool FX = false>
 __global__ __launch_bounds__(256) void k_apply_block(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
     const uint32_t *__restrict__ nodes, const int32_t *__restrict__ tile_step,
@@ -395,31 +460,43 @@ __global__ __launch_bounds__(256) void k_apply_block(
   if (stop && *stop) return;
   constexpr int UOFF = PA ? 0 : 3;
   constexpr int NR = UOFF + DPN;  // [x, y, z,] u[DPN], stored field by field
-  constexpr int KN = 4;        // node records per thread issued together (1024 per tile)
+  using FT = FxTile<DPN>;
+  // node records per thread issued together (all of a fixed tile, else 1024 per round)
+  constexpr int KN = FX ? (FT::NODES + 255) / 256 : 4;
+  static_assert(!FX || (ACC == kAccSplit && !PA), "FX instance");
+  // the LDS stride of a field: a constant on the fixed tile
+  const int MN = FX ? FT::NODES : max_nodes;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][max_nodes]
+  T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][MN]
   constexpr bool ONEACC = ACC != kAccCopies;
   constexpr int NACC = ONEACC ? 1 : 4;
-  T *sV = sR + size_t(NR) * max_nodes;       // [NACC][DPN][max_nodes]
+  T *sV = sR + size_t(NR) * MN;              // [NACC][DPN][MN]
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int tile = xcd_block_t(blockIdx.x, gridDim.x);
-  const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
-  const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
-  const uint32_t lat = tile_lat[tile], addr = tile_addr[tile];
+  const int n0 = node_ptr[tile], nm = FX ? FT::NODES : node_ptr[tile + 1] - n0;
+  const int s0 = tile_step[tile], s1 = FX ? s0 + FT::STEPS : tile_step[tile + 1];
+  const uint32_t lat = FX ? FT::LAT : tile_lat[tile], addr = tile_addr[tile];
   const int64_t g0 = tile_g0[tile];
   // node word of entry i: computed on lattice-addressed tiles, else loaded
   auto word = [&](int i) -> uint32_t {
-    return addr ? lattice_word(i, lat, addr, g0, sy, sz) : nodes[n0 + i];
+    if constexpr (FX)
+      return addr ? lattice_word_fixed<DPN>(i, addr, g0, sy, sz) : nodes[n0 + i];
+    else
+      return addr ? lattice_word(i, lat, addr, g0, sy, sz) : nodes[n0 + i];
   };
-  // the wave's first step is requested before staging, so its latency overlaps it
+  // the wave's first step: requested after the first staging round's loads, so
+  // that the waits of that round's LDS writes do not include it (its latency
+  // overlaps them and the barrier)
   uint4 pk0 = make_uint4(0xffffffffu, 0u, 0u, 0u);
   T c00 = T(0), c10 = T(0);
-  if (s0 + w < s1) {
-    const int64_t slot = int64_t(s0 + w) * kLanes + lane;
+  // (unconditional, at a clamped step, since a load under a branch makes the
+  // compiler wait for it at the branch's end; a wave without steps never uses it)
+  auto first_step = [&]() {
+    const int64_t slot = int64_t(min(s0 + w, s1 - 1)) * kLanes + lane;
     if (!lat) pk0 = lconn[slot];
     c00 = coef_t[slot];
     if constexpr (PH == 3) c10 = coef_t[coef_stride + slot];
-  }
+  };
   // stage the node records: all loads of a round are issued (unconditionally,
   // at clamped indices) before any LDS write, so the round costs one latency.
   // The first round's node words stay in registers for the write-back.
@@ -434,9 +511,11 @@ __global__ __launch_bounds__(256) void k_apply_block(
 #pragma unroll
       for (int k = 0; k < KN; ++k) {
         keep[k] = raw[k];
-        // slots are only used for shared entries (known at once on lattice-addressed tiles)
+        // slots are only used for shared entries (known at once on lattice-addressed
+        // tiles): the other lanes load the tile's first slot, one line per wavefront.
+        // The load is unconditional so that nothing waits for it before the write-back.
         const int sl = n0 + min(k * 256 + tid, nm - 1);
-        kslot[k] = !addr || (raw[k] & kSharedBit) ? slot[sl] : -1;
+        kslot[k] = slot[!addr || (raw[k] & kSharedBit) ? sl : n0];
       }
     }
 #pragma unroll
@@ -450,26 +529,27 @@ __global__ __launch_bounds__(256) void k_apply_block(
 #pragma unroll
       for (int j = 0; j < DPN; ++j) rec[k][UOFF + j] = x[g * DPN + j];
     }
+    if (base == 0) first_step();
 #pragma unroll
     for (int k = 0; k < KN; ++k) {
       const int i = base + k * 256 + tid;
       if (i < nm) {
         const bool fixed = (raw[k] & kFixedBit) != 0;
 #pragma unroll
-        for (int f = 0; f < UOFF; ++f) sR[size_t(f) * max_nodes + i] = rec[k][f];
+        for (int f = 0; f < UOFF; ++f) sR[size_t(f) * MN + i] = rec[k][f];
 #pragma unroll
         for (int j = 0; j < DPN; ++j)
-          sR[size_t(UOFF + j) * max_nodes + i] = fixed ? T(0) : rec[k][UOFF + j];
+          sR[size_t(UOFF + j) * MN + i] = fixed ? T(0) : rec[k][UOFF + j];
 #pragma unroll
-        for (int c = 0; c < NACC * DPN; ++c) sV[size_t(c) * max_nodes + i] = T(0);
+        for (int c = 0; c < NACC * DPN; ++c) sV[size_t(c) * MN + i] = T(0);
       }
     }
   }
   __syncthreads();
   if constexpr (ACC == kAccSplit) {
-    block_steps_split<T, PH, !PA, !ALLPAR, PA>(s0, s1, w, lane, max_nodes, sR, sV, lconn,
-                                               coef_t, coef_stride, pk0, c00, c10, qdata, lat,
-                                               !PA && !ALLPAR && tile_affine[tile]);
+    block_steps_split<T, PH, !PA, !ALLPAR, PA, FX>(s0, s1, w, lane, MN, sR, sV, lconn, coef_t,
+                                                   coef_stride, pk0, c00, c10, qdata, lat,
+                                                   !PA && !ALLPAR && tile_affine[tile]);
   } else {
     constexpr bool AT = LDS_ATOMIC || ACC == kAccShared;
     T *myV = ONEACC ? sV : sV + size_t(w) * DPN * max_nodes;
@@ -493,7 +573,7 @@ __global__ __launch_bounds__(256) void k_apply_block(
     const int64_t gg = raw & kIdMask;
 #pragma unroll
     for (int j = 0; j < DPN; ++j) {
-      const size_t o = size_t(j) * max_nodes + i, cs = size_t(DPN) * max_nodes;
+      const size_t o = size_t(j) * MN + i, cs = size_t(DPN) * MN;
       T v;
       if constexpr (ONEACC)
         v = sV[o];
@@ -639,9 +719,11 @@ __global__ __launch_bounds__(256) void k_diag_block(
       for (int r = 0; r < 3; ++r) X[r][a] = sR[size_t(r) * max_nodes + lc[a]];
     element_diag<T, PH>(X, coef_t[sl], PH == 3 ? coef_t[coef_stride + sl] : T(0), v);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
 #pragma unroll
       for (int j = 0; j < DPN; ++j) sV[j * max_nodes + lc[a]] += v[j][a];
+      lane_order();
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       hidx[k][a] = lc[4 + a];
@@ -654,9 +736,11 @@ __global__ __launch_bounds__(256) void k_diag_block(
   for (int k = 0; k < kSplitSteps; ++k)
 #pragma unroll
     for (int a = 0; a < 4; ++a)
-      if (hidx[k][a] >= 0)
+      if (hidx[k][a] >= 0) {
 #pragma unroll
         for (int j = 0; j < DPN; ++j) sV[j * max_nodes + hidx[k][a]] += hold[k][a][j];
+        lane_order();
+      }
   __syncthreads();
   for (int i = tid; i < nm; i += 256) {
     const uint32_t raw = nodes[n0 + i];
@@ -838,6 +922,30 @@ bool split_ok(const HostTiles &H, int t, int nm, int dpn) {
       }
     }
   }
+  return true;
+}
+
+// Whether every tile is the kind's fixed lattice tile (FxTile<DPN>), and the
+// built-in shape reproduces what the planner verified: the corner indices of
+// every (position, lane), and every entry's word on lattice-addressed tiles.
+template <int DPN>
+bool fixed_tiles(const HostTiles &H) {
+  using F = FxTile<DPN>;
+  if (H.max_nodes != F::NODES || H.tile_lat.empty() ||
+      !std::all_of(H.tile_lat.begin(), H.tile_lat.end(), [](uint32_t l) { return l == F::LAT; }))
+    return false;
+  for (int rel = 0; rel < F::STEPS; ++rel)
+    for (int l = 0; l < kLanes; ++l) {
+      int a[8], b[8];
+      corner_fixed<DPN>(rel, l, a);
+      if (!corner_lattice(F::LAT, rel, l, b) || !std::equal(a, a + 8, b)) return false;
+    }
+  for (size_t t = 0; t < H.tile_addr.size(); ++t)
+    if (H.tile_addr[t])
+      for (int i = 0; i < F::NODES; ++i)
+        if (lattice_word_fixed<DPN>(i, H.tile_addr[t], H.tile_g0[t], H.sy, H.sz) !=
+            lattice_word(i, F::LAT, H.tile_addr[t], H.tile_g0[t], H.sy, H.sz))
+          return false;
   return true;
 }
 
@@ -1118,6 +1226,10 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   tm.split = block && hex && H.split && !H.corner_collision;
   tm.all_affine = std::all_of(H.tile_affine.begin(), H.tile_affine.end(),
                               [](uint8_t a) { return a != 0; });
+  tm.fixed = op.dpn() == 1 ? fixed_tiles<1>(H) : fixed_tiles<3>(H);
+  tm.fixed = tm.fixed && tm.split && op.variant == Q1_V_BLOCK && op.elem == Q1_HEX8;
+  if (const char *e = std::getenv("Q1_FIXED_TILE"))  // "0": the general-shape instances
+    if (e[0] == '0') tm.fixed = false;
   auto up = [&](auto **dst, const auto &v) -> int {
     using E = typename std::remove_reference<decltype(v)>::type::value_type;
     const size_t b = std::max<size_t>(1, v.size()) * sizeof(E);
@@ -1223,6 +1335,9 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
     using tt = std::true_type;
     using ff = std::false_type;
     auto kb = pa ? pick(tt{}, ff{}) : allpar ? pick(ff{}, tt{}) : pick(ff{}, ff{});
+    if (tm.fixed)
+      kb = allpar ? k_apply_block<T, PH, false, kAccSplit, false, true, true>
+                  : k_apply_block<T, PH, false, kAccSplit, false, false, true>;
     hipLaunchKernelGGL(kb, dim3(tm.n_tiles), dim3(256), lds, s, tm.max_nodes, op.n_nodes,
                        tm.node_ptr, tm.nodes, tm.tile_step,
                        reinterpret_cast<const uint4 *>(tm.lconn),
