@@ -268,7 +268,7 @@ int q1_pcg(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit
  * each workspace entry before it reads it (the status record is cleared by a
  * kernel, not a memset).  Synchronises `stream`. */
 #define Q1_NOALLOC_MAX_DOF 3145728
-#define Q1_NOALLOC_BYTES (256 + 8 * 1024 * 8 + 4 * (size_t)Q1_NOALLOC_MAX_DOF * 8)
+#define Q1_NOALLOC_BYTES (256 + 8 * 1024 * 8 + 32768 * 8 + 4 * (size_t)Q1_NOALLOC_MAX_DOF * 8)
 int q1_pcg_noalloc(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, int maxit,
                    q1_stats *st, void *stream);
 

@@ -129,6 +129,14 @@ int launch_diag_family(Op &op, void *d, hipStream_t s);
 int validate_conn(const Op &op, hipStream_t s);
 int build_tiles(Op &op, hipStream_t s);
 int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop);
+// y = A x with the partial sums of x.y formed where y is written (per tile over its
+// own nodes, per halo-sum workgroup over shared and Dirichlet nodes plus a fixed
+// range of the tile partials): block and partial-assembly hexahedron operators.
+// apply_dot_parts: doubles the launch needs at parts (0: not available) and, in
+// *n_final, how many partials at parts[0..) make up x.y.
+int64_t apply_dot_parts(const Op &op, int64_t *n_final);
+int launch_apply_dot(Op &op, const void *x, void *y, hipStream_t s, const int *stop,
+                     double *parts);
 int launch_diag_tile(Op &op, void *d, hipStream_t s);
 void free_tiles(Op &op);
 int build_colors(Op &op, hipStream_t s);

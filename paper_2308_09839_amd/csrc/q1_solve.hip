@@ -38,6 +38,9 @@ namespace q1 {
 
 constexpr int kRT = 256;      // threads per reduction block
 constexpr int kMaxRB = 1024;  // partial sums per reduction (4 blocks per compute unit)
+// partials of p.q that a block apply may form (tile and halo-sum workgroups); an
+// operator needing more takes the separate dot kernel
+constexpr int kMaxDotParts = 32768;
 
 // Device status record, read by the host every few iterations.
 struct Status {
@@ -53,8 +56,9 @@ struct Status {
 constexpr int64_t kNoAllocMaxDof = Q1_NOALLOC_MAX_DOF;
 constexpr size_t kNoAllocHead = 256;  // status record, padded
 constexpr size_t kNoAllocPart = size_t(8) * kMaxRB * sizeof(double);
+constexpr size_t kNoAllocDot = size_t(kMaxDotParts) * sizeof(double);
 constexpr size_t kNoAllocVec = size_t(kNoAllocMaxDof) * sizeof(double);
-constexpr size_t kNoAllocBytes = kNoAllocHead + kNoAllocPart + 4 * kNoAllocVec;
+constexpr size_t kNoAllocBytes = kNoAllocHead + kNoAllocPart + kNoAllocDot + 4 * kNoAllocVec;
 static_assert(kNoAllocBytes == Q1_NOALLOC_BYTES, "header and workspace layout disagree");
 static_assert(sizeof(Status) <= kNoAllocHead, "status record exceeds its slot");
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
@@ -118,6 +122,23 @@ __device__ __forceinline__ void sum_partials_n(const double *const (&rows)[R], i
   block_sum<R>(out);
 }
 
+// sum_partials_n with a count per row (each row added in the order sum_partials uses)
+template <int R>
+__device__ __forceinline__ void sum_partials_nc(const double *const (&rows)[R],
+                                                const int (&cnt)[R], double (&out)[R]) {
+  int m = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    out[r] = 0.0;
+    m = cnt[r] > m ? cnt[r] : m;
+  }
+  for (int j = int(threadIdx.x); j < m; j += kRT)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (j < cnt[r]) out[r] += rows[r][j];
+  block_sum<R>(out);
+}
+
 struct Range {
   int64_t i0, i1;
 };
@@ -178,16 +199,17 @@ __global__ __launch_bounds__(kRT) void k_dot(int64_t n, const T *__restrict__ a,
 // FLEX (flexible PCG): keeps r_k in r_old and leaves rho_{k+1} to the
 // preconditioner step.  TP, the type of p and q, is float in the mixed-precision
 // solver (FP32 operator), whose x, r and w stay in double.
+// npq: the number of p.q partials (the apply's when it forms them, else gridDim.x).
 template <typename T, bool FLEX, typename TP = T>
 __global__ __launch_bounds__(kRT) void k_pcg_update(
     int64_t n, const TP *__restrict__ p, const TP *__restrict__ q, const T *__restrict__ w,
     T *__restrict__ x, T *__restrict__ r, T *__restrict__ r_old,
-    const double *__restrict__ part_pq, const double *__restrict__ part_rho_k,
+    const double *__restrict__ part_pq, int npq, const double *__restrict__ part_rho_k,
     double *__restrict__ part_rho_k1, double *__restrict__ part_rr, Status *__restrict__ st) {
   if (st->done) return;
   const int nb = gridDim.x;
   double t[2];
-  sum_partials_n<2>({part_pq, part_rho_k}, nb, t);
+  sum_partials_nc<2>({part_pq, part_rho_k}, {npq, nb}, t);
   const double pq = t[0], rho = t[1];
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -557,6 +579,7 @@ struct Work {
   void *r = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *r_old = nullptr,
        *z = nullptr;
   double *part = nullptr;  // [8][kMaxRB]
+  double *dparts = nullptr;  // [kMaxDotParts]: p.q partials formed by the apply
   Status *st = nullptr;    // device
   Status *hst = nullptr;   // host mirror (pinned when owned)
   bool owned = true;       // false: the buffers live in the static scratch array
@@ -564,7 +587,7 @@ struct Work {
   Work(const Work &) = delete;
   ~Work() {
     if (!owned) return;
-    void *d[] = {r, p, q, w, r_old, z, part, st};
+    void *d[] = {r, p, q, w, r_old, z, part, dparts, st};
     for (void *v : d)
       if (v) (void)hipFree(v);
     if (hst) (void)hipHostFree(hst);
@@ -590,6 +613,7 @@ int alloc_work(Work &W, int64_t n, bool flex) {
     Q1_HIP(hipMalloc(&W.z, b));
   }
   Q1_HIP(hipMalloc(&W.part, 8 * kMaxRB * sizeof(double)));
+  Q1_HIP(hipMalloc(&W.dparts, kMaxDotParts * sizeof(double)));
   Q1_HIP(hipMalloc(&W.st, sizeof(Status)));
   Q1_HIP(hipHostMalloc(&W.hst, sizeof(Status), hipHostMallocDefault));
   return Q1_OK;
@@ -663,6 +687,13 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
   double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB;
   T *r = static_cast<T *>(W.r), *p = static_cast<T *>(W.p), *q = static_cast<T *>(W.q),
     *w = static_cast<T *>(W.w);
+  // block operators form the partials of p.q while writing q (one pass less per
+  // iteration); the decision depends on the operator alone, so the allocating and
+  // the static-workspace entry points compute the same sums
+  int64_t n_dot = 0;
+  const int64_t need_dot = apply_dot_parts(op, &n_dot);
+  const bool fused_dot = need_dot > 0 && need_dot <= kMaxDotParts && W.dparts;
+  const int npq = fused_dot ? int(n_dot) : nb;
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, W.st);
   hipLaunchKernelGGL((k_pcg_init<T>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r, p, part_rho[0],
                      part_bb, 1);
@@ -683,11 +714,15 @@ int pcg_t(Op &op, int pc, const T *b, T *x, double rtol, int maxit, q1_stats *st
       const int m = std::min(batch, maxit - launched);
       for (int j = 0; j < m; ++j) {
         const int k = launched + j;
-        if ((rc = launch_apply(op, p, q, s, &W.st->done))) return rc;
-        hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
+        if (fused_dot) {  // p.q partials formed by the apply
+          if ((rc = launch_apply_dot(op, p, q, s, &W.st->done, W.dparts))) return rc;
+        } else {
+          if ((rc = launch_apply(op, p, q, s, &W.st->done))) return rc;
+          hipLaunchKernelGGL((k_dot<T>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
+        }
         hipLaunchKernelGGL((k_pcg_update<T, false>), dim3(nb), dim3(kRT), 0, s, n, p, q, w, x, r,
-                           nullptr, part_pq, part_rho[k & 1], part_rho[(k + 1) & 1], part_rr,
-                           W.st);
+                           nullptr, fused_dot ? W.dparts : part_pq, npq, part_rho[k & 1],
+                           part_rho[(k + 1) & 1], part_rr, W.st);
         hipLaunchKernelGGL((k_pcg_direction<T>), dim3(nb), dim3(kRT), 0, s, n, r, w, nullptr, p,
                            part_rho[(k + 1) & 1], part_rho[k & 1], part_rr, part_bb, tol2, k + 1,
                            maxit, W.st);
@@ -934,6 +969,11 @@ int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double del
   double *part_rho[2] = {P, P + kMaxRB};
   double *part_pq = P + 2 * kMaxRB, *part_rr = P + 3 * kMaxRB, *part_bb = P + 4 * kMaxRB;
   double *r = static_cast<double *>(W.r), *w = static_cast<double *>(W.w);
+  // the FP32 block apply forms the partials of p.q (as in pcg_t)
+  int64_t n_dot = 0;
+  const int64_t need_dot = apply_dot_parts(A32, &n_dot);
+  const bool fused_dot = need_dot > 0 && need_dot <= kMaxDotParts && W.dparts;
+  const int npq = fused_dot ? int(n_dot) : nb;
   Q1_HIP(hipMemsetAsync(W.st, 0, sizeof(Status), s));
   // x = 0, r = b, partials of rho_0 = b.(w b) and b.b; p = (float) (w b)
   hipLaunchKernelGGL((k_pcg_init<double>), dim3(nb), dim3(kRT), 0, s, n, b, w, x, r, nullptr,
@@ -956,11 +996,16 @@ int mpcg_t(Op &A64, Op &A32, const double *b, double *x, double rtol, double del
       while (!stop && k < maxit) {
         const int m = std::min(batch, maxit - k);
         for (int j = 0; j < m; ++j, ++k) {
-          if ((rc = launch_apply(A32, p, q, s, &W.st->done))) return rc;
-          hipLaunchKernelGGL((k_dot<float>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq, W.st);
+          if (fused_dot) {
+            if ((rc = launch_apply_dot(A32, p, q, s, &W.st->done, W.dparts))) return rc;
+          } else {
+            if ((rc = launch_apply(A32, p, q, s, &W.st->done))) return rc;
+            hipLaunchKernelGGL((k_dot<float>), dim3(nb), dim3(kRT), 0, s, n, p, q, part_pq,
+                               W.st);
+          }
           hipLaunchKernelGGL((k_pcg_update<double, false, float>), dim3(nb), dim3(kRT), 0, s, n,
-                             p, q, w, x, r, nullptr, part_pq, part_rho[k & 1],
-                             part_rho[(k + 1) & 1], part_rr, W.st);
+                             p, q, w, x, r, nullptr, fused_dot ? W.dparts : part_pq, npq,
+                             part_rho[k & 1], part_rho[(k + 1) & 1], part_rr, W.st);
           hipLaunchKernelGGL((k_pcg_direction<double, float>), dim3(nb), dim3(kRT), 0, s, n, r,
                              w, nullptr, p, part_rho[(k + 1) & 1], part_rho[k & 1], part_rr,
                              part_bb, thr / bb, k + 1, maxit, W.st);
@@ -1093,7 +1138,8 @@ int q1_pcg_noalloc(q1_op *op, int pc, const void *b_d, void *x_d, double rtol, i
   W.owned = false;
   W.st = reinterpret_cast<Status *>(base);
   W.part = reinterpret_cast<double *>(base + kNoAllocHead);
-  unsigned char *v = base + kNoAllocHead + kNoAllocPart;
+  W.dparts = reinterpret_cast<double *>(base + kNoAllocHead + kNoAllocPart);
+  unsigned char *v = base + kNoAllocHead + kNoAllocPart + kNoAllocDot;
   W.r = v;
   W.p = v + kNoAllocVec;
   W.q = v + 2 * kNoAllocVec;

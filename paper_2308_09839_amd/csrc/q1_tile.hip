@@ -172,6 +172,18 @@ __global__ void k_reset_nodes(int64_t n, const int32_t *__restrict__ ids,
 // lane).  This is that compiler-only barrier; it emits no instruction.
 __device__ __forceinline__ void lane_order() { asm volatile("" ::: "memory"); }
 
+// Sum of one value per thread over a 256-thread workgroup in a fixed order (a
+// wavefront shuffle tree, then the four wavefront sums in order); the result
+// is valid in thread 0.  Every thread of the workgroup must call it.
+__device__ __forceinline__ double block_sum_256(double v) {
+  __shared__ double wsum[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
 template <typename T, bool LDS_ATOMIC>
 __device__ __forceinline__ void acc_add(T *p, T v) {
   if constexpr (LDS_ATOMIC)
@@ -455,7 +467,7 @@ __global__ __launch_bounds__(256) void k_apply_block(
     const int *__restrict__ stop, const uint8_t *__restrict__ tile_affine,
     const int32_t *__restrict__ slot, T *__restrict__ halo, const T *__restrict__ qdata,
     const uint32_t *__restrict__ tile_lat, const uint32_t *__restrict__ tile_addr,
-    const int32_t *__restrict__ tile_g0, int64_t sy, int64_t sz) {
+    const int32_t *__restrict__ tile_g0, int64_t sy, int64_t sz, double *__restrict__ dot_part) {
   constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
   constexpr int UOFF = PA ? 0 : 3;
@@ -567,7 +579,9 @@ __global__ __launch_bounds__(256) void k_apply_block(
   }
   __syncthreads();
   // nodes of this tile only: y; nodes shared with other tiles: this tile's halo
-  // slot (summed by k_halo_sum); Dirichlet nodes: written by k_halo_sum
+  // slot (summed by k_halo_sum); Dirichlet nodes: written by k_halo_sum.
+  // dot_part: this tile's share of x.y, over the nodes it writes to y
+  double dsum = 0.0;
   auto write_node = [&](int i, uint32_t raw, int32_t sl) {
     if (raw & kFixedBit) return;
     const int64_t gg = raw & kIdMask;
@@ -579,23 +593,36 @@ __global__ __launch_bounds__(256) void k_apply_block(
         v = sV[o];
       else
         v = (sV[o] + sV[cs + o]) + (sV[2 * cs + o] + sV[3 * cs + o]);
-      if (raw & kSharedBit)
+      if (raw & kSharedBit) {
         halo[int64_t(sl) * DPN + j] = v;
-      else
+      } else {
         y[gg * DPN + j] = v;
+        if (dot_part) dsum += double(sR[size_t(UOFF + j) * MN + i]) * double(v);
+      }
     }
   };
 #pragma unroll
   for (int k = 0; k < KN; ++k)
     if (k * 256 + tid < nm) write_node(k * 256 + tid, keep[k], kslot[k]);
   for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, word(i), slot[n0 + i]);
+  if (dot_part) {
+    const double t = block_sum_256(dsum);
+    if (tid == 0) dot_part[tile] = t;
+  }
+}
+
+// Byte offset of the tetrahedron kernel's FP64 accumulator after the node
+// records (rec_bytes per node), rounded up to 8 bytes.
+__host__ __device__ inline size_t tet_acc_offset(int max_nodes, size_t rec_bytes) {
+  return (size_t(max_nodes) * rec_bytes + 7) & ~size_t(7);
 }
 
 // Block apply of linear tetrahedra: the block kernel's staging, write-back
 // and halo slots with the tetrahedron's element (tet_element); a tile is a
 // brick of cells' tetrahedra, wave w takes its steps w, w + 4, ... and adds
-// each tetrahedron's 4 corner contributions into one LDS accumulator with LDS
-// atomics (the order of those additions varies).
+// each tetrahedron's 4 corner contributions into one FP64 LDS accumulator with
+// LDS atomics (the order of those additions varies; FP64 in both precisions,
+// since the FP32 LDS atomic add measured twice as slow here).
 template <typename T, int PH>
 __global__ __launch_bounds__(256) void k_apply_block_tet(
     int max_nodes, int64_t nn, const int32_t *__restrict__ node_ptr,
@@ -606,59 +633,107 @@ __global__ __launch_bounds__(256) void k_apply_block_tet(
   constexpr int DPN = phys_dpn(PH);
   if (stop && *stop) return;
   constexpr int NR = 3 + DPN;
+  constexpr int KN = 4;  // node records per thread issued together (1024 per round)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sR = reinterpret_cast<T *>(smem_raw);  // [NR][max_nodes]
-  T *sV = sR + size_t(NR) * max_nodes;       // [DPN][max_nodes]
+  // the accumulator is FP64 in both precisions ([DPN][max_nodes], 8-byte aligned)
+  double *sV = reinterpret_cast<double *>(smem_raw + tet_acc_offset(max_nodes, NR * sizeof(T)));
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int tile = xcd_block_t(blockIdx.x, gridDim.x);
   const int n0 = node_ptr[tile], nm = node_ptr[tile + 1] - n0;
   const int s0 = tile_step[tile], s1 = tile_step[tile + 1];
-  for (int i = tid; i < nm; i += 256) {
-    const uint32_t raw = nodes[n0 + i];
-    const int64_t g = raw & kIdMask;
-    const bool fixed = (raw & kFixedBit) != 0;
+  // staging: all loads of a round (node words, then coordinates, input and the
+  // halo slots of shared entries) are issued before any LDS write; the first
+  // round's words and slots stay in registers for the write-back
+  uint32_t keep[KN];
+  int32_t kslot[KN];
+  for (int base = 0; base < nm; base += KN * 256) {
+    uint32_t raw[KN];
+    int32_t sl[KN];
+    T rec[KN][NR];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) sR[size_t(r) * max_nodes + i] = xyz[r * nn + g];
+    for (int k = 0; k < KN; ++k) raw[k] = nodes[n0 + min(base + k * 256 + tid, nm - 1)];
 #pragma unroll
-    for (int j = 0; j < DPN; ++j) {
-      sR[size_t(3 + j) * max_nodes + i] = fixed ? T(0) : x[g * DPN + j];
-      sV[size_t(j) * max_nodes + i] = T(0);
+    for (int k = 0; k < KN; ++k) {
+      const int64_t g = raw[k] & kIdMask;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) rec[k][r] = xyz[r * nn + g];
+#pragma unroll
+      for (int j = 0; j < DPN; ++j) rec[k][3 + j] = x[g * DPN + j];
+      sl[k] = slot[raw[k] & kSharedBit ? n0 + min(base + k * 256 + tid, nm - 1) : n0];
+    }
+    if (base == 0) {
+#pragma unroll
+      for (int k = 0; k < KN; ++k) {
+        keep[k] = raw[k];
+        kslot[k] = sl[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+      const int i = base + k * 256 + tid;
+      if (i < nm) {
+        const bool fixed = (raw[k] & kFixedBit) != 0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) sR[size_t(r) * max_nodes + i] = rec[k][r];
+#pragma unroll
+        for (int j = 0; j < DPN; ++j) {
+          sR[size_t(3 + j) * max_nodes + i] = fixed ? T(0) : rec[k][3 + j];
+          sV[size_t(j) * max_nodes + i] = 0.0;
+        }
+      }
     }
   }
   __syncthreads();
-  for (int s = s0 + w; s < s1; s += 4) {
-    const int64_t sl = int64_t(s) * kLanes + lane;
-    const uint4 pk = lconn[sl];
-    if (pk.x == 0xffffffffu) continue;  // empty lane
-    const int lc[4] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff), int(pk.y >> 16)};
-    T X[3][4], u[DPN][4], v[DPN][4];
+  // steps w, w + 4, ...: each step's corner indices and coefficients are
+  // requested one step ahead (at a clamped step, unconditionally)
+  int s = s0 + w;
+  int64_t sl0 = int64_t(min(s, s1 - 1)) * kLanes + lane;
+  uint4 pk = lconn[sl0];
+  T c0 = coef_t[sl0], c1 = PH == 3 ? coef_t[coef_stride + sl0] : T(0);
+  for (; s < s1; s += 4) {
+    const int64_t sn = int64_t(min(s + 4, s1 - 1)) * kLanes + lane;
+    const uint4 pkn = lconn[sn];
+    const T c0n = coef_t[sn], c1n = PH == 3 ? coef_t[coef_stride + sn] : T(0);
+    if (pk.x != 0xffffffffu) {  // empty lanes skip
+      const int lc[4] = {int(pk.x & 0xffff), int(pk.x >> 16), int(pk.y & 0xffff),
+                         int(pk.y >> 16)};
+      T X[3][4], u[DPN][4], v[DPN][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < 4; ++a) {
 #pragma unroll
-      for (int r = 0; r < 3; ++r) X[r][a] = sR[size_t(r) * max_nodes + lc[a]];
+        for (int r = 0; r < 3; ++r) X[r][a] = sR[size_t(r) * max_nodes + lc[a]];
 #pragma unroll
-      for (int j = 0; j < DPN; ++j) u[j][a] = sR[size_t(3 + j) * max_nodes + lc[a]];
+        for (int j = 0; j < DPN; ++j) u[j][a] = sR[size_t(3 + j) * max_nodes + lc[a]];
+      }
+      tet_element<T, PH>(X, u, c0, c1, v);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < DPN; ++j)
+          lds_add(&sV[size_t(j) * max_nodes + lc[a]], double(v[j][a]));
     }
-    tet_element<T, PH>(X, u, coef_t[sl], PH == 3 ? coef_t[coef_stride + sl] : T(0), v);
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int j = 0; j < DPN; ++j) lds_add(&sV[size_t(j) * max_nodes + lc[a]], v[j][a]);
+    pk = pkn;
+    c0 = c0n;
+    c1 = c1n;
   }
   __syncthreads();
-  for (int i = tid; i < nm; i += 256) {
-    const uint32_t raw = nodes[n0 + i];
-    if (raw & kFixedBit) continue;  // y = x written by k_halo_sum
+  auto write_node = [&](int i, uint32_t raw, int32_t sl) {
+    if (raw & kFixedBit) return;  // y = x written by k_halo_sum
     const int64_t g = raw & kIdMask;
 #pragma unroll
     for (int j = 0; j < DPN; ++j) {
-      const T v = sV[size_t(j) * max_nodes + i];
+      const T v = T(sV[size_t(j) * max_nodes + i]);
       if (raw & kSharedBit)
-        halo[int64_t(slot[n0 + i]) * DPN + j] = v;
+        halo[int64_t(sl) * DPN + j] = v;
       else
         y[g * DPN + j] = v;
     }
-  }
+  };
+#pragma unroll
+  for (int k = 0; k < KN; ++k)
+    if (k * 256 + tid < nm) write_node(k * 256 + tid, keep[k], kslot[k]);
+  for (int i = KN * 256 + tid; i < nm; i += 256) write_node(i, nodes[n0 + i], slot[n0 + i]);
 }
 
 // Diagonal of A on the block variants' tiles with the split accumulation
@@ -772,7 +847,10 @@ __global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__re
                                                   const T *__restrict__ x,
                                                   const T *__restrict__ halo,
                                                   T *__restrict__ y,
-                                                  const int *__restrict__ stop) {
+                                                  const int *__restrict__ stop,
+                                                  double *__restrict__ dot_part,
+                                                  const double *__restrict__ tile_part,
+                                                  int64_t n_tiles) {
   if (stop && *stop) return;
   const int64_t base = int64_t(blockIdx.x) * 256 * kHaloNpt + threadIdx.x;
   int64_t jj[kHaloNpt];
@@ -795,14 +873,26 @@ __global__ __launch_bounds__(256) void k_halo_sum(int64_t n, const int32_t *__re
     for (int32_t k = e0[p]; k < e1[p]; ++k)
 #pragma unroll
       for (int c = 0; c < DPN; ++c) acc[p][c] += halo[(2 * n + k) * DPN + c];
+  double dsum = 0.0;
 #pragma unroll
   for (int p = 0; p < kHaloNpt; ++p) {
     if (base + p * 256 >= n) continue;
     const bool fixed = h[p] < 0, orphan = (h[p] & 0x40000000) != 0;
     const int64_t g = h[p] & 0x3fffffff;
 #pragma unroll
-    for (int c = 0; c < DPN; ++c)
-      y[g * DPN + c] = fixed ? (x ? x[g * DPN + c] : T(1)) : orphan ? T(0) : acc[p][c];
+    for (int c = 0; c < DPN; ++c) {
+      const T v = fixed ? (x ? x[g * DPN + c] : T(1)) : orphan ? T(0) : acc[p][c];
+      y[g * DPN + c] = v;
+      if (dot_part) dsum += double(x[g * DPN + c]) * double(v);
+    }
+  }
+  // dot_part: x.y over this workgroup's nodes plus its range of the tile partials
+  if (dot_part) {
+    const int64_t t0 = n_tiles * blockIdx.x / gridDim.x;
+    const int64_t t1 = n_tiles * (blockIdx.x + 1) / gridDim.x;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) dsum += tile_part[t];
+    const double tot = block_sum_256(dsum);
+    if (threadIdx.x == 0) dot_part[blockIdx.x] = tot;
   }
 }
 
@@ -1286,13 +1376,25 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
 // one per wave for FP32)
 size_t block_lds_bytes(const Op &op) {
   const size_t rb = op.dtype == Q1_F64 ? 8 : 4;
+  if (op.elem == Q1_TET4)  // records, then the FP64 accumulator
+    return tet_acc_offset(op.tiles.max_nodes, rb * (3 + op.dpn())) +
+           size_t(op.tiles.max_nodes) * 8 * op.dpn();
   const size_t nacc = op.tiles.split || op.dtype == Q1_F64 || op.elem == Q1_TET4 ? 1 : 4;
   const size_t ncoord = op.variant == Q1_V_PA ? 0 : 3;
   return size_t(op.tiles.max_nodes) * rb * size_t(ncoord + op.dpn() + nacc * op.dpn());
 }
 
+// Halo-sum workgroups of an operator's block apply.
+int64_t halo_blocks(const TileMap &tm) {
+  return (tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt);
+}
+
+// dot: optional partials of x.y (block variants of hexahedra): with shared or
+// Dirichlet nodes, halo_blocks(tm) partials at dot[0..) that include the tile
+// partials at dot[halo_blocks(tm)..); without them, the tile partials at dot[0..).
 template <typename T, int PH>
-int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop) {
+int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop,
+                 double *dot = nullptr) {
   constexpr int DPN = phys_dpn(PH);
   const TileMap &tm = op.tiles;
   const T *x = static_cast<const T *>(xv);
@@ -1305,7 +1407,7 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block && op.elem == Q1_TET4) {
     if constexpr (PH != 2) {
-      const size_t tl = size_t(tm.max_nodes) * sizeof(T) * (3 + 2 * DPN);
+      const size_t tl = block_lds_bytes(op);
       hipLaunchKernelGGL((k_apply_block_tet<T, PH>), dim3(tm.n_tiles), dim3(256), tl, s,
                          tm.max_nodes, op.n_nodes, tm.node_ptr, tm.nodes, tm.tile_step,
                          reinterpret_cast<const uint4 *>(tm.lconn),
@@ -1313,10 +1415,10 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
                          static_cast<const T *>(op.xyz), x, y, stop, tm.slot,
                          static_cast<T *>(tm.halo));
       if (tm.n_reset > 0)
-        hipLaunchKernelGGL((k_halo_sum<T, DPN>),
-                           dim3(int((tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt))),
-                           dim3(256), 0, s, tm.n_reset, tm.hnode, tm.hptr, x,
-                           static_cast<const T *>(tm.halo), y, stop);
+        hipLaunchKernelGGL((k_halo_sum<T, DPN>), dim3(int(halo_blocks(tm))), dim3(256), 0, s,
+                           tm.n_reset, tm.hnode, tm.hptr, x, static_cast<const T *>(tm.halo), y,
+                           stop, static_cast<double *>(nullptr),
+                           static_cast<const double *>(nullptr), int64_t(0));
       Q1_HIP(hipGetLastError());
       return Q1_OK;
     }
@@ -1344,12 +1446,12 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
                        static_cast<const T *>(tm.coef_t), tm.n_steps * kLanes,
                        static_cast<const T *>(op.xyz), x, y, stop, tm.tile_affine, tm.slot,
                        static_cast<T *>(tm.halo), static_cast<const T *>(tm.qdata),
-                       tm.tile_lat, tm.tile_addr, tm.tile_g0, tm.sy, tm.sz);
+                       tm.tile_lat, tm.tile_addr, tm.tile_g0, tm.sy, tm.sz,
+                       dot ? dot + (tm.n_reset > 0 ? halo_blocks(tm) : 0) : nullptr);
     if (tm.n_reset > 0)
-      hipLaunchKernelGGL((k_halo_sum<T, DPN>),
-                         dim3(int((tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt))), dim3(256),
-                         0, s, tm.n_reset, tm.hnode, tm.hptr, x,
-                         static_cast<const T *>(tm.halo), y, stop);
+      hipLaunchKernelGGL((k_halo_sum<T, DPN>), dim3(int(halo_blocks(tm))), dim3(256), 0, s,
+                         tm.n_reset, tm.hnode, tm.hptr, x, static_cast<const T *>(tm.halo), y,
+                         stop, dot, dot ? dot + halo_blocks(tm) : nullptr, int64_t(tm.n_tiles));
     Q1_HIP(hipGetLastError());
     return Q1_OK;
   }
@@ -1431,10 +1533,11 @@ int launch_diag_tile(Op &op, void *dv, hipStream_t s) {
                        static_cast<const T *>(op.xyz), d, tm.slot, static_cast<T *>(tm.halo),
                        tm.tile_lat);
     if (tm.n_reset > 0)
-      hipLaunchKernelGGL((k_halo_sum<T, DPN>),
-                         dim3(int((tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt))), dim3(256),
-                         0, s, tm.n_reset, tm.hnode, tm.hptr, static_cast<const T *>(nullptr),
-                         static_cast<const T *>(tm.halo), d, static_cast<const int *>(nullptr));
+      hipLaunchKernelGGL((k_halo_sum<T, DPN>), dim3(int(halo_blocks(tm))), dim3(256), 0, s,
+                         tm.n_reset, tm.hnode, tm.hptr, static_cast<const T *>(nullptr),
+                         static_cast<const T *>(tm.halo), d, static_cast<const int *>(nullptr),
+                         static_cast<double *>(nullptr), static_cast<const double *>(nullptr),
+                         int64_t(0));
     Q1_HIP(hipGetLastError());
     return Q1_OK;
   });
@@ -1443,6 +1546,23 @@ int launch_diag_tile(Op &op, void *dv, hipStream_t s) {
 int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *stop) {
   return dispatch_phys(op, [&](auto t, auto ph) {
     return apply_tile_t<decltype(t), decltype(ph)::value>(op, x, y, s, stop);
+  });
+}
+
+int64_t apply_dot_parts(const Op &op, int64_t *n_final) {
+  const bool block = (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) && op.elem == Q1_HEX8;
+  if (!block || op.tiles.n_tiles == 0) return 0;
+  const int64_t h = op.tiles.n_reset > 0 ? halo_blocks(op.tiles) : 0;
+  if (n_final) *n_final = h > 0 ? h : op.tiles.n_tiles;
+  return h + op.tiles.n_tiles;
+}
+
+int launch_apply_dot(Op &op, const void *x, void *y, hipStream_t s, const int *stop,
+                     double *parts) {
+  Q1_CHECK(apply_dot_parts(op, nullptr) > 0, Q1_EUNSUPPORTED,
+           "apply with partial dot products: block variants of hexahedra only");
+  return dispatch_phys(op, [&](auto t, auto ph) {
+    return apply_tile_t<decltype(t), decltype(ph)::value>(op, x, y, s, stop, parts);
   });
 }
 
