@@ -39,8 +39,8 @@ ROTATE = 4  # resident copies the timed applies rotate over
 # were taken hashes differently, so its traffic is reported as null.
 KERNEL_SOURCES = ("paper_2308_09839_amd/csrc/q1_tile.hip", "paper_2308_09839_amd/csrc/q1_elem.hpp")
 MEASURED_TRAFFIC: dict = {
-    # 128^3: FETCH_SIZE 54,447 + 10,265 KiB (x 2), WRITE_SIZE 26,214 + 8,004 KiB (x 1) per apply
-    ("a114468c0b2d2e56", 128): 167.6e6,
+    # 128^3: FETCH_SIZE 54,489 + 10,269 KiB (x 2), WRITE_SIZE 26,256 + 8,004 KiB (x 1) per apply
+    ("d298bb2c2004594e", 128): 167.7e6,
 }
 
 
