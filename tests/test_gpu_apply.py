@@ -55,13 +55,15 @@ def test_apply_parity(q1, orc, physics, n, jitter, mask, dtype, variant):
     assert np.max(np.abs(y - ref)) <= 10 * TOL[dtype] * np.max(np.abs(ref))
 
 
-# Boxes made of whole default tiles (16 x 8 x 4 elements for the scalar kind,
-# 16 x 4 x 4 for the 3-DOF kinds): the block variant's instances with the tile
+# Boxes made of whole default tiles: the block variant's instances with the tile
 # shape built in, for parallelepipeds and general hexahedra, with and without
 # Dirichlet nodes (whose tiles load their node words instead of computing them).
+# Scalar kind: 16 x 8 x 4 tiles; 3-DOF kinds: 16 x 4 x 4 tiles.
 FIXED_TILE_CASES = [
     # physics, elements, jitter, mask
     (1, (16, 8, 4), 0.0, False),
+    (1, (16, 8, 16), 0.0, True),
+    (1, (32, 16, 16), 0.1, False),
     (1, (32, 16, 8), 0.0, False),
     (1, (32, 16, 8), 0.0, True),
     (1, (48, 24, 12), 0.0, True),
