@@ -98,45 +98,49 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
   }
 }
 
-// Re-reduce nb <= kMaxRB partials written by an earlier kernel: thread t adds
-// partials t, t + 256, ... in order, then the fixed block sum (same value in
-// every block).
-__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb) {
-  double v[1] = {0.0};
-  for (int j = int(threadIdx.x); j < nb; j += kRT) v[0] += part[j];
-  block_sum<1>(v);
-  return v[0];
-}
-
-// Several partial rows re-reduced at once: out[r] is what sum_partials gives
-// for row r (the same order of additions), with one block reduction instead
-// of one per row.
-template <int R>
-__device__ __forceinline__ void sum_partials_n(const double *const (&rows)[R], int nb,
-                                               double (&out)[R]) {
-#pragma unroll
-  for (int r = 0; r < R; ++r) out[r] = 0.0;
-  for (int j = int(threadIdx.x); j < nb; j += kRT)
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[r] += rows[r][j];
-  block_sum<R>(out);
-}
-
-// sum_partials_n with a count per row (each row added in the order sum_partials uses)
+// Re-reduce the partials written by an earlier kernel, R rows of cnt[r] >= 1
+// partials each: thread t adds partials t, t + 256, ... of each row in order,
+// then the fixed block sum (the same value in every block).  The loads of four
+// rounds are issued together, at clamped indices, before any of them is added.
 template <int R>
 __device__ __forceinline__ void sum_partials_nc(const double *const (&rows)[R],
                                                 const int (&cnt)[R], double (&out)[R]) {
+  constexpr int U = 4;
   int m = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     out[r] = 0.0;
     m = cnt[r] > m ? cnt[r] : m;
   }
-  for (int j = int(threadIdx.x); j < m; j += kRT)
+  for (int j0 = int(threadIdx.x); j0 < m; j0 += U * kRT) {
+    double a[U][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (j < cnt[r]) out[r] += rows[r][j];
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[u][r] = rows[r][min(j0 + u * kRT, cnt[r] - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (j0 + u * kRT < cnt[r]) out[r] += a[u][r];
+  }
   block_sum<R>(out);
+}
+
+// the same with one count for every row
+template <int R>
+__device__ __forceinline__ void sum_partials_n(const double *const (&rows)[R], int nb,
+                                               double (&out)[R]) {
+  int cnt[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) cnt[r] = nb;
+  sum_partials_nc<R>(rows, cnt, out);
+}
+
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb) {
+  double out[1];
+  sum_partials_n<1>({part}, nb, out);
+  return out[0];
 }
 
 struct Range {
@@ -190,7 +194,19 @@ __global__ __launch_bounds__(kRT) void k_dot(int64_t n, const T *__restrict__ a,
   if (st && st->done) return;
   const Range rg = block_range(n);
   double v[1] = {0.0};
-  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) v[0] += double(a[i]) * double(c[i]);
+  constexpr int U = 4;  // a round's loads together, the additions in the order i, i + 256, ...
+  for (int64_t i0 = rg.i0 + threadIdx.x; i0 < rg.i1; i0 += U * kRT) {
+    T av[U], cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = min(i0 + u * kRT, rg.i1 - 1);
+      av[u] = a[i];
+      cv[u] = c[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * kRT < rg.i1) v[0] += double(av[u]) * double(cv[u]);
+  }
   block_sum<1>(v);
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
@@ -221,14 +237,32 @@ __global__ __launch_bounds__(kRT) void k_pcg_update(
   const double alpha = rho / pq;
   const Range rg = block_range(n);
   double v[2] = {0.0, 0.0};
-  for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
-    const T ri = r[i];
-    if constexpr (FLEX) r_old[i] = ri;
-    const T rn = T(double(ri) - alpha * double(q[i]));
-    x[i] = T(double(x[i]) + alpha * double(p[i]));
-    r[i] = rn;
-    if constexpr (!FLEX) v[0] += double(rn) * double(w[i] * rn);
-    v[1] += double(rn) * double(rn);
+  // four elements per thread and round: all their loads (at clamped indices)
+  // before any store; the additions keep the order i, i + 256, ...
+  constexpr int U = 4;
+  for (int64_t i0 = rg.i0 + threadIdx.x; i0 < rg.i1; i0 += U * kRT) {
+    T rv[U], xv[U], wv[U];
+    TP pv[U], qv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = min(i0 + u * kRT, rg.i1 - 1);
+      rv[u] = r[i];
+      xv[u] = x[i];
+      pv[u] = p[i];
+      qv[u] = q[i];
+      if constexpr (!FLEX) wv[u] = w[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * kRT;
+      if (i >= rg.i1) continue;
+      if constexpr (FLEX) r_old[i] = rv[u];
+      const T rn = T(double(rv[u]) - alpha * double(qv[u]));
+      x[i] = T(double(xv[u]) + alpha * double(pv[u]));
+      r[i] = rn;
+      if constexpr (!FLEX) v[0] += double(rn) * double(wv[u] * rn);
+      v[1] += double(rn) * double(rn);
+    }
   }
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -257,9 +291,21 @@ __global__ __launch_bounds__(kRT) void k_pcg_direction(
   if (!stop) {
     const double beta = num / den;
     const Range rg = block_range(n);
-    for (int64_t i = rg.i0 + threadIdx.x; i < rg.i1; i += kRT) {
-      const T zi = z ? z[i] : T(w[i] * r[i]);
-      p[i] = TP(double(zi) + beta * double(p[i]));
+    constexpr int U = 4;  // as in k_pcg_update: a round's loads before its stores
+    for (int64_t i0 = rg.i0 + threadIdx.x; i0 < rg.i1; i0 += U * kRT) {
+      T zv[U];
+      TP pv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = min(i0 + u * kRT, rg.i1 - 1);
+        zv[u] = z ? z[i] : T(w[i] * r[i]);
+        pv[u] = p[i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + u * kRT;
+        if (i < rg.i1) p[i] = TP(double(zv[u]) + beta * double(pv[u]));
+      }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
