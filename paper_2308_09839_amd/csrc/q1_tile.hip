@@ -1294,7 +1294,9 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   if (rc) return rc;
   // lattice addressing for the scalar kind only: measured on 128^3 Laplace FP64
   // (applies streaming from HBM) 46.8 against 44.9 GDOF/s, while the 3-DOF kinds
-  // (fewer nodes per element, more arithmetic per node) ran 3-5% slower with it
+  // (fewer nodes per element, more arithmetic per node) ran 3-5% slower with it;
+  // in their fixed-shape instance it gains 2-3% streaming from HBM but nothing
+  // (FP64) or -5% (FP32) on MALL-resident data, where a solver's applies run
   if (block && hex && op.dpn() == 1) plan_addressing(H);
   else {
     H.tile_addr.assign(H.tile_lat.size(), 0u);
