@@ -184,8 +184,10 @@ int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t 
  * identical inputs give bitwise-identical results (the block and partial-
  * assembly variants on tiles that admit the split accumulation: every node
  * takes its LDS additions from one wavefront per pass, in a fixed order, and
- * shared nodes are summed in tile order; no floating-point atomics), else 0
- * (the atomic scatter variants, and tiles that fall back to LDS atomics). */
+ * shared nodes are summed in tile order; no global atomics; the owner-computes
+ * tiles of the scalar kind on box lattices add with LDS atomics, one
+ * wavefront per node and pass, in program order), else 0 (the atomic scatter
+ * variants, and tiles that fall back to LDS atomics across wavefronts). */
 int q1_op_reproducible(const q1_op *op, int *reproducible);
 /* Algorithmic bytes and FLOPs of one apply under the Table 2 convention with
  * perfect caching: 32 B of node ids and the cell coefficients per element;

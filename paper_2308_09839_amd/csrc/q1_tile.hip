@@ -611,6 +611,206 @@ __global__ __launch_bounds__(256) void k_apply_block(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Owner-computes tiles: the scalar Laplace operator on a box lattice of
+// parallelepipeds (element e = ex + nx (ey + ny ez), node i + (nx+1)(j +
+// (ny+1) k), local corner a = i + 2j + 4k), nx, ny, nz multiples of 16, 8, 4.
+// A workgroup owns a 16 x 8 x 4 box of nodes (the last tile in a direction
+// also owns the mesh's last node plane in it) and computes every element that
+// touches them: 17 x 9 x 5 elements over the 18 x 10 x 6 staged nodes.  What
+// an element adds to a node outside the box is dropped, so every entry of y is
+// written once, with a plain store, by the tile that owns it: no halo slots
+// and no second kernel, for 765 element evaluations per 512 owned nodes (the
+// shell of elements around the box is computed by both tiles beside it).
+//
+// Order of the additions (bitwise reproducible).  Wave w computes element
+// layer w + 1 of the box (153 elements, box row-major) and the w-th quarter of
+// layer 0 (elements [38w, 38(w+1)) of it, the last quarter up to 153), in three
+// steps of 64 lanes.  Pass L adds the lower corners of layer w + 1 into node
+// plane w + 1 (at once, as each step is computed); after a barrier pass U1 adds
+// the upper corners of layer w + 1 into plane w + 2 and those of the layer-0
+// quarters of waves 0 and 2 into plane 1; after another, pass U2 adds those of
+// the quarters of waves 1 and 3 into plane 1.  A quarter spans more than two
+// element rows, so quarters 0 and 2 (and 1 and 3) share no node; in every pass
+// each node receives additions from one wavefront, whose LDS adds execute in
+// program order, and within one instruction the lanes' nodes are distinct.
+// The accumulator is FP64 in both precisions (FP32 LDS atomic adds measured
+// slow here).
+struct OwnTile {
+  static constexpr int OX = 16, OY = 8, OZ = 4;              // owned nodes
+  static constexpr int AX = OX + 1, AY = OY + 1, AZ = OZ + 1;  // accumulator box
+  static constexpr int EX = OX + 1, EY = OY + 1;              // elements per layer
+  static constexpr int SX = OX + 2, SY = OY + 2, SZ = OZ + 2;  // staged nodes
+  static constexpr int NS = SX * SY * SZ;
+  static constexpr int NL = EX * EY;                          // 153
+  static constexpr int NA = AX * AY * AZ;
+  static constexpr int KN = (NS + 255) / 256;
+  static constexpr int NQ = NL / 4;  // elements of a layer-0 quarter (the last one: the rest)
+  static_assert(NL <= 192 && NL + (NL - 3 * NQ) <= 192, "three steps per wave");
+  static_assert(NQ > 2 * EX, "quarters 0 and 2 (1 and 3) share no node");
+  static_assert(OX == 16 && OY == 8, "write-back indexing");
+};
+
+__device__ __forceinline__ void lds_add_own(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <typename T, bool MASK>
+__global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
+                                                     const T *__restrict__ xyz,
+                                                     const T *__restrict__ coef,
+                                                     const uint8_t *__restrict__ mask,
+                                                     const T *__restrict__ x, T *__restrict__ y,
+                                                     const int *__restrict__ stop,
+                                                     double *__restrict__ dot_part) {
+  using F = OwnTile;
+  if (stop && *stop) return;
+  __shared__ T sR[4 * F::NS];   // x, y, z, input (0 on Dirichlet nodes), field by field
+  __shared__ double sV[F::NA];  // accumulator over the owned box
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tile = xcd_block_t(blockIdx.x, gridDim.x);
+  const int ntx = nx / F::OX, nty = ny / F::OY, ntz = nz / F::OZ;
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int hx = F::OX + (tx == ntx - 1), hy = F::OY + (ty == nty - 1),
+            hz = F::OZ + (tz == ntz - 1);
+  const int n1x = nx + 1, n1y = ny + 1;
+  const int64_t nn = int64_t(n1x) * n1y * (nz + 1);
+  // global lattice position of local node / element (0, 0, 0)
+  const int gx0 = tx * F::OX - 1, gy0 = ty * F::OY - 1, gz0 = tz * F::OZ - 1;
+  auto node_id = [&](int gx, int gy, int gz) -> int64_t {
+    return gx + int64_t(n1x) * (gy + int64_t(n1y) * gz);
+  };
+  // stage the node records: every load issued (at clamped positions) before any LDS write
+  T rec[F::KN][4];
+  bool fx[F::KN];
+#pragma unroll
+  for (int k = 0; k < F::KN; ++k) {
+    const int i = min(k * 256 + tid, F::NS - 1);
+    const int c = i / (F::SX * F::SY), r = i - c * (F::SX * F::SY), b = r / F::SX,
+              a = r - b * F::SX;
+    const int64_t g = node_id(min(max(gx0 + a, 0), nx), min(max(gy0 + b, 0), ny),
+                              min(max(gz0 + c, 0), nz));
+    rec[k][0] = xyz[g];
+    rec[k][1] = xyz[nn + g];
+    rec[k][2] = xyz[2 * nn + g];
+    rec[k][3] = x[g];
+    fx[k] = MASK && mask[g] != 0;
+  }
+  // the wave's three steps: element (ea, eb, ec) of the box, its mask of owned
+  // corners (bits 0-3 lower, 4-7 upper; the layer-0 quarters of odd waves
+  // carry their upper corners in bits 8-11, for pass U2) and its cell id
+  const int q0 = F::NQ * w, q1 = w == 3 ? F::NL : F::NQ * (w + 1);
+  int ea[3], eb[3], ec[3];
+  unsigned msk[3];
+  int64_t eg[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int j = k * 64 + lane;
+    const bool own_layer = j < F::NL;
+    const int qj = q0 + j - F::NL;
+    const int lin = own_layer ? j : min(qj, F::NL - 1);
+    ec[k] = own_layer ? w + 1 : 0;
+    eb[k] = lin / F::EX;
+    ea[k] = lin - eb[k] * F::EX;
+    const int gx = gx0 + ea[k], gy = gy0 + eb[k], gz = gz0 + ec[k];
+    const bool live = (own_layer || qj < q1) && gx >= 0 && gy >= 0 && gz >= 0 && gx < nx &&
+                      gy < ny && gz < nz;
+    const unsigned mx = (ea[k] >= 1 ? 1u : 0u) | (ea[k] + 1 <= hx ? 2u : 0u);
+    const unsigned my = (eb[k] >= 1 ? 1u : 0u) | (eb[k] + 1 <= hy ? 2u : 0u);
+    const unsigned mz = (ec[k] >= 1 ? 1u : 0u) | (ec[k] + 1 <= hz ? 2u : 0u);
+    unsigned m = 0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      m |= ((mx >> (a & 1)) & (my >> ((a >> 1) & 1)) & (mz >> (a >> 2)) & 1u) << a;
+    if (!own_layer && (w & 1)) m = (m & 0x0fu) | ((m & 0xf0u) << 4);
+    msk[k] = live ? m : 0u;
+    eg[k] = min(max(gx, 0), nx - 1) + int64_t(nx) * (min(max(gy, 0), ny - 1) +
+                                                     int64_t(ny) * min(max(gz, 0), nz - 1));
+  }
+  T cnext = coef[eg[0]];
+#pragma unroll
+  for (int k = 0; k < F::KN; ++k) {
+    const int i = k * 256 + tid;
+    if (i < F::NS) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) sR[f * F::NS + i] = rec[k][f];
+      sR[3 * F::NS + i] = fx[k] ? T(0) : rec[k][3];
+    }
+  }
+  for (int i = tid; i < F::NA; i += 256) sV[i] = 0.0;
+  __syncthreads();
+  double hold[3][4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T c = cnext;
+    if (k < 2) cnext = coef[eg[k + 1]];
+    const T *r = sR + (ea[k] + F::SX * (eb[k] + F::SY * ec[k]));
+    T X[3][8], u[1][8], v[1][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int o = (a & 1) + F::SX * ((a >> 1) & 1) + F::SX * F::SY * (a >> 2);
+      if (a == 0 || a == 1 || a == 2 || a == 4) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) X[d][a] = r[d * F::NS + o];
+      }
+      u[0][a] = r[3 * F::NS + o];
+    }
+    laplace_element_parallelepiped_n<T, 1>(X, u, c, v);
+    // accumulator entry of the element's corner 0 (may lie outside the box; only
+    // owned corners are addressed)
+    double *acc = sV + ((ea[k] - 1) + F::AX * ((eb[k] - 1) + F::AY * (ec[k] - 1)));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (msk[k] & (1u << a)) lds_add_own(acc + (a & 1) + F::AX * ((a >> 1) & 1), double(v[0][a]));
+#pragma unroll
+    for (int a = 0; a < 4; ++a) hold[k][a] = double(v[0][4 + a]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double *acc = sV + ((ea[k] - 1) + F::AX * ((eb[k] - 1) + F::AY * ec[k]));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (msk[k] & (16u << a)) lds_add_own(acc + (a & 1) + F::AX * ((a >> 1) & 1), hold[k][a]);
+  }
+  __syncthreads();
+  if (w & 1) {  // layer-0 lanes are in the last step only
+    double *acc = sV + ((ea[2] - 1) + F::AX * ((eb[2] - 1) + F::AY * ec[2]));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (msk[2] & (256u << a)) lds_add_own(acc + (a & 1) + F::AX * ((a >> 1) & 1), hold[2][a]);
+  }
+  __syncthreads();
+  // write-back of the owned box; dot_part: this tile's share of x.y
+  double dsum = 0.0;
+  auto put = [&](int a, int b, int c) {
+    const int64_t g = node_id(gx0 + 1 + a, gy0 + 1 + b, gz0 + 1 + c);
+    const double v = sV[a + F::AX * (b + F::AY * c)];
+    const T xs = sR[3 * F::NS + (a + 1) + F::SX * ((b + 1) + F::SY * (c + 1))];
+    if (MASK && mask[g]) {
+      const T xv = x[g];
+      y[g] = xv;
+      if (dot_part) dsum += double(xv) * double(xv);
+    } else {
+      const T yv = T(v);
+      y[g] = yv;
+      if (dot_part) dsum += double(xs) * double(yv);
+    }
+  };
+  for (int i = tid; i < F::OX * F::OY * F::OZ; i += 256) put(i & 15, (i >> 4) & 7, i >> 7);
+  if (hx + hy + hz > F::OX + F::OY + F::OZ) {  // the mesh's last node planes
+    for (int i = tid; i < F::NA; i += 256) {
+      const int c = i / (F::AX * F::AY), r = i - c * (F::AX * F::AY), b = r / F::AX,
+                a = r - b * F::AX;
+      if ((a == F::OX || b == F::OY || c == F::OZ) && a < hx && b < hy && c < hz) put(a, b, c);
+    }
+  }
+  if (dot_part) {
+    const double t = block_sum_256(dsum);
+    if (tid == 0) dot_part[tile] = t;
+  }
+}
+
 // Byte offset of the tetrahedron kernel's FP64 accumulator after the node
 // records (rec_bytes per node), rounded up to 8 bytes.
 __host__ __device__ inline size_t tet_acc_offset(int max_nodes, size_t rec_bytes) {
@@ -1266,6 +1466,38 @@ void plan_addressing(HostTiles &H) {
   }
 }
 
+// The mesh of an owner-computes operator: a box lattice in the generator's
+// numbering (element e = ex + nx (ey + ny ez) with corner a at node
+// (ex + a_x) + (nx+1)((ey + a_y) + (ny+1)(ez + a_z))), checked entry by entry,
+// with nx, ny, nz multiples of the owned box.
+bool owner_box(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx, int &ny,
+               int &nz) {
+  if (ne <= 0 || conn.size() != size_t(8) * ne || conn[0] != 0 || conn[ne] != 1) return false;
+  const int64_t bx = int64_t(conn[2 * ne]) - 1;
+  if (bx < 1 || int64_t(conn[4 * ne]) % (bx + 1)) return false;
+  const int64_t by = int64_t(conn[4 * ne]) / (bx + 1) - 1;
+  if (by < 1 || ne % (bx * by)) return false;
+  const int64_t bz = ne / (bx * by);
+  if ((bx + 1) * (by + 1) * (bz + 1) != nn) return false;
+  if (bx % OwnTile::OX || by % OwnTile::OY || bz % OwnTile::OZ) return false;
+  const int64_t sy = bx + 1, sz = (bx + 1) * (by + 1);
+  for (int64_t e = 0; e < ne; ++e) {
+    const int64_t ex = e % bx, ey = (e / bx) % by, ez = e / (bx * by);
+    const int64_t b = ex + sy * ey + sz * ez;
+    for (int a = 0; a < 8; ++a)
+      if (conn[size_t(a) * ne + e] != b + (a & 1) + sy * ((a >> 1) & 1) + sz * (a >> 2))
+        return false;
+  }
+  nx = int(bx);
+  ny = int(by);
+  nz = int(bz);
+  return true;
+}
+
+int64_t own_tiles(const TileMap &tm) {
+  return int64_t(tm.own_nx / OwnTile::OX) * (tm.own_ny / OwnTile::OY) * (tm.own_nz / OwnTile::OZ);
+}
+
 template <typename T>
 int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   const int64_t ne = op.n_elems, nn = op.n_nodes;
@@ -1322,6 +1554,13 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   tm.fixed = tm.fixed && tm.split && op.variant == Q1_V_BLOCK && op.elem == Q1_HEX8;
   if (const char *e = std::getenv("Q1_FIXED_TILE"))  // "0": the general-shape instances
     if (e[0] == '0') tm.fixed = false;
+  // owner-computes tiles for the scalar kind on a box lattice of parallelepipeds
+  // ("Q1_OWNER_TILE=0": the halo-slot tiles); the diagonal keeps the split tiles
+  tm.own_nx = tm.own_ny = tm.own_nz = 0;
+  const char *own_env = std::getenv("Q1_OWNER_TILE");
+  if (op.variant == Q1_V_BLOCK && hex && op.physics == Q1_LAPLACE && tm.all_affine && tm.split &&
+      !(own_env && own_env[0] == '0'))
+    owner_box(conn, ne, nn, tm.own_nx, tm.own_ny, tm.own_nz);
   auto up = [&](auto **dst, const auto &v) -> int {
     using E = typename std::remove_reference<decltype(v)>::type::value_type;
     const size_t b = std::max<size_t>(1, v.size()) * sizeof(E);
@@ -1391,9 +1630,10 @@ int64_t halo_blocks(const TileMap &tm) {
   return (tm.n_reset + 256 * kHaloNpt - 1) / (256 * kHaloNpt);
 }
 
-// dot: optional partials of x.y (block variants of hexahedra): with shared or
-// Dirichlet nodes, halo_blocks(tm) partials at dot[0..) that include the tile
-// partials at dot[halo_blocks(tm)..); without them, the tile partials at dot[0..).
+// dot: optional partials of x.y (block variants of hexahedra): on owner-computes
+// tiles, one per tile at dot[0..); else with shared or Dirichlet nodes,
+// halo_blocks(tm) partials at dot[0..) that include the tile partials at
+// dot[halo_blocks(tm)..); without them, the tile partials at dot[0..).
 template <typename T, int PH>
 int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *stop,
                  double *dot = nullptr) {
@@ -1425,6 +1665,16 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
       return Q1_OK;
     }
     return fail(Q1_EUNSUPPORTED, "tetrahedra: scalar Laplace and elasticity");
+  }
+  if (block && tm.own_nx > 0) {
+    if constexpr (PH == 1) {
+      auto kern = op.mask ? k_apply_owner<T, true> : k_apply_owner<T, false>;
+      hipLaunchKernelGGL(kern, dim3(unsigned(own_tiles(tm))), dim3(256), 0, s, tm.own_nx,
+                         tm.own_ny, tm.own_nz, static_cast<const T *>(op.xyz),
+                         static_cast<const T *>(op.coef), op.mask, x, y, stop, dot);
+      Q1_HIP(hipGetLastError());
+      return Q1_OK;
+    }
   }
   if (block) {
     // fallback accumulation when some tile does not admit the split one
@@ -1554,6 +1804,10 @@ int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *
 int64_t apply_dot_parts(const Op &op, int64_t *n_final) {
   const bool block = (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) && op.elem == Q1_HEX8;
   if (!block || op.tiles.n_tiles == 0) return 0;
+  if (op.tiles.own_nx > 0) {  // one partial per owner tile
+    if (n_final) *n_final = own_tiles(op.tiles);
+    return own_tiles(op.tiles);
+  }
   const int64_t h = op.tiles.n_reset > 0 ? halo_blocks(op.tiles) : 0;
   if (n_final) *n_final = h > 0 ? h : op.tiles.n_tiles;
   return h + op.tiles.n_tiles;

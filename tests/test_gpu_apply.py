@@ -95,6 +95,49 @@ def test_apply_parity_whole_tiles(q1, orc, physics, n, jitter, mask, dtype):
     assert rel_err(ds[0], A.diag()) <= TOL[dtype]
 
 
+# Owner-computes tiles (the default for the scalar kind on box lattices of
+# parallelepipeds whose element counts are multiples of 16, 8, 4): each tile owns
+# a 16 x 8 x 4 node box, the last tile in a direction also the mesh's last node
+# plane.  Dirichlet nodes are drawn at random so that they fall on tile borders,
+# box corners and the last planes.
+OWNER_CASES = [(16, 8, 4), (32, 8, 4), (16, 16, 8), (32, 16, 12), (48, 24, 8)]
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("mask", ["none", "random", "all_faces"])
+@pytest.mark.parametrize("n", OWNER_CASES)
+def test_owner_tiles_parity(q1, orc, monkeypatch, n, mask, dtype):
+    print(f"\n[owner tiles] n={n} mask={mask} dtype={dtype}", flush=True)
+    pr = problem(1, n, 0.0, 2317, False)
+    nn = pr["xyz"].shape[1]
+    if mask == "random":
+        pr["mask"] = (np.random.default_rng(2317).random(nn) < 0.15).astype(np.uint8)
+    elif mask == "all_faces":
+        m = np.zeros(nn, np.uint8)
+        for f in ("x0", "x1", "y0", "y1", "z0", "z1"):
+            m |= si.face_mask(*n, f).astype(np.uint8)
+        pr["mask"] = m
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    x = si.vec_uniform(A.n, 2317, si.STREAM_X)
+    ref = A.matvec(x)
+    op = make_op(pr, dtype, 0)
+    assert op.reproducible()
+    ys = [gpu_apply(op, x, dtype) for _ in range(3)]
+    assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    assert rel_err(ys[0], ref) <= TOL[dtype]
+    assert np.max(np.abs(ys[0] - ref)) <= 10 * TOL[dtype] * np.max(np.abs(ref))
+    if pr["mask"] is not None:
+        fixed = pr["mask"] == 1
+        assert np.array_equal(ys[0][fixed], x[fixed].astype(ys[0].dtype)) or dtype == 1
+    # the halo-slot tiles of the same operator agree to the same bar (they add in
+    # another order, so the two results are not bitwise equal: the owner path ran)
+    monkeypatch.setenv("Q1_OWNER_TILE", "0")
+    y_halo = gpu_apply(make_op(pr, dtype, 0), x, dtype)
+    monkeypatch.delenv("Q1_OWNER_TILE")
+    assert rel_err(y_halo, ref) <= TOL[dtype]
+    assert not np.array_equal(y_halo, ys[0])
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("physics,n", [(1, (1, 1, 1)), (1, (2, 2, 2)), (1, (3, 2, 2)),
                                        (3, (1, 1, 1)), (3, (2, 2, 1)), (2, (2, 1, 1))])

@@ -69,10 +69,13 @@ def solve_gpu(q1, op, b, dtype, pc=1, rtol=1e-8, maxit=20000):
     return xd.double().cpu().numpy(), st
 
 
-@pytest.mark.parametrize("csr", [False, True])
-def test_pcg_first_iterates(q1, orc, csr):
-    print(f"\n[pcg iterates] csr={csr}", flush=True)
-    pr = problem(1, (16, 16, 16), 0.1, 2308, True)
+@pytest.mark.parametrize("csr,jitter", [(False, 0.1), (True, 0.1), (False, 0.0)])
+def test_pcg_first_iterates(q1, orc, csr, jitter):
+    """The first ten iterates against the oracle's; undistorted, the default
+    operator takes the owner-computes tiles, whose apply also forms the p.q
+    partials the iteration reduces."""
+    print(f"\n[pcg iterates] csr={csr} jitter={jitter}", flush=True)
+    pr = problem(1, (16, 16, 16), jitter, 2308, True)
     A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
     b = rhs(A, pr, 2308)
     op = make_op(pr, 0, 0)
@@ -443,9 +446,10 @@ def test_solves_bitwise_reproducible(q1, orc):
     iterations and return bitwise-identical iterates: the apply, the diagonal and
     every reduction add in a fixed order."""
     import torch
-    for physics, n in ((1, (16, 16, 16)), (3, (10, 10, 10))):
-        print(f"\n[reproducible solve] physics={physics} n={n}", flush=True)
-        pr = problem(physics, n, 0.1, 83, True)
+    for physics, n, jitter in ((1, (16, 16, 16), 0.1), (3, (10, 10, 10), 0.1),
+                               (1, (32, 16, 8), 0.0)):
+        print(f"\n[reproducible solve] physics={physics} n={n} jitter={jitter}", flush=True)
+        pr = problem(physics, n, jitter, 83, True)
         A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
         b = rhs(A, pr, 83)
         op64, op32 = make_op(pr, 0, 0), make_op(pr, 1, 0)
