@@ -648,7 +648,6 @@ struct OwnTile {
   static constexpr int NQ = NL / 4;  // elements of a layer-0 quarter (the last one: the rest)
   static_assert(NL <= 192 && NL + (NL - 3 * NQ) <= 192, "three steps per wave");
   static_assert(NQ > 2 * EX, "quarters 0 and 2 (1 and 3) share no node");
-  static_assert(OX == 16 && OY == 8, "write-back indexing");
 };
 
 __device__ __forceinline__ void lds_add_own(double *p, double v) {
@@ -781,28 +780,19 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
       if (msk[2] & (256u << a)) lds_add_own(acc + (a & 1) + F::AX * ((a >> 1) & 1), hold[2][a]);
   }
   __syncthreads();
-  // write-back of the owned box; dot_part: this tile's share of x.y
+  // write-back: each thread stores the owned nodes among the records it staged
+  // (their ids, Dirichlet flags and input values are still in registers), so no
+  // global load waits at the end; dot_part: this tile's share of x.y
   double dsum = 0.0;
-  auto put = [&](int a, int b, int c) {
-    const int64_t g = node_id(gx0 + 1 + a, gy0 + 1 + b, gz0 + 1 + c);
-    const double v = sV[a + F::AX * (b + F::AY * c)];
-    const T xs = sR[3 * F::NS + (a + 1) + F::SX * ((b + 1) + F::SY * (c + 1))];
-    if (MASK && mask[g]) {
-      const T xv = x[g];
-      y[g] = xv;
-      if (dot_part) dsum += double(xv) * double(xv);
-    } else {
-      const T yv = T(v);
-      y[g] = yv;
-      if (dot_part) dsum += double(xs) * double(yv);
-    }
-  };
-  for (int i = tid; i < F::OX * F::OY * F::OZ; i += 256) put(i & 15, (i >> 4) & 7, i >> 7);
-  if (hx + hy + hz > F::OX + F::OY + F::OZ) {  // the mesh's last node planes
-    for (int i = tid; i < F::NA; i += 256) {
-      const int c = i / (F::AX * F::AY), r = i - c * (F::AX * F::AY), b = r / F::AX,
-                a = r - b * F::AX;
-      if ((a == F::OX || b == F::OY || c == F::OZ) && a < hx && b < hy && c < hz) put(a, b, c);
+#pragma unroll
+  for (int k = 0; k < F::KN; ++k) {
+    const int i = k * 256 + tid;
+    const int c = i / (F::SX * F::SY), r = i - c * (F::SX * F::SY), b = r / F::SX,
+              a = r - b * F::SX;
+    if (i < F::NS && a >= 1 && a <= hx && b >= 1 && b <= hy && c >= 1 && c <= hz) {
+      const T yv = fx[k] ? rec[k][3] : T(sV[(a - 1) + F::AX * ((b - 1) + F::AY * (c - 1))]);
+      y[node_id(gx0 + a, gy0 + b, gz0 + c)] = yv;
+      if (dot_part) dsum += double(rec[k][3]) * double(yv);
     }
   }
   if (dot_part) {
