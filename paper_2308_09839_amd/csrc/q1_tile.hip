@@ -636,6 +636,17 @@ __global__ __launch_bounds__(256) void k_apply_block(
 // program order, and within one instruction the lanes' nodes are distinct.
 // The accumulator is FP64 in both precisions (FP32 LDS atomic adds measured
 // slow here).
+// Loads and stores at a 32-bit byte offset from a base pointer held in scalar
+// registers (one address operand per access instead of a 64-bit vector address).
+template <typename E>
+__device__ __forceinline__ E ld_off(const E *base, uint32_t byte_off) {
+  return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename E>
+__device__ __forceinline__ void st_off(E *base, uint32_t byte_off, E v) {
+  *reinterpret_cast<E *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
 struct OwnTile {
   static constexpr int OX = 16, OY = 8, OZ = 4;              // owned nodes
   static constexpr int AX = OX + 1, AY = OY + 1, AZ = OZ + 1;  // accumulator box
@@ -676,32 +687,42 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
   const int64_t nn = int64_t(n1x) * n1y * (nz + 1);
   // global lattice position of local node / element (0, 0, 0)
   const int gx0 = tx * F::OX - 1, gy0 = ty * F::OY - 1, gz0 = tz * F::OZ - 1;
-  auto node_id = [&](int gx, int gy, int gz) -> int64_t {
-    return gx + int64_t(n1x) * (gy + int64_t(n1y) * gz);
-  };
-  // stage the node records: every load issued (at clamped positions) before any LDS write
+  // ids and byte offsets in 32 bits (the host takes this kernel for fewer than
+  // 2^32 bytes per field), each field's base in scalar registers
+  const T *X0 = xyz, *X1 = xyz + nn, *X2 = xyz + 2 * nn;
+  // stage the node records: every load issued (at clamped positions) before any
+  // LDS write.  gk, ak: the record's node id, and its accumulator entry when this
+  // tile owns the node (else -1); kept with the record for the write-back.
   T rec[F::KN][4];
   bool fx[F::KN];
+  uint32_t gk[F::KN];
+  int ak[F::KN];
 #pragma unroll
   for (int k = 0; k < F::KN; ++k) {
-    const int i = min(k * 256 + tid, F::NS - 1);
+    const int ii = k * 256 + tid, i = min(ii, F::NS - 1);
     const int c = i / (F::SX * F::SY), r = i - c * (F::SX * F::SY), b = r / F::SX,
               a = r - b * F::SX;
-    const int64_t g = node_id(min(max(gx0 + a, 0), nx), min(max(gy0 + b, 0), ny),
-                              min(max(gz0 + c, 0), nz));
-    rec[k][0] = xyz[g];
-    rec[k][1] = xyz[nn + g];
-    rec[k][2] = xyz[2 * nn + g];
-    rec[k][3] = x[g];
-    fx[k] = MASK && mask[g] != 0;
+    const uint32_t g = uint32_t(min(max(gx0 + a, 0), nx)) +
+                       uint32_t(n1x) * (uint32_t(min(max(gy0 + b, 0), ny)) +
+                                        uint32_t(n1y) * uint32_t(min(max(gz0 + c, 0), nz)));
+    const uint32_t o = g * uint32_t(sizeof(T));
+    rec[k][0] = ld_off(X0, o);
+    rec[k][1] = ld_off(X1, o);
+    rec[k][2] = ld_off(X2, o);
+    rec[k][3] = ld_off(x, o);
+    fx[k] = MASK && ld_off(mask, g) != 0;
+    gk[k] = g;
+    ak[k] = ii < F::NS && a >= 1 && a <= hx && b >= 1 && b <= hy && c >= 1 && c <= hz
+                ? (a - 1) + F::AX * ((b - 1) + F::AY * (c - 1))
+                : -1;
   }
   // the wave's three steps: element (ea, eb, ec) of the box, its mask of owned
   // corners (bits 0-3 lower, 4-7 upper; the layer-0 quarters of odd waves
-  // carry their upper corners in bits 8-11, for pass U2) and its cell id
+  // carry their upper corners in bits 8-11, for pass U2) and its cell's byte offset
   const int q0 = F::NQ * w, q1 = w == 3 ? F::NL : F::NQ * (w + 1);
   int ea[3], eb[3], ec[3];
   unsigned msk[3];
-  int64_t eg[3];
+  uint32_t eo[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int j = k * 64 + lane;
@@ -714,19 +735,21 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
     const int gx = gx0 + ea[k], gy = gy0 + eb[k], gz = gz0 + ec[k];
     const bool live = (own_layer || qj < q1) && gx >= 0 && gy >= 0 && gz >= 0 && gx < nx &&
                       gy < ny && gz < nz;
-    const unsigned mx = (ea[k] >= 1 ? 1u : 0u) | (ea[k] + 1 <= hx ? 2u : 0u);
-    const unsigned my = (eb[k] >= 1 ? 1u : 0u) | (eb[k] + 1 <= hy ? 2u : 0u);
-    const unsigned mz = (ec[k] >= 1 ? 1u : 0u) | (ec[k] + 1 <= hz ? 2u : 0u);
-    unsigned m = 0;
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-      m |= ((mx >> (a & 1)) & (my >> ((a >> 1) & 1)) & (mz >> (a >> 2)) & 1u) << a;
+    // corner a = i + 2j + 4k is owned when its x, y and z positions are: the
+    // corners with i = 0 are bits 0x55, i = 1 0xaa; j = 0 0x33, j = 1 0xcc; k = 0
+    // 0x0f, k = 1 0xf0
+    const unsigned bx = (ea[k] >= 1 ? 0x55u : 0u) | (ea[k] + 1 <= hx ? 0xaau : 0u);
+    const unsigned by = (eb[k] >= 1 ? 0x33u : 0u) | (eb[k] + 1 <= hy ? 0xccu : 0u);
+    const unsigned bz = (ec[k] >= 1 ? 0x0fu : 0u) | (ec[k] + 1 <= hz ? 0xf0u : 0u);
+    unsigned m = bx & by & bz;
     if (!own_layer && (w & 1)) m = (m & 0x0fu) | ((m & 0xf0u) << 4);
     msk[k] = live ? m : 0u;
-    eg[k] = min(max(gx, 0), nx - 1) + int64_t(nx) * (min(max(gy, 0), ny - 1) +
-                                                     int64_t(ny) * min(max(gz, 0), nz - 1));
+    eo[k] = (uint32_t(min(max(gx, 0), nx - 1)) +
+             uint32_t(nx) * (uint32_t(min(max(gy, 0), ny - 1)) +
+                             uint32_t(ny) * uint32_t(min(max(gz, 0), nz - 1)))) *
+            uint32_t(sizeof(T));
   }
-  T cnext = coef[eg[0]];
+  T cnext = ld_off(coef, eo[0]);
 #pragma unroll
   for (int k = 0; k < F::KN; ++k) {
     const int i = k * 256 + tid;
@@ -742,7 +765,7 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const T c = cnext;
-    if (k < 2) cnext = coef[eg[k + 1]];
+    if (k < 2) cnext = ld_off(coef, eo[k + 1]);
     const T *r = sR + (ea[k] + F::SX * (eb[k] + F::SY * ec[k]));
     T X[3][8], u[1][8], v[1][8];
 #pragma unroll
@@ -786,12 +809,9 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
   double dsum = 0.0;
 #pragma unroll
   for (int k = 0; k < F::KN; ++k) {
-    const int i = k * 256 + tid;
-    const int c = i / (F::SX * F::SY), r = i - c * (F::SX * F::SY), b = r / F::SX,
-              a = r - b * F::SX;
-    if (i < F::NS && a >= 1 && a <= hx && b >= 1 && b <= hy && c >= 1 && c <= hz) {
-      const T yv = fx[k] ? rec[k][3] : T(sV[(a - 1) + F::AX * ((b - 1) + F::AY * (c - 1))]);
-      y[node_id(gx0 + a, gy0 + b, gz0 + c)] = yv;
+    if (ak[k] >= 0) {
+      const T yv = fx[k] ? rec[k][3] : T(sV[ak[k]]);
+      st_off(y, gk[k] * uint32_t(sizeof(T)), yv);
       if (dot_part) dsum += double(rec[k][3]) * double(yv);
     }
   }
@@ -1459,7 +1479,7 @@ void plan_addressing(HostTiles &H) {
 // The mesh of an owner-computes operator: a box lattice in the generator's
 // numbering (element e = ex + nx (ey + ny ez) with corner a at node
 // (ex + a_x) + (nx+1)((ey + a_y) + (ny+1)(ez + a_z))), checked entry by entry,
-// with nx, ny, nz multiples of the owned box.
+// with nx, ny, nz multiples of the owned box and fewer than 2^29 nodes.
 bool owner_box(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx, int &ny,
                int &nz) {
   if (ne <= 0 || conn.size() != size_t(8) * ne || conn[0] != 0 || conn[ne] != 1) return false;
@@ -1469,6 +1489,7 @@ bool owner_box(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx
   if (by < 1 || ne % (bx * by)) return false;
   const int64_t bz = ne / (bx * by);
   if ((bx + 1) * (by + 1) * (bz + 1) != nn) return false;
+  if (nn * 8 >= (int64_t(1) << 32)) return false;  // the kernel's 32-bit byte offsets
   if (bx % OwnTile::OX || by % OwnTile::OY || bz % OwnTile::OZ) return false;
   const int64_t sy = bx + 1, sz = (bx + 1) * (by + 1);
   for (int64_t e = 0; e < ne; ++e) {
