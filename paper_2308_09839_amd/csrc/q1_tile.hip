@@ -656,6 +656,7 @@ struct OwnTile {
   static constexpr int NL = EX * EY;                          // 153
   static constexpr int NA = AX * AY * AZ;
   static constexpr int KN = (NS + 255) / 256;
+  static_assert((KN - 1) * 256 <= NS, "staging rounds before the last are full");
   static constexpr int NQ = NL / 4;  // elements of a layer-0 quarter (the last one: the rest)
   static_assert(NL <= 192 && NL + (NL - 3 * NQ) <= 192, "three steps per wave");
   static_assert(NQ > 2 * EX, "quarters 0 and 2 (1 and 3) share no node");
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
   // LDS write.  gk, ak: the record's node id, and its accumulator entry when this
   // tile owns the node (else -1); kept with the record for the write-back.
   T rec[F::KN][4];
-  bool fx[F::KN];
+  uint32_t fx[F::KN];  // the Dirichlet byte, kept raw: a compare at the load would wait for it
   uint32_t gk[F::KN];
   int ak[F::KN];
 #pragma unroll
@@ -702,19 +703,23 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
     const int ii = k * 256 + tid, i = min(ii, F::NS - 1);
     const int c = i / (F::SX * F::SY), r = i - c * (F::SX * F::SY), b = r / F::SX,
               a = r - b * F::SX;
-    const uint32_t g = uint32_t(min(max(gx0 + a, 0), nx)) +
-                       uint32_t(n1x) * (uint32_t(min(max(gy0 + b, 0), ny)) +
-                                        uint32_t(n1y) * uint32_t(min(max(gz0 + c, 0), nz)));
+    // 24-bit products (the host checks the factors' range): a 32-bit multiply-add
+    // in the wider form reads a neighbouring register, which then waits for a load
+    const uint32_t g = __umul24(uint32_t(n1x), __umul24(uint32_t(n1y),
+                                                        uint32_t(min(max(gz0 + c, 0), nz))) +
+                                                   uint32_t(min(max(gy0 + b, 0), ny))) +
+                       uint32_t(min(max(gx0 + a, 0), nx));
     const uint32_t o = g * uint32_t(sizeof(T));
     rec[k][0] = ld_off(X0, o);
     rec[k][1] = ld_off(X1, o);
     rec[k][2] = ld_off(X2, o);
     rec[k][3] = ld_off(x, o);
-    fx[k] = MASK && ld_off(mask, g) != 0;
+    fx[k] = MASK ? uint32_t(ld_off(mask, g)) : 0u;
     gk[k] = g;
-    ak[k] = ii < F::NS && a >= 1 && a <= hx && b >= 1 && b <= hy && c >= 1 && c <= hz
-                ? (a - 1) + F::AX * ((b - 1) + F::AY * (c - 1))
-                : -1;
+    // (range tests as unsigned compares joined without short-circuit: no branches)
+    const bool own = (ii < F::NS) & (unsigned(a - 1) < unsigned(hx)) &
+                     (unsigned(b - 1) < unsigned(hy)) & (unsigned(c - 1) < unsigned(hz));
+    ak[k] = own ? (a - 1) + F::AX * ((b - 1) + F::AY * (c - 1)) : -1;
   }
   // the wave's three steps: element (ea, eb, ec) of the box, its mask of owned
   // corners (bits 0-3 lower, 4-7 upper; the layer-0 quarters of odd waves
@@ -733,8 +738,8 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
     eb[k] = lin / F::EX;
     ea[k] = lin - eb[k] * F::EX;
     const int gx = gx0 + ea[k], gy = gy0 + eb[k], gz = gz0 + ec[k];
-    const bool live = (own_layer || qj < q1) && gx >= 0 && gy >= 0 && gz >= 0 && gx < nx &&
-                      gy < ny && gz < nz;
+    const bool live = (own_layer | (qj < q1)) & (unsigned(gx) < unsigned(nx)) &
+                      (unsigned(gy) < unsigned(ny)) & (unsigned(gz) < unsigned(nz));
     // corner a = i + 2j + 4k is owned when its x, y and z positions are: the
     // corners with i = 0 are bits 0x55, i = 1 0xaa; j = 0 0x33, j = 1 0xcc; k = 0
     // 0x0f, k = 1 0xf0
@@ -744,19 +749,19 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
     unsigned m = bx & by & bz;
     if (!own_layer && (w & 1)) m = (m & 0x0fu) | ((m & 0xf0u) << 4);
     msk[k] = live ? m : 0u;
-    eo[k] = (uint32_t(min(max(gx, 0), nx - 1)) +
-             uint32_t(nx) * (uint32_t(min(max(gy, 0), ny - 1)) +
-                             uint32_t(ny) * uint32_t(min(max(gz, 0), nz - 1)))) *
+    eo[k] = (__umul24(uint32_t(nx), __umul24(uint32_t(ny), uint32_t(min(max(gz, 0), nz - 1))) +
+                                        uint32_t(min(max(gy, 0), ny - 1))) +
+             uint32_t(min(max(gx, 0), nx - 1))) *
             uint32_t(sizeof(T));
   }
   T cnext = ld_off(coef, eo[0]);
 #pragma unroll
   for (int k = 0; k < F::KN; ++k) {
     const int i = k * 256 + tid;
-    if (i < F::NS) {
+    if (k < F::KN - 1 || i < F::NS) {  // only the last round is partial
 #pragma unroll
       for (int f = 0; f < 3; ++f) sR[f * F::NS + i] = rec[k][f];
-      sR[3 * F::NS + i] = fx[k] ? T(0) : rec[k][3];
+      sR[3 * F::NS + i] = fx[k] != 0 ? T(0) : rec[k][3];
     }
   }
   for (int i = tid; i < F::NA; i += 256) sV[i] = 0.0;
@@ -810,7 +815,7 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
 #pragma unroll
   for (int k = 0; k < F::KN; ++k) {
     if (ak[k] >= 0) {
-      const T yv = fx[k] ? rec[k][3] : T(sV[ak[k]]);
+      const T yv = fx[k] != 0 ? rec[k][3] : T(sV[ak[k]]);
       st_off(y, gk[k] * uint32_t(sizeof(T)), yv);
       if (dot_part) dsum += double(rec[k][3]) * double(yv);
     }
@@ -1479,7 +1484,8 @@ void plan_addressing(HostTiles &H) {
 // The mesh of an owner-computes operator: a box lattice in the generator's
 // numbering (element e = ex + nx (ey + ny ez) with corner a at node
 // (ex + a_x) + (nx+1)((ey + a_y) + (ny+1)(ez + a_z))), checked entry by entry,
-// with nx, ny, nz multiples of the owned box and fewer than 2^29 nodes.
+// with nx, ny, nz multiples of the owned box, fewer than 2^29 nodes and
+// (ny+1)(nz+1) below 2^24.
 bool owner_box(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx, int &ny,
                int &nz) {
   if (ne <= 0 || conn.size() != size_t(8) * ne || conn[0] != 0 || conn[ne] != 1) return false;
@@ -1490,6 +1496,8 @@ bool owner_box(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx
   const int64_t bz = ne / (bx * by);
   if ((bx + 1) * (by + 1) * (bz + 1) != nn) return false;
   if (nn * 8 >= (int64_t(1) << 32)) return false;  // the kernel's 32-bit byte offsets
+  if ((by + 1) * (bz + 1) >= (int64_t(1) << 24) || bx + 1 >= (int64_t(1) << 24))
+    return false;  // and its 24-bit products
   if (bx % OwnTile::OX || by % OwnTile::OY || bz % OwnTile::OZ) return false;
   const int64_t sy = bx + 1, sz = (bx + 1) * (by + 1);
   for (int64_t e = 0; e < ne; ++e) {
