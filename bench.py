@@ -134,7 +134,9 @@ def time_cold(op, x, y, reps, mode="write"):
     """Median of `reps` applies, each timed alone after touching a 1 GiB buffer, which evicts
     the operator's data from L2 and the MALL (256 MB): mode "write" fills it (the apply then
     also competes with the write-back of the dirty lines), mode "read" sums it (clean lines;
-    the apply reads from HBM)."""
+    the apply reads from HBM).  The events and the apply are queued behind the flush, not
+    after a synchronisation: on an idle GPU the first event would also time the host's
+    launch latency (Python, the binding and the runtime), which is no part of the apply."""
     import torch
     flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
@@ -144,7 +146,6 @@ def time_cold(op, x, y, reps, mode="write"):
             flush.fill_(float(i))
         else:
             flush.sum()
-        torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()

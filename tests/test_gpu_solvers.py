@@ -272,13 +272,15 @@ def test_ir_reaches_fp64_tolerance(q1, orc, physics, n):
 
 # -- mixed-precision PCG with reliable updates ---------------------------------------
 
-@pytest.mark.parametrize("physics,n", [(1, (16, 16, 16)), (3, (10, 10, 10))])
-def test_mpcg_reaches_fp64_tolerance(q1, orc, physics, n):
+@pytest.mark.parametrize("physics,n,jitter", [(1, (16, 16, 16), 0.1), (3, (10, 10, 10), 0.0),
+                                              (1, (32, 16, 8), 0.0)])
+def test_mpcg_reaches_fp64_tolerance(q1, orc, physics, n, jitter):
     """FP32 recurrences with FP64 refreshes reach an FP64 tolerance that FP32
-    PCG alone cannot, in about the iterations of FP64 PCG."""
+    PCG alone cannot, in about the iterations of FP64 PCG (undistorted 32 x 16 x 8:
+    both operators on owner-computes tiles)."""
     import torch
-    print(f"\n[mpcg] physics={physics} n={n}", flush=True)
-    pr = problem(physics, n, 0.1 if physics == 1 else 0.0, 82, True)
+    print(f"\n[mpcg] physics={physics} n={n} jitter={jitter}", flush=True)
+    pr = problem(physics, n, jitter, 82, True)
     A = orc.assemble(physics, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
     b = rhs(A, pr, 82)
     op64, op32 = make_op(pr, 0, 0), make_op(pr, 1, 0)

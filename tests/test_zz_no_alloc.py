@@ -29,8 +29,10 @@ def _rhs(n, mask, dpn, seed):
 def test_pcg_noalloc_matches_pcg(q1, orc):
     import torch
     cases = [(1, (24, 20, 18), 0.1, 0, 1e-10),   # larger first
+             (1, (32, 16, 8), 0.0, 0, 1e-10),    # owner-computes tiles (one partial per tile)
              (3, (8, 7, 6), 0.1, 0, 1e-10),      # then a smaller one (elasticity)
-             (1, (9, 8, 7), 0.0, 1, 1e-5)]       # and an FP32 operator
+             (1, (9, 8, 7), 0.0, 1, 1e-5),       # an FP32 operator
+             (1, (16, 8, 4), 0.0, 1, 1e-5)]      # and an FP32 owner-computes one
     for physics, n, jitter, dtype, rtol in cases:
         print(f"\n[noalloc] physics={physics} n={n} dtype={dtype}", flush=True)
         pr = problem(physics, n, jitter, 91, True)
