@@ -236,7 +236,8 @@ def cg16_problem(si):
 
 def bench_cg16(q1, si, n, seed, args):
     """16^3 jittered Laplace (launch-latency bound): microseconds per apply (median of
-    100 individually timed applies after 10 warm-up ones) and FP64 Jacobi-PCG to a 1e-8
+    100 individually timed applies after 10 warm-up ones, and 100 applies back to back)
+    and FP64 Jacobi-PCG to a 1e-8
     relative residual (wall time of the whole solve and per iteration) through the
     launch-per-kernel driver, the persistent batched kernel (one cooperative launch),
     and the fused single-workgroup kernel."""
@@ -248,6 +249,10 @@ def bench_cg16(q1, si, n, seed, args):
     op = q1.q1_op_create(1, 0, 0, *upload(pr, 0))
     yd = torch.empty_like(bd)
     res["cg16_apply_us"] = round(1e3 * time_each(lambda: op.apply(bd, yd), 100, 10), 2)
+    # the same 100 applies queued back to back (one event pair): the device time per apply,
+    # without the host's launch latency that each individually timed apply waits for
+    ms_b2b, _ = time_applies(op, bd, yd, 100, 10)
+    res["cg16_apply_us_back_to_back"] = round(1e3 * ms_b2b, 2)
     op.destroy()
     for tag, variant in (("", 0), ("_persistent", 3), ("_fused", 0)):
         op = q1.q1_op_create(1, 0, variant, *upload(pr, 0))
