@@ -50,6 +50,7 @@ struct TileMap {
   // owner-computes tiles (scalar Laplace on a box lattice of parallelepipeds whose
   // element counts per direction are multiples of 16, 8, 4): the box size, or 0
   int own_nx = 0, own_ny = 0, own_nz = 0;
+  bool own_general = false;       // owner tiles with the general-hexahedron element
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
   uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16 | C << 24, or 0
   uint32_t *tile_addr = nullptr;  // [n_tiles] lattice addressing: valid bit | shared-face bits, or 0

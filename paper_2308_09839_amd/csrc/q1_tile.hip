@@ -666,7 +666,10 @@ __device__ __forceinline__ void lds_add_own(double *p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <typename T, bool MASK>
+// GEN: the general hexahedron (isoparametric geometry at each Gauss point, the
+// whole 8 corners' coordinates), taken on small meshes whose elements are not all
+// parallelepipeds, where one kernel per apply matters more than the element work.
+template <typename T, bool MASK, bool GEN>
 __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
                                                      const T *__restrict__ xyz,
                                                      const T *__restrict__ coef,
@@ -776,13 +779,16 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int o = (a & 1) + F::SX * ((a >> 1) & 1) + F::SX * F::SY * (a >> 2);
-      if (a == 0 || a == 1 || a == 2 || a == 4) {
+      if (GEN || a == 0 || a == 1 || a == 2 || a == 4) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) X[d][a] = r[d * F::NS + o];
       }
       u[0][a] = r[3 * F::NS + o];
     }
-    laplace_element_parallelepiped_n<T, 1>(X, u, c, v);
+    if constexpr (GEN)
+      laplace_element_n<T, 1>(X, u, c, v);
+    else
+      laplace_element_parallelepiped_n<T, 1>(X, u, c, v);
     // accumulator entry of the element's corner 0 (may lie outside the box; only
     // owned corners are addressed)
     double *acc = sV + ((ea[k] - 1) + F::AX * ((eb[k] - 1) + F::AY * (ec[k] - 1)));
@@ -1513,6 +1519,12 @@ bool owner_box(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx
   return true;
 }
 
+// Largest mesh of general hexahedra that takes the owner-computes tiles: measured
+// on jittered n^3 Laplace FP64 (owner / halo-slot tiles, us per apply streaming):
+// 32^3 9.6 / 11.4, 48^3 10.2 / 11.9, 64^3 17.0 / 16.7, 128^3 99.8 / 80.6; the 16^3
+// Jacobi-PCG to 1e-8 2.23 / 2.40 ms.
+constexpr int64_t kOwnerGeneralElems = 128 * 1024;
+
 int64_t own_tiles(const TileMap &tm) {
   return int64_t(tm.own_nx / OwnTile::OX) * (tm.own_ny / OwnTile::OY) * (tm.own_nz / OwnTile::OZ);
 }
@@ -1573,11 +1585,17 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   tm.fixed = tm.fixed && tm.split && op.variant == Q1_V_BLOCK && op.elem == Q1_HEX8;
   if (const char *e = std::getenv("Q1_FIXED_TILE"))  // "0": the general-shape instances
     if (e[0] == '0') tm.fixed = false;
-  // owner-computes tiles for the scalar kind on a box lattice of parallelepipeds
-  // ("Q1_OWNER_TILE=0": the halo-slot tiles); the diagonal keeps the split tiles
+  // owner-computes tiles for the scalar kind on a box lattice ("Q1_OWNER_TILE=0": the
+  // halo-slot tiles); the diagonal keeps the split tiles.  Meshes of general hexahedra
+  // take them only when small (at most kOwnerGeneralElems elements), where the apply is
+  // bound by the latency of its kernels rather than by the element work that the
+  // owner tiles repeat on the shell ("Q1_OWNER_GENERAL=0" or "1" overrides).
   tm.own_nx = tm.own_ny = tm.own_nz = 0;
+  tm.own_general = !tm.all_affine;
+  bool own_ok = tm.all_affine || ne <= kOwnerGeneralElems;
+  if (const char *e = std::getenv("Q1_OWNER_GENERAL")) own_ok = tm.all_affine || e[0] == '1';
   const char *own_env = std::getenv("Q1_OWNER_TILE");
-  if (op.variant == Q1_V_BLOCK && hex && op.physics == Q1_LAPLACE && tm.all_affine && tm.split &&
+  if (op.variant == Q1_V_BLOCK && hex && op.physics == Q1_LAPLACE && own_ok && tm.split &&
       !(own_env && own_env[0] == '0'))
     owner_box(conn, ne, nn, tm.own_nx, tm.own_ny, tm.own_nz);
   auto up = [&](auto **dst, const auto &v) -> int {
@@ -1687,7 +1705,10 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   }
   if (block && tm.own_nx > 0) {
     if constexpr (PH == 1) {
-      auto kern = op.mask ? k_apply_owner<T, true> : k_apply_owner<T, false>;
+      auto kern = tm.own_general ? (op.mask ? k_apply_owner<T, true, true>
+                                            : k_apply_owner<T, false, true>)
+                                 : (op.mask ? k_apply_owner<T, true, false>
+                                            : k_apply_owner<T, false, false>);
       hipLaunchKernelGGL(kern, dim3(unsigned(own_tiles(tm))), dim3(256), 0, s, tm.own_nx,
                          tm.own_ny, tm.own_nz, static_cast<const T *>(op.xyz),
                          static_cast<const T *>(op.coef), op.mask, x, y, stop, dot);

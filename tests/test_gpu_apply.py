@@ -103,12 +103,15 @@ def test_apply_parity_whole_tiles(q1, orc, physics, n, jitter, mask, dtype):
 OWNER_CASES = [(16, 8, 4), (32, 8, 4), (16, 16, 8), (32, 16, 12), (48, 24, 8)]
 
 
+@pytest.mark.parametrize("jitter", [0.0, 0.1])
 @pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("mask", ["none", "random", "all_faces"])
 @pytest.mark.parametrize("n", OWNER_CASES)
-def test_owner_tiles_parity(q1, orc, monkeypatch, n, mask, dtype):
-    print(f"\n[owner tiles] n={n} mask={mask} dtype={dtype}", flush=True)
-    pr = problem(1, n, 0.0, 2317, False)
+def test_owner_tiles_parity(q1, orc, monkeypatch, n, mask, dtype, jitter):
+    """Parallelepipeds (jitter 0) take the closed-form element; these small jittered
+    meshes take the owner tiles with the general element."""
+    print(f"\n[owner tiles] n={n} mask={mask} dtype={dtype} jitter={jitter}", flush=True)
+    pr = problem(1, n, jitter, 2317, False)
     nn = pr["xyz"].shape[1]
     if mask == "random":
         pr["mask"] = (np.random.default_rng(2317).random(nn) < 0.15).astype(np.uint8)
