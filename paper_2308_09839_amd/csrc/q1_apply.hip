@@ -333,6 +333,8 @@ int validate_conn(const Op &op, hipStream_t s) {
 }
 
 int launch_diag(Op &op, void *d, hipStream_t s) {
+  if (op.elem == Q1_TET4 && op.variant == Q1_V_BLOCK && op.tiles.own_nx > 0)
+    return launch_diag_owner(op, d, s);
   if (op.elem != Q1_HEX8) return launch_diag_family(op, d, s);
   if ((op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) && op.tiles.split)
     return launch_diag_tile(op, d, s);

@@ -50,7 +50,8 @@ struct TileMap {
   // owner-computes tiles (scalar Laplace on a box lattice of parallelepipeds whose
   // element counts per direction are multiples of 16, 8, 4): the box size, or 0
   int own_nx = 0, own_ny = 0, own_nz = 0;
-  bool own_general = false;       // owner tiles with the general-hexahedron element
+  int own_elem = 0;               // owner tiles' element: 0 parallelepiped, 1 general
+                                  // hexahedron, 2 a cell's six Kuhn tetrahedra
   uint8_t *tile_affine = nullptr; // [n_tiles] 1: every element of the tile is a parallelepiped
   uint32_t *tile_lat = nullptr;   // [n_tiles] lattice tile A | B << 8 | steps-per-layer << 16 | C << 24, or 0
   uint32_t *tile_addr = nullptr;  // [n_tiles] lattice addressing: valid bit | shared-face bits, or 0
@@ -142,6 +143,8 @@ int64_t apply_dot_parts(const Op &op, int64_t *n_final);
 int launch_apply_dot(Op &op, const void *x, void *y, hipStream_t s, const int *stop,
                      double *parts);
 int launch_diag_tile(Op &op, void *d, hipStream_t s);
+// The diagonal on owner-computes tiles of tetrahedra (bitwise reproducible).
+int launch_diag_owner(Op &op, void *d, hipStream_t s);
 void free_tiles(Op &op);
 int build_colors(Op &op, hipStream_t s);
 void free_colors(Op &op);

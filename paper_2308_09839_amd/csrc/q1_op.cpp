@@ -188,7 +188,10 @@ int q1_op_info(const q1_op *op, int *physics, int *dtype, int *variant, int64_t 
 int q1_op_reproducible(const q1_op *op, int *reproducible) {
   Q1_CHECK(op && reproducible, Q1_EINVAL, "q1_op_reproducible: NULL argument");
   const bool block = op->variant == Q1_V_BLOCK || op->variant == Q1_V_PA;
-  *reproducible = op->elem == Q1_HEX8 && block && op->tiles.split ? 1 : 0;
+  *reproducible = (op->elem == Q1_HEX8 && block && op->tiles.split) ||
+                          (op->variant == Q1_V_BLOCK && op->tiles.own_nx > 0)
+                      ? 1
+                      : 0;
   return Q1_OK;
 }
 

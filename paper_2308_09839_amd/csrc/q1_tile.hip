@@ -666,10 +666,18 @@ __device__ __forceinline__ void lds_add_own(double *p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// GEN: the general hexahedron (isoparametric geometry at each Gauss point, the
-// whole 8 corners' coordinates), taken on small meshes whose elements are not all
-// parallelepipeds, where one kernel per apply matters more than the element work.
-template <typename T, bool MASK, bool GEN>
+// Element kinds of the owner-computes tiles: the parallelepiped hexahedron; the
+// general hexahedron (isoparametric geometry at each Gauss point, all 8 corners'
+// coordinates), taken on small meshes whose elements are not all parallelepipeds,
+// where one kernel per apply matters more than the element work; the six linear
+// tetrahedra of a cell's Kuhn split (tetrahedron t of cell e is element 6e + t,
+// with the cell corners of kKuhn[t]), their sum acting as the cell's element; and
+// the diagonal of that sum (no input; y is the diagonal, 1 on Dirichlet nodes).
+constexpr int kOwnPar = 0, kOwnGen = 1, kOwnKuhn = 2, kOwnKuhnDiag = 3;
+__device__ constexpr int kKuhn[6][4] = {{0, 1, 3, 7}, {0, 5, 1, 7}, {0, 3, 2, 7},
+                                        {0, 2, 6, 7}, {0, 6, 4, 7}, {0, 4, 5, 7}};
+
+template <typename T, bool MASK, int EK>
 __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
                                                      const T *__restrict__ xyz,
                                                      const T *__restrict__ coef,
@@ -678,6 +686,8 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
                                                      const int *__restrict__ stop,
                                                      double *__restrict__ dot_part) {
   using F = OwnTile;
+  constexpr int NC = EK >= kOwnKuhn ? 6 : 1;  // cell coefficients
+  constexpr bool ALLX = EK != kOwnPar;          // all 8 corners' coordinates
   if (stop && *stop) return;
   __shared__ T sR[4 * F::NS];   // x, y, z, input (0 on Dirichlet nodes), field by field
   __shared__ double sV[F::NA];  // accumulator over the owned box
@@ -716,7 +726,7 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
     rec[k][0] = ld_off(X0, o);
     rec[k][1] = ld_off(X1, o);
     rec[k][2] = ld_off(X2, o);
-    rec[k][3] = ld_off(x, o);
+    rec[k][3] = EK == kOwnKuhnDiag ? T(0) : ld_off(x, o);
     fx[k] = MASK ? uint32_t(ld_off(mask, g)) : 0u;
     gk[k] = g;
     // (range tests as unsigned compares joined without short-circuit: no branches)
@@ -755,9 +765,11 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
     eo[k] = (__umul24(uint32_t(nx), __umul24(uint32_t(ny), uint32_t(min(max(gz, 0), nz - 1))) +
                                         uint32_t(min(max(gy, 0), ny - 1))) +
              uint32_t(min(max(gx, 0), nx - 1))) *
-            uint32_t(sizeof(T));
+            uint32_t(NC * sizeof(T));
   }
-  T cnext = ld_off(coef, eo[0]);
+  T cnext[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) cnext[t] = ld_off(coef, eo[0] + uint32_t(t * sizeof(T)));
 #pragma unroll
   for (int k = 0; k < F::KN; ++k) {
     const int i = k * 256 + tid;
@@ -772,23 +784,60 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
   double hold[3][4];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const T c = cnext;
-    if (k < 2) cnext = ld_off(coef, eo[k + 1]);
+    T c[NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) c[t] = cnext[t];
+    if (k < 2) {
+#pragma unroll
+      for (int t = 0; t < NC; ++t) cnext[t] = ld_off(coef, eo[k + 1] + uint32_t(t * sizeof(T)));
+    }
     const T *r = sR + (ea[k] + F::SX * (eb[k] + F::SY * ec[k]));
     T X[3][8], u[1][8], v[1][8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int o = (a & 1) + F::SX * ((a >> 1) & 1) + F::SX * F::SY * (a >> 2);
-      if (GEN || a == 0 || a == 1 || a == 2 || a == 4) {
+      if (ALLX || a == 0 || a == 1 || a == 2 || a == 4) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) X[d][a] = r[d * F::NS + o];
       }
       u[0][a] = r[3 * F::NS + o];
     }
-    if constexpr (GEN)
-      laplace_element_n<T, 1>(X, u, c, v);
-    else
-      laplace_element_parallelepiped_n<T, 1>(X, u, c, v);
+    if constexpr (EK == kOwnGen) {
+      laplace_element_n<T, 1>(X, u, c[0], v);
+    } else if constexpr (EK == kOwnPar) {
+      laplace_element_parallelepiped_n<T, 1>(X, u, c[0], v);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) v[0][a] = T(0);
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        T Xt[3][4], ut[1][4], vt[1][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Xt[d][q] = X[d][kKuhn[t][q]];
+          ut[0][q] = u[0][kKuhn[t][q]];
+        }
+        if constexpr (EK == kOwnKuhn) {
+          tet_element<T, 1>(Xt, ut, c[t], T(0), vt);
+        } else {  // diagonal: k |c_q|^2 / (6 det) with c_q the scaled gradient of corner q
+          const T E1[3] = {Xt[0][1] - Xt[0][0], Xt[1][1] - Xt[1][0], Xt[2][1] - Xt[2][0]};
+          const T E2[3] = {Xt[0][2] - Xt[0][0], Xt[1][2] - Xt[1][0], Xt[2][2] - Xt[2][0]};
+          const T E3[3] = {Xt[0][3] - Xt[0][0], Xt[1][3] - Xt[1][0], Xt[2][3] - Xt[2][0]};
+          T g[4][3];
+          cross(E2, E3, g[1]);
+          cross(E3, E1, g[2]);
+          cross(E1, E2, g[3]);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+          const T ks = c[t] * rcp(T(6) * dot3(E1, g[1]));
+#pragma unroll
+          for (int q = 0; q < 4; ++q) vt[0][q] = ks * dot3(g[q], g[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[0][kKuhn[t][q]] += vt[0][q];
+      }
+    }
     // accumulator entry of the element's corner 0 (may lie outside the box; only
     // owned corners are addressed)
     double *acc = sV + ((ea[k] - 1) + F::AX * ((eb[k] - 1) + F::AY * (ec[k] - 1)));
@@ -821,7 +870,7 @@ __global__ __launch_bounds__(256) void k_apply_owner(int nx, int ny, int nz,
 #pragma unroll
   for (int k = 0; k < F::KN; ++k) {
     if (ak[k] >= 0) {
-      const T yv = fx[k] != 0 ? rec[k][3] : T(sV[ak[k]]);
+      const T yv = fx[k] != 0 ? (EK == kOwnKuhnDiag ? T(1) : rec[k][3]) : T(sV[ak[k]]);
       st_off(y, gk[k] * uint32_t(sizeof(T)), yv);
       if (dot_part) dsum += double(rec[k][3]) * double(yv);
     }
@@ -1519,6 +1568,46 @@ bool owner_box(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx
   return true;
 }
 
+// The tetrahedra of an owner-computes operator: the Kuhn split of a box lattice
+// (tetrahedron t of cell e is element 6e + t, its corners the cell corners kKuhn[t]
+// of the lattice cell e = ex + nx (ey + ny ez)), checked entry by entry, with the
+// limits of owner_box.
+bool owner_kuhn(const std::vector<int32_t> &conn, int64_t ne, int64_t nn, int &nx, int &ny,
+                int &nz) {
+  static constexpr int kt[6][4] = {{0, 1, 3, 7}, {0, 5, 1, 7}, {0, 3, 2, 7},
+                                   {0, 2, 6, 7}, {0, 6, 4, 7}, {0, 4, 5, 7}};
+  if (ne <= 0 || ne % 6 || conn.size() != size_t(4) * ne) return false;
+  const int64_t nc = ne / 6;
+  // cell 0's corners 1, 3 and 7 are tetrahedron 0's vertices 1, 2 and 3
+  if (conn[0] != 0 || conn[ne] != 1) return false;
+  const int64_t bx = int64_t(conn[2 * ne]) - 2;  // corner 3 = 1 + (nx + 1)
+  if (bx < 1) return false;
+  const int64_t c7 = int64_t(conn[3 * ne]) - 1 - (bx + 1);  // (nx + 1)(ny + 1)
+  if (c7 <= 0 || c7 % (bx + 1)) return false;
+  const int64_t by = c7 / (bx + 1) - 1;
+  if (by < 1 || nc % (bx * by)) return false;
+  const int64_t bz = nc / (bx * by);
+  if ((bx + 1) * (by + 1) * (bz + 1) != nn) return false;
+  if (nn * 8 >= (int64_t(1) << 32) || ne * 8 >= (int64_t(1) << 32)) return false;
+  if ((by + 1) * (bz + 1) >= (int64_t(1) << 24) || bx + 1 >= (int64_t(1) << 24)) return false;
+  if (bx % OwnTile::OX || by % OwnTile::OY || bz % OwnTile::OZ) return false;
+  const int64_t sy = bx + 1, sz = (bx + 1) * (by + 1);
+  for (int64_t e = 0; e < nc; ++e) {
+    const int64_t ex = e % bx, ey = (e / bx) % by, ez = e / (bx * by);
+    const int64_t b = ex + sy * ey + sz * ez;
+    for (int t = 0; t < 6; ++t)
+      for (int q = 0; q < 4; ++q) {
+        const int a = kt[t][q];
+        if (conn[size_t(q) * ne + 6 * e + t] != b + (a & 1) + sy * ((a >> 1) & 1) + sz * (a >> 2))
+          return false;
+      }
+  }
+  nx = int(bx);
+  ny = int(by);
+  nz = int(bz);
+  return true;
+}
+
 // Largest mesh of general hexahedra that takes the owner-computes tiles: measured
 // on jittered n^3 Laplace FP64 (owner / halo-slot tiles, us per apply streaming):
 // 32^3 9.6 / 11.4, 48^3 10.2 / 11.9, 64^3 17.0 / 16.7, 128^3 99.8 / 80.6; the 16^3
@@ -1590,14 +1679,19 @@ int build_tiles_t(Op &op, hipStream_t s, int patch_x, int patch_y, int layers) {
   // take them only when small (at most kOwnerGeneralElems elements), where the apply is
   // bound by the latency of its kernels rather than by the element work that the
   // owner tiles repeat on the shell ("Q1_OWNER_GENERAL=0" or "1" overrides).
+  // Tetrahedra of a lattice's Kuhn split take them too, each cell's six as one element
+  // (scalar kind; bitwise reproducible, unlike their block tiles).
   tm.own_nx = tm.own_ny = tm.own_nz = 0;
-  tm.own_general = !tm.all_affine;
+  tm.own_elem = tm.all_affine ? 0 : 1;
   bool own_ok = tm.all_affine || ne <= kOwnerGeneralElems;
   if (const char *e = std::getenv("Q1_OWNER_GENERAL")) own_ok = tm.all_affine || e[0] == '1';
   const char *own_env = std::getenv("Q1_OWNER_TILE");
-  if (op.variant == Q1_V_BLOCK && hex && op.physics == Q1_LAPLACE && own_ok && tm.split &&
-      !(own_env && own_env[0] == '0'))
+  const bool own_on = op.variant == Q1_V_BLOCK && op.physics == Q1_LAPLACE &&
+                      !(own_env && own_env[0] == '0');
+  if (own_on && hex && own_ok && tm.split)
     owner_box(conn, ne, nn, tm.own_nx, tm.own_ny, tm.own_nz);
+  if (own_on && op.elem == Q1_TET4 && owner_kuhn(conn, ne, nn, tm.own_nx, tm.own_ny, tm.own_nz))
+    tm.own_elem = 2;
   auto up = [&](auto **dst, const auto &v) -> int {
     using E = typename std::remove_reference<decltype(v)>::type::value_type;
     const size_t b = std::max<size_t>(1, v.size()) * sizeof(E);
@@ -1683,6 +1777,22 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
   if (tm.n_reset > 0 && !block)
     hipLaunchKernelGGL((k_reset_nodes<T, DPN>), dim3(int((tm.n_reset + 255) / 256)), dim3(256), 0,
                        s, tm.n_reset, tm.reset, op.mask, x, y, stop);
+  if (block && tm.own_nx > 0) {
+    if constexpr (PH == 1) {
+      auto pick = [&](auto ek) {
+        constexpr int EK = decltype(ek)::value;
+        return op.mask ? k_apply_owner<T, true, EK> : k_apply_owner<T, false, EK>;
+      };
+      auto kern = tm.own_elem == 2   ? pick(std::integral_constant<int, kOwnKuhn>{})
+                  : tm.own_elem == 1 ? pick(std::integral_constant<int, kOwnGen>{})
+                                     : pick(std::integral_constant<int, kOwnPar>{});
+      hipLaunchKernelGGL(kern, dim3(unsigned(own_tiles(tm))), dim3(256), 0, s, tm.own_nx,
+                         tm.own_ny, tm.own_nz, static_cast<const T *>(op.xyz),
+                         static_cast<const T *>(op.coef), op.mask, x, y, stop, dot);
+      Q1_HIP(hipGetLastError());
+      return Q1_OK;
+    }
+  }
   const size_t lds = block ? block_lds_bytes(op) : size_t(tm.max_nodes) * (DPN * sizeof(T) + sizeof(uint32_t));
   if (block && op.elem == Q1_TET4) {
     if constexpr (PH != 2) {
@@ -1702,19 +1812,6 @@ int apply_tile_t(Op &op, const void *xv, void *yv, hipStream_t s, const int *sto
       return Q1_OK;
     }
     return fail(Q1_EUNSUPPORTED, "tetrahedra: scalar Laplace and elasticity");
-  }
-  if (block && tm.own_nx > 0) {
-    if constexpr (PH == 1) {
-      auto kern = tm.own_general ? (op.mask ? k_apply_owner<T, true, true>
-                                            : k_apply_owner<T, false, true>)
-                                 : (op.mask ? k_apply_owner<T, true, false>
-                                            : k_apply_owner<T, false, false>);
-      hipLaunchKernelGGL(kern, dim3(unsigned(own_tiles(tm))), dim3(256), 0, s, tm.own_nx,
-                         tm.own_ny, tm.own_nz, static_cast<const T *>(op.xyz),
-                         static_cast<const T *>(op.coef), op.mask, x, y, stop, dot);
-      Q1_HIP(hipGetLastError());
-      return Q1_OK;
-    }
   }
   if (block) {
     // fallback accumulation when some tile does not admit the split one
@@ -1842,12 +1939,12 @@ int launch_apply_tile(Op &op, const void *x, void *y, hipStream_t s, const int *
 }
 
 int64_t apply_dot_parts(const Op &op, int64_t *n_final) {
-  const bool block = (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) && op.elem == Q1_HEX8;
-  if (!block || op.tiles.n_tiles == 0) return 0;
-  if (op.tiles.own_nx > 0) {  // one partial per owner tile
+  if (op.variant == Q1_V_BLOCK && op.tiles.own_nx > 0) {  // one partial per owner tile
     if (n_final) *n_final = own_tiles(op.tiles);
     return own_tiles(op.tiles);
   }
+  const bool block = (op.variant == Q1_V_BLOCK || op.variant == Q1_V_PA) && op.elem == Q1_HEX8;
+  if (!block || op.tiles.n_tiles == 0) return 0;
   const int64_t h = op.tiles.n_reset > 0 ? halo_blocks(op.tiles) : 0;
   if (n_final) *n_final = h > 0 ? h : op.tiles.n_tiles;
   return h + op.tiles.n_tiles;
@@ -1860,6 +1957,25 @@ int launch_apply_dot(Op &op, const void *x, void *y, hipStream_t s, const int *s
   return dispatch_phys(op, [&](auto t, auto ph) {
     return apply_tile_t<decltype(t), decltype(ph)::value>(op, x, y, s, stop, parts);
   });
+}
+
+int launch_diag_owner(Op &op, void *dv, hipStream_t s) {
+  const TileMap &tm = op.tiles;
+  Q1_CHECK(tm.own_nx > 0 && tm.own_elem == 2 && op.physics == Q1_LAPLACE, Q1_EUNSUPPORTED,
+           "owner-computes diagonal: the tetrahedra of a Kuhn-split lattice");
+  auto run = [&](auto t) -> int {
+    using T = decltype(t);
+    auto kern = op.mask ? k_apply_owner<T, true, kOwnKuhnDiag>
+                        : k_apply_owner<T, false, kOwnKuhnDiag>;
+    hipLaunchKernelGGL(kern, dim3(unsigned(own_tiles(tm))), dim3(256), 0, s, tm.own_nx,
+                       tm.own_ny, tm.own_nz, static_cast<const T *>(op.xyz),
+                       static_cast<const T *>(op.coef), op.mask, static_cast<const T *>(nullptr),
+                       static_cast<T *>(dv), static_cast<const int *>(nullptr),
+                       static_cast<double *>(nullptr));
+    Q1_HIP(hipGetLastError());
+    return Q1_OK;
+  };
+  return op.dtype == Q1_F64 ? run(double{}) : run(float{});
 }
 
 void free_tiles(Op &op) {

@@ -216,3 +216,77 @@ def test_family_unsupported_and_invalid(q1):
     with pytest.raises(q1.Q1Error) as ei:
         make_family_op(q1, dict(pr, elem=5))
     assert ei.value.code == -1
+
+
+# Tetrahedra of a Kuhn-split box lattice whose cell counts are multiples of 16, 8, 4:
+# the scalar operator takes the owner-computes tiles, each cell's six tetrahedra
+# evaluated as one element (bitwise reproducible apply and diagonal).
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("mask", ["none", "random", "all_faces"])
+@pytest.mark.parametrize("n,jitter", [((16, 8, 4), 0.0), ((32, 16, 8), 0.1), ((48, 8, 12), 0.1)])
+def test_owner_tets(q1, orc, monkeypatch, n, jitter, mask, dtype):
+    import torch
+    print(f"\n[owner tets] n={n} jitter={jitter} mask={mask} dtype={dtype}", flush=True)
+    pr = family_problem(4, 1, n, jitter, 2319, False)
+    nn = pr["xyz"].shape[1]
+    if mask == "random":
+        pr["mask"] = (np.random.default_rng(2319).random(nn) < 0.15).astype(np.uint8)
+    elif mask == "all_faces":
+        m = np.zeros(nn, np.uint8)
+        for f in ("x0", "x1", "y0", "y1", "z0", "z1"):
+            m |= si.face_mask(*n, f).astype(np.uint8)
+        pr["mask"] = m
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    x = si.vec_uniform(A.n, 2319, si.STREAM_X)
+    ref = A.matvec(x)
+    op = make_family_op(q1, pr, dtype)
+    assert op.reproducible()
+    ys = [apply(op, x, dtype) for _ in range(3)]
+    assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    assert rel_err(ys[0], ref) <= TOL[dtype], rel_err(ys[0], ref)
+    assert np.max(np.abs(ys[0] - ref)) <= 10 * TOL[dtype] * np.max(np.abs(ref))
+    ds = []
+    for _ in range(2):
+        d = torch_empty(A.n, dtype)
+        op.diag(d)
+        torch.cuda.synchronize()
+        ds.append(d.double().cpu().numpy())
+    assert np.array_equal(ds[0], ds[1])
+    dref = A.diag()
+    assert np.max(np.abs(ds[0] - dref)) <= 10 * TOL[dtype] * np.max(np.abs(dref))
+    # the block tiles of the same operator agree to the same bar, in another order
+    monkeypatch.setenv("Q1_OWNER_TILE", "0")
+    opb = make_family_op(q1, pr, dtype)
+    monkeypatch.delenv("Q1_OWNER_TILE")
+    assert not opb.reproducible()
+    yb = apply(opb, x, dtype)
+    assert rel_err(yb, ref) <= TOL[dtype]
+    assert not np.array_equal(yb, ys[0])
+
+
+def test_owner_tets_pcg(q1, orc):
+    """Jacobi-PCG on owner-computes tetrahedra (the apply forms the p.q partials):
+    the first iterates are the oracle's, and two solves are bitwise identical."""
+    import torch
+    pr = family_problem(4, 1, (32, 16, 8), 0.1, 62)
+    A = orc.assemble(1, pr["xyz"], pr["conn"], pr["coef"], pr["mask"])
+    b = si.vec_uniform(A.n, 62, si.STREAM_RHS)
+    b[pr["mask"] == 1] = 0.0
+    op = make_family_op(q1, pr)
+    assert op.reproducible()
+    bd = dev(b, torch.float64)
+    for k in (1, 5, 10):
+        xd = torch.empty_like(bd)
+        st = q1.q1_pcg(op, 1, bd, xd, 0.0, k)
+        ref = orc.pcg(A, b, rtol=0.0, maxit=k)
+        assert st["iters"] == k
+        assert np.linalg.norm(xd.cpu().numpy() - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    xs, its = [], []
+    for _ in range(2):
+        xd = torch.empty_like(bd)
+        st = q1.q1_pcg(op, 1, bd, xd, 1e-8, 20000)
+        assert st["status"] == 0
+        its.append(st["iters"])
+        xs.append(xd.cpu().numpy())
+    assert its[0] == its[1] and np.array_equal(xs[0], xs[1])
+    assert orc.true_rel_res(A, xs[0], b) <= 1e-8 * (1 + 1e-3)
