@@ -115,7 +115,16 @@ enum { Q1_F64 = 0, Q1_F32 = 1 };
  *            second kernel adds each node's slots in tile order (no global
  *            atomics; each entry of y is written once).  Because the halo
  *            buffer belongs to the operator, two applies of one BLOCK
- *            operator must not run concurrently (issue them on one stream);
+ *            operator must not run concurrently (issue them on one stream).
+ *            The scalar Laplace kind on a box lattice in this header's
+ *            numbering (element counts multiples of 16, 8 and 4; all elements
+ *            parallelepipeds, or at most 131,072 general hexahedra; or the
+ *            lattice's Kuhn split into tetrahedra, element 6e + t) takes
+ *            owner-computes tiles instead: each workgroup computes the
+ *            elements around a 16 x 8 x 4 box of nodes and stores those
+ *            nodes of y once, in one kernel with no halo slots (the mesh
+ *            checked entry by entry at creation; Q1_OWNER_TILE=0 in the
+ *            environment at creation keeps the halo-slot tiles);
  *   PA       "partial assembly" (Section 3; the storage of Table 3): BLOCK's
  *            tiles and halo, but at set-up quadrature data of every element
  *            and point is computed and stored, and the apply reads it instead
