@@ -160,7 +160,9 @@ def test_unet_forward_backward(q1):
     out = torch.empty((B, D, H, W), dtype=torch.float32, device="cuda")
     net.forward(xd, out, B)
     ref, cache = U.unet_forward(th, x[..., :2], bf16=True)
-    assert normrel(host(out), ref) <= 2e-3, normrel(host(out), ref)
+    print(f"  forward: {normrel(host(out), ref):.2e}")
+    # observed 1.5e-5: the two sides round the same BF16 activations at every layer
+    assert normrel(host(out), ref) <= 1e-4, normrel(host(out), ref)
     # loss kernel on seeded values (not on the network output)
     o_s = rnd((B, D, H, W), 35).astype(np.float32).astype(np.float64)
     tgt = rnd((B, D, H, W), 33).astype(np.float32).astype(np.float64)
@@ -182,7 +184,9 @@ def test_unet_forward_backward(q1):
         e_w = normrel(g[wo:wo + sz], gr[wo:wo + sz])
         e_b = normrel(g[bo:bo + co], gr[bo:bo + co])
         print(f"  {name}: w {e_w:.2e} b {e_b:.2e}")
-        assert e_w <= 1e-2 and e_b <= 1e-2, name
+        # observed at most 1.1e-3 (the encoder's first levels, deepest in the
+        # backward pass through BF16-rounded activations)
+        assert e_w <= 4e-3 and e_b <= 4e-3, name
 
 
 def test_unet_adam_step(q1):
