@@ -269,7 +269,8 @@ def test_unet_encoding_and_precond(q1, orc):
                                      q1._stream(None)) == 0
     out, _ = U.unet_forward(th, U.bf16_round(ref_in[None].astype(np.float32)), bf16=True)
     zr = U.decode_output(out, free, nx, ny, nz)
-    assert normrel(host(z), zr) <= 2e-3
+    print(f"  z: {normrel(host(z), zr):.2e}")
+    assert normrel(host(z), zr) <= 1e-6  # observed 5.3e-8 (FP32 decode of the same network output)
     assert np.all(host(z)[~free] == 0)
 
 
@@ -337,7 +338,8 @@ def test_two_level_precond(q1, orc):
     Ad = A.matvec(d)
     c = (d @ r1) / (d @ Ad)
     zr = z1 + c * d + omega * w * (r1 - c * Ad)
-    assert normrel(host(z), zr) <= 2e-3
+    print(f"  z: {normrel(host(z), zr):.2e}")
+    assert normrel(host(z), zr) <= 1e-8  # observed 2.5e-10
     assert np.all(host(z)[~free] == 0)
 
 
